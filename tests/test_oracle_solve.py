@@ -1,0 +1,83 @@
+"""Full-solve pins of the oracle: the ROM-FETI-DP reaches the conforming FE solution (CPU only)."""
+import numpy as np
+import pytest
+
+import latticegen
+from oracle import Model
+from oracle.direct import conforming_solve
+from oracle.fetidp import ExactFETIDP
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dim,shape,n_el,K", [
+    (2, (1, 1), 3, 1), (2, (2, 2), 3, 2), (2, (3, 3), 3, 3), (2, (4, 2), 4, 3), (3, (2, 2, 2), 2, 3)])
+def test_rom_fetidp_equals_direct_cholesky(dim, shape, n_el, K):
+    m = Model(latticegen.tiny(dim, shape, n_el, n_principal=K))
+    m.build_reduced_basis()
+    r = m.solve(tol=1e-12, inner_tol=1e-13, maxit=60)
+    ref = conforming_solve(m)
+    assert r["relres"] < 1e-11
+    assert _rel(r["u"], ref["u"]) < 1e-10
+    assert _rel(r["lam"], ref["lam"]) < 1e-9
+    # energy identity f^T u = u^T K u (no Dirichlet lifting: u0 = 0)
+    f = m.rhs_f[0]
+    assert np.isclose(f @ r["u"], r["u"] @ m.apply_K(r["u"]), rtol=1e-9)
+
+
+def test_c1_solve_matches_direct():
+    m = Model(latticegen.make("c1"))
+    m.build_reduced_basis()
+    r = m.solve(tol=1e-12, inner_tol=1e-13)
+    ref = conforming_solve(m)
+    assert _rel(r["u"], ref["u"]) < 1e-10
+    assert r["outer_its"] < 20
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (3, 2)), (3, (2, 2, 1))])
+def test_patch_test_uniform_strain_reproduced(dim, shape):
+    """Homogeneous material, u0 = eps x on the whole boundary => u = eps P at every control point."""
+    eps = np.array([[1e-3, 2e-4], [-5e-4, 3e-4]]) if dim == 2 else \
+        np.array([[1e-3, 2e-4, 0.0], [-5e-4, 3e-4, 1e-4], [2e-4, 0.0, -4e-4]])
+    faces = tuple(range(2 * dim))
+    p = latticegen.tiny(dim, shape, 3 if dim == 2 else 2, E_out=1.0, dirichlet_faces=faces, load_face=-1,
+                        u0_grad=eps, tractions=np.zeros((1, dim)), n_principal=2)
+    m = Model(p)
+    m.build_reduced_basis()
+    r = m.solve(tol=1e-13, inner_tol=1e-14, maxit=80)
+    u = m.full_cell_displacements(r["u"]).reshape(p.N, -1, dim)
+    expect = p.ctrl @ eps.T
+    assert np.abs(u - expect).max() < 1e-12 * np.abs(expect).max() * 1e3
+    ref = conforming_solve(m)
+    ud = ref["u_global"][ref["cdof"]].reshape(p.N, -1, dim)
+    assert np.abs(ud - expect).max() < 1e-10 * np.abs(expect).max()
+
+
+def test_identical_cells_one_global_iteration():
+    """Remark 11: with identical cells the ROM is exact and one global iteration suffices."""
+    p = latticegen.tiny(2, (4, 3), 3, amp=0.0, map_kind="identity", n_principal=4)
+    m = Model(p)
+    m.build_reduced_basis()
+    assert len(m.sigma) == 1
+    r = m.solve(tol=1e-8, inner_tol=1e-12)
+    assert r["outer_its"] == 1
+
+
+def test_local_iterations_match_standard_fetidp():
+    """Tables 1-2: the interface PCG needs (about) as many iterations as standard FETI-DP."""
+    m = Model(latticegen.tiny(2, (4, 4), 4, n_principal=4))
+    m.build_reduced_basis()
+    r = m.solve(tol=1e-8, inner_tol=1e-11)
+    ex = ExactFETIDP(m).solve(tol=1e-11)
+    assert abs(np.median(r["inner_its"]) - ex["its"]) <= 2
+
+
+def test_more_principals_fewer_outer_iterations():
+    m = Model(latticegen.make("c1"))
+    its = []
+    for K in (1, 4):
+        m.build_reduced_basis(n_principal=K)
+        its.append(m.solve(tol=1e-8)["outer_its"])
+    assert its[1] <= its[0]
