@@ -1,0 +1,170 @@
+/*
+ * ifeti.h -- C ABI of the MI355X (gfx950) ROM-based inexact FETI-DP library.
+ *
+ * Method: T. Hirschler, R. Bouclier, P. Antolin, A. Buffa, "Reduced Order
+ * Modeling based Inexact FETI-DP solver for lattice structures".  Every cell
+ * of a lattice is one subdomain (Sec. 2.1, eq. (1)); every cell space is the
+ * push-forward of one reference quadratic B-spline space (eq. (6)); corners
+ * are primal, the other cell-boundary control points dual (Sec. 2.2.2); the
+ * saddle system (16) is solved by flexible GMRES preconditioned by the block
+ * preconditioner (44) whose sub-blocks are built from a few principal cells
+ * chosen by the greedy of Algorithm 4 (Sec. 3, 4.2).
+ *
+ * Conventions (all calls):
+ *  - Every call returns an ifeti_status (0 = success) and never throws; on
+ *    failure a message is kept per thread and returned by ifeti_last_error().
+ *  - "dev" pointers are device (HIP) memory owned by the caller; "host"
+ *    pointers are host memory owned by the caller.  No call keeps a caller
+ *    pointer after it returns.  The context owns all of its internal
+ *    buffers (cell operators, principal bank, coefficients, coarse inverse).
+ *  - Work is enqueued on the stream given to ifeti_create; calls return
+ *    without a device synchronisation unless they write host outputs
+ *    (iteration counts, residuals, principal lists), which synchronise.
+ *  - Vectors are float64.  Multi-RHS vectors are rhs-major: right-hand side
+ *    r occupies [r*n, (r+1)*n).
+ *  - Displacement layout u = (u_r^(1), ..., u_r^(N), u_P) (eq. (13)):
+ *    u_r^(s) holds the n_r = n_i + n_d non-primal dofs of cell s, interior
+ *    dofs first then dual dofs, each in ascending local dof order with local
+ *    dof = dim*a + component and control point a = ax + nc*(ay + nc*az);
+ *    u_P holds the primal (corner) dofs of the lattice vertices not on a
+ *    Dirichlet face, vertex-major in lexicographic (x fastest) order.
+ *  - Multipliers lambda in R^L (eqs. (14)-(16)): one row per matching dual
+ *    dof pair (chained by ascending cell index where more than two cells share
+ *    a dof, +1 on the lower cell, -1 on the higher) and one +1 row per cell
+ *    copy of a dual dof on a Dirichlet face; interface rows sorted by
+ *    (global control point, component, chain position), then the Dirichlet
+ *    rows in the same key order.
+ *  - Cells: s = ix + nx*(iy + ny*iz).
+ */
+#ifndef IFETI_H
+#define IFETI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifeti_ctx ifeti_ctx;
+
+typedef enum {
+    IFETI_OK = 0,
+    IFETI_EINVAL = -1,      /* bad argument, shape or call order            */
+    IFETI_ENOMEM = -2,      /* device or host allocation failed             */
+    IFETI_ENOTSPD = -3,     /* a Cholesky factorisation met a pivot <= 0    */
+    IFETI_EBREAKDOWN = -4,  /* PCG p^T F p <= 0 or non-finite               */
+    IFETI_EMAXIT = -5,      /* iteration limit reached (partial result kept)*/
+    IFETI_EHIP = -6         /* a HIP runtime call failed                    */
+} ifeti_status;
+
+typedef enum {
+    IFETI_FP64 = 0,         /* every contraction in float64                 */
+    IFETI_FP32_LOCAL = 1,   /* principal contractions fp32 operands/accum   */
+    IFETI_BF16_LOCAL = 2    /* principal contractions bf16 operands, fp32 accum */
+} ifeti_precision;
+
+/* Lattice description (paper Sec. 2.2.1 and 4.1).  Geometry enters through
+ * the control points passed to ifeti_build_cells. */
+typedef struct {
+    int dim;                /* 2 (plane strain) or 3                         */
+    int nx, ny, nz;         /* cells per direction (nz = 1 in 2D)            */
+    int n_el;               /* elements per direction per cell               */
+    int degree;             /* spline degree; 2 is supported                 */
+    double h;               /* cell size of the reference lattice            */
+    double E_in, E_out;     /* Young modulus inside / outside the struts     */
+    double nu;              /* Poisson ratio                                 */
+    double smooth_eps;      /* 0: sharp strut indicator; > 0: tanh width     */
+    int dirichlet_mask;     /* bit f set: face f clamped (u = 0); faces
+                               0:X=0 1:X=Lx 2:Y=0 3:Y=Ly 4:Z=0 5:Z=Lz       */
+    int load_face;          /* face carrying the constant traction, -1: none */
+} ifeti_lattice_desc;
+
+typedef struct {
+    int N, dim, n_ctrl, n_dof;  /* cells; dofs per cell = dim*n_ctrl        */
+    int n_i, n_d, n_p, n_r;     /* local partition (eq. (12))               */
+    int L, L_interface;         /* multipliers; interface rows come first    */
+    int nP;                     /* assembled primal dofs                     */
+    long long nU;               /* N*n_r + nP (eq. (13))                     */
+    int K;                      /* principal cells (after the greedy)        */
+    int nrhs;                   /* load cases given to ifeti_build_cells     */
+} ifeti_sizes;
+
+typedef struct {
+    int precision;          /* ifeti_precision of the principal contractions */
+    int pcg_check_every;    /* PCG host convergence check interval (>= 1)    */
+    int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
+} ifeti_options;
+
+/* Create a context for the lattice `desc`; work goes to `hip_stream`
+ * (hipStream_t, may be NULL for the default stream).  EINVAL for an
+ * unsupported description. */
+int ifeti_create(ifeti_ctx **ctx, const ifeti_lattice_desc *desc, void *hip_stream);
+void ifeti_destroy(ifeti_ctx *ctx);
+const char *ifeti_last_error(void);
+int ifeti_get_sizes(const ifeti_ctx *ctx, ifeti_sizes *out);
+int ifeti_set_options(ifeti_ctx *ctx, const ifeti_options *opt);
+
+/* Assemble every cell (Sec. 4.2.1, eq. (52)): pulled-back material tensor at
+ * the 3^d Gauss points of each element (the greedy snapshots), cell
+ * stiffness on the shared stencil, consistent tractions (eq. (5b)), and the
+ * decomposition bookkeeping B, D, A_p (eqs. (14)-(18), (30)).
+ *   ctrl_pts  dev  N x n_ctrl x dim control points of the cell maps
+ *   widths    dev  N strut widths
+ *   tractions host nrhs x dim constant traction per load case on load_face
+ * EINVAL on a non-positive width or a non-invertible cell map. */
+int ifeti_build_cells(ifeti_ctx *ctx, const double *ctrl_pts, const double *widths,
+                      const double *tractions, int nrhs);
+
+/* Right-hand side of (16): f (dev, nU x nrhs) and d (dev, L x nrhs). */
+int ifeti_get_rhs(ifeti_ctx *ctx, double *f, double *d);
+
+/* Offline phase (Sec. 3.1, 3.2.1, 4.2.2): greedy of Algorithm 4 (stops after
+ * n_principal picks or when the residual max-norm falls to tol_rb), principal
+ * bank (eqs. (22), (27)-(30), (39)), coefficients pi, delta (eqs. (40)-(42)),
+ * ROM operators (43) and the coarse matrix with its explicit inverse.
+ *   principal_in  host, nullable: n_principal cell indices used instead of the greedy picks
+ *   principal_out host, nullable: receives the K chosen cells (room for n_principal)
+ *   theta_out     dev,  nullable: N x K affine coordinates alpha (eq. (38), (56))
+ * ENOTSPD if a principal K_rr or the coarse matrix is not positive definite. */
+int ifeti_build_reduced_basis(ifeti_ctx *ctx, int n_principal, double tol_rb,
+                              const int *principal_in, int *principal_out, double *theta_out);
+
+/* Host copies of the per-cell coefficients, each N x K row-major
+ * (alpha eq. (38); pi, delta eq. (41)).  Any pointer may be NULL. */
+int ifeti_get_coefficients(ifeti_ctx *ctx, double *alpha, double *pi, double *delta);
+
+/* out = F̊ lam, the ROM dual operator of eq. (48), lam/out dev L x nrhs. */
+int ifeti_apply_F(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
+/* out = M̊_D^-1 r, the ROM Dirichlet preconditioner of eq. (49). */
+int ifeti_apply_MD(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
+/* z = Ů v (Algorithm 3), v dev nU x nrhs, z dev L x nrhs. */
+int ifeti_apply_U(ifeti_ctx *ctx, const double *v, double *z, int nrhs);
+/* x = Ůᵀ y, y dev L x nrhs, x dev nU x nrhs. */
+int ifeti_apply_Ut(ifeti_ctx *ctx, const double *y, double *x, int nrhs);
+/* x = K̊^-ROM v (eq. (45), Algorithm 2, reduced local solves eq. (46)). */
+int ifeti_apply_Kinv_rom(ifeti_ctx *ctx, const double *v, double *x, int nrhs);
+/* y = [[K, B^T], [B, 0]] x, the true saddle operator of eq. (16);
+ * x, y dev (nU + L) x nrhs with u first then lambda for each rhs. */
+int ifeti_apply_A(ifeti_ctx *ctx, const double *x, double *y, int nrhs);
+
+/* Interface problem F̊ lam = rhs by PCG preconditioned with M̊_D^-1
+ * (Sec. 3.2.3), lam_0 = 0, stop when ||r_k||/||r_0|| <= tol for every rhs.
+ * iters_out/relres_out host arrays of nrhs (nullable).  EMAXIT keeps the
+ * last iterate; EBREAKDOWN if p^T F̊ p <= 0 or non-finite. */
+int ifeti_solve_interface(ifeti_ctx *ctx, const double *rhs, double *lam, int nrhs,
+                          double tol, int maxit, int *iters_out, double *relres_out);
+
+/* x = K̊^-ROM v - Ůᵀ y: the recovery step of Algorithm 1. */
+int ifeti_recover_displacement(ifeti_ctx *ctx, const double *v, const double *y, double *u, int nrhs);
+
+/* Solve (16) by right-preconditioned flexible GMRES with the block
+ * preconditioner (44) (Algorithm 1), x_0 = 0, until ||b - A x|| <= tol ||b||
+ * for every rhs.  f dev nU x nrhs, d dev L x nrhs, u dev nU x nrhs,
+ * lam dev L x nrhs.  inner_tol: relative tolerance of the interface PCG.
+ * outer_iters/inner_iters_total/relres host arrays of nrhs (nullable). */
+int ifeti_solve(ifeti_ctx *ctx, const double *f, const double *d, double *u, double *lam, int nrhs,
+                double tol, int maxit, double inner_tol, int *outer_iters, int *inner_iters_total,
+                double *relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFETI_H */

@@ -1,0 +1,292 @@
+// extern "C" entry points of libifeti (see include/ifeti.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace ifeti {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace ifeti
+
+using namespace ifeti;
+
+template <class F>
+static int guarded(F f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return IFETI_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return IFETI_EINVAL;
+    }
+}
+
+#define REQ(cond, msg) IFETI_REQUIRE(cond, IFETI_EINVAL, msg)
+
+extern "C" {
+
+const char *ifeti_last_error(void) { return g_last_error.c_str(); }
+
+int ifeti_create(ifeti_ctx **out, const ifeti_lattice_desc *d, void *stream) {
+    return guarded([&]() {
+        REQ(out && d, "null argument");
+        *out = nullptr;
+        REQ(d->dim == 2 || d->dim == 3, "dim must be 2 or 3");
+        REQ(d->nx >= 1 && d->ny >= 1 && d->nz >= 1, "cell counts must be >= 1");
+        REQ(d->dim == 3 || d->nz == 1, "nz must be 1 in 2D");
+        REQ(d->n_el >= 1, "n_el must be >= 1");
+        REQ(d->degree == 2, "only quadratic splines (degree 2) are supported");
+        REQ(d->h > 0 && d->E_in > 0 && d->E_out > 0, "h and moduli must be positive");
+        REQ(d->nu > -1.0 && d->nu < 0.5, "Poisson ratio must lie in (-1, 0.5)");
+        REQ(d->smooth_eps >= 0, "smooth_eps must be >= 0");
+        REQ(d->dirichlet_mask != 0 && (d->dirichlet_mask >> (2 * d->dim)) == 0, "dirichlet_mask must name faces");
+        REQ(d->load_face >= -1 && d->load_face < 2 * d->dim, "load_face out of range");
+        auto *c = new ifeti_ctx();
+        c->desc = *d;
+        c->dim = d->dim;
+        c->shape[0] = d->nx;
+        c->shape[1] = d->ny;
+        c->shape[2] = d->dim == 3 ? d->nz : 1;
+        c->N = c->shape[0] * c->shape[1] * c->shape[2];
+        c->stream = (hipStream_t)stream;
+        try {
+            build_reference_tables(c);
+            build_partition(c);
+            build_decomposition(c);
+            const RefTables &R = c->ref;
+            c->g_tables_w.upload(R.w, c->stream);
+            c->g_tables_xi.upload(R.xi, c->stream);
+            c->g_tables_dN.upload(R.dN, c->stream);
+            c->g_tables_ctrl.upload(R.elem_ctrl, c->stream);
+            c->g_idx_r.upload(c->idx_r, c->stream);
+            c->g_idx_p.upload(c->idx_p, c->stream);
+            IFETI_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            delete c;
+            throw;
+        }
+        *out = c;
+        return IFETI_OK;
+    });
+}
+
+void ifeti_destroy(ifeti_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+int ifeti_get_sizes(const ifeti_ctx *c, ifeti_sizes *o) {
+    return guarded([&]() {
+        REQ(c && o, "null argument");
+        o->N = c->N;
+        o->dim = c->dim;
+        o->n_ctrl = c->ref.n_ctrl;
+        o->n_dof = c->ref.n_dof;
+        o->n_i = c->n_i;
+        o->n_d = c->n_d;
+        o->n_p = c->n_p;
+        o->n_r = c->n_r;
+        o->L = c->L;
+        o->L_interface = c->L_int;
+        o->nP = c->nP;
+        o->nU = c->nU;
+        o->K = c->K;
+        o->nrhs = c->nrhs;
+        return IFETI_OK;
+    });
+}
+
+int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
+    return guarded([&]() {
+        REQ(c && opt, "null argument");
+        REQ(opt->precision == IFETI_FP64, "only the FP64 precision form is available in this build");
+        REQ(opt->pcg_check_every >= 1, "pcg_check_every must be >= 1");
+        REQ(opt->fgmres_restart >= 1, "fgmres_restart must be >= 1");
+        c->opt.precision = opt->precision;
+        c->opt.pcg_check_every = opt->pcg_check_every;
+        c->opt.fgmres_restart = opt->fgmres_restart;
+        return IFETI_OK;
+    });
+}
+
+int ifeti_build_cells(ifeti_ctx *c, const double *ctrl_pts, const double *widths, const double *tractions,
+                      int nrhs) {
+    return guarded([&]() {
+        REQ(c && ctrl_pts && widths, "null argument");
+        REQ(nrhs >= 1, "nrhs must be >= 1");
+        REQ(tractions || c->desc.load_face < 0, "tractions required when a load face is set");
+        const RefTables &R = c->ref;
+        const int N = c->N;
+        c->ctrl.alloc((size_t)N * R.n_ctrl * c->dim);
+        IFETI_HIP(hipMemcpyAsync(c->ctrl.p, ctrl_pts, c->ctrl.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        c->widths.alloc(N);
+        IFETI_HIP(hipMemcpyAsync(c->widths.p, widths, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        std::vector<double> hw(N);
+        IFETI_HIP(hipMemcpyAsync(hw.data(), widths, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        for (double w : hw) REQ(std::isfinite(w) && w > 0.0, "strut widths must be positive and finite");
+        c->nrhs = nrhs;
+        c->tractions.assign((size_t)nrhs * c->dim, 0.0);
+        if (tractions) std::memcpy(c->tractions.data(), tractions, c->tractions.size() * sizeof(double));
+        c->snap.alloc((size_t)N * R.n_snap);
+        c->Kst.alloc((size_t)N * R.n_ctrl * R.n_off * c->dim * c->dim);
+        launch_pulled_back(c);
+        launch_stiffness(c);
+        build_loads(c);
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        c->cells_built = true;
+        c->snap_valid = true;
+        c->rom_built = false;
+        return IFETI_OK;
+    });
+}
+
+int ifeti_get_rhs(ifeti_ctx *c, double *f, double *d) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        if (f)
+            IFETI_HIP(hipMemcpyAsync(f, c->f_vec.p, c->f_vec.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        if (d)
+            IFETI_HIP(hipMemcpyAsync(d, c->d_vec.p, c->d_vec.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        return IFETI_OK;
+    });
+}
+
+int ifeti_build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in,
+                              int *principal_out, double *theta_out) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        REQ(n_principal >= 1 && n_principal <= c->N, "n_principal must be in [1, N]");
+        REQ(n_principal <= 40, "at most 40 principal cells are supported");
+        REQ(tol_rb >= 0.0, "tol_rb must be >= 0");
+        if (!c->snap_valid) launch_pulled_back(c);  // the greedy consumes the snapshots
+        c->snap_valid = false;
+        c->rom_built = false;
+        build_reduced_basis(c, n_principal, tol_rb, principal_in);
+        if (principal_out)
+            for (int k = 0; k < c->K; ++k) principal_out[k] = c->sigma[k];
+        if (theta_out)
+            IFETI_HIP(hipMemcpyAsync(theta_out, c->alpha.p, c->alpha.n * sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream));
+        ensure_work(c, 1);
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        return IFETI_OK;
+    });
+}
+
+int ifeti_get_coefficients(ifeti_ctx *c, double *alpha, double *pi, double *delta) {
+    return guarded([&]() {
+        REQ(c && c->rom_built, "reduced basis not built");
+        if (alpha) std::memcpy(alpha, c->h_alpha.data(), c->h_alpha.size() * sizeof(double));
+        if (pi) std::memcpy(pi, c->h_pi.data(), c->h_pi.size() * sizeof(double));
+        if (delta) std::memcpy(delta, c->h_delta.data(), c->h_delta.size() * sizeof(double));
+        return IFETI_OK;
+    });
+}
+
+#define ROM_READY(c, nrhs)                                                        \
+    REQ(c && c->rom_built, "reduced basis not built");                           \
+    REQ((nrhs) >= 1 && (long long)c->N * (nrhs) < (1LL << 31), "nrhs out of range")
+
+int ifeti_apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(lam && out && lam != out, "bad pointers");
+        apply_F(c, lam, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(r && out && r != out, "bad pointers");
+        apply_MD(c, r, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(v && z, "bad pointers");
+        apply_U(c, v, z, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(y && x, "bad pointers");
+        apply_Ut(c, y, x, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(v && x && v != x, "bad pointers");
+        apply_Kinv_rom(c, v, x, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        REQ(nrhs >= 1, "nrhs must be >= 1");
+        REQ(x && y && x != y, "bad pointers");
+        apply_A(c, x, y, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit,
+                          int *iters_out, double *relres_out) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(rhs && lam && rhs != lam, "bad pointers");
+        REQ(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+        return solve_interface(c, rhs, lam, nrhs, tol, maxit, iters_out, relres_out);
+    });
+}
+
+int ifeti_recover_displacement(ifeti_ctx *c, const double *v, const double *y, double *u, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(v && y && u && v != u, "bad pointers");
+        DevBuf<double> t;
+        t.alloc((size_t)c->nU * nrhs);
+        apply_Kinv_rom(c, v, u, nrhs);
+        apply_Ut(c, y, t.p, nrhs);
+        // u -= Ůᵀ y
+        std::vector<double> m1(nrhs, -1.0);
+        DevBuf<double> coef;
+        coef.upload(m1, c->stream);
+        multiaxpy(c, t.p, 0, 1, coef.p, 1.0, u, c->nU, c->nU, nrhs);
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        return IFETI_OK;
+    });
+}
+
+int ifeti_solve(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
+                int maxit, double inner_tol, int *outer_iters, int *inner_iters_total, double *relres) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(f && d && u && lam, "bad pointers");
+        REQ(tol > 0 && inner_tol > 0 && maxit >= 1, "tolerances must be > 0 and maxit >= 1");
+        return solve_fgmres(c, f, d, u, lam, nrhs, tol, maxit, inner_tol, outer_iters, inner_iters_total, relres);
+    });
+}
+
+}  // extern "C"

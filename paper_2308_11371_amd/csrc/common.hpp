@@ -1,0 +1,218 @@
+// Internal declarations of the ROM-based inexact FETI-DP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ifeti.h"
+
+namespace ifeti {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+void set_last_error(const std::string &msg);
+
+#define IFETI_HIP(x)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess)                                                                \
+            throw ::ifeti::Error{IFETI_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define IFETI_REQUIRE(cond, code, msg)                                \
+    do {                                                              \
+        if (!(cond)) throw ::ifeti::Error{(code), std::string(msg)};  \
+    } while (0)
+
+// Owned device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        if (count == n && p) return;
+        release();
+        if (count) {
+            hipError_t e = hipMalloc(&p, count * sizeof(T));
+            if (e != hipSuccess) {
+                p = nullptr;
+                throw Error{IFETI_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+            }
+        }
+        n = count;
+    }
+    // grow-only allocation for work buffers (waits for queued work before freeing)
+    void ensure(size_t count, hipStream_t s) {
+        if (count <= n && p) return;
+        if (p) (void)hipStreamSynchronize(s);
+        alloc(count);
+    }
+    void upload(const std::vector<T> &h, hipStream_t s) {
+        alloc(h.size());
+        if (n) IFETI_HIP(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void zero(hipStream_t s) {
+        if (n) IFETI_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
+    }
+};
+
+// Reference-cell tables (eq. (6)): identical for every cell.
+struct RefTables {
+    int dim = 0, n_el = 0, p = 0, nc = 0, n_ctrl = 0, n_dof = 0;
+    int nq1 = 0, nq = 0, n_elem = 0, nloc = 0, n_off = 0, n_snap = 0;
+    std::vector<double> w;        // [E][q] quadrature weight (reference measure)
+    std::vector<double> xi;       // [E][q][dim] reference coordinates
+    std::vector<double> dN;       // [E][q][l][dim] gradients of the local functions
+    std::vector<int> elem_ctrl;   // [E][l] local control point index
+};
+
+// One group of the principal-combined contraction:
+//   Y[:, c] (+)= scale * sum_k coef[cell(c), k] * A_k X[:, c]
+struct GemmGroup {
+    const double *A = nullptr;  // K blocks, each M x Kd row-major, consecutive
+    const double *X = nullptr;  // column c at X + c*ldx, Kd entries
+    const double *coef = nullptr;  // [cell*K + k], or null for 1
+    int Kd = 0, ldx = 0, K = 1;
+    long long xbs = 0;          // stride between right-hand sides (0: ncells*ldx)
+    double scale = 1.0;
+};
+
+struct Options {
+    int precision = IFETI_FP64;
+    int pcg_check_every = 4;
+    int fgmres_restart = 60;
+};
+
+}  // namespace ifeti
+
+struct ifeti_ctx {
+    // ---- description
+    ifeti_lattice_desc desc{};
+    int dim = 0, shape[3] = {1, 1, 1}, N = 0;
+    hipStream_t stream = nullptr;
+    ifeti::Options opt;
+    ifeti::RefTables ref;
+
+    // ---- partition (eq. (12)), host
+    int n_i = 0, n_d = 0, n_p = 0, n_r = 0;
+    std::vector<int> idx_i, idx_d, idx_p, idx_r;
+    std::vector<int> dof_class_pos;     // local dof -> position in r (>=0) or -(1+pos in p)
+    // ---- multipliers and primal assembly, host + device
+    int L = 0, L_int = 0, nP = 0, n_vert_free = 0;
+    long long nU = 0;
+    ifeti::DevBuf<int> g_gather;     // [(s*n_d + j)*2 + t]: sign*(row+1), 0 none
+    ifeti::DevBuf<int> g_scatter;    // [l*2 + t]: sign*(s*n_d + j + 1), 0 none
+    ifeti::DevBuf<double> g_Dw;      // [L] multiplicity weights
+    ifeti::DevBuf<int> g_Ap;         // [s*n_p + j] global primal dof or -1
+    ifeti::DevBuf<int> g_Ppull;      // [P*maxc + t]: s*n_p + j, -1 none
+    int maxc = 0;
+    std::vector<int> h_Ap;
+    std::vector<double> h_d;         // Dirichlet data (zero: clamped faces)
+
+    // ---- cells (device)
+    int nrhs = 0;
+    std::vector<double> tractions;
+    ifeti::DevBuf<double> ctrl;      // [s][a][dim]
+    ifeti::DevBuf<double> widths;    // [s]
+    ifeti::DevBuf<double> snap;      // [s][E][q][dim^4] pulled-back tensor (greedy snapshots)
+    ifeti::DevBuf<double> Kst;       // [s][a][o][dim][dim] stencil stiffness values
+    ifeti::DevBuf<double> f_cells;   // [rhs][s][n_dof]
+    ifeti::DevBuf<double> f_vec;     // [rhs][nU]
+    ifeti::DevBuf<double> d_vec;     // [rhs][L]
+    ifeti::DevBuf<int> r_of_dof;     // [n_dof] r position or -1
+    ifeti::DevBuf<int> p_of_dof;     // [n_dof] p position or -1
+    ifeti::DevBuf<int> g_tables_ctrl;  // ref elem_ctrl
+    ifeti::DevBuf<int> g_idx_r, g_idx_p;  // local dof of each r / p position
+    ifeti::DevBuf<double> g_tables_w, g_tables_xi, g_tables_dN;
+    bool cells_built = false;
+    bool snap_valid = false;         // snapshots not yet consumed by a greedy
+
+    // ---- reduced basis (device unless noted)
+    int K = 0;
+    std::vector<int> sigma;
+    std::vector<double> h_alpha, h_pi, h_delta;   // [s*K + k]
+    ifeti::DevBuf<double> alpha, pi, delta;
+    ifeti::DevBuf<double> Fdd, Sdd;     // [k][n_d][n_d]
+    ifeti::DevBuf<double> W;            // [k][n_d][n_p]   T_dr U_rp
+    ifeti::DevBuf<double> WT;           // [k][n_p][n_d]
+    ifeti::DevBuf<double> UrdT;         // [k][n_d][n_r]
+    ifeti::DevBuf<double> Urd;          // [k][n_r][n_d]
+    ifeti::DevBuf<double> Urp;          // [k][n_r][n_p]
+    ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
+    ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
+    ifeti::DevBuf<double> Kst_pr;       // [k][a][o][dim][dim] principal stencil values
+    ifeti::DevBuf<double> SPPinv;       // [nP][nP]
+    bool rom_built = false;
+
+    // ---- work buffers
+    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_x, w_tmpL, w_tmpU;
+    ifeti::DevBuf<double> w_red;        // reduction partials
+    ifeti::DevBuf<double> w_scal;       // PCG scalars
+    ifeti::DevBuf<int> w_iflag;
+};
+
+namespace ifeti {
+// setup_host.cpp
+void build_reference_tables(ifeti_ctx *c);
+void build_partition(ifeti_ctx *c);
+void build_decomposition(ifeti_ctx *c);
+void build_loads(ifeti_ctx *c);
+void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in);
+
+// kernels_setup.hip
+void launch_pulled_back(ifeti_ctx *c);
+void launch_stiffness(ifeti_ctx *c);
+int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in,
+                  std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
+void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw);
+
+// gemm.hip
+// Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
+void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
+          bool accumulate, int ncells = 0);
+
+// ops.hip
+void ensure_work(ifeti_ctx *c, int nrhs);
+void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights);
+void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
+                int nrhs, bool weights);
+void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long long b_rs, double sgn, double *zP,
+                        long long z_rs, int nrhs);
+void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs);
+void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
+                     double scale);
+void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs);
+void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs);
+void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs);
+void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs);
+void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs);
+void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs);
+void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs);
+int reduce_blocks(long long n);
+void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
+              int nrhs, double *out_dev);
+void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
+               long long n, long long rs, int nrhs);
+void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs);
+
+// solver.hip
+int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
+                    double *relres);
+int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
+                 int maxit, double inner_tol, int *outer, int *inner_total, double *relres);
+}  // namespace ifeti

@@ -1,0 +1,415 @@
+// Device kernels of the offline phase: pulled-back material tensor and cell
+// stiffness (Sec. 4.2.1, eq. (52)), greedy sweeps (Algorithm 4), explicit
+// coarse inverse from the banded Cholesky factor (Sec. 3.2.1).
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace ifeti {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline double seg_dist2d(double x, double y, double ax, double ay, double bx, double by) {
+    double ux = bx - ax, uy = by - ay;
+    double t = ((x - ax) * ux + (y - ay) * uy) / (ux * ux + uy * uy);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    double dx = x - (ax + t * ux), dy = y - (ay + t * uy);
+    return sqrt(dx * dx + dy * dy);
+}
+
+// Distance from a reference point to the nearest strut axis.  2D: the four
+// cell edges and both diagonals (Euclidean); 3D: the twelve cube edges
+// (Chebyshev distance across the edge).
+template <int D>
+__device__ double strut_distance(const double *xi) {
+    if constexpr (D == 2) {
+        double x = xi[0], y = xi[1];
+        double d = seg_dist2d(x, y, 0, 0, 1, 0);
+        d = fmin(d, seg_dist2d(x, y, 1, 0, 1, 1));
+        d = fmin(d, seg_dist2d(x, y, 1, 1, 0, 1));
+        d = fmin(d, seg_dist2d(x, y, 0, 1, 0, 0));
+        d = fmin(d, seg_dist2d(x, y, 0, 0, 1, 1));
+        d = fmin(d, seg_dist2d(x, y, 1, 0, 0, 1));
+        return d;
+    } else {
+        double best = 1e300;
+        for (int axis = 0; axis < 3; ++axis) {
+            int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+            for (int c1 = 0; c1 < 2; ++c1)
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    double d = fmax(fabs(xi[o1] - c1), fabs(xi[o2] - c2));
+                    best = fmin(best, d);
+                }
+        }
+        return best;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pulled_back(const double *__restrict__ ctrl,
+                                                        const double *__restrict__ widths,
+                                                        const double *__restrict__ xi,
+                                                        const double *__restrict__ dN,
+                                                        const int *__restrict__ elem_ctrl, int N, int nE, int nq,
+                                                        int nloc, int n_ctrl, double E_in, double E_out, double nu,
+                                                        double eps, double h, double *__restrict__ snap,
+                                                        int *__restrict__ bad) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)N * nE * nq;
+    if (t >= total) return;
+    int q = (int)(t % nq);
+    int E = (int)((t / nq) % nE);
+    int s = (int)(t / ((long long)nq * nE));
+    double J[D][D];
+#pragma unroll
+    for (int m = 0; m < D; ++m)
+#pragma unroll
+        for (int j = 0; j < D; ++j) J[m][j] = 0.0;
+    const double *dNq = dN + (size_t)(E * nq + q) * nloc * D;
+    for (int l = 0; l < nloc; ++l) {
+        int a = elem_ctrl[E * nloc + l];
+        const double *P = ctrl + ((size_t)s * n_ctrl + a) * D;
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+#pragma unroll
+            for (int j = 0; j < D; ++j) J[m][j] += P[m] * dNq[l * D + j];
+    }
+    double det, G[D][D];  // G = J^-1, G[j][m]
+    if constexpr (D == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        G[0][0] = J[1][1] / det;
+        G[0][1] = -J[0][1] / det;
+        G[1][0] = -J[1][0] / det;
+        G[1][1] = J[0][0] / det;
+    } else {
+        double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        G[0][0] = c00 / det;
+        G[1][0] = c01 / det;
+        G[2][0] = c02 / det;
+        G[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        G[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        G[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        G[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        G[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        G[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    if (!(det > 0.0)) atomicOr(bad, 1);
+    // ersatz material: E_in inside the struts, E_out elsewhere (optionally tanh-smoothed)
+    double dist = strut_distance<D>(xi + (size_t)(E * nq + q) * D) * h;
+    double half = 0.5 * widths[s];
+    double Ey;
+    if (eps > 0.0)
+        Ey = E_out + (E_in - E_out) * 0.5 * (1.0 + tanh((half - dist) / eps));
+    else
+        Ey = dist < half ? E_in : E_out;
+    double lam = Ey * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double mu = Ey / (2.0 * (1.0 + nu));
+    double *out = snap + (size_t)t * D * D * D * D;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    double gg = 0.0;
+#pragma unroll
+                    for (int m = 0; m < D; ++m) gg += G[j][m] * G[l][m];
+                    double v = lam * G[j][i] * G[l][k] + mu * ((i == k ? gg : 0.0) + G[j][k] * G[l][i]);
+                    out[((i * D + j) * D + k) * D + l] = det * v;
+                }
+}
+
+// Stiffness block (a, b = a + offset) of every cell, gathered over the
+// elements shared by the supports of N_a and N_b (no atomics).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_stiffness(const double *__restrict__ snap,
+                                                      const double *__restrict__ wq,
+                                                      const double *__restrict__ dN, int N, int n_el, int p,
+                                                      int nc, int nq, int nloc, int n_off,
+                                                      double *__restrict__ Kst) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int n_ctrl = 1;
+    for (int j = 0; j < D; ++j) n_ctrl *= nc;
+    long long total = (long long)N * n_ctrl * n_off;
+    if (t >= total) return;
+    int o = (int)(t % n_off);
+    int a = (int)((t / n_off) % n_ctrl);
+    int s = (int)(t / ((long long)n_off * n_ctrl));
+    int ma[D], mb[D], lo[D], hi[D];
+    int w = 2 * p + 1;
+    bool valid = true;
+    {
+        int ta = a, to = o;
+        for (int j = 0; j < D; ++j) {
+            ma[j] = ta % nc;
+            ta /= nc;
+            mb[j] = ma[j] + (to % w) - p;
+            to /= w;
+            if (mb[j] < 0 || mb[j] >= nc) valid = false;
+            lo[j] = max(max(ma[j], mb[j]) - p, 0);
+            hi[j] = min(min(ma[j], mb[j]), n_el - 1);
+            if (lo[j] > hi[j]) valid = false;
+        }
+    }
+    double Kb[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) Kb[i][k] = 0.0;
+    int nE = 1;
+    for (int j = 0; j < D; ++j) nE *= n_el;
+    if (valid) {
+        int e[D];
+        for (int j = 0; j < D; ++j) e[j] = lo[j];
+        while (true) {
+            int E = 0, la = 0, lb = 0;
+            for (int j = D - 1; j >= 0; --j) {
+                E = E * n_el + e[j];
+                la = la * (p + 1) + (ma[j] - e[j]);
+                lb = lb * (p + 1) + (mb[j] - e[j]);
+            }
+            for (int q = 0; q < nq; ++q) {
+                const double *dNa = dN + ((size_t)(E * nq + q) * nloc + la) * D;
+                const double *dNb = dN + ((size_t)(E * nq + q) * nloc + lb) * D;
+                const double *C = snap + ((size_t)((long long)s * nE + E) * nq + q) * D * D * D * D;
+                double wv = wq[E * nq + q];
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int j = 0; j < D; ++j)
+#pragma unroll
+                            for (int l = 0; l < D; ++l) acc += dNa[j] * C[((i * D + j) * D + k) * D + l] * dNb[l];
+                        Kb[i][k] += wv * acc;
+                    }
+            }
+            int j = 0;
+            for (; j < D; ++j) {
+                if (++e[j] <= hi[j]) break;
+                e[j] = lo[j];
+            }
+            if (j == D) break;
+        }
+    }
+    double *out = Kst + (size_t)t * D * D;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) out[i * D + k] = Kb[i][k];
+}
+
+// -------------------------------------------------------------- greedy sweeps
+__device__ inline double block_sum(double v, double *sh) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) sh[tid] += sh[tid + off];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) sh[tid] = fmax(sh[tid], sh[tid + off]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// norms[s] = ||A_s||_2, then A_s /= norms[s]; absmax[s] = ||A_s||_inf afterwards.
+__global__ __launch_bounds__(kBlock) void k_normalise_rows(double *__restrict__ A, long long n,
+                                                           double *__restrict__ norms, double *__restrict__ absmax) {
+    __shared__ double sh[kBlock];
+    double *row = A + (size_t)blockIdx.x * n;
+    double s2 = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) s2 += row[i] * row[i];
+    double nrm = sqrt(block_sum(s2, sh));
+    double inv = 1.0 / nrm;
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = row[i] * inv;
+        row[i] = v;
+        mx = fmax(mx, fabs(v));
+    }
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        norms[blockIdx.x] = nrm;
+        absmax[blockIdx.x] = mx;
+    }
+}
+
+// zeta = A_sigma / ||A_sigma||
+__global__ __launch_bounds__(kBlock) void k_make_zeta(const double *__restrict__ A, long long n, int sigma,
+                                                      double *__restrict__ z) {
+    __shared__ double sh[kBlock];
+    const double *row = A + (size_t)sigma * n;
+    double s2 = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) s2 += row[i] * row[i];
+    double inv = 1.0 / sqrt(block_sum(s2, sh));
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) z[i] = row[i] * inv;
+}
+
+// beta_s = Delta_s . zeta; Delta_s -= beta_s zeta; absmax_s = ||Delta_s||_inf
+__global__ __launch_bounds__(kBlock) void k_gs_update(double *__restrict__ A, long long n,
+                                                      const double *__restrict__ z, double *__restrict__ beta,
+                                                      double *__restrict__ absmax) {
+    __shared__ double sh[kBlock];
+    double *row = A + (size_t)blockIdx.x * n;
+    double dot = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) dot += row[i] * z[i];
+    double b = block_sum(dot, sh);
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = row[i] - b * z[i];
+        row[i] = v;
+        mx = fmax(mx, fabs(v));
+    }
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        beta[blockIdx.x] = b;
+        absmax[blockIdx.x] = mx;
+    }
+}
+
+// Column j of (L L^T)^-1 for a banded lower factor band[i*(bw+1) + (i-k)] = L[i][k].
+__global__ __launch_bounds__(kBlock) void k_band_inverse(const double *__restrict__ band, int n, int bw,
+                                                         double *__restrict__ X) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int ld = bw + 1;
+    for (int i = 0; i < j; ++i) X[(size_t)i * n + j] = 0.0;
+    for (int i = j; i < n; ++i) {  // forward: L y = e_j
+        double t = (i == j) ? 1.0 : 0.0;
+        int k0 = max(j, i - bw);
+        const double *Li = band + (size_t)i * ld;
+        for (int k = k0; k < i; ++k) t -= Li[i - k] * X[(size_t)k * n + j];
+        X[(size_t)i * n + j] = t / Li[0];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // backward: L^T x = y
+        double t = X[(size_t)i * n + j];
+        int k1 = min(n - 1, i + bw);
+        for (int k = i + 1; k <= k1; ++k) t -= band[(size_t)k * ld + (k - i)] * X[(size_t)k * n + j];
+        X[(size_t)i * n + j] = t / band[(size_t)i * ld];
+    }
+}
+
+inline unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_pulled_back(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    DevBuf<int> bad;
+    bad.alloc(1);
+    bad.zero(c->stream);
+    long long total = (long long)c->N * R.n_elem * R.nq;
+    const auto &d = c->desc;
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_pulled_back<2>, dim3(blocks_for(total)), dim3(kBlock), 0, c->stream, c->ctrl.p,
+                           c->widths.p, c->g_tables_xi.p, c->g_tables_dN.p, c->g_tables_ctrl.p, c->N, R.n_elem,
+                           R.nq, R.nloc, R.n_ctrl, d.E_in, d.E_out, d.nu, d.smooth_eps, d.h, c->snap.p, bad.p);
+    else
+        hipLaunchKernelGGL(k_pulled_back<3>, dim3(blocks_for(total)), dim3(kBlock), 0, c->stream, c->ctrl.p,
+                           c->widths.p, c->g_tables_xi.p, c->g_tables_dN.p, c->g_tables_ctrl.p, c->N, R.n_elem,
+                           R.nq, R.nloc, R.n_ctrl, d.E_in, d.E_out, d.nu, d.smooth_eps, d.h, c->snap.p, bad.p);
+    IFETI_HIP(hipGetLastError());
+    int hbad = 0;
+    IFETI_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    IFETI_REQUIRE(hbad == 0, IFETI_EINVAL, "a cell map has a non-positive Jacobian determinant");
+}
+
+void launch_stiffness(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    long long total = (long long)c->N * R.n_ctrl * R.n_off;
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_stiffness<2>, dim3(blocks_for(total)), dim3(kBlock), 0, c->stream, c->snap.p,
+                           c->g_tables_w.p, c->g_tables_dN.p, c->N, R.n_el, R.p, R.nc, R.nq, R.nloc, R.n_off,
+                           c->Kst.p);
+    else
+        hipLaunchKernelGGL(k_stiffness<3>, dim3(blocks_for(total)), dim3(kBlock), 0, c->stream, c->snap.p,
+                           c->g_tables_w.p, c->g_tables_dN.p, c->N, R.n_el, R.p, R.nc, R.nq, R.nloc, R.n_off,
+                           c->Kst.p);
+    IFETI_HIP(hipGetLastError());
+}
+
+// Algorithm 4 on the snapshots held in c->snap (overwritten by the residuals).
+int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in, std::vector<int> &sigma,
+                  std::vector<double> &beta, std::vector<double> &norms) {
+    const int N = c->N;
+    const long long n = c->ref.n_snap;
+    DevBuf<double> d_norm, d_absmax, d_beta, d_z;
+    d_norm.alloc(N);
+    d_absmax.alloc(N);
+    d_beta.alloc(N);
+    d_z.alloc(n);
+    hipLaunchKernelGGL(k_normalise_rows, dim3(N), dim3(kBlock), 0, c->stream, c->snap.p, n, d_norm.p, d_absmax.p);
+    IFETI_HIP(hipGetLastError());
+    norms.assign(N, 0.0);
+    std::vector<double> absmax(N), b(N);
+    IFETI_HIP(hipMemcpyAsync(norms.data(), d_norm.p, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    std::vector<std::vector<double>> betas;
+    sigma.clear();
+    for (int i = 0; i < n_principal; ++i) {
+        IFETI_HIP(hipMemcpyAsync(absmax.data(), d_absmax.p, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        int s;
+        if (principal_in) {
+            s = principal_in[i];
+            IFETI_REQUIRE(s >= 0 && s < N, IFETI_EINVAL, "principal cell index out of range");
+        } else {
+            double mx = *std::max_element(absmax.begin(), absmax.end());
+            if (!(mx > tol_rb)) break;
+            s = -1;
+            for (int t = 0; t < N; ++t)
+                if (absmax[t] >= mx * (1.0 - 1e-12)) {
+                    s = t;
+                    break;
+                }
+        }
+        hipLaunchKernelGGL(k_make_zeta, dim3(1), dim3(kBlock), 0, c->stream, c->snap.p, n, s, d_z.p);
+        hipLaunchKernelGGL(k_gs_update, dim3(N), dim3(kBlock), 0, c->stream, c->snap.p, n, d_z.p, d_beta.p,
+                           d_absmax.p);
+        IFETI_HIP(hipGetLastError());
+        IFETI_HIP(hipMemcpyAsync(b.data(), d_beta.p, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        sigma.push_back(s);
+        betas.push_back(b);
+    }
+    const int K = (int)sigma.size();
+    IFETI_REQUIRE(K > 0, IFETI_EINVAL, "greedy selected no principal cell");
+    beta.assign((size_t)N * K, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int s = 0; s < N; ++s) beta[(size_t)s * K + k] = betas[k][s];
+    return K;
+}
+
+void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw) {
+    DevBuf<double> band;
+    band.upload(band_L, c->stream);
+    c->SPPinv.alloc((size_t)c->nP * c->nP);
+    hipLaunchKernelGGL(k_band_inverse, dim3(blocks_for(c->nP, 64)), dim3(64), 0, c->stream, band.p, c->nP, bw,
+                       c->SPPinv.p);
+    IFETI_HIP(hipGetLastError());
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace ifeti

@@ -1,0 +1,688 @@
+// Online operators of the ROM-based inexact FETI-DP preconditioner (paper
+// Sec. 3.2): jump gather/scatter (eq. (15)), primal assembly (eq. (18)), coarse
+// solve (Sec. 3.2.1), F̊ (48), M̊_D^-1 (49), Ů / Ůᵀ (Algorithm 3), K̊^-ROM
+// (eqs. (45)-(46), Algorithm 2), the true saddle operator (16), and the
+// vector kernels of the Krylov solvers.
+//
+// Cell vectors are cell-major: column c = rhs*N + s holds cell s of load case
+// rhs.  Scatters are pull-based (every multiplier row reads its at most two
+// signed endpoints, every primal dof its at most 2^d cell corners), so results
+// are bitwise reproducible and no floating-point atomics are used.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace ifeti {
+namespace {
+
+constexpr int kB = 256;
+inline unsigned nblocks(long long n, int b = kB) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ B_d^T, B_d
+__global__ __launch_bounds__(kB) void k_gather(const int *__restrict__ gl, const double *__restrict__ Dw,
+                                               const double *__restrict__ lam, long long lam_rs,
+                                               double *__restrict__ out, int N, int n_d, int nrhs, int weights) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long per = (long long)N * n_d;
+    if (t >= per * nrhs) return;
+    int rhs = (int)(t / per);
+    long long sj = t % per;
+    const double *l = lam + rhs * lam_rs;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        int code = gl[sj * 2 + u];
+        if (code == 0) continue;
+        int row = (code > 0 ? code : -code) - 1;
+        double x = l[row] * (weights ? Dw[row] : 1.0);
+        v += code > 0 ? x : -x;
+    }
+    out[t] = v;
+}
+
+__global__ __launch_bounds__(kB) void k_scatter(const int *__restrict__ sl, const double *__restrict__ Dw,
+                                                const double *__restrict__ Y, int y_ld, int y_off, long long y_rs,
+                                                double *__restrict__ out, long long out_rs, int L, int n_d, int nrhs,
+                                                int weights) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)L * nrhs) return;
+    int rhs = (int)(t / L), l = (int)(t % L);
+    const double *y = Y + rhs * y_rs;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        int code = sl[(size_t)l * 2 + u];
+        if (code == 0) continue;
+        int e = (code > 0 ? code : -code) - 1;
+        int s = e / n_d, j = e % n_d;
+        double x = y[(size_t)s * y_ld + y_off + j];
+        v += code > 0 ? x : -x;
+    }
+    out[rhs * out_rs + l] = weights ? v * Dw[l] : v;
+}
+
+// ------------------------------------------------------------------ A_p, A_p^T
+__global__ __launch_bounds__(kB) void k_assemble_primal(const int *__restrict__ pull, int maxc,
+                                                        const double *__restrict__ cp, int N, int n_p,
+                                                        const double *__restrict__ base, long long b_rs, double sgn,
+                                                        double *__restrict__ zP, long long z_rs, int nP, int nrhs) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nP * nrhs) return;
+    int rhs = (int)(t / nP), P = (int)(t % nP);
+    double v = 0.0;
+    for (int u = 0; u < maxc; ++u) {
+        int e = pull[(size_t)P * maxc + u];
+        if (e < 0) break;
+        v += cp[((size_t)rhs * N) * n_p + e];
+    }
+    double b = base ? base[rhs * b_rs + P] : 0.0;
+    zP[rhs * z_rs + P] = b + sgn * v;
+}
+
+__global__ __launch_bounds__(kB) void k_restrict_primal(const int *__restrict__ Ap, const double *__restrict__ xP,
+                                                        long long x_rs, double *__restrict__ xp, int N, int n_p,
+                                                        int nrhs) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long per = (long long)N * n_p;
+    if (t >= per * nrhs) return;
+    int rhs = (int)(t / per);
+    int P = Ap[t % per];
+    xp[t] = P >= 0 ? xP[rhs * x_rs + P] : 0.0;
+}
+
+// ------------------------------------------------------------------ coarse solve, one wave per row
+__global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S, int n, const double *__restrict__ z,
+                                                    double *__restrict__ y, double scale) {
+    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (wave >= n) return;
+    const double *row = S + (size_t)wave * n;
+    double acc = 0.0;
+    if ((n & 1) == 0) {  // rows start 16-byte aligned: paired loads
+        const double2 *r2 = reinterpret_cast<const double2 *>(row);
+        const double2 *z2 = reinterpret_cast<const double2 *>(z);
+        for (int i = lane; i < n / 2; i += 64) {
+            double2 a = r2[i], b = z2[i];
+            acc += a.x * b.x + a.y * b.y;
+        }
+    } else {
+        for (int i = lane; i < n; i += 64) acc += row[i] * z[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) y[wave] = scale * acc;
+}
+
+// ------------------------------------------------------------------ reduced local solve (46), Gram part
+// One workgroup per column c (cell s, load case rhs).  R_c holds the K
+// reduced-basis vectors K_rr^(sigma_k)^-1 v (column-major, n_r x K).  The Gram
+// matrix G = R^T K̃_s R uses K̃_s = sum_m alpha_m K_rr^(sigma_m) evaluated on the
+// fly from the principal stencil values; G c = R^T v is solved by Cholesky
+// (symmetric pseudo-inverse with a 1e-13 relative cut if a pivot fails) and
+// x = R c is written.
+constexpr int kRomChunk = 64;
+constexpr int kMaxK = 40;
+constexpr int kHGroups = kB / kRomChunk;                       // threads per row of a chunk
+constexpr int kHMax = (kMaxK + kHGroups - 1) / kHGroups;       // columns per thread
+constexpr int kGMax = (kMaxK * kMaxK + kMaxK + kB - 1) / kB;   // Gram entries per thread
+
+// Small dense solve by thread 0: x = A^-1 b for symmetric A (K x K, row-major in
+// shared memory).  Cholesky; if a pivot is not positive, a cyclic Jacobi
+// eigen-decomposition gives the pseudo-inverse with a 1e-13 relative cut.
+__device__ void small_sym_solve(double *A, double *Lm, double *V, const double *b, double *x, int K) {
+    bool ok = true;
+    for (int j = 0; j < K && ok; ++j) {
+        double sj = A[j * K + j];
+        for (int k = 0; k < j; ++k) sj -= Lm[j * K + k] * Lm[j * K + k];
+        if (!(sj > 0.0)) {
+            ok = false;
+            break;
+        }
+        double l = sqrt(sj);
+        Lm[j * K + j] = l;
+        for (int i = j + 1; i < K; ++i) {
+            double t = A[i * K + j];
+            for (int k = 0; k < j; ++k) t -= Lm[i * K + k] * Lm[j * K + k];
+            Lm[i * K + j] = t / l;
+        }
+    }
+    if (ok) {
+        for (int i = 0; i < K; ++i) {
+            double t = b[i];
+            for (int k = 0; k < i; ++k) t -= Lm[i * K + k] * x[k];
+            x[i] = t / Lm[i * K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double t = x[i];
+            for (int k = i + 1; k < K; ++k) t -= Lm[k * K + i] * x[k];
+            x[i] = t / Lm[i * K + i];
+        }
+        return;
+    }
+    for (int i = 0; i < K * K; ++i) V[i] = 0.0;
+    for (int i = 0; i < K; ++i) V[i * K + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j) {
+                double a = A[i * K + j];
+                tot += a * a;
+                if (i != j) off += a * a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int pp = 0; pp < K; ++pp)
+            for (int q = pp + 1; q < K; ++q) {
+                double apq = A[pp * K + q];
+                if (apq == 0.0) continue;
+                double th = (A[q * K + q] - A[pp * K + pp]) / (2.0 * apq);
+                double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < K; ++k) {
+                    double akp = A[k * K + pp], akq = A[k * K + q];
+                    A[k * K + pp] = cs * akp - sn * akq;
+                    A[k * K + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < K; ++k) {
+                    double apk = A[pp * K + k], aqk = A[q * K + k];
+                    A[pp * K + k] = cs * apk - sn * aqk;
+                    A[q * K + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < K; ++k) {
+                    double vkp = V[k * K + pp], vkq = V[k * K + q];
+                    V[k * K + pp] = cs * vkp - sn * vkq;
+                    V[k * K + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    double wmax = 0.0;
+    for (int i = 0; i < K; ++i) wmax = fmax(wmax, A[i * K + i]);
+    for (int i = 0; i < K; ++i) x[i] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double wk = A[k * K + k];
+        if (!(wk > 1e-13 * wmax)) continue;
+        double proj = 0.0;
+        for (int i = 0; i < K; ++i) proj += V[i * K + k] * b[i];
+        proj /= wk;
+        for (int i = 0; i < K; ++i) x[i] += proj * V[i * K + k];
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kB) void k_rom_local(const double *__restrict__ vR, long long v_rs,
+                                                  const double *__restrict__ R, const double *__restrict__ alpha,
+                                                  const double *__restrict__ Kpr, const int *__restrict__ r_of_dof,
+                                                  const int *__restrict__ idx_r, int N, int K, int n_r, int nc,
+                                                  int n_ctrl, int n_off, int p, double *__restrict__ xR,
+                                                  long long x_rs) {
+    constexpr int LDR = kRomChunk + 1;
+    __shared__ double sm[2 * kMaxK * LDR];       // R and H chunks; reused by the small solve
+    __shared__ double G[kMaxK * kMaxK + kMaxK];  // Gram matrix, then R^T v
+    __shared__ double vs[kRomChunk];
+    __shared__ double cvec[kMaxK];
+    __shared__ double al[kMaxK];
+    double *Rs = sm, *Hs = sm + kMaxK * LDR;
+    const int col = blockIdx.x;
+    const int rhs = col / N, s = col % N;
+    const int tid = threadIdx.x;
+    const double *v = vR + rhs * v_rs + (size_t)s * n_r;
+    const double *Rc = R + (size_t)col * K * n_r;
+    if (tid < K) al[tid] = alpha[(size_t)s * K + tid];
+    const int KK = K * K, npair = KK + K;
+    double gacc[kGMax];
+#pragma unroll
+    for (int u = 0; u < kGMax; ++u) gacc[u] = 0.0;
+    const int w = 2 * p + 1;
+    const size_t mstride = (size_t)n_ctrl * n_off * D * D;
+    __syncthreads();
+    for (int r0 = 0; r0 < n_r; r0 += kRomChunk) {
+        const int rl = tid % kRomChunk, kg = tid / kRomChunk;
+        const int row = r0 + rl;
+        double h[kHMax];
+#pragma unroll
+        for (int u = 0; u < kHMax; ++u) h[u] = 0.0;
+        if (row < n_r) {
+            const int dof = idx_r[row];
+            const int a = dof / D, i = dof % D;
+            int ma[D];
+            int ta = a;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                ma[j] = ta % nc;
+                ta /= nc;
+            }
+            for (int o = 0; o < n_off; ++o) {
+                int to = o, b = 0;
+                bool ok = true;
+                int mb[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    mb[j] = ma[j] + (to % w) - p;
+                    to /= w;
+                    if (mb[j] < 0 || mb[j] >= nc) ok = false;
+                }
+                if (!ok) continue;
+#pragma unroll
+                for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const int rc = r_of_dof[b * D + k];
+                    if (rc < 0) continue;
+                    const size_t off = (((size_t)a * n_off + o) * D + i) * D + k;
+                    double val = 0.0;
+                    for (int m = 0; m < K; ++m) val += al[m] * Kpr[m * mstride + off];   // K̃_s entry
+#pragma unroll
+                    for (int u = 0; u < kHMax; ++u) {
+                        const int kk = kg + u * kHGroups;
+                        if (kk < K) h[u] += val * Rc[(size_t)kk * n_r + rc];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kHMax; ++u) {
+            const int kk = kg + u * kHGroups;
+            if (kk < K) {
+                Hs[kk * LDR + rl] = row < n_r ? h[u] : 0.0;
+                Rs[kk * LDR + rl] = row < n_r ? Rc[(size_t)kk * n_r + row] : 0.0;
+            }
+        }
+        if (kg == 0) vs[rl] = row < n_r ? v[row] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kGMax; ++u) {
+            const int pr = tid + u * kB;
+            if (pr < npair) {
+                double sacc = 0.0;
+                if (pr < KK) {
+                    const int k1 = pr / K, k2 = pr % K;
+                    for (int t = 0; t < kRomChunk; ++t) sacc += Rs[k1 * LDR + t] * Hs[k2 * LDR + t];
+                } else {
+                    const int k1 = pr - KK;
+                    for (int t = 0; t < kRomChunk; ++t) sacc += Rs[k1 * LDR + t] * vs[t];
+                }
+                gacc[u] += sacc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kGMax; ++u) {
+        const int pr = tid + u * kB;
+        if (pr < npair) G[pr] = gacc[u];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double *A = sm, *Lm = sm + KK, *V = sm + 2 * KK;
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j) A[i * K + j] = 0.5 * (G[i * K + j] + G[j * K + i]);
+        small_sym_solve(A, Lm, V, G + KK, cvec, K);
+    }
+    __syncthreads();
+    double *x = xR + rhs * x_rs + (size_t)s * n_r;
+    for (int row = tid; row < n_r; row += kB) {
+        double t = 0.0;
+        for (int k = 0; k < K; ++k) t += Rc[(size_t)k * n_r + row] * cvec[k];
+        x[row] = t;
+    }
+}
+
+// ------------------------------------------------------------------ true cell operator (16)
+// y_R = K_rr u_r + K_rp u_p + B_r^T lam ;  yp (per cell) = K_pr u_r + K_pp u_p
+template <int D>
+__global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, const double *__restrict__ x,
+                                               long long x_rs, long long nU, const int *__restrict__ Ap,
+                                               const int *__restrict__ idx_r, const int *__restrict__ idx_p,
+                                               const int *__restrict__ r_of_dof, const int *__restrict__ p_of_dof,
+                                               const int *__restrict__ gl, int N, int n_r, int n_p, int n_i,
+                                               int n_d, int nc, int n_ctrl, int n_off, int p,
+                                               double *__restrict__ y, long long y_rs,
+                                               double *__restrict__ yp_cells) {
+    extern __shared__ double uloc[];
+    const int col = blockIdx.x;
+    const int rhs = col / N, s = col % N;
+    const int tid = threadIdx.x;
+    const int n_dof = n_ctrl * D;
+    const double *u = x + rhs * x_rs;
+    const double *lam = u + nU;
+    for (int i = tid; i < n_r; i += kB) uloc[idx_r[i]] = u[(size_t)s * n_r + i];
+    for (int j = tid; j < n_p; j += kB) {
+        int P = Ap[(size_t)s * n_p + j];
+        uloc[idx_p[j]] = P >= 0 ? u[(size_t)N * n_r + P] : 0.0;
+    }
+    __syncthreads();
+    const int w = 2 * p + 1;
+    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
+    double *yr = y + rhs * y_rs + (size_t)s * n_r;
+    for (int row = tid; row < n_dof; row += kB) {
+        int a = row / D, i = row % D;
+        int ma[D];
+        int ta = a;
+        for (int j = 0; j < D; ++j) {
+            ma[j] = ta % nc;
+            ta /= nc;
+        }
+        double acc = 0.0;
+        for (int o = 0; o < n_off; ++o) {
+            int to = o, b = 0;
+            bool ok = true;
+            int mb[D];
+            for (int j = 0; j < D; ++j) {
+                mb[j] = ma[j] + (to % w) - p;
+                to /= w;
+                if (mb[j] < 0 || mb[j] >= nc) ok = false;
+            }
+            if (!ok) continue;
+            for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+            const double *blk = Ks + ((size_t)a * n_off + o) * D * D + i * D;
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc += blk[k] * uloc[b * D + k];
+        }
+        int rp = r_of_dof[row];
+        if (rp >= 0) {
+            if (rp >= n_i) {  // dual dof: add B_d^T lam
+                int j = rp - n_i;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    int code = gl[((size_t)s * n_d + j) * 2 + t];
+                    if (code == 0) continue;
+                    double lv = lam[(code > 0 ? code : -code) - 1];
+                    acc += code > 0 ? lv : -lv;
+                }
+            }
+            yr[rp] = acc;
+        } else {
+            yp_cells[(size_t)col * n_p + p_of_dof[row]] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ reductions (deterministic)
+__device__ inline double block_reduce(double v, double *sh) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) sh[tid] += sh[tid + off];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[(rhs*nv + i)*nblk + b] = sum over block b's chunk of V_i . w (per rhs)
+__global__ __launch_bounds__(kB) void k_multidot_partial(const double *__restrict__ V, long long vstride, int nv,
+                                                         const double *__restrict__ w, long long n, long long rs,
+                                                         int nblk, double *__restrict__ partial) {
+    __shared__ double sh[kB];
+    int b = blockIdx.x, rhs = blockIdx.y;
+    long long chunk = (n + nblk - 1) / nblk;
+    long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+    const double *wr = w + rhs * rs;
+    for (int i = 0; i < nv; ++i) {
+        const double *vr = V + i * vstride + rhs * rs;
+        double acc = 0.0;
+        for (long long t = i0 + threadIdx.x; t < i1; t += kB) acc += vr[t] * wr[t];
+        acc = block_reduce(acc, sh);
+        if (threadIdx.x == 0) partial[((size_t)rhs * nv + i) * nblk + b] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_reduce_partials(const double *__restrict__ partial, int nblk,
+                                                        double *__restrict__ out) {
+    __shared__ double sh[kB];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kB) acc += partial[(size_t)blockIdx.x * nblk + b];
+    acc = block_reduce(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// w[rhs] = a*w[rhs] + sum_i coef[rhs*nv + i] * V_i[rhs]
+__global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, long long vstride, int nv,
+                                                  const double *__restrict__ coef, double a, double *__restrict__ w,
+                                                  long long n, long long rs, int nrhs) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    long long i = t % n;
+    double acc = a * w[rhs * rs + i];
+    for (int k = 0; k < nv; ++k) acc += coef[rhs * nv + k] * V[k * vstride + rhs * rs + i];
+    w[rhs * rs + i] = acc;
+}
+
+__global__ __launch_bounds__(kB) void k_scale_copy(const double *__restrict__ x, long long n, long long rs,
+                                                   const double *__restrict__ sc, double *__restrict__ y, int nrhs) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    long long i = t % n;
+    y[rhs * rs + i] = sc[rhs] * x[rhs * rs + i];
+}
+
+}  // namespace
+
+// ================================================================== host wrappers
+void ensure_work(ifeti_ctx *c, int nrhs) {
+    size_t cols = (size_t)c->N * nrhs;
+    hipStream_t s = c->stream;
+    c->w_Lam.ensure(cols * std::max(c->n_d, c->n_p), s);
+    c->w_Y.ensure(cols * c->n_d, s);
+    c->w_c.ensure(cols * c->n_p, s);
+    c->w_yp.ensure(cols * c->n_p, s);
+    c->w_zP.ensure((size_t)std::max(c->nP, 1) * nrhs, s);
+    c->w_yP.ensure((size_t)std::max(c->nP, 1) * nrhs, s);
+    if (c->K > 0) c->w_R.ensure(cols * c->K * c->n_r, s);
+    c->w_red.ensure((size_t)256 * 64 * nrhs + 1024, s);
+}
+
+void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights) {
+    long long n = (long long)c->N * c->n_d * nrhs;
+    hipLaunchKernelGGL(k_gather, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_gather.p, c->g_Dw.p, lam, lam_rs,
+                       Lam, c->N, c->n_d, nrhs, weights ? 1 : 0);
+}
+
+void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
+                int nrhs, bool weights) {
+    long long n = (long long)c->L * nrhs;
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_scatter.p, c->g_Dw.p, Y, y_ld,
+                       y_off, y_rs, out, out_rs, c->L, c->n_d, nrhs, weights ? 1 : 0);
+}
+
+void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long long b_rs, double sgn, double *zP,
+                        long long z_rs, int nrhs) {
+    long long n = (long long)c->nP * nrhs;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_assemble_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ppull.p, c->maxc, cp, c->N,
+                       c->n_p, base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
+}
+
+void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs) {
+    long long n = (long long)c->N * c->n_p * nrhs;
+    hipLaunchKernelGGL(k_restrict_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ap.p, xP, x_rs, xp, c->N,
+                       c->n_p, nrhs);
+}
+
+void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
+                     double scale) {
+    if (c->nP == 0) return;
+    if (nrhs < 4) {
+        for (int r = 0; r < nrhs; ++r)
+            hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks((long long)c->nP * 64)), dim3(kB), 0, c->stream,
+                               c->SPPinv.p, c->nP, z + r * z_rs, y + r * y_rs, scale);
+    } else {
+        GemmGroup g;
+        g.A = c->SPPinv.p;
+        g.X = z;
+        g.Kd = c->nP;
+        g.ldx = (int)z_rs;
+        g.xbs = (long long)nrhs * z_rs;
+        g.K = 1;
+        g.scale = scale;
+        gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs);
+    }
+}
+
+// ------------------------------------------------------------------ F̊ (48)
+void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nd = c->n_d, np = c->n_p, K = c->K;
+    const int cols = N * nrhs;
+    op_gather(c, lam, c->L, c->w_Lam.p, nrhs, false);                       // Lambda = B_d^T lam
+    GemmGroup g0;                                                              // c_s = sum pi_k W_k^T Lambda_s
+    g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
+    op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
+    op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
+    GemmGroup g[2];                                                            // Y = F̊_dd Lambda + (T_dr Ů_rp) y_p
+    g[0].A = c->Fdd.p; g[0].X = c->w_Lam.p; g[0].coef = c->delta.p; g[0].Kd = nd; g[0].ldx = nd; g[0].K = K;
+    g[1].A = c->W.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
+    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false);
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ M̊_D^-1 (49)
+void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nd = c->n_d, K = c->K;
+    op_gather(c, r, c->L, c->w_Lam.p, nrhs, true);
+    GemmGroup g;
+    g.A = c->Sdd.p; g.X = c->w_Lam.p; g.coef = c->alpha.p; g.Kd = nd; g.ldx = nd; g.K = K;
+    gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, true);
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Ů (Algorithm 3)
+void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nd = c->n_d, np = c->n_p, nr = c->n_r, K = c->K;
+    const int cols = N * nrhs;
+    const long long nU = c->nU;
+    GemmGroup g0;  // t_s = Ů_rp^T v_r
+    g0.A = c->UrpT.p; g0.X = v; g0.coef = c->pi.p; g0.Kd = nr; g0.ldx = nr; g0.xbs = nU; g0.K = K;
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    // v̄_P = v_P - Ů_RP^T v_R
+    op_assemble_primal(c, c->w_c.p, v + (size_t)N * nr, nU, -1.0, c->w_zP.p, c->nP, nrhs);
+    op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
+    op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
+    GemmGroup g[2];  // Y = Ů_rd^T v_r - T_dr Ů_rp z_p
+    g[0].A = c->UrdT.p; g[0].X = v; g[0].coef = c->delta.p; g[0].Kd = nr; g[0].ldx = nr; g[0].xbs = nU; g[0].K = K;
+    g[1].A = c->W.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
+    g[1].scale = -1.0;
+    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, z, c->L, nrhs, false);
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Ůᵀ (transpose of Algorithm 3)
+void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nd = c->n_d, np = c->n_p, nr = c->n_r, K = c->K;
+    const int cols = N * nrhs;
+    const long long nU = c->nU;
+    op_gather(c, y, c->L, c->w_Lam.p, nrhs, false);
+    GemmGroup g0;
+    g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
+    double *xP = x + (size_t)N * nr;
+    op_coarse_solve(c, c->w_zP.p, c->nP, xP, nU, nrhs, -1.0);  // x_P = -S̊^-1 Ů_RP^T B_R^T y
+    op_restrict_primal(c, xP, nU, c->w_yp.p, nrhs);
+    GemmGroup g[2];  // x_r = Ů_rd B_d^T y - Ů_rp A_p^T x_P
+    g[0].A = c->Urd.p; g[0].X = c->w_Lam.p; g[0].coef = c->delta.p; g[0].Kd = nd; g[0].ldx = nd; g[0].K = K;
+    g[1].A = c->Urp.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
+    g[1].scale = -1.0;
+    gemm(c, g, 2, x, nr, nU, nr, cols, false);
+    IFETI_HIP(hipGetLastError());
+}
+
+void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs) {
+    const int N = c->N, nr = c->n_r, K = c->K;
+    IFETI_REQUIRE(K <= kMaxK, IFETI_EINVAL, "reduced local solve supports at most 40 principal cells");
+    // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the stacked explicit inverses
+    GemmGroup g;
+    g.A = c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
+    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false);
+    // (46b) per-cell Gram system and combination
+    const RefTables &R = c->ref;
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_rom_local<2>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->alpha.p,
+                           c->Kst_pr.p, c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR,
+                           x_rs);
+    else
+        hipLaunchKernelGGL(k_rom_local<3>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->alpha.p,
+                           c->Kst_pr.p, c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR,
+                           x_rs);
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ K̊^-ROM (45), Algorithm 2
+void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, np = c->n_p, nr = c->n_r, K = c->K;
+    const int cols = N * nrhs;
+    const long long nU = c->nU;
+    GemmGroup g0;
+    g0.A = c->UrpT.p; g0.X = v; g0.coef = c->pi.p; g0.Kd = nr; g0.ldx = nr; g0.xbs = nU; g0.K = K;
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    op_assemble_primal(c, c->w_c.p, v + (size_t)N * nr, nU, -1.0, c->w_zP.p, c->nP, nrhs);
+    double *xP = x + (size_t)N * nr;
+    op_coarse_solve(c, c->w_zP.p, c->nP, xP, nU, nrhs, 1.0);
+    op_rom_local(c, v, nU, x, nU, nrhs);                       // x_R = K̊_RR^-ROM v_R
+    op_restrict_primal(c, xP, nU, c->w_yp.p, nrhs);
+    GemmGroup g;                                                 // x_R -= Ů_RP x_P
+    g.A = c->Urp.p; g.X = c->w_yp.p; g.coef = c->pi.p; g.Kd = np; g.ldx = np; g.K = K; g.scale = -1.0;
+    gemm(c, &g, 1, x, nr, nU, nr, cols, true);
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ true saddle operator (16)
+void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nr = c->n_r, np = c->n_p;
+    const long long nU = c->nU, rs = nU + c->L;
+    const RefTables &R = c->ref;
+    size_t shmem = (size_t)R.n_dof * sizeof(double);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_true_K<2>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
+                           c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
+                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
+    else
+        hipLaunchKernelGGL(k_true_K<3>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
+                           c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
+                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
+    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, y + (size_t)N * nr, rs, nrhs);
+    op_scatter(c, x, nr, c->n_i, rs, y + nU, rs, nrhs, false);  // B u
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ vector helpers
+int reduce_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(256, (n + 4095) / 4096)); }
+
+// out_dev[rhs*nv + i] = V_i[rhs] . w[rhs]
+void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
+              int nrhs, double *out_dev) {
+    int nblk = reduce_blocks(n);
+    size_t need = (size_t)nblk * nv * nrhs;
+    c->w_red.ensure(need, c->stream);
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, nrhs), dim3(kB), 0, c->stream, V, vstride, nv, w, n, rs, nblk,
+                       c->w_red.p);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv * nrhs), dim3(kB), 0, c->stream, c->w_red.p, nblk, out_dev);
+    IFETI_HIP(hipGetLastError());
+}
+
+void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
+               long long n, long long rs, int nrhs) {
+    hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, nv, coef_dev, a, w,
+                       n, rs, nrhs);
+    IFETI_HIP(hipGetLastError());
+}
+
+void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, x, n, rs, sc_dev, y, nrhs);
+    IFETI_HIP(hipGetLastError());
+}
+
+}  // namespace ifeti

@@ -1,0 +1,935 @@
+// Host side of the offline phase: reference tables, decomposition bookkeeping,
+// loads, principal bank, coefficient systems and the coarse matrix.
+//
+// Paper: Sec. 2.2 (eqs. (6), (12)-(18), (22), (27)-(30)), Sec. 3.1 (eqs. (38)-(43)),
+// Sec. 3.2.1 (coarse problem), Sec. 4.2 (eqs. (52), (56), Algorithm 4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "common.hpp"
+
+namespace ifeti {
+
+// ------------------------------------------------------------------ splines
+namespace {
+
+std::vector<double> knot_vector(int n_el, int p) {
+    std::vector<double> U;
+    for (int i = 0; i <= p; ++i) U.push_back(0.0);
+    for (int i = 1; i < n_el; ++i) U.push_back(double(i) / n_el);
+    for (int i = 0; i <= p; ++i) U.push_back(1.0);
+    return U;
+}
+
+// Non-zero B-splines of degree p on knot span `span` at u (triangular
+// recurrence of the Cox-de Boor relation); out[r] is function span-p+r.
+void span_basis(const std::vector<double> &U, int span, double u, int p, double *out) {
+    std::vector<double> left(p + 1), right(p + 1);
+    out[0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = u - U[span + 1 - j];
+        right[j] = U[span + j] - u;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            double tmp = out[r] / (right[r + 1] + left[j - r]);
+            out[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        out[j] = saved;
+    }
+}
+
+// Values and first derivatives of the p+1 non-zero functions on `span`.
+void span_basis_ders(const std::vector<double> &U, int span, double u, int p, double *val, double *der) {
+    span_basis(U, span, u, p, val);
+    if (p == 0) {
+        der[0] = 0.0;
+        return;
+    }
+    std::vector<double> low(p);
+    span_basis(U, span, u, p - 1, low.data());  // functions span-p+1 .. span of degree p-1
+    for (int r = 0; r <= p; ++r) {
+        int g = span - p + r;
+        double a = 0.0, b = 0.0;
+        if (r >= 1) {
+            double den = U[g + p] - U[g];
+            if (den > 0) a = low[r - 1] / den;
+        }
+        if (r <= p - 1) {
+            double den = U[g + p + 1] - U[g + 1];
+            if (den > 0) b = low[r] / den;
+        }
+        der[r] = p * (a - b);
+    }
+}
+
+// n-point Gauss-Legendre rule on [0,1] by Newton iteration on P_n.
+void gauss_rule(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                // final derivative for the weight
+                double q0 = 1.0, q1 = 0.0;
+                for (int k = 1; k <= n; ++k) {
+                    double q2 = q1;
+                    q1 = q0;
+                    q0 = ((2.0 * k - 1.0) * z * q1 - (k - 1.0) * q2) / k;
+                }
+                dp = n * (z * q0 - q1) / (z * z - 1.0);
+                break;
+            }
+        }
+        x[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2)P'^2) scaled by 1/2
+    }
+    // ascending order
+    std::vector<int> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+    std::vector<double> xs(n), ws(n);
+    for (int i = 0; i < n; ++i) {
+        xs[i] = x[idx[i]];
+        ws[i] = w[idx[i]];
+    }
+    x = xs;
+    w = ws;
+}
+
+inline void multi_index(int a, int n, int dim, int *out) {
+    for (int j = 0; j < dim; ++j) {
+        out[j] = a % n;
+        a /= n;
+    }
+}
+
+}  // namespace
+
+void build_reference_tables(ifeti_ctx *c) {
+    RefTables &R = c->ref;
+    const int dim = c->dim, p = c->desc.degree, n_el = c->desc.n_el;
+    R.dim = dim;
+    R.n_el = n_el;
+    R.p = p;
+    R.nc = n_el + p;
+    R.n_ctrl = 1;
+    for (int j = 0; j < dim; ++j) R.n_ctrl *= R.nc;
+    R.n_dof = R.n_ctrl * dim;
+    R.nq1 = p + 1;
+    R.nq = 1;
+    R.n_elem = 1;
+    R.nloc = 1;
+    R.n_off = 1;
+    for (int j = 0; j < dim; ++j) {
+        R.nq *= R.nq1;
+        R.n_elem *= n_el;
+        R.nloc *= p + 1;
+        R.n_off *= 2 * p + 1;
+    }
+    int d4 = dim * dim * dim * dim;
+    R.n_snap = R.n_elem * R.nq * d4;
+    std::vector<double> U = knot_vector(n_el, p);
+    std::vector<double> gx, gw;
+    gauss_rule(R.nq1, gx, gw);
+    // 1D tables per element e and point g: values/derivatives of local functions
+    std::vector<double> v1(n_el * R.nq1 * (p + 1)), d1(n_el * R.nq1 * (p + 1)), x1(n_el * R.nq1),
+        w1(n_el * R.nq1);
+    for (int e = 0; e < n_el; ++e)
+        for (int g = 0; g < R.nq1; ++g) {
+            double u = (e + gx[g]) / n_el;
+            x1[e * R.nq1 + g] = u;
+            w1[e * R.nq1 + g] = gw[g] / n_el;
+            span_basis_ders(U, e + p, u, p, &v1[(e * R.nq1 + g) * (p + 1)], &d1[(e * R.nq1 + g) * (p + 1)]);
+        }
+    R.w.assign(R.n_elem * R.nq, 0.0);
+    R.xi.assign(R.n_elem * R.nq * dim, 0.0);
+    R.dN.assign((size_t)R.n_elem * R.nq * R.nloc * dim, 0.0);
+    R.elem_ctrl.assign(R.n_elem * R.nloc, 0);
+    int e_idx[3], g_idx[3], l_idx[3];
+    for (int E = 0; E < R.n_elem; ++E) {
+        multi_index(E, n_el, dim, e_idx);
+        for (int l = 0; l < R.nloc; ++l) {
+            multi_index(l, p + 1, dim, l_idx);
+            int a = 0;
+            for (int j = dim - 1; j >= 0; --j) a = a * R.nc + (e_idx[j] + l_idx[j]);
+            R.elem_ctrl[E * R.nloc + l] = a;
+        }
+        for (int q = 0; q < R.nq; ++q) {
+            multi_index(q, R.nq1, dim, g_idx);
+            double wq = 1.0;
+            for (int j = 0; j < dim; ++j) {
+                wq *= w1[e_idx[j] * R.nq1 + g_idx[j]];
+                R.xi[(E * R.nq + q) * dim + j] = x1[e_idx[j] * R.nq1 + g_idx[j]];
+            }
+            R.w[E * R.nq + q] = wq;
+            for (int l = 0; l < R.nloc; ++l) {
+                multi_index(l, p + 1, dim, l_idx);
+                for (int jd = 0; jd < dim; ++jd) {
+                    double prod = 1.0;
+                    for (int j = 0; j < dim; ++j) {
+                        size_t o = (e_idx[j] * R.nq1 + g_idx[j]) * (p + 1) + l_idx[j];
+                        prod *= (j == jd) ? d1[o] : v1[o];
+                    }
+                    R.dN[((size_t)(E * R.nq + q) * R.nloc + l) * dim + jd] = prod;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ partition (12)
+void build_partition(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    const int dim = c->dim, nc = R.nc;
+    c->idx_i.clear();
+    c->idx_d.clear();
+    c->idx_p.clear();
+    int mi[3];
+    for (int a = 0; a < R.n_ctrl; ++a) {
+        multi_index(a, nc, dim, mi);
+        int nb = 0;
+        for (int j = 0; j < dim; ++j) nb += (mi[j] == 0 || mi[j] == nc - 1);
+        std::vector<int> *dst = (nb == dim) ? &c->idx_p : (nb > 0 ? &c->idx_d : &c->idx_i);
+        for (int k = 0; k < dim; ++k) dst->push_back(a * dim + k);
+    }
+    c->n_i = (int)c->idx_i.size();
+    c->n_d = (int)c->idx_d.size();
+    c->n_p = (int)c->idx_p.size();
+    c->n_r = c->n_i + c->n_d;
+    c->idx_r = c->idx_i;
+    c->idx_r.insert(c->idx_r.end(), c->idx_d.begin(), c->idx_d.end());
+    std::vector<int> rpos(R.n_dof, -1), ppos(R.n_dof, -1);
+    for (int i = 0; i < c->n_r; ++i) rpos[c->idx_r[i]] = i;
+    for (int i = 0; i < c->n_p; ++i) ppos[c->idx_p[i]] = i;
+    c->r_of_dof.upload(rpos, c->stream);
+    c->p_of_dof.upload(ppos, c->stream);
+}
+
+// ------------------------------------------------------------------ B, D, A_p (14)-(18), (30)
+void build_decomposition(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    const int dim = c->dim, nc = R.nc, N = c->N;
+    int G[3] = {1, 1, 1}, V[3] = {1, 1, 1};
+    for (int j = 0; j < dim; ++j) {
+        G[j] = c->shape[j] * (nc - 1) + 1;
+        V[j] = c->shape[j] + 1;
+    }
+    auto cell_coord = [&](int s, int *cc) {
+        cc[0] = s % c->shape[0];
+        cc[1] = (s / c->shape[0]) % c->shape[1];
+        cc[2] = s / (c->shape[0] * c->shape[1]);
+    };
+    auto on_dirichlet = [&](const int *gp, const int *ext) {
+        for (int f = 0; f < 2 * dim; ++f)
+            if (c->desc.dirichlet_mask & (1 << f)) {
+                int axis = f / 2, side = f % 2;
+                if (gp[axis] == (side ? ext[axis] - 1 : 0)) return true;
+            }
+        return false;
+    };
+    // dual control points of the reference cell
+    std::vector<int> dual_ctrl;
+    for (size_t t = 0; t < c->idx_d.size(); t += dim) dual_ctrl.push_back(c->idx_d[t] / dim);
+    const int ndc = (int)dual_ctrl.size();
+    struct Entry {
+        long long g;
+        int s, t;
+        bool dir;
+    };
+    std::vector<Entry> ent;
+    ent.reserve((size_t)N * ndc);
+    int cc[3], mi[3], gp[3];
+    for (int s = 0; s < N; ++s) {
+        cell_coord(s, cc);
+        for (int t = 0; t < ndc; ++t) {
+            multi_index(dual_ctrl[t], nc, dim, mi);
+            long long g = 0;
+            for (int j = dim - 1; j >= 0; --j) {
+                gp[j] = cc[j] * (nc - 1) + mi[j];
+                g = g * G[j] + gp[j];
+            }
+            ent.push_back({g, s, t, on_dirichlet(gp, G)});
+        }
+    }
+    std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) {
+        return a.g != b.g ? a.g < b.g : a.s < b.s;
+    });
+    // rows: interface (chained pairs), then Dirichlet (every copy); both by (g, comp, position)
+    std::vector<int> row_e1, row_e2, row_comp;  // entry indices (e2 = -1 for Dirichlet rows)
+    std::vector<int> dir_e, dir_comp;
+    size_t i0 = 0;
+    while (i0 < ent.size()) {
+        size_t i1 = i0;
+        while (i1 < ent.size() && ent[i1].g == ent[i0].g) ++i1;
+        if (ent[i0].dir) {
+            for (int k = 0; k < dim; ++k)
+                for (size_t e = i0; e < i1; ++e) {
+                    dir_e.push_back((int)e);
+                    dir_comp.push_back(k);
+                }
+        } else {
+            for (int k = 0; k < dim; ++k)
+                for (size_t e = i0; e + 1 < i1; ++e) {
+                    row_e1.push_back((int)e);
+                    row_e2.push_back((int)e + 1);
+                    row_comp.push_back(k);
+                }
+        }
+        i0 = i1;
+    }
+    c->L_int = (int)row_e1.size();
+    c->L = c->L_int + (int)dir_e.size();
+    const int L = c->L, n_d = c->n_d;
+    std::vector<int> gat((size_t)N * n_d * 2, 0), sca((size_t)L * 2, 0);
+    std::vector<double> Dw(L, 1.0);
+    auto add_gather = [&](int s, int j, int row, int sign) {
+        size_t base = ((size_t)s * n_d + j) * 2;
+        if (gat[base] == 0)
+            gat[base] = sign * (row + 1);
+        else if (gat[base + 1] == 0)
+            gat[base + 1] = sign * (row + 1);
+        else
+            throw Error{IFETI_EINVAL, "more than two multipliers on one dual dof"};
+    };
+    for (int r = 0; r < c->L_int; ++r) {
+        const Entry &a = ent[row_e1[r]], &b = ent[row_e2[r]];
+        int k = row_comp[r];
+        int ja = a.t * dim + k, jb = b.t * dim + k;
+        add_gather(a.s, ja, r, +1);
+        add_gather(b.s, jb, r, -1);
+        sca[2 * r] = +(a.s * n_d + ja + 1);
+        sca[2 * r + 1] = -(b.s * n_d + jb + 1);
+        Dw[r] = 0.5;
+    }
+    for (size_t q = 0; q < dir_e.size(); ++q) {
+        int r = c->L_int + (int)q;
+        const Entry &a = ent[dir_e[q]];
+        int j = a.t * dim + dir_comp[q];
+        add_gather(a.s, j, r, +1);
+        sca[2 * r] = a.s * n_d + j + 1;
+        Dw[r] = 1.0;
+    }
+    c->g_gather.upload(gat, c->stream);
+    c->g_scatter.upload(sca, c->stream);
+    c->g_Dw.upload(Dw, c->stream);
+    c->h_d.assign(L, 0.0);
+
+    // primal assembly A_p (18): free lattice vertices in lexicographic order
+    long long nV = (long long)V[0] * V[1] * V[2];
+    std::vector<int> vnum(nV, -1);
+    int nfree = 0;
+    for (long long v = 0; v < nV; ++v) {
+        int vp[3] = {(int)(v % V[0]), (int)((v / V[0]) % V[1]), (int)(v / ((long long)V[0] * V[1]))};
+        if (!on_dirichlet(vp, V)) vnum[v] = nfree++;
+    }
+    c->n_vert_free = nfree;
+    c->nP = nfree * dim;
+    c->nU = (long long)N * c->n_r + c->nP;
+    const int n_p = c->n_p, ncorner = n_p / dim;
+    c->h_Ap.assign((size_t)N * n_p, -1);
+    std::vector<int> corner_ctrl;
+    for (int t = 0; t < n_p; t += dim) corner_ctrl.push_back(c->idx_p[t] / dim);
+    for (int s = 0; s < N; ++s) {
+        cell_coord(s, cc);
+        for (int q = 0; q < ncorner; ++q) {
+            multi_index(corner_ctrl[q], nc, dim, mi);
+            long long v = 0;
+            for (int j = dim - 1; j >= 0; --j) v = v * V[j] + (cc[j] + mi[j] / (nc - 1));
+            int num = vnum[v];
+            for (int k = 0; k < dim; ++k) c->h_Ap[(size_t)s * n_p + q * dim + k] = num < 0 ? -1 : num * dim + k;
+        }
+    }
+    c->g_Ap.upload(c->h_Ap, c->stream);
+    c->maxc = 1 << dim;
+    std::vector<int> pull((size_t)c->nP * c->maxc, -1), cnt(c->nP, 0);
+    for (int s = 0; s < N; ++s)
+        for (int j = 0; j < n_p; ++j) {
+            int P = c->h_Ap[(size_t)s * n_p + j];
+            if (P < 0) continue;
+            IFETI_REQUIRE(cnt[P] < c->maxc, IFETI_EINVAL, "primal dof shared by too many cells");
+            pull[(size_t)P * c->maxc + cnt[P]++] = s * n_p + j;
+        }
+    c->g_Ppull.upload(pull, c->stream);
+}
+
+// ------------------------------------------------------------------ loads (5b)
+void build_loads(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    const int dim = c->dim, nc = R.nc, N = c->N, p = R.p, nrhs = c->nrhs;
+    const int n_dof = R.n_dof;
+    std::vector<double> fc((size_t)nrhs * N * n_dof, 0.0);
+    int face = c->desc.load_face;
+    if (face >= 0) {
+        std::vector<double> P((size_t)N * R.n_ctrl * dim);
+        IFETI_HIP(hipMemcpyAsync(P.data(), c->ctrl.p, P.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        const int axis = face / 2, side = face % 2;
+        int tang[2], nt = 0;
+        for (int j = 0; j < dim; ++j)
+            if (j != axis) tang[nt++] = j;
+        std::vector<double> U = knot_vector(R.n_el, p), gx, gw;
+        gauss_rule(R.nq1, gx, gw);
+        const int nf1 = R.n_el * R.nq1;  // 1D face points
+        std::vector<double> fv(nf1 * (p + 1)), fd(nf1 * (p + 1)), fw(nf1);
+        std::vector<int> ffirst(nf1);
+        for (int e = 0; e < R.n_el; ++e)
+            for (int g = 0; g < R.nq1; ++g) {
+                int i = e * R.nq1 + g;
+                span_basis_ders(U, e + p, (e + gx[g]) / R.n_el, p, &fv[i * (p + 1)], &fd[i * (p + 1)]);
+                fw[i] = gw[g] / R.n_el;
+                ffirst[i] = e;
+            }
+        const int a_norm = side ? nc - 1 : 0;  // the only function non-zero on the face
+        int npts = (dim == 2) ? nf1 : nf1 * nf1;
+        int nlf = (dim == 2) ? (p + 1) : (p + 1) * (p + 1);
+        int cc[3];
+        for (int s = 0; s < N; ++s) {
+            cc[0] = s % c->shape[0];
+            cc[1] = (s / c->shape[0]) % c->shape[1];
+            cc[2] = s / (c->shape[0] * c->shape[1]);
+            if (cc[axis] != (side ? c->shape[axis] - 1 : 0)) continue;
+            const double *Ps = &P[(size_t)s * R.n_ctrl * dim];
+            for (int ip = 0; ip < npts; ++ip) {
+                int i0 = ip % nf1, i1 = (dim == 3) ? ip / nf1 : 0;
+                double T[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                std::vector<int> ctrl_ids(nlf);
+                std::vector<double> Nv(nlf);
+                for (int l = 0; l < nlf; ++l) {
+                    int l0 = l % (p + 1), l1 = l / (p + 1);
+                    int t0 = ffirst[i0] + l0, t1 = (dim == 3) ? ffirst[i1] + l1 : 0;
+                    int mi[3];
+                    mi[axis] = a_norm;
+                    mi[tang[0]] = t0;
+                    if (dim == 3) mi[tang[1]] = t1;
+                    int a = 0;
+                    for (int j = dim - 1; j >= 0; --j) a = a * nc + mi[j];
+                    ctrl_ids[l] = a;
+                    double v0 = fv[i0 * (p + 1) + l0], d0 = fd[i0 * (p + 1) + l0];
+                    double v1 = (dim == 3) ? fv[i1 * (p + 1) + l1] : 1.0;
+                    double d1 = (dim == 3) ? fd[i1 * (p + 1) + l1] : 0.0;
+                    Nv[l] = v0 * v1;
+                    for (int m = 0; m < dim; ++m) {
+                        T[0][m] += Ps[a * dim + m] * d0 * v1;
+                        if (dim == 3) T[1][m] += Ps[a * dim + m] * v0 * d1;
+                    }
+                }
+                double meas;
+                if (dim == 2) {
+                    meas = std::hypot(T[0][0], T[0][1]);
+                } else {
+                    double cx = T[0][1] * T[1][2] - T[0][2] * T[1][1];
+                    double cy = T[0][2] * T[1][0] - T[0][0] * T[1][2];
+                    double cz = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+                    meas = std::sqrt(cx * cx + cy * cy + cz * cz);
+                }
+                double wq = fw[i0] * ((dim == 3) ? fw[i1] : 1.0) * meas;
+                for (int l = 0; l < nlf; ++l)
+                    for (int r = 0; r < nrhs; ++r)
+                        for (int m = 0; m < dim; ++m)
+                            fc[((size_t)r * N + s) * n_dof + ctrl_ids[l] * dim + m] +=
+                                wq * Nv[l] * c->tractions[r * dim + m];
+            }
+        }
+    }
+    c->f_cells.upload(fc, c->stream);
+    // f of (16): f_R per cell, f_P assembled (18)
+    std::vector<double> fv((size_t)nrhs * c->nU, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+        for (int s = 0; s < N; ++s) {
+            const double *fs = &fc[((size_t)r * N + s) * n_dof];
+            double *fR = &fv[(size_t)r * c->nU + (size_t)s * c->n_r];
+            for (int i = 0; i < c->n_r; ++i) fR[i] = fs[c->idx_r[i]];
+            for (int j = 0; j < c->n_p; ++j) {
+                int P = c->h_Ap[(size_t)s * c->n_p + j];
+                if (P >= 0) fv[(size_t)r * c->nU + (size_t)N * c->n_r + P] += fs[c->idx_p[j]];
+            }
+        }
+    c->f_vec.upload(fv, c->stream);
+    std::vector<double> dv((size_t)nrhs * c->L, 0.0);
+    for (int r = 0; r < nrhs; ++r) std::copy(c->h_d.begin(), c->h_d.end(), dv.begin() + (size_t)r * c->L);
+    c->d_vec.upload(dv, c->stream);
+}
+
+// ------------------------------------------------------------------ dense helpers
+namespace {
+
+// In-place lower Cholesky of a row-major n x n SPD matrix; false on a pivot <= 0.
+bool cholesky(std::vector<double> &A, int n) {
+    for (int j = 0; j < n; ++j) {
+        double *Aj = &A[(size_t)j * n];
+        double s = Aj[j];
+        for (int k = 0; k < j; ++k) s -= Aj[k] * Aj[k];
+        if (!(s > 0.0)) return false;
+        double ljj = std::sqrt(s);
+        Aj[j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double *Ai = &A[(size_t)i * n];
+            double t = Ai[j];
+            for (int k = 0; k < j; ++k) t -= Ai[k] * Aj[k];
+            Ai[j] = t / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = 0.0;
+    return true;
+}
+
+// X (n x m, row-major) <- (L L^T)^-1 X.
+void chol_solve(const std::vector<double> &Lf, int n, std::vector<double> &X, int m) {
+    for (int i = 0; i < n; ++i) {
+        double *Xi = &X[(size_t)i * m];
+        const double *Li = &Lf[(size_t)i * n];
+        for (int k = 0; k < i; ++k) {
+            double l = Li[k];
+            if (l == 0.0) continue;
+            const double *Xk = &X[(size_t)k * m];
+            for (int c = 0; c < m; ++c) Xi[c] -= l * Xk[c];
+        }
+        double inv = 1.0 / Li[i];
+        for (int c = 0; c < m; ++c) Xi[c] *= inv;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double *Xi = &X[(size_t)i * m];
+        for (int k = i + 1; k < n; ++k) {
+            double l = Lf[(size_t)k * n + i];
+            if (l == 0.0) continue;
+            const double *Xk = &X[(size_t)k * m];
+            for (int c = 0; c < m; ++c) Xi[c] -= l * Xk[c];
+        }
+        double inv = 1.0 / Lf[(size_t)i * n + i];
+        for (int c = 0; c < m; ++c) Xi[c] *= inv;
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major).
+void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vector<double> &V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = cs * akp - sn * akq;
+                    A[k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = cs * apk - sn * aqk;
+                    A[q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = cs * vkp - sn * vkq;
+                    V[k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+}
+
+// x = A^-1 b for a small SPD A: Cholesky, or a symmetric pseudo-inverse cutting
+// eigenvalues below 1e-13 of the largest when the factorisation fails.
+std::vector<double> small_spd_solve(const std::vector<double> &A, int n, const std::vector<double> &b) {
+    std::vector<double> Lf = A;
+    bool ok = cholesky(Lf, n);
+    if (ok)
+        for (int i = 0; i < n * n; ++i) ok = ok && std::isfinite(Lf[i]);
+    if (ok) {
+        std::vector<double> x = b;
+        chol_solve(Lf, n, x, 1);
+        return x;
+    }
+    std::vector<double> S(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) S[i * n + j] = 0.5 * (A[i * n + j] + A[j * n + i]);
+    std::vector<double> w, V;
+    jacobi_eig(S, n, w, V);
+    double wmax = 0.0;
+    for (double v : w) wmax = std::max(wmax, v);
+    std::vector<double> x(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        if (!(w[k] > 1e-13 * wmax)) continue;
+        double proj = 0.0;
+        for (int i = 0; i < n; ++i) proj += V[i * n + k] * b[i];
+        proj /= w[k];
+        for (int i = 0; i < n; ++i) x[i] += proj * V[i * n + k];
+    }
+    return x;
+}
+
+struct Principal {
+    std::vector<double> Kst;                  // stencil values of the cell
+    std::vector<double> Krp, Kpp;             // dense blocks
+    std::vector<double> Kinv, Urp, Fdd, Sdd;  // n_r x n_r, n_r x n_p, n_d x n_d, n_d x n_d
+    bool ok = true;
+    std::string err;
+};
+
+// Dense local matrix entry access through the stencil layout.
+struct StencilView {
+    const ifeti_ctx *c;
+    int off[125][3];
+    StencilView(const ifeti_ctx *cc) : c(cc) {
+        const RefTables &R = c->ref;
+        int w = 2 * R.p + 1;
+        for (int o = 0; o < R.n_off; ++o) {
+            int t = o;
+            for (int j = 0; j < 3; ++j) {
+                off[o][j] = (j < R.dim) ? (t % w) - R.p : 0;
+                if (j < R.dim) t /= w;
+            }
+        }
+    }
+    // full dense n_dof x n_dof matrix
+    std::vector<double> dense(const double *Kst) const {
+        const RefTables &R = c->ref;
+        const int d = R.dim, nc = R.nc;
+        std::vector<double> K((size_t)R.n_dof * R.n_dof, 0.0);
+        int mi[3];
+        for (int a = 0; a < R.n_ctrl; ++a) {
+            multi_index(a, nc, d, mi);
+            for (int o = 0; o < R.n_off; ++o) {
+                int b = 0;
+                bool ok = true;
+                for (int j = d - 1; j >= 0; --j) {
+                    int bj = mi[j] + off[o][j];
+                    if (bj < 0 || bj >= nc) ok = false;
+                    b = b * nc + bj;
+                }
+                if (!ok) continue;
+                const double *blk = Kst + ((size_t)a * R.n_off + o) * d * d;
+                for (int i = 0; i < d; ++i)
+                    for (int k = 0; k < d; ++k) K[(size_t)(a * d + i) * R.n_dof + b * d + k] = blk[i * d + k];
+            }
+        }
+        return K;
+    }
+};
+
+void build_principal(const ifeti_ctx *c, const StencilView &sv, Principal &P) {
+    const int n = c->ref.n_dof, nr = c->n_r, np = c->n_p, nd = c->n_d, ni = c->n_i;
+    std::vector<double> K = sv.dense(P.Kst.data());
+    std::vector<double> Krr((size_t)nr * nr), Kii((size_t)ni * ni), Kid((size_t)ni * nd), Kdd((size_t)nd * nd);
+    P.Krp.assign((size_t)nr * np, 0.0);
+    P.Kpp.assign((size_t)np * np, 0.0);
+    for (int i = 0; i < nr; ++i) {
+        for (int j = 0; j < nr; ++j) Krr[(size_t)i * nr + j] = K[(size_t)c->idx_r[i] * n + c->idx_r[j]];
+        for (int j = 0; j < np; ++j) P.Krp[(size_t)i * np + j] = K[(size_t)c->idx_r[i] * n + c->idx_p[j]];
+    }
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) P.Kpp[(size_t)i * np + j] = K[(size_t)c->idx_p[i] * n + c->idx_p[j]];
+    for (int i = 0; i < ni; ++i) {
+        for (int j = 0; j < ni; ++j) Kii[(size_t)i * ni + j] = K[(size_t)c->idx_i[i] * n + c->idx_i[j]];
+        for (int j = 0; j < nd; ++j) Kid[(size_t)i * nd + j] = K[(size_t)c->idx_i[i] * n + c->idx_d[j]];
+    }
+    for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < nd; ++j) Kdd[(size_t)i * nd + j] = K[(size_t)c->idx_d[i] * n + c->idx_d[j]];
+    std::vector<double> Lr = Krr;
+    if (!cholesky(Lr, nr)) {
+        P.ok = false;
+        P.err = "principal K_rr is not positive definite";
+        return;
+    }
+    // K_rr^-1 (eqs. (27)-(28)), U_rp = K_rr^-1 K_rp (29)
+    P.Kinv.assign((size_t)nr * nr, 0.0);
+    for (int i = 0; i < nr; ++i) P.Kinv[(size_t)i * nr + i] = 1.0;
+    chol_solve(Lr, nr, P.Kinv, nr);
+    for (int i = 0; i < nr; ++i)  // symmetrise the computed inverse
+        for (int j = i + 1; j < nr; ++j) {
+            double v = 0.5 * (P.Kinv[(size_t)i * nr + j] + P.Kinv[(size_t)j * nr + i]);
+            P.Kinv[(size_t)i * nr + j] = P.Kinv[(size_t)j * nr + i] = v;
+        }
+    P.Urp = P.Krp;
+    chol_solve(Lr, nr, P.Urp, np);
+    P.Fdd.assign((size_t)nd * nd, 0.0);
+    for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < nd; ++j) P.Fdd[(size_t)i * nd + j] = P.Kinv[(size_t)(ni + i) * nr + ni + j];
+    // S_dd = K_dd - K_di K_ii^-1 K_id (30)
+    std::vector<double> Li = Kii;
+    if (!cholesky(Li, ni)) {
+        P.ok = false;
+        P.err = "principal K_ii is not positive definite";
+        return;
+    }
+    std::vector<double> X = Kid;
+    chol_solve(Li, ni, X, nd);
+    P.Sdd = Kdd;
+    for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < nd; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < ni; ++k) s += Kid[(size_t)k * nd + i] * X[(size_t)k * nd + j];
+            P.Sdd[(size_t)i * nd + j] -= s;
+        }
+}
+
+// Y (n_r x m) = K_rr X using the stencil values of one cell (r rows/cols only).
+void stencil_rr_matmul(const ifeti_ctx *c, const StencilView &sv, const double *Kst, const double *X, int m,
+                       double *Y) {
+    const RefTables &R = c->ref;
+    const int d = R.dim, nc = R.nc;
+    std::vector<int> rpos(R.n_dof, -1);
+    for (int i = 0; i < c->n_r; ++i) rpos[c->idx_r[i]] = i;
+    std::fill(Y, Y + (size_t)c->n_r * m, 0.0);
+    int mi[3];
+    for (int a = 0; a < R.n_ctrl; ++a) {
+        multi_index(a, nc, d, mi);
+        for (int o = 0; o < R.n_off; ++o) {
+            int b = 0;
+            bool ok = true;
+            for (int j = d - 1; j >= 0; --j) {
+                int bj = mi[j] + sv.off[o][j];
+                if (bj < 0 || bj >= nc) ok = false;
+                b = b * nc + bj;
+            }
+            if (!ok) continue;
+            const double *blk = Kst + ((size_t)a * R.n_off + o) * d * d;
+            for (int i = 0; i < d; ++i) {
+                int ri = rpos[a * d + i];
+                if (ri < 0) continue;
+                double *Yi = Y + (size_t)ri * m;
+                for (int k = 0; k < d; ++k) {
+                    int rk = rpos[b * d + k];
+                    if (rk < 0) continue;
+                    double v = blk[i * d + k];
+                    const double *Xk = X + (size_t)rk * m;
+                    for (int t = 0; t < m; ++t) Yi[t] += v * Xk[t];
+                }
+            }
+        }
+    }
+}
+
+template <class F>
+void parallel_for(int n, F f) {
+    unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int nt = std::min<int>(n, (int)hw);
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int i = t; i < n; i += nt) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ offline phase
+void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in) {
+    const RefTables &R = c->ref;
+    const int N = c->N, nr = c->n_r, np = c->n_p, nd = c->n_d, ni = c->n_i;
+    // 1. greedy (Algorithm 4) on the device; affine coordinates (56) on the host
+    std::vector<int> sigma;
+    std::vector<double> beta, norms;
+    int K = greedy_device(c, n_principal, tol_rb, principal_in, sigma, beta, norms);
+    std::vector<double> alpha((size_t)N * K, 0.0);
+    {
+        std::vector<double> U((size_t)K * K, 0.0);  // U[i][j] = ||A^(sigma_j)|| beta_i^(sigma_j), i <= j
+        for (int j = 0; j < K; ++j)
+            for (int i = 0; i <= j; ++i) U[i * K + j] = norms[sigma[j]] * beta[(size_t)sigma[j] * K + i];
+        for (int s = 0; s < N; ++s) {
+            double *a = &alpha[(size_t)s * K];
+            for (int i = K - 1; i >= 0; --i) {
+                double t = norms[s] * beta[(size_t)s * K + i];
+                for (int j = i + 1; j < K; ++j) t -= U[i * K + j] * a[j];
+                a[i] = t / U[i * K + i];
+            }
+        }
+    }
+    // 2. principal bank (eqs. (22), (27)-(30), (39))
+    const size_t kst_n = (size_t)R.n_ctrl * R.n_off * R.dim * R.dim;
+    std::vector<Principal> bank(K);
+    for (int k = 0; k < K; ++k) {
+        bank[k].Kst.resize(kst_n);
+        IFETI_HIP(hipMemcpyAsync(bank[k].Kst.data(), c->Kst.p + (size_t)sigma[k] * kst_n, kst_n * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    }
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    StencilView sv(c);
+    parallel_for(K, [&](int k) { build_principal(c, sv, bank[k]); });
+    for (int k = 0; k < K; ++k) IFETI_REQUIRE(bank[k].ok, IFETI_ENOTSPD, bank[k].err);
+    // 3. traces of eq. (42) per (i, j, m) with the affine ROM operator K̃ = sum_m alpha_m K^(sigma_m)
+    std::vector<double> GA((size_t)K * K * K), GM((size_t)K * K * K), gb((size_t)K * K), dv(K);
+    parallel_for(K, [&](int m) {
+        std::vector<double> KU((size_t)nr * std::max(np, nd));
+        std::vector<double> Ud((size_t)nr * nd);
+        for (int j = 0; j < K; ++j) {
+            stencil_rr_matmul(c, sv, bank[m].Kst.data(), bank[j].Urp.data(), np, KU.data());
+            for (int i = 0; i < K; ++i) {
+                double s = 0.0;
+                for (size_t t = 0; t < (size_t)nr * np; ++t) s += bank[i].Urp[t] * KU[t];
+                GA[((size_t)m * K + i) * K + j] = s;
+            }
+            // U_rd^(j) = last n_d columns of K_rr^-1
+            for (int r = 0; r < nr; ++r)
+                for (int q = 0; q < nd; ++q) Ud[(size_t)r * nd + q] = bank[j].Kinv[(size_t)r * nr + ni + q];
+            stencil_rr_matmul(c, sv, bank[m].Kst.data(), Ud.data(), nd, KU.data());
+            for (int i = 0; i < K; ++i) {
+                double s = 0.0;
+                for (int r = 0; r < nr; ++r)
+                    for (int q = 0; q < nd; ++q) s += bank[i].Kinv[(size_t)r * nr + ni + q] * KU[(size_t)r * nd + q];
+                GM[((size_t)m * K + i) * K + j] = s;
+            }
+        }
+        for (int i = 0; i < K; ++i) {
+            double s = 0.0;
+            for (size_t t = 0; t < (size_t)nr * np; ++t) s += bank[i].Urp[t] * bank[m].Krp[t];
+            gb[(size_t)m * K + i] = s;
+        }
+        double tr = 0.0;
+        for (int q = 0; q < nd; ++q) tr += bank[m].Fdd[(size_t)q * nd + q];
+        dv[m] = tr;
+    });
+    // 4. per-cell pi, delta (41)
+    std::vector<double> pi((size_t)N * K), delta((size_t)N * K);
+    parallel_for(N, [&](int s) {
+        std::vector<double> A((size_t)K * K, 0.0), M((size_t)K * K, 0.0), b(K, 0.0);
+        const double *a = &alpha[(size_t)s * K];
+        for (int m = 0; m < K; ++m) {
+            for (int t = 0; t < K * K; ++t) {
+                A[t] += a[m] * GA[(size_t)m * K * K + t];
+                M[t] += a[m] * GM[(size_t)m * K * K + t];
+            }
+            for (int i = 0; i < K; ++i) b[i] += a[m] * gb[(size_t)m * K + i];
+        }
+        std::vector<double> x = small_spd_solve(A, K, b), y = small_spd_solve(M, K, dv);
+        std::copy(x.begin(), x.end(), &pi[(size_t)s * K]);
+        std::copy(y.begin(), y.end(), &delta[(size_t)s * K]);
+    });
+    // 5. S̊_pp^(s) = sym(K̊_pp - K̊_rp^T Ů_rp) (43) and the coarse matrix (Sec. 3.2.1)
+    std::vector<double> Q((size_t)K * K * np * np);  // Q[m][k] = K_rp^(m)T U_rp^(k)
+    for (int m = 0; m < K; ++m)
+        for (int k = 0; k < K; ++k)
+            for (int a = 0; a < np; ++a)
+                for (int b = 0; b < np; ++b) {
+                    double s = 0.0;
+                    for (int r = 0; r < nr; ++r) s += bank[m].Krp[(size_t)r * np + a] * bank[k].Urp[(size_t)r * np + b];
+                    Q[(((size_t)m * K + k) * np + a) * np + b] = s;
+                }
+    const int nP = c->nP;
+    int bw = 0;
+    for (int s = 0; s < N; ++s)
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) {
+                int A1 = c->h_Ap[(size_t)s * np + a], B1 = c->h_Ap[(size_t)s * np + b];
+                if (A1 >= 0 && B1 >= 0) bw = std::max(bw, std::abs(A1 - B1));
+            }
+    std::vector<double> band((size_t)nP * (bw + 1), 0.0);  // band[i][i-j] for j <= i
+    for (int s = 0; s < N; ++s) {
+        const double *a = &alpha[(size_t)s * K], *pk = &pi[(size_t)s * K];
+        std::vector<double> X((size_t)np * np, 0.0);
+        for (int m = 0; m < K; ++m) {
+            for (int t = 0; t < np * np; ++t) X[t] += a[m] * bank[m].Kpp[t];
+            for (int k = 0; k < K; ++k) {
+                double w = a[m] * pk[k];
+                const double *q = &Q[((size_t)m * K + k) * np * np];
+                for (int t = 0; t < np * np; ++t) X[t] -= w * q[t];
+            }
+        }
+        for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) {
+                int I = c->h_Ap[(size_t)s * np + i], J = c->h_Ap[(size_t)s * np + j];
+                if (I < 0 || J < 0 || J > I) continue;
+                band[(size_t)I * (bw + 1) + (I - J)] += 0.5 * (X[i * np + j] + X[j * np + i]);
+            }
+    }
+    // banded Cholesky: band[i][i-j] <- L[i][j]
+    for (int j = 0; j < nP; ++j) {
+        double s = band[(size_t)j * (bw + 1)];
+        for (int k = std::max(0, j - bw); k < j; ++k) {
+            double l = band[(size_t)j * (bw + 1) + (j - k)];
+            s -= l * l;
+        }
+        IFETI_REQUIRE(s > 0.0, IFETI_ENOTSPD, "coarse matrix S_PP is not positive definite");
+        double ljj = std::sqrt(s);
+        band[(size_t)j * (bw + 1)] = ljj;
+        for (int i = j + 1; i <= std::min(nP - 1, j + bw); ++i) {
+            double t = band[(size_t)i * (bw + 1) + (i - j)];
+            for (int k = std::max(0, i - bw); k < j; ++k)
+                t -= band[(size_t)i * (bw + 1) + (i - k)] * band[(size_t)j * (bw + 1) + (j - k)];
+            band[(size_t)i * (bw + 1) + (i - j)] = t / ljj;
+        }
+    }
+    // 6. upload the bank and the coefficients
+    c->K = K;
+    c->sigma = sigma;
+    c->h_alpha = alpha;
+    c->h_pi = pi;
+    c->h_delta = delta;
+    c->alpha.upload(alpha, c->stream);
+    c->pi.upload(pi, c->stream);
+    c->delta.upload(delta, c->stream);
+    std::vector<double> Fdd((size_t)K * nd * nd), Sdd((size_t)K * nd * nd), W((size_t)K * nd * np),
+        WT((size_t)K * np * nd), UrdT((size_t)K * nd * nr), Urd((size_t)K * nr * nd), Urp((size_t)K * nr * np),
+        UrpT((size_t)K * np * nr), Kinv((size_t)K * nr * nr), Kpr((size_t)K * kst_n);
+    for (int k = 0; k < K; ++k) {
+        const Principal &P = bank[k];
+        std::copy(P.Fdd.begin(), P.Fdd.end(), &Fdd[(size_t)k * nd * nd]);
+        std::copy(P.Sdd.begin(), P.Sdd.end(), &Sdd[(size_t)k * nd * nd]);
+        std::copy(P.Kinv.begin(), P.Kinv.end(), &Kinv[(size_t)k * nr * nr]);
+        std::copy(P.Urp.begin(), P.Urp.end(), &Urp[(size_t)k * nr * np]);
+        std::copy(P.Kst.begin(), P.Kst.end(), &Kpr[(size_t)k * kst_n]);
+        for (int q = 0; q < nd; ++q)
+            for (int a = 0; a < np; ++a) {
+                double v = P.Urp[(size_t)(ni + q) * np + a];
+                W[((size_t)k * nd + q) * np + a] = v;
+                WT[((size_t)k * np + a) * nd + q] = v;
+            }
+        for (int r = 0; r < nr; ++r) {
+            for (int q = 0; q < nd; ++q) {
+                double v = P.Kinv[(size_t)r * nr + ni + q];
+                Urd[((size_t)k * nr + r) * nd + q] = v;
+                UrdT[((size_t)k * nd + q) * nr + r] = v;
+            }
+            for (int a = 0; a < np; ++a) UrpT[((size_t)k * np + a) * nr + r] = P.Urp[(size_t)r * np + a];
+        }
+    }
+    c->Fdd.upload(Fdd, c->stream);
+    c->Sdd.upload(Sdd, c->stream);
+    c->W.upload(W, c->stream);
+    c->WT.upload(WT, c->stream);
+    c->UrdT.upload(UrdT, c->stream);
+    c->Urd.upload(Urd, c->stream);
+    c->Urp.upload(Urp, c->stream);
+    c->UrpT.upload(UrpT, c->stream);
+    c->Kinv.upload(Kinv, c->stream);
+    c->Kst_pr.upload(Kpr, c->stream);
+    // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
+    coarse_inverse_device(c, band, bw);
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    c->rom_built = true;
+}
+
+}  // namespace ifeti

@@ -1,0 +1,457 @@
+// Krylov drivers: interface PCG on F̊ preconditioned by M̊_D^-1 (paper
+// Sec. 3.2.3, eqs. (48)-(49)) and right-preconditioned flexible GMRES on the
+// saddle system (16) with the block preconditioner (44) (Algorithm 1).
+//
+// Several load cases run as independent recurrences that share every operator
+// application (one batched F̊ / M̊_D^-1 / K̊^-ROM per step); a load case that has
+// converged is frozen (zero step length) so each one follows exactly its
+// single-load-case iteration.  All PCG scalars live on the device; the host
+// only polls the convergence flags every `pcg_check_every` iterations.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ifeti {
+namespace {
+
+constexpr int kB = 256;
+inline unsigned nblocks(long long n) { return (unsigned)((n + kB - 1) / kB); }
+
+// PCG state per load case (doubles): rho, r0, relres, alpha, beta
+enum { S_RHO = 0, S_R0, S_REL, S_ALPHA, S_BETA, S_N };
+// ints: active, iters, breakdown
+enum { I_ACT = 0, I_IT, I_BRK, I_N };
+
+__device__ inline double block_reduce(double v, double *sh) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) sh[tid] += sh[tid + off];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[rhs*nblk + b] = x . y over block b's chunk
+__global__ __launch_bounds__(kB) void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y,
+                                                    long long n, long long rs, int nblk, double *__restrict__ part) {
+    __shared__ double sh[kB];
+    int b = blockIdx.x, rhs = blockIdx.y;
+    long long chunk = (n + nblk - 1) / nblk;
+    long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+    const double *xr = x + rhs * rs, *yr = y + rhs * rs;
+    double acc = 0.0;
+    for (long long t = i0 + threadIdx.x; t < i1; t += kB) acc += xr[t] * yr[t];
+    acc = block_reduce(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)rhs * nblk + b] = acc;
+}
+
+__device__ inline double sum_partials(const double *part, int nblk, double *sh) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kB) acc += part[b];
+    return block_reduce(acc, sh);
+}
+
+// stage 0: r0 = ||r||, rho = r.z
+__global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr, const double *__restrict__ p_rz,
+                                                 int nblk, double *__restrict__ st, int *__restrict__ ist) {
+    __shared__ double sh[kB];
+    int rhs = blockIdx.x;
+    double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
+    double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        double r0 = sqrt(rr);
+        st[rhs * S_N + S_RHO] = rz;
+        st[rhs * S_N + S_R0] = r0;
+        st[rhs * S_N + S_REL] = r0 > 0.0 ? 1.0 : 0.0;
+        st[rhs * S_N + S_ALPHA] = 0.0;
+        st[rhs * S_N + S_BETA] = 0.0;
+        ist[rhs * I_N + I_ACT] = r0 > 0.0 ? 1 : 0;
+        ist[rhs * I_N + I_IT] = 0;
+        ist[rhs * I_N + I_BRK] = 0;
+    }
+}
+
+// alpha = rho / p.q (breakdown if p.q <= 0 or not finite)
+__global__ __launch_bounds__(kB) void k_pcg_alpha(const double *__restrict__ p_pq, int nblk, double *__restrict__ st,
+                                                  int *__restrict__ ist) {
+    __shared__ double sh[kB];
+    int rhs = blockIdx.x;
+    double pq = sum_partials(p_pq + (size_t)rhs * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        if (ist[rhs * I_N + I_ACT]) {
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                ist[rhs * I_N + I_BRK] = 1;
+                ist[rhs * I_N + I_ACT] = 0;
+            } else {
+                a = st[rhs * S_N + S_RHO] / pq;
+            }
+        }
+        st[rhs * S_N + S_ALPHA] = a;
+    }
+}
+
+// lam += alpha p; r -= alpha q; partial ||r||^2
+__global__ __launch_bounds__(kB) void k_pcg_update(double *__restrict__ lam, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   long long n, long long rs, const double *__restrict__ st, int nblk,
+                                                   double *__restrict__ part) {
+    __shared__ double sh[kB];
+    int b = blockIdx.x, rhs = blockIdx.y;
+    double a = st[rhs * S_N + S_ALPHA];
+    long long chunk = (n + nblk - 1) / nblk;
+    long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+    double acc = 0.0;
+    size_t base = (size_t)rhs * rs;
+    for (long long t = i0 + threadIdx.x; t < i1; t += kB) {
+        double rv = r[base + t];
+        if (a != 0.0) {
+            lam[base + t] += a * p[base + t];
+            rv -= a * q[base + t];
+            r[base + t] = rv;
+        }
+        acc += rv * rv;
+    }
+    acc = block_reduce(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)rhs * nblk + b] = acc;
+}
+
+__global__ __launch_bounds__(kB) void k_pcg_check(const double *__restrict__ p_rr, int nblk, double *__restrict__ st,
+                                                  int *__restrict__ ist, double tol, int it) {
+    __shared__ double sh[kB];
+    int rhs = blockIdx.x;
+    double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
+    if (threadIdx.x == 0 && ist[rhs * I_N + I_ACT]) {
+        double rel = sqrt(rr) / st[rhs * S_N + S_R0];
+        st[rhs * S_N + S_REL] = rel;
+        ist[rhs * I_N + I_IT] = it;
+        if (rel <= tol) ist[rhs * I_N + I_ACT] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_pcg_beta(const double *__restrict__ p_rz, int nblk, double *__restrict__ st,
+                                                 const int *__restrict__ ist) {
+    __shared__ double sh[kB];
+    int rhs = blockIdx.x;
+    double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        if (ist[rhs * I_N + I_ACT]) {
+            st[rhs * S_N + S_BETA] = rz / st[rhs * S_N + S_RHO];
+            st[rhs * S_N + S_RHO] = rz;
+        } else {
+            st[rhs * S_N + S_BETA] = 0.0;
+        }
+    }
+}
+
+// p = z + beta p (active load cases only)
+__global__ __launch_bounds__(kB) void k_pcg_p(double *__restrict__ p, const double *__restrict__ z, long long n,
+                                              long long rs, int nrhs, const double *__restrict__ st,
+                                              const int *__restrict__ ist) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    if (!ist[rhs * I_N + I_ACT]) return;
+    size_t i = (size_t)rhs * rs + (t % n);
+    p[i] = z[i] + st[rhs * S_N + S_BETA] * p[i];
+}
+
+__global__ __launch_bounds__(kB) void k_copy(const double *__restrict__ x, double *__restrict__ y, long long n) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = x[t];
+}
+
+__global__ __launch_bounds__(kB) void k_fill(double *__restrict__ y, long long n, double v) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = v;
+}
+
+// out[rhs*n + i] = in1 segment followed by in2 segment (saddle vector packing)
+__global__ __launch_bounds__(kB) void k_pack(const double *__restrict__ a, long long na,
+                                             const double *__restrict__ b, long long nb, double *__restrict__ out,
+                                             int nrhs) {
+    long long n = na + nb;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    long long i = t % n;
+    out[t] = i < na ? a[rhs * na + i] : b[rhs * nb + (i - na)];
+}
+
+__global__ __launch_bounds__(kB) void k_unpack(const double *__restrict__ x, long long na, long long nb,
+                                               double *__restrict__ a, double *__restrict__ b, int nrhs) {
+    long long n = na + nb;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    long long i = t % n;
+    if (i < na)
+        a[rhs * na + i] = x[t];
+    else
+        b[rhs * nb + (i - na)] = x[t];
+}
+
+// x = a - b (per element) on a strided sub-vector set
+__global__ __launch_bounds__(kB) void k_sub(const double *__restrict__ a, long long a_rs, const double *__restrict__ b,
+                                            long long b_rs, double *__restrict__ out, long long o_rs, long long n,
+                                            int nrhs, double sb) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    int rhs = (int)(t / n);
+    long long i = t % n;
+    out[rhs * o_rs + i] = a[rhs * a_rs + i] + sb * b[rhs * b_rs + i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ interface PCG
+int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
+                    double *relres) {
+    const long long L = c->L;
+    const long long n = L * nrhs;
+    DevBuf<double> r, z, p, q, st, part_a, part_b;
+    DevBuf<int> ist;
+    r.alloc(n);
+    z.alloc(n);
+    p.alloc(n);
+    q.alloc(n);
+    st.alloc((size_t)S_N * nrhs);
+    ist.alloc((size_t)I_N * nrhs);
+    const int nblk = reduce_blocks(L);
+    part_a.alloc((size_t)nblk * nrhs);
+    part_b.alloc((size_t)nblk * nrhs);
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, rhs, r.p, n);
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kB), 0, s, lam, n, 0.0);
+    apply_MD(c, r.p, z.p, nrhs);
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, r.p, L, L, nblk, part_a.p);
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_b.p);
+    hipLaunchKernelGGL(k_pcg_init, dim3(nrhs), dim3(kB), 0, s, part_a.p, part_b.p, nblk, st.p, ist.p);
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, z.p, p.p, n);
+    IFETI_HIP(hipGetLastError());
+    std::vector<int> hist((size_t)I_N * nrhs);
+    auto any_active = [&]() {
+        IFETI_HIP(hipMemcpyAsync(hist.data(), ist.p, hist.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipStreamSynchronize(s));
+        bool act = false, brk = false;
+        for (int r2 = 0; r2 < nrhs; ++r2) {
+            act |= hist[r2 * I_N + I_ACT] != 0;
+            brk |= hist[r2 * I_N + I_BRK] != 0;
+        }
+        return std::make_pair(act, brk);
+    };
+    auto st0 = any_active();
+    const int every = std::max(1, c->opt.pcg_check_every);
+    for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
+        apply_F(c, p.p, q.p, nrhs);
+        hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, p.p, q.p, L, L, nblk, part_a.p);
+        hipLaunchKernelGGL(k_pcg_alpha, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
+        hipLaunchKernelGGL(k_pcg_update, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r.p, p.p, q.p, L, L, st.p, nblk,
+                           part_b.p);
+        hipLaunchKernelGGL(k_pcg_check, dim3(nrhs), dim3(kB), 0, s, part_b.p, nblk, st.p, ist.p, tol, it);
+        apply_MD(c, r.p, z.p, nrhs);
+        hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_a.p);
+        hipLaunchKernelGGL(k_pcg_beta, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
+        hipLaunchKernelGGL(k_pcg_p, dim3(nblocks(n)), dim3(kB), 0, s, p.p, z.p, L, L, nrhs, st.p, ist.p);
+        IFETI_HIP(hipGetLastError());
+        if (it % every == 0 || it == maxit) st0 = any_active();
+    }
+    st0 = any_active();
+    std::vector<double> hst((size_t)S_N * nrhs);
+    IFETI_HIP(hipMemcpyAsync(hst.data(), st.p, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    IFETI_HIP(hipStreamSynchronize(s));
+    for (int r2 = 0; r2 < nrhs; ++r2) {
+        if (iters) iters[r2] = hist[r2 * I_N + I_IT];
+        if (relres) relres[r2] = hst[r2 * S_N + S_REL];
+    }
+    if (st0.second) {
+        set_last_error("PCG breakdown: p^T F p <= 0 or non-finite");
+        return IFETI_EBREAKDOWN;
+    }
+    if (st0.first) {
+        set_last_error("PCG reached the iteration limit");
+        return IFETI_EMAXIT;
+    }
+    return IFETI_OK;
+}
+
+// ------------------------------------------------------------------ Algorithm 1 / (44)
+// x = (v, w) -> (x_u, y):  w̄ = w - Ů v;  y = -F̊^-pcg w̄;  x_u = K̊^-ROM v - Ůᵀ y
+static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, double inner_tol, int inner_maxit,
+                      std::vector<long long> &inner_total, DevBuf<double> &t_u, DevBuf<double> &t_L, DevBuf<double> &t_L2,
+                      DevBuf<double> &t_u2) {
+    const long long nU = c->nU, L = c->L, ns = nU + L;
+    hipStream_t s = c->stream;
+    // split the packed saddle vector (rhs-major, u then lambda)
+    t_u.alloc((size_t)nU * nrhs);
+    t_u2.alloc((size_t)nU * nrhs);
+    t_L.alloc((size_t)L * nrhs);
+    t_L2.alloc((size_t)L * nrhs);
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, in, nU, L, t_u.p, t_L.p, nrhs);
+    apply_U(c, t_u.p, t_L2.p, nrhs);                                      // Ů v
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
+                       -1.0);                                            // w̄ = w - Ů v
+    std::vector<int> its(nrhs);
+    int st = solve_interface(c, t_L.p, t_L2.p, nrhs, inner_tol, inner_maxit, its.data(), nullptr);
+    for (int r = 0; r < nrhs; ++r) inner_total[r] += its[r];
+    if (st != IFETI_OK && st != IFETI_EMAXIT) return st;
+    // y = -lambda; x_u = K̊^-ROM v + Ůᵀ lambda
+    apply_Kinv_rom(c, t_u.p, t_u2.p, nrhs);
+    apply_Ut(c, t_L2.p, t_u.p, nrhs);
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(nU * nrhs)), dim3(kB), 0, s, t_u2.p, nU, t_u.p, nU, t_u2.p, nU, nU,
+                       nrhs, 1.0);
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L * nrhs, 0.0);
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
+                       -1.0);                                            // y = -lambda
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, t_u2.p, nU, t_L.p, L, out, nrhs);
+    IFETI_HIP(hipGetLastError());
+    return IFETI_OK;
+}
+
+// ------------------------------------------------------------------ flexible GMRES on (16)
+int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
+                 int maxit, double inner_tol, int *outer, int *inner_total, double *relres) {
+    const long long nU = c->nU, L = c->L, ns = nU + L;
+    const int m = std::max(1, std::min(maxit, c->opt.fgmres_restart));
+    hipStream_t s = c->stream;
+    DevBuf<double> V, Z, w, coef, tu, tL, tL2, tu2, hdev;
+    V.alloc((size_t)(m + 1) * ns * nrhs);
+    Z.alloc((size_t)m * ns * nrhs);
+    w.alloc((size_t)ns * nrhs);
+    hdev.alloc((size_t)(m + 1) * nrhs + 16);
+    coef.alloc((size_t)(m + 1) * nrhs + 16);
+    const long long vs = ns * nrhs;  // stride between basis blocks
+    // b = (f, d) packed into V_0 (unnormalised)
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, V.p, nrhs);
+    multidot(c, V.p, 0, 1, V.p, ns, ns, nrhs, hdev.p);
+    std::vector<double> bn(nrhs);
+    IFETI_HIP(hipMemcpyAsync(bn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    IFETI_HIP(hipStreamSynchronize(s));
+    std::vector<double> beta(nrhs), inv(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        beta[r] = std::sqrt(bn[r]);
+        inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+    }
+    IFETI_HIP(hipMemcpyAsync(coef.p, inv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    scale_copy(c, V.p, ns, ns, coef.p, V.p, nrhs);
+    // per-load-case Hessenberg and Givens data on the host
+    std::vector<std::vector<double>> H(nrhs, std::vector<double>((size_t)(m + 1) * m, 0.0));
+    std::vector<std::vector<double>> cs(nrhs, std::vector<double>(m)), sn(nrhs, std::vector<double>(m));
+    std::vector<std::vector<double>> g(nrhs, std::vector<double>(m + 1, 0.0));
+    std::vector<int> kdim(nrhs, 0), done(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+        g[r][0] = beta[r];
+        if (beta[r] == 0.0) done[r] = 1;
+    }
+    std::vector<long long> inner(nrhs, 0);
+    int status = IFETI_OK;
+    std::vector<double> h1((size_t)(m + 1) * nrhs), h2((size_t)(m + 1) * nrhs), hn(nrhs);
+    int j = 0;
+    for (; j < m; ++j) {
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all = all && done[r];
+        if (all) break;
+        double *Vj = V.p + (size_t)j * vs, *Zj = Z.p + (size_t)j * vs;
+        int st = apply_prec(c, Vj, Zj, nrhs, inner_tol, 1000, inner, tu, tL, tL2, tu2);
+        if (st != IFETI_OK) {
+            status = st;
+            break;
+        }
+        apply_A(c, Zj, w.p, nrhs);
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            multidot(c, V.p, vs, j + 1, w.p, ns, ns, nrhs, hdev.p);
+            std::vector<double> &hh = pass == 0 ? h1 : h2;
+            IFETI_HIP(hipMemcpyAsync(hh.data(), hdev.p, (size_t)(j + 1) * nrhs * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            IFETI_HIP(hipStreamSynchronize(s));
+            std::vector<double> neg((size_t)(j + 1) * nrhs);
+            for (size_t t = 0; t < neg.size(); ++t) neg[t] = -hh[t];
+            IFETI_HIP(hipMemcpyAsync(coef.p, neg.data(), neg.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            multiaxpy(c, V.p, vs, j + 1, coef.p, 1.0, w.p, ns, ns, nrhs);
+        }
+        multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hdev.p);
+        IFETI_HIP(hipMemcpyAsync(hn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipStreamSynchronize(s));
+        std::vector<double> sc(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            double hj1 = std::sqrt(hn[r]);
+            sc[r] = hj1 > 0 ? 1.0 / hj1 : 0.0;
+            if (done[r]) continue;
+            std::vector<double> &Hr = H[r];
+            for (int i = 0; i <= j; ++i) Hr[(size_t)i * m + j] = h1[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
+            Hr[(size_t)(j + 1) * m + j] = hj1;
+            for (int i = 0; i < j; ++i) {
+                double a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
+                Hr[(size_t)i * m + j] = cs[r][i] * a + sn[r][i] * b;
+                Hr[(size_t)(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * b;
+            }
+            double a = Hr[(size_t)j * m + j], b = Hr[(size_t)(j + 1) * m + j];
+            double den = std::hypot(a, b);
+            cs[r][j] = a / den;
+            sn[r][j] = b / den;
+            Hr[(size_t)j * m + j] = den;
+            Hr[(size_t)(j + 1) * m + j] = 0.0;
+            g[r][j + 1] = -sn[r][j] * g[r][j];
+            g[r][j] = cs[r][j] * g[r][j];
+            kdim[r] = j + 1;
+            if (std::fabs(g[r][j + 1]) <= tol * beta[r] || hj1 == 0.0) done[r] = 1;
+        }
+        IFETI_HIP(hipMemcpyAsync(coef.p, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        scale_copy(c, w.p, ns, ns, coef.p, V.p + (size_t)(j + 1) * vs, nrhs);
+    }
+    // x = sum_i y_i Z_i per load case
+    int kmax = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        int k = kdim[r];
+        kmax = std::max(kmax, k);
+        std::vector<double> y(k, 0.0);
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[r][i];
+            for (int l = i + 1; l < k; ++l) t -= H[r][(size_t)i * m + l] * y[l];
+            y[i] = t / H[r][(size_t)i * m + i];
+        }
+        for (int i = 0; i < k; ++i) g[r][i] = y[i];  // keep the solution coefficients
+    }
+    std::vector<double> yc((size_t)std::max(kmax, 1) * nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+        for (int i = 0; i < kdim[r]; ++i) yc[(size_t)r * kmax + i] = g[r][i];
+    DevBuf<double> xs;
+    xs.alloc((size_t)ns * nrhs);
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, ns * nrhs, 0.0);
+    if (kmax > 0) {
+        IFETI_HIP(hipMemcpyAsync(coef.p, yc.data(), yc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        multiaxpy(c, Z.p, vs, kmax, coef.p, 1.0, xs.p, ns, ns, nrhs);
+    }
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, nU, L, u, lam, nrhs);
+    // true residual ||b - A x|| / ||b||
+    apply_A(c, xs.p, w.p, nrhs);
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, xs.p, nrhs);
+    hipLaunchKernelGGL(k_sub, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, ns, w.p, ns, xs.p, ns, ns, nrhs, -1.0);
+    multidot(c, xs.p, 0, 1, xs.p, ns, ns, nrhs, hdev.p);
+    IFETI_HIP(hipMemcpyAsync(hn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    IFETI_HIP(hipStreamSynchronize(s));
+    bool conv = true;
+    for (int r = 0; r < nrhs; ++r) {
+        double rel = beta[r] > 0 ? std::sqrt(hn[r]) / beta[r] : 0.0;
+        if (relres) relres[r] = rel;
+        if (outer) outer[r] = kdim[r];
+        conv = conv && done[r];
+    }
+    if (inner_total)
+        for (int r = 0; r < nrhs; ++r) inner_total[r] = (int)inner[r];
+    if (status != IFETI_OK) return status;
+    if (!conv) {
+        set_last_error("FGMRES reached the iteration limit");
+        return IFETI_EMAXIT;
+    }
+    return IFETI_OK;
+}
+
+}  // namespace ifeti

@@ -1,0 +1,149 @@
+"""GPU library vs CPU oracle, call by call through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import latticegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+CASES = {
+    "tiny2d": lambda: latticegen.tiny(2, (3, 3), 3, n_principal=3),
+    "ragged2d": lambda: latticegen.tiny(2, (5, 3), 4, n_principal=4, tractions=[[0.3, -0.7]]),
+    "c1": lambda: latticegen.make("c1"),
+    "tiny3d": lambda: latticegen.tiny(3, (2, 2, 2), 2, n_principal=3),
+}
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    _cuda()
+    from oracle import Model
+    from paper_2308_11371_amd import ifeti
+    print(f"[gpu parity] case {request.param}", flush=True)
+    prob = CASES[request.param]()
+    m = Model(prob)
+    m.build_reduced_basis()
+    ctx = ifeti.setup(prob, principal_in=m.sigma)
+    yield request.param, prob, m, ctx
+    ctx.close()
+
+
+def test_sizes_and_rhs(pair):
+    name, prob, m, ctx = pair
+    s = ctx.sizes
+    dd = m.dd
+    assert (s.n_i, s.n_d, s.n_p, s.n_r, s.L, s.nP, s.nU) == (dd.n_i, dd.n_d, dd.n_p, dd.n_r, m.L, dd.nP, m.nU)
+    f, d = ctx.get_rhs()
+    assert rel(host(f)[:m.nU], m.rhs_f[0]) < 1e-13
+    assert np.array_equal(host(d)[:m.L], m.rhs_d)
+
+
+def test_greedy_and_coefficients(pair):
+    name, prob, m, ctx = pair
+    from paper_2308_11371_amd import ifeti
+    ctx2 = ifeti.setup(prob)                     # the library's own greedy
+    s2 = ctx2.build_reduced_basis(prob.n_principal)
+    assert list(s2) == list(m.sigma)             # index work: bit-exact
+    a, p, d = ctx2.get_coefficients()
+    assert np.abs(a - m.alpha).max() < 1e-10 * max(1.0, np.abs(m.alpha).max())
+    assert rel(p, m.pi) < 1e-8
+    assert rel(d, m.delta) < 1e-8
+    ctx2.close()
+
+
+def _rand(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+@pytest.mark.parametrize("op", ["F", "MD", "U", "Ut", "Kinv_rom", "A"])
+def test_operator_parity(pair, op):
+    name, prob, m, ctx = pair
+    nU, L = m.nU, m.L
+    if op in ("F", "MD"):
+        x = _rand(L, 11)
+    elif op == "Ut":
+        x = _rand(L, 12)
+    elif op == "A":
+        x = _rand(nU + L, 13)
+    else:
+        x = _rand(nU, 14)
+    expect = {"F": m.apply_F, "MD": m.apply_MD, "U": m.apply_U, "Ut": m.apply_Ut,
+              "Kinv_rom": m.apply_Kinv_rom, "A": m.apply_A}[op](x)
+    got = host(getattr(ctx, "apply_" + op)(dev(x)))
+    assert rel(got, expect) < 1e-11, f"{name} {op}: rel err {rel(got, expect):.3e}"
+
+
+def test_multi_rhs_equals_single(pair):
+    name, prob, m, ctx = pair
+    L = m.L
+    X = np.stack([_rand(L, 20 + r) for r in range(3)])
+    Y = host(ctx.apply_F(dev(X.ravel()), nrhs=3)).reshape(3, L)
+    for r in range(3):
+        y1 = host(ctx.apply_F(dev(X[r])))
+        assert np.array_equal(Y[r], y1)
+    U = np.stack([_rand(m.nU, 30 + r) for r in range(2)])
+    K2 = host(ctx.apply_Kinv_rom(dev(U.ravel()), nrhs=2)).reshape(2, m.nU)
+    for r in range(2):
+        assert np.array_equal(K2[r], host(ctx.apply_Kinv_rom(dev(U[r]))))
+
+
+def test_bitwise_repeatable(pair):
+    name, prob, m, ctx = pair
+    x = dev(_rand(m.L, 40))
+    a = host(ctx.apply_F(x))
+    b = host(ctx.apply_F(x))
+    assert np.array_equal(a, b)
+
+
+def test_interface_pcg(pair):
+    name, prob, m, ctx = pair
+    rhs = _rand(m.L, 50)
+    lam_o, its_o, _ = m.solve_interface(rhs, tol=1e-12)
+    lam, its, relres, st = ctx.solve_interface(dev(rhs), tol=1e-12)
+    assert rel(host(lam), lam_o) < 1e-9
+    assert abs(int(its[0]) - its_o) <= 2
+    assert relres[0] <= 1e-12
+
+
+def test_full_solve(pair):
+    name, prob, m, ctx = pair
+    ro = m.solve(tol=1e-12, inner_tol=1e-13, maxit=80)
+    f, d = ctx.get_rhs()
+    u, lam, info = ctx.solve(f[:m.nU].contiguous(), d[:m.L].contiguous(), tol=1e-12, inner_tol=1e-13, maxit=80)
+    assert info["relres"][0] < 1e-11
+    assert rel(host(u), ro["u"]) < 1e-9
+    assert rel(host(lam), ro["lam"]) < 1e-9
+    assert abs(int(info["outer_its"][0]) - ro["outer_its"]) <= 1
+
+
+def test_recover_displacement(pair):
+    name, prob, m, ctx = pair
+    v = _rand(m.nU, 60)
+    y = _rand(m.L, 61)
+    expect = m.apply_Kinv_rom(v) - m.apply_Ut(y)
+    got = host(ctx.recover_displacement(dev(v), dev(y)))
+    assert rel(got, expect) < 1e-11
