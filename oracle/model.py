@@ -10,8 +10,8 @@ Operators (paper Sec. 3.2):
   apply_U/Ut     Ů and Ůᵀ, Algorithm 3 with the first term read as
                  sum_s B_d^(s) Ů_rd^(s)T v_r^(s) (eq. (28)); Ůᵀ by transposition
   apply_Kinv_rom K̊^-ROM of eq. (45) / Algorithm 2 with the reduced local
-                 solves of eq. (46), the Gram matrix taken with the affine ROM
-                 K̃^(s) = sum_m alpha_m K_rr^(sigma_m)
+                 solves of eq. (46), the Gram matrix taken with the cell's own
+                 K_rr^(s)
   apply_A        the true saddle operator of eq. (16)
   apply_prec     the block preconditioner (44), Algorithm 1 (signs as printed:
                  y = -F̊^-pcg w̄ and x = K̊^-ROM v - Ůᵀ y)
@@ -110,8 +110,7 @@ class Model:
         self.sigma = g["sigma"]
         self.alpha = g["alpha"]
         self.bank = romlib.PrincipalBank(self.ref, self.dd, self.Kvals[self.sigma])
-        self.GA, self.gb, self.GM, self.dvec = romlib.coefficient_tensors(self.bank)
-        self.pi, self.delta = romlib.cell_coefficients(self.alpha, self.GA, self.gb, self.GM, self.dvec)
+        self.pi, self.delta = romlib.cell_coefficients(self.ref, self.dd, self.bank, self.Kvals)
         self.Spp_cells = romlib.rom_Spp(self.bank, self.alpha, self.pi)
         self.SPP = romlib.assemble_coarse(self.dd, self.Spp_cells)
         self.coarse = romlib.BandedCholesky(self.SPP)
@@ -162,22 +161,18 @@ class Model:
 
     # ----------------------------------------------------------- K̊^-ROM (45)-(46)
     def rom_local_solve(self, vR: np.ndarray) -> np.ndarray:
-        """Eq. (46): x_r = R (R^T K̃ R)^-1 R^T v_r, R = [K_rr^(sigma_k)-1 v_r]_k, per cell."""
+        """Eq. (46): x_r = R (R^T K_rr^(s) R)^-1 R^T v_r, R = [K_rr^(sigma_k)-1 v_r]_k, per cell."""
         b = self.bank
         N, nr = vR.shape
         K = b.K
         R = np.stack([vR @ b.Kinv[k].T for k in range(K)], axis=2)   # (N, n_r, K)
-        H = np.zeros_like(R)
-        for m in range(K):                                              # K̃_s R_s
-            KR = (b.Krr_sparse[m] @ R.transpose(1, 0, 2).reshape(nr, N * K)).reshape(nr, N, K)
-            H += self.alpha[:, m][:, None, None] * KR.transpose(1, 0, 2)
-        G = np.einsum("sik,sil->skl", R, H)
-        rhs = np.einsum("sik,si->sk", R, vR)
         x = np.zeros_like(vR)
         for s in range(N):
             if not np.any(vR[s]):
                 continue
-            c = romlib.spd_solve(G[s], rhs[s])
+            Krr, _ = romlib.cell_blocks(self.ref, self.dd, self.Kvals[s])
+            G = R[s].T @ (Krr @ R[s])
+            c = romlib.spd_solve(G, R[s].T @ vR[s])
             x[s] = R[s] @ c
         return x
 

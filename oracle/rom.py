@@ -9,10 +9,10 @@ partitioned as in eq. (12) and r = (i, d):
   S_dd = K_dd - K_di K_ii^-1 K_id              eq. (30)  (= F_dd^-1, Sec. 3.1.1)
   K_rr^-1 (explicit, for the reduced solves of eq. (46a))
 
-Per-cell coefficients (eqs. (40)-(42)), with the cell operator replaced by its
-affine ROM K̃^(s) = sum_m alpha_m K^(sigma_m) (eq. (38)):
-  A[i,j] = tr(U_rp^(i)T K̃_rr U_rp^(j)),  b[i] = tr(U_rp^(i)T K̃_rp)
-  M[i,j] = tr(U_rd^(i)T K̃_rr U_rd^(j)),  d[i] = tr(U_rd^(i)T T_rd) = tr(F_dd^(i))
+Per-cell coefficients (eqs. (40)-(42)), energy products taken with the cell's
+own operator K^(s), as the paper writes them:
+  A[i,j] = tr(U_rp^(i)T K_rr^(s) U_rp^(j)),  b[i] = tr(U_rp^(i)T K_rp^(s))
+  M[i,j] = tr(U_rd^(i)T K_rr^(s) U_rd^(j)),  d[i] = tr(U_rd^(i)T T_rd) = tr(F_dd^(i))
   A pi = b,  M delta = d  (Cholesky; symmetric pseudo-inverse with relative
   eigenvalue cut 1e-13 if the Cholesky fails)
 ROM local operators, eq. (43): Ů_rp = sum pi_k U_rp^(k),
@@ -84,33 +84,32 @@ class PrincipalBank:
         self.W = self.Urp[:, ni:, :]          # T_dr U_rp^(k), (K, n_d, n_p)
 
 
-def coefficient_tensors(bank: PrincipalBank):
-    """Traces of eq. (42) for every principal pair and every affine term m."""
+def cell_blocks(ref, dd, vals: np.ndarray):
+    """Sparse K_rr^(s) and K_rp^(s) of one cell from its pattern values."""
+    K = sp.csr_matrix((vals, (ref.pat_rows, ref.pat_cols)), shape=(ref.n_dof, ref.n_dof))
+    Kr = K[dd.idx_r]
+    return Kr[:, dd.idx_r].tocsr(), Kr[:, dd.idx_p].tocsr()
+
+
+def cell_coefficients(ref, dd, bank: PrincipalBank, Kvals: np.ndarray, cells=None):
+    """pi^(s), delta^(s) of eq. (41) with the traces of eq. (42), shape (len(cells), K) each."""
+    N = Kvals.shape[0]
+    cells = np.arange(N) if cells is None else np.atleast_1d(cells)
     K = bank.K
-    GA = np.zeros((K, K, K))
-    GM = np.zeros((K, K, K))
-    gb = np.zeros((K, K))
-    for m in range(K):
-        KU_p = np.matmul(bank.Krr[m][None], bank.Urp)                # K_rr^m U_rp^j
-        KU_d = np.matmul(bank.Krr[m][None], bank.Urd)
-        GA[m] = np.einsum("irp,jrp->ij", bank.Urp, KU_p)
-        GM[m] = np.einsum("ird,jrd->ij", bank.Urd, KU_d)
-        gb[m] = np.einsum("irp,rp->i", bank.Urp, bank.Krp[m])
+    Urp = bank.Urp.transpose(1, 0, 2).reshape(dd.n_r, K * dd.n_p)        # [U_rp^(1) ... U_rp^(K)]
+    Urd = bank.Urd.transpose(1, 0, 2).reshape(dd.n_r, K * dd.n_d)        # [U_rd^(1) ... U_rd^(K)]
     dvec = np.einsum("kdd->k", bank.Fdd)
-    return GA, gb, GM, dvec
-
-
-def cell_coefficients(alpha: np.ndarray, GA, gb, GM, dvec):
-    """pi^(s), delta^(s) from eq. (41), shape (N, K) each."""
-    N, K = alpha.shape
-    pi = np.zeros((N, K))
-    delta = np.zeros((N, K))
-    for s in range(N):
-        A = np.einsum("m,mij->ij", alpha[s], GA)
-        b = alpha[s] @ gb
-        M = np.einsum("m,mij->ij", alpha[s], GM)
-        pi[s] = spd_solve(A, b)
-        delta[s] = spd_solve(M, dvec)
+    pi = np.zeros((cells.size, K))
+    delta = np.zeros((cells.size, K))
+    for t, s in enumerate(cells):
+        Krr, Krp = cell_blocks(ref, dd, Kvals[s])
+        KUp = (Krr @ Urp).reshape(dd.n_r, K, dd.n_p)
+        KUd = (Krr @ Urd).reshape(dd.n_r, K, dd.n_d)
+        A = np.einsum("rip,rjp->ij", bank.Urp.transpose(1, 0, 2), KUp)
+        M = np.einsum("rid,rjd->ij", bank.Urd.transpose(1, 0, 2), KUd)
+        b = np.einsum("irp,rp->i", bank.Urp, Krp.toarray())
+        pi[t] = spd_solve(A, b)
+        delta[t] = spd_solve(M, dvec)
     return pi, delta
 
 
