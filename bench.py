@@ -1,0 +1,185 @@
+"""Benchmark: ROM-based inexact FETI-DP solve on one MI355X.
+
+One step = one full solve of the saddle system (16) to a relative residual of
+1e-8: right-preconditioned FGMRES whose preconditioner (Algorithm 1) runs the
+interface PCG on F̊ with M̊_D^-1, the reduced local solves K̊^-ROM and the Ů/Ůᵀ
+transfers, plus the true operator; inputs (cell operators, principal bank,
+coefficients, coarse inverse, f, d) are resident in HBM before the timed
+region.  Workload: 2D 64x64-cell lattice, 16x16 quadratic elements per cell
+(648 dof/cell), 12 principal cells, FP64, one load case.
+
+value = cell local-solve applies per second over the timed steps, counting one
+apply per cell per load case for each F̊, M̊_D^-1, Ů, Ůᵀ and K̊^-ROM application.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+CELL_OPS = ("F", "MD", "U", "Ut", "Kinv_rom")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def roofline_of(kstats: dict):
+    """Dominant kernel family (largest measured time) against its roofline."""
+    name, k = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_s = k["total_ms"] / 1e3 / max(k["launches"], 1)
+    flops = k["flops"] / max(k["launches"], 1)
+    byts = k["bytes"] / max(k["launches"], 1)
+    ai = flops / byts if byts > 0 else float("inf")
+    if ai > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+        ach = flops / avg_s / 1e12
+        return name, dict(bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=ach / PEAK_FP64_TFLOPS,
+                          traffic=None, kernel=name, launches=k["launches"], avg_us=avg_s * 1e6,
+                          flops_per_launch=flops, bytes_per_launch=byts)
+    ach = byts / avg_s / 1e9
+    return name, dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS,
+                      traffic=None, kernel=name, launches=k["launches"], avg_us=avg_s * 1e6,
+                      flops_per_launch=flops, bytes_per_launch=byts)
+
+
+def cpu_baseline(budget_s: float = 10.0):
+    """The CPU oracle on a bounded sample of the same workload.
+
+    Sample: the c2 cell discretisation (16x16 quadratic elements per cell,
+    12 principal cells, same material, map amplitude and width recipe) on a
+    32x32-cell lattice; FGMRES solves capped at three outer iterations are
+    repeated until `budget_s` seconds of CPU work; applies counted as on the GPU.
+    """
+    import numpy as np
+    import latticegen
+    from oracle import Model
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    p = latticegen.tiny(2, (32, 32), 16, amp=0.15, width=("linx", 0.15, 0.30), n_principal=12)
+    m = Model(p)
+    m.build_reduced_basis()
+    counts = dict.fromkeys(CELL_OPS, 0)
+    for op in CELL_OPS:
+        fn = getattr(m, "apply_" + op)
+
+        def wrapped(x, _fn=fn, _op=op):
+            counts[_op] += 1
+            return _fn(x)
+        setattr(m, "apply_" + op, wrapped)
+    t0 = time.perf_counter()
+    nsolve = 0
+    while True:
+        r = m.solve(tol=1e-8, maxit=3)
+        nsolve += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    applies = sum(counts.values()) * p.N
+    return dict(value=applies / dt, unit="cell-applies/s", cores=int(cores), kind="oracle",
+                sample=f"{nsolve} oracle FP64 solves capped at 3 outer FGMRES iterations ({r['inner_its']} PCG "
+                       f"iterations each) on a 32x32-cell lattice with the c2 cell discretisation; "
+                       f"{applies} cell applies in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--n-principal", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-tol", type=float, default=1e-11)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob = latticegen.make(args.config, n_principal=args.n_principal)
+    t0 = time.perf_counter()
+    ctx = ifeti.setup(prob)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    s = ctx.sizes
+    log(f"setup {setup_s:.1f}s  N={s.N} n_r={s.n_r} n_d={s.n_d} L={s.L} nP={s.nP} K={s.K}")
+    f, d = ctx.get_rhs()
+    f = f[:s.nU].contiguous()
+    d = d[:s.L].contiguous()
+    for i in range(args.warmup):
+        t1 = time.perf_counter()
+        u, lam, info = ctx.solve(f, d, tol=args.tol, inner_tol=args.inner_tol, maxit=200)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t1:.3f}s outer={info['outer_its'][0]} "
+            f"pcg={info['inner_its'][0]} relres={info['relres'][0]:.2e}")
+    ctx.set_options(timing=1)
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        u, lam, info = ctx.solve(f, d, tol=args.tol, inner_tol=args.inner_tol, maxit=200)
+        infos.append(info)
+        log(f"step {i}: outer={info['outer_its'][0]} pcg={info['inner_its'][0]} relres={info['relres'][0]:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = ctx.stats()
+    ctx.set_options(timing=0)
+    applies = sum(st["applies"][op] for op in CELL_OPS) * s.N
+    value = applies / elapsed
+    dom, roof = roofline_of(st["kernels"])
+    kernels = {k: dict(launches=v["launches"], avg_us=v["total_ms"] * 1e3 / max(v["launches"], 1),
+                       share=v["total_ms"] / 1e3 / elapsed) for k, v in sorted(
+                           st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:8]}
+    out = {
+        "metric": "cell local-solve applies/s",
+        "value": value,
+        "unit": "cell-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: 2D 64x64-cell lattice, 648 dof/cell, {s.K} principal cells, "
+                               f"FP64, 1 load case, FGMRES to relres {args.tol:g}",
+                   "cells": s.N, "dof_torn": int(s.nU), "multipliers": s.L, "principal_cells": s.K,
+                   "precision": "fp64", "nrhs": 1},
+        "solve_time_s": elapsed / args.steps,
+        "setup_s": setup_s,
+        "outer_its": int(infos[-1]["outer_its"][0]),
+        "pcg_its_per_solve": int(infos[-1]["inner_its"][0]),
+        "relres": float(infos[-1]["relres"][0]),
+        "applies_per_solve": {k: v // args.steps for k, v in st["applies"].items()},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,7 +91,34 @@ typedef struct {
     int precision;          /* ifeti_precision of the principal contractions */
     int pcg_check_every;    /* PCG host convergence check interval (>= 1)    */
     int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
+    int timing;             /* 1: time every kernel launch with HIP events   */
 } ifeti_options;
+
+/* Per-kernel-family statistics.  flops and bytes are the algorithmic counts
+ * (operations the method needs, minimum HBM traffic of the launch), summed
+ * over launches; total_ms is the sum of the HIP-event durations measured on
+ * the context stream around each launch (0 unless options.timing = 1). */
+typedef struct {
+    char name[32];
+    long long launches;
+    double total_ms;
+    double flops;
+    double bytes;
+} ifeti_kernel_stat;
+
+enum { IFETI_OP_F = 0, IFETI_OP_MD, IFETI_OP_U, IFETI_OP_UT, IFETI_OP_KINV_ROM, IFETI_OP_A, IFETI_OP_COUNT };
+
+typedef struct {
+    long long applies[IFETI_OP_COUNT];  /* operator applications times load cases */
+    long long pcg_iterations;           /* interface PCG iterations, summed over load cases */
+    long long fgmres_iterations;        /* outer iterations, summed over load cases */
+    int n_kernels;
+    ifeti_kernel_stat kernels[32];
+} ifeti_stats;
+
+/* Statistics since the last reset (synchronises the stream when timing is on). */
+int ifeti_get_stats(ifeti_ctx *ctx, ifeti_stats *out);
+int ifeti_reset_stats(ifeti_ctx *ctx);
 
 /* Create a context for the lattice `desc`; work goes to `hip_stream`
  * (hipStream_t, may be NULL for the default stream).  EINVAL for an

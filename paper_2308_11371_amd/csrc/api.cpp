@@ -80,7 +80,42 @@ int ifeti_create(ifeti_ctx **out, const ifeti_lattice_desc *d, void *stream) {
 void ifeti_destroy(ifeti_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    release_events(c);
     delete c;
+}
+
+int ifeti_get_stats(ifeti_ctx *c, ifeti_stats *o) {
+    return guarded([&]() {
+        REQ(c && o, "null argument");
+        flush_events(c);
+        std::memset(o, 0, sizeof(*o));
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) o->applies[i] = c->applies[i];
+        o->pcg_iterations = c->pcg_its;
+        o->fgmres_iterations = c->fgmres_its;
+        int n = 0;
+        for (const auto &k : c->kstats) {
+            if (n >= 32) break;
+            ifeti_kernel_stat &d = o->kernels[n++];
+            std::strncpy(d.name, k.name.c_str(), sizeof(d.name) - 1);
+            d.launches = k.launches;
+            d.total_ms = k.ms;
+            d.flops = k.flops;
+            d.bytes = k.bytes;
+        }
+        o->n_kernels = n;
+        return IFETI_OK;
+    });
+}
+
+int ifeti_reset_stats(ifeti_ctx *c) {
+    return guarded([&]() {
+        REQ(c, "null argument");
+        flush_events(c);
+        for (auto &x : c->applies) x = 0;
+        c->pcg_its = c->fgmres_its = 0;
+        c->kstats.clear();
+        return IFETI_OK;
+    });
 }
 
 int ifeti_get_sizes(const ifeti_ctx *c, ifeti_sizes *o) {
@@ -113,6 +148,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.precision = opt->precision;
         c->opt.pcg_check_every = opt->pcg_check_every;
         c->opt.fgmres_restart = opt->fgmres_restart;
+        if (!opt->timing) flush_events(c);
+        c->opt.timing = opt->timing ? 1 : 0;
         return IFETI_OK;
     });
 }

@@ -96,6 +96,19 @@ struct Options {
     int precision = IFETI_FP64;
     int pcg_check_every = 4;
     int fgmres_restart = 60;
+    int timing = 0;
+};
+
+// Kernel statistics: algorithmic flops/bytes per launch and, when timing is
+// enabled, HIP-event durations recorded on the context stream.
+struct KernelStat {
+    std::string name;
+    long long launches = 0;
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+struct PendingEvent {
+    int id;
+    hipEvent_t a, b;
 };
 
 }  // namespace ifeti
@@ -111,7 +124,7 @@ struct ifeti_ctx {
     // ---- partition (eq. (12)), host
     int n_i = 0, n_d = 0, n_p = 0, n_r = 0;
     std::vector<int> idx_i, idx_d, idx_p, idx_r;
-    std::vector<int> dof_class_pos;     // local dof -> position in r (>=0) or -(1+pos in p)
+    long long nnz_rr = 0, nnz_full = 0;  // stencil non-zeros of K_rr and of the full cell matrix
     // ---- multipliers and primal assembly, host + device
     int L = 0, L_int = 0, nP = 0, n_vert_free = 0;
     long long nU = 0;
@@ -155,9 +168,15 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> Urp;          // [k][n_r][n_p]
     ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
     ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
-    ifeti::DevBuf<double> Kst_pr;       // [k][a][o][dim][dim] principal stencil values
     ifeti::DevBuf<double> SPPinv;       // [nP][nP]
     bool rom_built = false;
+
+    // ---- statistics
+    long long applies[IFETI_OP_COUNT] = {0, 0, 0, 0, 0, 0};
+    long long pcg_its = 0, fgmres_its = 0;
+    std::vector<ifeti::KernelStat> kstats;
+    std::vector<ifeti::PendingEvent> pending;
+    std::vector<hipEvent_t> event_pool;
 
     // ---- work buffers
     ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_x, w_tmpL, w_tmpU;
@@ -167,6 +186,20 @@ struct ifeti_ctx {
 };
 
 namespace ifeti {
+// stats.cpp: RAII timing of one launch (flops/bytes always counted)
+class Prof {
+   public:
+    Prof(ifeti_ctx *c, const char *name, double flops, double bytes);
+    ~Prof();
+
+   private:
+    ifeti_ctx *c_;
+    int id_;
+    hipEvent_t a_ = nullptr;
+};
+void flush_events(ifeti_ctx *c);
+void release_events(ifeti_ctx *c);
+
 // setup_host.cpp
 void build_reference_tables(ifeti_ctx *c);
 void build_partition(ifeti_ctx *c);
@@ -184,7 +217,7 @@ void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int 
 // gemm.hip
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells = 0);
+          bool accumulate, int ncells = 0, const char *tag = "gemm");
 
 // ops.hip
 void ensure_work(ifeti_ctx *c, int nrhs);

@@ -133,7 +133,7 @@ void launch(const GemmArgsDev &a, hipStream_t s) {
 }  // namespace
 
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells) {
+          bool accumulate, int ncells, const char *tag) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
     if (ncols <= 0 || M <= 0) return;
     GemmArgsDev a{};
@@ -155,6 +155,14 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     a.M = M;
     a.ncols = ncols;
     a.accumulate = accumulate ? 1 : 0;
+    // algorithmic work: 2*M*ncols*sum_g K_g*Kd_g flops; operators, cell vectors and results moved once
+    double flops = 0.0, bytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
+    for (int i = 0; i < ngroups; ++i) {
+        flops += 2.0 * M * (double)ncols * groups[i].K * groups[i].Kd;
+        bytes += 8.0 * ((double)groups[i].K * M * groups[i].Kd + (double)ncols * groups[i].Kd +
+                        (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
+    }
+    Prof prof(c, tag, flops, bytes);
     // tile choice: keep >= 256 workgroups where the shape allows it
     long long tiles64 = (long long)((ncols + 63) / 64) * ((M + 63) / 64);
     if (M <= 16)

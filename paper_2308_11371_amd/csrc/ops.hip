@@ -116,10 +116,9 @@ __global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S
 // ------------------------------------------------------------------ reduced local solve (46), Gram part
 // One workgroup per column c (cell s, load case rhs).  R_c holds the K
 // reduced-basis vectors K_rr^(sigma_k)^-1 v (column-major, n_r x K).  The Gram
-// matrix G = R^T K̃_s R uses K̃_s = sum_m alpha_m K_rr^(sigma_m) evaluated on the
-// fly from the principal stencil values; G c = R^T v is solved by Cholesky
-// (symmetric pseudo-inverse with a 1e-13 relative cut if a pivot fails) and
-// x = R c is written.
+// matrix G = R^T K_rr^(s) R uses the cell's own stencil values; G c = R^T v is
+// solved by Cholesky (symmetric pseudo-inverse with a 1e-13 relative cut if a
+// pivot fails) and x = R c is written.
 constexpr int kRomChunk = 64;
 constexpr int kMaxK = 40;
 constexpr int kHGroups = kB / kRomChunk;                       // threads per row of a chunk
@@ -209,8 +208,8 @@ __device__ void small_sym_solve(double *A, double *Lm, double *V, const double *
 
 template <int D>
 __global__ __launch_bounds__(kB) void k_rom_local(const double *__restrict__ vR, long long v_rs,
-                                                  const double *__restrict__ R, const double *__restrict__ alpha,
-                                                  const double *__restrict__ Kpr, const int *__restrict__ r_of_dof,
+                                                  const double *__restrict__ R, const double *__restrict__ Kst,
+                                                  const int *__restrict__ r_of_dof,
                                                   const int *__restrict__ idx_r, int N, int K, int n_r, int nc,
                                                   int n_ctrl, int n_off, int p, double *__restrict__ xR,
                                                   long long x_rs) {
@@ -219,21 +218,18 @@ __global__ __launch_bounds__(kB) void k_rom_local(const double *__restrict__ vR,
     __shared__ double G[kMaxK * kMaxK + kMaxK];  // Gram matrix, then R^T v
     __shared__ double vs[kRomChunk];
     __shared__ double cvec[kMaxK];
-    __shared__ double al[kMaxK];
     double *Rs = sm, *Hs = sm + kMaxK * LDR;
     const int col = blockIdx.x;
     const int rhs = col / N, s = col % N;
     const int tid = threadIdx.x;
     const double *v = vR + rhs * v_rs + (size_t)s * n_r;
     const double *Rc = R + (size_t)col * K * n_r;
-    if (tid < K) al[tid] = alpha[(size_t)s * K + tid];
     const int KK = K * K, npair = KK + K;
     double gacc[kGMax];
 #pragma unroll
     for (int u = 0; u < kGMax; ++u) gacc[u] = 0.0;
     const int w = 2 * p + 1;
-    const size_t mstride = (size_t)n_ctrl * n_off * D * D;
-    __syncthreads();
+    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
     for (int r0 = 0; r0 < n_r; r0 += kRomChunk) {
         const int rl = tid % kRomChunk, kg = tid / kRomChunk;
         const int row = r0 + rl;
@@ -267,9 +263,7 @@ __global__ __launch_bounds__(kB) void k_rom_local(const double *__restrict__ vR,
                 for (int k = 0; k < D; ++k) {
                     const int rc = r_of_dof[b * D + k];
                     if (rc < 0) continue;
-                    const size_t off = (((size_t)a * n_off + o) * D + i) * D + k;
-                    double val = 0.0;
-                    for (int m = 0; m < K; ++m) val += al[m] * Kpr[m * mstride + off];   // K̃_s entry
+                    const double val = Ks[(((size_t)a * n_off + o) * D + i) * D + k];
 #pragma unroll
                     for (int u = 0; u < kHMax; ++u) {
                         const int kk = kg + u * kHGroups;
@@ -477,6 +471,7 @@ void ensure_work(ifeti_ctx *c, int nrhs) {
 
 void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights) {
     long long n = (long long)c->N * c->n_d * nrhs;
+    Prof prof(c, "gather", 0.0, 8.0 * (double)n + 8.0 * (double)c->L * nrhs + 8.0 * (double)c->N * c->n_d);
     hipLaunchKernelGGL(k_gather, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_gather.p, c->g_Dw.p, lam, lam_rs,
                        Lam, c->N, c->n_d, nrhs, weights ? 1 : 0);
 }
@@ -484,6 +479,7 @@ void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, i
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
                 int nrhs, bool weights) {
     long long n = (long long)c->L * nrhs;
+    Prof prof(c, "scatter", 0.0, 8.0 * (double)n + 8.0 * (double)c->N * c->n_d * nrhs + 8.0 * (double)c->L);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_scatter.p, c->g_Dw.p, Y, y_ld,
                        y_off, y_rs, out, out_rs, c->L, c->n_d, nrhs, weights ? 1 : 0);
 }
@@ -492,12 +488,15 @@ void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long
                         long long z_rs, int nrhs) {
     long long n = (long long)c->nP * nrhs;
     if (n == 0) return;
+    Prof prof(c, "assemble_primal", 0.0,
+              8.0 * ((double)c->N * c->n_p * nrhs + (double)n * (base ? 2 : 1)) + 4.0 * (double)c->nP * c->maxc);
     hipLaunchKernelGGL(k_assemble_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ppull.p, c->maxc, cp, c->N,
                        c->n_p, base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
 }
 
 void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs) {
     long long n = (long long)c->N * c->n_p * nrhs;
+    Prof prof(c, "restrict_primal", 0.0, 8.0 * (double)n + 8.0 * (double)c->nP * nrhs + 4.0 * (double)c->N * c->n_p);
     hipLaunchKernelGGL(k_restrict_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ap.p, xP, x_rs, xp, c->N,
                        c->n_p, nrhs);
 }
@@ -506,9 +505,12 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
                      double scale) {
     if (c->nP == 0) return;
     if (nrhs < 4) {
-        for (int r = 0; r < nrhs; ++r)
+        const double n2 = (double)c->nP * c->nP;
+        for (int r = 0; r < nrhs; ++r) {
+            Prof prof(c, "coarse_gemv", 2.0 * n2, 8.0 * n2 + 16.0 * c->nP);
             hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks((long long)c->nP * 64)), dim3(kB), 0, c->stream,
                                c->SPPinv.p, c->nP, z + r * z_rs, y + r * y_rs, scale);
+        }
     } else {
         GemmGroup g;
         g.A = c->SPPinv.p;
@@ -518,7 +520,7 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
         g.xbs = (long long)nrhs * z_rs;
         g.K = 1;
         g.scale = scale;
-        gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs);
+        gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs, "coarse_gemm");
     }
 }
 
@@ -530,15 +532,16 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
     op_gather(c, lam, c->L, c->w_Lam.p, nrhs, false);                       // Lambda = B_d^T lam
     GemmGroup g0;                                                              // c_s = sum pi_k W_k^T Lambda_s
     g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
-    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "F_restrict_gemm");
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
     op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
     op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
     GemmGroup g[2];                                                            // Y = F̊_dd Lambda + (T_dr Ů_rp) y_p
     g[0].A = c->Fdd.p; g[0].X = c->w_Lam.p; g[0].coef = c->delta.p; g[0].Kd = nd; g[0].ldx = nd; g[0].K = K;
     g[1].A = c->W.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
-    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false);
+    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false);
+    c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -549,8 +552,9 @@ void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
     op_gather(c, r, c->L, c->w_Lam.p, nrhs, true);
     GemmGroup g;
     g.A = c->Sdd.p; g.X = c->w_Lam.p; g.coef = c->alpha.p; g.Kd = nd; g.ldx = nd; g.K = K;
-    gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false);
+    gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false, 0, "MD_gemm");
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, true);
+    c->applies[IFETI_OP_MD] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -562,7 +566,7 @@ void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs) {
     const long long nU = c->nU;
     GemmGroup g0;  // t_s = Ů_rp^T v_r
     g0.A = c->UrpT.p; g0.X = v; g0.coef = c->pi.p; g0.Kd = nr; g0.ldx = nr; g0.xbs = nU; g0.K = K;
-    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "U_restrict_gemm");
     // v̄_P = v_P - Ů_RP^T v_R
     op_assemble_primal(c, c->w_c.p, v + (size_t)N * nr, nU, -1.0, c->w_zP.p, c->nP, nrhs);
     op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
@@ -571,8 +575,9 @@ void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs) {
     g[0].A = c->UrdT.p; g[0].X = v; g[0].coef = c->delta.p; g[0].Kd = nr; g[0].ldx = nr; g[0].xbs = nU; g[0].K = K;
     g[1].A = c->W.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
     g[1].scale = -1.0;
-    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false);
+    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false, 0, "U_gemm");
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, z, c->L, nrhs, false);
+    c->applies[IFETI_OP_U] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -585,7 +590,7 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
     op_gather(c, y, c->L, c->w_Lam.p, nrhs, false);
     GemmGroup g0;
     g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
-    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "Ut_restrict_gemm");
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
     double *xP = x + (size_t)N * nr;
     op_coarse_solve(c, c->w_zP.p, c->nP, xP, nU, nrhs, -1.0);  // x_P = -S̊^-1 Ů_RP^T B_R^T y
@@ -594,7 +599,8 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
     g[0].A = c->Urd.p; g[0].X = c->w_Lam.p; g[0].coef = c->delta.p; g[0].Kd = nd; g[0].ldx = nd; g[0].K = K;
     g[1].A = c->Urp.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
     g[1].scale = -1.0;
-    gemm(c, g, 2, x, nr, nU, nr, cols, false);
+    gemm(c, g, 2, x, nr, nU, nr, cols, false, 0, "Ut_gemm");
+    c->applies[IFETI_OP_UT] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -604,17 +610,18 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the stacked explicit inverses
     GemmGroup g;
     g.A = c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
-    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false);
+    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, "rom_R_gemm");
     // (46b) per-cell Gram system and combination
     const RefTables &R = c->ref;
+    const double colsd = (double)N * nrhs;
+    Prof prof(c, "rom_local", colsd * (2.0 * K * c->nnz_rr + 2.0 * K * K * nr + 4.0 * K * nr),
+              colsd * 8.0 * ((K + 2.0) * nr + (double)c->nnz_rr));
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_rom_local<2>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->alpha.p,
-                           c->Kst_pr.p, c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR,
-                           x_rs);
+        hipLaunchKernelGGL(k_rom_local<2>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->Kst.p,
+                           c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR, x_rs);
     else
-        hipLaunchKernelGGL(k_rom_local<3>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->alpha.p,
-                           c->Kst_pr.p, c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR,
-                           x_rs);
+        hipLaunchKernelGGL(k_rom_local<3>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->Kst.p,
+                           c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR, x_rs);
     IFETI_HIP(hipGetLastError());
 }
 
@@ -626,7 +633,7 @@ void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
     const long long nU = c->nU;
     GemmGroup g0;
     g0.A = c->UrpT.p; g0.X = v; g0.coef = c->pi.p; g0.Kd = nr; g0.ldx = nr; g0.xbs = nU; g0.K = K;
-    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false);
+    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "Kinv_restrict_gemm");
     op_assemble_primal(c, c->w_c.p, v + (size_t)N * nr, nU, -1.0, c->w_zP.p, c->nP, nrhs);
     double *xP = x + (size_t)N * nr;
     op_coarse_solve(c, c->w_zP.p, c->nP, xP, nU, nrhs, 1.0);
@@ -634,7 +641,8 @@ void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
     op_restrict_primal(c, xP, nU, c->w_yp.p, nrhs);
     GemmGroup g;                                                 // x_R -= Ů_RP x_P
     g.A = c->Urp.p; g.X = c->w_yp.p; g.coef = c->pi.p; g.Kd = np; g.ldx = np; g.K = K; g.scale = -1.0;
-    gemm(c, &g, 1, x, nr, nU, nr, cols, true);
+    gemm(c, &g, 1, x, nr, nU, nr, cols, true, 0, "Kinv_prolong_gemm");
+    c->applies[IFETI_OP_KINV_ROM] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -645,6 +653,10 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const long long nU = c->nU, rs = nU + c->L;
     const RefTables &R = c->ref;
     size_t shmem = (size_t)R.n_dof * sizeof(double);
+    {
+    const double colsd = (double)N * nrhs;
+    Prof prof(c, "true_K", colsd * 2.0 * c->nnz_full,
+              8.0 * (double)N * R.n_ctrl * R.n_off * c->dim * c->dim + colsd * 8.0 * 2.0 * R.n_dof);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_true_K<2>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
@@ -653,8 +665,10 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
         hipLaunchKernelGGL(k_true_K<3>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
                            c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
+    }
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, y + (size_t)N * nr, rs, nrhs);
     op_scatter(c, x, nr, c->n_i, rs, y + nU, rs, nrhs, false);  // B u
+    c->applies[IFETI_OP_A] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
@@ -667,6 +681,7 @@ void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const do
     int nblk = reduce_blocks(n);
     size_t need = (size_t)nblk * nv * nrhs;
     c->w_red.ensure(need, c->stream);
+    Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 1) * nrhs);
     hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, nrhs), dim3(kB), 0, c->stream, V, vstride, nv, w, n, rs, nblk,
                        c->w_red.p);
     hipLaunchKernelGGL(k_reduce_partials, dim3(nv * nrhs), dim3(kB), 0, c->stream, c->w_red.p, nblk, out_dev);
@@ -675,12 +690,14 @@ void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const do
 
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
                long long n, long long rs, int nrhs) {
+    Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 2) * nrhs);
     hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, nv, coef_dev, a, w,
                        n, rs, nrhs);
     IFETI_HIP(hipGetLastError());
 }
 
 void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs) {
+    Prof prof(c, "gmres_vec", (double)n * nrhs, 16.0 * (double)n * nrhs);
     hipLaunchKernelGGL(k_scale_copy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, x, n, rs, sc_dev, y, nrhs);
     IFETI_HIP(hipGetLastError());
 }

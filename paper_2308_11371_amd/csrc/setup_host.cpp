@@ -218,6 +218,29 @@ void build_partition(ifeti_ctx *c) {
     for (int i = 0; i < c->n_p; ++i) ppos[c->idx_p[i]] = i;
     c->r_of_dof.upload(rpos, c->stream);
     c->p_of_dof.upload(ppos, c->stream);
+    // non-zeros of the shared stencil (full cell matrix and its r-r block)
+    const int w = 2 * R.p + 1;
+    c->nnz_rr = c->nnz_full = 0;
+    int mb[3];
+    for (int a = 0; a < R.n_ctrl; ++a) {
+        multi_index(a, nc, dim, mi);
+        for (int o = 0; o < R.n_off; ++o) {
+            int t = o, b = 0;
+            bool ok = true;
+            for (int j = 0; j < dim; ++j) {
+                mb[j] = mi[j] + (t % w) - R.p;
+                t /= w;
+                if (mb[j] < 0 || mb[j] >= nc) ok = false;
+            }
+            if (!ok) continue;
+            for (int j = dim - 1; j >= 0; --j) b = b * nc + mb[j];
+            for (int i = 0; i < dim; ++i)
+                for (int k = 0; k < dim; ++k) {
+                    c->nnz_full += 1;
+                    if (rpos[a * dim + i] >= 0 && rpos[b * dim + k] >= 0) c->nnz_rr += 1;
+                }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ B, D, A_p (14)-(18), (30)
@@ -691,43 +714,6 @@ void build_principal(const ifeti_ctx *c, const StencilView &sv, Principal &P) {
         }
 }
 
-// Y (n_r x m) = K_rr X using the stencil values of one cell (r rows/cols only).
-void stencil_rr_matmul(const ifeti_ctx *c, const StencilView &sv, const double *Kst, const double *X, int m,
-                       double *Y) {
-    const RefTables &R = c->ref;
-    const int d = R.dim, nc = R.nc;
-    std::vector<int> rpos(R.n_dof, -1);
-    for (int i = 0; i < c->n_r; ++i) rpos[c->idx_r[i]] = i;
-    std::fill(Y, Y + (size_t)c->n_r * m, 0.0);
-    int mi[3];
-    for (int a = 0; a < R.n_ctrl; ++a) {
-        multi_index(a, nc, d, mi);
-        for (int o = 0; o < R.n_off; ++o) {
-            int b = 0;
-            bool ok = true;
-            for (int j = d - 1; j >= 0; --j) {
-                int bj = mi[j] + sv.off[o][j];
-                if (bj < 0 || bj >= nc) ok = false;
-                b = b * nc + bj;
-            }
-            if (!ok) continue;
-            const double *blk = Kst + ((size_t)a * R.n_off + o) * d * d;
-            for (int i = 0; i < d; ++i) {
-                int ri = rpos[a * d + i];
-                if (ri < 0) continue;
-                double *Yi = Y + (size_t)ri * m;
-                for (int k = 0; k < d; ++k) {
-                    int rk = rpos[b * d + k];
-                    if (rk < 0) continue;
-                    double v = blk[i * d + k];
-                    const double *Xk = X + (size_t)rk * m;
-                    for (int t = 0; t < m; ++t) Yi[t] += v * Xk[t];
-                }
-            }
-        }
-    }
-}
-
 template <class F>
 void parallel_for(int n, F f) {
     unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -780,50 +766,121 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     StencilView sv(c);
     parallel_for(K, [&](int k) { build_principal(c, sv, bank[k]); });
     for (int k = 0; k < K; ++k) IFETI_REQUIRE(bank[k].ok, IFETI_ENOTSPD, bank[k].err);
-    // 3. traces of eq. (42) per (i, j, m) with the affine ROM operator K̃ = sum_m alpha_m K^(sigma_m)
-    std::vector<double> GA((size_t)K * K * K), GM((size_t)K * K * K), gb((size_t)K * K), dv(K);
-    parallel_for(K, [&](int m) {
-        std::vector<double> KU((size_t)nr * std::max(np, nd));
-        std::vector<double> Ud((size_t)nr * nd);
-        for (int j = 0; j < K; ++j) {
-            stencil_rr_matmul(c, sv, bank[m].Kst.data(), bank[j].Urp.data(), np, KU.data());
-            for (int i = 0; i < K; ++i) {
-                double s = 0.0;
-                for (size_t t = 0; t < (size_t)nr * np; ++t) s += bank[i].Urp[t] * KU[t];
-                GA[((size_t)m * K + i) * K + j] = s;
+    // 3. traces of eq. (42) with every cell's own operator K^(s).  K^(s) is linear in the cell's
+    //    pulled-back tensor at the quadrature points (eq. (52)), so each trace tr(U^T K^(s) V) is the
+    //    dot product of the cell snapshot with a table Psi[q][ab][cd] = w_q sum_col (grad U)_ab (grad V)_cd
+    //    built once from the principal fields (the lookup-table idea of Sec. 4.2.1, Remark 9); all cells
+    //    then need one GEMM against their snapshots.
+    const int d = R.dim, d2 = d * d, d4 = d2 * d2;
+    const int npair = K * (K + 1) / 2;
+    const int ncoef = 2 * npair + K;  // A pairs, M pairs, b
+    std::vector<int> pi_i(npair), pi_j(npair);
+    {
+        int t = 0;
+        for (int i = 0; i < K; ++i)
+            for (int j = i; j < K; ++j) {
+                pi_i[t] = i;
+                pi_j[t] = j;
+                ++t;
             }
-            // U_rd^(j) = last n_d columns of K_rr^-1
-            for (int r = 0; r < nr; ++r)
-                for (int q = 0; q < nd; ++q) Ud[(size_t)r * nd + q] = bank[j].Kinv[(size_t)r * nr + ni + q];
-            stencil_rr_matmul(c, sv, bank[m].Kst.data(), Ud.data(), nd, KU.data());
-            for (int i = 0; i < K; ++i) {
-                double s = 0.0;
-                for (int r = 0; r < nr; ++r)
-                    for (int q = 0; q < nd; ++q) s += bank[i].Kinv[(size_t)r * nr + ni + q] * KU[(size_t)r * nd + q];
-                GM[((size_t)m * K + i) * K + j] = s;
+    }
+    std::vector<int> rpos_of(R.n_dof, -1), ppos_of(R.n_dof, -1);
+    for (int i = 0; i < nr; ++i) rpos_of[c->idx_r[i]] = i;
+    for (int i = 0; i < np; ++i) ppos_of[c->idx_p[i]] = i;
+    const size_t nsnap = (size_t)R.n_snap;
+    std::vector<double> Psi((size_t)ncoef * nsnap, 0.0);
+    const int nqp = R.n_elem * R.nq;
+    parallel_for(nqp, [&](int eq) {
+        const int E = eq / R.nq;
+        const double wq = R.w[eq];
+        // gradients at this point: gp[k][ab][a] (U_rp), gd[k][ab][col] (U_rd), ge[ab][a] (primal unit fields)
+        std::vector<double> gp((size_t)K * d2 * np, 0.0), gd((size_t)K * d2 * nd, 0.0), ge((size_t)d2 * np, 0.0);
+        for (int l = 0; l < R.nloc; ++l) {
+            const int a = R.elem_ctrl[E * R.nloc + l];
+            const double *dNl = &R.dN[((size_t)eq * R.nloc + l) * d];
+            for (int i1 = 0; i1 < d; ++i1) {
+                const int dof = a * d + i1;
+                const int rp = rpos_of[dof], pp = ppos_of[dof];
+                for (int j1 = 0; j1 < d; ++j1) {
+                    const int ab = i1 * d + j1;
+                    const double g = dNl[j1];
+                    if (pp >= 0) ge[(size_t)ab * np + pp] += g;
+                    if (rp < 0) continue;
+                    for (int k = 0; k < K; ++k) {
+                        const double *urp = &bank[k].Urp[(size_t)rp * np];
+                        double *gpk = &gp[((size_t)k * d2 + ab) * np];
+                        for (int t = 0; t < np; ++t) gpk[t] += g * urp[t];
+                        const double *urd = &bank[k].Kinv[(size_t)rp * nr + ni];
+                        double *gdk = &gd[((size_t)k * d2 + ab) * nd];
+                        for (int t = 0; t < nd; ++t) gdk[t] += g * urd[t];
+                    }
+                }
             }
+        }
+        const size_t base = (size_t)eq * d4;
+        for (int t = 0; t < npair; ++t) {
+            const int i = pi_i[t], j = pi_j[t];
+            double *psiA = &Psi[(size_t)t * nsnap + base];
+            double *psiM = &Psi[(size_t)(npair + t) * nsnap + base];
+            for (int ab = 0; ab < d2; ++ab)
+                for (int cd = 0; cd < d2; ++cd) {
+                    const double *u = &gp[((size_t)i * d2 + ab) * np], *v = &gp[((size_t)j * d2 + cd) * np];
+                    double sa = 0.0;
+                    for (int q = 0; q < np; ++q) sa += u[q] * v[q];
+                    psiA[ab * d2 + cd] = wq * sa;
+                    const double *x = &gd[((size_t)i * d2 + ab) * nd], *y = &gd[((size_t)j * d2 + cd) * nd];
+                    double sm = 0.0;
+                    for (int q = 0; q < nd; ++q) sm += x[q] * y[q];
+                    psiM[ab * d2 + cd] = wq * sm;
+                }
         }
         for (int i = 0; i < K; ++i) {
-            double s = 0.0;
-            for (size_t t = 0; t < (size_t)nr * np; ++t) s += bank[i].Urp[t] * bank[m].Krp[t];
-            gb[(size_t)m * K + i] = s;
+            double *psib = &Psi[(size_t)(2 * npair + i) * nsnap + base];
+            for (int ab = 0; ab < d2; ++ab)
+                for (int cd = 0; cd < d2; ++cd) {
+                    const double *u = &gp[((size_t)i * d2 + ab) * np], *v = &ge[(size_t)cd * np];
+                    double sb = 0.0;
+                    for (int q = 0; q < np; ++q) sb += u[q] * v[q];
+                    psib[ab * d2 + cd] = wq * sb;
+                }
         }
+    });
+    std::vector<double> dv(K);
+    for (int m = 0; m < K; ++m) {
         double tr = 0.0;
         for (int q = 0; q < nd; ++q) tr += bank[m].Fdd[(size_t)q * nd + q];
         dv[m] = tr;
-    });
+    }
+    // the greedy overwrote the snapshots with its residuals: rebuild them, then contract on the device
+    launch_pulled_back(c);
+    std::vector<double> traces((size_t)N * ncoef);
+    {
+        DevBuf<double> dPsi, dOut;
+        dPsi.upload(Psi, c->stream);
+        dOut.alloc((size_t)N * ncoef);
+        GemmGroup g;
+        g.A = dPsi.p;
+        g.X = c->snap.p;
+        g.Kd = (int)nsnap;
+        g.ldx = (int)nsnap;
+        g.K = 1;
+        gemm(c, &g, 1, dOut.p, ncoef, 0, ncoef, N, false, 0, "coef_traces_gemm");
+        IFETI_HIP(hipMemcpyAsync(traces.data(), dOut.p, traces.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+    }
+    c->snap_valid = true;
     // 4. per-cell pi, delta (41)
     std::vector<double> pi((size_t)N * K), delta((size_t)N * K);
     parallel_for(N, [&](int s) {
         std::vector<double> A((size_t)K * K, 0.0), M((size_t)K * K, 0.0), b(K, 0.0);
-        const double *a = &alpha[(size_t)s * K];
-        for (int m = 0; m < K; ++m) {
-            for (int t = 0; t < K * K; ++t) {
-                A[t] += a[m] * GA[(size_t)m * K * K + t];
-                M[t] += a[m] * GM[(size_t)m * K * K + t];
-            }
-            for (int i = 0; i < K; ++i) b[i] += a[m] * gb[(size_t)m * K + i];
+        const double *tr = &traces[(size_t)s * ncoef];
+        for (int t = 0; t < npair; ++t) {
+            const int i = pi_i[t], j = pi_j[t];
+            A[i * K + j] = A[j * K + i] = tr[t];
+            M[i * K + j] = M[j * K + i] = tr[npair + t];
         }
+        for (int i = 0; i < K; ++i) b[i] = tr[2 * npair + i];
         std::vector<double> x = small_spd_solve(A, K, b), y = small_spd_solve(M, K, dv);
         std::copy(x.begin(), x.end(), &pi[(size_t)s * K]);
         std::copy(y.begin(), y.end(), &delta[(size_t)s * K]);
@@ -893,14 +950,13 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     c->delta.upload(delta, c->stream);
     std::vector<double> Fdd((size_t)K * nd * nd), Sdd((size_t)K * nd * nd), W((size_t)K * nd * np),
         WT((size_t)K * np * nd), UrdT((size_t)K * nd * nr), Urd((size_t)K * nr * nd), Urp((size_t)K * nr * np),
-        UrpT((size_t)K * np * nr), Kinv((size_t)K * nr * nr), Kpr((size_t)K * kst_n);
+        UrpT((size_t)K * np * nr), Kinv((size_t)K * nr * nr);
     for (int k = 0; k < K; ++k) {
         const Principal &P = bank[k];
         std::copy(P.Fdd.begin(), P.Fdd.end(), &Fdd[(size_t)k * nd * nd]);
         std::copy(P.Sdd.begin(), P.Sdd.end(), &Sdd[(size_t)k * nd * nd]);
         std::copy(P.Kinv.begin(), P.Kinv.end(), &Kinv[(size_t)k * nr * nr]);
         std::copy(P.Urp.begin(), P.Urp.end(), &Urp[(size_t)k * nr * np]);
-        std::copy(P.Kst.begin(), P.Kst.end(), &Kpr[(size_t)k * kst_n]);
         for (int q = 0; q < nd; ++q)
             for (int a = 0; a < np; ++a) {
                 double v = P.Urp[(size_t)(ni + q) * np + a];
@@ -925,7 +981,6 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     c->Urp.upload(Urp, c->stream);
     c->UrpT.upload(UrpT, c->stream);
     c->Kinv.upload(Kinv, c->stream);
-    c->Kst_pr.upload(Kpr, c->stream);
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
     coarse_inverse_device(c, band, bw);
     IFETI_HIP(hipStreamSynchronize(c->stream));

@@ -248,17 +248,39 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     };
     auto st0 = any_active();
     const int every = std::max(1, c->opt.pcg_check_every);
+    const double Ld = (double)L * nrhs;
     for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
         apply_F(c, p.p, q.p, nrhs);
-        hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, p.p, q.p, L, L, nblk, part_a.p);
-        hipLaunchKernelGGL(k_pcg_alpha, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
-        hipLaunchKernelGGL(k_pcg_update, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r.p, p.p, q.p, L, L, st.p, nblk,
-                           part_b.p);
-        hipLaunchKernelGGL(k_pcg_check, dim3(nrhs), dim3(kB), 0, s, part_b.p, nblk, st.p, ist.p, tol, it);
+        {
+            Prof prof(c, "pcg_dot", 2.0 * Ld, 16.0 * Ld);
+            hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, p.p, q.p, L, L, nblk, part_a.p);
+        }
+        {
+            Prof prof(c, "pcg_scalar", 0.0, 0.0);
+            hipLaunchKernelGGL(k_pcg_alpha, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
+        }
+        {
+            Prof prof(c, "pcg_update", 5.0 * Ld, 48.0 * Ld);  // read lam, p, q, r; write lam, r
+            hipLaunchKernelGGL(k_pcg_update, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r.p, p.p, q.p, L, L, st.p, nblk,
+                               part_b.p);
+        }
+        {
+            Prof prof(c, "pcg_scalar", 0.0, 0.0);
+            hipLaunchKernelGGL(k_pcg_check, dim3(nrhs), dim3(kB), 0, s, part_b.p, nblk, st.p, ist.p, tol, it);
+        }
         apply_MD(c, r.p, z.p, nrhs);
-        hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_a.p);
-        hipLaunchKernelGGL(k_pcg_beta, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
-        hipLaunchKernelGGL(k_pcg_p, dim3(nblocks(n)), dim3(kB), 0, s, p.p, z.p, L, L, nrhs, st.p, ist.p);
+        {
+            Prof prof(c, "pcg_dot", 2.0 * Ld, 16.0 * Ld);
+            hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_a.p);
+        }
+        {
+            Prof prof(c, "pcg_scalar", 0.0, 0.0);
+            hipLaunchKernelGGL(k_pcg_beta, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
+        }
+        {
+            Prof prof(c, "pcg_p", 2.0 * Ld, 24.0 * Ld);
+            hipLaunchKernelGGL(k_pcg_p, dim3(nblocks(n)), dim3(kB), 0, s, p.p, z.p, L, L, nrhs, st.p, ist.p);
+        }
         IFETI_HIP(hipGetLastError());
         if (it % every == 0 || it == maxit) st0 = any_active();
     }
@@ -267,6 +289,7 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     IFETI_HIP(hipMemcpyAsync(hst.data(), st.p, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     IFETI_HIP(hipStreamSynchronize(s));
     for (int r2 = 0; r2 < nrhs; ++r2) {
+        c->pcg_its += hist[r2 * I_N + I_IT];
         if (iters) iters[r2] = hist[r2 * I_N + I_IT];
         if (relres) relres[r2] = hst[r2 * S_N + S_REL];
     }
@@ -442,6 +465,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         double rel = beta[r] > 0 ? std::sqrt(hn[r]) / beta[r] : 0.0;
         if (relres) relres[r] = rel;
         if (outer) outer[r] = kdim[r];
+        c->fgmres_its += kdim[r];
         conv = conv && done[r];
     }
     if (inner_total)

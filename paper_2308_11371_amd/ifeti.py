@@ -23,7 +23,8 @@ IFETI_FP64, IFETI_FP32_LOCAL, IFETI_BF16_LOCAL = 0, 1, 2
 EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_sizes", "ifeti_set_options",
             "ifeti_build_cells", "ifeti_get_rhs", "ifeti_build_reduced_basis", "ifeti_get_coefficients",
             "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_U", "ifeti_apply_Ut", "ifeti_apply_Kinv_rom",
-            "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve")
+            "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
+            "ifeti_get_stats", "ifeti_reset_stats")
 
 
 class LatticeDesc(ctypes.Structure):
@@ -41,7 +42,22 @@ class Sizes(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int),
+                ("timing", ctypes.c_int)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+OP_NAMES = ("F", "MD", "U", "Ut", "Kinv_rom", "A")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("applies", ctypes.c_longlong * 6), ("pcg_iterations", ctypes.c_longlong),
+                ("fgmres_iterations", ctypes.c_longlong), ("n_kernels", ctypes.c_int),
+                ("kernels", KernelStat * 32)]
 
 
 class IfetiError(RuntimeError):
@@ -81,6 +97,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_solve_interface": [P, P, P, I, D, I, P, P],
         "ifeti_recover_displacement": [P, P, P, P, I],
         "ifeti_solve": [P, P, P, P, P, I, D, I, D, P, P, P],
+        "ifeti_get_stats": [P, ctypes.POINTER(Stats)],
+        "ifeti_reset_stats": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -154,9 +172,22 @@ class Context:
         _check(self.lib.ifeti_get_sizes(self.h, ctypes.byref(s)))
         return s
 
-    def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60):
-        o = Options(precision, pcg_check_every, fgmres_restart)
+    def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, timing=0):
+        o = Options(precision, pcg_check_every, fgmres_restart, timing)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self.lib.ifeti_get_stats(self.h, ctypes.byref(s)))
+        kern = {}
+        for i in range(s.n_kernels):
+            k = s.kernels[i]
+            kern[k.name.decode()] = dict(launches=k.launches, total_ms=k.total_ms, flops=k.flops, bytes=k.bytes)
+        return dict(applies={n: s.applies[i] for i, n in enumerate(OP_NAMES)}, pcg_iterations=s.pcg_iterations,
+                    fgmres_iterations=s.fgmres_iterations, kernels=kern)
+
+    def reset_stats(self):
+        _check(self.lib.ifeti_reset_stats(self.h))
 
     # ------------------------------------------------------------ setup
     def build_cells(self, ctrl_pts, widths, tractions: np.ndarray):
