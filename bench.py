@@ -34,7 +34,7 @@ def log(*a):
 
 
 def roofline_of(kstats: dict):
-    """Dominant kernel family (largest measured time) against its roofline."""
+    """Kernel family with the largest measured time against its roofline."""
     name, k = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
     avg_s = k["total_ms"] / 1e3 / max(k["launches"], 1)
     flops = k["flops"] / max(k["launches"], 1)
@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-11)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-kernel", default="F_gemm",
+                    help="kernel family timed with HIP events during the timed steps")
+    ap.add_argument("--all-kernels", action="store_true", help="event-time every kernel family (slower)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -129,7 +132,7 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t1:.3f}s outer={info['outer_its'][0]} "
             f"pcg={info['inner_its'][0]} relres={info['relres'][0]:.2e}")
-    ctx.set_options(timing=1)
+    ctx.set_options(timing=1, timing_filter="" if args.all_kernels else args.roofline_kernel)
     ctx.reset_stats()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -147,7 +150,7 @@ def main():
     dom, roof = roofline_of(st["kernels"])
     kernels = {k: dict(launches=v["launches"], avg_us=v["total_ms"] * 1e3 / max(v["launches"], 1),
                        share=v["total_ms"] / 1e3 / elapsed) for k, v in sorted(
-                           st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:8]}
+                           st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:10] if v["total_ms"] > 0}
     out = {
         "metric": "cell local-solve applies/s",
         "value": value,

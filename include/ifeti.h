@@ -91,7 +91,8 @@ typedef struct {
     int precision;          /* ifeti_precision of the principal contractions */
     int pcg_check_every;    /* PCG host convergence check interval (>= 1)    */
     int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
-    int timing;             /* 1: time every kernel launch with HIP events   */
+    int timing;             /* 1: time kernel launches with HIP events       */
+    char timing_filter[32]; /* "" : every kernel family; else only this one  */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

@@ -81,6 +81,12 @@ void ifeti_destroy(ifeti_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     release_events(c);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+        (void)hipEventDestroy(c->ev_fork);
+        (void)hipEventDestroy(c->ev_join);
+    }
     delete c;
 }
 
@@ -150,6 +156,7 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.fgmres_restart = opt->fgmres_restart;
         if (!opt->timing) flush_events(c);
         c->opt.timing = opt->timing ? 1 : 0;
+        c->opt.timing_filter.assign(opt->timing_filter, strnlen(opt->timing_filter, sizeof(opt->timing_filter)));
         return IFETI_OK;
     });
 }

@@ -97,6 +97,7 @@ struct Options {
     int pcg_check_every = 4;
     int fgmres_restart = 60;
     int timing = 0;
+    std::string timing_filter;  // empty: time every kernel family; else only this one
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
@@ -117,7 +118,10 @@ struct ifeti_ctx {
     // ---- description
     ifeti_lattice_desc desc{};
     int dim = 0, shape[3] = {1, 1, 1}, N = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // stream work is enqueued on (the caller's, except inside a SideStream)
+    hipStream_t side_stream = nullptr;   // second stream for the coarse path
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool side_pending = false;
     ifeti::Options opt;
     ifeti::RefTables ref;
 
@@ -220,6 +224,16 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
           bool accumulate, int ncells = 0, const char *tag = "gemm");
 
 // ops.hip
+class SideStream {
+   public:
+    explicit SideStream(ifeti_ctx *c);
+    ~SideStream();
+
+   private:
+    ifeti_ctx *c_;
+    hipStream_t main_;
+};
+void join_side(ifeti_ctx *c);
 void ensure_work(ifeti_ctx *c, int nrhs);
 void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights);
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,

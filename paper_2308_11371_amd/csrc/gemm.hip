@@ -2,17 +2,29 @@
 //
 //   Y[:, c] (+)= sum_g scale_g sum_k coef_g[cell(c), k] * A_{g,k} X_g[:, c]
 //
-// Every cell (column c; cell = c mod N) combines the same few principal
+// Every cell (column c; cell = c mod ncells) combines the same few principal
 // operators A_{g,k} with its own coefficients (paper Remark 7: the ROM
 // operators of eqs. (48), (49), Algorithm 3 and eq. (46a) as sums over the
-// principal cells), so all cells become one dense GEMM whose B operand is
-// the cell vectors scaled by the coefficients while being staged.
+// principal cells), so all cells become one dense contraction.
 //
-// Tiling: 256 threads = 4 wave64, a TM x TN output tile, wave grid WM x WN;
-// each wave owns (TM/WM) x (TN/WN) made of 16x16 MFMA blocks.  A chunk of the
-// principal operator (TM x KC) and of the cell vectors (TN x KC) are staged in
-// LDS (rows padded by one double against bank conflicts); the coefficient
-// scaling is applied when the B fragment is read from LDS.
+// Mapping (one wave64 = one 16-column block x BM 16-row blocks):
+//  * the wave keeps its 16 cell vectors X[:, c] in registers, one chunk of
+//    up to 128 rows at a time (B fragment of the MFMA: lane l holds column
+//    l%16, rows 4t + l/16), and scales them by the cell coefficient of the
+//    current principal while feeding the MFMA;
+//  * the principal operator streams from L2 (A fragment: lane l holds row
+//    l%16, columns 4t + l/16); 8 steps of A fragments are loaded ahead of
+//    their MFMAs to cover the L2 latency;
+//  * a workgroup is 4 waves.  SPLIT = 1: the 4 waves own 4 consecutive
+//    column blocks of the same rows (they read the same A stream, shared
+//    through L1).  SPLIT = 4: the 4 waves own the same tile and split the
+//    principals (k = wave mod 4); partial sums are reduced through LDS in a
+//    fixed order (small M, e.g. the 8 primal rows).
+// The 16x16 f64 MFMA returns D with lane l, register i -> row 4*i + l/16,
+// column l % 16 (checked on gfx950).
+#include <algorithm>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace ifeti {
@@ -33,101 +45,204 @@ struct GemmArgsDev {
     int ldy, M, ncols, ncells, accumulate;
 };
 
-template <int TM, int TN, int WM, int WN, int KC>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgsDev g) {
-    constexpr int WTM = TM / WM, WTN = TN / WN;
-    constexpr int BM = WTM / 16, BN = WTN / 16;
-    static_assert(WM * WN == 4, "four waves");
-    static_assert(BM >= 1 && BN >= 1, "wave tile >= 16x16");
-    __shared__ double As[TM][KC + 1];
-    __shared__ double Xs[TN][KC + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-    const int m0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
-    const int lr = lane & 15, lk = lane >> 4;
+constexpr int KCH = 128;       // rows of X held in registers per chunk
+constexpr int TSTEPS = KCH / 4;
+constexpr int PF = 8;          // A-fragment steps loaded ahead
 
-    v4d acc[BM][BN];
+template <int BM, int SPLIT>
+__global__ __launch_bounds__(256) void k_pcontract(GemmArgsDev g) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int m0 = blockIdx.y * (16 * BM);
+    const int cblk = SPLIT == 1 ? (blockIdx.x * 4 + wave) : blockIdx.x;
+    const int col = cblk * 16 + lr;
+    const bool cvalid = col < g.ncols;
+    const int cell = cvalid ? col % g.ncells : 0;
+    const long long rhs = cvalid ? col / g.ncells : 0;
+
+    v4d acc[BM];
 #pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-        for (int j = 0; j < BN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < BM; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
 
     for (int gi = 0; gi < g.ngroups; ++gi) {
         const double *__restrict__ A = g.A[gi];
-        const double *__restrict__ X = g.X[gi];
         const double *__restrict__ coef = g.coef[gi];
-        const int Kd = g.Kd[gi], ldx = g.ldx[gi], K = g.K[gi];
-        const long long xbs = g.xbs[gi];
-        const double scale = g.scale[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi];
         const long long strideA = (long long)g.M * Kd;
-        // per-lane cell of each of its B blocks
-        int cell[BN];
-        bool cvalid[BN];
+        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
+        const double scale = g.scale[gi];
+        for (int kk = 0; kk < Kd; kk += KCH) {
+            // cell vectors of this chunk -> registers
+            double braw[TSTEPS];
 #pragma unroll
-        for (int bn = 0; bn < BN; ++bn) {
-            int col = c0 + wn * WTN + bn * 16 + lr;
-            cvalid[bn] = col < g.ncols;
-            cell[bn] = cvalid[bn] ? col % g.ncells : 0;
-        }
-        for (int kk = 0; kk < Kd; kk += KC) {
-            __syncthreads();
-            for (int idx = tid; idx < TN * KC; idx += 256) {
-                int n = idx / KC, kc = idx % KC;
-                int col = c0 + n, kx = kk + kc;
-                Xs[n][kc] = (col < g.ncols && kx < Kd)
-                                ? X[(col / g.ncells) * xbs + (size_t)(col % g.ncells) * ldx + kx]
-                                : 0.0;
+            for (int t = 0; t < TSTEPS; ++t) {
+                const int kx = kk + 4 * t + lk;
+                braw[t] = (cvalid && kx < Kd) ? xcol[kx] : 0.0;
             }
-            for (int k = 0; k < K; ++k) {
-                __syncthreads();
+            const int tmax = std::min(TSTEPS, (Kd - kk + 3) / 4);
+            for (int k = (SPLIT == 1 ? 0 : wave); k < K; k += SPLIT) {
+                const double cf = cvalid ? scale * (coef ? coef[(size_t)cell * K + k] : 1.0) : 0.0;
                 const double *__restrict__ Ak = A + (size_t)k * strideA;
-                for (int idx = tid; idx < TM * KC; idx += 256) {
-                    int m = idx / KC, kc = idx % KC;
-                    int row = m0 + m, kx = kk + kc;
-                    As[m][kc] = (row < g.M && kx < Kd) ? Ak[(size_t)row * Kd + kx] : 0.0;
+                const double *arow[BM];
+                bool rvalid[BM];
+#pragma unroll
+                for (int bm = 0; bm < BM; ++bm) {
+                    const int row = m0 + bm * 16 + lr;
+                    rvalid[bm] = row < g.M;
+                    arow[bm] = Ak + (size_t)(rvalid[bm] ? row : 0) * Kd;
                 }
-                __syncthreads();
-                double cf[BN];
 #pragma unroll
-                for (int bn = 0; bn < BN; ++bn)
-                    cf[bn] = scale * (coef ? (cvalid[bn] ? coef[(size_t)cell[bn] * K + k] : 0.0) : 1.0);
+                for (int t0 = 0; t0 < TSTEPS; t0 += PF) {
+                    if (t0 >= tmax) break;
+                    double a[PF][BM];
 #pragma unroll
-                for (int kc = 0; kc < KC; kc += 4) {
-                    double a[BM], b[BN];
+                    for (int u = 0; u < PF; ++u) {
+                        const int kx = kk + 4 * (t0 + u) + lk;
 #pragma unroll
-                    for (int bm = 0; bm < BM; ++bm) a[bm] = As[wm * WTM + bm * 16 + lr][kc + lk];
+                        for (int bm = 0; bm < BM; ++bm)
+                            a[u][bm] = (t0 + u < tmax && rvalid[bm] && kx < Kd) ? arow[bm][kx] : 0.0;
+                    }
 #pragma unroll
-                    for (int bn = 0; bn < BN; ++bn) b[bn] = Xs[wn * WTN + bn * 16 + lr][kc + lk] * cf[bn];
+                    for (int u = 0; u < PF; ++u) {
+                        const double b = braw[t0 + u] * cf;
 #pragma unroll
-                    for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-                        for (int bn = 0; bn < BN; ++bn)
-                            acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+                        for (int bm = 0; bm < BM; ++bm)
+                            acc[bm] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][bm], b, acc[bm], 0, 0, 0);
+                    }
                 }
             }
         }
     }
-    // D layout of the 16x16 f64 MFMA (checked on gfx950): lane l, register i -> row 4*i + l/16, column l % 16
+    if constexpr (SPLIT > 1) {
+        __shared__ double red[SPLIT][BM][4][64];
+#pragma unroll
+        for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave][bm][i][lane] = acc[bm][i];
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double s = red[0][bm][i][lane];
+#pragma unroll
+                for (int w = 1; w < SPLIT; ++w) s += red[w][bm][i][lane];
+                acc[bm][i] = s;
+            }
+    }
+    if (!cvalid) return;
+    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
 #pragma unroll
     for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-        for (int bn = 0; bn < BN; ++bn) {
-            int col = c0 + wn * WTN + bn * 16 + lr;
-            if (col >= g.ncols) continue;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int row = m0 + wm * WTM + bm * 16 + 4 * i + lk;
-                if (row >= g.M) continue;
-                double *y = g.Y + (col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy + row;
-                *y = g.accumulate ? *y + acc[bm][bn][i] : acc[bm][bn][i];
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int row = m0 + bm * 16 + 4 * i + lk;
+            if (row >= g.M) continue;
+            ycol[row] = g.accumulate ? ycol[row] + acc[bm][i] : acc[bm][i];
         }
 }
 
-template <int TM, int TN, int WM, int WN, int KC>
+// LDS-staged variant for row counts >= 32: the workgroup (4 waves = 4 column
+// blocks of 16 cells, 32 rows) stages each 32 x 64 tile of a principal
+// operator in LDS with coalesced 16-byte loads, double-buffered through
+// registers so the next tile is in flight while the MFMAs consume this one.
+constexpr int LT = 64;          // columns of A per LDS tile
+constexpr int LDA = LT + 4;     // padded LDS row (doubles)
+
+__global__ __launch_bounds__(256) void k_pcontract_lds(GemmArgsDev g) {
+    __shared__ double As[2][32][LDA];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int m0 = blockIdx.y * 32;
+    const int col = (blockIdx.x * 4 + wave) * 16 + lr;
+    const bool cvalid = col < g.ncols;
+    const int cell = cvalid ? col % g.ncells : 0;
+    const long long rhs = cvalid ? col / g.ncells : 0;
+    // cooperative tile load: thread -> (row, 8 consecutive doubles)
+    const int ld_row = tid >> 3, ld_c = (tid & 7) * 8;
+
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const double *__restrict__ A = g.A[gi];
+        const double *__restrict__ coef = g.coef[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi];
+        const long long strideA = (long long)g.M * Kd;
+        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
+        const double scale = g.scale[gi];
+        const bool vec_ok = (Kd % 2) == 0;
+        for (int kk = 0; kk < Kd; kk += KCH) {
+            double braw[TSTEPS];
+#pragma unroll
+            for (int t = 0; t < TSTEPS; ++t) {
+                const int kx = kk + 4 * t + lk;
+                braw[t] = (cvalid && kx < Kd) ? xcol[kx] : 0.0;
+            }
+            const int nsub = (std::min(KCH, Kd - kk) + LT - 1) / LT;  // LDS tiles per principal
+            const int ntile = K * nsub;
+            // register stage of the next tile
+            double st[8];
+            auto fetch = [&](int tile) {
+                const int k = tile / nsub, sub = tile % nsub;
+                const int row = m0 + ld_row;
+                const int c0 = kk + sub * LT + ld_c;
+                const double *src = A + (size_t)k * strideA + (size_t)row * Kd + c0;
+                if (row < g.M && vec_ok && c0 + 7 < Kd) {
+                    const double2 *s2 = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double2 v = s2[u];
+                        st[2 * u] = v.x;
+                        st[2 * u + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) st[u] = (row < g.M && c0 + u < Kd) ? src[u] : 0.0;
+                }
+            };
+            fetch(0);
+            for (int tile = 0; tile < ntile; ++tile) {
+                const int buf = tile & 1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) As[buf][ld_row][ld_c + u] = st[u];
+                __syncthreads();
+                if (tile + 1 < ntile) fetch(tile + 1);
+                const int k = tile / nsub, sub = tile % nsub;
+                const double cf = cvalid ? scale * (coef ? coef[(size_t)cell * K + k] : 1.0) : 0.0;
+                auto consume = [&](auto SUB) {
+                    constexpr int sb = decltype(SUB)::value;
+#pragma unroll
+                    for (int u = 0; u < LT / 4; ++u) {
+                        const double b = braw[sb * (LT / 4) + u] * cf;
+                        const double a0 = As[buf][lr][4 * u + lk];
+                        const double a1 = As[buf][16 + lr][4 * u + lk];
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1, 0, 0, 0);
+                    }
+                };
+                if (sub == 0)
+                    consume(std::integral_constant<int, 0>{});
+                else
+                    consume(std::integral_constant<int, 1>{});
+                __syncthreads();
+            }
+        }
+    }
+    if (!cvalid) return;
+    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r0 = m0 + 4 * i + lk, r1 = r0 + 16;
+        if (r0 < g.M) ycol[r0] = g.accumulate ? ycol[r0] + acc0[i] : acc0[i];
+        if (r1 < g.M) ycol[r1] = g.accumulate ? ycol[r1] + acc1[i] : acc1[i];
+    }
+}
+
+template <int BM, int SPLIT>
 void launch(const GemmArgsDev &a, hipStream_t s) {
-    dim3 grid((a.ncols + TN - 1) / TN, (a.M + TM - 1) / TM);
-    hipLaunchKernelGGL((k_gemm_f64<TM, TN, WM, WN, KC>), grid, dim3(256), 0, s, a);
+    const int cblocks = (a.ncols + 15) / 16;
+    dim3 grid(SPLIT == 1 ? (cblocks + 3) / 4 : cblocks, (a.M + 16 * BM - 1) / (16 * BM));
+    hipLaunchKernelGGL((k_pcontract<BM, SPLIT>), grid, dim3(256), 0, s, a);
 }
 
 }  // namespace
@@ -138,7 +253,9 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     if (ncols <= 0 || M <= 0) return;
     GemmArgsDev a{};
     a.ncells = ncells > 0 ? ncells : c->N;
+    int Kmax = 0, Kdmax = 0;
     for (int i = 0; i < ngroups; ++i) {
+        Kdmax = std::max(Kdmax, groups[i].Kd);
         a.A[i] = groups[i].A;
         a.X[i] = groups[i].X;
         a.coef[i] = groups[i].coef;
@@ -147,6 +264,7 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         a.xbs[i] = groups[i].xbs ? groups[i].xbs : (long long)a.ncells * groups[i].ldx;
         a.K[i] = groups[i].K;
         a.scale[i] = groups[i].scale;
+        Kmax = std::max(Kmax, groups[i].K);
     }
     a.ngroups = ngroups;
     a.Y = Y;
@@ -163,16 +281,16 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
                         (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
     }
     Prof prof(c, tag, flops, bytes);
-    // tile choice: keep >= 256 workgroups where the shape allows it
-    long long tiles64 = (long long)((ncols + 63) / 64) * ((M + 63) / 64);
-    if (M <= 16)
-        launch<16, 64, 1, 4, 32>(a, c->stream);
-    else if (M <= 32)
-        launch<32, 64, 2, 2, 32>(a, c->stream);
-    else if (tiles64 >= 512)
-        launch<64, 64, 2, 2, 32>(a, c->stream);
-    else
-        launch<64, 32, 2, 2, 32>(a, c->stream);
+    // enough waves to cover the 1024 SIMDs; two row blocks per wave when there are plenty
+    const long long cblocks = (ncols + 15) / 16;
+    if (M <= 16 && Kmax >= 4) {
+        launch<1, 4>(a, c->stream);
+    } else if (M <= 16 || Kdmax <= 16) {
+        launch<1, 1>(a, c->stream);
+    } else {
+        dim3 grid((unsigned)((cblocks + 3) / 4), (unsigned)((M + 31) / 32));
+        hipLaunchKernelGGL(k_pcontract_lds, grid, dim3(256), 0, c->stream, a);
+    }
     IFETI_HIP(hipGetLastError());
 }
 

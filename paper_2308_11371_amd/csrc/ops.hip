@@ -99,13 +99,25 @@ __global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S
     if (wave >= n) return;
     const double *row = S + (size_t)wave * n;
     double acc = 0.0;
-    if ((n & 1) == 0) {  // rows start 16-byte aligned: paired loads
+    if ((n & 1) == 0) {  // rows start 16-byte aligned: paired loads, 4 in flight per lane
         const double2 *r2 = reinterpret_cast<const double2 *>(row);
         const double2 *z2 = reinterpret_cast<const double2 *>(z);
-        for (int i = lane; i < n / 2; i += 64) {
+        const int n2 = n / 2;
+        double acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        int i = lane;
+        for (; i + 192 < n2; i += 256) {
+            double2 a0 = r2[i], a1 = r2[i + 64], a2 = r2[i + 128], a3 = r2[i + 192];
+            double2 b0 = z2[i], b1 = z2[i + 64], b2 = z2[i + 128], b3 = z2[i + 192];
+            acc += a0.x * b0.x + a0.y * b0.y;
+            acc1 += a1.x * b1.x + a1.y * b1.y;
+            acc2 += a2.x * b2.x + a2.y * b2.y;
+            acc3 += a3.x * b3.x + a3.y * b3.y;
+        }
+        for (; i < n2; i += 64) {
             double2 a = r2[i], b = z2[i];
             acc += a.x * b.x + a.y * b.y;
         }
+        acc += (acc1 + acc2) + acc3;
     } else {
         for (int i = lane; i < n; i += 64) acc += row[i] * z[i];
     }
@@ -456,6 +468,32 @@ __global__ __launch_bounds__(kB) void k_scale_copy(const double *__restrict__ x,
 }  // namespace
 
 // ================================================================== host wrappers
+// Work enqueued inside a SideStream scope goes to the context's second stream
+// (default priority); it starts after everything queued so far on the main
+// stream, and join_side() makes the main stream wait for it.
+SideStream::SideStream(ifeti_ctx *c) : c_(c), main_(c->stream) {
+    if (!c->side_stream) {
+        IFETI_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+        IFETI_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        IFETI_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    IFETI_HIP(hipEventRecord(c->ev_fork, main_));
+    IFETI_HIP(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+    c->stream = c->side_stream;
+}
+
+SideStream::~SideStream() {
+    (void)hipEventRecord(c_->ev_join, c_->side_stream);
+    c_->stream = main_;
+    c_->side_pending = true;
+}
+
+void join_side(ifeti_ctx *c) {
+    if (!c->side_pending) return;
+    IFETI_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    c->side_pending = false;
+}
+
 void ensure_work(ifeti_ctx *c, int nrhs) {
     size_t cols = (size_t)c->N * nrhs;
     hipStream_t s = c->stream;
@@ -525,21 +563,31 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 }
 
 // ------------------------------------------------------------------ F̊ (48)
+// Lambda = B_d^T lam; c_s = (T_dr Ů_rp^(s))^T Lambda_s, assembled and sent through the
+// coarse solve on the side stream while the main stream runs the dominant
+// contraction sum_k delta_k F_dd^(k) Lambda; the coarse correction
+// (T_dr Ů_rp^(s)) A_p^T y_P is added after the join, then B_d scatters.
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
     ensure_work(c, nrhs);
     const int N = c->N, nd = c->n_d, np = c->n_p, K = c->K;
     const int cols = N * nrhs;
-    op_gather(c, lam, c->L, c->w_Lam.p, nrhs, false);                       // Lambda = B_d^T lam
-    GemmGroup g0;                                                              // c_s = sum pi_k W_k^T Lambda_s
+    op_gather(c, lam, c->L, c->w_Lam.p, nrhs, false);
+    GemmGroup g0;
     g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
     gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "F_restrict_gemm");
-    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
-    op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
-    op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
-    GemmGroup g[2];                                                            // Y = F̊_dd Lambda + (T_dr Ů_rp) y_p
-    g[0].A = c->Fdd.p; g[0].X = c->w_Lam.p; g[0].coef = c->delta.p; g[0].Kd = nd; g[0].ldx = nd; g[0].K = K;
-    g[1].A = c->W.p; g[1].X = c->w_yp.p; g[1].coef = c->pi.p; g[1].Kd = np; g[1].ldx = np; g[1].K = K;
-    gemm(c, g, 2, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
+    {
+        SideStream side(c);
+        op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
+        op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
+        op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
+    }
+    GemmGroup g1;
+    g1.A = c->Fdd.p; g1.X = c->w_Lam.p; g1.coef = c->delta.p; g1.Kd = nd; g1.ldx = nd; g1.K = K;
+    gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
+    join_side(c);
+    GemmGroup g2;
+    g2.A = c->W.p; g2.X = c->w_yp.p; g2.coef = c->pi.p; g2.Kd = np; g2.ldx = np; g2.K = K;
+    gemm(c, &g2, 1, c->w_Y.p, nd, 0, nd, cols, true, 0, "F_prolong_gemm");
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());

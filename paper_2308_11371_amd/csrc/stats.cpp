@@ -28,7 +28,7 @@ Prof::Prof(ifeti_ctx *c, const char *name, double flops, double bytes) : c_(c), 
     k.launches += 1;
     k.flops += flops;
     k.bytes += bytes;
-    if (c->opt.timing) {
+    if (c->opt.timing && (c->opt.timing_filter.empty() || c->opt.timing_filter == name)) {
         a_ = get_event(c);
         IFETI_HIP(hipEventRecord(a_, c->stream));
     }
