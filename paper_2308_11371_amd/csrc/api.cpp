@@ -148,7 +148,8 @@ int ifeti_get_sizes(const ifeti_ctx *c, ifeti_sizes *o) {
 int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
     return guarded([&]() {
         REQ(c && opt, "null argument");
-        REQ(opt->precision == IFETI_FP64, "only the FP64 precision form is available in this build");
+        REQ(opt->precision == IFETI_FP64 || opt->precision == IFETI_FP32_LOCAL || opt->precision == IFETI_BF16_LOCAL,
+            "precision must be IFETI_FP64, IFETI_FP32_LOCAL or IFETI_BF16_LOCAL");
         REQ(opt->pcg_check_every >= 1, "pcg_check_every must be >= 1");
         REQ(opt->fgmres_restart >= 1, "fgmres_restart must be >= 1");
         c->opt.precision = opt->precision;

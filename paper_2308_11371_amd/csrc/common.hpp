@@ -174,6 +174,18 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
     ifeti::DevBuf<double> SPPinv;       // [nP][nP]
     bool rom_built = false;
+    struct LPCopy {                     // fp32 / bf16 copies of a bank array (precision form)
+        const double *src = nullptr;
+        size_t n = 0;
+        void *f32 = nullptr, *bf16 = nullptr;
+    };
+    std::vector<LPCopy> lp;
+    ~ifeti_ctx() {
+        for (auto &cp : lp) {
+            if (cp.f32) (void)hipFree(cp.f32);
+            if (cp.bf16) (void)hipFree(cp.bf16);
+        }
+    }
 
     // ---- statistics
     long long applies[IFETI_OP_COUNT] = {0, 0, 0, 0, 0, 0};
@@ -221,7 +233,9 @@ void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int 
 // gemm.hip
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells = 0, const char *tag = "gemm");
+          bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
+void make_lp_copies(ifeti_ctx *c, const std::vector<std::pair<const double *, size_t>> &arrays);
+const void *lp_copy(ifeti_ctx *c, const double *A, int precision);
 
 // ops.hip
 class SideStream {

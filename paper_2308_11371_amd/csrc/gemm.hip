@@ -238,6 +238,125 @@ __global__ __launch_bounds__(256) void k_pcontract_lds(GemmArgsDev g) {
     }
 }
 
+// ---------------------------------------------------------------- low-precision operands
+// Precision form: the principal operators (and the cell vectors, rounded as they
+// are fed) in fp32 (v_mfma_f32_16x16x4f32) or bf16 (v_mfma_f32_16x16x32_bf16)
+// with fp32 accumulation; results are returned in float64.  Same staging as the
+// FP64 kernel: 32 x 64 operator tiles in LDS, double-buffered through registers;
+// each wave keeps 16 cell vectors in registers.  The f32/bf16 16x16 MFMAs return
+// D with lane l, register i -> row 4*(l/16) + i, column l % 16 (checked on gfx950).
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+struct GemmArgsLP {
+    const void *A[2];
+    const double *X[2];
+    const double *coef[2];
+    int Kd[2], ldx[2], K[2];
+    long long xbs[2];
+    double scale[2];
+    int ngroups;
+    double *Y;
+    long long ybs;
+    int ldy, M, ncols, ncells, accumulate;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcontract_lp(GemmArgsLP g) {
+    constexpr bool BF = sizeof(T) == 2;
+    constexpr int KS = BF ? 32 : 4;          // reduction depth of one MFMA
+    constexpr int LDL = LT + (BF ? 8 : 4);   // padded LDS row (elements)
+    __shared__ __attribute__((aligned(16))) T As[2][32][LDL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int m0 = blockIdx.y * 32;
+    const int col = (blockIdx.x * 4 + wave) * 16 + lr;
+    const bool cvalid = col < g.ncols;
+    const int cell = cvalid ? col % g.ncells : 0;
+    const long long rhs = cvalid ? col / g.ncells : 0;
+    const int ld_row = tid >> 3, ld_c = (tid & 7) * 8;
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const T *__restrict__ A = reinterpret_cast<const T *>(g.A[gi]);
+        const double *__restrict__ coef = g.coef[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi];
+        const long long strideA = (long long)g.M * Kd;
+        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
+        const double scale = g.scale[gi];
+        for (int kk = 0; kk < Kd; kk += KCH) {
+            // lane's share of the chunk: f32: k = 4t + l/16; bf16: k = 32t + 8(l/16) + e
+            float braw[TSTEPS];
+#pragma unroll
+            for (int t = 0; t < TSTEPS; ++t) {
+                const int kx = BF ? kk + 32 * (t / 8) + 8 * lk + (t % 8) : kk + 4 * t + lk;
+                braw[t] = (cvalid && kx < Kd) ? (float)xcol[kx] : 0.f;
+            }
+            const int nsub = (std::min(KCH, Kd - kk) + LT - 1) / LT;
+            const int ntile = K * nsub;
+            T st[8];
+            auto fetch = [&](int tile) {
+                const int k = tile / nsub, sub = tile % nsub;
+                const int row = m0 + ld_row, c0 = kk + sub * LT + ld_c;
+                const T *src = A + (size_t)k * strideA + (size_t)row * Kd + c0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) st[u] = (row < g.M && c0 + u < Kd) ? src[u] : T(0.f);
+            };
+            fetch(0);
+            for (int tile = 0; tile < ntile; ++tile) {
+                const int buf = tile & 1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) As[buf][ld_row][ld_c + u] = st[u];
+                __syncthreads();
+                if (tile + 1 < ntile) fetch(tile + 1);
+                const int k = tile / nsub, sub = tile % nsub;
+                const float cf = cvalid ? (float)(scale * (coef ? coef[(size_t)cell * K + k] : 1.0)) : 0.f;
+                auto consume = [&](auto SUB) {
+                    constexpr int sb = decltype(SUB)::value;
+#pragma unroll
+                    for (int u = 0; u < LT / KS; ++u) {
+                        if constexpr (BF) {
+                            const v8bf a0 = *reinterpret_cast<const v8bf *>(&As[buf][lr][KS * u + 8 * lk]);
+                            const v8bf a1 = *reinterpret_cast<const v8bf *>(&As[buf][16 + lr][KS * u + 8 * lk]);
+                            v8bf b;
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) b[e] = (__bf16)(braw[(sb * (LT / KS) + u) * 8 + e] * cf);
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc1, 0, 0, 0);
+                        } else {
+                            const float b = braw[sb * (LT / KS) + u] * cf;
+                            const float a0 = As[buf][lr][KS * u + lk];
+                            const float a1 = As[buf][16 + lr][KS * u + lk];
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc1, 0, 0, 0);
+                        }
+                    }
+                };
+                if (sub == 0)
+                    consume(std::integral_constant<int, 0>{});
+                else
+                    consume(std::integral_constant<int, 1>{});
+                __syncthreads();
+            }
+        }
+    }
+    if (!cvalid) return;
+    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r0 = m0 + 4 * lk + i, r1 = r0 + 16;
+        if (r0 < g.M) ycol[r0] = g.accumulate ? ycol[r0] + (double)acc0[i] : (double)acc0[i];
+        if (r1 < g.M) ycol[r1] = g.accumulate ? ycol[r1] + (double)acc1[i] : (double)acc1[i];
+    }
+}
+
+__global__ void k_to_lp(const double *__restrict__ x, float *__restrict__ f, __bf16 *__restrict__ b, long long n) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float v = (float)x[t];
+    f[t] = v;
+    b[t] = (__bf16)v;
+}
+
 template <int BM, int SPLIT>
 void launch(const GemmArgsDev &a, hipStream_t s) {
     const int cblocks = (a.ncols + 15) / 16;
@@ -247,8 +366,34 @@ void launch(const GemmArgsDev &a, hipStream_t s) {
 
 }  // namespace
 
+// fp32/bf16 copies of the principal operators used by the precision form
+void make_lp_copies(ifeti_ctx *c, const std::vector<std::pair<const double *, size_t>> &arrays) {
+    c->lp.clear();
+    for (auto &ar : arrays) {
+        ifeti_ctx::LPCopy cp;
+        cp.src = ar.first;
+        cp.n = ar.second;
+        IFETI_HIP(hipMalloc(&cp.f32, ar.second * sizeof(float)));
+        IFETI_HIP(hipMalloc(&cp.bf16, ar.second * 2));
+        hipLaunchKernelGGL(k_to_lp, dim3((unsigned)((ar.second + 255) / 256)), dim3(256), 0, c->stream, ar.first,
+                           (float *)cp.f32, (__bf16 *)cp.bf16, (long long)ar.second);
+        IFETI_HIP(hipGetLastError());
+        c->lp.push_back(cp);
+    }
+}
+
+const void *lp_copy(ifeti_ctx *c, const double *A, int precision) {
+    for (auto &cp : c->lp)
+        if (A >= cp.src && A < cp.src + cp.n) {
+            const size_t off = A - cp.src;
+            return precision == IFETI_FP32_LOCAL ? (const void *)((const float *)cp.f32 + off)
+                                                 : (const void *)((const uint16_t *)cp.bf16 + off);
+        }
+    return nullptr;
+}
+
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells, const char *tag) {
+          bool accumulate, int ncells, const char *tag, bool lp_ok) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
     if (ncols <= 0 || M <= 0) return;
     GemmArgsDev a{};
@@ -280,9 +425,46 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         bytes += 8.0 * ((double)groups[i].K * M * groups[i].Kd + (double)ncols * groups[i].Kd +
                         (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
     }
-    Prof prof(c, tag, flops, bytes);
-    // enough waves to cover the 1024 SIMDs; two row blocks per wave when there are plenty
     const long long cblocks = (ncols + 15) / 16;
+    if (lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16) {
+        GemmArgsLP b{};
+        bool all = true;
+        for (int i = 0; i < ngroups; ++i) {
+            const void *lpA = lp_copy(c, groups[i].A, c->opt.precision);
+            all = all && lpA;
+            b.A[i] = lpA;
+            b.X[i] = a.X[i];
+            b.coef[i] = a.coef[i];
+            b.Kd[i] = a.Kd[i];
+            b.ldx[i] = a.ldx[i];
+            b.xbs[i] = a.xbs[i];
+            b.K[i] = a.K[i];
+            b.scale[i] = a.scale[i];
+        }
+        if (all) {
+            b.ngroups = ngroups;
+            b.Y = Y;
+            b.ybs = a.ybs;
+            b.ldy = ldy;
+            b.M = M;
+            b.ncols = ncols;
+            b.ncells = a.ncells;
+            b.accumulate = a.accumulate;
+            const double esz = c->opt.precision == IFETI_FP32_LOCAL ? 4.0 : 2.0;
+            double lbytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
+            for (int i = 0; i < ngroups; ++i)
+                lbytes += esz * (double)groups[i].K * M * groups[i].Kd + 8.0 * (double)ncols * groups[i].Kd;
+            Prof prof(c, tag, flops, lbytes);
+            dim3 grid((unsigned)((cblocks + 3) / 4), (unsigned)((M + 31) / 32));
+            if (c->opt.precision == IFETI_FP32_LOCAL)
+                hipLaunchKernelGGL(k_pcontract_lp<float>, grid, dim3(256), 0, c->stream, b);
+            else
+                hipLaunchKernelGGL(k_pcontract_lp<__bf16>, grid, dim3(256), 0, c->stream, b);
+            IFETI_HIP(hipGetLastError());
+            return;
+        }
+    }
+    Prof prof(c, tag, flops, bytes);
     if (M <= 16 && Kmax >= 4) {
         launch<1, 4>(a, c->stream);
     } else if (M <= 16 || Kdmax <= 16) {

@@ -558,7 +558,7 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
         g.xbs = (long long)nrhs * z_rs;
         g.K = 1;
         g.scale = scale;
-        gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs, "coarse_gemm");
+        gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs, "coarse_gemm", false);
     }
 }
 

@@ -864,7 +864,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
         g.Kd = (int)nsnap;
         g.ldx = (int)nsnap;
         g.K = 1;
-        gemm(c, &g, 1, dOut.p, ncoef, 0, ncoef, N, false, 0, "coef_traces_gemm");
+        gemm(c, &g, 1, dOut.p, ncoef, 0, ncoef, N, false, 0, "coef_traces_gemm", false);
         IFETI_HIP(hipMemcpyAsync(traces.data(), dOut.p, traces.size() * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
         IFETI_HIP(hipStreamSynchronize(c->stream));
@@ -981,6 +981,14 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     c->Urp.upload(Urp, c->stream);
     c->UrpT.upload(UrpT, c->stream);
     c->Kinv.upload(Kinv, c->stream);
+    for (auto &cp : c->lp) {
+        (void)hipFree(cp.f32);
+        (void)hipFree(cp.bf16);
+    }
+    c->lp.clear();
+    make_lp_copies(c, {{c->Fdd.p, c->Fdd.n}, {c->Sdd.p, c->Sdd.n}, {c->W.p, c->W.n}, {c->WT.p, c->WT.n},
+                       {c->UrdT.p, c->UrdT.n}, {c->Urd.p, c->Urd.n}, {c->Urp.p, c->Urp.n}, {c->UrpT.p, c->UrpT.n},
+                       {c->Kinv.p, c->Kinv.n}});
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
     coarse_inverse_device(c, band, bw);
     IFETI_HIP(hipStreamSynchronize(c->stream));

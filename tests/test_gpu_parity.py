@@ -147,3 +147,30 @@ def test_recover_displacement(pair):
     expect = m.apply_Kinv_rom(v) - m.apply_Ut(y)
     got = host(ctx.recover_displacement(dev(v), dev(y)))
     assert rel(got, expect) < 1e-11
+
+
+def test_block_rhs_equals_single_solves():
+    """Block form: nrhs independent recurrences sharing every operator application equal nrhs
+    single-load-case solves (interface PCG bitwise per iteration count, full solve to rounding)."""
+    _cuda()
+    from paper_2308_11371_amd import ifeti
+    tr = np.array([[1.0, 0.0], [0.3, -0.8], [-0.5, 0.5]])
+    prob = latticegen.tiny(2, (4, 3), 3, n_principal=3, tractions=tr)
+    ctx = ifeti.setup(prob)
+    s = ctx.sizes
+    rng = np.random.default_rng(70)
+    R = rng.standard_normal((3, s.L))
+    R[2] *= 1e-3                                   # a load case that converges at a different pace
+    lam3, its3, rel3, st = ctx.solve_interface(dev(R.ravel()), nrhs=3, tol=1e-11)
+    for r in range(3):
+        lam1, its1, rel1, _ = ctx.solve_interface(dev(R[r]), nrhs=1, tol=1e-11)
+        assert its1[0] == its3[r]
+        assert rel(host(lam3)[r * s.L:(r + 1) * s.L], host(lam1)) < 1e-12
+    f, d = ctx.get_rhs()
+    u3, l3, info3 = ctx.solve(f, d, nrhs=3, tol=1e-11, inner_tol=1e-12)
+    for r in range(3):
+        u1, l1, info1 = ctx.solve(f[r * s.nU:(r + 1) * s.nU].contiguous(), d[r * s.L:(r + 1) * s.L].contiguous(),
+                                  tol=1e-11, inner_tol=1e-12)
+        assert info1["outer_its"][0] == info3["outer_its"][r]
+        assert rel(host(u3)[r * s.nU:(r + 1) * s.nU], host(u1)) < 1e-10
+    ctx.close()
