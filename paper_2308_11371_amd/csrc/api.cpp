@@ -152,6 +152,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
             "precision must be IFETI_FP64, IFETI_FP32_LOCAL or IFETI_BF16_LOCAL");
         REQ(opt->pcg_check_every >= 1, "pcg_check_every must be >= 1");
         REQ(opt->fgmres_restart >= 1, "fgmres_restart must be >= 1");
+        REQ(opt->pcg_maxit >= 1, "pcg_maxit must be >= 1");
+        c->opt.pcg_maxit = opt->pcg_maxit;
         c->opt.precision = opt->precision;
         c->opt.pcg_check_every = opt->pcg_check_every;
         c->opt.fgmres_restart = opt->fgmres_restart;

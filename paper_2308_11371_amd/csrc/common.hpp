@@ -96,6 +96,7 @@ struct Options {
     int precision = IFETI_FP64;
     int pcg_check_every = 4;
     int fgmres_restart = 60;
+    int pcg_maxit = 1000;
     int timing = 0;
     std::string timing_filter;  // empty: time every kernel family; else only this one
 };
@@ -265,10 +266,11 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs);
 void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs);
 void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs);
 int reduce_blocks(long long n);
+// V_i = Vp[i] when a device pointer table is given, else V + i*vstride
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
-              int nrhs, double *out_dev);
+              int nrhs, double *out_dev, const double *const *Vp = nullptr);
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
-               long long n, long long rs, int nrhs);
+               long long n, long long rs, int nrhs, const double *const *Vp = nullptr);
 void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs);
 
 // solver.hip

@@ -417,7 +417,8 @@ __device__ inline double block_reduce(double v, double *sh) {
 }
 
 // partial[(rhs*nv + i)*nblk + b] = sum over block b's chunk of V_i . w (per rhs)
-__global__ __launch_bounds__(kB) void k_multidot_partial(const double *__restrict__ V, long long vstride, int nv,
+__global__ __launch_bounds__(kB) void k_multidot_partial(const double *__restrict__ V, long long vstride,
+                                                         const double *const *__restrict__ Vp, int nv,
                                                          const double *__restrict__ w, long long n, long long rs,
                                                          int nblk, double *__restrict__ partial) {
     __shared__ double sh[kB];
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(kB) void k_multidot_partial(const double *__restric
     long long i0 = b * chunk, i1 = min(n, i0 + chunk);
     const double *wr = w + rhs * rs;
     for (int i = 0; i < nv; ++i) {
-        const double *vr = V + i * vstride + rhs * rs;
+        const double *vr = (Vp ? Vp[i] : V + i * vstride) + rhs * rs;
         double acc = 0.0;
         for (long long t = i0 + threadIdx.x; t < i1; t += kB) acc += vr[t] * wr[t];
         acc = block_reduce(acc, sh);
@@ -444,7 +445,8 @@ __global__ __launch_bounds__(kB) void k_reduce_partials(const double *__restrict
 }
 
 // w[rhs] = a*w[rhs] + sum_i coef[rhs*nv + i] * V_i[rhs]
-__global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, long long vstride, int nv,
+__global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, long long vstride,
+                                                  const double *const *__restrict__ Vp, int nv,
                                                   const double *__restrict__ coef, double a, double *__restrict__ w,
                                                   long long n, long long rs, int nrhs) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, 
     int rhs = (int)(t / n);
     long long i = t % n;
     double acc = a * w[rhs * rs + i];
-    for (int k = 0; k < nv; ++k) acc += coef[rhs * nv + k] * V[k * vstride + rhs * rs + i];
+    for (int k = 0; k < nv; ++k) acc += coef[rhs * nv + k] * (Vp ? Vp[k] : V + k * vstride)[rhs * rs + i];
     w[rhs * rs + i] = acc;
 }
 
@@ -725,21 +727,21 @@ int reduce_blocks(long long n) { return (int)std::max<long long>(1, std::min<lon
 
 // out_dev[rhs*nv + i] = V_i[rhs] . w[rhs]
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
-              int nrhs, double *out_dev) {
+              int nrhs, double *out_dev, const double *const *Vp) {
     int nblk = reduce_blocks(n);
     size_t need = (size_t)nblk * nv * nrhs;
     c->w_red.ensure(need, c->stream);
     Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 1) * nrhs);
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, nrhs), dim3(kB), 0, c->stream, V, vstride, nv, w, n, rs, nblk,
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, nrhs), dim3(kB), 0, c->stream, V, vstride, Vp, nv, w, n, rs, nblk,
                        c->w_red.p);
     hipLaunchKernelGGL(k_reduce_partials, dim3(nv * nrhs), dim3(kB), 0, c->stream, c->w_red.p, nblk, out_dev);
     IFETI_HIP(hipGetLastError());
 }
 
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
-               long long n, long long rs, int nrhs) {
+               long long n, long long rs, int nrhs, const double *const *Vp) {
     Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 2) * nrhs);
-    hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, nv, coef_dev, a, w,
+    hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, Vp, nv, coef_dev, a, w,
                        n, rs, nrhs);
     IFETI_HIP(hipGetLastError());
 }

@@ -9,6 +9,7 @@
 // only polls the convergence flags every `pcg_check_every` iterations.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -343,16 +344,29 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     const long long nU = c->nU, L = c->L, ns = nU + L;
     const int m = std::max(1, std::min(maxit, c->opt.fgmres_restart));
     hipStream_t s = c->stream;
-    DevBuf<double> V, Z, w, coef, tu, tL, tL2, tu2, hdev;
-    V.alloc((size_t)(m + 1) * ns * nrhs);
-    Z.alloc((size_t)m * ns * nrhs);
+    // Krylov blocks are allocated as the iteration needs them (memory ~ iterations used x load cases)
+    std::vector<std::unique_ptr<DevBuf<double>>> Vb, Zb;
+    std::vector<const double *> hVp, hZp;
+    DevBuf<const double *> dVp, dZp;
+    dVp.alloc(m + 1);
+    dZp.alloc(m + 1);
+    auto new_block = [&](std::vector<std::unique_ptr<DevBuf<double>>> &blocks, std::vector<const double *> &hp,
+                         DevBuf<const double *> &dp) {
+        blocks.emplace_back(new DevBuf<double>());
+        blocks.back()->alloc((size_t)ns * nrhs);
+        hp.push_back(blocks.back()->p);
+        IFETI_HIP(hipMemcpyAsync(dp.p, hp.data(), hp.size() * sizeof(double *), hipMemcpyHostToDevice, s));
+        IFETI_HIP(hipStreamSynchronize(s));
+        return blocks.back()->p;
+    };
+    DevBuf<double> w, coef, tu, tL, tL2, tu2, hdev;
     w.alloc((size_t)ns * nrhs);
     hdev.alloc((size_t)(m + 1) * nrhs + 16);
     coef.alloc((size_t)(m + 1) * nrhs + 16);
-    const long long vs = ns * nrhs;  // stride between basis blocks
+    double *V0 = new_block(Vb, hVp, dVp);
     // b = (f, d) packed into V_0 (unnormalised)
-    hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, V.p, nrhs);
-    multidot(c, V.p, 0, 1, V.p, ns, ns, nrhs, hdev.p);
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, V0, nrhs);
+    multidot(c, V0, 0, 1, V0, ns, ns, nrhs, hdev.p);
     std::vector<double> bn(nrhs);
     IFETI_HIP(hipMemcpyAsync(bn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     IFETI_HIP(hipStreamSynchronize(s));
@@ -362,7 +376,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
     }
     IFETI_HIP(hipMemcpyAsync(coef.p, inv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-    scale_copy(c, V.p, ns, ns, coef.p, V.p, nrhs);
+    scale_copy(c, V0, ns, ns, coef.p, V0, nrhs);
     // per-load-case Hessenberg and Givens data on the host
     std::vector<std::vector<double>> H(nrhs, std::vector<double>((size_t)(m + 1) * m, 0.0));
     std::vector<std::vector<double>> cs(nrhs, std::vector<double>(m)), sn(nrhs, std::vector<double>(m));
@@ -380,8 +394,9 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         bool all = true;
         for (int r = 0; r < nrhs; ++r) all = all && done[r];
         if (all) break;
-        double *Vj = V.p + (size_t)j * vs, *Zj = Z.p + (size_t)j * vs;
-        int st = apply_prec(c, Vj, Zj, nrhs, inner_tol, 1000, inner, tu, tL, tL2, tu2);
+        double *Vj = Vb[j]->p;
+        double *Zj = new_block(Zb, hZp, dZp);
+        int st = apply_prec(c, Vj, Zj, nrhs, inner_tol, c->opt.pcg_maxit, inner, tu, tL, tL2, tu2);
         if (st != IFETI_OK) {
             status = st;
             break;
@@ -389,7 +404,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         apply_A(c, Zj, w.p, nrhs);
         // classical Gram-Schmidt, twice
         for (int pass = 0; pass < 2; ++pass) {
-            multidot(c, V.p, vs, j + 1, w.p, ns, ns, nrhs, hdev.p);
+            multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hdev.p, dVp.p);
             std::vector<double> &hh = pass == 0 ? h1 : h2;
             IFETI_HIP(hipMemcpyAsync(hh.data(), hdev.p, (size_t)(j + 1) * nrhs * sizeof(double),
                                      hipMemcpyDeviceToHost, s));
@@ -397,7 +412,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
             std::vector<double> neg((size_t)(j + 1) * nrhs);
             for (size_t t = 0; t < neg.size(); ++t) neg[t] = -hh[t];
             IFETI_HIP(hipMemcpyAsync(coef.p, neg.data(), neg.size() * sizeof(double), hipMemcpyHostToDevice, s));
-            multiaxpy(c, V.p, vs, j + 1, coef.p, 1.0, w.p, ns, ns, nrhs);
+            multiaxpy(c, nullptr, 0, j + 1, coef.p, 1.0, w.p, ns, ns, nrhs, dVp.p);
         }
         multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hdev.p);
         IFETI_HIP(hipMemcpyAsync(hn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -427,7 +442,8 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
             if (std::fabs(g[r][j + 1]) <= tol * beta[r] || hj1 == 0.0) done[r] = 1;
         }
         IFETI_HIP(hipMemcpyAsync(coef.p, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        scale_copy(c, w.p, ns, ns, coef.p, V.p + (size_t)(j + 1) * vs, nrhs);
+        double *Vn = new_block(Vb, hVp, dVp);
+        scale_copy(c, w.p, ns, ns, coef.p, Vn, nrhs);
     }
     // x = sum_i y_i Z_i per load case
     int kmax = 0;
@@ -450,7 +466,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     hipLaunchKernelGGL(k_fill, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, ns * nrhs, 0.0);
     if (kmax > 0) {
         IFETI_HIP(hipMemcpyAsync(coef.p, yc.data(), yc.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        multiaxpy(c, Z.p, vs, kmax, coef.p, 1.0, xs.p, ns, ns, nrhs);
+        multiaxpy(c, nullptr, 0, kmax, coef.p, 1.0, xs.p, ns, ns, nrhs, dZp.p);
     }
     hipLaunchKernelGGL(k_unpack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, nU, L, u, lam, nrhs);
     // true residual ||b - A x|| / ||b||

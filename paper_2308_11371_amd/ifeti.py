@@ -43,7 +43,7 @@ class Sizes(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int),
-                ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32)]
+                ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -172,8 +172,9 @@ class Context:
         _check(self.lib.ifeti_get_sizes(self.h, ctypes.byref(s)))
         return s
 
-    def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, timing=0, timing_filter=""):
-        o = Options(precision, pcg_check_every, fgmres_restart, timing, timing_filter.encode()[:31])
+    def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
+                    timing_filter=""):
+        o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31])
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
 
     def stats(self) -> dict:
