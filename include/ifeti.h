@@ -193,6 +193,24 @@ int ifeti_solve(ifeti_ctx *ctx, const double *f, const double *d, double *u, dou
                 double tol, int maxit, double inner_tol, int *outer_iters, int *inner_iters_total,
                 double *relres);
 
+/* Differentiation form.  Compliance c = f^T u and its gradient with respect
+ * to every cell's strut width, dc/dw_s = -u_s^T (dK^(s)/dw_s) u_s (the system
+ * (16) is self-adjoint and f does not depend on the widths), evaluated by
+ * quadrature of the width derivative of eq. (52).  Meaningful with a smoothed
+ * strut indicator (smooth_eps > 0); zero for the sharp one.
+ *   f, u        dev nU x nrhs (u: a converged solution of ifeti_solve)
+ *   grad        dev N x nrhs (rhs-major)
+ *   compliance  host nrhs, nullable. */
+int ifeti_compliance_grad(ifeti_ctx *ctx, const double *f, const double *u, double *grad,
+                          double *compliance, int nrhs);
+
+/* Replace the strut widths (dev N) and re-assemble the cells (snapshots and
+ * stiffness) while keeping the reduced basis, coefficients and coarse inverse
+ * of the last ifeti_build_reduced_basis: the preconditioner is then that of the
+ * previous widths, the outer iteration uses the new operator, so ifeti_solve
+ * converges to the solution for the new widths.  EINVAL on a non-positive width. */
+int ifeti_update_widths(ifeti_ctx *ctx, const double *widths);
+
 #ifdef __cplusplus
 }
 #endif

@@ -336,4 +336,34 @@ int ifeti_solve(ifeti_ctx *c, const double *f, const double *d, double *u, doubl
     });
 }
 
+int ifeti_compliance_grad(ifeti_ctx *c, const double *f, const double *u, double *grad, double *compliance,
+                          int nrhs) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        REQ(f && u && grad, "bad pointers");
+        REQ(nrhs >= 1, "nrhs must be >= 1");
+        ensure_work(c, nrhs);
+        compliance_grad(c, f, u, grad, compliance, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_update_widths(ifeti_ctx *c, const double *widths) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        REQ(widths, "bad pointer");
+        const int N = c->N;
+        std::vector<double> hw(N);
+        IFETI_HIP(hipMemcpyAsync(hw.data(), widths, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        for (double w : hw) REQ(std::isfinite(w) && w > 0.0, "strut widths must be positive and finite");
+        IFETI_HIP(hipMemcpyAsync(c->widths.p, widths, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        launch_pulled_back(c);
+        launch_stiffness(c);
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        c->snap_valid = true;
+        return IFETI_OK;
+    });
+}
+
 }  // extern "C"

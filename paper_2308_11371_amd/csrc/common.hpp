@@ -273,6 +273,9 @@ void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const d
                long long n, long long rs, int nrhs, const double *const *Vp = nullptr);
 void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs);
 
+// gradient.hip
+void compliance_grad(ifeti_ctx *c, const double *f, const double *u, double *grad, double *comp_host, int nrhs);
+
 // solver.hip
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres);

@@ -24,7 +24,7 @@ EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_size
             "ifeti_build_cells", "ifeti_get_rhs", "ifeti_build_reduced_basis", "ifeti_get_coefficients",
             "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_U", "ifeti_apply_Ut", "ifeti_apply_Kinv_rom",
             "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
-            "ifeti_get_stats", "ifeti_reset_stats")
+            "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths")
 
 
 class LatticeDesc(ctypes.Structure):
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_solve": [P, P, P, P, P, I, D, I, D, P, P, P],
         "ifeti_get_stats": [P, ctypes.POINTER(Stats)],
         "ifeti_reset_stats": [P],
+        "ifeti_compliance_grad": [P, P, P, P, P, I],
+        "ifeti_update_widths": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -284,6 +286,51 @@ class Context:
         if check:
             _check(st)
         return u, lam, dict(outer_its=outer, inner_its=inner, relres=rel, status=st)
+
+
+def _compliance_grad(self, f, u, nrhs=1):
+    """(compliance per load case as numpy, gradient tensor N x nrhs rhs-major)."""
+    import torch
+    g = torch.empty(self.sizes.N * nrhs, dtype=torch.float64, device=u.device)
+    c = np.zeros(nrhs)
+    _check(self.lib.ifeti_compliance_grad(self.h, _ptr(f), _ptr(u), _ptr(g), c.ctypes.data_as(ctypes.c_void_p),
+                                          int(nrhs)))
+    return c, g
+
+
+def _update_widths(self, widths):
+    _check(self.lib.ifeti_update_widths(self.h, _ptr(widths)))
+
+
+Context.compliance_grad = _compliance_grad
+Context.update_widths = _update_widths
+
+
+def _autograd():
+    import torch
+
+    class ComplianceFn(torch.autograd.Function):
+        """c(w) = f^T u(w); backward returns -u_s^T dK_s/dw_s u_s from the library (self-adjoint solve)."""
+
+        @staticmethod
+        def forward(fctx, widths, lattice, f, d, tol, inner_tol):
+            lattice.update_widths(widths.detach().contiguous())
+            u, lam, info = lattice.solve(f, d, tol=tol, inner_tol=inner_tol)
+            c, g = lattice.compliance_grad(f, u)
+            fctx.save_for_backward(g)
+            return torch.tensor(c[0], dtype=torch.float64, device=widths.device)
+
+        @staticmethod
+        def backward(fctx, gout):
+            (g,) = fctx.saved_tensors
+            return gout * g, None, None, None, None, None
+
+    return ComplianceFn
+
+
+def compliance(widths, lattice, f, d, tol=1e-10, inner_tol=1e-11):
+    """Differentiable compliance of the lattice for strut widths `widths` (torch, on the GPU)."""
+    return _autograd().apply(widths, lattice, f, d, tol, inner_tol)
 
 
 def setup(problem, n_principal=None, principal_in=None, stream=None) -> Context:
