@@ -148,7 +148,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> ctrl;      // [s][a][dim]
     ifeti::DevBuf<double> widths;    // [s]
     ifeti::DevBuf<double> snap;      // [s][E][q][dim^4] pulled-back tensor (greedy snapshots)
-    ifeti::DevBuf<double> Kst;       // [s][a][o][dim][dim] stencil stiffness values
+    ifeti::DevBuf<double> Kst;       // [s][o][i][k][a] stencil stiffness values (offset o, comps i,k)
     ifeti::DevBuf<double> f_cells;   // [rhs][s][n_dof]
     ifeti::DevBuf<double> f_vec;     // [rhs][nU]
     ifeti::DevBuf<double> d_vec;     // [rhs][L]
@@ -196,7 +196,7 @@ struct ifeti_ctx {
     std::vector<hipEvent_t> event_pool;
 
     // ---- work buffers
-    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_x, w_tmpL, w_tmpU;
+    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_x, w_tmpL, w_tmpU;
     ifeti::DevBuf<double> w_red;        // reduction partials
     ifeti::DevBuf<double> w_scal;       // PCG scalars
     ifeti::DevBuf<int> w_iflag;

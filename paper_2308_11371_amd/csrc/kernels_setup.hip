@@ -200,11 +200,12 @@ __global__ __launch_bounds__(kBlock) void k_stiffness(const double *__restrict__
             if (j == D) break;
         }
     }
-    double *out = Kst + (size_t)t * D * D;
+    // layout [s][o][i][k][a]: consecutive control points adjacent (coalesced cell mat-vecs)
+    double *out = Kst + (size_t)s * n_off * D * D * n_ctrl;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int k = 0; k < D; ++k) out[i * D + k] = Kb[i][k];
+        for (int k = 0; k < D; ++k) out[(((size_t)o * D + i) * D + k) * n_ctrl + a] = Kb[i][k];
 }
 
 // -------------------------------------------------------------- greedy sweeps

@@ -125,21 +125,90 @@ __global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S
     if (lane == 0) y[wave] = scale * acc;
 }
 
-// ------------------------------------------------------------------ reduced local solve (46), Gram part
-// One workgroup per column c (cell s, load case rhs).  R_c holds the K
-// reduced-basis vectors K_rr^(sigma_k)^-1 v (column-major, n_r x K).  The Gram
-// matrix G = R^T K_rr^(s) R uses the cell's own stencil values; G c = R^T v is
-// solved by Cholesky (symmetric pseudo-inverse with a 1e-13 relative cut if a
-// pivot fails) and x = R c is written.
-constexpr int kRomChunk = 64;
-constexpr int kMaxK = 40;
-constexpr int kHGroups = kB / kRomChunk;                       // threads per row of a chunk
-constexpr int kHMax = (kMaxK + kHGroups - 1) / kHGroups;       // columns per thread
-constexpr int kGMax = (kMaxK * kMaxK + kMaxK + kB - 1) / kB;   // Gram entries per thread
+// ------------------------------------------------------------------ reduced local solve (46)
+// Column c = rhs*N + s.  R_c holds the K reduced-basis vectors
+// K_rr^(sigma_k)^-1 v (n_r x K, vector k contiguous).  The Gram matrix
+// G = R^T K_rr^(s) R uses the cell's own stencil values; G c = R^T v is solved
+// by Cholesky (symmetric pseudo-inverse with a 1e-13 relative cut if a pivot
+// fails) and x = R c is written.
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Small dense solve by thread 0: x = A^-1 b for symmetric A (K x K, row-major in
-// shared memory).  Cholesky; if a pivot is not positive, a cyclic Jacobi
-// eigen-decomposition gives the pseudo-inverse with a 1e-13 relative cut.
+// (46b) step 1: H_c = K_rr^(s) R_c for a chunk of KCOL reduced-basis vectors.
+// One workgroup per column c; the chunk of R (n_r x KCOL) is staged in LDS
+// (row-major, KCOL contiguous); one thread per (control point a) accumulates
+// the d x KCOL block of H for the rows of a from the cell's stencil values
+// (layout [o][i][k][a], coalesced over a).  H is written as [k][r].
+constexpr int kRomHB = 512;
+
+template <int D, int KCOL>
+__global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, const double *__restrict__ Kst,
+                                              const int *__restrict__ r_of_dof, int N, int K, int k0, int n_r,
+                                              int nc, int n_ctrl, int n_off, int p, double *__restrict__ H) {
+    extern __shared__ double Rl[];  // [n_r][KCOL]
+    const int col = blockIdx.x, s = col % N, tid = threadIdx.x;
+    const double *Rc = R + (size_t)col * K * n_r;
+    const int kc = min(KCOL, K - k0), nt = blockDim.x;
+    for (int e = tid; e < n_r * KCOL; e += nt) {
+        const int kk = e / n_r, r = e % n_r;
+        Rl[r * KCOL + kk] = kk < kc ? Rc[(size_t)(k0 + kk) * n_r + r] : 0.0;
+    }
+    __syncthreads();
+    const int w = 2 * p + 1;
+    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
+    double *Hc = H + (size_t)col * K * n_r;
+    for (int a = tid; a < n_ctrl; a += nt) {
+        int ma[D];
+        int ta = a;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            ma[j] = ta % nc;
+            ta /= nc;
+        }
+        double h[D][KCOL];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int q = 0; q < KCOL; ++q) h[i][q] = 0.0;
+        for (int o = 0; o < n_off; ++o) {
+            int to = o, b = 0;
+            bool ok = true;
+            int mb[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                mb[j] = ma[j] + (to % w) - p;
+                to /= w;
+                if (mb[j] < 0 || mb[j] >= nc) ok = false;
+            }
+            if (!ok) continue;
+#pragma unroll
+            for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int rk = r_of_dof[b * D + k];
+                if (rk < 0) continue;
+                const double *rrow = Rl + rk * KCOL;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const double v = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
+#pragma unroll
+                    for (int q = 0; q < KCOL; ++q) h[i][q] += v * rrow[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int ri = r_of_dof[a * D + i];
+            if (ri < 0) continue;
+#pragma unroll
+            for (int q = 0; q < KCOL; ++q)
+                if (q < kc) Hc[(size_t)(k0 + q) * n_r + ri] = h[i][q];
+        }
+    }
+}
+
+// Small dense solve by one lane: x = A^-1 b for symmetric A (K x K, row-major).
+// Cholesky; if a pivot is not positive, a cyclic Jacobi eigen-decomposition
+// gives the pseudo-inverse with a 1e-13 relative cut.
 __device__ void small_sym_solve(double *A, double *Lm, double *V, const double *b, double *x, int K) {
     bool ok = true;
     for (int j = 0; j < K && ok; ++j) {
@@ -218,117 +287,79 @@ __device__ void small_sym_solve(double *A, double *Lm, double *V, const double *
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(kB) void k_rom_local(const double *__restrict__ vR, long long v_rs,
-                                                  const double *__restrict__ R, const double *__restrict__ Kst,
-                                                  const int *__restrict__ r_of_dof,
-                                                  const int *__restrict__ idx_r, int N, int K, int n_r, int nc,
-                                                  int n_ctrl, int n_off, int p, double *__restrict__ xR,
-                                                  long long x_rs) {
-    constexpr int LDR = kRomChunk + 1;
-    __shared__ double sm[2 * kMaxK * LDR];       // R and H chunks; reused by the small solve
-    __shared__ double G[kMaxK * kMaxK + kMaxK];  // Gram matrix, then R^T v
-    __shared__ double vs[kRomChunk];
-    __shared__ double cvec[kMaxK];
-    double *Rs = sm, *Hs = sm + kMaxK * LDR;
-    const int col = blockIdx.x;
+constexpr int kMaxK = 40;
+
+// (46b) step 2, one wave64 per column c: [G | g] = R^T [H | v] on the FP64 MFMA
+// (A fragment R^T: lane l -> basis vector l%16, rows 4t + l/16; B fragment
+// [H | v]: rows 4t + l/16, column l%16), then G c = g by lane 0 and x = R c.
+// G is symmetric up to rounding; its upper triangle is mirrored.  KB =
+// 16-blocks of the padded (K + 1) dimension, WPB = waves per workgroup; each
+// wave owns 3K^2 + 2K doubles of dynamic LDS (G, Cholesky factor, eigenvector
+// scratch, right-hand side, coefficients).
+template <int KB, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_rom_gram(const double *__restrict__ vR, long long v_rs,
+                                                       const double *__restrict__ R, const double *__restrict__ H,
+                                                       int N, int ncols, int K, int n_r, double *__restrict__ xR,
+                                                       long long x_rs) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * WPB + wave;
+    const bool active = col < ncols;
     const int rhs = col / N, s = col % N;
-    const int tid = threadIdx.x;
-    const double *v = vR + rhs * v_rs + (size_t)s * n_r;
+    const int lr = lane & 15, lk = lane >> 4;
     const double *Rc = R + (size_t)col * K * n_r;
-    const int KK = K * K, npair = KK + K;
-    double gacc[kGMax];
+    const double *Hc = H + (size_t)col * K * n_r;
+    double *A = lds + (size_t)wave * (3 * K * K + 2 * K);
+    double *Lm = A + K * K, *Vm = Lm + K * K, *rhsb = Vm + K * K, *cv = rhsb + K;
+    if (active) {
+        const double *v = vR + rhs * v_rs + (size_t)s * n_r;
+        v4d acc[KB][KB];
 #pragma unroll
-    for (int u = 0; u < kGMax; ++u) gacc[u] = 0.0;
-    const int w = 2 * p + 1;
-    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
-    for (int r0 = 0; r0 < n_r; r0 += kRomChunk) {
-        const int rl = tid % kRomChunk, kg = tid / kRomChunk;
-        const int row = r0 + rl;
-        double h[kHMax];
+        for (int a = 0; a < KB; ++a)
 #pragma unroll
-        for (int u = 0; u < kHMax; ++u) h[u] = 0.0;
-        if (row < n_r) {
-            const int dof = idx_r[row];
-            const int a = dof / D, i = dof % D;
-            int ma[D];
-            int ta = a;
+            for (int b = 0; b < KB; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int nt4 = (n_r + 3) / 4;
+        for (int t = 0; t < nt4; ++t) {  // uniform trip count: the MFMA needs all 64 lanes
+            const int r = 4 * t + lk;
+            const bool rin = r < n_r;
+            double af[KB], bf[KB];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                ma[j] = ta % nc;
-                ta /= nc;
+            for (int a = 0; a < KB; ++a) {
+                const int k1 = 16 * a + lr;
+                af[a] = (rin && k1 < K) ? Rc[(size_t)k1 * n_r + r] : 0.0;
+                bf[a] = !rin ? 0.0 : (k1 < K ? Hc[(size_t)k1 * n_r + r] : (k1 == K ? v[r] : 0.0));
             }
-            for (int o = 0; o < n_off; ++o) {
-                int to = o, b = 0;
-                bool ok = true;
-                int mb[D];
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    mb[j] = ma[j] + (to % w) - p;
-                    to /= w;
-                    if (mb[j] < 0 || mb[j] >= nc) ok = false;
-                }
-                if (!ok) continue;
+            for (int a = 0; a < KB; ++a)
 #pragma unroll
-                for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+                for (int b = 0; b < KB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const int rc = r_of_dof[b * D + k];
-                    if (rc < 0) continue;
-                    const double val = Ks[(((size_t)a * n_off + o) * D + i) * D + k];
+        for (int a = 0; a < KB; ++a)
 #pragma unroll
-                    for (int u = 0; u < kHMax; ++u) {
-                        const int kk = kg + u * kHGroups;
-                        if (kk < K) h[u] += val * Rc[(size_t)kk * n_r + rc];
+            for (int b = 0; b < KB; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * a + 4 * i + lk, cc = 16 * b + lr;
+                    if (row >= K) continue;
+                    if (cc == K) rhsb[row] = acc[a][b][i];
+                    else if (row <= cc && cc < K) {
+                        A[row * K + cc] = acc[a][b][i];
+                        A[cc * K + row] = acc[a][b][i];
                     }
                 }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kHMax; ++u) {
-            const int kk = kg + u * kHGroups;
-            if (kk < K) {
-                Hs[kk * LDR + rl] = row < n_r ? h[u] : 0.0;
-                Rs[kk * LDR + rl] = row < n_r ? Rc[(size_t)kk * n_r + row] : 0.0;
-            }
-        }
-        if (kg == 0) vs[rl] = row < n_r ? v[row] : 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kGMax; ++u) {
-            const int pr = tid + u * kB;
-            if (pr < npair) {
-                double sacc = 0.0;
-                if (pr < KK) {
-                    const int k1 = pr / K, k2 = pr % K;
-                    for (int t = 0; t < kRomChunk; ++t) sacc += Rs[k1 * LDR + t] * Hs[k2 * LDR + t];
-                } else {
-                    const int k1 = pr - KK;
-                    for (int t = 0; t < kRomChunk; ++t) sacc += Rs[k1 * LDR + t] * vs[t];
-                }
-                gacc[u] += sacc;
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < kGMax; ++u) {
-        const int pr = tid + u * kB;
-        if (pr < npair) G[pr] = gacc[u];
     }
     __syncthreads();
-    if (tid == 0) {
-        double *A = sm, *Lm = sm + KK, *V = sm + 2 * KK;
-        for (int i = 0; i < K; ++i)
-            for (int j = 0; j < K; ++j) A[i * K + j] = 0.5 * (G[i * K + j] + G[j * K + i]);
-        small_sym_solve(A, Lm, V, G + KK, cvec, K);
-    }
+    if (active && lane == 0) small_sym_solve(A, Lm, Vm, rhsb, cv, K);
     __syncthreads();
-    double *x = xR + rhs * x_rs + (size_t)s * n_r;
-    for (int row = tid; row < n_r; row += kB) {
-        double t = 0.0;
-        for (int k = 0; k < K; ++k) t += Rc[(size_t)k * n_r + row] * cvec[k];
-        x[row] = t;
+    if (active) {
+        double *x = xR + rhs * x_rs + (size_t)s * n_r;
+        for (int r = lane; r < n_r; r += 64) {
+            double t = 0.0;
+            for (int k = 0; k < K; ++k) t += Rc[(size_t)k * n_r + r] * cv[k];
+            x[r] = t;
+        }
     }
 }
 
@@ -359,8 +390,9 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
     const int w = 2 * p + 1;
     const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
     double *yr = y + rhs * y_rs + (size_t)s * n_r;
-    for (int row = tid; row < n_dof; row += kB) {
-        int a = row / D, i = row % D;
+    for (int t = tid; t < n_dof; t += kB) {
+        const int i = t / n_ctrl, a = t % n_ctrl;
+        const int row = a * D + i;
         int ma[D];
         int ta = a;
         for (int j = 0; j < D; ++j) {
@@ -379,17 +411,16 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
             }
             if (!ok) continue;
             for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
-            const double *blk = Ks + ((size_t)a * n_off + o) * D * D + i * D;
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc += blk[k] * uloc[b * D + k];
+            for (int k = 0; k < D; ++k) acc += Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a] * uloc[b * D + k];
         }
         int rp = r_of_dof[row];
         if (rp >= 0) {
             if (rp >= n_i) {  // dual dof: add B_d^T lam
                 int j = rp - n_i;
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    int code = gl[((size_t)s * n_d + j) * 2 + t];
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    int code = gl[((size_t)s * n_d + j) * 2 + t2];
                     if (code == 0) continue;
                     double lv = lam[(code > 0 ? code : -code) - 1];
                     acc += code > 0 ? lv : -lv;
@@ -505,7 +536,10 @@ void ensure_work(ifeti_ctx *c, int nrhs) {
     c->w_yp.ensure(cols * c->n_p, s);
     c->w_zP.ensure((size_t)std::max(c->nP, 1) * nrhs, s);
     c->w_yP.ensure((size_t)std::max(c->nP, 1) * nrhs, s);
-    if (c->K > 0) c->w_R.ensure(cols * c->K * c->n_r, s);
+    if (c->K > 0) {
+        c->w_R.ensure(cols * c->K * c->n_r, s);
+        c->w_H.ensure(cols * c->K * c->n_r, s);
+    }
     c->w_red.ensure((size_t)256 * 64 * nrhs + 1024, s);
 }
 
@@ -661,18 +695,61 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     GemmGroup g;
     g.A = c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
     gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, "rom_R_gemm");
-    // (46b) per-cell Gram system and combination
+    // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
     const RefTables &R = c->ref;
-    const double colsd = (double)N * nrhs;
-    Prof prof(c, "rom_local", colsd * (2.0 * K * c->nnz_rr + 2.0 * K * K * nr + 4.0 * K * nr),
-              colsd * 8.0 * ((K + 2.0) * nr + (double)c->nnz_rr));
-    if (c->dim == 2)
-        hipLaunchKernelGGL(k_rom_local<2>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->Kst.p,
-                           c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR, x_rs);
-    else
-        hipLaunchKernelGGL(k_rom_local<3>, dim3(N * nrhs), dim3(kB), 0, c->stream, vR, v_rs, c->w_R.p, c->Kst.p,
-                           c->r_of_dof.p, c->g_idx_r.p, N, K, nr, R.nc, R.n_ctrl, R.n_off, R.p, xR, x_rs);
-    IFETI_HIP(hipGetLastError());
+    const int cols = N * nrhs;
+    const double colsd = (double)cols;
+    {
+        int kcol = 4;
+        for (int cand : {8, 12, 16})
+            if ((size_t)nr * cand * 8 <= 100 * 1024 && kcol < K) kcol = cand;
+        const int nthr = std::min(kRomHB, (R.n_ctrl + 63) / 64 * 64);
+        const size_t lds = (size_t)nr * kcol * sizeof(double);
+        IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "cell too large for the LDS-staged reduced local solve");
+        const double chunks = (double)((K + kcol - 1) / kcol);
+        Prof prof(c, "rom_H", colsd * 2.0 * K * c->nnz_rr,
+                  colsd * 8.0 * (2.0 * K * nr + chunks * (double)R.n_ctrl * R.n_off * c->dim * c->dim));
+        for (int k0 = 0; k0 < K; k0 += kcol) {
+#define IFETI_ROM_H(DD, KC)                                                                                       \
+    do {                                                                                                          \
+    (void)hipFuncSetAttribute((const void *)k_rom_H<DD, KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipGetLastError();                                                                                      \
+    hipLaunchKernelGGL((k_rom_H<DD, KC>), dim3(cols), dim3(nthr), lds, c->stream, c->w_R.p, c->Kst.p,             \
+                       c->r_of_dof.p, N, K, k0, nr, R.nc, R.n_ctrl, R.n_off, R.p, c->w_H.p);               \
+    } while (0)
+            if (c->dim == 2) {
+                if (kcol == 4) IFETI_ROM_H(2, 4);
+                else if (kcol == 8) IFETI_ROM_H(2, 8);
+                else if (kcol == 12) IFETI_ROM_H(2, 12);
+                else IFETI_ROM_H(2, 16);
+            } else {
+                if (kcol == 4) IFETI_ROM_H(3, 4);
+                else if (kcol == 8) IFETI_ROM_H(3, 8);
+                else if (kcol == 12) IFETI_ROM_H(3, 12);
+                else IFETI_ROM_H(3, 16);
+            }
+#undef IFETI_ROM_H
+            IFETI_HIP(hipGetLastError());
+        }
+    }
+    {
+        Prof prof(c, "rom_gram", colsd * (2.0 * (K + 1.0) * K * nr + 2.0 * K * nr),
+                  colsd * 8.0 * (3.0 * K * nr + 2.0 * nr));
+        const int kb = (K + 1 + 15) / 16;
+        const int wpb = kb == 3 ? 2 : 4;
+        const size_t lds = (size_t)wpb * (3 * K * K + 2 * K) * sizeof(double);
+        const dim3 grid((cols + wpb - 1) / wpb), block(64 * wpb);
+        if (kb == 1)
+            hipLaunchKernelGGL((k_rom_gram<1, 4>), grid, block, lds, c->stream, vR, v_rs, c->w_R.p, c->w_H.p, N, cols,
+                               K, nr, xR, x_rs);
+        else if (kb == 2)
+            hipLaunchKernelGGL((k_rom_gram<2, 4>), grid, block, lds, c->stream, vR, v_rs, c->w_R.p, c->w_H.p, N, cols,
+                               K, nr, xR, x_rs);
+        else
+            hipLaunchKernelGGL((k_rom_gram<3, 2>), grid, block, lds, c->stream, vR, v_rs, c->w_R.p, c->w_H.p, N, cols,
+                               K, nr, xR, x_rs);
+        IFETI_HIP(hipGetLastError());
+    }
 }
 
 // ------------------------------------------------------------------ K̊^-ROM (45), Algorithm 2

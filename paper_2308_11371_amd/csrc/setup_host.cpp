@@ -649,9 +649,10 @@ struct StencilView {
                     b = b * nc + bj;
                 }
                 if (!ok) continue;
-                const double *blk = Kst + ((size_t)a * R.n_off + o) * d * d;
                 for (int i = 0; i < d; ++i)
-                    for (int k = 0; k < d; ++k) K[(size_t)(a * d + i) * R.n_dof + b * d + k] = blk[i * d + k];
+                    for (int k = 0; k < d; ++k)
+                        K[(size_t)(a * d + i) * R.n_dof + b * d + k] =
+                            Kst[(((size_t)o * d + i) * d + k) * R.n_ctrl + a];
             }
         }
         return K;
