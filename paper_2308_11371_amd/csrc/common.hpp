@@ -90,6 +90,11 @@ struct GemmGroup {
     int Kd = 0, ldx = 0, K = 1;
     long long xbs = 0;          // stride between right-hand sides (0: ncells*ldx)
     double scale = 1.0;
+    // optional fused B_d^T: X is then a multiplier vector (load case stride xbs) and
+    // column c = cell s takes entry j from the signed rows gcodes[(s*Kd + j)*2 + u],
+    // each multiplied by gw[row] when gw is set (the scaled jump operator)
+    const int *gcodes = nullptr;
+    const double *gw = nullptr;
 };
 
 struct Options {
@@ -174,6 +179,11 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
     ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
     ifeti::DevBuf<double> SPPinv;       // [nP][nP]
+    // lower-triangle 64x64 tiles of SPPinv, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
+    ifeti::DevBuf<double> SPPt;
+    ifeti::DevBuf<int> sym_tiles;       // [tile] -> (I, J)
+    ifeti::DevBuf<double> w_symP;       // [tile][rhs][row partial 64 | column partial 64]
+    int nT = 0;
     bool rom_built = false;
     struct LPCopy {                     // fp32 / bf16 copies of a bank array (precision form)
         const double *src = nullptr;
@@ -181,12 +191,23 @@ struct ifeti_ctx {
         void *f32 = nullptr, *bf16 = nullptr;
     };
     std::vector<LPCopy> lp;
-    ~ifeti_ctx() {
+    struct FragCopy {                   // a bank array in FP64 MFMA-fragment order, per (M, Kd, K) view
+        const double *src = nullptr;
+        int M = 0, Kd = 0, K = 0;
+        double *frag = nullptr;
+    };
+    std::vector<FragCopy> frag;
+    void free_copies() {
         for (auto &cp : lp) {
             if (cp.f32) (void)hipFree(cp.f32);
             if (cp.bf16) (void)hipFree(cp.bf16);
         }
+        lp.clear();
+        for (auto &cp : frag)
+            if (cp.frag) (void)hipFree(cp.frag);
+        frag.clear();
     }
+    ~ifeti_ctx() { free_copies(); }
 
     // ---- statistics
     long long applies[IFETI_OP_COUNT] = {0, 0, 0, 0, 0, 0};
@@ -198,6 +219,8 @@ struct ifeti_ctx {
     // ---- work buffers
     ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_x, w_tmpL, w_tmpU;
     ifeti::DevBuf<double> w_red;        // reduction partials
+    ifeti::DevBuf<double> pcg_r, pcg_z, pcg_p, pcg_q, pcg_st, pcg_pa, pcg_pb, pcg_pc;  // interface PCG state
+    ifeti::DevBuf<int> pcg_ist;
     ifeti::DevBuf<double> w_scal;       // PCG scalars
     ifeti::DevBuf<int> w_iflag;
 };
@@ -252,15 +275,20 @@ void join_side(ifeti_ctx *c);
 void ensure_work(ifeti_ctx *c, int nrhs);
 void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights);
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
-                int nrhs, bool weights);
+                int nrhs, bool weights, const double *dot_w = nullptr, double *dot_part = nullptr);
 void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long long b_rs, double sgn, double *zP,
                         long long z_rs, int nrhs);
 void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs);
 void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
                      double scale);
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs);
-void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs);
-void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs);
+// dot_w / dot_part (optional): the final scatter also writes the per-block partial
+// sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
+void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
+             double *dot_part = nullptr);
+void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
+              double *dot_part = nullptr);
+int dot_blocks(long long n);
 void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs);
 void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs);
 void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs);

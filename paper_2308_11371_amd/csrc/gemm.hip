@@ -357,6 +357,211 @@ __global__ void k_to_lp(const double *__restrict__ x, float *__restrict__ f, __b
     b[t] = (__bf16)v;
 }
 
+// ---------------------------------------------------------------- fragment-ordered FP64 path
+// For operators that stay resident in L2 (the dual/primal blocks of the
+// principal bank), A_k is copied once into MFMA-fragment order: for row tile
+// mt (16 rows) and pair q of 4-deep k-steps, lane l holds rows mt*16 + l%16
+// and inner indices (2q + j)*4 + l/16, j = 0, 1, as one 16-byte pair, so a
+// coalesced 1 KB wave load feeds two MFMAs.
+__global__ void k_to_frag(const double *__restrict__ A, int M, int Kd, int K, int MT, int KT2,
+                          double *__restrict__ F) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)K * MT * KT2 * 128;
+    if (t >= total) return;
+    const int j = (int)(t & 1), lane = (int)((t >> 1) & 63);
+    long long rest = t >> 7;
+    const int q = (int)(rest % KT2);
+    rest /= KT2;
+    const int mt = (int)(rest % MT), k = (int)(rest / MT);
+    const int row = mt * 16 + (lane & 15), inner = (2 * q + j) * 4 + (lane >> 4);
+    F[t] = (row < M && inner < Kd) ? A[(size_t)k * M * Kd + (size_t)row * Kd + inner] : 0.0;
+}
+
+struct GemmArgsFrag {
+    const double *Af[2];
+    const double *X[2];
+    const double *coef[2];
+    const int *gcodes[2];
+    const double *gw[2];
+    int Kd[2], ldx[2], K[2], KT2[2];
+    long long xbs[2];
+    double scale[2];
+    int ngroups;
+    double *Y;
+    long long ybs;
+    int ldy, M, MT, ncols, ncells, accumulate;
+};
+
+constexpr int FKC = 128;      // inner rows of the cell vectors staged per chunk
+constexpr int FXS = FKC + 2;  // LDS row stride (doubles): conflict-free B-fragment reads
+constexpr int kMaxCoefK = 40;
+
+// Workgroup = NW waves sharing one output tile of RT row tiles x CB column
+// blocks (16 x 16 each).  The cell vectors of the tile's 16*CB columns and
+// their coefficients are staged in LDS; the (principal, k-step pair) sequence
+// is dealt round-robin to the NW waves, each streaming its A fragments from L2
+// PF pairs ahead; partial tiles are summed through LDS by a fixed pairwise
+// tree, so every column's result is independent of the launch shape and of
+// the other columns (bitwise reproducible).
+template <int RT, int CB, int PF, int NW>
+__global__ __launch_bounds__(64 * NW) void k_pc64(GemmArgsFrag g) {
+    static_assert((NW & (NW - 1)) == 0, "NW must be a power of two");
+    constexpr int NT = 64 * NW;
+    constexpr int NC = 16 * CB;
+    constexpr int XW = NC * FXS;
+    constexpr int RED = (NW / 2) * RT * CB * 256;
+    constexpr int SX = XW > RED ? XW : RED;
+    __shared__ double Xs[SX];
+    __shared__ double Cs[kMaxCoefK * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mt0 = blockIdx.y * RT, col0 = blockIdx.x * NC;
+    v4d acc[RT][CB];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    bool rtv[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) rtv[rt] = mt0 + rt < g.MT;
+
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const double *__restrict__ Af = g.Af[gi];
+        const double *__restrict__ X = g.X[gi];
+        const double *__restrict__ coef = g.coef[gi];
+        const int *__restrict__ gcodes = g.gcodes[gi];
+        const double *__restrict__ gw = g.gw[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi], KT2 = g.KT2[gi], ldx = g.ldx[gi];
+        const long long xbs = g.xbs[gi];
+        const double scale = g.scale[gi];
+        for (int kk = 0; kk < Kd; kk += FKC) {
+            const int kc = min(FKC, Kd - kk);
+            __syncthreads();  // previous chunk fully consumed
+            for (int e = tid; e < NC * FKC; e += NT) {
+                const int cc = e / FKC, r = e % FKC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols && r < kc) {
+                    const int cell = col % g.ncells;
+                    const long long rhs = col / g.ncells;
+                    if (gcodes) {  // fused (scaled) jump transpose: signed multiplier rows
+                        const double *lam = X + rhs * xbs;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int code = gcodes[((size_t)cell * Kd + kk + r) * 2 + u];
+                            if (code == 0) continue;
+                            const int row = (code > 0 ? code : -code) - 1;
+                            const double x = gw ? lam[row] * gw[row] : lam[row];
+                            v += code > 0 ? x : -x;
+                        }
+                    } else {
+                        v = X[rhs * xbs + (size_t)cell * ldx + kk + r];
+                    }
+                }
+                Xs[cc * FXS + r] = v;
+            }
+            for (int e = tid; e < K * NC; e += NT) {
+                const int k = e / NC, cc = e % NC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
+                Cs[e] = v;
+            }
+            __syncthreads();
+            const int np = (kc + 7) / 8;  // fragment pairs of this chunk
+            const int q0 = kk / 8;
+            const int total = K * np;
+            const int ns = wave < total ? (total - wave + NW - 1) / NW : 0;  // steps s = wave + NW i
+            auto load = [&](int i, double2 (&dst)[RT]) {
+                const int s = wave + NW * i, k = s / np, q = s % np;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rtv[rt]) {
+                        const double2 *p = reinterpret_cast<const double2 *>(
+                                               Af + (((size_t)k * g.MT + mt0 + rt) * KT2 + q0 + q) * 128) +
+                                           lane;
+                        dst[rt] = *p;
+                    } else {
+                        dst[rt] = double2{0.0, 0.0};
+                    }
+                }
+            };
+            double2 ab[PF][RT];
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (u < ns) load(u, ab[u]);
+            for (int i0 = 0; i0 < ns; i0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int i = i0 + u;
+                    if (i < ns) {
+                        double2 a[RT];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt) a[rt] = ab[u][rt];
+                        if (i + PF < ns) load(i + PF, ab[u]);
+                        const int s = wave + NW * i, k = s / np, q = s % np;
+                        double cf[CB];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const int r = 4 * (2 * q + j) + lk;
+                            double b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * FXS + r] * cf[cb];
+#pragma unroll
+                            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, b[cb],
+                                                                                       acc[rt][cb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // pairwise tree over the waves: wave w += wave w + h, h = NW/2, NW/4, ..., 1
+#pragma unroll
+    for (int h = NW / 2; h >= 1; h >>= 1) {
+        __syncthreads();
+        if (wave >= h && wave < 2 * h)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        Xs[(((wave - h) * RT + rt) * CB + cb) * 256 + i * 64 + lane] = acc[rt][cb][i];
+        __syncthreads();
+        if (wave < h)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[rt][cb][i] += Xs[((wave * RT + rt) * CB + cb) * 256 + i * 64 + lane];
+    }
+    if (wave != 0) return;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int mt = mt0 + rt, col = col0 + cb * 16 + lr;
+            if (mt >= g.MT || col >= g.ncols) continue;
+            double *ycol = g.Y + (long long)(col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * i + lk;
+                if (row < g.M) ycol[row] = g.accumulate ? ycol[row] + acc[rt][cb][i] : acc[rt][cb][i];
+            }
+        }
+}
+
+template <int RT, int CB, int PF, int NW>
+void launch_frag(const GemmArgsFrag &a, hipStream_t s) {
+    dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RT - 1) / RT));
+    hipLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, a);
+}
+
 template <int BM, int SPLIT>
 void launch(const GemmArgsDev &a, hipStream_t s) {
     const int cblocks = (a.ncols + 15) / 16;
@@ -368,7 +573,8 @@ void launch(const GemmArgsDev &a, hipStream_t s) {
 
 // fp32/bf16 copies of the principal operators used by the precision form
 void make_lp_copies(ifeti_ctx *c, const std::vector<std::pair<const double *, size_t>> &arrays) {
-    c->lp.clear();
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    c->free_copies();  // the bank was (re)built: every derived copy is stale
     for (auto &ar : arrays) {
         ifeti_ctx::LPCopy cp;
         cp.src = ar.first;
@@ -392,10 +598,31 @@ const void *lp_copy(ifeti_ctx *c, const double *A, int precision) {
     return nullptr;
 }
 
+// fragment-ordered copy of A viewed as K stacked M x Kd operators (built on first use)
+static const double *frag_copy(ifeti_ctx *c, const double *A, int M, int Kd, int K) {
+    for (auto &cp : c->frag)
+        if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K) return cp.frag;
+    const int MT = (M + 15) / 16, KT2 = (Kd + 7) / 8;
+    const long long n = (long long)K * MT * KT2 * 128;
+    ifeti_ctx::FragCopy cp;
+    cp.src = A;
+    cp.M = M;
+    cp.Kd = Kd;
+    cp.K = K;
+    IFETI_HIP(hipMalloc(&cp.frag, n * sizeof(double)));
+    hipLaunchKernelGGL(k_to_frag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, M, Kd, K, MT, KT2,
+                       cp.frag);
+    IFETI_HIP(hipGetLastError());
+    c->frag.push_back(cp);
+    return cp.frag;
+}
+
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
           bool accumulate, int ncells, const char *tag, bool lp_ok) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
     if (ncols <= 0 || M <= 0) return;
+    int ngather = 0;
+    for (int i = 0; i < ngroups; ++i) ngather += groups[i].gcodes ? 1 : 0;
     GemmArgsDev a{};
     a.ncells = ncells > 0 ? ncells : c->N;
     int Kmax = 0, Kdmax = 0;
@@ -426,7 +653,31 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
                         (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
     }
     const long long cblocks = (ncols + 15) / 16;
-    if (lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16) {
+    double abytes = 0.0;
+    for (int i = 0; i < ngroups; ++i) abytes += 8.0 * (double)groups[i].K * M * groups[i].Kd;
+    const bool lp_path = lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16;
+    const bool frag_path = !lp_path && abytes <= 4.0 * 1024 * 1024 && Kmax <= kMaxCoefK;
+    if (ngather > 0 && !frag_path) {
+        // only the fragment kernel stages through the jump codes: gather first, then contract
+        IFETI_REQUIRE(ngather == 1, IFETI_EINVAL, "gemm: at most one gathered group");
+        IFETI_REQUIRE(ncells <= 0 || ncells == c->N, IFETI_EINVAL, "gemm: gathered group needs all cells");
+        GemmGroup gg[2];
+        for (int i = 0; i < ngroups; ++i) {
+            gg[i] = groups[i];
+            if (gg[i].gcodes) {
+                const int nrhs = (int)(ncols / c->N);
+                op_gather(c, gg[i].X, gg[i].xbs, c->w_Lam.p, nrhs, gg[i].gw != nullptr);
+                gg[i].X = c->w_Lam.p;
+                gg[i].ldx = gg[i].Kd;
+                gg[i].xbs = 0;
+                gg[i].gcodes = nullptr;
+                gg[i].gw = nullptr;
+            }
+        }
+        gemm(c, gg, ngroups, Y, ldy, ybs, M, ncols, accumulate, ncells, tag, lp_ok);
+        return;
+    }
+    if (lp_path) {
         GemmArgsLP b{};
         bool all = true;
         for (int i = 0; i < ngroups; ++i) {
@@ -463,6 +714,42 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             IFETI_HIP(hipGetLastError());
             return;
         }
+    }
+    // L2-resident operators (a few MB per XCD) take the fragment-ordered path
+    if (frag_path) {
+        GemmArgsFrag f{};
+        for (int i = 0; i < ngroups; ++i) {
+            f.Af[i] = frag_copy(c, groups[i].A, M, groups[i].Kd, groups[i].K);
+            f.X[i] = a.X[i];
+            f.coef[i] = a.coef[i];
+            f.gcodes[i] = groups[i].gcodes;
+            f.gw[i] = groups[i].gw;
+            f.Kd[i] = a.Kd[i];
+            f.ldx[i] = a.ldx[i];
+            f.K[i] = a.K[i];
+            f.KT2[i] = (a.Kd[i] + 7) / 8;
+            f.xbs[i] = a.xbs[i];
+            f.scale[i] = a.scale[i];
+        }
+        f.ngroups = ngroups;
+        f.Y = Y;
+        f.ybs = a.ybs;
+        f.ldy = ldy;
+        f.M = M;
+        f.MT = (M + 15) / 16;
+        f.ncols = ncols;
+        f.ncells = a.ncells;
+        f.accumulate = a.accumulate;
+        Prof prof(c, tag, flops, bytes);
+        // shapes tuned on gfx950: few rows -> many waves per tile; few inner steps -> tall tiles
+        if (f.MT == 1)
+            launch_frag<1, 1, 2, 16>(f, c->stream);
+        else if (Kdmax <= 16)
+            launch_frag<4, 1, 4, 4>(f, c->stream);
+        else
+            launch_frag<4, 2, 2, 8>(f, c->stream);
+        IFETI_HIP(hipGetLastError());
+        return;
     }
     Prof prof(c, tag, flops, bytes);
     if (M <= 16 && Kmax >= 4) {

@@ -403,6 +403,18 @@ int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *princ
     return K;
 }
 
+// lower-triangle tiles of the explicit coarse inverse (one workgroup per tile,
+// tiles with J > I exit), zero-padded beyond nP
+__global__ __launch_bounds__(kBlock) void k_sym_pack(const double *__restrict__ S, int n, double *__restrict__ T) {
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (J > I) return;
+    double *dst = T + ((size_t)I * (I + 1) / 2 + J) * 4096;
+    for (int e = threadIdx.x; e < 4096; e += kBlock) {
+        const int r = I * 64 + e / 64, cc = J * 64 + e % 64;
+        dst[e] = (r < n && cc < n) ? S[(size_t)r * n + cc] : 0.0;
+    }
+}
+
 void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw) {
     DevBuf<double> band;
     band.upload(band_L, c->stream);
@@ -410,6 +422,21 @@ void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int 
     hipLaunchKernelGGL(k_band_inverse, dim3(blocks_for(c->nP, 64)), dim3(64), 0, c->stream, band.p, c->nP, bw,
                        c->SPPinv.p);
     IFETI_HIP(hipGetLastError());
+    const int nT = (c->nP + 63) / 64;
+    const size_t ntiles = (size_t)nT * (nT + 1) / 2;
+    c->nT = nT;
+    c->SPPt.alloc(ntiles * 4096);
+    hipLaunchKernelGGL(k_sym_pack, dim3(nT, nT), dim3(kBlock), 0, c->stream, c->SPPinv.p, c->nP, c->SPPt.p);
+    IFETI_HIP(hipGetLastError());
+    std::vector<int> tl(2 * ntiles);
+    for (int I = 0; I < nT; ++I)
+        for (int J = 0; J <= I; ++J) {
+            const size_t t = (size_t)I * (I + 1) / 2 + J;
+            tl[2 * t] = I;
+            tl[2 * t + 1] = J;
+        }
+    c->sym_tiles.upload(tl, c->stream);
+    c->w_symP.alloc(ntiles * 3 * 128);  // up to 3 load cases per pass
     IFETI_HIP(hipStreamSynchronize(c->stream));
 }
 

@@ -62,6 +62,44 @@ __global__ __launch_bounds__(kB) void k_scatter(const int *__restrict__ sl, cons
     out[rhs * out_rs + l] = weights ? v * Dw[l] : v;
 }
 
+// B_d (and D-scaling) with the PCG dot product fused: grid (nblk, nrhs), block b
+// owns the contiguous chunk b of the L multipliers of its load case and writes
+// its partial sum of out . w (tree-reduced in a fixed order).
+__global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, const double *__restrict__ Dw,
+                                                    const double *__restrict__ Y, int y_ld, int y_off, long long y_rs,
+                                                    double *__restrict__ out, long long out_rs, int L, int n_d,
+                                                    int weights, const double *__restrict__ w, int nblk,
+                                                    double *__restrict__ part) {
+    __shared__ double sh[kB];
+    const int b = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x;
+    const int chunk = (L + nblk - 1) / nblk;
+    const int i0 = b * chunk, i1 = min(L, i0 + chunk);
+    const double *y = Y + rhs * y_rs;
+    double acc = 0.0;
+    for (int l = i0 + tid; l < i1; l += kB) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int code = sl[(size_t)l * 2 + u];
+            if (code == 0) continue;
+            int e = (code > 0 ? code : -code) - 1;
+            int s = e / n_d, j = e % n_d;
+            double x = y[(size_t)s * y_ld + y_off + j];
+            v += code > 0 ? x : -x;
+        }
+        if (weights) v *= Dw[l];
+        out[rhs * out_rs + l] = v;
+        acc += v * w[rhs * out_rs + l];
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (tid < off) sh[tid] += sh[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) part[(size_t)rhs * nblk + b] = sh[0];
+}
+
 // ------------------------------------------------------------------ A_p, A_p^T
 __global__ __launch_bounds__(kB) void k_assemble_primal(const int *__restrict__ pull, int maxc,
                                                         const double *__restrict__ cp, int N, int n_p,
@@ -89,6 +127,110 @@ __global__ __launch_bounds__(kB) void k_restrict_primal(const int *__restrict__ 
     int rhs = (int)(t / per);
     int P = Ap[t % per];
     xp[t] = P >= 0 ? xP[rhs * x_rs + P] : 0.0;
+}
+
+// ------------------------------------------------------------------ coarse solve, symmetric tiles
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// y = scale * S z with S = S̊_PP^-1 stored as its lower-triangle 64x64 tiles.
+// Pass 1, one workgroup per tile (I, J), streamed with non-temporal loads so
+// the L2-resident principal operators of the concurrent contraction stay
+// cached: each thread owns 4 rows x 4 columns; the row partial S_IJ z_J and,
+// off the diagonal, the column partial S_IJ^T z_I are reduced with lane
+// shuffles and LDS in a fixed order and written per tile.  Pass 2 sums, for every row of block I, the row partials
+// of tiles (I, 0..I) and the column partials of tiles (I+1..nT-1, I) in that
+// fixed order (bitwise reproducible, no atomics).
+template <int NR>
+__global__ __launch_bounds__(256) void k_sym_tiles(const double *__restrict__ T, const int *__restrict__ tiles, int n,
+                                                   const double *__restrict__ z, long long z_rs,
+                                                   double *__restrict__ P) {
+    __shared__ double red[NR][4][64];
+    const int tile = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+    // thread owns rows 4a + i and columns cidx(j) = 2b + (j & 1) + 32 (j >> 1): each
+    // 16-byte load instruction covers 4 rows x 256 contiguous bytes per wave
+    const int a = tid >> 4, b = tid & 15;
+    double S[4][4];
+    const double *src = T + (size_t)tile * 4096;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const v2d v0 = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(src + (4 * a + i) * 64 + 2 * b));
+        const v2d v1 = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(src + (4 * a + i) * 64 + 32 + 2 * b));
+        S[i][0] = v0.x;
+        S[i][1] = v0.y;
+        S[i][2] = v1.x;
+        S[i][3] = v1.y;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const double *zq = z + q * z_rs;
+        double zJ[4], zI[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int cJ = J * 64 + 2 * b + (j & 1) + 32 * (j >> 1), rI = I * 64 + 4 * a + j;
+            zJ[j] = cJ < n ? zq[cJ] : 0.0;
+            zI[j] = rI < n ? zq[rI] : 0.0;
+        }
+        double pr[4], pc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            pr[i] = ((S[i][0] * zJ[0] + S[i][1] * zJ[1]) + S[i][2] * zJ[2]) + S[i][3] * zJ[3];
+            pc[i] = ((S[0][i] * zI[0] + S[1][i] * zI[1]) + S[2][i] * zI[2]) + S[3][i] * zI[3];
+        }
+        // row partials: sum over the 16 column groups b (lanes of one 16-lane row)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pr[i] += __shfl_xor(pr[i], off);
+        double *Pt = P + ((size_t)tile * NR + q) * 128;
+        if (b == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Pt[4 * a + i] = pr[i];
+        if (I != J) {
+            // column partials: sum over the 16 row groups a (4 per wave, then the 4 waves)
+#pragma unroll
+            for (int off = 16; off < 64; off <<= 1)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pc[j] += __shfl_xor(pc[j], off);
+            if (lane < 16)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[q][wave][2 * b + (j & 1) + 32 * (j >> 1)] = pc[j];
+        }
+    }
+    if (I == J) return;  // uniform per workgroup
+    __syncthreads();
+    if (tid < 64)
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            P[((size_t)tile * NR + q) * 128 + 64 + tid] =
+                ((red[q][0][tid] + red[q][1][tid]) + red[q][2][tid]) + red[q][3][tid];
+}
+
+// one workgroup per (block row I, load case): thread (part, r) sums the
+// contributions J = part, part + 16, ... of row r; the 16 parts are added in
+// order through LDS
+__global__ __launch_bounds__(1024) void k_sym_reduce(const double *__restrict__ P, int n, int nT, int NR,
+                                                     double *__restrict__ y, long long y_rs, double scale) {
+    __shared__ double part_s[16][64];
+    const int I = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+    const int r = tid & 63, part = tid >> 6;
+    const size_t base = (size_t)I * (I + 1) / 2;
+    double s = 0.0;
+#pragma unroll 4
+    for (int J = part; J < nT; J += 16) {
+        const size_t off = J <= I ? ((base + J) * NR + q) * 128 + r
+                                  : (((size_t)J * (J + 1) / 2 + I) * NR + q) * 128 + 64 + r;
+        s += P[off];
+    }
+    part_s[part][r] = s;
+    __syncthreads();
+    const int row = I * 64 + tid;
+    if (tid < 64 && row < n) {
+        double t = part_s[0][tid];
+#pragma unroll
+        for (int p = 1; p < 16; ++p) t += part_s[p][tid];
+        y[q * y_rs + row] = scale * t;
+    }
 }
 
 // ------------------------------------------------------------------ coarse solve, one wave per row
@@ -550,9 +692,19 @@ void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, i
                        Lam, c->N, c->n_d, nrhs, weights ? 1 : 0);
 }
 
+int dot_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(1024, (n + 1023) / 1024)); }
+
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
-                int nrhs, bool weights) {
+                int nrhs, bool weights, const double *dot_w, double *dot_part) {
     long long n = (long long)c->L * nrhs;
+    if (dot_w) {
+        const int nblk = dot_blocks(c->L);
+        Prof prof(c, "scatter_dot", 2.0 * (double)n,
+                  16.0 * (double)n + 8.0 * (double)c->N * c->n_d * nrhs + 8.0 * (double)c->L);
+        hipLaunchKernelGGL(k_scatter_dot, dim3(nblk, nrhs), dim3(kB), 0, c->stream, c->g_scatter.p, c->g_Dw.p, Y,
+                           y_ld, y_off, y_rs, out, out_rs, c->L, c->n_d, weights ? 1 : 0, dot_w, nblk, dot_part);
+        return;
+    }
     Prof prof(c, "scatter", 0.0, 8.0 * (double)n + 8.0 * (double)c->N * c->n_d * nrhs + 8.0 * (double)c->L);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_scatter.p, c->g_Dw.p, Y, y_ld,
                        y_off, y_rs, out, out_rs, c->L, c->n_d, nrhs, weights ? 1 : 0);
@@ -579,12 +731,26 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
                      double scale) {
     if (c->nP == 0) return;
     if (nrhs < 4) {
-        const double n2 = (double)c->nP * c->nP;
-        for (int r = 0; r < nrhs; ++r) {
-            Prof prof(c, "coarse_gemv", 2.0 * n2, 8.0 * n2 + 16.0 * c->nP);
-            hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks((long long)c->nP * 64)), dim3(kB), 0, c->stream,
-                               c->SPPinv.p, c->nP, z + r * z_rs, y + r * y_rs, scale);
+        const double n = (double)c->nP, nt = (double)c->nT * (c->nT + 1) / 2;
+        {
+            // algorithmic: the symmetric operator's n(n+1)/2 entries read once, the vectors, the partials
+            Prof prof(c, "coarse_symv", 2.0 * n * n * nrhs,
+                      8.0 * (n * (n + 1) / 2 + 2.0 * n * nrhs + nt * 128.0 * nrhs));
+            const unsigned ntiles = (unsigned)nt;
+            if (nrhs == 1)
+                hipLaunchKernelGGL(k_sym_tiles<1>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
+                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+            else if (nrhs == 2)
+                hipLaunchKernelGGL(k_sym_tiles<2>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
+                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+            else
+                hipLaunchKernelGGL(k_sym_tiles<3>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
+                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+            IFETI_HIP(hipGetLastError());
         }
+        Prof prof(c, "coarse_reduce", (double)nrhs * nt * 128.0, 8.0 * (nt * 128.0 + n) * nrhs);
+        hipLaunchKernelGGL(k_sym_reduce, dim3(c->nT, nrhs), dim3(1024), 0, c->stream, c->w_symP.p, c->nP, c->nT,
+                           nrhs, y, y_rs, scale);
     } else {
         GemmGroup g;
         g.A = c->SPPinv.p;
@@ -603,13 +769,14 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 // coarse solve on the side stream while the main stream runs the dominant
 // contraction sum_k delta_k F_dd^(k) Lambda; the coarse correction
 // (T_dr Ů_rp^(s)) A_p^T y_P is added after the join, then B_d scatters.
-void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
+void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
     ensure_work(c, nrhs);
     const int N = c->N, nd = c->n_d, np = c->n_p, K = c->K;
     const int cols = N * nrhs;
-    op_gather(c, lam, c->L, c->w_Lam.p, nrhs, false);
+    // B_d^T lam is fused into the staging of both contractions that read it
     GemmGroup g0;
-    g0.A = c->WT.p; g0.X = c->w_Lam.p; g0.coef = c->pi.p; g0.Kd = nd; g0.ldx = nd; g0.K = K;
+    g0.A = c->WT.p; g0.X = lam; g0.xbs = c->L; g0.gcodes = c->g_gather.p; g0.coef = c->pi.p; g0.Kd = nd;
+    g0.K = K;
     gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "F_restrict_gemm");
     {
         SideStream side(c);
@@ -618,26 +785,27 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
         op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
     }
     GemmGroup g1;
-    g1.A = c->Fdd.p; g1.X = c->w_Lam.p; g1.coef = c->delta.p; g1.Kd = nd; g1.ldx = nd; g1.K = K;
+    g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
+    g1.K = K;
     gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
     join_side(c);
     GemmGroup g2;
     g2.A = c->W.p; g2.X = c->w_yp.p; g2.coef = c->pi.p; g2.Kd = np; g2.ldx = np; g2.K = K;
     gemm(c, &g2, 1, c->w_Y.p, nd, 0, nd, cols, true, 0, "F_prolong_gemm");
-    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ M̊_D^-1 (49)
-void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w, double *dot_part) {
     ensure_work(c, nrhs);
     const int N = c->N, nd = c->n_d, K = c->K;
-    op_gather(c, r, c->L, c->w_Lam.p, nrhs, true);
-    GemmGroup g;
-    g.A = c->Sdd.p; g.X = c->w_Lam.p; g.coef = c->alpha.p; g.Kd = nd; g.ldx = nd; g.K = K;
+    GemmGroup g;  // D-scaled B_d^T r fused into the staging
+    g.A = c->Sdd.p; g.X = r; g.xbs = c->L; g.gcodes = c->g_gather.p; g.gw = c->g_Dw.p; g.coef = c->alpha.p;
+    g.Kd = nd; g.K = K;
     gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false, 0, "MD_gemm");
-    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, true);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, true, dot_w, dot_part);
     c->applies[IFETI_OP_MD] += nrhs;
     IFETI_HIP(hipGetLastError());
 }

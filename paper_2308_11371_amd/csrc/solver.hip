@@ -78,39 +78,48 @@ __global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr
     }
 }
 
-// alpha = rho / p.q (breakdown if p.q <= 0 or not finite)
-__global__ __launch_bounds__(kB) void k_pcg_alpha(const double *__restrict__ p_pq, int nblk, double *__restrict__ st,
-                                                  int *__restrict__ ist) {
-    __shared__ double sh[kB];
-    int rhs = blockIdx.x;
-    double pq = sum_partials(p_pq + (size_t)rhs * nblk, nblk, sh);
-    if (threadIdx.x == 0) {
-        double a = 0.0;
-        if (ist[rhs * I_N + I_ACT]) {
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                ist[rhs * I_N + I_BRK] = 1;
-                ist[rhs * I_N + I_ACT] = 0;
-            } else {
-                a = st[rhs * S_N + S_RHO] / pq;
-            }
-        }
-        st[rhs * S_N + S_ALPHA] = a;
-    }
-}
+// ---- fused PCG step kernels.  The scalar state is double-buffered: slot 0
+// holds the state between iterations, slot 1 the state after the update.
+// Every block recomputes the scalars it needs from the partial sums (fixed
+// order, so all blocks agree bitwise) and reads only the slot the kernel does
+// not write; block (0, rhs) writes the other slot.
 
-// lam += alpha p; r -= alpha q; partial ||r||^2
-__global__ __launch_bounds__(kB) void k_pcg_update(double *__restrict__ lam, double *__restrict__ r,
-                                                   const double *__restrict__ p, const double *__restrict__ q,
-                                                   long long n, long long rs, const double *__restrict__ st, int nblk,
-                                                   double *__restrict__ part) {
+// alpha = rho / p.q (breakdown if p.q <= 0 or not finite); lam += alpha p,
+// r -= alpha q; partial ||r||^2.  Reads slot 0, writes slot 1.
+__global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, double *__restrict__ r,
+                                                 const double *__restrict__ p, const double *__restrict__ q,
+                                                 long long n, long long rs, int nrhs, double *__restrict__ st,
+                                                 int *__restrict__ ist, const double *__restrict__ p_pq, int nblk,
+                                                 double *__restrict__ p_rr) {
     __shared__ double sh[kB];
-    int b = blockIdx.x, rhs = blockIdx.y;
-    double a = st[rhs * S_N + S_ALPHA];
-    long long chunk = (n + nblk - 1) / nblk;
-    long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+    const int b = blockIdx.x, rhs = blockIdx.y;
+    const double *s0 = st + (size_t)rhs * S_N;
+    const int *i0s = ist + (size_t)rhs * I_N;
+    double *s1 = st + ((size_t)nrhs + rhs) * S_N;
+    int *i1s = ist + ((size_t)nrhs + rhs) * I_N;
+    const double pq = sum_partials(p_pq + (size_t)rhs * nblk, nblk, sh);
+    int act = i0s[I_ACT], brk = i0s[I_BRK];
+    double a = 0.0;
+    if (act) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            brk = 1;
+            act = 0;
+        } else {
+            a = s0[S_RHO] / pq;
+        }
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < S_N; ++k) s1[k] = s0[k];
+        s1[S_ALPHA] = a;
+        i1s[I_ACT] = act;
+        i1s[I_IT] = i0s[I_IT];
+        i1s[I_BRK] = brk;
+    }
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
+    const size_t base = (size_t)rhs * rs;
     double acc = 0.0;
-    size_t base = (size_t)rhs * rs;
-    for (long long t = i0 + threadIdx.x; t < i1; t += kB) {
+    for (long long t = j0 + threadIdx.x; t < j1; t += kB) {
         double rv = r[base + t];
         if (a != 0.0) {
             lam[base + t] += a * p[base + t];
@@ -120,47 +129,48 @@ __global__ __launch_bounds__(kB) void k_pcg_update(double *__restrict__ lam, dou
         acc += rv * rv;
     }
     acc = block_reduce(acc, sh);
-    if (threadIdx.x == 0) part[(size_t)rhs * nblk + b] = acc;
+    if (threadIdx.x == 0) p_rr[(size_t)rhs * nblk + b] = acc;
 }
 
-__global__ __launch_bounds__(kB) void k_pcg_check(const double *__restrict__ p_rr, int nblk, double *__restrict__ st,
-                                                  int *__restrict__ ist, double tol, int it) {
+// relres from ||r||^2 (stop at tol), beta = r.z / rho, p = z + beta p for the
+// load cases still active.  Reads slot 1, writes slot 0.
+__global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const double *__restrict__ z, long long n,
+                                                 long long rs, int nrhs, double *__restrict__ st,
+                                                 int *__restrict__ ist, const double *__restrict__ p_rr,
+                                                 const double *__restrict__ p_rz, int nblk, double tol, int it) {
     __shared__ double sh[kB];
-    int rhs = blockIdx.x;
-    double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
-    if (threadIdx.x == 0 && ist[rhs * I_N + I_ACT]) {
-        double rel = sqrt(rr) / st[rhs * S_N + S_R0];
-        st[rhs * S_N + S_REL] = rel;
-        ist[rhs * I_N + I_IT] = it;
-        if (rel <= tol) ist[rhs * I_N + I_ACT] = 0;
+    const int b = blockIdx.x, rhs = blockIdx.y;
+    double *s0 = st + (size_t)rhs * S_N;
+    int *i0s = ist + (size_t)rhs * I_N;
+    const double *s1 = st + ((size_t)nrhs + rhs) * S_N;
+    const int *i1s = ist + ((size_t)nrhs + rhs) * I_N;
+    const double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
+    const double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
+    int act = i1s[I_ACT], its = i1s[I_IT];
+    double rel = s1[S_REL], rho = s1[S_RHO], beta = 0.0;
+    if (act) {
+        rel = sqrt(rr) / s1[S_R0];
+        its = it;
+        if (rel <= tol) act = 0;
     }
-}
-
-__global__ __launch_bounds__(kB) void k_pcg_beta(const double *__restrict__ p_rz, int nblk, double *__restrict__ st,
-                                                 const int *__restrict__ ist) {
-    __shared__ double sh[kB];
-    int rhs = blockIdx.x;
-    double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
-    if (threadIdx.x == 0) {
-        if (ist[rhs * I_N + I_ACT]) {
-            st[rhs * S_N + S_BETA] = rz / st[rhs * S_N + S_RHO];
-            st[rhs * S_N + S_RHO] = rz;
-        } else {
-            st[rhs * S_N + S_BETA] = 0.0;
-        }
+    if (act) {
+        beta = rz / rho;
+        rho = rz;
     }
-}
-
-// p = z + beta p (active load cases only)
-__global__ __launch_bounds__(kB) void k_pcg_p(double *__restrict__ p, const double *__restrict__ z, long long n,
-                                              long long rs, int nrhs, const double *__restrict__ st,
-                                              const int *__restrict__ ist) {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nrhs) return;
-    int rhs = (int)(t / n);
-    if (!ist[rhs * I_N + I_ACT]) return;
-    size_t i = (size_t)rhs * rs + (t % n);
-    p[i] = z[i] + st[rhs * S_N + S_BETA] * p[i];
+    if (b == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < S_N; ++k) s0[k] = s1[k];
+        s0[S_REL] = rel;
+        s0[S_RHO] = rho;
+        s0[S_BETA] = beta;
+        i0s[I_ACT] = act;
+        i0s[I_IT] = its;
+        i0s[I_BRK] = i1s[I_BRK];
+    }
+    if (!act) return;
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
+    const size_t base = (size_t)rhs * rs;
+    for (long long t = j0 + threadIdx.x; t < j1; t += kB) p[base + t] = z[base + t] + beta * p[base + t];
 }
 
 __global__ __launch_bounds__(kB) void k_copy(const double *__restrict__ x, double *__restrict__ y, long long n) {
@@ -212,33 +222,36 @@ __global__ __launch_bounds__(kB) void k_sub(const double *__restrict__ a, long l
 }  // namespace
 
 // ------------------------------------------------------------------ interface PCG
+// One iteration = F̊ p (its final scatter also yields the p.q partials),
+// k_pcg_step, M̊_D^-1 r (its scatter yields the r.z partials), k_pcg_next.
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres) {
     const long long L = c->L;
     const long long n = L * nrhs;
-    DevBuf<double> r, z, p, q, st, part_a, part_b;
-    DevBuf<int> ist;
-    r.alloc(n);
-    z.alloc(n);
-    p.alloc(n);
-    q.alloc(n);
-    st.alloc((size_t)S_N * nrhs);
-    ist.alloc((size_t)I_N * nrhs);
-    const int nblk = reduce_blocks(L);
-    part_a.alloc((size_t)nblk * nrhs);
-    part_b.alloc((size_t)nblk * nrhs);
     hipStream_t s = c->stream;
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, rhs, r.p, n);
+    const int nblk = dot_blocks(L);
+    c->pcg_r.ensure(n, s);
+    c->pcg_z.ensure(n, s);
+    c->pcg_p.ensure(n, s);
+    c->pcg_q.ensure(n, s);
+    c->pcg_st.ensure((size_t)2 * S_N * nrhs, s);
+    c->pcg_ist.ensure((size_t)2 * I_N * nrhs, s);
+    c->pcg_pa.ensure((size_t)nblk * nrhs, s);
+    c->pcg_pb.ensure((size_t)nblk * nrhs, s);
+    c->pcg_pc.ensure((size_t)nblk * nrhs, s);
+    double *r = c->pcg_r.p, *z = c->pcg_z.p, *p = c->pcg_p.p, *q = c->pcg_q.p, *st = c->pcg_st.p;
+    double *pa = c->pcg_pa.p, *pb = c->pcg_pb.p, *pc = c->pcg_pc.p;
+    int *ist = c->pcg_ist.p;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, rhs, r, n);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kB), 0, s, lam, n, 0.0);
-    apply_MD(c, r.p, z.p, nrhs);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, r.p, L, L, nblk, part_a.p);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_b.p);
-    hipLaunchKernelGGL(k_pcg_init, dim3(nrhs), dim3(kB), 0, s, part_a.p, part_b.p, nblk, st.p, ist.p);
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, z.p, p.p, n);
+    apply_MD(c, r, z, nrhs, r, pb);                                   // z = M r, partials of r.z
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r, r, L, L, nblk, pa);
+    hipLaunchKernelGGL(k_pcg_init, dim3(nrhs), dim3(kB), 0, s, pa, pb, nblk, st, ist);
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, z, p, n);
     IFETI_HIP(hipGetLastError());
     std::vector<int> hist((size_t)I_N * nrhs);
-    auto any_active = [&]() {
-        IFETI_HIP(hipMemcpyAsync(hist.data(), ist.p, hist.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    auto any_active = [&]() {  // slot 0 holds the state between iterations
+        IFETI_HIP(hipMemcpyAsync(hist.data(), ist, hist.size() * sizeof(int), hipMemcpyDeviceToHost, s));
         IFETI_HIP(hipStreamSynchronize(s));
         bool act = false, brk = false;
         for (int r2 = 0; r2 < nrhs; ++r2) {
@@ -251,43 +264,24 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     const int every = std::max(1, c->opt.pcg_check_every);
     const double Ld = (double)L * nrhs;
     for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
-        apply_F(c, p.p, q.p, nrhs);
+        apply_F(c, p, q, nrhs, p, pa);                                // q = F p, partials of p.q
         {
-            Prof prof(c, "pcg_dot", 2.0 * Ld, 16.0 * Ld);
-            hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, p.p, q.p, L, L, nblk, part_a.p);
+            Prof prof(c, "pcg_step", 5.0 * Ld, 48.0 * Ld);            // read lam, p, q, r; write lam, r
+            hipLaunchKernelGGL(k_pcg_step, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r, p, q, L, L, nrhs, st, ist, pa,
+                               nblk, pb);
         }
+        apply_MD(c, r, z, nrhs, r, pc);                               // z = M r, partials of r.z
         {
-            Prof prof(c, "pcg_scalar", 0.0, 0.0);
-            hipLaunchKernelGGL(k_pcg_alpha, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
-        }
-        {
-            Prof prof(c, "pcg_update", 5.0 * Ld, 48.0 * Ld);  // read lam, p, q, r; write lam, r
-            hipLaunchKernelGGL(k_pcg_update, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r.p, p.p, q.p, L, L, st.p, nblk,
-                               part_b.p);
-        }
-        {
-            Prof prof(c, "pcg_scalar", 0.0, 0.0);
-            hipLaunchKernelGGL(k_pcg_check, dim3(nrhs), dim3(kB), 0, s, part_b.p, nblk, st.p, ist.p, tol, it);
-        }
-        apply_MD(c, r.p, z.p, nrhs);
-        {
-            Prof prof(c, "pcg_dot", 2.0 * Ld, 16.0 * Ld);
-            hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r.p, z.p, L, L, nblk, part_a.p);
-        }
-        {
-            Prof prof(c, "pcg_scalar", 0.0, 0.0);
-            hipLaunchKernelGGL(k_pcg_beta, dim3(nrhs), dim3(kB), 0, s, part_a.p, nblk, st.p, ist.p);
-        }
-        {
-            Prof prof(c, "pcg_p", 2.0 * Ld, 24.0 * Ld);
-            hipLaunchKernelGGL(k_pcg_p, dim3(nblocks(n)), dim3(kB), 0, s, p.p, z.p, L, L, nrhs, st.p, ist.p);
+            Prof prof(c, "pcg_next", 2.0 * Ld, 24.0 * Ld);
+            hipLaunchKernelGGL(k_pcg_next, dim3(nblk, nrhs), dim3(kB), 0, s, p, z, L, L, nrhs, st, ist, pb, pc,
+                               nblk, tol, it);
         }
         IFETI_HIP(hipGetLastError());
         if (it % every == 0 || it == maxit) st0 = any_active();
     }
     st0 = any_active();
     std::vector<double> hst((size_t)S_N * nrhs);
-    IFETI_HIP(hipMemcpyAsync(hst.data(), st.p, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    IFETI_HIP(hipMemcpyAsync(hst.data(), st, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     IFETI_HIP(hipStreamSynchronize(s));
     for (int r2 = 0; r2 < nrhs; ++r2) {
         c->pcg_its += hist[r2 * I_N + I_IT];
