@@ -177,6 +177,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> Urd;          // [k][n_r][n_d]
     ifeti::DevBuf<double> Urp;          // [k][n_r][n_p]
     ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
+    ifeti::DevBuf<double> Wc;           // [s][n_p][n_d] per-cell sum_k pi_sk (T_dr U_rp^(k))^T
     ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
     ifeti::DevBuf<double> SPPinv;       // [nP][nP]
     // lower-triangle 64x64 tiles of SPPinv, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
@@ -284,6 +285,7 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs);
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
+void combine_coarse_maps(ifeti_ctx *c);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);
 void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,

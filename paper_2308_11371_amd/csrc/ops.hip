@@ -100,6 +100,100 @@ __global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, 
     if (tid == 0) part[(size_t)rhs * nblk + b] = sh[0];
 }
 
+// ------------------------------------------------------------------ coarse maps of F̊ (48)
+// The coarse restriction and prolongation of F̊ use, per cell, the same
+// n_p x n_d matrix C_s = sum_k pi_sk (T_dr U_rp^(k))^T.  It depends only on the
+// coefficients, so it is combined once per reduced basis and both maps become
+// streaming per-cell products instead of small-M contractions.
+__global__ __launch_bounds__(kB) void k_combine_wt(const double *__restrict__ pi, const double *__restrict__ WT,
+                                                   int N, int K, int npd, double *__restrict__ C) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)N * npd) return;
+    const int s = (int)(t / npd), e = (int)(t % npd);
+    double v = 0.0;
+    for (int k = 0; k < K; ++k) v += pi[(size_t)s * K + k] * WT[(size_t)k * npd + e];
+    C[t] = v;
+}
+
+constexpr int kMaxNp = 24;  // primal (corner) dofs per cell: 4 x 2 in 2D, 8 x 3 in 3D
+
+// c_s = C_s B_d^T lam for column (rhs, s): one wave per column; lane j-stride
+// gathers the signed multipliers of the cell's dual dofs, the n_p sums are
+// reduced across the wave.
+template <int NPM>
+__global__ __launch_bounds__(256) void k_restrict_c(const double *__restrict__ C, const int *__restrict__ gl,
+                                                    const double *__restrict__ lam, long long lam_rs, int N, int n_d,
+                                                    int n_p, int ncols, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= ncols) return;  // uniform per wave; no block-level synchronisation below
+    const int rhs = col / N, s = col % N;
+    const double *l = lam + rhs * lam_rs;
+    const double *Cs = C + (size_t)s * n_p * n_d;
+    double acc[NPM];
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) acc[i] = 0.0;
+    for (int j = lane; j < n_d; j += 64) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int code = gl[((size_t)s * n_d + j) * 2 + u];
+            if (code == 0) continue;
+            const double x = l[(code > 0 ? code : -code) - 1];
+            v += code > 0 ? x : -x;
+        }
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (i < n_p) acc[i] += Cs[(size_t)i * n_d + j] * v;
+    }
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) {
+        if (i >= n_p) break;
+        double v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc[i] = v;
+    }
+    if (lane < n_p) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (i == lane) v = acc[i];
+        out[(size_t)col * n_p + lane] = v;
+    }
+}
+
+// Y_s += C_s^T y_P[A_p(s)] for column (rhs, s): one wave per column, lanes
+// over the cell's dual rows (coalesced rows of C_s); the n_p primal values of
+// the cell are wave-uniform.
+template <int NPM>
+__global__ __launch_bounds__(256) void k_prolong_c(const double *__restrict__ C, const int *__restrict__ Ap,
+                                                   const double *__restrict__ yP, long long yP_rs, int N, int n_d,
+                                                   int n_p, int ncols, double *__restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= ncols) return;
+    const int rhs = col / N, s = col % N;
+    const double *zP = yP + rhs * yP_rs;
+    const double *Cs = C + (size_t)s * n_p * n_d;
+    double yp[NPM];
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) {
+        yp[i] = 0.0;
+        if (i < n_p) {
+            const int P = Ap[(size_t)s * n_p + i];
+            if (P >= 0) yp[i] = zP[P];
+        }
+    }
+    double *Yc = Y + (size_t)col * n_d;
+    for (int j = lane; j < n_d; j += 64) {
+        double v = Yc[j];
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (i < n_p) v += Cs[(size_t)i * n_d + j] * yp[i];
+        Yc[j] = v;
+    }
+}
+
 // ------------------------------------------------------------------ A_p, A_p^T
 __global__ __launch_bounds__(kB) void k_assemble_primal(const int *__restrict__ pull, int maxc,
                                                         const double *__restrict__ cp, int N, int n_p,
@@ -769,29 +863,53 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 // coarse solve on the side stream while the main stream runs the dominant
 // contraction sum_k delta_k F_dd^(k) Lambda; the coarse correction
 // (T_dr Ů_rp^(s)) A_p^T y_P is added after the join, then B_d scatters.
+void combine_coarse_maps(ifeti_ctx *c) {
+    const int npd = c->n_p * c->n_d;
+    IFETI_REQUIRE(c->n_p <= kMaxNp, IFETI_EINVAL, "too many primal dofs per cell");
+    c->Wc.alloc((size_t)c->N * npd);
+    hipLaunchKernelGGL(k_combine_wt, dim3(nblocks((long long)c->N * npd)), dim3(kB), 0, c->stream, c->pi.p, c->WT.p,
+                       c->N, c->K, npd, c->Wc.p);
+    IFETI_HIP(hipGetLastError());
+}
+
+// F̊ lam = B_d [sum_k delta_k F_dd^(k) B_d^T lam + C^T A_p S̊_PP^-1 A_p^T C B_d^T lam]:
+// the coarse branch (restriction, assembly, symmetric coarse solve) runs on the
+// side stream while the main stream runs the dominant contraction; the
+// prolongation is folded into the final scatter.
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
     ensure_work(c, nrhs);
     const int N = c->N, nd = c->n_d, np = c->n_p, K = c->K;
     const int cols = N * nrhs;
-    // B_d^T lam is fused into the staging of both contractions that read it
-    GemmGroup g0;
-    g0.A = c->WT.p; g0.X = lam; g0.xbs = c->L; g0.gcodes = c->g_gather.p; g0.coef = c->pi.p; g0.Kd = nd;
-    g0.K = K;
-    gemm(c, &g0, 1, c->w_c.p, np, 0, np, cols, false, 0, "F_restrict_gemm");
+    const double cmap_bytes = 8.0 * (double)N * np * nd;
+    {
+        Prof prof(c, "F_restrict", 2.0 * (double)cols * np * nd,
+                  cmap_bytes + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
+        if (np <= 8)
+            hipLaunchKernelGGL(k_restrict_c<8>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
+                               c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
+        else
+            hipLaunchKernelGGL(k_restrict_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
+                               c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
+    }
     {
         SideStream side(c);
         op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
         op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
-        op_restrict_primal(c, c->w_yP.p, c->nP, c->w_yp.p, nrhs);
     }
-    GemmGroup g1;
+    GemmGroup g1;  // B_d^T lam fused into the staging
     g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
     g1.K = K;
     gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
     join_side(c);
-    GemmGroup g2;
-    g2.A = c->W.p; g2.X = c->w_yp.p; g2.coef = c->pi.p; g2.Kd = np; g2.ldx = np; g2.K = K;
-    gemm(c, &g2, 1, c->w_Y.p, nd, 0, nd, cols, true, 0, "F_prolong_gemm");
+    {
+        Prof prof(c, "F_prolong", 2.0 * (double)cols * np * nd, cmap_bytes + 16.0 * (double)cols * nd);
+        if (np <= 8)
+            hipLaunchKernelGGL(k_prolong_c<8>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p, c->g_Ap.p,
+                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Y.p);
+        else
+            hipLaunchKernelGGL(k_prolong_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
+                               c->g_Ap.p, c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Y.p);
+    }
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());

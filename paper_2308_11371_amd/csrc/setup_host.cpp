@@ -982,11 +982,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     c->Urp.upload(Urp, c->stream);
     c->UrpT.upload(UrpT, c->stream);
     c->Kinv.upload(Kinv, c->stream);
-    for (auto &cp : c->lp) {
-        (void)hipFree(cp.f32);
-        (void)hipFree(cp.bf16);
-    }
-    c->lp.clear();
+    combine_coarse_maps(c);
     make_lp_copies(c, {{c->Fdd.p, c->Fdd.n}, {c->Sdd.p, c->Sdd.n}, {c->W.p, c->W.n}, {c->WT.p, c->WT.n},
                        {c->UrdT.p, c->UrdT.n}, {c->Urd.p, c->Urd.n}, {c->Urp.p, c->Urp.n}, {c->UrpT.p, c->UrpT.n},
                        {c->Kinv.p, c->Kinv.n}});
