@@ -93,6 +93,47 @@ def cpu_baseline(budget_s: float = 10.0):
                        f"{applies} cell applies in {dt:.1f} s")
 
 
+def timed_solve(ctx, f, d, nrhs, tol, inner_tol, reps=1):
+    import torch
+    ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=200)  # untimed warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=200)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, info
+
+
+def run_forms(ctx, f, d, t_fp64, args):
+    """Precision form (FP32 / BF16 local contractions, FP64 PCG, coarse solve and outer FGMRES) on the
+    same lattice, and the block-RHS form: 32 load cases in one batched solve (FP32 local), each against
+    the plain FP64 solve time per load case."""
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+    res = {"fp64_plain": {"solve_time_s": t_fp64}}
+    for name, prec, itol in (("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6), ("bf16_local", ifeti.IFETI_BF16_LOCAL, 1e-3)):
+        ctx.set_options(precision=prec)
+        t, info = timed_solve(ctx, f, d, 1, args.tol, itol)
+        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
+                     "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
+        log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+    ctx.set_options()
+    prob = latticegen.make("c4")
+    c4 = ifeti.setup(prob)
+    s4 = c4.sizes
+    f4, d4 = c4.get_rhs()
+    c4.set_options(precision=ifeti.IFETI_FP32_LOCAL)
+    t, info = timed_solve(c4, f4, d4, s4.nrhs, args.tol, 1e-6)
+    res["block_rhs_fp32_local"] = {
+        "workload": f"c4: the c2 lattice with {s4.nrhs} seeded right-edge load cases in one batched solve",
+        "nrhs": int(s4.nrhs), "solve_time_s": t, "per_load_case_s": t / s4.nrhs,
+        "vs_fp64_plain_per_load_case": t / s4.nrhs / t_fp64,
+        "max_outer_its": int(max(info["outer_its"])), "max_relres": float(max(info["relres"]))}
+    log(f"form block_rhs: {t:.3f}s for {s4.nrhs} load cases")
+    c4.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +147,9 @@ def main():
     ap.add_argument("--roofline-kernel", default="F_gemm",
                     help="kernel family timed with HIP events during the timed steps")
     ap.add_argument("--all-kernels", action="store_true", help="event-time every kernel family (slower)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision and block-RHS legs")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
+                    help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -116,6 +160,14 @@ def main():
     from paper_2308_11371_amd import ifeti
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 20)) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read, {n * 8} bytes written")
+        del a, c
     prob = latticegen.make(args.config, n_principal=args.n_principal)
     t0 = time.perf_counter()
     ctx = ifeti.setup(prob)
@@ -151,8 +203,9 @@ def main():
     kernels = {k: dict(launches=v["launches"], avg_us=v["total_ms"] * 1e3 / max(v["launches"], 1),
                        share=v["total_ms"] / 1e3 / elapsed) for k, v in sorted(
                            st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:10] if v["total_ms"] > 0}
+    forms = None if args.no_forms else run_forms(ctx, f, d, elapsed / args.steps, args)
     out = {
-        "metric": "cell local-solve applies/s",
+        "metric": "cell local-solve applies/s; solve time to rel. residual 1e-8 vs FP64 plain",
         "value": value,
         "unit": "cell-applies/s",
         "n_gpus": 1,
@@ -177,6 +230,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if forms is not None:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline()
