@@ -93,19 +93,22 @@ typedef struct {
     int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
     int pcg_maxit;          /* iteration cap of the interface PCG inside the preconditioner */
     int timing;             /* 1: time kernel launches with HIP events       */
-    char timing_filter[32]; /* "" : every kernel family; else only this one  */
+    char timing_filter[32]; /* "" : every kernel family; else a comma-separated list of families */
+    int timing_every;       /* time one launch in this many of each family (<= 1: every launch) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts
  * (operations the method needs, minimum HBM traffic of the launch), summed
- * over launches; total_ms is the sum of the HIP-event durations measured on
- * the context stream around each launch (0 unless options.timing = 1). */
+ * over launches; total_ms is the sum of the HIP-event durations of the `timed`
+ * launches (0 unless options.timing = 1); the average launch time is
+ * total_ms / timed. */
 typedef struct {
     char name[32];
     long long launches;
     double total_ms;
     double flops;
     double bytes;
+    long long timed;
 } ifeti_kernel_stat;
 
 enum { IFETI_OP_F = 0, IFETI_OP_MD, IFETI_OP_U, IFETI_OP_UT, IFETI_OP_KINV_ROM, IFETI_OP_A, IFETI_OP_COUNT };

@@ -1,3 +1,4 @@
+#include <algorithm>
 // extern "C" entry points of libifeti (see include/ifeti.h).
 #include <cmath>
 #include <cstring>
@@ -104,6 +105,7 @@ int ifeti_get_stats(ifeti_ctx *c, ifeti_stats *o) {
             ifeti_kernel_stat &d = o->kernels[n++];
             std::strncpy(d.name, k.name.c_str(), sizeof(d.name) - 1);
             d.launches = k.launches;
+            d.timed = k.timed;
             d.total_ms = k.ms;
             d.flops = k.flops;
             d.bytes = k.bytes;
@@ -160,6 +162,7 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         if (!opt->timing) flush_events(c);
         c->opt.timing = opt->timing ? 1 : 0;
         c->opt.timing_filter.assign(opt->timing_filter, strnlen(opt->timing_filter, sizeof(opt->timing_filter)));
+        c->opt.timing_every = std::max(1, opt->timing_every);
         return IFETI_OK;
     });
 }

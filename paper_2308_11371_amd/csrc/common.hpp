@@ -103,14 +103,15 @@ struct Options {
     int fgmres_restart = 60;
     int pcg_maxit = 1000;
     int timing = 0;
-    std::string timing_filter;  // empty: time every kernel family; else only this one
+    std::string timing_filter;  // empty: time every kernel family; else a comma-separated list
+    int timing_every = 1;       // time one launch in this many of each family
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
 // enabled, HIP-event durations recorded on the context stream.
 struct KernelStat {
     std::string name;
-    long long launches = 0;
+    long long launches = 0, timed = 0;
     double ms = 0.0, flops = 0.0, bytes = 0.0;
 };
 struct PendingEvent {
@@ -228,15 +229,23 @@ struct ifeti_ctx {
 
 namespace ifeti {
 // stats.cpp: RAII timing of one launch (flops/bytes always counted)
+// Counts one launch of a kernel family (algorithmic flops / bytes) and, when
+// timing is on for that family, brackets it with HIP events.  With
+// in_packet = true the launcher passes start() / stop() to
+// hipExtLaunchKernelGGL, so the events are stamped by the kernel's own
+// dispatch packet (kernel duration without the marker-packet latency).
 class Prof {
    public:
-    Prof(ifeti_ctx *c, const char *name, double flops, double bytes);
+    Prof(ifeti_ctx *c, const char *name, double flops, double bytes, bool in_packet = false);
     ~Prof();
+    hipEvent_t start() const { return a_; }
+    hipEvent_t stop() const { return b_; }
 
    private:
     ifeti_ctx *c_;
     int id_;
-    hipEvent_t a_ = nullptr;
+    bool in_packet_ = false;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 void flush_events(ifeti_ctx *c);
 void release_events(ifeti_ctx *c);
@@ -286,6 +295,7 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);
+void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);
 void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
@@ -299,8 +309,10 @@ int reduce_blocks(long long n);
 // V_i = Vp[i] when a device pointer table is given, else V + i*vstride
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
               int nrhs, double *out_dev, const double *const *Vp = nullptr);
+// w = a w + cscale * sum_k coef_k V_k (per load case)
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
-               long long n, long long rs, int nrhs, const double *const *Vp = nullptr);
+               long long n, long long rs, int nrhs, const double *const *Vp = nullptr, double cscale = 1.0);
+void inv_sqrt(ifeti_ctx *c, const double *h, double *sc, int n);
 void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs);
 
 // gradient.hip

@@ -25,12 +25,15 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace ifeti {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 struct GemmArgsDev {
     const double *A[2];
@@ -403,19 +406,24 @@ constexpr int kMaxCoefK = 40;
 // PF pairs ahead; partial tiles are summed through LDS by a fixed pairwise
 // tree, so every column's result is independent of the launch shape and of
 // the other columns (bitwise reproducible).
+template <int RT, int CB, int NW>
+struct Pc64Lds {
+    static constexpr int NC = 16 * CB;
+    static constexpr int XW = NC * FXS;
+    static constexpr int RED = (NW / 2) * RT * CB * 256;
+    static constexpr int SX = XW > RED ? XW : RED;
+    static constexpr int SC = kMaxCoefK * NC;
+};
+
 template <int RT, int CB, int PF, int NW>
-__global__ __launch_bounds__(64 * NW) void k_pc64(GemmArgsFrag g) {
+__device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by, double *__restrict__ Xs,
+                                          double *__restrict__ Cs) {
     static_assert((NW & (NW - 1)) == 0, "NW must be a power of two");
     constexpr int NT = 64 * NW;
     constexpr int NC = 16 * CB;
-    constexpr int XW = NC * FXS;
-    constexpr int RED = (NW / 2) * RT * CB * 256;
-    constexpr int SX = XW > RED ? XW : RED;
-    __shared__ double Xs[SX];
-    __shared__ double Cs[kMaxCoefK * NC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int mt0 = blockIdx.y * RT, col0 = blockIdx.x * NC;
+    const int mt0 = by * RT, col0 = bx * NC;
     v4d acc[RT][CB];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -557,9 +565,161 @@ __global__ __launch_bounds__(64 * NW) void k_pc64(GemmArgsFrag g) {
 }
 
 template <int RT, int CB, int PF, int NW>
-void launch_frag(const GemmArgsFrag &a, hipStream_t s) {
+__global__ __launch_bounds__(64 * NW) void k_pc64(GemmArgsFrag g) {
+    using L = Pc64Lds<RT, CB, NW>;
+    __shared__ double Xs[L::SX];
+    __shared__ double Cs[L::SC];
+    pc64_tile<RT, CB, PF, NW>(g, blockIdx.x, blockIdx.y, Xs, Cs);
+}
+
+
+// Large-M variant (operators that do not stay in L2, e.g. the stacked local
+// inverses of (46a)): the NW waves of a workgroup own distinct row tiles
+// (RTW each) of one 16*CB-column block and all of them run the full
+// (principal, k-step pair) sequence, with the column chunk (KCB inner rows)
+// and coefficients shared through LDS; no cross-wave reduction.
+template <int RTW, int CB, int NW, int KCB>
+__global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
+    constexpr int NT = 64 * NW;
+    constexpr int NC = 16 * CB;
+    constexpr int XSB = KCB + 2;
+    constexpr int PF = 2;
+    static_assert(KCB % 8 == 0, "chunk must hold whole fragment pairs");
+    __shared__ double Xs[NC * XSB];
+    __shared__ double Cs[kMaxCoefK * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mt0 = (blockIdx.y * NW + wave) * RTW, col0 = blockIdx.x * NC;
+    v4d acc[RTW][CB];
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    bool rtv[RTW];
+    bool any = false;
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt) {
+        rtv[rt] = mt0 + rt < g.MT;
+        any = any || rtv[rt];
+    }
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const double *__restrict__ Af = g.Af[gi];
+        const double *__restrict__ X = g.X[gi];
+        const double *__restrict__ coef = g.coef[gi];
+        const int *__restrict__ gcodes = g.gcodes[gi];
+        const double *__restrict__ gw = g.gw[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi], KT2 = g.KT2[gi], ldx = g.ldx[gi];
+        const long long xbs = g.xbs[gi];
+        const double scale = g.scale[gi];
+        for (int kk = 0; kk < Kd; kk += KCB) {
+            const int kc = min(KCB, Kd - kk);
+            __syncthreads();
+            for (int e = tid; e < NC * KCB; e += NT) {
+                const int cc = e / KCB, r = e % KCB, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols && r < kc) {
+                    const int cell = col % g.ncells;
+                    const long long rhs = col / g.ncells;
+                    if (gcodes) {
+                        const double *lam = X + rhs * xbs;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int code = gcodes[((size_t)cell * Kd + kk + r) * 2 + u];
+                            if (code == 0) continue;
+                            const int row = (code > 0 ? code : -code) - 1;
+                            const double x = gw ? lam[row] * gw[row] : lam[row];
+                            v += code > 0 ? x : -x;
+                        }
+                    } else {
+                        v = X[rhs * xbs + (size_t)cell * ldx + kk + r];
+                    }
+                }
+                Xs[cc * XSB + r] = v;
+            }
+            for (int e = tid; e < K * NC; e += NT) {
+                const int k = e / NC, cc = e % NC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
+                Cs[e] = v;
+            }
+            __syncthreads();
+            if (!any) continue;  // wave-uniform: this wave's row tiles lie beyond M
+            const int np = (kc + 7) / 8, q0 = kk / 8, ns = K * np;
+            auto load = [&](int s, double2 (&dst)[RTW]) {
+                const int k = s / np, q = s % np;
+#pragma unroll
+                for (int rt = 0; rt < RTW; ++rt)
+                    dst[rt] = rtv[rt] ? reinterpret_cast<const double2 *>(
+                                            Af + (((size_t)k * g.MT + mt0 + rt) * KT2 + q0 + q) * 128)[lane]
+                                      : double2{0.0, 0.0};
+            };
+            double2 ab[PF][RTW];
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (u < ns) load(u, ab[u]);
+            for (int s0 = 0; s0 < ns; s0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int s = s0 + u;
+                    if (s < ns) {
+                        double2 a[RTW];
+#pragma unroll
+                        for (int rt = 0; rt < RTW; ++rt) a[rt] = ab[u][rt];
+                        if (s + PF < ns) load(s + PF, ab[u]);
+                        const int k = s / np, q = s % np;
+                        double cf[CB];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const int r = 4 * (2 * q + j) + lk;
+                            double b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XSB + r] * cf[cb];
+#pragma unroll
+                            for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, b[cb],
+                                                                                       acc[rt][cb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int mt = mt0 + rt, col = col0 + cb * 16 + lr;
+            if (mt >= g.MT || col >= g.ncols) continue;
+            double *ycol = g.Y + (long long)(col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * i + lk;
+                if (row < g.M) ycol[row] = g.accumulate ? ycol[row] + acc[rt][cb][i] : acc[rt][cb][i];
+            }
+        }
+}
+
+template <int RTW, int CB, int NW, int KCB>
+void launch_big(const GemmArgsFrag &a, hipStream_t s, const Prof &prof) {
+    dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RTW * NW - 1) / (RTW * NW)));
+    if (prof.start())
+        hipExtLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(), 0,
+                              a);
+    else
+        hipLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, a);
+}
+
+template <int RT, int CB, int PF, int NW>
+void launch_frag(const GemmArgsFrag &a, hipStream_t s, const Prof &prof) {
     dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RT - 1) / RT));
-    hipLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, a);
+    if (prof.start())
+        hipExtLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(), 0, a);
+    else
+        hipLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, a);
 }
 
 template <int BM, int SPLIT>
@@ -656,7 +816,9 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     double abytes = 0.0;
     for (int i = 0; i < ngroups; ++i) abytes += 8.0 * (double)groups[i].K * M * groups[i].Kd;
     const bool lp_path = lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16;
-    const bool frag_path = !lp_path && abytes <= 4.0 * 1024 * 1024 && Kmax <= kMaxCoefK;
+    const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
+    const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
+    const bool frag_path = !lp_path && Kmax <= kMaxCoefK && (frag_small || M >= 128);
     if (ngather > 0 && !frag_path) {
         // only the fragment kernel stages through the jump codes: gather first, then contract
         IFETI_REQUIRE(ngather == 1, IFETI_EINVAL, "gemm: at most one gathered group");
@@ -740,14 +902,16 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         f.ncols = ncols;
         f.ncells = a.ncells;
         f.accumulate = a.accumulate;
-        Prof prof(c, tag, flops, bytes);
+        Prof prof(c, tag, flops, bytes, true);
         // shapes tuned on gfx950: few rows -> many waves per tile; few inner steps -> tall tiles
-        if (f.MT == 1)
-            launch_frag<1, 1, 2, 16>(f, c->stream);
+        if (frag_big)
+            launch_big<2, 4, 4, 64>(f, c->stream, prof);
+        else if (f.MT == 1)
+            launch_frag<1, 1, 2, 16>(f, c->stream, prof);
         else if (Kdmax <= 16)
-            launch_frag<4, 1, 4, 4>(f, c->stream);
+            launch_frag<4, 1, 4, 4>(f, c->stream, prof);
         else
-            launch_frag<4, 2, 2, 8>(f, c->stream);
+            launch_frag<4, 2, 2, 8>(f, c->stream, prof);
         IFETI_HIP(hipGetLastError());
         return;
     }
@@ -762,5 +926,6 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     }
     IFETI_HIP(hipGetLastError());
 }
+
 
 }  // namespace ifeti

@@ -369,65 +369,84 @@ __global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S
 // fails) and x = R c is written.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// (46b) step 1: H_c = K_rr^(s) R_c for a chunk of KCOL reduced-basis vectors.
+// (46b) step 1: H_c = K_rr^(s) R for a chunk of KCOL reduced-basis vectors.
 // One workgroup per column c; the chunk of R (n_r x KCOL) is staged in LDS
-// (row-major, KCOL contiguous); one thread per (control point a) accumulates
-// the d x KCOL block of H for the rows of a from the cell's stencil values
-// (layout [o][i][k][a], coalesced over a).  H is written as [k][r].
+// (row-major with an odd row stride, plus a zero row that primal dofs map to) with
+// the dof -> r-row map; one thread per control point a accumulates the
+// d x KCOL block of H for the rows of a.  The stencil offsets are unrolled
+// and branch-free: an out-of-range neighbour is clamped onto a itself, whose
+// stencil value for that offset is stored as zero, so every stencil load
+// (layout [o][i][k][a], coalesced over a) is in bounds and independent.
 constexpr int kRomHB = 512;
 
 template <int D, int KCOL>
 __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, const double *__restrict__ Kst,
-                                              const int *__restrict__ r_of_dof, int N, int K, int k0, int n_r,
-                                              int nc, int n_ctrl, int n_off, int p, double *__restrict__ H) {
-    extern __shared__ double Rl[];  // [n_r][KCOL]
-    const int col = blockIdx.x, s = col % N, tid = threadIdx.x;
+                                                  const int *__restrict__ r_of_dof, int N, int K, int k0, int n_r,
+                                                  int nc, int n_ctrl, double *__restrict__ H) {
+    constexpr int P = 2;                   // quadratic B-splines: neighbours within +-2
+    constexpr int W = 2 * P + 1;
+    constexpr int NOFF = D == 2 ? W * W : W * W * W;
+    constexpr int KP = KCOL | 1;           // odd row stride: lanes reading neighbouring rows hit distinct banks
+    extern __shared__ double Rl[];         // [n_r + 1][KP], then int rmap[n_ctrl * D]
+    const int col = blockIdx.x, s = col % N, tid = threadIdx.x, nt = blockDim.x;
+    int *rmap = reinterpret_cast<int *>(Rl + (size_t)(n_r + 1) * KP);
     const double *Rc = R + (size_t)col * K * n_r;
-    const int kc = min(KCOL, K - k0), nt = blockDim.x;
-    for (int e = tid; e < n_r * KCOL; e += nt) {
-        const int kk = e / n_r, r = e % n_r;
-        Rl[r * KCOL + kk] = kk < kc ? Rc[(size_t)(k0 + kk) * n_r + r] : 0.0;
+    const int kc = min(KCOL, K - k0);
+    for (int e = tid; e < (n_r + 1) * KCOL; e += nt) {
+        const int kk = e / (n_r + 1), r = e % (n_r + 1);
+        Rl[r * KP + kk] = (kk < kc && r < n_r) ? Rc[(size_t)(k0 + kk) * n_r + r] : 0.0;
+    }
+    for (int e = tid; e < n_ctrl * D; e += nt) {
+        const int rr = r_of_dof[e];
+        rmap[e] = rr >= 0 ? rr : n_r;
     }
     __syncthreads();
-    const int w = 2 * p + 1;
-    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
+    const double *Ks = Kst + (size_t)s * n_ctrl * NOFF * D * D;
     double *Hc = H + (size_t)col * K * n_r;
     for (int a = tid; a < n_ctrl; a += nt) {
-        int ma[D];
-        int ta = a;
+        int ma[D], stride[D];
+        {
+            int ta = a, st = 1;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            ma[j] = ta % nc;
-            ta /= nc;
+            for (int j = 0; j < D; ++j) {
+                ma[j] = ta % nc;
+                ta /= nc;
+                stride[j] = st;
+                st *= nc;
+            }
         }
         double h[D][KCOL];
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int q = 0; q < KCOL; ++q) h[i][q] = 0.0;
-        for (int o = 0; o < n_off; ++o) {
-            int to = o, b = 0;
+#pragma unroll W
+        for (int o = 0; o < NOFF; ++o) {
+            int b = a;
             bool ok = true;
-            int mb[D];
+            {
+                int to = o;
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                mb[j] = ma[j] + (to % w) - p;
-                to /= w;
-                if (mb[j] < 0 || mb[j] >= nc) ok = false;
+                for (int j = 0; j < D; ++j) {
+                    const int d = to % W - P;
+                    to /= W;
+                    const int m = ma[j] + d;
+                    ok = ok && m >= 0 && m < nc;
+                    b += d * stride[j];
+                }
             }
-            if (!ok) continue;
-#pragma unroll
-            for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+            if (!ok) b = a;  // stencil value stored as zero for this offset
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const int rk = r_of_dof[b * D + k];
-                if (rk < 0) continue;
-                const double *rrow = Rl + rk * KCOL;
+                const double *row = Rl + rmap[b * D + k] * KP;
+                double kv[D];
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const double v = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
+                for (int i = 0; i < D; ++i) kv[i] = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
 #pragma unroll
-                    for (int q = 0; q < KCOL; ++q) h[i][q] += v * rrow[q];
+                for (int q = 0; q < KCOL; ++q) {
+                    const double rq = row[q];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) h[i][q] += kv[i] * rq;
                 }
             }
         }
@@ -715,14 +734,21 @@ __global__ __launch_bounds__(kB) void k_reduce_partials(const double *__restrict
 __global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, long long vstride,
                                                   const double *const *__restrict__ Vp, int nv,
                                                   const double *__restrict__ coef, double a, double *__restrict__ w,
-                                                  long long n, long long rs, int nrhs) {
+                                                  long long n, long long rs, int nrhs, double cscale) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nrhs) return;
     int rhs = (int)(t / n);
     long long i = t % n;
     double acc = a * w[rhs * rs + i];
-    for (int k = 0; k < nv; ++k) acc += coef[rhs * nv + k] * (Vp ? Vp[k] : V + k * vstride)[rhs * rs + i];
+    for (int k = 0; k < nv; ++k)
+        acc += (cscale * coef[rhs * nv + k]) * (Vp ? Vp[k] : V + k * vstride)[rhs * rs + i];
     w[rhs * rs + i] = acc;
+}
+
+// sc[r] = 1 / sqrt(h[r]) (0 for a zero norm)
+__global__ void k_inv_sqrt(const double *__restrict__ h, double *__restrict__ sc, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) sc[t] = h[t] > 0.0 ? 1.0 / sqrt(h[t]) : 0.0;
 }
 
 __global__ __launch_bounds__(kB) void k_scale_copy(const double *__restrict__ x, long long n, long long rs,
@@ -743,8 +769,9 @@ __global__ __launch_bounds__(kB) void k_scale_copy(const double *__restrict__ x,
 SideStream::SideStream(ifeti_ctx *c) : c_(c), main_(c->stream) {
     if (!c->side_stream) {
         IFETI_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-        IFETI_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        IFETI_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        // device-local hand-offs only: no system-scope (host-visibility) fence on these markers
+        IFETI_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence));
+        IFETI_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming | hipEventDisableSystemFence));
     }
     IFETI_HIP(hipEventRecord(c->ev_fork, main_));
     IFETI_HIP(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
@@ -821,6 +848,13 @@ void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *
                        c->n_p, nrhs);
 }
 
+void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale) {
+    const double n = (double)c->nP, nt = (double)c->nT * (c->nT + 1) / 2;
+    Prof prof(c, "coarse_reduce", (double)nrhs * nt * 128.0, 8.0 * (nt * 128.0 + n) * nrhs);
+    hipLaunchKernelGGL(k_sym_reduce, dim3(c->nT, nrhs), dim3(1024), 0, c->stream, c->w_symP.p, c->nP, c->nT, nrhs, y,
+                       y_rs, scale);
+}
+
 void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
                      double scale) {
     if (c->nP == 0) return;
@@ -842,9 +876,7 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
                                    c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
             IFETI_HIP(hipGetLastError());
         }
-        Prof prof(c, "coarse_reduce", (double)nrhs * nt * 128.0, 8.0 * (nt * 128.0 + n) * nrhs);
-        hipLaunchKernelGGL(k_sym_reduce, dim3(c->nT, nrhs), dim3(1024), 0, c->stream, c->w_symP.p, c->nP, c->nT,
-                           nrhs, y, y_rs, scale);
+        coarse_reduce(c, y, y_rs, nrhs, scale);
     } else {
         GemmGroup g;
         g.A = c->SPPinv.p;
@@ -891,14 +923,14 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
             hipLaunchKernelGGL(k_restrict_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
                                c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
     }
+    GemmGroup g1;  // B_d^T lam fused into the staging
+    g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
+    g1.K = K;
     {
         SideStream side(c);
         op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
         op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
     }
-    GemmGroup g1;  // B_d^T lam fused into the staging
-    g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
-    g1.K = K;
     gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
     join_side(c);
     {
@@ -988,9 +1020,9 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     {
         int kcol = 4;
         for (int cand : {8, 12, 16})
-            if ((size_t)nr * cand * 8 <= 100 * 1024 && kcol < K) kcol = cand;
+            if ((size_t)(nr + 1) * (cand | 1) * 8 <= 100 * 1024 && kcol < K) kcol = cand;
         const int nthr = std::min(kRomHB, (R.n_ctrl + 63) / 64 * 64);
-        const size_t lds = (size_t)nr * kcol * sizeof(double);
+        const size_t lds = (size_t)(nr + 1) * (kcol | 1) * sizeof(double) + (size_t)R.n_ctrl * c->dim * sizeof(int);
         IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "cell too large for the LDS-staged reduced local solve");
         const double chunks = (double)((K + kcol - 1) / kcol);
         Prof prof(c, "rom_H", colsd * 2.0 * K * c->nnz_rr,
@@ -1001,7 +1033,7 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     (void)hipFuncSetAttribute((const void *)k_rom_H<DD, KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     (void)hipGetLastError();                                                                                      \
     hipLaunchKernelGGL((k_rom_H<DD, KC>), dim3(cols), dim3(nthr), lds, c->stream, c->w_R.p, c->Kst.p,             \
-                       c->r_of_dof.p, N, K, k0, nr, R.nc, R.n_ctrl, R.n_off, R.p, c->w_H.p);               \
+                       c->r_of_dof.p, N, K, k0, nr, R.nc, R.n_ctrl, c->w_H.p);               \
     } while (0)
             if (c->dim == 2) {
                 if (kcol == 4) IFETI_ROM_H(2, 4);
@@ -1102,10 +1134,15 @@ void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const do
 }
 
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
-               long long n, long long rs, int nrhs, const double *const *Vp) {
+               long long n, long long rs, int nrhs, const double *const *Vp, double cscale) {
     Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 2) * nrhs);
     hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, Vp, nv, coef_dev, a, w,
-                       n, rs, nrhs);
+                       n, rs, nrhs, cscale);
+    IFETI_HIP(hipGetLastError());
+}
+
+void inv_sqrt(ifeti_ctx *c, const double *h, double *sc, int n) {
+    hipLaunchKernelGGL(k_inv_sqrt, dim3((n + 255) / 256), dim3(256), 0, c->stream, h, sc, n);
     IFETI_HIP(hipGetLastError());
 }
 

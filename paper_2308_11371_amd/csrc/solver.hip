@@ -341,6 +341,8 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     // Krylov blocks are allocated as the iteration needs them (memory ~ iterations used x load cases)
     std::vector<std::unique_ptr<DevBuf<double>>> Vb, Zb;
     std::vector<const double *> hVp, hZp;
+    hVp.reserve(m + 2);  // stable storage: the pointer-table uploads below read it asynchronously
+    hZp.reserve(m + 2);
     DevBuf<const double *> dVp, dZp;
     dVp.alloc(m + 1);
     dZp.alloc(m + 1);
@@ -349,14 +351,17 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         blocks.emplace_back(new DevBuf<double>());
         blocks.back()->alloc((size_t)ns * nrhs);
         hp.push_back(blocks.back()->p);
-        IFETI_HIP(hipMemcpyAsync(dp.p, hp.data(), hp.size() * sizeof(double *), hipMemcpyHostToDevice, s));
-        IFETI_HIP(hipStreamSynchronize(s));
+        const size_t k = hp.size() - 1;  // only the new entry: earlier ones are already on the device
+        IFETI_HIP(hipMemcpyAsync(dp.p + k, hp.data() + k, sizeof(double *), hipMemcpyHostToDevice, s));
         return blocks.back()->p;
     };
-    DevBuf<double> w, coef, tu, tL, tL2, tu2, hdev;
+    DevBuf<double> w, coef, tu, tL, tL2, tu2, hdev, hall, scd;
     w.alloc((size_t)ns * nrhs);
     hdev.alloc((size_t)(m + 1) * nrhs + 16);
     coef.alloc((size_t)(m + 1) * nrhs + 16);
+    const size_t hstride = (size_t)(m + 1) * nrhs;
+    hall.alloc(2 * hstride + nrhs);  // [h pass 1 | h pass 2 | ||w||^2]
+    scd.alloc(nrhs);
     double *V0 = new_block(Vb, hVp, dVp);
     // b = (f, d) packed into V_0 (unnormalised)
     hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, V0, nrhs);
@@ -396,25 +401,24 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
             break;
         }
         apply_A(c, Zj, w.p, nrhs);
-        // classical Gram-Schmidt, twice
+        // classical Gram-Schmidt, twice, with the projections kept on the device; the next basis
+        // vector is normalised on the device and the host reads the Hessenberg column once
         for (int pass = 0; pass < 2; ++pass) {
-            multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hdev.p, dVp.p);
-            std::vector<double> &hh = pass == 0 ? h1 : h2;
-            IFETI_HIP(hipMemcpyAsync(hh.data(), hdev.p, (size_t)(j + 1) * nrhs * sizeof(double),
-                                     hipMemcpyDeviceToHost, s));
-            IFETI_HIP(hipStreamSynchronize(s));
-            std::vector<double> neg((size_t)(j + 1) * nrhs);
-            for (size_t t = 0; t < neg.size(); ++t) neg[t] = -hh[t];
-            IFETI_HIP(hipMemcpyAsync(coef.p, neg.data(), neg.size() * sizeof(double), hipMemcpyHostToDevice, s));
-            multiaxpy(c, nullptr, 0, j + 1, coef.p, 1.0, w.p, ns, ns, nrhs, dVp.p);
+            double *hp = hall.p + pass * hstride;
+            multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hp, dVp.p);
+            multiaxpy(c, nullptr, 0, j + 1, hp, 1.0, w.p, ns, ns, nrhs, dVp.p, -1.0);
         }
-        multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hdev.p);
-        IFETI_HIP(hipMemcpyAsync(hn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hall.p + 2 * hstride);
+        inv_sqrt(c, hall.p + 2 * hstride, scd.p, nrhs);
+        double *Vn = new_block(Vb, hVp, dVp);
+        scale_copy(c, w.p, ns, ns, scd.p, Vn, nrhs);
+        IFETI_HIP(hipMemcpyAsync(h1.data(), hall.p, (size_t)(j + 1) * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipMemcpyAsync(h2.data(), hall.p + hstride, (size_t)(j + 1) * nrhs * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipMemcpyAsync(hn.data(), hall.p + 2 * hstride, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
         IFETI_HIP(hipStreamSynchronize(s));
-        std::vector<double> sc(nrhs);
         for (int r = 0; r < nrhs; ++r) {
             double hj1 = std::sqrt(hn[r]);
-            sc[r] = hj1 > 0 ? 1.0 / hj1 : 0.0;
             if (done[r]) continue;
             std::vector<double> &Hr = H[r];
             for (int i = 0; i <= j; ++i) Hr[(size_t)i * m + j] = h1[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
@@ -435,9 +439,6 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
             kdim[r] = j + 1;
             if (std::fabs(g[r][j + 1]) <= tol * beta[r] || hj1 == 0.0) done[r] = 1;
         }
-        IFETI_HIP(hipMemcpyAsync(coef.p, sc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        double *Vn = new_block(Vb, hVp, dVp);
-        scale_copy(c, w.p, ns, ns, coef.p, Vn, nrhs);
     }
     // x = sum_i y_i Z_i per load case
     int kmax = 0;

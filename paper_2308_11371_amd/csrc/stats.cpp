@@ -1,4 +1,5 @@
 // Kernel statistics and HIP-event timing of individual launches.
+#include <algorithm>
 #include <cstring>
 
 #include "common.hpp"
@@ -23,35 +24,52 @@ static hipEvent_t get_event(ifeti_ctx *c) {
     return e;
 }
 
-Prof::Prof(ifeti_ctx *c, const char *name, double flops, double bytes) : c_(c), id_(stat_id(c, name)) {
+// timing filter: empty = every family, else a comma-separated list of family names
+static bool filter_match(const std::string &filter, const char *name) {
+    if (filter.empty()) return true;
+    const size_t n = std::strlen(name);
+    size_t p = 0;
+    while (p <= filter.size()) {
+        size_t e = filter.find(',', p);
+        if (e == std::string::npos) e = filter.size();
+        if (e - p == n && filter.compare(p, n, name) == 0) return true;
+        p = e + 1;
+    }
+    return false;
+}
+
+Prof::Prof(ifeti_ctx *c, const char *name, double flops, double bytes, bool in_packet)
+    : c_(c), id_(stat_id(c, name)), in_packet_(in_packet) {
     KernelStat &k = c->kstats[id_];
     k.launches += 1;
     k.flops += flops;
     k.bytes += bytes;
-    if (c->opt.timing && (c->opt.timing_filter.empty() || c->opt.timing_filter == name)) {
+    if (c->opt.timing && filter_match(c->opt.timing_filter, name) &&
+        (k.launches - 1) % std::max(1, c->opt.timing_every) == 0) {
+        k.timed += 1;
         a_ = get_event(c);
-        IFETI_HIP(hipEventRecord(a_, c->stream));
+        b_ = get_event(c);
+        if (!in_packet_) IFETI_HIP(hipEventRecord(a_, c->stream));
     }
 }
 
 Prof::~Prof() {
     if (!a_) return;
-    hipEvent_t b = nullptr;
-    try {
-        b = get_event(c_);
-    } catch (...) {
-        return;
+    if (in_packet_ || hipEventRecord(b_, c_->stream) == hipSuccess) c_->pending.push_back(PendingEvent{id_, a_, b_});
+    if (c_->pending.size() > 20000) {
+        try {
+            flush_events(c_);
+        } catch (...) {
+        }
     }
-    if (hipEventRecord(b, c_->stream) == hipSuccess) c_->pending.push_back(PendingEvent{id_, a_, b});
-    if (c_->pending.size() > 20000) flush_events(c_);
 }
 
 void flush_events(ifeti_ctx *c) {
     if (c->pending.empty()) return;
-    IFETI_HIP(hipStreamSynchronize(c->stream));
     for (auto &p : c->pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) c->kstats[p.id].ms += ms;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
+            c->kstats[p.id].ms += ms;
         c->event_pool.push_back(p.a);
         c->event_pool.push_back(p.b);
     }

@@ -43,12 +43,13 @@ class Sizes(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int),
-                ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32)]
+                ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32),
+                ("timing_every", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double),
-                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double), ("timed", ctypes.c_longlong)]
 
 
 OP_NAMES = ("F", "MD", "U", "Ut", "Kinv_rom", "A")
@@ -175,8 +176,9 @@ class Context:
         return s
 
     def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
-                    timing_filter=""):
-        o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31])
+                    timing_filter="", timing_every=1):
+        o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
+                    timing_every)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
 
     def stats(self) -> dict:
@@ -185,7 +187,8 @@ class Context:
         kern = {}
         for i in range(s.n_kernels):
             k = s.kernels[i]
-            kern[k.name.decode()] = dict(launches=k.launches, total_ms=k.total_ms, flops=k.flops, bytes=k.bytes)
+            kern[k.name.decode()] = dict(launches=k.launches, timed=k.timed, total_ms=k.total_ms, flops=k.flops,
+                                         bytes=k.bytes)
         return dict(applies={n: s.applies[i] for i, n in enumerate(OP_NAMES)}, pcg_iterations=s.pcg_iterations,
                     fgmres_iterations=s.fgmres_iterations, kernels=kern)
 
