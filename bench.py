@@ -57,6 +57,30 @@ def roofline_of(kstats: dict, families):
     return dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS, **common)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pc64_MD_gemm_c2_fp64_hbm_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2308_11371_amd", "csrc", "gemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("source_sha256") != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(budget_s: float = 10.0):
     """The CPU oracle on a bounded sample of the same workload.
 
@@ -212,6 +236,8 @@ def main():
     applies = sum(st["applies"][op] for op in CELL_OPS) * s.N
     value = applies / elapsed
     roof = roofline_of(st["kernels"], args.roofline_kernel.split(","))
+    if args.roofline_kernel == "MD_gemm":
+        roof["traffic"] = measured_traffic()
     kernels = {k: dict(launches=v["launches"], timed=v["timed"], avg_us=v["total_ms"] * 1e3 / max(v["timed"], 1),
                        share=v["total_ms"] / max(v["timed"], 1) * v["launches"] / 1e3 / elapsed) for k, v in sorted(
                            st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:10] if v["total_ms"] > 0}

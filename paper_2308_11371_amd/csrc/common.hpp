@@ -179,7 +179,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> Urp;          // [k][n_r][n_p]
     ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
     ifeti::DevBuf<double> Wc;           // [s][n_p][n_d] per-cell sum_k pi_sk (T_dr U_rp^(k))^T
-    ifeti::DevBuf<double> Kinv;         // [k][n_r][n_r] stacked
+    ifeti::DevBuf<double> Kinv;         // [n_r][k][n_r]: row r*K + k is row r of K_rr^(sigma_k)^-1
     ifeti::DevBuf<double> SPPinv;       // [nP][nP]
     // lower-triangle 64x64 tiles of SPPinv, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
     ifeti::DevBuf<double> SPPt;

@@ -363,21 +363,21 @@ __global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S
 
 // ------------------------------------------------------------------ reduced local solve (46)
 // Column c = rhs*N + s.  R_c holds the K reduced-basis vectors
-// K_rr^(sigma_k)^-1 v (n_r x K, vector k contiguous).  The Gram matrix
+// K_rr^(sigma_k)^-1 v as [r][k] (the K values of one row contiguous).  The Gram matrix
 // G = R^T K_rr^(s) R uses the cell's own stencil values; G c = R^T v is solved
 // by Cholesky (symmetric pseudo-inverse with a 1e-13 relative cut if a pivot
 // fails) and x = R c is written.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // (46b) step 1: H_c = K_rr^(s) R for a chunk of KCOL reduced-basis vectors.
-// One workgroup per column c; the chunk of R (n_r x KCOL) is staged in LDS
+// One workgroup per column c; the chunk of R (n_r x KCOL, from the [r][k] layout) is staged in LDS
 // (row-major with an odd row stride, plus a zero row that primal dofs map to) with
 // the dof -> r-row map; one thread per control point a accumulates the
 // d x KCOL block of H for the rows of a.  The stencil offsets are unrolled
 // and branch-free: an out-of-range neighbour is clamped onto a itself, whose
 // stencil value for that offset is stored as zero, so every stencil load
 // (layout [o][i][k][a], coalesced over a) is in bounds and independent.
-constexpr int kRomHB = 512;
+constexpr int kRomHB = 1024;
 
 template <int D, int KCOL>
 __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, const double *__restrict__ Kst,
@@ -393,8 +393,8 @@ __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, 
     const double *Rc = R + (size_t)col * K * n_r;
     const int kc = min(KCOL, K - k0);
     for (int e = tid; e < (n_r + 1) * KCOL; e += nt) {
-        const int kk = e / (n_r + 1), r = e % (n_r + 1);
-        Rl[r * KP + kk] = (kk < kc && r < n_r) ? Rc[(size_t)(k0 + kk) * n_r + r] : 0.0;
+        const int r = e / KCOL, kk = e % KCOL;
+        Rl[r * KP + kk] = (kk < kc && r < n_r) ? Rc[(size_t)r * K + k0 + kk] : 0.0;
     }
     for (int e = tid; e < n_ctrl * D; e += nt) {
         const int rr = r_of_dof[e];
@@ -403,7 +403,9 @@ __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, 
     __syncthreads();
     const double *Ks = Kst + (size_t)s * n_ctrl * NOFF * D * D;
     double *Hc = H + (size_t)col * K * n_r;
-    for (int a = tid; a < n_ctrl; a += nt) {
+    double hsave[D][KCOL];
+    int arow = -1;
+    for (int a = tid; a < n_ctrl; a += nt) {  // one control point per thread (blockDim >= n_ctrl)
         int ma[D], stride[D];
         {
             int ta = a, st = 1;
@@ -450,14 +452,26 @@ __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, 
                 }
             }
         }
+        // park this control point's rows until every thread has finished reading R
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int q = 0; q < KCOL; ++q) hsave[i][q] = h[i][q];
+        arow = a;
+    }
+    __syncthreads();  // R no longer needed: reuse its LDS rows for H ([r][KP])
+    if (arow >= 0)
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const int ri = r_of_dof[a * D + i];
+            const int ri = r_of_dof[arow * D + i];
             if (ri < 0) continue;
 #pragma unroll
-            for (int q = 0; q < KCOL; ++q)
-                if (q < kc) Hc[(size_t)(k0 + q) * n_r + ri] = h[i][q];
+            for (int q = 0; q < KCOL; ++q) Rl[ri * KP + q] = hsave[i][q];
         }
+    __syncthreads();
+    for (int e = tid; e < n_r * KCOL; e += nt) {  // coalesced: [r][k0 .. k0+kc) of H
+        const int r = e / KCOL, kk = e % KCOL;
+        if (kk < kc) Hc[(size_t)r * K + k0 + kk] = Rl[r * KP + kk];
     }
 }
 
@@ -581,8 +595,8 @@ __global__ __launch_bounds__(64 * WPB) void k_rom_gram(const double *__restrict_
 #pragma unroll
             for (int a = 0; a < KB; ++a) {
                 const int k1 = 16 * a + lr;
-                af[a] = (rin && k1 < K) ? Rc[(size_t)k1 * n_r + r] : 0.0;
-                bf[a] = !rin ? 0.0 : (k1 < K ? Hc[(size_t)k1 * n_r + r] : (k1 == K ? v[r] : 0.0));
+                af[a] = (rin && k1 < K) ? Rc[(size_t)r * K + k1] : 0.0;
+                bf[a] = !rin ? 0.0 : (k1 < K ? Hc[(size_t)r * K + k1] : (k1 == K ? v[r] : 0.0));
             }
 #pragma unroll
             for (int a = 0; a < KB; ++a)
@@ -612,7 +626,7 @@ __global__ __launch_bounds__(64 * WPB) void k_rom_gram(const double *__restrict_
         double *x = xR + rhs * x_rs + (size_t)s * n_r;
         for (int r = lane; r < n_r; r += 64) {
             double t = 0.0;
-            for (int k = 0; k < K; ++k) t += Rc[(size_t)k * n_r + r] * cv[k];
+            for (int k = 0; k < K; ++k) t += Rc[(size_t)r * K + k] * cv[k];
             x[r] = t;
         }
     }
@@ -1009,7 +1023,8 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs) {
     const int N = c->N, nr = c->n_r, K = c->K;
     IFETI_REQUIRE(K <= kMaxK, IFETI_EINVAL, "reduced local solve supports at most 40 principal cells");
-    // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the stacked explicit inverses
+    // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
+    // column comes out as [r][k]
     GemmGroup g;
     g.A = c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
     gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, "rom_R_gemm");
@@ -1021,7 +1036,8 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
         int kcol = 4;
         for (int cand : {8, 12, 16})
             if ((size_t)(nr + 1) * (cand | 1) * 8 <= 100 * 1024 && kcol < K) kcol = cand;
-        const int nthr = std::min(kRomHB, (R.n_ctrl + 63) / 64 * 64);
+        const int nthr = (R.n_ctrl + 63) / 64 * 64;
+        IFETI_REQUIRE(nthr <= kRomHB, IFETI_EINVAL, "reduced local solve: too many control points per cell");
         const size_t lds = (size_t)(nr + 1) * (kcol | 1) * sizeof(double) + (size_t)R.n_ctrl * c->dim * sizeof(int);
         IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "cell too large for the LDS-staged reduced local solve");
         const double chunks = (double)((K + kcol - 1) / kcol);

@@ -956,7 +956,8 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
         const Principal &P = bank[k];
         std::copy(P.Fdd.begin(), P.Fdd.end(), &Fdd[(size_t)k * nd * nd]);
         std::copy(P.Sdd.begin(), P.Sdd.end(), &Sdd[(size_t)k * nd * nd]);
-        std::copy(P.Kinv.begin(), P.Kinv.end(), &Kinv[(size_t)k * nr * nr]);
+        for (int r = 0; r < nr; ++r)  // interleaved rows r*K + k: reduced bases come out as [r][k]
+            std::copy(&P.Kinv[(size_t)r * nr], &P.Kinv[(size_t)(r + 1) * nr], &Kinv[((size_t)r * K + k) * nr]);
         std::copy(P.Urp.begin(), P.Urp.end(), &Urp[(size_t)k * nr * np]);
         for (int q = 0; q < nd; ++q)
             for (int a = 0; a < np; ++a) {

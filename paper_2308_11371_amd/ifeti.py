@@ -220,7 +220,8 @@ class Context:
             self.h, int(n_principal), float(tol_rb),
             pin.ctypes.data_as(ctypes.c_void_p) if pin is not None else None,
             pout.ctypes.data_as(ctypes.c_void_p), _ptr(theta_out) if theta_out is not None else None))
-        return pout[:self.sizes.K].copy()
+        self.sigma = pout[:self.sizes.K].copy()
+        return self.sigma.copy()
 
     def get_coefficients(self):
         s = self.sizes
