@@ -219,7 +219,7 @@ struct ifeti_ctx {
     std::vector<hipEvent_t> event_pool;
 
     // ---- work buffers
-    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_x, w_tmpL, w_tmpU;
+    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_Yc, w_x, w_tmpL, w_tmpU;
     ifeti::DevBuf<double> w_red;        // reduction partials
     ifeti::DevBuf<double> pcg_r, pcg_z, pcg_p, pcg_q, pcg_st, pcg_pa, pcg_pb, pcg_pc;  // interface PCG state
     ifeti::DevBuf<int> pcg_ist;
@@ -285,7 +285,8 @@ void join_side(ifeti_ctx *c);
 void ensure_work(ifeti_ctx *c, int nrhs);
 void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights);
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
-                int nrhs, bool weights, const double *dot_w = nullptr, double *dot_part = nullptr);
+                int nrhs, bool weights, const double *dot_w = nullptr, double *dot_part = nullptr,
+                const double *Y2 = nullptr);
 void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long long b_rs, double sgn, double *zP,
                         long long z_rs, int nrhs);
 void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs);

@@ -66,7 +66,8 @@ __global__ __launch_bounds__(kB) void k_scatter(const int *__restrict__ sl, cons
 // owns the contiguous chunk b of the L multipliers of its load case and writes
 // its partial sum of out . w (tree-reduced in a fixed order).
 __global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, const double *__restrict__ Dw,
-                                                    const double *__restrict__ Y, int y_ld, int y_off, long long y_rs,
+                                                    const double *__restrict__ Y, const double *__restrict__ Y2,
+                                                    int y_ld, int y_off, long long y_rs,
                                                     double *__restrict__ out, long long out_rs, int L, int n_d,
                                                     int weights, const double *__restrict__ w, int nblk,
                                                     double *__restrict__ part) {
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, 
     const int chunk = (L + nblk - 1) / nblk;
     const int i0 = b * chunk, i1 = min(L, i0 + chunk);
     const double *y = Y + rhs * y_rs;
+    const double *y2 = Y2 ? Y2 + rhs * y_rs : nullptr;
     double acc = 0.0;
     for (int l = i0 + tid; l < i1; l += kB) {
         double v = 0.0;
@@ -84,13 +86,15 @@ __global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, 
             if (code == 0) continue;
             int e = (code > 0 ? code : -code) - 1;
             int s = e / n_d, j = e % n_d;
-            double x = y[(size_t)s * y_ld + y_off + j];
+            const size_t at = (size_t)s * y_ld + y_off + j;
+            double x = y2 ? y[at] + y2[at] : y[at];
             v += code > 0 ? x : -x;
         }
         if (weights) v *= Dw[l];
         out[rhs * out_rs + l] = v;
-        acc += v * w[rhs * out_rs + l];
+        if (w) acc += v * w[rhs * out_rs + l];
     }
+    if (!part) return;  // uniform
     sh[tid] = acc;
     __syncthreads();
     for (int off = kB / 2; off > 0; off >>= 1) {
@@ -162,13 +166,13 @@ __global__ __launch_bounds__(256) void k_restrict_c(const double *__restrict__ C
     }
 }
 
-// Y_s += C_s^T y_P[A_p(s)] for column (rhs, s): one wave per column, lanes
+// Y_s (+)= C_s^T y_P[A_p(s)] for column (rhs, s): one wave per column, lanes
 // over the cell's dual rows (coalesced rows of C_s); the n_p primal values of
 // the cell are wave-uniform.
 template <int NPM>
 __global__ __launch_bounds__(256) void k_prolong_c(const double *__restrict__ C, const int *__restrict__ Ap,
                                                    const double *__restrict__ yP, long long yP_rs, int N, int n_d,
-                                                   int n_p, int ncols, double *__restrict__ Y) {
+                                                   int n_p, int ncols, double *__restrict__ Y, int accumulate) {
     const int lane = threadIdx.x & 63;
     const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (col >= ncols) return;
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(256) void k_prolong_c(const double *__restrict__ C,
     }
     double *Yc = Y + (size_t)col * n_d;
     for (int j = lane; j < n_d; j += 64) {
-        double v = Yc[j];
+        double v = accumulate ? Yc[j] : 0.0;
 #pragma unroll
         for (int i = 0; i < NPM; ++i)
             if (i < n_p) v += Cs[(size_t)i * n_d + j] * yp[i];
@@ -809,6 +813,7 @@ void ensure_work(ifeti_ctx *c, int nrhs) {
     hipStream_t s = c->stream;
     c->w_Lam.ensure(cols * std::max(c->n_d, c->n_p), s);
     c->w_Y.ensure(cols * c->n_d, s);
+    c->w_Yc.ensure(cols * c->n_d, s);
     c->w_c.ensure(cols * c->n_p, s);
     c->w_yp.ensure(cols * c->n_p, s);
     c->w_zP.ensure((size_t)std::max(c->nP, 1) * nrhs, s);
@@ -830,14 +835,15 @@ void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, i
 int dot_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(1024, (n + 1023) / 1024)); }
 
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
-                int nrhs, bool weights, const double *dot_w, double *dot_part) {
+                int nrhs, bool weights, const double *dot_w, double *dot_part, const double *Y2) {
     long long n = (long long)c->L * nrhs;
-    if (dot_w) {
+    if (dot_w || Y2) {
         const int nblk = dot_blocks(c->L);
         Prof prof(c, "scatter_dot", 2.0 * (double)n,
                   16.0 * (double)n + 8.0 * (double)c->N * c->n_d * nrhs + 8.0 * (double)c->L);
         hipLaunchKernelGGL(k_scatter_dot, dim3(nblk, nrhs), dim3(kB), 0, c->stream, c->g_scatter.p, c->g_Dw.p, Y,
-                           y_ld, y_off, y_rs, out, out_rs, c->L, c->n_d, weights ? 1 : 0, dot_w, nblk, dot_part);
+                           Y2, y_ld, y_off, y_rs, out, out_rs, c->L, c->n_d, weights ? 1 : 0, dot_w, nblk,
+                           dot_w ? dot_part : nullptr);
         return;
     }
     Prof prof(c, "scatter", 0.0, 8.0 * (double)n + 8.0 * (double)c->N * c->n_d * nrhs + 8.0 * (double)c->L);
@@ -928,6 +934,14 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
     const int cols = N * nrhs;
     const double cmap_bytes = 8.0 * (double)N * np * nd;
     {
+        // the dominant contraction runs beside the coarse branch, into its own buffer
+        SideStream side(c);
+        GemmGroup g1;  // B_d^T lam fused into the staging
+        g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
+        g1.K = K;
+        gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
+    }
+    {
         Prof prof(c, "F_restrict", 2.0 * (double)cols * np * nd,
                   cmap_bytes + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
         if (np <= 8)
@@ -937,26 +951,19 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
             hipLaunchKernelGGL(k_restrict_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
                                c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
     }
-    GemmGroup g1;  // B_d^T lam fused into the staging
-    g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
-    g1.K = K;
+    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
+    op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
     {
-        SideStream side(c);
-        op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
-        op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
-    }
-    gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
-    join_side(c);
-    {
-        Prof prof(c, "F_prolong", 2.0 * (double)cols * np * nd, cmap_bytes + 16.0 * (double)cols * nd);
+        Prof prof(c, "F_prolong", 2.0 * (double)cols * np * nd, cmap_bytes + 8.0 * (double)cols * nd);
         if (np <= 8)
             hipLaunchKernelGGL(k_prolong_c<8>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p, c->g_Ap.p,
-                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Y.p);
+                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
         else
             hipLaunchKernelGGL(k_prolong_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
-                               c->g_Ap.p, c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Y.p);
+                               c->g_Ap.p, c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
     }
-    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part);
+    join_side(c);
+    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, c->w_Yc.p);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
 }
