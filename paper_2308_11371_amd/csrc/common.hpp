@@ -193,10 +193,10 @@ struct ifeti_ctx {
         void *f32 = nullptr, *bf16 = nullptr;
     };
     std::vector<LPCopy> lp;
-    struct FragCopy {                   // a bank array in FP64 MFMA-fragment order, per (M, Kd, K) view
+    struct FragCopy {                   // a bank array in MFMA-fragment order, per (M, Kd, K, element type) view
         const double *src = nullptr;
-        int M = 0, Kd = 0, K = 0;
-        double *frag = nullptr;
+        int M = 0, Kd = 0, K = 0, kind = 0;  // kind: IFETI_FP64 / IFETI_FP32_LOCAL / IFETI_BF16_LOCAL
+        void *frag = nullptr;
     };
     std::vector<FragCopy> frag;
     void free_copies() {
@@ -219,7 +219,7 @@ struct ifeti_ctx {
     std::vector<hipEvent_t> event_pool;
 
     // ---- work buffers
-    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_Yc, w_x, w_tmpL, w_tmpU;
+    ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_Yc, w_split, w_x, w_tmpL, w_tmpU;
     ifeti::DevBuf<double> w_red;        // reduction partials
     ifeti::DevBuf<double> pcg_r, pcg_z, pcg_p, pcg_q, pcg_st, pcg_pa, pcg_pb, pcg_pc;  // interface PCG state
     ifeti::DevBuf<int> pcg_ist;

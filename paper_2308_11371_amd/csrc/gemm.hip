@@ -393,6 +393,8 @@ struct GemmArgsFrag {
     double *Y;
     long long ybs;
     int ldy, M, MT, ncols, ncells, accumulate;
+    int ksplit;    // >1: inner range split over blockIdx.z, partials to `part` ([z][col][M])
+    double *part;
 };
 
 constexpr int FKC = 128;      // inner rows of the cell vectors staged per chunk
@@ -578,12 +580,11 @@ __global__ __launch_bounds__(64 * NW) void k_pc64(GemmArgsFrag g) {
 // (RTW each) of one 16*CB-column block and all of them run the full
 // (principal, k-step pair) sequence, with the column chunk (KCB inner rows)
 // and coefficients shared through LDS; no cross-wave reduction.
-template <int RTW, int CB, int NW, int KCB>
+template <int RTW, int CB, int NW, int KCB, int PF>
 __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
     constexpr int NT = 64 * NW;
     constexpr int NC = 16 * CB;
     constexpr int XSB = KCB + 2;
-    constexpr int PF = 2;
     static_assert(KCB % 8 == 0, "chunk must hold whole fragment pairs");
     __shared__ double Xs[NC * XSB];
     __shared__ double Cs[kMaxCoefK * NC];
@@ -611,8 +612,12 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
         const int Kd = g.Kd[gi], K = g.K[gi], KT2 = g.KT2[gi], ldx = g.ldx[gi];
         const long long xbs = g.xbs[gi];
         const double scale = g.scale[gi];
-        for (int kk = 0; kk < Kd; kk += KCB) {
-            const int kc = min(KCB, Kd - kk);
+        // inner range of this split (whole chunks), all of it when ksplit = 1
+        const int nsplit = g.ksplit > 1 ? g.ksplit : 1;
+        const int per = ((Kd + KCB * nsplit - 1) / (KCB * nsplit)) * KCB;
+        const int kbeg = blockIdx.z * per, kend = min(Kd, kbeg + per);
+        for (int kk = kbeg; kk < kend; kk += KCB) {
+            const int kc = min(KCB, kend - kk);
             __syncthreads();
             for (int e = tid; e < NC * KCB; e += NT) {
                 const int cc = e / KCB, r = e % KCB, col = col0 + cc;
@@ -694,6 +699,15 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
         for (int cb = 0; cb < CB; ++cb) {
             const int mt = mt0 + rt, col = col0 + cb * 16 + lr;
             if (mt >= g.MT || col >= g.ncols) continue;
+            if (g.part) {
+                double *pcol = g.part + ((size_t)blockIdx.z * g.ncols + col) * g.M;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = mt * 16 + 4 * i + lk;
+                    if (row < g.M) pcol[row] = acc[rt][cb][i];
+                }
+                continue;
+            }
             double *ycol = g.Y + (long long)(col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -703,14 +717,225 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
         }
 }
 
-template <int RTW, int CB, int NW, int KCB>
+// sum of the split-K partials in split order, into Y
+__global__ __launch_bounds__(256) void k_split_reduce(const double *__restrict__ part, int ksplit, int ncols, int M,
+                                                      int ncells, double *__restrict__ Y, long long ybs, int ldy,
+                                                      int accumulate) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)ncols * M) return;
+    const int col = (int)(t / M), row = (int)(t % M);
+    double v = part[t];
+    for (int z = 1; z < ksplit; ++z) v += part[(size_t)z * ncols * M + t];
+    double *y = Y + (long long)(col / ncells) * ybs + (size_t)(col % ncells) * ldy + row;
+    *y = accumulate ? *y + v : v;
+}
+
+// ---------------------------------------------------------------- precision form, large M
+// FP32 / BF16 counterpart of k_pc64_big.  The operator is copied once into
+// 16-byte fragment units: FP32 — lane l holds rows mt*16 + l%16 and inner
+// indices (4u + j)*4 + l/16, j = 0..3 (four 16x16x4 MFMAs); BF16 — inner
+// indices 32u + 8(l/16) + e, e = 0..7 (one 16x16x32 MFMA).  Cell vectors are
+// staged in LDS as FP32 and scaled by the coefficients as they are fed;
+// accumulation in FP32, result written in FP64.
+template <typename T>
+struct LpUnit;
+template <>
+struct LpUnit<float> {
+    static constexpr int KPF = 16, U = 4;
+};
+template <>
+struct LpUnit<__bf16> {
+    static constexpr int KPF = 32, U = 8;
+};
+
+template <typename T>
+__global__ void k_to_frag_lp(const double *__restrict__ A, int M, int Kd, int K, int MT, int QU, T *__restrict__ F) {
+    constexpr int U = LpUnit<T>::U;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)K * MT * QU * 64 * U;
+    if (t >= total) return;
+    const int u = (int)(t % U), lane = (int)((t / U) % 64);
+    long long rest = t / (U * 64);
+    const int qu = (int)(rest % QU);
+    rest /= QU;
+    const int mt = (int)(rest % MT), k = (int)(rest / MT);
+    const int row = mt * 16 + (lane & 15);
+    const int inner = U == 4 ? (4 * qu + u) * 4 + (lane >> 4) : 32 * qu + 8 * (lane >> 4) + u;
+    F[t] = (row < M && inner < Kd) ? (T)(float)A[(size_t)k * M * Kd + (size_t)row * Kd + inner] : (T)0.f;
+}
+
+struct GemmArgsFragLP {
+    int ksplit;    // inner-range splits over blockIdx.z (0/1: none)
+    const void *Af[2];
+    const double *X[2];
+    const double *coef[2];
+    const int *gcodes[2];
+    const double *gw[2];
+    int Kd[2], ldx[2], K[2], QU[2];
+    long long xbs[2];
+    double scale[2];
+    int ngroups;
+    double *Y;
+    long long ybs;
+    int ldy, M, MT, ncols, ncells, accumulate;
+};
+
+template <typename T, int RTW, int CB, int NW, int KCB>
+__global__ __launch_bounds__(64 * NW) void k_pclp_big(GemmArgsFragLP g) {
+    constexpr bool BF = sizeof(T) == 2;
+    constexpr int KPF = LpUnit<T>::KPF, U = LpUnit<T>::U;
+    constexpr int NT = 64 * NW, NC = 16 * CB, XS = KCB + 4, PF = 2;
+    static_assert(KCB % KPF == 0, "chunk must hold whole fragment units");
+    __shared__ __attribute__((aligned(16))) float Xs[NC * XS];
+    __shared__ float Cs[kMaxCoefK * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mt0 = (blockIdx.y * NW + wave) * RTW, col0 = blockIdx.x * NC;
+    v4f acc[RTW][CB];
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    bool rtv[RTW];
+    bool any = false;
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt) {
+        rtv[rt] = mt0 + rt < g.MT;
+        any = any || rtv[rt];
+    }
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const T *__restrict__ Af = reinterpret_cast<const T *>(g.Af[gi]);
+        const double *__restrict__ X = g.X[gi];
+        const double *__restrict__ coef = g.coef[gi];
+        const int *__restrict__ gcodes = g.gcodes[gi];
+        const double *__restrict__ gw = g.gw[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi], QU = g.QU[gi], ldx = g.ldx[gi];
+        const long long xbs = g.xbs[gi];
+        const double scale = g.scale[gi];
+        // inner range of this split (whole chunks), all of it when ksplit = 1
+        const int nsplit = g.ksplit > 1 ? g.ksplit : 1;
+        const int per = ((Kd + KCB * nsplit - 1) / (KCB * nsplit)) * KCB;
+        const int kbeg = blockIdx.z * per, kend = min(Kd, kbeg + per);
+        for (int kk = kbeg; kk < kend; kk += KCB) {
+            const int kc = min(KCB, kend - kk);
+            __syncthreads();
+            for (int e = tid; e < NC * KCB; e += NT) {
+                const int cc = e / KCB, r = e % KCB, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols && r < kc) {
+                    const int cell = col % g.ncells;
+                    const long long rhs = col / g.ncells;
+                    if (gcodes) {
+                        const double *lam = X + rhs * xbs;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int code = gcodes[((size_t)cell * Kd + kk + r) * 2 + u];
+                            if (code == 0) continue;
+                            const int row = (code > 0 ? code : -code) - 1;
+                            const double x = gw ? lam[row] * gw[row] : lam[row];
+                            v += code > 0 ? x : -x;
+                        }
+                    } else {
+                        v = X[rhs * xbs + (size_t)cell * ldx + kk + r];
+                    }
+                }
+                Xs[cc * XS + r] = (float)v;
+            }
+            for (int e = tid; e < K * NC; e += NT) {
+                const int k = e / NC, cc = e % NC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
+                Cs[e] = (float)v;
+            }
+            __syncthreads();
+            if (!any) continue;
+            const int np = (kc + KPF - 1) / KPF, q0 = kk / KPF, ns = K * np;
+            auto load = [&](int s, uint4 (&dst)[RTW]) {
+                const int k = s / np, q = s % np;
+#pragma unroll
+                for (int rt = 0; rt < RTW; ++rt)
+                    dst[rt] = rtv[rt] ? reinterpret_cast<const uint4 *>(
+                                            Af + ((((size_t)k * g.MT + mt0 + rt) * QU + q0 + q) * 64 + lane) * U)[0]
+                                      : uint4{0u, 0u, 0u, 0u};
+            };
+            uint4 ab[PF][RTW];
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (u < ns) load(u, ab[u]);
+            for (int s0 = 0; s0 < ns; s0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int s = s0 + u;
+                    if (s < ns) {
+                        uint4 a[RTW];
+#pragma unroll
+                        for (int rt = 0; rt < RTW; ++rt) a[rt] = ab[u][rt];
+                        if (s + PF < ns) load(s + PF, ab[u]);
+                        const int k = s / np, q = s % np;
+                        float cf[CB];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+                        if constexpr (BF) {
+                            v8bf b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) {
+                                const float *xr = Xs + (cb * 16 + lr) * XS + q * KPF + 8 * lk;
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
+                            }
+#pragma unroll
+                            for (int rt = 0; rt < RTW; ++rt) {
+                                const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int r = q * KPF + 4 * j + lk;
+                                float b[CB];
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XS + r] * cf[cb];
+#pragma unroll
+                                for (int rt = 0; rt < RTW; ++rt) {
+                                    const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
+                                    const float av = __builtin_bit_cast(float, aw);
+#pragma unroll
+                                    for (int cb = 0; cb < CB; ++cb)
+                                        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int mt = mt0 + rt, col = col0 + cb * 16 + lr;
+            if (mt >= g.MT || col >= g.ncols) continue;
+            double *ycol = g.Y + (long long)(col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * lk + i;
+                if (row < g.M) ycol[row] = g.accumulate ? ycol[row] + (double)acc[rt][cb][i] : (double)acc[rt][cb][i];
+            }
+        }
+}
+
+template <int RTW, int CB, int NW, int KCB, int PF = 2>
 void launch_big(const GemmArgsFrag &a, hipStream_t s, const Prof &prof) {
-    dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RTW * NW - 1) / (RTW * NW)));
+    dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RTW * NW - 1) / (RTW * NW)),
+              (unsigned)std::max(1, a.ksplit));
     if (prof.start())
-        hipExtLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(), 0,
-                              a);
+        hipExtLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB, PF>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(),
+                              0, a);
     else
-        hipLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, a);
+        hipLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB, PF>), grid, dim3(64 * NW), 0, s, a);
 }
 
 template <int RT, int CB, int PF, int NW>
@@ -761,7 +986,8 @@ const void *lp_copy(ifeti_ctx *c, const double *A, int precision) {
 // fragment-ordered copy of A viewed as K stacked M x Kd operators (built on first use)
 static const double *frag_copy(ifeti_ctx *c, const double *A, int M, int Kd, int K) {
     for (auto &cp : c->frag)
-        if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K) return cp.frag;
+        if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K && cp.kind == IFETI_FP64)
+            return (const double *)cp.frag;
     const int MT = (M + 15) / 16, KT2 = (Kd + 7) / 8;
     const long long n = (long long)K * MT * KT2 * 128;
     ifeti_ctx::FragCopy cp;
@@ -769,9 +995,35 @@ static const double *frag_copy(ifeti_ctx *c, const double *A, int M, int Kd, int
     cp.M = M;
     cp.Kd = Kd;
     cp.K = K;
+    cp.kind = IFETI_FP64;
     IFETI_HIP(hipMalloc(&cp.frag, n * sizeof(double)));
     hipLaunchKernelGGL(k_to_frag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, M, Kd, K, MT, KT2,
-                       cp.frag);
+                       (double *)cp.frag);
+    IFETI_HIP(hipGetLastError());
+    c->frag.push_back(cp);
+    return (const double *)cp.frag;
+}
+
+// FP32 / BF16 fragment-unit copy of A (precision form, large M), built on first use
+static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, int K, int kind) {
+    for (auto &cp : c->frag)
+        if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K && cp.kind == kind) return cp.frag;
+    const bool bf = kind == IFETI_BF16_LOCAL;
+    const int MT = (M + 15) / 16, QU = (Kd + (bf ? 31 : 15)) / (bf ? 32 : 16), U = bf ? 8 : 4;
+    const long long n = (long long)K * MT * QU * 64 * U;
+    ifeti_ctx::FragCopy cp;
+    cp.src = A;
+    cp.M = M;
+    cp.Kd = Kd;
+    cp.K = K;
+    cp.kind = kind;
+    IFETI_HIP(hipMalloc(&cp.frag, n * (bf ? 2 : 4)));
+    if (bf)
+        hipLaunchKernelGGL(k_to_frag_lp<__bf16>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, M, Kd,
+                           K, MT, QU, (__bf16 *)cp.frag);
+    else
+        hipLaunchKernelGGL(k_to_frag_lp<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, M, Kd,
+                           K, MT, QU, (float *)cp.frag);
     IFETI_HIP(hipGetLastError());
     c->frag.push_back(cp);
     return cp.frag;
@@ -819,6 +1071,48 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
     const bool frag_path = !lp_path && Kmax <= kMaxCoefK && (frag_small || M >= 128);
+    // large operators, or many columns (a block of load cases): row-owning waves, fragment units
+    const bool lp_big = lp_path && Kmax <= kMaxCoefK && ((!frag_small && M >= 512) || (M >= 64 && ncols >= 16384));
+    if (lp_big) {
+        GemmArgsFragLP f{};
+        const int kind = c->opt.precision;
+        const bool bf = kind == IFETI_BF16_LOCAL;
+        for (int i = 0; i < ngroups; ++i) {
+            f.Af[i] = frag_copy_lp(c, groups[i].A, M, groups[i].Kd, groups[i].K, kind);
+            f.X[i] = a.X[i];
+            f.coef[i] = a.coef[i];
+            f.gcodes[i] = groups[i].gcodes;
+            f.gw[i] = groups[i].gw;
+            f.Kd[i] = a.Kd[i];
+            f.ldx[i] = a.ldx[i];
+            f.K[i] = a.K[i];
+            f.QU[i] = (a.Kd[i] + (bf ? 31 : 15)) / (bf ? 32 : 16);
+            f.xbs[i] = a.xbs[i];
+            f.scale[i] = a.scale[i];
+        }
+        f.ngroups = ngroups;
+        f.Y = Y;
+        f.ybs = a.ybs;
+        f.ldy = ldy;
+        f.M = M;
+        f.MT = (M + 15) / 16;
+        f.ncols = ncols;
+        f.ncells = a.ncells;
+        f.accumulate = a.accumulate;
+        const double esz = bf ? 2.0 : 4.0;
+        double lbytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
+        for (int i = 0; i < ngroups; ++i)
+            lbytes += esz * (double)groups[i].K * M * groups[i].Kd + 8.0 * (double)ncols * groups[i].Kd;
+        Prof prof(c, tag, flops, lbytes);
+        constexpr int RTW = 2, CB = 4, NW = 4, KCB = 64;
+        dim3 grid((unsigned)((ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((f.MT + RTW * NW - 1) / (RTW * NW)));
+        if (bf)
+            hipLaunchKernelGGL((k_pclp_big<__bf16, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, c->stream, f);
+        else
+            hipLaunchKernelGGL((k_pclp_big<float, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, c->stream, f);
+        IFETI_HIP(hipGetLastError());
+        return;
+    }
     if (ngather > 0 && !frag_path) {
         // only the fragment kernel stages through the jump codes: gather first, then contract
         IFETI_REQUIRE(ngather == 1, IFETI_EINVAL, "gemm: at most one gathered group");
@@ -904,7 +1198,17 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         f.accumulate = a.accumulate;
         Prof prof(c, tag, flops, bytes, true);
         // shapes tuned on gfx950: few rows -> many waves per tile; few inner steps -> tall tiles
-        if (frag_big)
+        if (frag_big && ncols <= 128 && ngroups == 1) {
+            // tall operator, few columns (coarse solve of a block of load cases): 64-row tiles, inner range
+            // split 8 ways over blockIdx.z, partials summed in split order
+            f.ksplit = 8;
+            c->w_split.ensure((size_t)f.ksplit * ncols * M, c->stream);
+            f.part = c->w_split.p;
+            launch_big<1, 2, 4, 128, 8>(f, c->stream, prof);  // 8 fragment pairs in flight per wave
+            const long long n = (long long)ncols * M;
+            hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                               c->w_split.p, f.ksplit, ncols, M, f.ncells, Y, f.ybs, ldy, f.accumulate);
+        } else if (frag_big)
             launch_big<2, 4, 4, 64>(f, c->stream, prof);
         else if (f.MT == 1)
             launch_frag<1, 1, 2, 16>(f, c->stream, prof);

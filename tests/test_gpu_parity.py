@@ -174,3 +174,17 @@ def test_block_rhs_equals_single_solves():
         assert info1["outer_its"][0] == info3["outer_its"][r]
         assert rel(host(u3)[r * s.nU:(r + 1) * s.nU], host(u1)) < 1e-10
     ctx.close()
+
+
+def test_five_rhs_match_single(pair):
+    """Five load cases at once take the block coarse solve (a split-K contraction with the dense
+    inverse) instead of the symmetric tile pass; each load case matches its single apply."""
+    name, prob, m, ctx = pair
+    L, nU = m.L, m.nU
+    X = np.stack([_rand(L, 80 + r) for r in range(5)])
+    V = np.stack([_rand(nU, 90 + r) for r in range(5)])
+    for op, Z, n in (("F", X, L), ("Ut", X, nU), ("U", V, L), ("Kinv_rom", V, nU)):
+        Y = host(getattr(ctx, "apply_" + op)(dev(Z.ravel()), nrhs=5)).reshape(5, n)
+        for r in range(5):
+            y1 = host(getattr(ctx, "apply_" + op)(dev(Z[r])))
+            assert rel(Y[r], y1) < 1e-12, f"{name} {op} rhs {r}: {rel(Y[r], y1):.2e}"
