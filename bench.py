@@ -61,10 +61,21 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pc64_MD_gemm_c2_fp64_hbm_cou
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2308_11371_amd", "csrc", "gemm.hip")
 
 
+def kernel_source_hash():
+    """sha256 of the dominant kernel's source text: its argument block, constants, device body and
+    launch wrapper in gemm.hip (host-side edits elsewhere in the file do not invalidate the counters)."""
+    import hashlib
+    with open(KERNEL_SOURCE) as f:
+        src = f.read()
+    a = src.index("struct GemmArgsFrag {")
+    end_marker = "pc64_tile<RT, CB, PF, NW>(g, blockIdx.x, blockIdx.y, Xs, Cs);\n}\n"
+    e = src.index(end_marker, a) + len(end_marker)
+    return hashlib.sha256(src[a:e].encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (copy-calibrated), or None when the kernel source changed since the counters were taken."""
-    import hashlib
     try:
         fields = {}
         with open(TRAFFIC_PROFILE) as f:
@@ -72,8 +83,7 @@ def measured_traffic():
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_hash()
         if fields.get("source_sha256") != sha:
             return None
         return float(fields["traffic_bytes_per_launch"])

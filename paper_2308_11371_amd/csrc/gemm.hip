@@ -1061,8 +1061,13 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     double flops = 0.0, bytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
     for (int i = 0; i < ngroups; ++i) {
         flops += 2.0 * M * (double)ncols * groups[i].K * groups[i].Kd;
-        bytes += 8.0 * ((double)groups[i].K * M * groups[i].Kd + (double)ncols * groups[i].Kd +
-                        (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
+        bytes += 8.0 * ((double)groups[i].K * M * groups[i].Kd + (groups[i].coef ? (double)a.ncells * groups[i].K : 0.0));
+        if (groups[i].gcodes) {  // gathered staging: multipliers (+ weights) once, two int32 codes per slot
+            const double nr = (double)ncols / a.ncells;
+            bytes += 8.0 * (double)groups[i].xbs * nr * (groups[i].gw ? 2.0 : 1.0) + 8.0 * (double)a.ncells * groups[i].Kd;
+        } else {
+            bytes += 8.0 * (double)ncols * groups[i].Kd;
+        }
     }
     const long long cblocks = (ncols + 15) / 16;
     double abytes = 0.0;
