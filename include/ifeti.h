@@ -95,6 +95,10 @@ typedef struct {
     int timing;             /* 1: time kernel launches with HIP events       */
     char timing_filter[32]; /* "" : every kernel family; else a comma-separated list of families */
     int timing_every;       /* time one launch in this many of each family (<= 1: every launch) */
+    int use_graph;          /* 1: the interface PCG runs its first iteration eagerly, captures the
+                               second in a HIP graph (both streams) and replays it for the rest;
+                               results are bitwise those of the eager loop; kernel timing is off
+                               for the replayed iterations */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

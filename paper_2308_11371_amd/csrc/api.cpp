@@ -88,6 +88,12 @@ void ifeti_destroy(ifeti_ctx *c) {
         (void)hipEventDestroy(c->ev_fork);
         (void)hipEventDestroy(c->ev_join);
     }
+    if (c->own_stream) {
+        (void)hipStreamSynchronize(c->own_stream);
+        (void)hipStreamDestroy(c->own_stream);
+        (void)hipEventDestroy(c->ev_own_in);
+        (void)hipEventDestroy(c->ev_own_out);
+    }
     delete c;
 }
 
@@ -163,6 +169,7 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.timing = opt->timing ? 1 : 0;
         c->opt.timing_filter.assign(opt->timing_filter, strnlen(opt->timing_filter, sizeof(opt->timing_filter)));
         c->opt.timing_every = std::max(1, opt->timing_every);
+        c->opt.use_graph = opt->use_graph ? 1 : 0;
         return IFETI_OK;
     });
 }

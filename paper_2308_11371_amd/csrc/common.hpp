@@ -105,6 +105,7 @@ struct Options {
     int timing = 0;
     std::string timing_filter;  // empty: time every kernel family; else a comma-separated list
     int timing_every = 1;       // time one launch in this many of each family
+    int use_graph = 0;          // replay captured interface-PCG iterations (HIP graph)
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
@@ -192,6 +193,9 @@ struct ifeti_ctx {
         size_t n = 0;
         void *f32 = nullptr, *bf16 = nullptr;
     };
+    bool capturing = false;             // a HIP graph capture is in progress on `stream`
+    hipStream_t own_stream = nullptr;   // non-blocking stream of the graph form (default priority)
+    hipEvent_t ev_own_in = nullptr, ev_own_out = nullptr;
     std::vector<LPCopy> lp;
     struct FragCopy {                   // a bank array in MFMA-fragment order, per (M, Kd, K, element type) view
         const double *src = nullptr;

@@ -22,8 +22,8 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kB - 1) / kB); }
 
 // PCG state per load case (doubles): rho, r0, relres, alpha, beta
 enum { S_RHO = 0, S_R0, S_REL, S_ALPHA, S_BETA, S_N };
-// ints: active, iters, breakdown
-enum { I_ACT = 0, I_IT, I_BRK, I_N };
+// ints: active, iterations when last active, breakdown, iterations executed (all load cases)
+enum { I_ACT = 0, I_IT, I_BRK, I_ITER, I_N };
 
 __device__ inline double block_reduce(double v, double *sh) {
     int tid = threadIdx.x;
@@ -74,6 +74,7 @@ __global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr
         st[rhs * S_N + S_BETA] = 0.0;
         ist[rhs * I_N + I_ACT] = r0 > 0.0 ? 1 : 0;
         ist[rhs * I_N + I_IT] = 0;
+        ist[rhs * I_N + I_ITER] = 0;
         ist[rhs * I_N + I_BRK] = 0;
     }
 }
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, doubl
         s1[S_ALPHA] = a;
         i1s[I_ACT] = act;
         i1s[I_IT] = i0s[I_IT];
+        i1s[I_ITER] = i0s[I_ITER];
         i1s[I_BRK] = brk;
     }
     const long long chunk = (n + nblk - 1) / nblk;
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, doubl
 __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const double *__restrict__ z, long long n,
                                                  long long rs, int nrhs, double *__restrict__ st,
                                                  int *__restrict__ ist, const double *__restrict__ p_rr,
-                                                 const double *__restrict__ p_rz, int nblk, double tol, int it) {
+                                                 const double *__restrict__ p_rz, int nblk, double tol) {
     __shared__ double sh[kB];
     const int b = blockIdx.x, rhs = blockIdx.y;
     double *s0 = st + (size_t)rhs * S_N;
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
     const int *i1s = ist + ((size_t)nrhs + rhs) * I_N;
     const double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
     const double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
+    const int it = i1s[I_ITER] + 1;  // this iteration's number, kept on the device (graph replays)
     int act = i1s[I_ACT], its = i1s[I_IT];
     double rel = s1[S_REL], rho = s1[S_RHO], beta = 0.0;
     if (act) {
@@ -164,6 +167,7 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
         s0[S_BETA] = beta;
         i0s[I_ACT] = act;
         i0s[I_IT] = its;
+        i0s[I_ITER] = it;
         i0s[I_BRK] = i1s[I_BRK];
     }
     if (!act) return;
@@ -219,13 +223,108 @@ __global__ __launch_bounds__(kB) void k_sub(const double *__restrict__ a, long l
     out[rhs * o_rs + i] = a[rhs * a_rs + i] + sb * b[rhs * b_rs + i];
 }
 
+// One captured PCG iteration: capture (with the side stream joined through the fork/join events),
+// instantiate, replay; the statistics of the captured iteration are re-applied per replay.
+class GraphIteration {
+   public:
+    explicit GraphIteration(ifeti_ctx *c) : c_(c) {}
+    ~GraphIteration() {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+    }
+    bool ready() const { return exec_ != nullptr; }
+    template <typename F>
+    void capture(F &&body) {
+        std::vector<KernelStat> ks0 = c_->kstats;
+        long long ap0[IFETI_OP_COUNT];
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) ap0[i] = c_->applies[i];
+        IFETI_HIP(hipStreamBeginCapture(c_->stream, hipStreamCaptureModeThreadLocal));
+        c_->capturing = true;
+        try {
+            body();
+        } catch (...) {
+            c_->capturing = false;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(c_->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        c_->capturing = false;
+        IFETI_HIP(hipStreamEndCapture(c_->stream, &graph_));
+        IFETI_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        // nothing ran during the capture: keep the per-iteration increments, restore the counters
+        for (size_t i = 0; i < c_->kstats.size(); ++i) {
+            KernelStat d = c_->kstats[i];
+            if (i < ks0.size()) {
+                d.launches -= ks0[i].launches;
+                d.flops -= ks0[i].flops;
+                d.bytes -= ks0[i].bytes;
+                c_->kstats[i] = ks0[i];
+            } else {
+                c_->kstats[i].launches = 0;
+                c_->kstats[i].flops = c_->kstats[i].bytes = 0.0;
+            }
+            delta_.push_back(d);
+        }
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) {
+            dap_[i] = c_->applies[i] - ap0[i];
+            c_->applies[i] = ap0[i];
+        }
+    }
+    void launch() {
+        IFETI_HIP(hipGraphLaunch(exec_, c_->stream));
+        for (size_t i = 0; i < delta_.size() && i < c_->kstats.size(); ++i) {
+            c_->kstats[i].launches += delta_[i].launches;
+            c_->kstats[i].flops += delta_[i].flops;
+            c_->kstats[i].bytes += delta_[i].bytes;
+        }
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) c_->applies[i] += dap_[i];
+    }
+
+   private:
+    ifeti_ctx *c_;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    std::vector<KernelStat> delta_;
+    long long dap_[IFETI_OP_COUNT] = {};
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ interface PCG
 // One iteration = F̊ p (its final scatter also yields the p.q partials),
 // k_pcg_step, M̊_D^-1 r (its scatter yields the r.z partials), k_pcg_next.
+// Runs the enclosed work on the context's own non-blocking stream (capturable, unlike a caller's
+// legacy default stream), ordered after and before the caller's stream by events.
+class OwnStream {
+   public:
+    OwnStream(ifeti_ctx *c, bool on) : c_(c), caller_(c->stream), on_(on) {
+        if (!on_) return;
+        if (!c->own_stream) {
+            IFETI_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+            IFETI_HIP(hipEventCreateWithFlags(&c->ev_own_in, hipEventDisableTiming));
+            IFETI_HIP(hipEventCreateWithFlags(&c->ev_own_out, hipEventDisableTiming));
+        }
+        IFETI_HIP(hipEventRecord(c->ev_own_in, caller_));
+        IFETI_HIP(hipStreamWaitEvent(c->own_stream, c->ev_own_in, 0));
+        c->stream = c->own_stream;
+    }
+    ~OwnStream() {
+        if (!on_) return;
+        (void)hipEventRecord(c_->ev_own_out, c_->own_stream);
+        (void)hipStreamWaitEvent(caller_, c_->ev_own_out, 0);
+        c_->stream = caller_;
+    }
+
+   private:
+    ifeti_ctx *c_;
+    hipStream_t caller_;
+    bool on_;
+};
+
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres) {
+    OwnStream own(c, c->opt.use_graph != 0);
     const long long L = c->L;
     const long long n = L * nrhs;
     hipStream_t s = c->stream;
@@ -263,7 +362,7 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     auto st0 = any_active();
     const int every = std::max(1, c->opt.pcg_check_every);
     const double Ld = (double)L * nrhs;
-    for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
+    auto iteration = [&]() {
         apply_F(c, p, q, nrhs, p, pa);                                // q = F p, partials of p.q
         {
             Prof prof(c, "pcg_step", 5.0 * Ld, 48.0 * Ld);            // read lam, p, q, r; write lam, r
@@ -274,9 +373,21 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
         {
             Prof prof(c, "pcg_next", 2.0 * Ld, 24.0 * Ld);
             hipLaunchKernelGGL(k_pcg_next, dim3(nblk, nrhs), dim3(kB), 0, s, p, z, L, L, nrhs, st, ist, pb, pc,
-                               nblk, tol, it);
+                               nblk, tol);
         }
         IFETI_HIP(hipGetLastError());
+    };
+    // Graph form: the first iteration runs eagerly (work buffers and operator copies exist
+    // afterwards), the second is captured once (both streams) and every later one is a replay
+    // of that graph; the counters of one iteration are added per replay.
+    GraphIteration graph(c);
+    for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
+        if (c->opt.use_graph && it >= 2) {
+            if (!graph.ready()) graph.capture(iteration);
+            graph.launch();
+        } else {
+            iteration();
+        }
         if (it % every == 0 || it == maxit) st0 = any_active();
     }
     st0 = any_active();

@@ -44,7 +44,7 @@ Prof::Prof(ifeti_ctx *c, const char *name, double flops, double bytes, bool in_p
     k.launches += 1;
     k.flops += flops;
     k.bytes += bytes;
-    if (c->opt.timing && filter_match(c->opt.timing_filter, name) &&
+    if (c->opt.timing && !c->capturing && filter_match(c->opt.timing_filter, name) &&
         (k.launches - 1) % std::max(1, c->opt.timing_every) == 0) {
         k.timed += 1;
         a_ = get_event(c);

@@ -188,3 +188,34 @@ def test_five_rhs_match_single(pair):
         for r in range(5):
             y1 = host(getattr(ctx, "apply_" + op)(dev(Z[r])))
             assert rel(Y[r], y1) < 1e-12, f"{name} {op} rhs {r}: {rel(Y[r], y1):.2e}"
+
+
+def test_graph_replay_equals_eager():
+    """HIP-graph form of the interface PCG (first iteration eager, second captured, the rest replayed
+    with host convergence polls in between): multipliers and iteration counts bitwise those of the
+    eager loop, for one and for three load cases, twice in a row."""
+    _cuda()
+    from paper_2308_11371_amd import ifeti
+    tr = np.array([[1.0, 0.0], [0.3, -0.8], [-0.5, 0.5]])
+    prob = latticegen.tiny(2, (4, 3), 3, n_principal=3, tractions=tr)
+    ctx = ifeti.setup(prob)
+    s = ctx.sizes
+    R = np.random.default_rng(71).standard_normal((3, s.L))
+    for nrhs in (1, 3):
+        rhs = dev(R[:nrhs].ravel())
+        ctx.set_options(use_graph=0)
+        lam0, its0, rel0, _ = ctx.solve_interface(rhs, nrhs=nrhs, tol=1e-11)
+        ref = host(lam0)
+        ctx.set_options(use_graph=1)
+        for rep in range(2):
+            lam1, its1, rel1, _ = ctx.solve_interface(rhs, nrhs=nrhs, tol=1e-11)
+            assert list(its1) == list(its0)
+            assert np.array_equal(host(lam1), ref), f"nrhs={nrhs} rep={rep}"
+    f, d = ctx.get_rhs()
+    ctx.set_options(use_graph=0)
+    u0, l0, i0 = ctx.solve(f, d, nrhs=3, tol=1e-10, inner_tol=1e-12)
+    ctx.set_options(use_graph=1)
+    u1, l1, i1 = ctx.solve(f, d, nrhs=3, tol=1e-10, inner_tol=1e-12)
+    assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(l0), host(l1))
+    assert list(i0["inner_its"]) == list(i1["inner_its"])
+    ctx.close()
