@@ -88,6 +88,7 @@ void ifeti_destroy(ifeti_ctx *c) {
         (void)hipEventDestroy(c->ev_fork);
         (void)hipEventDestroy(c->ev_join);
     }
+    release_graph(c);
     if (c->own_stream) {
         (void)hipStreamSynchronize(c->own_stream);
         (void)hipStreamDestroy(c->own_stream);
@@ -372,6 +373,7 @@ int ifeti_update_widths(ifeti_ctx *c, const double *widths) {
         launch_stiffness(c);
         IFETI_HIP(hipStreamSynchronize(c->stream));
         c->snap_valid = true;
+        ++c->rom_gen;
         return IFETI_OK;
     });
 }

@@ -195,6 +195,12 @@ struct ifeti_ctx {
     };
     bool capturing = false;             // a HIP graph capture is in progress on `stream`
     hipStream_t own_stream = nullptr;   // non-blocking stream of the graph form (default priority)
+    hipGraph_t g_graph = nullptr;       // cached captured PCG iteration and its key / counters
+    hipGraphExec_t g_exec = nullptr;
+    std::vector<uintptr_t> g_key;
+    std::vector<ifeti::KernelStat> g_delta;
+    long long g_dap[IFETI_OP_COUNT] = {};
+    long long rom_gen = 0;              // bumped whenever the reduced basis / cell data change
     hipEvent_t ev_own_in = nullptr, ev_own_out = nullptr;
     std::vector<LPCopy> lp;
     struct FragCopy {                   // a bank array in MFMA-fragment order, per (M, Kd, K, element type) view
@@ -204,6 +210,7 @@ struct ifeti_ctx {
     };
     std::vector<FragCopy> frag;
     void free_copies() {
+        ++rom_gen;
         for (auto &cp : lp) {
             if (cp.f32) (void)hipFree(cp.f32);
             if (cp.bf16) (void)hipFree(cp.bf16);
@@ -300,6 +307,7 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);
+void release_graph(ifeti_ctx *c);
 void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);

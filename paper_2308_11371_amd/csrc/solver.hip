@@ -9,6 +9,7 @@
 // only polls the convergence flags every `pcg_check_every` iterations.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -223,70 +224,68 @@ __global__ __launch_bounds__(kB) void k_sub(const double *__restrict__ a, long l
     out[rhs * o_rs + i] = a[rhs * a_rs + i] + sb * b[rhs * b_rs + i];
 }
 
-// One captured PCG iteration: capture (with the side stream joined through the fork/join events),
-// instantiate, replay; the statistics of the captured iteration are re-applied per replay.
-class GraphIteration {
-   public:
-    explicit GraphIteration(ifeti_ctx *c) : c_(c) {}
-    ~GraphIteration() {
-        if (exec_) (void)hipGraphExecDestroy(exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
+// One captured PCG iteration (both streams, joined through the fork/join events), instantiated
+// and kept in the context while its key (every buffer the iteration touches, load cases,
+// tolerance, precision, reduced-basis generation) is unchanged; the statistics of the
+// captured iteration are re-applied per replay.
+struct GraphIteration {
+    static void release(ifeti_ctx *c) {
+        if (c->g_exec) (void)hipGraphExecDestroy(c->g_exec);
+        if (c->g_graph) (void)hipGraphDestroy(c->g_graph);
+        c->g_exec = nullptr;
+        c->g_graph = nullptr;
+        c->g_key.clear();
+        c->g_delta.clear();
     }
-    bool ready() const { return exec_ != nullptr; }
     template <typename F>
-    void capture(F &&body) {
-        std::vector<KernelStat> ks0 = c_->kstats;
+    static void capture(ifeti_ctx *c, const std::vector<uintptr_t> &key, F &&body) {
+        release(c);
+        std::vector<KernelStat> ks0 = c->kstats;
         long long ap0[IFETI_OP_COUNT];
-        for (int i = 0; i < IFETI_OP_COUNT; ++i) ap0[i] = c_->applies[i];
-        IFETI_HIP(hipStreamBeginCapture(c_->stream, hipStreamCaptureModeThreadLocal));
-        c_->capturing = true;
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) ap0[i] = c->applies[i];
+        IFETI_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
         try {
             body();
         } catch (...) {
-            c_->capturing = false;
+            c->capturing = false;
             hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(c_->stream, &g);
+            (void)hipStreamEndCapture(c->stream, &g);
             if (g) (void)hipGraphDestroy(g);
             throw;
         }
-        c_->capturing = false;
-        IFETI_HIP(hipStreamEndCapture(c_->stream, &graph_));
-        IFETI_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        c->capturing = false;
+        IFETI_HIP(hipStreamEndCapture(c->stream, &c->g_graph));
+        IFETI_HIP(hipGraphInstantiate(&c->g_exec, c->g_graph, nullptr, nullptr, 0));
         // nothing ran during the capture: keep the per-iteration increments, restore the counters
-        for (size_t i = 0; i < c_->kstats.size(); ++i) {
-            KernelStat d = c_->kstats[i];
+        for (size_t i = 0; i < c->kstats.size(); ++i) {
+            KernelStat d = c->kstats[i];
             if (i < ks0.size()) {
                 d.launches -= ks0[i].launches;
                 d.flops -= ks0[i].flops;
                 d.bytes -= ks0[i].bytes;
-                c_->kstats[i] = ks0[i];
+                c->kstats[i] = ks0[i];
             } else {
-                c_->kstats[i].launches = 0;
-                c_->kstats[i].flops = c_->kstats[i].bytes = 0.0;
+                c->kstats[i].launches = 0;
+                c->kstats[i].flops = c->kstats[i].bytes = 0.0;
             }
-            delta_.push_back(d);
+            c->g_delta.push_back(d);
         }
         for (int i = 0; i < IFETI_OP_COUNT; ++i) {
-            dap_[i] = c_->applies[i] - ap0[i];
-            c_->applies[i] = ap0[i];
+            c->g_dap[i] = c->applies[i] - ap0[i];
+            c->applies[i] = ap0[i];
         }
+        c->g_key = key;
     }
-    void launch() {
-        IFETI_HIP(hipGraphLaunch(exec_, c_->stream));
-        for (size_t i = 0; i < delta_.size() && i < c_->kstats.size(); ++i) {
-            c_->kstats[i].launches += delta_[i].launches;
-            c_->kstats[i].flops += delta_[i].flops;
-            c_->kstats[i].bytes += delta_[i].bytes;
+    static void launch(ifeti_ctx *c) {
+        IFETI_HIP(hipGraphLaunch(c->g_exec, c->stream));
+        for (size_t i = 0; i < c->g_delta.size() && i < c->kstats.size(); ++i) {
+            c->kstats[i].launches += c->g_delta[i].launches;
+            c->kstats[i].flops += c->g_delta[i].flops;
+            c->kstats[i].bytes += c->g_delta[i].bytes;
         }
-        for (int i = 0; i < IFETI_OP_COUNT; ++i) c_->applies[i] += dap_[i];
+        for (int i = 0; i < IFETI_OP_COUNT; ++i) c->applies[i] += c->g_dap[i];
     }
-
-   private:
-    ifeti_ctx *c_;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t exec_ = nullptr;
-    std::vector<KernelStat> delta_;
-    long long dap_[IFETI_OP_COUNT] = {};
 };
 
 }  // namespace
@@ -321,6 +320,8 @@ class OwnStream {
     hipStream_t caller_;
     bool on_;
 };
+
+void release_graph(ifeti_ctx *c) { GraphIteration::release(c); }
 
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres) {
@@ -377,14 +378,27 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
         }
         IFETI_HIP(hipGetLastError());
     };
-    // Graph form: the first iteration runs eagerly (work buffers and operator copies exist
-    // afterwards), the second is captured once (both streams) and every later one is a replay
-    // of that graph; the counters of one iteration are added per replay.
-    GraphIteration graph(c);
+    // Graph form: with a cached graph of this exact configuration every iteration is a replay;
+    // otherwise the first iteration runs eagerly (work buffers and operator copies exist
+    // afterwards) and the second is captured.
+    std::vector<uintptr_t> key;
+    if (c->opt.use_graph) {
+        const void *bufs[] = {lam, r, z, p, q, st, ist, pa, pb, pc, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p,
+                              c->w_yP.p, c->w_symP.p, c->w_split.p, c->w_Lam.p, c->side_stream, c->stream};
+        for (const void *b : bufs) key.push_back((uintptr_t)b);
+        for (long long v : {(long long)nrhs, (long long)c->opt.precision, c->rom_gen, (long long)nblk})
+            key.push_back((uintptr_t)v);
+        double tv = tol;
+        uintptr_t tb = 0;
+        std::memcpy(&tb, &tv, sizeof(tv));
+        key.push_back(tb);
+    }
     for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
-        if (c->opt.use_graph && it >= 2) {
-            if (!graph.ready()) graph.capture(iteration);
-            graph.launch();
+        if (c->opt.use_graph && (c->g_exec && c->g_key == key)) {
+            GraphIteration::launch(c);
+        } else if (c->opt.use_graph && it >= 2) {
+            GraphIteration::capture(c, key, iteration);
+            GraphIteration::launch(c);
         } else {
             iteration();
         }
