@@ -99,6 +99,9 @@ typedef struct {
                                second in a HIP graph (both streams) and replays it for the rest;
                                results are bitwise those of the eager loop; kernel timing is off
                                for the replayed iterations */
+    int autotune;           /* 1: the first launch of each contraction shape times the candidate tile
+                               shapes and keeps the fastest for the context's lifetime (results then
+                               agree with the default tiles to rounding, not bitwise) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

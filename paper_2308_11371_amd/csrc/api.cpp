@@ -171,6 +171,7 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.timing_filter.assign(opt->timing_filter, strnlen(opt->timing_filter, sizeof(opt->timing_filter)));
         c->opt.timing_every = std::max(1, opt->timing_every);
         c->opt.use_graph = opt->use_graph ? 1 : 0;
+        c->opt.autotune = opt->autotune ? 1 : 0;
         return IFETI_OK;
     });
 }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "ifeti.h"
@@ -106,6 +107,7 @@ struct Options {
     std::string timing_filter;  // empty: time every kernel family; else a comma-separated list
     int timing_every = 1;       // time one launch in this many of each family
     int use_graph = 0;          // replay captured interface-PCG iterations (HIP graph)
+    int autotune = 0;           // time the candidate tile shapes on first use of each contraction shape
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
@@ -201,6 +203,7 @@ struct ifeti_ctx {
     std::vector<ifeti::KernelStat> g_delta;
     long long g_dap[IFETI_OP_COUNT] = {};
     long long rom_gen = 0;              // bumped whenever the reduced basis / cell data change
+    std::map<std::vector<long long>, int> tuned;  // contraction shape -> chosen tile candidate
     hipEvent_t ev_own_in = nullptr, ev_own_out = nullptr;
     std::vector<LPCopy> lp;
     struct FragCopy {                   // a bank array in MFMA-fragment order, per (M, Kd, K, element type) view

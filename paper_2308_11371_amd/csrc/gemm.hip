@@ -928,21 +928,20 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_big(GemmArgsFragLP g) {
 }
 
 template <int RTW, int CB, int NW, int KCB, int PF = 2>
-void launch_big(const GemmArgsFrag &a, hipStream_t s, const Prof &prof) {
+void launch_big(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RTW * NW - 1) / (RTW * NW)),
               (unsigned)std::max(1, a.ksplit));
-    if (prof.start())
-        hipExtLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB, PF>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(),
-                              0, a);
+    if (t0)
+        hipExtLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB, PF>), grid, dim3(64 * NW), 0, s, t0, t1, 0, a);
     else
         hipLaunchKernelGGL((k_pc64_big<RTW, CB, NW, KCB, PF>), grid, dim3(64 * NW), 0, s, a);
 }
 
 template <int RT, int CB, int PF, int NW>
-void launch_frag(const GemmArgsFrag &a, hipStream_t s, const Prof &prof) {
+void launch_frag(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RT - 1) / RT));
-    if (prof.start())
-        hipExtLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, prof.start(), prof.stop(), 0, a);
+    if (t0)
+        hipExtLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, t0, t1, 0, a);
     else
         hipLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, a);
 }
@@ -981,6 +980,97 @@ const void *lp_copy(ifeti_ctx *c, const double *A, int precision) {
                                                  : (const void *)((const uint16_t *)cp.bf16 + off);
         }
     return nullptr;
+}
+
+// ---------------------------------------------------------------- tile autotuner
+// Candidate tile shapes of the two FP64 fragment kernels.  With options.autotune on, the first
+// launch of each (shape, column count) times every candidate of its family in place (the output
+// is overwritten, so only non-accumulating launches are tuned) and keeps the fastest; otherwise
+// the defaults below are used (chosen by sweeps on gfx950).  Candidates differ in the order of
+// the fixed-order sums, so results agree to rounding, not bitwise, across candidates.
+using FragLauncher = void (*)(const GemmArgsFrag &, hipStream_t, hipEvent_t, hipEvent_t);
+const FragLauncher kSmallCandidates[] = {launch_frag<4, 2, 2, 8>, launch_frag<2, 4, 4, 8>, launch_frag<2, 2, 4, 8>,
+                                         launch_frag<4, 1, 4, 4>, launch_frag<1, 1, 2, 16>, launch_frag<2, 2, 2, 4>};
+const FragLauncher kBigCandidates[] = {launch_big<2, 4, 4, 64>, launch_big<4, 2, 4, 64>, launch_big<2, 2, 8, 64>,
+                                       launch_big<1, 4, 4, 64>, launch_big<2, 4, 4, 128>};
+constexpr int kNSmall = sizeof(kSmallCandidates) / sizeof(kSmallCandidates[0]);
+constexpr int kNBig = sizeof(kBigCandidates) / sizeof(kBigCandidates[0]);
+
+static FragLauncher choose_launcher(ifeti_ctx *c, const GemmArgsFrag &f, bool big, int def, bool tunable) {
+    const FragLauncher *cand = big ? kBigCandidates : kSmallCandidates;
+    const int n = big ? kNBig : kNSmall;
+    if (!c->opt.autotune || !tunable || c->capturing) return cand[def];
+    std::vector<long long> key = {big ? 1 : 0, f.M, f.ncols, f.ngroups};
+    for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) return cand[it->second];
+    hipEvent_t e0, e1;
+    IFETI_HIP(hipEventCreate(&e0));
+    IFETI_HIP(hipEventCreate(&e1));
+    int best = def;
+    float best_ms = 1e30f;
+    for (int i = 0; i < n; ++i) {
+        cand[i](f, c->stream, nullptr, nullptr);  // warm-up
+        float tot = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            cand[i](f, c->stream, e0, e1);
+            IFETI_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            IFETI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        if (tot < best_ms) {
+            best_ms = tot;
+            best = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[key] = best;
+    return cand[best];
+}
+
+template <typename T, int RTW, int CB, int NW, int KCB>
+void launch_lp_big(const GemmArgsFragLP &f, hipStream_t s) {
+    dim3 grid((unsigned)((f.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((f.MT + RTW * NW - 1) / (RTW * NW)));
+    hipLaunchKernelGGL((k_pclp_big<T, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, f);
+}
+using LpLauncher = void (*)(const GemmArgsFragLP &, hipStream_t);
+const LpLauncher kLpF32Candidates[] = {launch_lp_big<float, 2, 4, 4, 64>, launch_lp_big<float, 4, 2, 4, 64>,
+                                       launch_lp_big<float, 2, 2, 8, 64>, launch_lp_big<float, 2, 4, 4, 128>};
+const LpLauncher kLpBF16Candidates[] = {launch_lp_big<__bf16, 2, 4, 4, 64>, launch_lp_big<__bf16, 4, 2, 4, 64>,
+                                        launch_lp_big<__bf16, 2, 2, 8, 64>, launch_lp_big<__bf16, 2, 4, 4, 128>};
+constexpr int kNLp = 4;
+
+static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool bf, bool tunable) {
+    const LpLauncher *cand = bf ? kLpBF16Candidates : kLpF32Candidates;
+    if (!c->opt.autotune || !tunable || c->capturing) return cand[0];
+    std::vector<long long> key = {bf ? 3 : 2, f.M, f.ncols, f.ngroups};
+    for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) return cand[it->second];
+    hipEvent_t e0, e1;
+    IFETI_HIP(hipEventCreate(&e0));
+    IFETI_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int i = 0; i < kNLp; ++i) {
+        cand[i](f, c->stream);  // warm-up
+        IFETI_HIP(hipEventRecord(e0, c->stream));
+        for (int rep = 0; rep < 3; ++rep) cand[i](f, c->stream);
+        IFETI_HIP(hipEventRecord(e1, c->stream));
+        IFETI_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        IFETI_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[key] = best;
+    return cand[best];
 }
 
 // fragment-ordered copy of A viewed as K stacked M x Kd operators (built on first use)
@@ -1109,12 +1199,8 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         for (int i = 0; i < ngroups; ++i)
             lbytes += esz * (double)groups[i].K * M * groups[i].Kd + 8.0 * (double)ncols * groups[i].Kd;
         Prof prof(c, tag, flops, lbytes);
-        constexpr int RTW = 2, CB = 4, NW = 4, KCB = 64;
-        dim3 grid((unsigned)((ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((f.MT + RTW * NW - 1) / (RTW * NW)));
-        if (bf)
-            hipLaunchKernelGGL((k_pclp_big<__bf16, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, c->stream, f);
-        else
-            hipLaunchKernelGGL((k_pclp_big<float, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, c->stream, f);
+        LpLauncher launch_fn = choose_lp_launcher(c, f, bf, !accumulate);
+        launch_fn(f, c->stream);
         IFETI_HIP(hipGetLastError());
         return;
     }
@@ -1209,18 +1295,15 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             f.ksplit = 8;
             c->w_split.ensure((size_t)f.ksplit * ncols * M, c->stream);
             f.part = c->w_split.p;
-            launch_big<1, 2, 4, 128, 8>(f, c->stream, prof);  // 8 fragment pairs in flight per wave
+            launch_big<1, 2, 4, 128, 8>(f, c->stream, prof.start(), prof.stop());  // 8 pairs in flight per wave
             const long long n = (long long)ncols * M;
             hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                                c->w_split.p, f.ksplit, ncols, M, f.ncells, Y, f.ybs, ldy, f.accumulate);
-        } else if (frag_big)
-            launch_big<2, 4, 4, 64>(f, c->stream, prof);
-        else if (f.MT == 1)
-            launch_frag<1, 1, 2, 16>(f, c->stream, prof);
-        else if (Kdmax <= 16)
-            launch_frag<4, 1, 4, 4>(f, c->stream, prof);
-        else
-            launch_frag<4, 2, 2, 8>(f, c->stream, prof);
+        } else {
+            const int def = frag_big ? 0 : (f.MT == 1 ? 4 : (Kdmax <= 16 ? 3 : 0));
+            FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate);
+            launch_fn(f, c->stream, prof.start(), prof.stop());
+        }
         IFETI_HIP(hipGetLastError());
         return;
     }

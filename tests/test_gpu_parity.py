@@ -219,3 +219,22 @@ def test_graph_replay_equals_eager():
     assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(l0), host(l1))
     assert list(i0["inner_its"]) == list(i1["inner_its"])
     ctx.close()
+
+
+def test_autotuned_tiles_match_defaults():
+    """With the tile autotuner on, each contraction shape is timed over its candidate tiles on first use
+    and the fastest kept; every operator still matches the oracle-checked default path to rounding."""
+    _cuda()
+    from paper_2308_11371_amd import ifeti
+    prob = latticegen.tiny(2, (5, 3), 4, n_principal=4, tractions=[[0.3, -0.7]])
+    ctx = ifeti.setup(prob)
+    s = ctx.sizes
+    xs = {"F": _rand(s.L, 11), "MD": _rand(s.L, 12), "Ut": _rand(s.L, 13), "U": _rand(s.nU, 14),
+          "Kinv_rom": _rand(s.nU, 15)}
+    ref = {op: host(getattr(ctx, "apply_" + op)(dev(x))) for op, x in xs.items()}
+    ctx.set_options(autotune=1)
+    for rep in range(2):  # first call tunes, second uses the kept choice
+        for op, x in xs.items():
+            got = host(getattr(ctx, "apply_" + op)(dev(x)))
+            assert rel(got, ref[op]) < 1e-13, f"{op} rep {rep}: {rel(got, ref[op]):.2e}"
+    ctx.close()
