@@ -172,7 +172,38 @@ def run_forms(ctx, f, d, t_fp64, args):
         "max_outer_its": int(max(info["outer_its"])), "max_relres": float(max(info["relres"]))}
     log(f"form block_rhs: {t:.3f}s for {s4.nrhs} load cases")
     c4.close()
+    if not args.no_3d:
+        res["c3_3d"] = run_c3(args)
     return res
+
+
+def run_c3(args):
+    """3D lattice c3 (2048 cells, 1536 dof/cell, 16 principal cells): FP64 plain vs FP32 / BF16 local
+    contractions, each solved to relres 1e-8 (interface PCG capped at 200 iterations in 3D)."""
+    import torch
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+    t0 = time.perf_counter()
+    prob = latticegen.make("c3")
+    ctx = ifeti.setup(prob)
+    torch.cuda.synchronize()
+    s = ctx.sizes
+    out = {"workload": "c3: 3D 16x16x8-cell lattice, 1536 dof/cell, 16 principal cells, 1 load case",
+           "setup_s": time.perf_counter() - t0}
+    f, d = ctx.get_rhs()
+    f = f[:s.nU].contiguous()
+    d = d[:s.L].contiguous()
+    for name, prec, itol in (("fp64_plain", ifeti.IFETI_FP64, 1e-11), ("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6),
+                             ("bf16_local", ifeti.IFETI_BF16_LOCAL, 1e-3)):
+        ctx.set_options(precision=prec, pcg_maxit=200)
+        t, info = timed_solve(ctx, f, d, 1, args.tol, itol)
+        out[name] = {"solve_time_s": t, "outer_its": int(info["outer_its"][0]), "pcg_its": int(info["inner_its"][0]),
+                     "relres": float(info["relres"][0]), "inner_tol": itol}
+        if name != "fp64_plain":
+            out[name]["vs_fp64"] = t / out["fp64_plain"]["solve_time_s"]
+        log(f"form c3 {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+    ctx.close()
+    return out
 
 
 def main():
@@ -193,6 +224,7 @@ def main():
     ap.add_argument("--timing-every", type=int, default=8,
                     help="event-time one launch in this many of each timed family (keeps the timeline unperturbed)")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and block-RHS legs")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (c3) precision leg of the forms")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()

@@ -121,23 +121,24 @@ __global__ __launch_bounds__(kB) void k_combine_wt(const double *__restrict__ pi
 
 constexpr int kMaxNp = 24;  // primal (corner) dofs per cell: 4 x 2 in 2D, 8 x 3 in 3D
 
-// c_s = C_s B_d^T lam for column (rhs, s): one wave per column; lane j-stride
-// gathers the signed multipliers of the cell's dual dofs, the n_p sums are
-// reduced across the wave.
-template <int NPM>
-__global__ __launch_bounds__(256) void k_restrict_c(const double *__restrict__ C, const int *__restrict__ gl,
-                                                    const double *__restrict__ lam, long long lam_rs, int N, int n_d,
-                                                    int n_p, int ncols, double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (col >= ncols) return;  // uniform per wave; no block-level synchronisation below
+// c_s = C_s B_d^T lam for column (rhs, s): one workgroup of NWC waves per column;
+// wave w takes the 64-row chunks w, w + NWC, ... of the cell's dual dofs (lanes
+// gather the signed multipliers), reduces its n_p sums across the wave, and the
+// NWC partial vectors are added in wave order through LDS.
+template <int NPM, int NWC>
+__global__ __launch_bounds__(64 * NWC) void k_restrict_c(const double *__restrict__ C, const int *__restrict__ gl,
+                                                          const double *__restrict__ lam, long long lam_rs, int N,
+                                                          int n_d, int n_p, int ncols, double *__restrict__ out) {
+    __shared__ double part[NWC][NPM];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x;
     const int rhs = col / N, s = col % N;
     const double *l = lam + rhs * lam_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
     double acc[NPM];
 #pragma unroll
     for (int i = 0; i < NPM; ++i) acc[i] = 0.0;
-    for (int j = lane; j < n_d; j += 64) {
+    for (int j = 64 * wave + lane; j < n_d; j += 64 * NWC) {
         double v = 0.0;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -155,27 +156,26 @@ __global__ __launch_bounds__(256) void k_restrict_c(const double *__restrict__ C
         if (i >= n_p) break;
         double v = acc[i];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        acc[i] = v;
+        if (lane == 0) part[wave][i] = v;
     }
-    if (lane < n_p) {
-        double v = 0.0;
+    __syncthreads();
+    if (threadIdx.x < n_p) {
+        double v = part[0][threadIdx.x];
 #pragma unroll
-        for (int i = 0; i < NPM; ++i)
-            if (i == lane) v = acc[i];
-        out[(size_t)col * n_p + lane] = v;
+        for (int w = 1; w < NWC; ++w) v += part[w][threadIdx.x];
+        out[(size_t)col * n_p + threadIdx.x] = v;
     }
 }
 
-// Y_s (+)= C_s^T y_P[A_p(s)] for column (rhs, s): one wave per column, lanes
-// over the cell's dual rows (coalesced rows of C_s); the n_p primal values of
-// the cell are wave-uniform.
-template <int NPM>
-__global__ __launch_bounds__(256) void k_prolong_c(const double *__restrict__ C, const int *__restrict__ Ap,
-                                                   const double *__restrict__ yP, long long yP_rs, int N, int n_d,
-                                                   int n_p, int ncols, double *__restrict__ Y, int accumulate) {
-    const int lane = threadIdx.x & 63;
-    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (col >= ncols) return;
+// Y_s (+)= C_s^T y_P[A_p(s)] for column (rhs, s): one workgroup of NWC waves per
+// column, lanes over the cell's dual rows (coalesced rows of C_s); the n_p
+// primal values of the cell are uniform.
+template <int NPM, int NWC>
+__global__ __launch_bounds__(64 * NWC) void k_prolong_c(const double *__restrict__ C, const int *__restrict__ Ap,
+                                                         const double *__restrict__ yP, long long yP_rs, int N,
+                                                         int n_d, int n_p, int ncols, double *__restrict__ Y,
+                                                         int accumulate) {
+    const int col = blockIdx.x;
     const int rhs = col / N, s = col % N;
     const double *zP = yP + rhs * yP_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_prolong_c(const double *__restrict__ C,
         }
     }
     double *Yc = Y + (size_t)col * n_d;
-    for (int j = lane; j < n_d; j += 64) {
+    for (int j = threadIdx.x; j < n_d; j += 64 * NWC) {
         double v = accumulate ? Yc[j] : 0.0;
 #pragma unroll
         for (int i = 0; i < NPM; ++i)
@@ -945,10 +945,12 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
         Prof prof(c, "F_restrict", 2.0 * (double)cols * np * nd,
                   cmap_bytes + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
         if (np <= 8)
-            hipLaunchKernelGGL(k_restrict_c<8>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
-                               c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
+            hipLaunchKernelGGL((k_restrict_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, c->Wc.p, c->g_gather.p, lam,
+                               c->L, N, nd, np, cols, c->w_c.p);
         else
-            hipLaunchKernelGGL(k_restrict_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
+            // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
+            // coarse branch from crowding it
+            hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, c->Wc.p,
                                c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
     }
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
@@ -956,11 +958,11 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
     {
         Prof prof(c, "F_prolong", 2.0 * (double)cols * np * nd, cmap_bytes + 8.0 * (double)cols * nd);
         if (np <= 8)
-            hipLaunchKernelGGL(k_prolong_c<8>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p, c->g_Ap.p,
+            hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, c->Wc.p, c->g_Ap.p,
                                c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
         else
-            hipLaunchKernelGGL(k_prolong_c<kMaxNp>, dim3((cols + 3) / 4), dim3(256), 0, c->stream, c->Wc.p,
-                               c->g_Ap.p, c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
+            hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, c->Wc.p, c->g_Ap.p,
+                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
     }
     join_side(c);
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, c->w_Yc.p);
