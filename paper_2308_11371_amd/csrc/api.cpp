@@ -89,6 +89,8 @@ void ifeti_destroy(ifeti_ctx *c) {
         (void)hipEventDestroy(c->ev_join);
     }
     release_graph(c);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    if (c->ev_poll) (void)hipEventDestroy(c->ev_poll);
     if (c->own_stream) {
         (void)hipStreamSynchronize(c->own_stream);
         (void)hipStreamDestroy(c->own_stream);

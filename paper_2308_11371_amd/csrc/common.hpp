@@ -197,6 +197,9 @@ struct ifeti_ctx {
     };
     bool capturing = false;             // a HIP graph capture is in progress on `stream`
     hipStream_t own_stream = nullptr;   // non-blocking stream of the graph form (default priority)
+    void *h_pin = nullptr;              // pinned host staging for convergence reads (hipHostMalloc)
+    size_t h_pin_bytes = 0;
+    hipEvent_t ev_poll = nullptr;
     hipGraph_t g_graph = nullptr;       // cached captured PCG iteration and its key / counters
     hipGraphExec_t g_exec = nullptr;
     std::vector<uintptr_t> g_key;
@@ -311,6 +314,9 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);
 void release_graph(ifeti_ctx *c);
+// copy `bytes` from device memory to pinned host staging on the context stream and wait for it by
+// spinning on an event (no blocking stream synchronisation); returns the staging pointer
+const void *read_back(ifeti_ctx *c, const void *dev, size_t bytes);
 void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);

@@ -23,6 +23,8 @@
 // The 16x16 f64 MFMA returns D with lane l, register i -> row 4*i + l/16,
 // column l % 16 (checked on gfx950).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -1027,6 +1029,9 @@ static FragLauncher choose_launcher(ifeti_ctx *c, const GemmArgsFrag &f, bool bi
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->tuned[key] = best;
+    if (std::getenv("IFETI_TUNE_VERBOSE"))
+        std::fprintf(stderr, "[ifeti tune] %s M=%d ncols=%d Kd=%d K=%d -> candidate %d\n", big ? "big" : "small", f.M,
+                     f.ncols, f.Kd[0], f.K[0], best);
     return cand[best];
 }
 
@@ -1044,7 +1049,7 @@ constexpr int kNLp = 4;
 
 static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool bf, bool tunable) {
     const LpLauncher *cand = bf ? kLpBF16Candidates : kLpF32Candidates;
-    if (!c->opt.autotune || !tunable || c->capturing) return cand[0];
+    if (!c->opt.autotune || !tunable || c->capturing) return cand[2];  // the tuner's usual choice
     std::vector<long long> key = {bf ? 3 : 2, f.M, f.ncols, f.ngroups};
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
     auto it = c->tuned.find(key);
@@ -1070,6 +1075,9 @@ static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->tuned[key] = best;
+    if (std::getenv("IFETI_TUNE_VERBOSE"))
+        std::fprintf(stderr, "[ifeti tune] %s M=%d ncols=%d Kd=%d K=%d -> candidate %d\n", bf ? "bf16" : "fp32", f.M,
+                     f.ncols, f.Kd[0], f.K[0], best);
     return cand[best];
 }
 
@@ -1300,7 +1308,8 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                                c->w_split.p, f.ksplit, ncols, M, f.ncells, Y, f.ybs, ldy, f.accumulate);
         } else {
-            const int def = frag_big ? 0 : (f.MT == 1 ? 4 : (Kdmax <= 16 ? 3 : 0));
+            // defaults = the autotuner's usual choice on gfx950 (2D and 3D lattices)
+            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : 0));
             FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate);
             launch_fn(f, c->stream, prof.start(), prof.stop());
         }

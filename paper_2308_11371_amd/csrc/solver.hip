@@ -351,8 +351,8 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     IFETI_HIP(hipGetLastError());
     std::vector<int> hist((size_t)I_N * nrhs);
     auto any_active = [&]() {  // slot 0 holds the state between iterations
-        IFETI_HIP(hipMemcpyAsync(hist.data(), ist, hist.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        IFETI_HIP(hipStreamSynchronize(s));
+        const int *hp = (const int *)read_back(c, ist, hist.size() * sizeof(int));
+        std::copy(hp, hp + hist.size(), hist.begin());
         bool act = false, brk = false;
         for (int r2 = 0; r2 < nrhs; ++r2) {
             act |= hist[r2 * I_N + I_ACT] != 0;
@@ -537,11 +537,12 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         inv_sqrt(c, hall.p + 2 * hstride, scd.p, nrhs);
         double *Vn = new_block(Vb, hVp, dVp);
         scale_copy(c, w.p, ns, ns, scd.p, Vn, nrhs);
-        IFETI_HIP(hipMemcpyAsync(h1.data(), hall.p, (size_t)(j + 1) * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-        IFETI_HIP(hipMemcpyAsync(h2.data(), hall.p + hstride, (size_t)(j + 1) * nrhs * sizeof(double),
-                                 hipMemcpyDeviceToHost, s));
-        IFETI_HIP(hipMemcpyAsync(hn.data(), hall.p + 2 * hstride, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-        IFETI_HIP(hipStreamSynchronize(s));
+        {  // one read of [h pass 1 | h pass 2 | ||w||^2]
+            const double *hp = (const double *)read_back(c, hall.p, (2 * hstride + nrhs) * sizeof(double));
+            std::copy(hp, hp + (size_t)(j + 1) * nrhs, h1.begin());
+            std::copy(hp + hstride, hp + hstride + (size_t)(j + 1) * nrhs, h2.begin());
+            std::copy(hp + 2 * hstride, hp + 2 * hstride + nrhs, hn.begin());
+        }
         for (int r = 0; r < nrhs; ++r) {
             double hj1 = std::sqrt(hn[r]);
             if (done[r]) continue;

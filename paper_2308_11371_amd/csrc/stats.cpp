@@ -76,6 +76,27 @@ void flush_events(ifeti_ctx *c) {
     c->pending.clear();
 }
 
+const void *read_back(ifeti_ctx *c, const void *dev, size_t bytes) {
+    if (bytes > c->h_pin_bytes) {
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        if (c->h_pin) (void)hipHostFree(c->h_pin);
+        c->h_pin = nullptr;
+        c->h_pin_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 1 << 16);
+        IFETI_HIP(hipHostMalloc(&c->h_pin, want, hipHostMallocDefault));
+        c->h_pin_bytes = want;
+    }
+    if (!c->ev_poll) IFETI_HIP(hipEventCreateWithFlags(&c->ev_poll, hipEventDisableTiming));
+    IFETI_HIP(hipMemcpyAsync(c->h_pin, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipEventRecord(c->ev_poll, c->stream));
+    for (;;) {
+        const hipError_t e = hipEventQuery(c->ev_poll);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) IFETI_HIP(e);
+    }
+    return c->h_pin;
+}
+
 void release_events(ifeti_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &p : c->pending) {
