@@ -50,198 +50,10 @@ struct GemmArgsDev {
     int ldy, M, ncols, ncells, accumulate;
 };
 
+constexpr int LT = 64;          // columns of A per LDS tile
 constexpr int KCH = 128;       // rows of X held in registers per chunk
 constexpr int TSTEPS = KCH / 4;
 constexpr int PF = 8;          // A-fragment steps loaded ahead
-
-template <int BM, int SPLIT>
-__global__ __launch_bounds__(256) void k_pcontract(GemmArgsDev g) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int m0 = blockIdx.y * (16 * BM);
-    const int cblk = SPLIT == 1 ? (blockIdx.x * 4 + wave) : blockIdx.x;
-    const int col = cblk * 16 + lr;
-    const bool cvalid = col < g.ncols;
-    const int cell = cvalid ? col % g.ncells : 0;
-    const long long rhs = cvalid ? col / g.ncells : 0;
-
-    v4d acc[BM];
-#pragma unroll
-    for (int i = 0; i < BM; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    for (int gi = 0; gi < g.ngroups; ++gi) {
-        const double *__restrict__ A = g.A[gi];
-        const double *__restrict__ coef = g.coef[gi];
-        const int Kd = g.Kd[gi], K = g.K[gi];
-        const long long strideA = (long long)g.M * Kd;
-        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
-        const double scale = g.scale[gi];
-        for (int kk = 0; kk < Kd; kk += KCH) {
-            // cell vectors of this chunk -> registers
-            double braw[TSTEPS];
-#pragma unroll
-            for (int t = 0; t < TSTEPS; ++t) {
-                const int kx = kk + 4 * t + lk;
-                braw[t] = (cvalid && kx < Kd) ? xcol[kx] : 0.0;
-            }
-            const int tmax = std::min(TSTEPS, (Kd - kk + 3) / 4);
-            for (int k = (SPLIT == 1 ? 0 : wave); k < K; k += SPLIT) {
-                const double cf = cvalid ? scale * (coef ? coef[(size_t)cell * K + k] : 1.0) : 0.0;
-                const double *__restrict__ Ak = A + (size_t)k * strideA;
-                const double *arow[BM];
-                bool rvalid[BM];
-#pragma unroll
-                for (int bm = 0; bm < BM; ++bm) {
-                    const int row = m0 + bm * 16 + lr;
-                    rvalid[bm] = row < g.M;
-                    arow[bm] = Ak + (size_t)(rvalid[bm] ? row : 0) * Kd;
-                }
-#pragma unroll
-                for (int t0 = 0; t0 < TSTEPS; t0 += PF) {
-                    if (t0 >= tmax) break;
-                    double a[PF][BM];
-#pragma unroll
-                    for (int u = 0; u < PF; ++u) {
-                        const int kx = kk + 4 * (t0 + u) + lk;
-#pragma unroll
-                        for (int bm = 0; bm < BM; ++bm)
-                            a[u][bm] = (t0 + u < tmax && rvalid[bm] && kx < Kd) ? arow[bm][kx] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < PF; ++u) {
-                        const double b = braw[t0 + u] * cf;
-#pragma unroll
-                        for (int bm = 0; bm < BM; ++bm)
-                            acc[bm] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][bm], b, acc[bm], 0, 0, 0);
-                    }
-                }
-            }
-        }
-    }
-    if constexpr (SPLIT > 1) {
-        __shared__ double red[SPLIT][BM][4][64];
-#pragma unroll
-        for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) red[wave][bm][i][lane] = acc[bm][i];
-        __syncthreads();
-        if (wave != 0) return;
-#pragma unroll
-        for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                double s = red[0][bm][i][lane];
-#pragma unroll
-                for (int w = 1; w < SPLIT; ++w) s += red[w][bm][i][lane];
-                acc[bm][i] = s;
-            }
-    }
-    if (!cvalid) return;
-    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
-#pragma unroll
-    for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = m0 + bm * 16 + 4 * i + lk;
-            if (row >= g.M) continue;
-            ycol[row] = g.accumulate ? ycol[row] + acc[bm][i] : acc[bm][i];
-        }
-}
-
-// LDS-staged variant for row counts >= 32: the workgroup (4 waves = 4 column
-// blocks of 16 cells, 32 rows) stages each 32 x 64 tile of a principal
-// operator in LDS with coalesced 16-byte loads, double-buffered through
-// registers so the next tile is in flight while the MFMAs consume this one.
-constexpr int LT = 64;          // columns of A per LDS tile
-constexpr int LDA = LT + 4;     // padded LDS row (doubles)
-
-__global__ __launch_bounds__(256) void k_pcontract_lds(GemmArgsDev g) {
-    __shared__ double As[2][32][LDA];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int m0 = blockIdx.y * 32;
-    const int col = (blockIdx.x * 4 + wave) * 16 + lr;
-    const bool cvalid = col < g.ncols;
-    const int cell = cvalid ? col % g.ncells : 0;
-    const long long rhs = cvalid ? col / g.ncells : 0;
-    // cooperative tile load: thread -> (row, 8 consecutive doubles)
-    const int ld_row = tid >> 3, ld_c = (tid & 7) * 8;
-
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int gi = 0; gi < g.ngroups; ++gi) {
-        const double *__restrict__ A = g.A[gi];
-        const double *__restrict__ coef = g.coef[gi];
-        const int Kd = g.Kd[gi], K = g.K[gi];
-        const long long strideA = (long long)g.M * Kd;
-        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
-        const double scale = g.scale[gi];
-        const bool vec_ok = (Kd % 2) == 0;
-        for (int kk = 0; kk < Kd; kk += KCH) {
-            double braw[TSTEPS];
-#pragma unroll
-            for (int t = 0; t < TSTEPS; ++t) {
-                const int kx = kk + 4 * t + lk;
-                braw[t] = (cvalid && kx < Kd) ? xcol[kx] : 0.0;
-            }
-            const int nsub = (std::min(KCH, Kd - kk) + LT - 1) / LT;  // LDS tiles per principal
-            const int ntile = K * nsub;
-            // register stage of the next tile
-            double st[8];
-            auto fetch = [&](int tile) {
-                const int k = tile / nsub, sub = tile % nsub;
-                const int row = m0 + ld_row;
-                const int c0 = kk + sub * LT + ld_c;
-                const double *src = A + (size_t)k * strideA + (size_t)row * Kd + c0;
-                if (row < g.M && vec_ok && c0 + 7 < Kd) {
-                    const double2 *s2 = reinterpret_cast<const double2 *>(src);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        double2 v = s2[u];
-                        st[2 * u] = v.x;
-                        st[2 * u + 1] = v.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) st[u] = (row < g.M && c0 + u < Kd) ? src[u] : 0.0;
-                }
-            };
-            fetch(0);
-            for (int tile = 0; tile < ntile; ++tile) {
-                const int buf = tile & 1;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) As[buf][ld_row][ld_c + u] = st[u];
-                __syncthreads();
-                if (tile + 1 < ntile) fetch(tile + 1);
-                const int k = tile / nsub, sub = tile % nsub;
-                const double cf = cvalid ? scale * (coef ? coef[(size_t)cell * K + k] : 1.0) : 0.0;
-                auto consume = [&](auto SUB) {
-                    constexpr int sb = decltype(SUB)::value;
-#pragma unroll
-                    for (int u = 0; u < LT / 4; ++u) {
-                        const double b = braw[sb * (LT / 4) + u] * cf;
-                        const double a0 = As[buf][lr][4 * u + lk];
-                        const double a1 = As[buf][16 + lr][4 * u + lk];
-                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1, 0, 0, 0);
-                    }
-                };
-                if (sub == 0)
-                    consume(std::integral_constant<int, 0>{});
-                else
-                    consume(std::integral_constant<int, 1>{});
-                __syncthreads();
-            }
-        }
-    }
-    if (!cvalid) return;
-    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r0 = m0 + 4 * i + lk, r1 = r0 + 16;
-        if (r0 < g.M) ycol[r0] = g.accumulate ? ycol[r0] + acc0[i] : acc0[i];
-        if (r1 < g.M) ycol[r1] = g.accumulate ? ycol[r1] + acc1[i] : acc1[i];
-    }
-}
 
 // ---------------------------------------------------------------- low-precision operands
 // Precision form: the principal operators (and the cell vectors, rounded as they
@@ -948,12 +760,6 @@ void launch_frag(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t
         hipLaunchKernelGGL((k_pc64<RT, CB, PF, NW>), grid, dim3(64 * NW), 0, s, a);
 }
 
-template <int BM, int SPLIT>
-void launch(const GemmArgsDev &a, hipStream_t s) {
-    const int cblocks = (a.ncols + 15) / 16;
-    dim3 grid(SPLIT == 1 ? (cblocks + 3) / 4 : cblocks, (a.M + 16 * BM - 1) / (16 * BM));
-    hipLaunchKernelGGL((k_pcontract<BM, SPLIT>), grid, dim3(256), 0, s, a);
-}
 
 }  // namespace
 
@@ -1130,6 +936,8 @@ static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, in
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
           bool accumulate, int ncells, const char *tag, bool lp_ok) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
+    for (int i = 0; i < ngroups; ++i)
+        IFETI_REQUIRE(groups[i].K >= 1 && groups[i].K <= kMaxCoefK, IFETI_EINVAL, "gemm: 1 to 40 principal operators");
     if (ncols <= 0 || M <= 0) return;
     int ngather = 0;
     for (int i = 0; i < ngroups; ++i) ngather += groups[i].gcodes ? 1 : 0;
@@ -1173,7 +981,7 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     const bool lp_path = lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16;
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
-    const bool frag_path = !lp_path && Kmax <= kMaxCoefK && (frag_small || M >= 128);
+    const bool frag_path = !lp_path;
     // large operators, or many columns (a block of load cases): row-owning waves, fragment units
     const bool lp_big = lp_path && Kmax <= kMaxCoefK && ((!frag_small && M >= 512) || (M >= 64 && ncols >= 16384));
     if (lp_big) {
@@ -1316,16 +1124,7 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         IFETI_HIP(hipGetLastError());
         return;
     }
-    Prof prof(c, tag, flops, bytes);
-    if (M <= 16 && Kmax >= 4) {
-        launch<1, 4>(a, c->stream);
-    } else if (M <= 16 || Kdmax <= 16) {
-        launch<1, 1>(a, c->stream);
-    } else {
-        dim3 grid((unsigned)((cblocks + 3) / 4), (unsigned)((M + 31) / 32));
-        hipLaunchKernelGGL(k_pcontract_lds, grid, dim3(256), 0, c->stream, a);
-    }
-    IFETI_HIP(hipGetLastError());
+    IFETI_REQUIRE(false, IFETI_EINVAL, "gemm: no kernel for this contraction");
 }
 
 

@@ -331,39 +331,6 @@ __global__ __launch_bounds__(1024) void k_sym_reduce(const double *__restrict__ 
     }
 }
 
-// ------------------------------------------------------------------ coarse solve, one wave per row
-__global__ __launch_bounds__(kB) void k_coarse_gemv(const double *__restrict__ S, int n, const double *__restrict__ z,
-                                                    double *__restrict__ y, double scale) {
-    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
-    if (wave >= n) return;
-    const double *row = S + (size_t)wave * n;
-    double acc = 0.0;
-    if ((n & 1) == 0) {  // rows start 16-byte aligned: paired loads, 4 in flight per lane
-        const double2 *r2 = reinterpret_cast<const double2 *>(row);
-        const double2 *z2 = reinterpret_cast<const double2 *>(z);
-        const int n2 = n / 2;
-        double acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        int i = lane;
-        for (; i + 192 < n2; i += 256) {
-            double2 a0 = r2[i], a1 = r2[i + 64], a2 = r2[i + 128], a3 = r2[i + 192];
-            double2 b0 = z2[i], b1 = z2[i + 64], b2 = z2[i + 128], b3 = z2[i + 192];
-            acc += a0.x * b0.x + a0.y * b0.y;
-            acc1 += a1.x * b1.x + a1.y * b1.y;
-            acc2 += a2.x * b2.x + a2.y * b2.y;
-            acc3 += a3.x * b3.x + a3.y * b3.y;
-        }
-        for (; i < n2; i += 64) {
-            double2 a = r2[i], b = z2[i];
-            acc += a.x * b.x + a.y * b.y;
-        }
-        acc += (acc1 + acc2) + acc3;
-    } else {
-        for (int i = lane; i < n; i += 64) acc += row[i] * z[i];
-    }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) y[wave] = scale * acc;
-}
 
 // ------------------------------------------------------------------ reduced local solve (46)
 // Column c = rhs*N + s.  R_c holds the K reduced-basis vectors
