@@ -174,6 +174,7 @@ def run_forms(ctx, f, d, t_fp64, args):
     c4.close()
     if not args.no_3d:
         res["c3_3d"] = run_c3(args)
+        res["c5_gradient"] = run_c5(args)
     return res
 
 
@@ -204,6 +205,58 @@ def run_c3(args):
         if name != "fp64_plain":
             out[name]["vs_fp64"] = t / out["fp64_plain"]["solve_time_s"]
         log(f"form c3 {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+    ctx.close()
+    return out
+
+
+def run_c5(args):
+    """Differentiation form on c5 (3D 12x12x12 cells, 1536 dof/cell, 16 principal cells, per-cell strut
+    widths uniform in [0.15, 0.30]): compliance and its gradient with respect to all 1728 widths through
+    the torch.autograd.Function (width update with refreshed ROM coefficients, FP64 solve to relres 1e-8,
+    adjoint gradient kernel), timed after one untimed evaluation; then each part timed on its own."""
+    import torch
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+    t0 = time.perf_counter()
+    prob = latticegen.make("c5")
+    ctx = ifeti.setup(prob)
+    torch.cuda.synchronize()
+    s = ctx.sizes
+    out = {"workload": f"c5: 3D 12x12x12-cell lattice, 1536 dof/cell, {s.K} principal cells, per-cell widths, "
+                       f"gradient w.r.t. {s.N} widths", "setup_s": time.perf_counter() - t0}
+    ctx.set_options(pcg_maxit=200)
+    f, d = ctx.get_rhs()
+    f = f[:s.nU].contiguous()
+    d = d[:s.L].contiguous()
+    w = torch.tensor(prob.widths, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def evaluate():
+        c = ifeti.compliance(w, ctx, f, d, tol=args.tol, inner_tol=1e-11)
+        (g,) = torch.autograd.grad(c, w)
+        return c, g
+
+    evaluate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c, g = evaluate()
+    torch.cuda.synchronize()
+    out["compliance_and_gradient_s"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    ctx.update_widths(w.detach())
+    torch.cuda.synchronize()
+    out["width_update_s"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    u, lam, info = ctx.solve(f, d, tol=args.tol, inner_tol=1e-11, maxit=200)
+    torch.cuda.synchronize()
+    out["solve_s"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    ctx.compliance_grad(f, u)
+    torch.cuda.synchronize()
+    out["gradient_kernel_s"] = time.perf_counter() - t1
+    out.update(outer_its=int(info["outer_its"][0]), pcg_its=int(info["inner_its"][0]),
+               relres=float(info["relres"][0]), compliance=float(c), grad_norm=float(torch.linalg.norm(g)))
+    log(f"form c5 gradient: {out['compliance_and_gradient_s']:.3f}s (update {out['width_update_s']:.3f}, "
+        f"solve {out['solve_s']:.3f}, gradient {out['gradient_kernel_s'] * 1e3:.2f} ms)")
     ctx.close()
     return out
 

@@ -215,6 +215,61 @@ constexpr int FKC = 128;      // inner rows of the cell vectors staged per chunk
 constexpr int FXS = FKC + 2;  // LDS row stride (doubles): conflict-free B-fragment reads
 constexpr int kMaxCoefK = 40;
 
+// Stages the cell vectors of columns [col0, col0 + NC), inner rows [kk, kk + kc) into
+// Xs[col][row] (row stride XST), zero-padded to KC rows: plain strided columns, or the
+// fused (weighted) jump transpose from the signed multiplier rows in `gcodes`.  Entries
+// are taken in batches of up to 8 per thread with every load of a batch (codes, then
+// multiplier rows and weights) issued before the first is consumed.
+template <int NC, int KC, int NT, int XST>
+__device__ __forceinline__ void stage_chunk(const GemmArgsFrag &g, const double *__restrict__ X,
+                                            const int *__restrict__ gcodes, const double *__restrict__ gw, int Kd,
+                                            int ldx, long long xbs, int col0, int kk, int kc, double *__restrict__ Xs,
+                                            int tid) {
+    constexpr int PER = (NC * KC + NT - 1) / NT;
+    constexpr int SB = PER < 4 ? PER : 4;
+#pragma unroll 1
+    for (int i0 = 0; i0 < PER; i0 += SB) {
+        int2 cd[SB];
+        double v[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int e = tid + (i0 + i) * NT, cc = e / KC, r = e % KC, col = col0 + cc;
+            cd[i] = int2{0, 0};
+            v[i] = 0.0;
+            if (e < NC * KC && col < g.ncols && r < kc) {
+                const int cell = col % g.ncells;
+                if (gcodes)
+                    cd[i] = *reinterpret_cast<const int2 *>(gcodes + ((size_t)cell * Kd + kk + r) * 2);
+                else
+                    v[i] = X[(long long)(col / g.ncells) * xbs + (size_t)cell * ldx + kk + r];
+            }
+        }
+        if (gcodes) {
+            double x0[SB], x1[SB];
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                const int col = col0 + (tid + (i0 + i) * NT) / KC;
+                const double *lam = X + (long long)(col / g.ncells) * xbs;
+                const int r0 = abs(cd[i].x) - 1, r1 = abs(cd[i].y) - 1;
+                x0[i] = cd[i].x ? lam[r0] : 0.0;
+                x1[i] = cd[i].y ? lam[r1] : 0.0;
+                if (gw) {
+                    x0[i] *= cd[i].x ? gw[r0] : 0.0;
+                    x1[i] *= cd[i].y ? gw[r1] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SB; ++i)
+                v[i] = (cd[i].x >= 0 ? x0[i] : -x0[i]) + (cd[i].y >= 0 ? x1[i] : -x1[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            const int e = tid + (i0 + i) * NT;
+            if (e < NC * KC) Xs[(e / KC) * XST + e % KC] = v[i];
+        }
+    }
+}
+
 // Workgroup = NW waves sharing one output tile of RT row tiles x CB column
 // blocks (16 x 16 each).  The cell vectors of the tile's 16*CB columns and
 // their coefficients are staged in LDS; the (principal, k-step pair) sequence
@@ -261,28 +316,7 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
         for (int kk = 0; kk < Kd; kk += FKC) {
             const int kc = min(FKC, Kd - kk);
             __syncthreads();  // previous chunk fully consumed
-            for (int e = tid; e < NC * FKC; e += NT) {
-                const int cc = e / FKC, r = e % FKC, col = col0 + cc;
-                double v = 0.0;
-                if (col < g.ncols && r < kc) {
-                    const int cell = col % g.ncells;
-                    const long long rhs = col / g.ncells;
-                    if (gcodes) {  // fused (scaled) jump transpose: signed multiplier rows
-                        const double *lam = X + rhs * xbs;
-#pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const int code = gcodes[((size_t)cell * Kd + kk + r) * 2 + u];
-                            if (code == 0) continue;
-                            const int row = (code > 0 ? code : -code) - 1;
-                            const double x = gw ? lam[row] * gw[row] : lam[row];
-                            v += code > 0 ? x : -x;
-                        }
-                    } else {
-                        v = X[rhs * xbs + (size_t)cell * ldx + kk + r];
-                    }
-                }
-                Xs[cc * FXS + r] = v;
-            }
+            stage_chunk<NC, FKC, NT, FXS>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
             for (int e = tid; e < K * NC; e += NT) {
                 const int k = e / NC, cc = e % NC, col = col0 + cc;
                 double v = 0.0;
@@ -433,28 +467,7 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
         for (int kk = kbeg; kk < kend; kk += KCB) {
             const int kc = min(KCB, kend - kk);
             __syncthreads();
-            for (int e = tid; e < NC * KCB; e += NT) {
-                const int cc = e / KCB, r = e % KCB, col = col0 + cc;
-                double v = 0.0;
-                if (col < g.ncols && r < kc) {
-                    const int cell = col % g.ncells;
-                    const long long rhs = col / g.ncells;
-                    if (gcodes) {
-                        const double *lam = X + rhs * xbs;
-#pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const int code = gcodes[((size_t)cell * Kd + kk + r) * 2 + u];
-                            if (code == 0) continue;
-                            const int row = (code > 0 ? code : -code) - 1;
-                            const double x = gw ? lam[row] * gw[row] : lam[row];
-                            v += code > 0 ? x : -x;
-                        }
-                    } else {
-                        v = X[rhs * xbs + (size_t)cell * ldx + kk + r];
-                    }
-                }
-                Xs[cc * XSB + r] = v;
-            }
+            stage_chunk<NC, KCB, NT, XSB>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
             for (int e = tid; e < K * NC; e += NT) {
                 const int k = e / NC, cc = e % NC, col = col0 + cc;
                 double v = 0.0;
