@@ -102,6 +102,9 @@ typedef struct {
     int autotune;           /* 1: the first launch of each contraction shape times the candidate tile
                                shapes and keeps the fastest for the context's lifetime (results then
                                agree with the default tiles to rounding, not bitwise) */
+    int coarse_parts;       /* coarse solve S̊_PP^-1 for 1-3 load cases: 0 automatic (fewest bytes per
+                               apply), 1 the explicit inverse in symmetric tiles, p >= 2 the partitioned
+                               solve with p interior blocks (EINVAL if the band does not allow p) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

@@ -91,6 +91,10 @@ void ifeti_destroy(ifeti_ctx *c) {
     release_graph(c);
     if (c->h_pin) (void)hipHostFree(c->h_pin);
     if (c->ev_poll) (void)hipEventDestroy(c->ev_poll);
+    for (int i = 0; i < 2; ++i) {
+        if (c->h_poll[i]) (void)hipHostFree(c->h_poll[i]);
+        if (c->ev_pollv[i]) (void)hipEventDestroy(c->ev_pollv[i]);
+    }
     if (c->own_stream) {
         (void)hipStreamSynchronize(c->own_stream);
         (void)hipStreamDestroy(c->own_stream);
@@ -174,6 +178,11 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.timing_every = std::max(1, opt->timing_every);
         c->opt.use_graph = opt->use_graph ? 1 : 0;
         c->opt.autotune = opt->autotune ? 1 : 0;
+        REQ(opt->coarse_parts >= 0, "coarse_parts must be >= 0");
+        if (opt->coarse_parts != c->opt.coarse_parts) {
+            c->opt.coarse_parts = opt->coarse_parts;
+            if (c->rom_built) build_coarse_partition(c);
+        }
         return IFETI_OK;
     });
 }

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <string>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "ifeti.h"
@@ -108,6 +109,13 @@ struct Options {
     int timing_every = 1;       // time one launch in this many of each family
     int use_graph = 0;          // replay captured interface-PCG iterations (HIP graph)
     int autotune = 0;           // time the candidate tile shapes on first use of each contraction shape
+    int coarse_parts = 0;       // coarse solve: 0 automatic, 1 symmetric-tile inverse, >= 2 that many blocks
+};
+
+// One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
+struct CoarseRow {
+    long long off;
+    int xlo, len, out, pad;
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
@@ -189,6 +197,14 @@ struct ifeti_ctx {
     ifeti::DevBuf<int> sym_tiles;       // [tile] -> (I, J)
     ifeti::DevBuf<double> w_symP;       // [tile][rhs][row partial 64 | column partial 64]
     int nT = 0;
+    // partitioned coarse solve (interior blocks separated by bandwidth-wide separators): phase 1 the
+    // separator right-hand side, phase 2 the separator Schur-complement inverse, phase 3 the interiors
+    std::vector<double> h_Sband;        // lower band of S̊_PP before factorisation, [i][i-j], width bw+1
+    int h_bw = 0;
+    int cp_p = 0, cp_ns = 0;            // interior blocks (0: not built), separator rows
+    ifeti::DevBuf<double> cp_M1, cp_M2, cp_M3;
+    ifeti::DevBuf<ifeti::CoarseRow> cp_R1, cp_R2, cp_R3;
+    ifeti::DevBuf<double> w_cg, w_cw;   // separator rhs [rhs][ns], assembled input [rhs][nP]
     bool rom_built = false;
     struct LPCopy {                     // fp32 / bf16 copies of a bank array (precision form)
         const double *src = nullptr;
@@ -200,6 +216,15 @@ struct ifeti_ctx {
     void *h_pin = nullptr;              // pinned host staging for convergence reads (hipHostMalloc)
     size_t h_pin_bytes = 0;
     hipEvent_t ev_poll = nullptr;
+    // FGMRES storage kept across solves (grow-only, no allocation inside a warm solve): Krylov
+    // blocks V_j and Z_j, their device pointer tables (with host mirrors) and work vectors
+    std::vector<std::unique_ptr<ifeti::DevBuf<double>>> fg_V, fg_Z;
+    ifeti::DevBuf<const double *> fg_dV, fg_dZ;
+    std::vector<const double *> fg_hV, fg_hZ;
+    ifeti::DevBuf<double> fg_w, fg_coef, fg_tu, fg_tL, fg_tL2, fg_tu2, fg_hdev, fg_hall, fg_scd, fg_xs;
+    void *h_poll[2] = {nullptr, nullptr};  // pinned slots of the look-ahead convergence polls
+    size_t h_poll_bytes = 0;
+    hipEvent_t ev_pollv[2] = {nullptr, nullptr};
     hipGraph_t g_graph = nullptr;       // cached captured PCG iteration and its key / counters
     hipGraphExec_t g_exec = nullptr;
     std::vector<uintptr_t> g_key;
@@ -280,6 +305,7 @@ void launch_stiffness(ifeti_ctx *c);
 int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in,
                   std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
 void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw);
+void build_coarse_partition(ifeti_ctx *c);
 
 // gemm.hip
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)

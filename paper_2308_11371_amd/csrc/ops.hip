@@ -304,6 +304,78 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const double *__restrict__ T,
                 ((red[q][0][tid] + red[q][1][tid]) + red[q][2][tid]) + red[q][3][tid];
 }
 
+// Partitioned coarse solve, one phase: row w < nrows (WPR waves per row, 256/(64 WPR) rows per
+// workgroup) computes R = rows[w],
+//   y[q][R.out] = alpha * dot,  y2[q][R.out] = alpha2 * dot (if y2),  dot = M[R.off + c] x[q][R.xlo + c]
+// summed over c < R.len (thread t of the row takes c = t mod 64 WPR in increasing c, then a fixed
+// butterfly within each wave and the waves in order), for NR load cases at once; the operator rows
+// are streamed with non-temporal loads.  Rows w >= nrows copy cz to cw (ncopy entries per load
+// case), which phase 1 uses to assemble the phase-3 input.
+template <int NR, int WPR>
+__global__ __launch_bounds__(256) void k_coarse_rows(const double *__restrict__ M, const CoarseRow *__restrict__ rows,
+                                                     int nrows, const double *__restrict__ x, long long x_rs,
+                                                     double alpha, double *__restrict__ y, long long y_rs,
+                                                     double alpha2, double *__restrict__ y2, long long y2_rs,
+                                                     const double *__restrict__ cz, long long cz_rs,
+                                                     double *__restrict__ cw, long long cw_rs, int ncopy) {
+    constexpr int RT = 64 * WPR;        // threads per row
+    constexpr int RPB = 256 / RT;       // rows per workgroup
+    __shared__ double red[4][NR];
+    const int w = blockIdx.x * RPB + threadIdx.x / RT, t = threadIdx.x % RT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool dot = w < nrows;  // uniform per row (whole waves)
+    if (!dot) {
+        const long long e = (long long)(w - nrows) * RT + t;
+        if (e < ncopy)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) cw[q * cw_rs + e] = cz[q * cz_rs + e];
+    }
+    const CoarseRow R = dot ? rows[w] : CoarseRow{0, 0, 0, 0, 0};
+    const double *m = M + R.off;
+    double acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+    // batches of 8 predicated loads per thread, all issued before the first is used
+    for (int c = t; c < R.len; c += 8 * RT) {
+        double a[8], xv[8][NR];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int cc = c + RT * u;
+            a[u] = cc < R.len ? __builtin_nontemporal_load(m + cc) : 0.0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) xv[u][q] = cc < R.len ? x[q * x_rs + R.xlo + cc] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q] += a[u] * xv[u][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    if constexpr (WPR > 1) {
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) red[wave][q] = acc[q];
+        __syncthreads();  // reached by every thread of the workgroup (no early exits above)
+        if (!dot || t != 0) return;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            double s = red[wave][q];
+#pragma unroll
+            for (int v = 1; v < WPR; ++v) s += red[wave + v][q];
+            acc[q] = s;
+        }
+    } else if (!dot || lane != 0) {
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        y[q * y_rs + R.out] = alpha * acc[q];
+        if (y2) y2[q * y2_rs + R.out] = alpha2 * acc[q];
+    }
+}
+
 // one workgroup per (block row I, load case): thread (part, r) sums the
 // contributions J = part, part + 16, ... of row r; the 16 parts are added in
 // order through LDS
@@ -842,10 +914,63 @@ void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double sca
                        y_rs, scale);
 }
 
+template <int NR, int WPR>
+void coarse_rows(ifeti_ctx *c, const double *M, const CoarseRow *rows, int nrows, const double *x, long long x_rs,
+                 double alpha, double *y, long long y_rs, double alpha2, double *y2, long long y2_rs,
+                 const double *cz, long long cz_rs, double *cw, long long cw_rs, int ncopy) {
+    constexpr int RPB = 4 / WPR;
+    const long long total_rows = (long long)nrows + (ncopy + 64 * WPR - 1) / (64 * WPR);
+    hipLaunchKernelGGL((k_coarse_rows<NR, WPR>), dim3((unsigned)((total_rows + RPB - 1) / RPB)), dim3(256), 0,
+                       c->stream, M, rows, nrows, x, x_rs, alpha, y, y_rs, alpha2, y2, y2_rs, cz, cz_rs, cw, cw_rs,
+                       ncopy);
+    IFETI_HIP(hipGetLastError());
+}
+
+// y = scale * S̊_PP^-1 z through the three phases of the partitioned solve (1 to 3 load cases)
+void coarse_partitioned(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
+                        double scale) {
+    const int n = c->nP, ns = c->cp_ns, nI = n - ns;
+    // separator phases have few rows (one workgroup per row keeps enough loads in flight); the
+    // interior phase has many (two waves per row)
+    auto launch = [&](auto wpr, const double *M, const CoarseRow *rows, int nrows, const double *x, long long x_rs,
+                      double alpha, double *yy, long long yy_rs, double alpha2, double *y2, long long y2_rs,
+                      const double *cz, int ncopy) {
+        constexpr int W = decltype(wpr)::value;
+        if (nrhs == 1)
+            coarse_rows<1, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+                              n, ncopy);
+        else if (nrhs == 2)
+            coarse_rows<2, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+                              n, ncopy);
+        else
+            coarse_rows<3, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+                              n, ncopy);
+    };
+    using Sep = std::integral_constant<int, 4>;
+    using Int = std::integral_constant<int, 2>;
+    {
+        Prof prof(c, "coarse_sep_rhs", 2.0 * (double)c->cp_M1.n * nrhs,
+                  8.0 * ((double)c->cp_M1.n + (double)ns * nrhs + 2.0 * n * nrhs) + 24.0 * ns);
+        launch(Sep{}, c->cp_M1.p, c->cp_R1.p, ns, z, z_rs, -1.0, c->w_cg.p, ns, 0.0, nullptr, 0, z, n);
+    }
+    {
+        Prof prof(c, "coarse_sep_solve", 2.0 * (double)ns * ns * nrhs,
+                  8.0 * ((double)ns * ns + 3.0 * ns * nrhs) + 24.0 * ns);
+        launch(Sep{}, c->cp_M2.p, c->cp_R2.p, ns, c->w_cg.p, ns, 1.0, c->w_cw.p, n, scale, y, y_rs, nullptr, 0);
+    }
+    {
+        Prof prof(c, "coarse_interior", 2.0 * (double)c->cp_M3.n * nrhs,
+                  8.0 * ((double)c->cp_M3.n + (double)n * nrhs + (double)nI * nrhs) + 24.0 * nI);
+        launch(Int{}, c->cp_M3.p, c->cp_R3.p, nI, c->w_cw.p, n, scale, y, y_rs, 0.0, nullptr, 0, nullptr, 0);
+    }
+}
+
 void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
                      double scale) {
     if (c->nP == 0) return;
-    if (nrhs < 4) {
+    if (nrhs < 4 && c->cp_p >= 2) {
+        coarse_partitioned(c, z, z_rs, y, y_rs, nrhs, scale);
+    } else if (nrhs < 4) {
         const double n = (double)c->nP, nt = (double)c->nT * (c->nT + 1) / 2;
         {
             // algorithmic: the symmetric operator's n(n+1)/2 entries read once, the vectors, the partials

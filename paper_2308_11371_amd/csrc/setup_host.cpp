@@ -923,6 +923,8 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                 band[(size_t)I * (bw + 1) + (I - J)] += 0.5 * (X[i * np + j] + X[j * np + i]);
             }
     }
+    c->h_Sband = band;
+    c->h_bw = bw;
     // banded Cholesky: band[i][i-j] <- L[i][j]
     for (int j = 0; j < nP; ++j) {
         double s = band[(size_t)j * (bw + 1)];
@@ -989,6 +991,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                        {c->Kinv.p, c->Kinv.n}});
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
     coarse_inverse_device(c, band, bw);
+    build_coarse_partition(c);
     IFETI_HIP(hipStreamSynchronize(c->stream));
     c->rom_built = true;
 }

@@ -393,6 +393,60 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
         std::memcpy(&tb, &tv, sizeof(tv));
         key.push_back(tb);
     }
+    // Convergence polls with look-ahead: the poll after chunk k (every `every` iterations) is read
+    // while chunk k+1 already runs, unless the residual trend of the last two polls predicts the
+    // end within the next two chunks, in which case it is read at once.  Iterations after a load
+    // case has converged leave its state unchanged, so a look-ahead chunk changes no result.
+    const size_t ib = hist.size() * sizeof(int), sb = (size_t)S_N * nrhs * sizeof(double);
+    const size_t soff = (ib + 15) / 16 * 16;
+    if (soff + sb > c->h_poll_bytes) {
+        IFETI_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < 2; ++i) {
+            if (c->h_poll[i]) (void)hipHostFree(c->h_poll[i]);
+            c->h_poll[i] = nullptr;
+        }
+        c->h_poll_bytes = 0;
+        const size_t want = std::max<size_t>(soff + sb, 1 << 12);
+        for (int i = 0; i < 2; ++i) IFETI_HIP(hipHostMalloc(&c->h_poll[i], want, hipHostMallocDefault));
+        c->h_poll_bytes = want;
+    }
+    for (int i = 0; i < 2; ++i)
+        if (!c->ev_pollv[i]) IFETI_HIP(hipEventCreateWithFlags(&c->ev_pollv[i], hipEventDisableTiming));
+    auto poll_issue = [&](int slot) {
+        IFETI_HIP(hipMemcpyAsync(c->h_poll[slot], ist, ib, hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipMemcpyAsync((char *)c->h_poll[slot] + soff, st, sb, hipMemcpyDeviceToHost, s));
+        IFETI_HIP(hipEventRecord(c->ev_pollv[slot], s));
+    };
+    struct Poll {
+        bool act, brk;
+        int it;
+        double rel;  // largest relative residual over the active load cases
+    };
+    auto poll_wait = [&](int slot, int it) {
+        for (;;) {
+            const hipError_t e = hipEventQuery(c->ev_pollv[slot]);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) IFETI_HIP(e);
+        }
+        const int *hi = (const int *)c->h_poll[slot];
+        const double *hs = (const double *)((const char *)c->h_poll[slot] + soff);
+        Poll P{false, false, it, 0.0};
+        for (int r2 = 0; r2 < nrhs; ++r2) {
+            const bool a = hi[r2 * I_N + I_ACT] != 0;
+            P.act |= a;
+            P.brk |= hi[r2 * I_N + I_BRK] != 0;
+            if (a) P.rel = std::max(P.rel, hs[r2 * S_N + S_REL]);
+        }
+        return P;
+    };
+    Poll prev{true, false, 0, 1.0}, last{true, false, 0, 1.0};
+    int pending = -1, pending_it = 0, slot = 0;
+    auto near_end = [&]() {  // iterations left predicted from the last two polls
+        if (last.it <= prev.it || !(last.rel > 0.0) || !(prev.rel > last.rel)) return true;
+        const double rate = std::log(prev.rel / last.rel) / (last.it - prev.it);
+        const double left = std::log(last.rel / tol) / rate;
+        return left <= 2.0 * every;
+    };
     for (int it = 1; it <= maxit && st0.first && !st0.second; ++it) {
         if (c->opt.use_graph && (c->g_exec && c->g_key == key)) {
             GraphIteration::launch(c);
@@ -402,16 +456,43 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
         } else {
             iteration();
         }
-        if (it % every == 0 || it == maxit) st0 = any_active();
+        if (it % every == 0 || it == maxit) {
+            poll_issue(slot);
+            if (pending >= 0) {  // the previous chunk's poll, read while this chunk runs
+                prev = last;
+                last = poll_wait(pending, pending_it);
+                pending = -1;
+                if (!last.act || last.brk) {
+                    st0 = {last.act, last.brk};
+                    break;
+                }
+            }
+            if (near_end() || it == maxit) {
+                prev = last;
+                last = poll_wait(slot, it);
+                st0 = {last.act, last.brk};
+            } else {
+                pending = slot;
+                pending_it = it;
+            }
+            slot ^= 1;
+        }
     }
-    st0 = any_active();
-    std::vector<double> hst((size_t)S_N * nrhs);
-    IFETI_HIP(hipMemcpyAsync(hst.data(), st, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    IFETI_HIP(hipStreamSynchronize(s));
-    for (int r2 = 0; r2 < nrhs; ++r2) {
-        c->pcg_its += hist[r2 * I_N + I_IT];
-        if (iters) iters[r2] = hist[r2 * I_N + I_IT];
-        if (relres) relres[r2] = hst[r2 * S_N + S_REL];
+    // final state: flags, counts and residuals in one pinned read
+    poll_issue(slot);
+    (void)poll_wait(slot, 0);
+    {
+        const int *hi = (const int *)c->h_poll[slot];
+        const double *hs = (const double *)((const char *)c->h_poll[slot] + soff);
+        std::copy(hi, hi + hist.size(), hist.begin());
+        st0 = {false, false};
+        for (int r2 = 0; r2 < nrhs; ++r2) {
+            st0.first |= hist[r2 * I_N + I_ACT] != 0;
+            st0.second |= hist[r2 * I_N + I_BRK] != 0;
+            c->pcg_its += hist[r2 * I_N + I_IT];
+            if (iters) iters[r2] = hist[r2 * I_N + I_IT];
+            if (relres) relres[r2] = hs[r2 * S_N + S_REL];
+        }
     }
     if (st0.second) {
         set_last_error("PCG breakdown: p^T F p <= 0 or non-finite");
@@ -432,10 +513,10 @@ static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, dou
     const long long nU = c->nU, L = c->L, ns = nU + L;
     hipStream_t s = c->stream;
     // split the packed saddle vector (rhs-major, u then lambda)
-    t_u.alloc((size_t)nU * nrhs);
-    t_u2.alloc((size_t)nU * nrhs);
-    t_L.alloc((size_t)L * nrhs);
-    t_L2.alloc((size_t)L * nrhs);
+    t_u.ensure((size_t)nU * nrhs, s);
+    t_u2.ensure((size_t)nU * nrhs, s);
+    t_L.ensure((size_t)L * nrhs, s);
+    t_L2.ensure((size_t)L * nrhs, s);
     hipLaunchKernelGGL(k_unpack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, in, nU, L, t_u.p, t_L.p, nrhs);
     apply_U(c, t_u.p, t_L2.p, nrhs);                                      // Ů v
     hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
@@ -463,37 +544,46 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     const long long nU = c->nU, L = c->L, ns = nU + L;
     const int m = std::max(1, std::min(maxit, c->opt.fgmres_restart));
     hipStream_t s = c->stream;
-    // Krylov blocks are allocated as the iteration needs them (memory ~ iterations used x load cases)
-    std::vector<std::unique_ptr<DevBuf<double>>> Vb, Zb;
-    std::vector<const double *> hVp, hZp;
-    hVp.reserve(m + 2);  // stable storage: the pointer-table uploads below read it asynchronously
-    hZp.reserve(m + 2);
-    DevBuf<const double *> dVp, dZp;
-    dVp.alloc(m + 1);
-    dZp.alloc(m + 1);
-    auto new_block = [&](std::vector<std::unique_ptr<DevBuf<double>>> &blocks, std::vector<const double *> &hp,
-                         DevBuf<const double *> &dp) {
-        blocks.emplace_back(new DevBuf<double>());
-        blocks.back()->alloc((size_t)ns * nrhs);
-        hp.push_back(blocks.back()->p);
-        const size_t k = hp.size() - 1;  // only the new entry: earlier ones are already on the device
-        IFETI_HIP(hipMemcpyAsync(dp.p + k, hp.data() + k, sizeof(double *), hipMemcpyHostToDevice, s));
-        return blocks.back()->p;
+    // Krylov blocks come from a pool kept in the context: allocated the first time an iteration
+    // count is reached, reused by later solves (memory ~ iterations used x load cases)
+    const size_t nblk_elems = (size_t)ns * nrhs;
+    c->fg_dV.ensure(m + 1, s);
+    c->fg_dZ.ensure(m + 1, s);
+    if (c->fg_hV.size() < (size_t)m + 1) c->fg_hV.resize(m + 1, nullptr);
+    if (c->fg_hZ.size() < (size_t)m + 1) c->fg_hZ.resize(m + 1, nullptr);
+    int nV = 0, nZ = 0;
+    auto new_block = [&](std::vector<std::unique_ptr<DevBuf<double>>> &pool, std::vector<const double *> &hp,
+                         DevBuf<const double *> &dp, int &k) {
+        if ((size_t)k == pool.size()) pool.emplace_back(new DevBuf<double>());
+        DevBuf<double> &b = *pool[k];
+        if (b.n < nblk_elems) {
+            IFETI_HIP(hipStreamSynchronize(s));  // earlier work may still read the old block
+            b.alloc(nblk_elems);
+        }
+        if (hp[k] != b.p) {  // the device table changes only when a block is (re)allocated
+            hp[k] = b.p;
+            IFETI_HIP(hipMemcpyAsync(dp.p + k, hp.data() + k, sizeof(double *), hipMemcpyHostToDevice, s));
+        }
+        return pool[k++]->p;
     };
-    DevBuf<double> w, coef, tu, tL, tL2, tu2, hdev, hall, scd;
-    w.alloc((size_t)ns * nrhs);
-    hdev.alloc((size_t)(m + 1) * nrhs + 16);
-    coef.alloc((size_t)(m + 1) * nrhs + 16);
+    DevBuf<double> &w = c->fg_w, &coef = c->fg_coef, &hdev = c->fg_hdev, &hall = c->fg_hall, &scd = c->fg_scd;
+    DevBuf<double> &tu = c->fg_tu, &tL = c->fg_tL, &tL2 = c->fg_tL2, &tu2 = c->fg_tu2;
+    DevBuf<const double *> &dVp = c->fg_dV, &dZp = c->fg_dZ;
+    w.ensure((size_t)ns * nrhs, s);
+    hdev.ensure((size_t)(m + 1) * nrhs + 16, s);
+    coef.ensure((size_t)(m + 1) * nrhs + 16, s);
     const size_t hstride = (size_t)(m + 1) * nrhs;
-    hall.alloc(2 * hstride + nrhs);  // [h pass 1 | h pass 2 | ||w||^2]
-    scd.alloc(nrhs);
-    double *V0 = new_block(Vb, hVp, dVp);
+    hall.ensure(2 * hstride + nrhs, s);  // [h pass 1 | h pass 2 | ||w||^2]
+    scd.ensure(nrhs, s);
+    double *V0 = new_block(c->fg_V, c->fg_hV, dVp, nV);
     // b = (f, d) packed into V_0 (unnormalised)
     hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, V0, nrhs);
     multidot(c, V0, 0, 1, V0, ns, ns, nrhs, hdev.p);
     std::vector<double> bn(nrhs);
-    IFETI_HIP(hipMemcpyAsync(bn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    IFETI_HIP(hipStreamSynchronize(s));
+    {
+        const double *hp = (const double *)read_back(c, hdev.p, nrhs * sizeof(double));
+        std::copy(hp, hp + nrhs, bn.begin());
+    }
     std::vector<double> beta(nrhs), inv(nrhs);
     for (int r = 0; r < nrhs; ++r) {
         beta[r] = std::sqrt(bn[r]);
@@ -518,8 +608,8 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         bool all = true;
         for (int r = 0; r < nrhs; ++r) all = all && done[r];
         if (all) break;
-        double *Vj = Vb[j]->p;
-        double *Zj = new_block(Zb, hZp, dZp);
+        double *Vj = c->fg_V[j]->p;
+        double *Zj = new_block(c->fg_Z, c->fg_hZ, dZp, nZ);
         int st = apply_prec(c, Vj, Zj, nrhs, inner_tol, c->opt.pcg_maxit, inner, tu, tL, tL2, tu2);
         if (st != IFETI_OK) {
             status = st;
@@ -535,7 +625,7 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         }
         multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hall.p + 2 * hstride);
         inv_sqrt(c, hall.p + 2 * hstride, scd.p, nrhs);
-        double *Vn = new_block(Vb, hVp, dVp);
+        double *Vn = new_block(c->fg_V, c->fg_hV, dVp, nV);
         scale_copy(c, w.p, ns, ns, scd.p, Vn, nrhs);
         {  // one read of [h pass 1 | h pass 2 | ||w||^2]
             const double *hp = (const double *)read_back(c, hall.p, (2 * hstride + nrhs) * sizeof(double));
@@ -582,8 +672,8 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     std::vector<double> yc((size_t)std::max(kmax, 1) * nrhs, 0.0);
     for (int r = 0; r < nrhs; ++r)
         for (int i = 0; i < kdim[r]; ++i) yc[(size_t)r * kmax + i] = g[r][i];
-    DevBuf<double> xs;
-    xs.alloc((size_t)ns * nrhs);
+    DevBuf<double> &xs = c->fg_xs;
+    xs.ensure((size_t)ns * nrhs, s);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, ns * nrhs, 0.0);
     if (kmax > 0) {
         IFETI_HIP(hipMemcpyAsync(coef.p, yc.data(), yc.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -595,8 +685,10 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     hipLaunchKernelGGL(k_pack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, f, nU, d, L, xs.p, nrhs);
     hipLaunchKernelGGL(k_sub, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, xs.p, ns, w.p, ns, xs.p, ns, ns, nrhs, -1.0);
     multidot(c, xs.p, 0, 1, xs.p, ns, ns, nrhs, hdev.p);
-    IFETI_HIP(hipMemcpyAsync(hn.data(), hdev.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    IFETI_HIP(hipStreamSynchronize(s));
+    {
+        const double *hp = (const double *)read_back(c, hdev.p, nrhs * sizeof(double));
+        std::copy(hp, hp + nrhs, hn.begin());
+    }
     bool conv = true;
     for (int r = 0; r < nrhs; ++r) {
         double rel = beta[r] > 0 ? std::sqrt(hn[r]) / beta[r] : 0.0;

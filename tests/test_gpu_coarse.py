@@ -1,0 +1,90 @@
+"""Coarse solve S̊_PP^-1 (Sec. 3.2.1): the partitioned direct solve (interior blocks, separator Schur
+complement) against the oracle's banded Cholesky, through the operators that contain it, for several
+block counts, 1-3 load cases and a 3D band (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import latticegen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    # 10x7 cells: 11x8 vertices, left column clamped -> nP = 160; blocks of unequal size for p = 3
+    "2d": (lambda: latticegen.tiny(2, (10, 7), 3, n_principal=4), (1, 2, 3, 5)),
+    "3d": (lambda: latticegen.tiny(3, (4, 3, 3), 2, n_principal=3), (1, 2)),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    _cuda()
+    from oracle import Model
+    from paper_2308_11371_amd import ifeti
+    print(f"[gpu coarse] case {request.param}", flush=True)
+    make, parts = CASES[request.param]
+    prob = make()
+    m = Model(prob)
+    m.build_reduced_basis()
+    ctx = ifeti.setup(prob, principal_in=m.sigma)
+    yield request.param, parts, m, ctx
+    ctx.close()
+
+
+def test_partitioned_matches_oracle(pair):
+    name, parts, m, ctx = pair
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal((3, m.L))
+    v = rng.standard_normal(m.nU)
+    F_ref = [m.apply_F(lam[r]) for r in range(3)]
+    U_ref = m.apply_U(v)
+    Ut_ref = m.apply_Ut(lam[0])
+    ref_sym = None
+    for p in parts:
+        print(f"[gpu coarse] {name} coarse_parts={p}", flush=True)
+        ctx.set_options(coarse_parts=p)
+        F3 = host(ctx.apply_F(dev(lam.ravel()), nrhs=3)).reshape(3, m.L)
+        for r in range(3):
+            assert rel(F3[r], F_ref[r]) < 1e-11, f"{name} p={p} rhs {r}: {rel(F3[r], F_ref[r]):.2e}"
+            # 1-3 load cases per launch: each load case bitwise as alone
+            assert np.array_equal(F3[r], host(ctx.apply_F(dev(lam[r]))))
+        F2 = host(ctx.apply_F(dev(lam[:2].ravel()), nrhs=2)).reshape(2, m.L)
+        assert np.array_equal(F2, F3[:2])
+        U = host(ctx.apply_U(dev(v)))
+        Ut = host(ctx.apply_Ut(dev(lam[0])))
+        assert rel(U, U_ref) < 1e-11 and rel(Ut, Ut_ref) < 1e-11
+        if p == 1:
+            ref_sym = F3
+        else:
+            assert rel(F3, ref_sym) < 1e-12      # partitioned vs explicit inverse: rounding only
+    ctx.set_options()
+
+
+def test_block_count_beyond_the_band_is_rejected(pair):
+    name, parts, m, ctx = pair
+    from paper_2308_11371_amd import ifeti
+    with pytest.raises(ifeti.IfetiError):
+        ctx.set_options(coarse_parts=10_000)
+    # the context falls back to the explicit inverse and stays usable
+    x = np.random.default_rng(3).standard_normal(m.L)
+    assert rel(host(ctx.apply_F(dev(x))), m.apply_F(x)) < 1e-11
+    ctx.set_options()
