@@ -353,7 +353,6 @@ void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs);
 void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs);
 void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs);
 void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs);
-int reduce_blocks(long long n);
 // V_i = Vp[i] when a device pointer table is given, else V + i*vstride
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
               int nrhs, double *out_dev, const double *const *Vp = nullptr);

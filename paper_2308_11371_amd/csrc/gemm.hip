@@ -218,15 +218,15 @@ constexpr int kMaxCoefK = 40;
 // Stages the cell vectors of columns [col0, col0 + NC), inner rows [kk, kk + kc) into
 // Xs[col][row] (row stride XST), zero-padded to KC rows: plain strided columns, or the
 // fused (weighted) jump transpose from the signed multiplier rows in `gcodes`.  Entries
-// are taken in batches of up to 8 per thread with every load of a batch (codes, then
+// are taken in batches of up to SBMAX per thread with every load of a batch (codes, then
 // multiplier rows and weights) issued before the first is consumed.
-template <int NC, int KC, int NT, int XST>
+template <int NC, int KC, int NT, int XST, int SBMAX>
 __device__ __forceinline__ void stage_chunk(const GemmArgsFrag &g, const double *__restrict__ X,
                                             const int *__restrict__ gcodes, const double *__restrict__ gw, int Kd,
                                             int ldx, long long xbs, int col0, int kk, int kc, double *__restrict__ Xs,
                                             int tid) {
     constexpr int PER = (NC * KC + NT - 1) / NT;
-    constexpr int SB = PER < 4 ? PER : 4;
+    constexpr int SB = PER < SBMAX ? PER : SBMAX;
 #pragma unroll 1
     for (int i0 = 0; i0 < PER; i0 += SB) {
         int2 cd[SB];
@@ -316,7 +316,7 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
         for (int kk = 0; kk < Kd; kk += FKC) {
             const int kc = min(FKC, Kd - kk);
             __syncthreads();  // previous chunk fully consumed
-            stage_chunk<NC, FKC, NT, FXS>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
+            stage_chunk<NC, FKC, NT, FXS, 4>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
             for (int e = tid; e < K * NC; e += NT) {
                 const int k = e / NC, cc = e % NC, col = col0 + cc;
                 double v = 0.0;
@@ -467,7 +467,8 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
         for (int kk = kbeg; kk < kend; kk += KCB) {
             const int kc = min(KCB, kend - kk);
             __syncthreads();
-            stage_chunk<NC, KCB, NT, XSB>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
+            // one entry at a time: the chunk loop repeats often and occupancy hides the latency
+            stage_chunk<NC, KCB, NT, XSB, 1>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
             for (int e = tid; e < K * NC; e += NT) {
                 const int k = e / NC, cc = e % NC, col = col0 + cc;
                 double v = 0.0;

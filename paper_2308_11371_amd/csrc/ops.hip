@@ -759,22 +759,46 @@ __device__ inline double block_reduce(double v, double *sh) {
     return r;
 }
 
-// partial[(rhs*nv + i)*nblk + b] = sum over block b's chunk of V_i . w (per rhs)
-__global__ __launch_bounds__(kB) void k_multidot_partial(const double *__restrict__ V, long long vstride,
-                                                         const double *const *__restrict__ Vp, int nv,
-                                                         const double *__restrict__ w, long long n, long long rs,
-                                                         int nblk, double *__restrict__ partial) {
-    __shared__ double sh[kB];
-    int b = blockIdx.x, rhs = blockIdx.y;
-    long long chunk = (n + nblk - 1) / nblk;
-    long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+// partial[(rhs*nv + i)*nblk + b] = sum over block b's chunk of V_i . w (per rhs).  The vectors
+// are taken G at a time so each pass reads w once beside G vector streams; per thread the
+// elements are summed in increasing order, then a fixed butterfly per wave and the 4 waves in
+// order.
+template <int G>
+__global__ __launch_bounds__(256) void k_multidot_partial(const double *__restrict__ V, long long vstride,
+                                                          const double *const *__restrict__ Vp, int nv,
+                                                          const double *__restrict__ w, long long n, long long rs,
+                                                          int nblk, double *__restrict__ partial) {
+    __shared__ double sh[4][G];
+    const int b = blockIdx.x, rhs = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long i0 = b * chunk, i1 = min(n, i0 + chunk);
     const double *wr = w + rhs * rs;
-    for (int i = 0; i < nv; ++i) {
-        const double *vr = (Vp ? Vp[i] : V + i * vstride) + rhs * rs;
-        double acc = 0.0;
-        for (long long t = i0 + threadIdx.x; t < i1; t += kB) acc += vr[t] * wr[t];
-        acc = block_reduce(acc, sh);
-        if (threadIdx.x == 0) partial[((size_t)rhs * nv + i) * nblk + b] = acc;
+    for (int g0 = 0; g0 < nv; g0 += G) {
+        const int ng = min(G, nv - g0);
+        const double *vp[G];
+        double acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            vp[g] = g < ng ? (Vp ? Vp[g0 + g] : V + (g0 + g) * vstride) + rhs * rs : wr;
+            acc[g] = 0.0;
+        }
+        for (long long t = i0 + threadIdx.x; t < i1; t += 256) {
+            const double x = wr[t];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (g < ng) acc[g] += vp[g][t] * x;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            for (int off = 32; off > 0; off >>= 1) acc[g] += __shfl_xor(acc[g], off);
+        if (lane == 0)
+#pragma unroll
+            for (int g = 0; g < G; ++g) sh[wave][g] = acc[g];
+        __syncthreads();
+        if (threadIdx.x < ng)
+            partial[((size_t)rhs * nv + g0 + threadIdx.x) * nblk + b] =
+                ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -861,7 +885,7 @@ void ensure_work(ifeti_ctx *c, int nrhs) {
         c->w_R.ensure(cols * c->K * c->n_r, s);
         c->w_H.ensure(cols * c->K * c->n_r, s);
     }
-    c->w_red.ensure((size_t)256 * 64 * nrhs + 1024, s);
+    c->w_red.ensure((size_t)2048 * 64 * nrhs + 1024, s);
 }
 
 void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, int nrhs, bool weights) {
@@ -1235,17 +1259,17 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
 }
 
 // ------------------------------------------------------------------ vector helpers
-int reduce_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(256, (n + 4095) / 4096)); }
 
 // out_dev[rhs*nv + i] = V_i[rhs] . w[rhs]
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,
               int nrhs, double *out_dev, const double *const *Vp) {
-    int nblk = reduce_blocks(n);
+    // enough workgroups to keep the vector streams in flight (about 2K elements per workgroup)
+    const int nblk = (int)std::max<long long>(1, std::min<long long>(2048, (n + 2047) / 2048));
     size_t need = (size_t)nblk * nv * nrhs;
     c->w_red.ensure(need, c->stream);
     Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs, 8.0 * (double)n * (nv + 1) * nrhs);
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, nrhs), dim3(kB), 0, c->stream, V, vstride, Vp, nv, w, n, rs, nblk,
-                       c->w_red.p);
+    hipLaunchKernelGGL(k_multidot_partial<8>, dim3(nblk, nrhs), dim3(256), 0, c->stream, V, vstride, Vp, nv, w, n, rs,
+                       nblk, c->w_red.p);
     hipLaunchKernelGGL(k_reduce_partials, dim3(nv * nrhs), dim3(kB), 0, c->stream, c->w_red.p, nblk, out_dev);
     IFETI_HIP(hipGetLastError());
 }
