@@ -212,8 +212,10 @@ def run_c3(args):
 def run_c5(args):
     """Differentiation form on c5 (3D 12x12x12 cells, 1536 dof/cell, 16 principal cells, per-cell strut
     widths uniform in [0.15, 0.30]): compliance and its gradient with respect to all 1728 widths through
-    the torch.autograd.Function (width update with refreshed ROM coefficients, FP64 solve to relres 1e-8,
-    adjoint gradient kernel), timed after one untimed evaluation; then each part timed on its own."""
+    the torch.autograd.Function (width update: cell operators rebuilt, which the true operator and the
+    reduced local solves of (46b) use, while the principal bank, coefficients and coarse factor are
+    kept; FP64 solve to relres 1e-8; adjoint gradient kernel), timed after one untimed evaluation; then
+    each part timed on its own."""
     import torch
     import latticegen
     from paper_2308_11371_amd import ifeti
@@ -254,7 +256,7 @@ def run_c5(args):
     torch.cuda.synchronize()
     out["gradient_kernel_s"] = time.perf_counter() - t1
     out.update(outer_its=int(info["outer_its"][0]), pcg_its=int(info["inner_its"][0]),
-               relres=float(info["relres"][0]), compliance=float(c), grad_norm=float(torch.linalg.norm(g)))
+               relres=float(info["relres"][0]), compliance=float(c.detach()), grad_norm=float(torch.linalg.norm(g)))
     log(f"form c5 gradient: {out['compliance_and_gradient_s']:.3f}s (update {out['width_update_s']:.3f}, "
         f"solve {out['solve_s']:.3f}, gradient {out['gradient_kernel_s'] * 1e3:.2f} ms)")
     ctx.close()
