@@ -224,6 +224,36 @@ int ifeti_compliance_grad(ifeti_ctx *ctx, const double *f, const double *u, doub
  * converges to the solution for the new widths.  EINVAL on a non-positive width. */
 int ifeti_update_widths(ifeti_ctx *ctx, const double *widths);
 
+/* ---- Standard (exact) FETI-DP, the paper's comparator (Sec. 2.2.4) ----
+ * Factorise every cell's K_rr^(s) (batched blocked Cholesky on the GPU) and keep, per cell, the
+ * factor, F_dd = [K_rr^-1]_dd (eq. (27)), the Dirichlet Schur complement S_dd (eq. (30)), the
+ * dual rows of U_rp = K_rr^-1 K_rp (eq. (29)), S_pp (eq. (22)) and K_pr; assemble the exact
+ * S_PP and build its coarse solver.  Needs ifeti_build_cells (not the reduced basis); device
+ * memory grows by N (n_r^2 + 2 n_d^2 + n_p (n_d + n_p + n_r)) doubles plus the coarse solver
+ * (c2: 14 GB), and a 6 GB workspace during the call.  ifeti_update_widths invalidates it.
+ * ENOTSPD if a cell's K_rr is not positive definite. */
+int ifeti_build_exact(ifeti_ctx *ctx);
+
+/* out = F lam, the exact dual operator of eq. (24) (B_R K_RR^-1 B_R^T plus the coarse term with
+ * the exact S_PP), lam/out dev L x nrhs. */
+int ifeti_exact_apply_F(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
+
+/* out = M_D^-1 r = sum_s D B_d^(s) S_dd^(s) B_d^(s)T D r, the exact Dirichlet preconditioner
+ * (eq. (30)), r/out dev L x nrhs. */
+int ifeti_exact_apply_MD(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
+
+/* Standard FETI-DP solve of (16): the right-hand side d̄ of eq. (25), PCG on F with M_D^-1 from
+ * lam_0 = 0 to ||r|| <= tol ||d̄||, then u_P by eq. (21) and u_R by eq. (20).
+ *   f dev nU x nrhs, d dev L x nrhs, u dev nU x nrhs (eq. (13) order), lam dev L x nrhs;
+ *   iters, relres host arrays of nrhs (nullable).  EMAXIT keeps the last iterate. */
+int ifeti_exact_solve(ifeti_ctx *ctx, const double *f, const double *d, double *u, double *lam, int nrhs,
+                      double tol, int maxit, int *iters, double *relres);
+
+/* Host copies of cell s's exact blocks (any pointer may be NULL): Fdd, Sdd n_d x n_d, Spp
+ * n_p x n_p, Ud n_d x n_p (row-major), and the device bytes the exact form holds. */
+int ifeti_exact_cell_blocks(ifeti_ctx *ctx, int s, double *Fdd, double *Sdd, double *Spp, double *Ud,
+                            long long *device_bytes);
+
 #ifdef __cplusplus
 }
 #endif

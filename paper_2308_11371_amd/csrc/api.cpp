@@ -181,7 +181,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         REQ(opt->coarse_parts >= 0, "coarse_parts must be >= 0");
         if (opt->coarse_parts != c->opt.coarse_parts) {
             c->opt.coarse_parts = opt->coarse_parts;
-            if (c->rom_built) build_coarse_partition(c);
+            if (c->rom_built) build_coarse_partition(c, c->co);
+            if (c->ex_built) build_coarse_partition(c, c->co_ex);
         }
         return IFETI_OK;
     });
@@ -386,6 +387,78 @@ int ifeti_update_widths(ifeti_ctx *c, const double *widths) {
         IFETI_HIP(hipStreamSynchronize(c->stream));
         c->snap_valid = true;
         ++c->rom_gen;
+        c->ex_built = false;  // the exact factorisation belongs to the previous widths
+        return IFETI_OK;
+    });
+}
+
+#define EXACT_READY(c, nrhs)                                                      \
+    REQ(c && c->ex_built, "exact FETI-DP not built (ifeti_build_exact)");        \
+    REQ((nrhs) >= 1 && (long long)c->N * (nrhs) < (1LL << 31), "nrhs out of range")
+
+int ifeti_build_exact(ifeti_ctx *c) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        c->ex_built = false;
+        build_exact(c);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_exact_apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs) {
+    return guarded([&]() {
+        EXACT_READY(c, nrhs);
+        REQ(lam && out && lam != out, "bad pointers");
+        apply_F_exact(c, lam, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_exact_apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+    return guarded([&]() {
+        EXACT_READY(c, nrhs);
+        REQ(r && out && r != out, "bad pointers");
+        apply_MD_exact(c, r, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_exact_solve(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
+                      int maxit, int *iters, double *relres) {
+    return guarded([&]() {
+        EXACT_READY(c, nrhs);
+        REQ(f && d && u && lam, "bad pointers");
+        REQ(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+        const int st = solve_exact(c, f, d, u, lam, nrhs, tol, maxit, iters, relres);
+        if (st == IFETI_EMAXIT) set_last_error("PCG reached the iteration limit");
+        return st;
+    });
+}
+
+int ifeti_exact_cell_blocks(ifeti_ctx *c, int s, double *Fdd, double *Sdd, double *Spp, double *Ud,
+                            long long *device_bytes) {
+    return guarded([&]() {
+        REQ(c && c->ex_built, "exact FETI-DP not built (ifeti_build_exact)");
+        REQ(s >= 0 && s < c->N, "cell index out of range");
+        const size_t nd = c->n_d, np = c->n_p;
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        if (Fdd) IFETI_HIP(hipMemcpy(Fdd, c->ex_Fdd.p + s * nd * nd, nd * nd * sizeof(double), hipMemcpyDeviceToHost));
+        if (Sdd) IFETI_HIP(hipMemcpy(Sdd, c->ex_Sdd.p + s * nd * nd, nd * nd * sizeof(double), hipMemcpyDeviceToHost));
+        if (Spp) IFETI_HIP(hipMemcpy(Spp, c->ex_Spp.p + s * np * np, np * np * sizeof(double), hipMemcpyDeviceToHost));
+        if (Ud) {
+            std::vector<double> C(np * nd);
+            IFETI_HIP(hipMemcpy(C.data(), c->ex_C.p + s * np * nd, C.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (size_t j = 0; j < nd; ++j)
+                for (size_t a = 0; a < np; ++a) Ud[j * np + a] = C[a * nd + j];
+        }
+        if (device_bytes) {
+            const CoarseSolver &co = c->co_ex;
+            long long b = 0;
+            for (size_t n : {c->ex_L.n, c->ex_Fdd.n, c->ex_Sdd.n, c->ex_C.n, c->ex_Spp.n, c->ex_Kpr.n, co.SPPinv.n,
+                             co.SPPt.n, co.cp_M1.n, co.cp_M2.n, co.cp_M3.n})
+                b += (long long)n * 8;
+            *device_bytes = b;
+        }
         return IFETI_OK;
     });
 }

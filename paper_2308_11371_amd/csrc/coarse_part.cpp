@@ -127,10 +127,15 @@ Layout layout(int n, int bw, int p) {
 
 }  // namespace
 
-void build_coarse_partition(ifeti_ctx *c) {
-    c->cp_p = 0;
-    c->cp_ns = 0;
-    const int n = c->nP, bw = c->h_bw;
+std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw) {
+    const Band A{band, n, bw};
+    return band_chol(A, 0, n);
+}
+
+void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co) {
+    co.cp_p = 0;
+    co.cp_ns = 0;
+    const int n = c->nP, bw = co.bw;
     if (n == 0 || c->opt.coarse_parts == 1) return;
     Layout best;
     if (c->opt.coarse_parts >= 2) {
@@ -147,7 +152,7 @@ void build_coarse_partition(ifeti_ctx *c) {
         if (best.lo.empty() || best.bytes > 0.6 * sym) return;
     }
     const int p = best.p, ns = best.ns;
-    const Band A{c->h_Sband, n, bw};
+    const Band A{co.h_Sband, n, bw};
     // interior inverses and their couplings to the adjacent separators
     std::vector<std::vector<double>> Ainv(p), EL(p), ER(p);
     for (int i = 0; i < p; ++i) {
@@ -263,17 +268,17 @@ void build_coarse_partition(ifeti_ctx *c) {
             for (int t = 0; t < br; ++t) M3.push_back(-ER[i][(size_t)t * m + q]);
         }
     }
-    c->cp_M1.upload(M1, c->stream);
-    c->cp_M2.upload(Sinv, c->stream);
-    c->cp_M3.upload(M3, c->stream);
-    c->cp_R1.upload(R1, c->stream);
-    c->cp_R2.upload(R2, c->stream);
-    c->cp_R3.upload(R3, c->stream);
-    c->w_cg.alloc((size_t)ns * 3);
-    c->w_cw.alloc((size_t)n * 3);
+    co.cp_M1.upload(M1, c->stream);
+    co.cp_M2.upload(Sinv, c->stream);
+    co.cp_M3.upload(M3, c->stream);
+    co.cp_R1.upload(R1, c->stream);
+    co.cp_R2.upload(R2, c->stream);
+    co.cp_R3.upload(R3, c->stream);
+    co.w_cg.alloc((size_t)ns * 3);
+    co.w_cw.alloc((size_t)n * 3);
     IFETI_HIP(hipStreamSynchronize(c->stream));
-    c->cp_p = p;
-    c->cp_ns = ns;
+    co.cp_p = p;
+    co.cp_ns = ns;
 }
 
 }  // namespace ifeti

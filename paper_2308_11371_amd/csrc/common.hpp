@@ -118,6 +118,23 @@ struct CoarseRow {
     int xlo, len, out, pad;
 };
 
+// Direct solver of an assembled coarse problem S_PP (banded in the lexicographic vertex order).
+struct CoarseSolver {
+    std::vector<double> h_Sband;  // lower band before factorisation, [i][i-j], width bw+1
+    int bw = 0;
+    DevBuf<double> SPPinv;        // [nP][nP] explicit inverse
+    DevBuf<double> SPPt;          // its lower-triangle 64x64 tiles, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
+    DevBuf<int> sym_tiles;        // [tile] -> (I, J)
+    DevBuf<double> w_symP;        // [tile][rhs][row partial 64 | column partial 64]
+    int nT = 0;
+    // partitioned form (interior blocks separated by bandwidth-wide separators): phase 1 the
+    // separator right-hand side, phase 2 the separator Schur-complement inverse, phase 3 the interiors
+    int cp_p = 0, cp_ns = 0;      // interior blocks (0: not built), separator rows
+    DevBuf<double> cp_M1, cp_M2, cp_M3;
+    DevBuf<CoarseRow> cp_R1, cp_R2, cp_R3;
+    DevBuf<double> w_cg, w_cw;    // separator rhs [rhs][ns], assembled input [rhs][nP]
+};
+
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
 // enabled, HIP-event durations recorded on the context stream.
 struct KernelStat {
@@ -191,20 +208,14 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> UrpT;         // [k][n_p][n_r]
     ifeti::DevBuf<double> Wc;           // [s][n_p][n_d] per-cell sum_k pi_sk (T_dr U_rp^(k))^T
     ifeti::DevBuf<double> Kinv;         // [n_r][k][n_r]: row r*K + k is row r of K_rr^(sigma_k)^-1
-    ifeti::DevBuf<double> SPPinv;       // [nP][nP]
-    // lower-triangle 64x64 tiles of SPPinv, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
-    ifeti::DevBuf<double> SPPt;
-    ifeti::DevBuf<int> sym_tiles;       // [tile] -> (I, J)
-    ifeti::DevBuf<double> w_symP;       // [tile][rhs][row partial 64 | column partial 64]
-    int nT = 0;
-    // partitioned coarse solve (interior blocks separated by bandwidth-wide separators): phase 1 the
-    // separator right-hand side, phase 2 the separator Schur-complement inverse, phase 3 the interiors
-    std::vector<double> h_Sband;        // lower band of S̊_PP before factorisation, [i][i-j], width bw+1
-    int h_bw = 0;
-    int cp_p = 0, cp_ns = 0;            // interior blocks (0: not built), separator rows
-    ifeti::DevBuf<double> cp_M1, cp_M2, cp_M3;
-    ifeti::DevBuf<ifeti::CoarseRow> cp_R1, cp_R2, cp_R3;
-    ifeti::DevBuf<double> w_cg, w_cw;   // separator rhs [rhs][ns], assembled input [rhs][nP]
+    ifeti::CoarseSolver co;             // S̊_PP of the ROM operators (Sec. 3.2.1)
+    // standard (exact) FETI-DP (Sec. 2.2.4): factor of every K_rr^(s) [s][n_r][n_r] (lower,
+    // column-major), F_dd and S_dd [s][n_d][n_d], U_d^T [s][n_p][n_d], S_pp [s][n_p][n_p],
+    // K_pr [s][n_p][n_r]; the exact S_PP and its solver; work vectors of the exact solve
+    bool ex_built = false;
+    ifeti::DevBuf<double> ex_L, ex_Fdd, ex_Sdd, ex_C, ex_Spp, ex_Kpr;
+    ifeti::CoarseSolver co_ex;
+    ifeti::DevBuf<double> ex_w, ex_g, ex_z, ex_d;
     bool rom_built = false;
     struct LPCopy {                     // fp32 / bf16 copies of a bank array (precision form)
         const double *src = nullptr;
@@ -304,8 +315,10 @@ void launch_pulled_back(ifeti_ctx *c);
 void launch_stiffness(ifeti_ctx *c);
 int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in,
                   std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
-void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw);
-void build_coarse_partition(ifeti_ctx *c);
+void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw);
+void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co);
+// lower-band Cholesky factor L[i][i-j] of the symmetric band matrix band[i][i-j] (ENOTSPD if not SPD)
+std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw);
 
 // gemm.hip
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
@@ -333,8 +346,16 @@ void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_
 void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long long b_rs, double sgn, double *zP,
                         long long z_rs, int nrhs);
 void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs);
+// c_s = C_s B_d^(s)T lam (C [s][n_p][n_d], gather fused); Y_s (+)= C_s^T yP[A_p(s)] (Y [col][n_d])
+void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long long lam_rs, double *out, int nrhs,
+                       const char *tag);
+void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long yP_rs, double *Y, int nrhs,
+                      bool accumulate, const char *tag);
 void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
                      double scale);
+// the same with an explicit coarse solver (the exact FETI-DP operators carry their own)
+void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
+                  int nrhs, double scale);
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs);
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
@@ -343,7 +364,7 @@ void release_graph(ifeti_ctx *c);
 // copy `bytes` from device memory to pinned host staging on the context stream and wait for it by
 // spinning on an event (no blocking stream synchronisation); returns the staging pointer
 const void *read_back(ifeti_ctx *c, const void *dev, size_t bytes);
-void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale);
+void coarse_reduce(ifeti_ctx *c, const CoarseSolver &co, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);
 void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
@@ -365,9 +386,18 @@ void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const 
 // gradient.hip
 void compliance_grad(ifeti_ctx *c, const double *f, const double *u, double *grad, double *comp_host, int nrhs);
 
-// solver.hip
+// solver.hip (exact: the standard FETI-DP operators F and M_D instead of F̊ and M̊_D^-1)
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
-                    double *relres);
+                    double *relres, bool exact = false);
+
+// exact.hip: standard FETI-DP (Sec. 2.2.4)
+void build_exact(ifeti_ctx *c);
+void apply_F_exact(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
+                   double *dot_part = nullptr);
+void apply_MD_exact(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
+                    double *dot_part = nullptr);
+int solve_exact(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
+                int maxit, int *iters, double *relres);
 int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, double *lam, int nrhs, double tol,
                  int maxit, double inner_tol, int *outer, int *inner_total, double *relres);
 }  // namespace ifeti

@@ -415,18 +415,18 @@ __global__ __launch_bounds__(kBlock) void k_sym_pack(const double *__restrict__ 
     }
 }
 
-void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int bw) {
+void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw) {
     DevBuf<double> band;
     band.upload(band_L, c->stream);
-    c->SPPinv.alloc((size_t)c->nP * c->nP);
+    co.SPPinv.alloc((size_t)c->nP * c->nP);
     hipLaunchKernelGGL(k_band_inverse, dim3(blocks_for(c->nP, 64)), dim3(64), 0, c->stream, band.p, c->nP, bw,
-                       c->SPPinv.p);
+                       co.SPPinv.p);
     IFETI_HIP(hipGetLastError());
     const int nT = (c->nP + 63) / 64;
     const size_t ntiles = (size_t)nT * (nT + 1) / 2;
-    c->nT = nT;
-    c->SPPt.alloc(ntiles * 4096);
-    hipLaunchKernelGGL(k_sym_pack, dim3(nT, nT), dim3(kBlock), 0, c->stream, c->SPPinv.p, c->nP, c->SPPt.p);
+    co.nT = nT;
+    co.SPPt.alloc(ntiles * 4096);
+    hipLaunchKernelGGL(k_sym_pack, dim3(nT, nT), dim3(kBlock), 0, c->stream, co.SPPinv.p, c->nP, co.SPPt.p);
     IFETI_HIP(hipGetLastError());
     std::vector<int> tl(2 * ntiles);
     for (int I = 0; I < nT; ++I)
@@ -435,8 +435,8 @@ void coarse_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int 
             tl[2 * t] = I;
             tl[2 * t + 1] = J;
         }
-    c->sym_tiles.upload(tl, c->stream);
-    c->w_symP.alloc(ntiles * 3 * 128);  // up to 3 load cases per pass
+    co.sym_tiles.upload(tl, c->stream);
+    co.w_symP.alloc(ntiles * 3 * 128);  // up to 3 load cases per pass
     IFETI_HIP(hipStreamSynchronize(c->stream));
 }
 

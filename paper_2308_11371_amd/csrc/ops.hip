@@ -931,10 +931,10 @@ void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *
                        c->n_p, nrhs);
 }
 
-void coarse_reduce(ifeti_ctx *c, double *y, long long y_rs, int nrhs, double scale) {
-    const double n = (double)c->nP, nt = (double)c->nT * (c->nT + 1) / 2;
+void coarse_reduce(ifeti_ctx *c, const CoarseSolver &co, double *y, long long y_rs, int nrhs, double scale) {
+    const double n = (double)c->nP, nt = (double)co.nT * (co.nT + 1) / 2;
     Prof prof(c, "coarse_reduce", (double)nrhs * nt * 128.0, 8.0 * (nt * 128.0 + n) * nrhs);
-    hipLaunchKernelGGL(k_sym_reduce, dim3(c->nT, nrhs), dim3(1024), 0, c->stream, c->w_symP.p, c->nP, c->nT, nrhs, y,
+    hipLaunchKernelGGL(k_sym_reduce, dim3(co.nT, nrhs), dim3(1024), 0, c->stream, co.w_symP.p, c->nP, co.nT, nrhs, y,
                        y_rs, scale);
 }
 
@@ -951,9 +951,9 @@ void coarse_rows(ifeti_ctx *c, const double *M, const CoarseRow *rows, int nrows
 }
 
 // y = scale * S̊_PP^-1 z through the three phases of the partitioned solve (1 to 3 load cases)
-void coarse_partitioned(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
-                        double scale) {
-    const int n = c->nP, ns = c->cp_ns, nI = n - ns;
+void coarse_partitioned(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
+                        int nrhs, double scale) {
+    const int n = c->nP, ns = co.cp_ns, nI = n - ns;
     // separator phases have few rows (one workgroup per row keeps enough loads in flight); the
     // interior phase has many (two waves per row)
     auto launch = [&](auto wpr, const double *M, const CoarseRow *rows, int nrows, const double *x, long long x_rs,
@@ -961,61 +961,61 @@ void coarse_partitioned(ifeti_ctx *c, const double *z, long long z_rs, double *y
                       const double *cz, int ncopy) {
         constexpr int W = decltype(wpr)::value;
         if (nrhs == 1)
-            coarse_rows<1, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+            coarse_rows<1, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, co.w_cw.p,
                               n, ncopy);
         else if (nrhs == 2)
-            coarse_rows<2, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+            coarse_rows<2, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, co.w_cw.p,
                               n, ncopy);
         else
-            coarse_rows<3, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, c->w_cw.p,
+            coarse_rows<3, W>(c, M, rows, nrows, x, x_rs, alpha, yy, yy_rs, alpha2, y2, y2_rs, cz, z_rs, co.w_cw.p,
                               n, ncopy);
     };
     using Sep = std::integral_constant<int, 4>;
     using Int = std::integral_constant<int, 2>;
     {
-        Prof prof(c, "coarse_sep_rhs", 2.0 * (double)c->cp_M1.n * nrhs,
-                  8.0 * ((double)c->cp_M1.n + (double)ns * nrhs + 2.0 * n * nrhs) + 24.0 * ns);
-        launch(Sep{}, c->cp_M1.p, c->cp_R1.p, ns, z, z_rs, -1.0, c->w_cg.p, ns, 0.0, nullptr, 0, z, n);
+        Prof prof(c, "coarse_sep_rhs", 2.0 * (double)co.cp_M1.n * nrhs,
+                  8.0 * ((double)co.cp_M1.n + (double)ns * nrhs + 2.0 * n * nrhs) + 24.0 * ns);
+        launch(Sep{}, co.cp_M1.p, co.cp_R1.p, ns, z, z_rs, -1.0, co.w_cg.p, ns, 0.0, nullptr, 0, z, n);
     }
     {
         Prof prof(c, "coarse_sep_solve", 2.0 * (double)ns * ns * nrhs,
                   8.0 * ((double)ns * ns + 3.0 * ns * nrhs) + 24.0 * ns);
-        launch(Sep{}, c->cp_M2.p, c->cp_R2.p, ns, c->w_cg.p, ns, 1.0, c->w_cw.p, n, scale, y, y_rs, nullptr, 0);
+        launch(Sep{}, co.cp_M2.p, co.cp_R2.p, ns, co.w_cg.p, ns, 1.0, co.w_cw.p, n, scale, y, y_rs, nullptr, 0);
     }
     {
-        Prof prof(c, "coarse_interior", 2.0 * (double)c->cp_M3.n * nrhs,
-                  8.0 * ((double)c->cp_M3.n + (double)n * nrhs + (double)nI * nrhs) + 24.0 * nI);
-        launch(Int{}, c->cp_M3.p, c->cp_R3.p, nI, c->w_cw.p, n, scale, y, y_rs, 0.0, nullptr, 0, nullptr, 0);
+        Prof prof(c, "coarse_interior", 2.0 * (double)co.cp_M3.n * nrhs,
+                  8.0 * ((double)co.cp_M3.n + (double)n * nrhs + (double)nI * nrhs) + 24.0 * nI);
+        launch(Int{}, co.cp_M3.p, co.cp_R3.p, nI, co.w_cw.p, n, scale, y, y_rs, 0.0, nullptr, 0, nullptr, 0);
     }
 }
 
-void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
-                     double scale) {
+void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
+                  int nrhs, double scale) {
     if (c->nP == 0) return;
-    if (nrhs < 4 && c->cp_p >= 2) {
-        coarse_partitioned(c, z, z_rs, y, y_rs, nrhs, scale);
+    if (nrhs < 4 && co.cp_p >= 2) {
+        coarse_partitioned(c, co, z, z_rs, y, y_rs, nrhs, scale);
     } else if (nrhs < 4) {
-        const double n = (double)c->nP, nt = (double)c->nT * (c->nT + 1) / 2;
+        const double n = (double)c->nP, nt = (double)co.nT * (co.nT + 1) / 2;
         {
             // algorithmic: the symmetric operator's n(n+1)/2 entries read once, the vectors, the partials
             Prof prof(c, "coarse_symv", 2.0 * n * n * nrhs,
                       8.0 * (n * (n + 1) / 2 + 2.0 * n * nrhs + nt * 128.0 * nrhs));
             const unsigned ntiles = (unsigned)nt;
             if (nrhs == 1)
-                hipLaunchKernelGGL(k_sym_tiles<1>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
-                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+                hipLaunchKernelGGL(k_sym_tiles<1>, dim3(ntiles), dim3(256), 0, c->stream, co.SPPt.p,
+                                   co.sym_tiles.p, c->nP, z, z_rs, co.w_symP.p);
             else if (nrhs == 2)
-                hipLaunchKernelGGL(k_sym_tiles<2>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
-                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+                hipLaunchKernelGGL(k_sym_tiles<2>, dim3(ntiles), dim3(256), 0, c->stream, co.SPPt.p,
+                                   co.sym_tiles.p, c->nP, z, z_rs, co.w_symP.p);
             else
-                hipLaunchKernelGGL(k_sym_tiles<3>, dim3(ntiles), dim3(256), 0, c->stream, c->SPPt.p,
-                                   c->sym_tiles.p, c->nP, z, z_rs, c->w_symP.p);
+                hipLaunchKernelGGL(k_sym_tiles<3>, dim3(ntiles), dim3(256), 0, c->stream, co.SPPt.p,
+                                   co.sym_tiles.p, c->nP, z, z_rs, co.w_symP.p);
             IFETI_HIP(hipGetLastError());
         }
-        coarse_reduce(c, y, y_rs, nrhs, scale);
+        coarse_reduce(c, co, y, y_rs, nrhs, scale);
     } else {
         GemmGroup g;
-        g.A = c->SPPinv.p;
+        g.A = co.SPPinv.p;
         g.X = z;
         g.Kd = c->nP;
         g.ldx = (int)z_rs;
@@ -1024,6 +1024,11 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
         g.scale = scale;
         gemm(c, &g, 1, y, (int)y_rs, (long long)nrhs * y_rs, c->nP, nrhs, false, nrhs, "coarse_gemm", false);
     }
+}
+
+void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, long long y_rs, int nrhs,
+                     double scale) {
+    coarse_solve(c, c->co, z, z_rs, y, y_rs, nrhs, scale);
 }
 
 // ------------------------------------------------------------------ F̊ (48)
@@ -1040,15 +1045,45 @@ void combine_coarse_maps(ifeti_ctx *c) {
     IFETI_HIP(hipGetLastError());
 }
 
+// c_s = C_s B_d^(s)T lam for every column (rhs, s); C is [s][n_p][n_d]
+void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long long lam_rs, double *out, int nrhs,
+                       const char *tag) {
+    const int N = c->N, nd = c->n_d, np = c->n_p, cols = N * nrhs;
+    Prof prof(c, tag, 2.0 * (double)cols * np * nd,
+              8.0 * (double)N * np * nd + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
+    if (np <= 8)
+        hipLaunchKernelGGL((k_restrict_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
+                           N, nd, np, cols, out);
+    else
+        // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
+        // coarse branch from crowding it
+        hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, C, c->g_gather.p, lam,
+                           lam_rs, N, nd, np, cols, out);
+    IFETI_HIP(hipGetLastError());
+}
+
+// Y_s (+)= C_s^T yP[A_p(s)] for every column (rhs, s); Y is [col][n_d]
+void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long yP_rs, double *Y, int nrhs,
+                      bool accumulate, const char *tag) {
+    const int N = c->N, nd = c->n_d, np = c->n_p, cols = N * nrhs;
+    Prof prof(c, tag, 2.0 * (double)cols * np * nd, 8.0 * (double)N * np * nd + 8.0 * (double)cols * nd);
+    if (np <= 8)
+        hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N, nd,
+                           np, cols, Y, accumulate ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N,
+                           nd, np, cols, Y, accumulate ? 1 : 0);
+    IFETI_HIP(hipGetLastError());
+}
+
 // F̊ lam = B_d [sum_k delta_k F_dd^(k) B_d^T lam + C^T A_p S̊_PP^-1 A_p^T C B_d^T lam]:
 // the coarse branch (restriction, assembly, symmetric coarse solve) runs on the
 // side stream while the main stream runs the dominant contraction; the
 // prolongation is folded into the final scatter.
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
     ensure_work(c, nrhs);
-    const int N = c->N, nd = c->n_d, np = c->n_p, K = c->K;
+    const int N = c->N, nd = c->n_d, K = c->K;
     const int cols = N * nrhs;
-    const double cmap_bytes = 8.0 * (double)N * np * nd;
     {
         // the dominant contraction runs beside the coarse branch, into its own buffer
         SideStream side(c);
@@ -1057,29 +1092,10 @@ void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const doubl
         g1.K = K;
         gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
     }
-    {
-        Prof prof(c, "F_restrict", 2.0 * (double)cols * np * nd,
-                  cmap_bytes + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
-        if (np <= 8)
-            hipLaunchKernelGGL((k_restrict_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, c->Wc.p, c->g_gather.p, lam,
-                               c->L, N, nd, np, cols, c->w_c.p);
-        else
-            // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
-            // coarse branch from crowding it
-            hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, c->Wc.p,
-                               c->g_gather.p, lam, c->L, N, nd, np, cols, c->w_c.p);
-    }
+    op_restrict_cells(c, c->Wc.p, lam, c->L, c->w_c.p, nrhs, "F_restrict");
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
     op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
-    {
-        Prof prof(c, "F_prolong", 2.0 * (double)cols * np * nd, cmap_bytes + 8.0 * (double)cols * nd);
-        if (np <= 8)
-            hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, c->Wc.p, c->g_Ap.p,
-                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
-        else
-            hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, c->Wc.p, c->g_Ap.p,
-                               c->w_yP.p, (long long)c->nP, N, nd, np, cols, c->w_Yc.p, 0);
-    }
+    op_prolong_cells(c, c->Wc.p, c->w_yP.p, c->nP, c->w_Yc.p, nrhs, false, "F_prolong");
     join_side(c);
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, c->w_Yc.p);
     c->applies[IFETI_OP_F] += nrhs;

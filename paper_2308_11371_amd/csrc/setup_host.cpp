@@ -923,8 +923,8 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                 band[(size_t)I * (bw + 1) + (I - J)] += 0.5 * (X[i * np + j] + X[j * np + i]);
             }
     }
-    c->h_Sband = band;
-    c->h_bw = bw;
+    c->co.h_Sband = band;
+    c->co.bw = bw;
     // banded Cholesky: band[i][i-j] <- L[i][j]
     for (int j = 0; j < nP; ++j) {
         double s = band[(size_t)j * (bw + 1)];
@@ -990,8 +990,8 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                        {c->UrdT.p, c->UrdT.n}, {c->Urd.p, c->Urd.n}, {c->Urp.p, c->Urp.n}, {c->UrpT.p, c->UrpT.n},
                        {c->Kinv.p, c->Kinv.n}});
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
-    coarse_inverse_device(c, band, bw);
-    build_coarse_partition(c);
+    coarse_inverse_device(c, c->co, band, bw);
+    build_coarse_partition(c, c->co);
     IFETI_HIP(hipStreamSynchronize(c->stream));
     c->rom_built = true;
 }

@@ -324,7 +324,9 @@ class OwnStream {
 void release_graph(ifeti_ctx *c) { GraphIteration::release(c); }
 
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
-                    double *relres) {
+                    double *relres, bool exact) {
+    auto opF = exact ? apply_F_exact : apply_F;
+    auto opMD = exact ? apply_MD_exact : apply_MD;
     OwnStream own(c, c->opt.use_graph != 0);
     const long long L = c->L;
     const long long n = L * nrhs;
@@ -344,7 +346,7 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     int *ist = c->pcg_ist.p;
     hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, rhs, r, n);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kB), 0, s, lam, n, 0.0);
-    apply_MD(c, r, z, nrhs, r, pb);                                   // z = M r, partials of r.z
+    opMD(c, r, z, nrhs, r, pb);                                       // z = M r, partials of r.z
     hipLaunchKernelGGL(k_dot_partial, dim3(nblk, nrhs), dim3(kB), 0, s, r, r, L, L, nblk, pa);
     hipLaunchKernelGGL(k_pcg_init, dim3(nrhs), dim3(kB), 0, s, pa, pb, nblk, st, ist);
     hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, s, z, p, n);
@@ -364,13 +366,13 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     const int every = std::max(1, c->opt.pcg_check_every);
     const double Ld = (double)L * nrhs;
     auto iteration = [&]() {
-        apply_F(c, p, q, nrhs, p, pa);                                // q = F p, partials of p.q
+        opF(c, p, q, nrhs, p, pa);                                    // q = F p, partials of p.q
         {
             Prof prof(c, "pcg_step", 5.0 * Ld, 48.0 * Ld);            // read lam, p, q, r; write lam, r
             hipLaunchKernelGGL(k_pcg_step, dim3(nblk, nrhs), dim3(kB), 0, s, lam, r, p, q, L, L, nrhs, st, ist, pa,
                                nblk, pb);
         }
-        apply_MD(c, r, z, nrhs, r, pc);                               // z = M r, partials of r.z
+        opMD(c, r, z, nrhs, r, pc);                                   // z = M r, partials of r.z
         {
             Prof prof(c, "pcg_next", 2.0 * Ld, 24.0 * Ld);
             hipLaunchKernelGGL(k_pcg_next, dim3(nblk, nrhs), dim3(kB), 0, s, p, z, L, L, nrhs, st, ist, pb, pc,
@@ -384,9 +386,10 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
     std::vector<uintptr_t> key;
     if (c->opt.use_graph) {
         const void *bufs[] = {lam, r, z, p, q, st, ist, pa, pb, pc, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p,
-                              c->w_yP.p, c->w_symP.p, c->w_split.p, c->w_Lam.p, c->side_stream, c->stream};
+                              c->w_yP.p, c->co.w_symP.p, c->w_split.p, c->w_Lam.p, c->side_stream, c->stream};
         for (const void *b : bufs) key.push_back((uintptr_t)b);
-        for (long long v : {(long long)nrhs, (long long)c->opt.precision, c->rom_gen, (long long)nblk})
+        for (long long v : {(long long)nrhs, (long long)c->opt.precision, c->rom_gen, (long long)nblk,
+                            (long long)exact})
             key.push_back((uintptr_t)v);
         double tv = tol;
         uintptr_t tb = 0;

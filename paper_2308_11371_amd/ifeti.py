@@ -24,7 +24,9 @@ EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_size
             "ifeti_build_cells", "ifeti_get_rhs", "ifeti_build_reduced_basis", "ifeti_get_coefficients",
             "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_U", "ifeti_apply_Ut", "ifeti_apply_Kinv_rom",
             "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
-            "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths")
+            "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths",
+            "ifeti_build_exact", "ifeti_exact_apply_F", "ifeti_exact_apply_MD", "ifeti_exact_solve",
+            "ifeti_exact_cell_blocks")
 
 
 class LatticeDesc(ctypes.Structure):
@@ -103,6 +105,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_reset_stats": [P],
         "ifeti_compliance_grad": [P, P, P, P, P, I],
         "ifeti_update_widths": [P, P],
+        "ifeti_build_exact": [P],
+        "ifeti_exact_apply_F": [P, P, P, I],
+        "ifeti_exact_apply_MD": [P, P, P, I],
+        "ifeti_exact_solve": [P, P, P, P, P, I, D, I, P, P],
+        "ifeti_exact_cell_blocks": [P, I, P, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -309,6 +316,55 @@ def _update_widths(self, widths):
 
 Context.compliance_grad = _compliance_grad
 Context.update_widths = _update_widths
+
+
+# ---------------------------------------------------------------- standard (exact) FETI-DP
+def _build_exact(self):
+    """Factorise every cell (ifeti_build_exact); the exact operators and solve become available."""
+    _check(self.lib.ifeti_build_exact(self.h))
+
+
+def _exact_apply_F(self, lam, nrhs=1, out=None):
+    return self._apply(self.lib.ifeti_exact_apply_F, lam, self.sizes.L, nrhs, out)
+
+
+def _exact_apply_MD(self, r, nrhs=1, out=None):
+    return self._apply(self.lib.ifeti_exact_apply_MD, r, self.sizes.L, nrhs, out)
+
+
+def _exact_solve(self, f, d, nrhs=1, tol=1e-11, maxit=1000, check=True):
+    import torch
+    s = self.sizes
+    u = torch.empty(s.nU * nrhs, dtype=torch.float64, device=f.device)
+    lam = torch.empty(s.L * nrhs, dtype=torch.float64, device=f.device)
+    its = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs)
+    st = self.lib.ifeti_exact_solve(self.h, _ptr(f), _ptr(d), _ptr(u), _ptr(lam), int(nrhs), float(tol), int(maxit),
+                                    its.ctypes.data_as(ctypes.c_void_p), rel.ctypes.data_as(ctypes.c_void_p))
+    if check:
+        _check(st)
+    return u, lam, dict(iters=its, relres=rel, status=st)
+
+
+def _exact_cell_blocks(self, s):
+    """(F_dd, S_dd, S_pp, U_d) of cell s as numpy arrays, and the device bytes of the exact form."""
+    z = self.sizes
+    F = np.zeros((z.n_d, z.n_d))
+    S = np.zeros((z.n_d, z.n_d))
+    P = np.zeros((z.n_p, z.n_p))
+    U = np.zeros((z.n_d, z.n_p))
+    b = ctypes.c_longlong(0)
+    vp = ctypes.c_void_p
+    _check(self.lib.ifeti_exact_cell_blocks(self.h, int(s), F.ctypes.data_as(vp), S.ctypes.data_as(vp),
+                                            P.ctypes.data_as(vp), U.ctypes.data_as(vp), ctypes.byref(b)))
+    return F, S, P, U, int(b.value)
+
+
+Context.build_exact = _build_exact
+Context.exact_apply_F = _exact_apply_F
+Context.exact_apply_MD = _exact_apply_MD
+Context.exact_solve = _exact_solve
+Context.exact_cell_blocks = _exact_cell_blocks
 
 
 def _autograd():
