@@ -321,12 +321,23 @@ __global__ __launch_bounds__(256) void k_ex_cell_gemv(const double *__restrict__
     __syncthreads();
     const double *Ms = Mops + (size_t)s * n_d * n_d;
     double *y = Y + (size_t)col * n_d;
-    for (int r = wave; r < n_d; r += 4) {
-        const double *mr = Ms + (size_t)r * n_d;
-        double acc = 0.0;
-        for (int c = lane; c < n_d; c += 64) acc += __builtin_nontemporal_load(mr + c) * xs[c];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) y[r] = acc;
+    // four rows per wave at a time, so each lane keeps several row loads in flight
+    for (int r0 = 4 * wave; r0 < n_d; r0 += 16) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = lane; c < n_d; c += 64) {
+            double m[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) m[q] = r0 + q < n_d ? __builtin_nontemporal_load(Ms + (size_t)(r0 + q) * n_d + c) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += m[q] * xs[c];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (r0 + q < n_d) y[r0 + q] = acc[q];
     }
 }
 

@@ -87,3 +87,33 @@ def test_full_solve_properties(c2):
     rel = (torch.linalg.norm(r) / torch.linalg.norm(torch.cat([f, d]))).item()
     assert rel <= 1.01e-8
     assert 1 <= int(info["outer_its"][0]) <= 60
+
+
+def test_exact_fetidp_full_size(c2):
+    """Standard FETI-DP at full size: the batched factorisation's blocks of sampled cells against the
+    oracle's dense factorisation of those cells, and the standard solve's true residual of (16)."""
+    prob, ctx, gold = c2
+    from oracle import Model
+    from oracle.assembly import cell_matrix_values
+    from oracle.rom import PrincipalBank
+    print("[gpu fullsize] c2 exact factorisation", flush=True)
+    ctx.build_exact()
+    m0 = Model(prob, build_all_cells=False)
+    cells = np.array([0, 1234, 4095])
+    bank = PrincipalBank(m0.ref, m0.dd, cell_matrix_values(m0.ref, prob, cells))
+    for k, s in enumerate(cells):
+        F, S, P, U, nbytes = ctx.exact_cell_blocks(int(s))
+        for got, exp in ((F, bank.Fdd[k]), (S, bank.Sdd[k]), (P, bank.Spp[k]), (U, bank.W[k])):
+            assert np.linalg.norm(got - exp) <= 1e-10 * np.linalg.norm(exp)
+    s = ctx.sizes
+    f, d = ctx.get_rhs()
+    f = f[:s.nU].contiguous()
+    d = d[:s.L].contiguous()
+    # the interface residual is relative to the d-bar of (25), whose norm is several hundred times
+    # that of (f, d) on these soft lattices: an interface tolerance of 1e-12 bounds (16) well below 1e-8
+    u, lam, info = ctx.exact_solve(f, d, tol=1e-12, maxit=3000)
+    x = torch.cat([u, lam])
+    b = torch.cat([f, d])
+    rel = (torch.linalg.norm(b - ctx.apply_A(x)) / torch.linalg.norm(b)).item()
+    print(f"[gpu fullsize] exact solve: {int(info['iters'][0])} PCG its, saddle relres {rel:.2e}", flush=True)
+    assert rel <= 1e-8
