@@ -71,6 +71,11 @@ struct DevBuf {
     void zero(hipStream_t s) {
         if (n) IFETI_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
     }
+    // asynchronous copy to a host vector of size n (the caller synchronises the stream)
+    void download(std::vector<T> &h, hipStream_t s) const {
+        h.resize(n);
+        if (n) IFETI_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    }
 };
 
 // Reference-cell tables (eq. (6)): identical for every cell.
@@ -390,7 +395,20 @@ void compliance_grad(ifeti_ctx *c, const double *f, const double *u, double *gra
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres, bool exact = false);
 
-// exact.hip: standard FETI-DP (Sec. 2.2.4)
+// exact.hip: standard FETI-DP (Sec. 2.2.4) and the batched factorisation it shares with the
+// principal bank.  Outputs per list entry k (any may be null except Fq, Spp, UqT, Kpr):
+struct FactorOut {
+    double *L = nullptr;    // [k][n_r][n_r] Cholesky factor of K_rr (lower, column-major)
+    double *Fq = nullptr;   // [k][n_q][n_q] E^T K_rr^-1 E for the selected rows
+    double *Sdd = nullptr;  // [k][n_d][n_d] Dirichlet Schur complement (30)
+    double *UqT = nullptr;  // [k][n_p][n_q] selected rows of U_rp = K_rr^-1 K_rp, transposed
+    double *Spp = nullptr;  // [k][n_p][n_p] S_pp (22)
+    double *Kpr = nullptr;  // [k][n_p][n_r]
+    double *Kpp = nullptr;  // [k][n_p][n_p] (lower triangle)
+};
+void factor_cells(ifeti_ctx *c, const int *cells, int ncell, int q_lo, int n_q, const FactorOut &o);
+// lower-band Cholesky factor of an SPD band matrix band[i][i-j] computed on the GPU (ENOTSPD if not SPD)
+std::vector<double> band_cholesky_device(ifeti_ctx *c, const std::vector<double> &band, int n, int bw);
 void build_exact(ifeti_ctx *c);
 void apply_F_exact(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
                    double *dot_part = nullptr);

@@ -53,16 +53,18 @@ __device__ __forceinline__ double stencil_entry(const double *__restrict__ Ks, i
     return Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
 }
 
-// Lower triangle of the augmented matrix of cells s0 + blockIdx.y (column-major, leading
-// dimension lda), one wave per column; K_pr of each cell is written on the side.
+// Lower triangle of the augmented matrix of list entries k = k0 + blockIdx.y (cell cells[k], or k
+// without a list), column-major with leading dimension lda, one wave per column.  The q block
+// selects the r rows [q_lo, q_lo + n_q).  K_pr and K_pp (lower) of each entry are written on the side.
 template <int D>
-__global__ __launch_bounds__(256) void k_ex_densify(const double *__restrict__ Kst, int s0, int n_r, int n_p,
-                                                    int n_i, int n_a, int lda, const int *__restrict__ idx_r,
-                                                    const int *__restrict__ idx_p, int nc, int n_ctrl, int n_off,
-                                                    int p, double *__restrict__ A, double *__restrict__ Kpr) {
+__global__ __launch_bounds__(256) void k_ex_densify(const double *__restrict__ Kst, const int *__restrict__ cells,
+                                                    int k0, int n_r, int n_p, int q_lo, int n_a, int lda,
+                                                    const int *__restrict__ idx_r, const int *__restrict__ idx_p,
+                                                    int nc, int n_ctrl, int n_off, int p, double *__restrict__ A,
+                                                    double *__restrict__ Kpr, double *__restrict__ Kpp) {
     const int col = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (col >= n_a) return;
-    const int s = s0 + blockIdx.y;
+    const int k = k0 + blockIdx.y, s = cells ? cells[k] : k;
     const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
     double *M = A + (size_t)blockIdx.y * lda * n_a;
     const int nrp = n_r + n_p;
@@ -72,9 +74,10 @@ __global__ __launch_bounds__(256) void k_ex_densify(const double *__restrict__ K
         if (row < nrp) {
             const int u = row < n_r ? idx_r[row] : idx_p[row - n_r];
             val = stencil_entry<D>(Ks, u, v, nc, n_ctrl, p);
-            if (row >= n_r && col < n_r) Kpr[((size_t)s * n_p + (row - n_r)) * n_r + col] = val;
+            if (row >= n_r && col < n_r) Kpr[((size_t)k * n_p + (row - n_r)) * n_r + col] = val;
+            if (row >= n_r && col >= n_r && Kpp) Kpp[((size_t)k * n_p + (row - n_r)) * n_p + (col - n_r)] = val;
         } else {
-            val = (col == n_i + (row - nrp)) ? 1.0 : 0.0;  // E^T; zero against p and q
+            val = (col == q_lo + (row - nrp)) ? 1.0 : 0.0;  // E^T; zero against p and q
         }
         M[(size_t)col * lda + row] = val;
     }
@@ -212,29 +215,31 @@ __global__ __launch_bounds__(256) void k_ex_syrk(double *__restrict__ A, int lda
         }
 }
 
-// F_dd = -A[q,q], S_pp = A[p,p], C = U_d^T = -A[q,p]^T, L = the first n_r columns (lower)
+// Fq = -A[q,q] = E^T K_rr^-1 E (full, from the lower triangle), S_pp = A[p,p], UqT = -A[q,p]^T
+// (the q rows of U_rp, transposed: [n_p][n_q]), L = the first n_r columns (lower; skipped if null)
 __global__ __launch_bounds__(256) void k_ex_extract(const double *__restrict__ A, int lda, int n_a, int n_r,
-                                                    int n_p, int n_d, int s0, double *__restrict__ Fdd,
-                                                    double *__restrict__ Spp, double *__restrict__ C,
+                                                    int n_p, int n_q, int k0, double *__restrict__ Fq,
+                                                    double *__restrict__ Spp, double *__restrict__ UqT,
                                                     double *__restrict__ L) {
     const double *M = A + (size_t)blockIdx.x * lda * n_a;
-    const int s = s0 + blockIdx.x, q0 = n_r + n_p;
-    double *F = Fdd + (size_t)s * n_d * n_d;
-    for (int e = threadIdx.x; e < n_d * n_d; e += 256) {
-        const int i = e / n_d, j = e % n_d, hi = max(i, j), lo = min(i, j);
+    const int k = k0 + blockIdx.x, q0 = n_r + n_p;
+    double *F = Fq + (size_t)k * n_q * n_q;
+    for (long long e = threadIdx.x; e < (long long)n_q * n_q; e += 256) {
+        const int i = (int)(e / n_q), j = (int)(e % n_q), hi = max(i, j), lo = min(i, j);
         F[e] = -M[(size_t)(q0 + lo) * lda + q0 + hi];
     }
-    double *S = Spp + (size_t)s * n_p * n_p;
+    double *S = Spp + (size_t)k * n_p * n_p;
     for (int e = threadIdx.x; e < n_p * n_p; e += 256) {
         const int a = e / n_p, b = e % n_p, hi = max(a, b), lo = min(a, b);
         S[e] = M[(size_t)(n_r + lo) * lda + n_r + hi];
     }
-    double *Cs = C + (size_t)s * n_p * n_d;
-    for (int e = threadIdx.x; e < n_p * n_d; e += 256) {
-        const int a = e / n_d, j = e % n_d;
+    double *Cs = UqT + (size_t)k * n_p * n_q;
+    for (int e = threadIdx.x; e < n_p * n_q; e += 256) {
+        const int a = e / n_q, j = e % n_q;
         Cs[e] = -M[(size_t)(n_r + a) * lda + q0 + j];
     }
-    double *Ls = L + (size_t)s * n_r * n_r;
+    if (!L) return;
+    double *Ls = L + (size_t)k * n_r * n_r;
     for (int col = threadIdx.x >> 6; col < n_r; col += 4)
         for (int row = col + (threadIdx.x & 63); row < n_r; row += 64)
             Ls[(size_t)col * n_r + row] = M[(size_t)col * lda + row];
@@ -400,6 +405,23 @@ __global__ __launch_bounds__(256) void k_ex_rhs_u(const double *__restrict__ f, 
     }
 }
 
+// dense lower (column-major) from the symmetric band band[i][i-j] (width bw+1); zero outside the band
+__global__ __launch_bounds__(256) void k_band_to_dense(const double *__restrict__ band, int n, int bw,
+                                                       double *__restrict__ A) {
+    const int col = blockIdx.x;
+    for (int row = col + threadIdx.x; row < n; row += 256)
+        A[(size_t)col * n + row] = row - col <= bw ? band[(size_t)row * (bw + 1) + (row - col)] : 0.0;
+}
+
+// band[i][i-j] = L[i][j] for j >= i - bw, from the dense lower factor
+__global__ __launch_bounds__(256) void k_dense_to_band(const double *__restrict__ A, int n, int bw,
+                                                       double *__restrict__ band) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)n * (bw + 1)) return;
+    const int i = (int)(t / (bw + 1)), d = (int)(t % (bw + 1)), j = i - d;
+    band[t] = j >= 0 ? A[(size_t)j * n + i] : 0.0;
+}
+
 // out = a + sb * b per load case
 __global__ __launch_bounds__(256) void k_ex_axpy(const double *__restrict__ a, const double *__restrict__ b,
                                                  double *__restrict__ out, long long n, double sb) {
@@ -430,52 +452,50 @@ void cell_gemv(ifeti_ctx *c, const double *Mops, const double *lam, bool weights
 
 }  // namespace
 
-void build_exact(ifeti_ctx *c) {
-    const int N = c->N, nr = c->n_r, np = c->n_p, nd = c->n_d, ni = c->n_i, dim = c->dim;
-    IFETI_REQUIRE(np <= kExMaxNp, IFETI_EINVAL, "too many primal dofs per cell");
+// Batched factorisation of the augmented matrices of ncell list entries (cells[k], or k when cells
+// is null), q block = the r rows [q_lo, q_lo + n_q); outputs per list entry (see FactorOut).
+void factor_cells(ifeti_ctx *c, const int *cells, int ncell, int q_lo, int n_q, const FactorOut &o) {
+    const int nr = c->n_r, np = c->n_p, ni = c->n_i, nd = c->n_d, dim = c->dim;
     const RefTables &R = c->ref;
-    const int na = nr + np + nd, lda = na;
+    const int na = nr + np + n_q, lda = na;
     const size_t cell_elems = (size_t)lda * na;
-    // batch of cells whose augmented matrices fit a fixed workspace
+    // batch of entries whose augmented matrices fit a fixed workspace
     const size_t budget = (size_t)6 << 30;
-    const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)N, budget / (cell_elems * sizeof(double))));
+    const int batch =
+        (int)std::max<size_t>(1, std::min<size_t>((size_t)ncell, budget / (cell_elems * sizeof(double))));
     DevBuf<double> A;
     A.alloc(cell_elems * batch);
-    c->ex_L.alloc((size_t)N * nr * nr);
-    c->ex_Fdd.alloc((size_t)N * nd * nd);
-    c->ex_Sdd.alloc((size_t)N * nd * nd);
-    c->ex_C.alloc((size_t)N * np * nd);
-    c->ex_Spp.alloc((size_t)N * np * np);
-    c->ex_Kpr.alloc((size_t)N * np * nr);
     DevBuf<int> bad;
-    bad.alloc(N);
-    IFETI_HIP(hipMemsetAsync(bad.p, 0, (size_t)N * sizeof(int), c->stream));
-    for (int s0 = 0; s0 < N; s0 += batch) {
-        const int nb_cells = std::min(batch, N - s0);
+    bad.alloc(ncell);
+    IFETI_HIP(hipMemsetAsync(bad.p, 0, (size_t)ncell * sizeof(int), c->stream));
+    for (int k0 = 0; k0 < ncell; k0 += batch) {
+        const int nb_cells = std::min(batch, ncell - k0);
         {
             Prof prof(c, "exact_densify", 0.0, 8.0 * (double)nb_cells * na * (na + 1) / 2);
             const dim3 grid((na + 3) / 4, nb_cells);
             if (dim == 2)
-                hipLaunchKernelGGL(k_ex_densify<2>, grid, dim3(256), 0, c->stream, c->Kst.p, s0, nr, np, ni, na, lda,
-                                   c->g_idx_r.p, c->g_idx_p.p, R.nc, R.n_ctrl, R.n_off, R.p, A.p, c->ex_Kpr.p);
+                hipLaunchKernelGGL(k_ex_densify<2>, grid, dim3(256), 0, c->stream, c->Kst.p, cells, k0, nr, np, q_lo,
+                                   na, lda, c->g_idx_r.p, c->g_idx_p.p, R.nc, R.n_ctrl, R.n_off, R.p, A.p, o.Kpr,
+                                   o.Kpp);
             else
-                hipLaunchKernelGGL(k_ex_densify<3>, grid, dim3(256), 0, c->stream, c->Kst.p, s0, nr, np, ni, na, lda,
-                                   c->g_idx_r.p, c->g_idx_p.p, R.nc, R.n_ctrl, R.n_off, R.p, A.p, c->ex_Kpr.p);
+                hipLaunchKernelGGL(k_ex_densify<3>, grid, dim3(256), 0, c->stream, c->Kst.p, cells, k0, nr, np, q_lo,
+                                   na, lda, c->g_idx_r.p, c->g_idx_p.p, R.nc, R.n_ctrl, R.n_off, R.p, A.p, o.Kpr,
+                                   o.Kpp);
             IFETI_HIP(hipGetLastError());
         }
         for (int j0 = 0; j0 < nr;) {
             const int j1 = std::min(j0 + XB, j0 < ni ? ni : nr);
             const int nbp = j1 - j0;
-            if (j0 == ni) {
-                hipLaunchKernelGGL(k_ex_snap_sdd, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, ni, nd, s0,
-                                   c->ex_Sdd.p);
+            if (j0 == ni && o.Sdd) {
+                hipLaunchKernelGGL(k_ex_snap_sdd, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, ni, nd, k0,
+                                   o.Sdd);
                 IFETI_HIP(hipGetLastError());
             }
             {
                 Prof prof(c, "exact_panel", (double)nb_cells * ((double)nbp * nbp * nbp / 3.0 +
                                                                  (double)(na - j1) * nbp * nbp),
                           16.0 * (double)nb_cells * (na - j0) * nbp);
-                hipLaunchKernelGGL(k_ex_panel, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, j0, nbp, s0,
+                hipLaunchKernelGGL(k_ex_panel, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, j0, nbp, k0,
                                    bad.p);
                 IFETI_HIP(hipGetLastError());
             }
@@ -489,16 +509,71 @@ void build_exact(ifeti_ctx *c) {
             }
             j0 = j1;
         }
-        hipLaunchKernelGGL(k_ex_extract, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, nr, np, nd, s0,
-                           c->ex_Fdd.p, c->ex_Spp.p, c->ex_C.p, c->ex_L.p);
+        hipLaunchKernelGGL(k_ex_extract, dim3(nb_cells), dim3(256), 0, c->stream, A.p, lda, na, nr, np, n_q, k0, o.Fq,
+                           o.Spp, o.UqT, o.L);
         IFETI_HIP(hipGetLastError());
     }
-    std::vector<int> hbad(N);
-    IFETI_HIP(hipMemcpyAsync(hbad.data(), bad.p, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> hbad(ncell);
+    IFETI_HIP(hipMemcpyAsync(hbad.data(), bad.p, (size_t)ncell * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < ncell; ++k) IFETI_REQUIRE(!hbad[k], IFETI_ENOTSPD, "a cell's K_rr is not positive definite");
+}
+
+// Cholesky factor of a symmetric positive definite band matrix on the GPU: the band is expanded
+// to a dense lower matrix and eliminated with the blocked panel and trailing-update kernels of the
+// cell factorisations; the factor keeps the band, which is returned in the same band form.
+std::vector<double> band_cholesky_device(ifeti_ctx *c, const std::vector<double> &band, int n, int bw) {
+    std::vector<double> out;
+    if (n == 0) return out;
+    DevBuf<double> db, A;
+    DevBuf<int> bad;
+    db.upload(band, c->stream);
+    A.alloc((size_t)n * n);
+    bad.alloc(1);
+    bad.zero(c->stream);
+    hipLaunchKernelGGL(k_band_to_dense, dim3(n), dim3(256), 0, c->stream, db.p, n, bw, A.p);
+    IFETI_HIP(hipGetLastError());
+    for (int j0 = 0; j0 < n; j0 += XB) {
+        const int j1 = std::min(n, j0 + XB), nbp = j1 - j0;
+        hipLaunchKernelGGL(k_ex_panel, dim3(1), dim3(256), 0, c->stream, A.p, n, n, j0, nbp, 0, bad.p);
+        if (j1 < n) {
+            const long long t = n - j1, T = (t + 63) / 64, tiles = T * (T + 1) / 2;
+            hipLaunchKernelGGL(k_ex_syrk, dim3((unsigned)tiles, 1), dim3(256), 0, c->stream, A.p, n, n, j0, nbp,
+                               (int)j1);
+        }
+        IFETI_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_dense_to_band, dim3(nblk((long long)n * (bw + 1))), dim3(256), 0, c->stream, A.p, n, bw,
+                       db.p);
+    IFETI_HIP(hipGetLastError());
+    db.download(out, c->stream);
+    int hbad = 0;
+    IFETI_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    IFETI_REQUIRE(!hbad, IFETI_ENOTSPD, "coarse matrix S_PP is not positive definite");
+    return out;
+}
+
+void build_exact(ifeti_ctx *c) {
+    const int N = c->N, nr = c->n_r, np = c->n_p, nd = c->n_d;
+    IFETI_REQUIRE(np <= kExMaxNp, IFETI_EINVAL, "too many primal dofs per cell");
+    c->ex_L.alloc((size_t)N * nr * nr);
+    c->ex_Fdd.alloc((size_t)N * nd * nd);
+    c->ex_Sdd.alloc((size_t)N * nd * nd);
+    c->ex_C.alloc((size_t)N * np * nd);
+    c->ex_Spp.alloc((size_t)N * np * np);
+    c->ex_Kpr.alloc((size_t)N * np * nr);
+    FactorOut o;
+    o.L = c->ex_L.p;
+    o.Fq = c->ex_Fdd.p;
+    o.Sdd = c->ex_Sdd.p;
+    o.UqT = c->ex_C.p;
+    o.Spp = c->ex_Spp.p;
+    o.Kpr = c->ex_Kpr.p;
+    factor_cells(c, nullptr, N, c->n_i, nd, o);
     std::vector<double> Spp((size_t)N * np * np);
     IFETI_HIP(hipMemcpyAsync(Spp.data(), c->ex_Spp.p, Spp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     IFETI_HIP(hipStreamSynchronize(c->stream));
-    for (int s = 0; s < N; ++s) IFETI_REQUIRE(!hbad[s], IFETI_ENOTSPD, "a cell's K_rr is not positive definite");
     // assembled S_PP (eq. (22)) in band form, then its own coarse solver
     const int nP = c->nP;
     int bw = 0;
@@ -521,7 +596,7 @@ void build_exact(ifeti_ctx *c) {
     c->co_ex.h_Sband = band;
     c->co_ex.bw = bw;
     if (nP > 0) {
-        coarse_inverse_device(c, c->co_ex, band_cholesky(band, nP, bw), bw);
+        coarse_inverse_device(c, c->co_ex, band_cholesky_device(c, band, nP, bw), bw);
         build_coarse_partition(c, c->co_ex);
     }
     IFETI_HIP(hipStreamSynchronize(c->stream));

@@ -290,26 +290,40 @@ __global__ __launch_bounds__(kBlock) void k_gs_update(double *__restrict__ A, lo
     }
 }
 
-// Column j of (L L^T)^-1 for a banded lower factor band[i*(bw+1) + (i-k)] = L[i][k].
-__global__ __launch_bounds__(kBlock) void k_band_inverse(const double *__restrict__ band, int n, int bw,
-                                                         double *__restrict__ X) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// Row j of (L L^T)^-1 (= column j, the inverse is symmetric) for a banded lower factor
+// band[i*(bw+1) + (i-k)] = L[i][k]: one single-wave workgroup per j, the solution vector in LDS
+// (dynamic, n doubles), the lanes spread over the band of each substitution step and a fixed
+// butterfly per step.
+__global__ __launch_bounds__(64) void k_band_inverse(const double *__restrict__ band, int n, int bw,
+                                                     double *__restrict__ X) {
+    extern __shared__ double x[];
+    const int j = blockIdx.x, lane = threadIdx.x;
     const int ld = bw + 1;
-    for (int i = 0; i < j; ++i) X[(size_t)i * n + j] = 0.0;
-    for (int i = j; i < n; ++i) {  // forward: L y = e_j
-        double t = (i == j) ? 1.0 : 0.0;
-        int k0 = max(j, i - bw);
+    for (int i = lane; i < n; i += 64) x[i] = 0.0;
+    __syncthreads();
+    // forward: L y = e_j (rows above j stay 0)
+    for (int i = j; i < n; ++i) {
         const double *Li = band + (size_t)i * ld;
-        for (int k = k0; k < i; ++k) t -= Li[i - k] * X[(size_t)k * n + j];
-        X[(size_t)i * n + j] = t / Li[0];
+        double t = 0.0;
+        for (int k = max(j, i - bw) + lane; k < i; k += 64) t += Li[i - k] * x[k];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const double v = ((i == j ? 1.0 : 0.0) - t) / Li[0];
+        __syncthreads();  // every lane has read x[] for this step
+        if (lane == 0) x[i] = v;
+        __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {  // backward: L^T x = y
-        double t = X[(size_t)i * n + j];
-        int k1 = min(n - 1, i + bw);
-        for (int k = i + 1; k <= k1; ++k) t -= band[(size_t)k * ld + (k - i)] * X[(size_t)k * n + j];
-        X[(size_t)i * n + j] = t / band[(size_t)i * ld];
+    // backward: L^T x = y
+    for (int i = n - 1; i >= 0; --i) {
+        double t = 0.0;
+        const int k1 = min(n - 1, i + bw);
+        for (int k = i + 1 + lane; k <= k1; k += 64) t += band[(size_t)k * ld + (k - i)] * x[k];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const double v = (x[i] - t) / band[(size_t)i * ld];
+        __syncthreads();
+        if (lane == 0) x[i] = v;
+        __syncthreads();
     }
+    for (int i = lane; i < n; i += 64) X[(size_t)j * n + i] = x[i];
 }
 
 inline unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
@@ -419,8 +433,11 @@ void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<dou
     DevBuf<double> band;
     band.upload(band_L, c->stream);
     co.SPPinv.alloc((size_t)c->nP * c->nP);
-    hipLaunchKernelGGL(k_band_inverse, dim3(blocks_for(c->nP, 64)), dim3(64), 0, c->stream, band.p, c->nP, bw,
-                       co.SPPinv.p);
+    const size_t lds = (size_t)c->nP * sizeof(double);
+    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "coarse problem too large for the LDS");
+    IFETI_HIP(hipFuncSetAttribute((const void *)k_band_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_band_inverse, dim3(c->nP), dim3(64), (size_t)c->nP * sizeof(double), c->stream, band.p, c->nP,
+                       bw, co.SPPinv.p);
     IFETI_HIP(hipGetLastError());
     const int nT = (c->nP + 63) / 64;
     const size_t ntiles = (size_t)nT * (nT + 1) / 2;

@@ -9,6 +9,10 @@
 #include <numeric>
 #include <thread>
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace ifeti {
@@ -609,111 +613,12 @@ std::vector<double> small_spd_solve(const std::vector<double> &A, int n, const s
     return x;
 }
 
+// Principal-cell operators on the host (eqs. (22), (27)-(30), (39)), from the batched GPU
+// factorisation of the principal cells.
 struct Principal {
-    std::vector<double> Kst;                  // stencil values of the cell
-    std::vector<double> Krp, Kpp;             // dense blocks
+    std::vector<double> Krp, Kpp;             // dense blocks, n_r x n_p and n_p x n_p (row-major)
     std::vector<double> Kinv, Urp, Fdd, Sdd;  // n_r x n_r, n_r x n_p, n_d x n_d, n_d x n_d
-    bool ok = true;
-    std::string err;
 };
-
-// Dense local matrix entry access through the stencil layout.
-struct StencilView {
-    const ifeti_ctx *c;
-    int off[125][3];
-    StencilView(const ifeti_ctx *cc) : c(cc) {
-        const RefTables &R = c->ref;
-        int w = 2 * R.p + 1;
-        for (int o = 0; o < R.n_off; ++o) {
-            int t = o;
-            for (int j = 0; j < 3; ++j) {
-                off[o][j] = (j < R.dim) ? (t % w) - R.p : 0;
-                if (j < R.dim) t /= w;
-            }
-        }
-    }
-    // full dense n_dof x n_dof matrix
-    std::vector<double> dense(const double *Kst) const {
-        const RefTables &R = c->ref;
-        const int d = R.dim, nc = R.nc;
-        std::vector<double> K((size_t)R.n_dof * R.n_dof, 0.0);
-        int mi[3];
-        for (int a = 0; a < R.n_ctrl; ++a) {
-            multi_index(a, nc, d, mi);
-            for (int o = 0; o < R.n_off; ++o) {
-                int b = 0;
-                bool ok = true;
-                for (int j = d - 1; j >= 0; --j) {
-                    int bj = mi[j] + off[o][j];
-                    if (bj < 0 || bj >= nc) ok = false;
-                    b = b * nc + bj;
-                }
-                if (!ok) continue;
-                for (int i = 0; i < d; ++i)
-                    for (int k = 0; k < d; ++k)
-                        K[(size_t)(a * d + i) * R.n_dof + b * d + k] =
-                            Kst[(((size_t)o * d + i) * d + k) * R.n_ctrl + a];
-            }
-        }
-        return K;
-    }
-};
-
-void build_principal(const ifeti_ctx *c, const StencilView &sv, Principal &P) {
-    const int n = c->ref.n_dof, nr = c->n_r, np = c->n_p, nd = c->n_d, ni = c->n_i;
-    std::vector<double> K = sv.dense(P.Kst.data());
-    std::vector<double> Krr((size_t)nr * nr), Kii((size_t)ni * ni), Kid((size_t)ni * nd), Kdd((size_t)nd * nd);
-    P.Krp.assign((size_t)nr * np, 0.0);
-    P.Kpp.assign((size_t)np * np, 0.0);
-    for (int i = 0; i < nr; ++i) {
-        for (int j = 0; j < nr; ++j) Krr[(size_t)i * nr + j] = K[(size_t)c->idx_r[i] * n + c->idx_r[j]];
-        for (int j = 0; j < np; ++j) P.Krp[(size_t)i * np + j] = K[(size_t)c->idx_r[i] * n + c->idx_p[j]];
-    }
-    for (int i = 0; i < np; ++i)
-        for (int j = 0; j < np; ++j) P.Kpp[(size_t)i * np + j] = K[(size_t)c->idx_p[i] * n + c->idx_p[j]];
-    for (int i = 0; i < ni; ++i) {
-        for (int j = 0; j < ni; ++j) Kii[(size_t)i * ni + j] = K[(size_t)c->idx_i[i] * n + c->idx_i[j]];
-        for (int j = 0; j < nd; ++j) Kid[(size_t)i * nd + j] = K[(size_t)c->idx_i[i] * n + c->idx_d[j]];
-    }
-    for (int i = 0; i < nd; ++i)
-        for (int j = 0; j < nd; ++j) Kdd[(size_t)i * nd + j] = K[(size_t)c->idx_d[i] * n + c->idx_d[j]];
-    std::vector<double> Lr = Krr;
-    if (!cholesky(Lr, nr)) {
-        P.ok = false;
-        P.err = "principal K_rr is not positive definite";
-        return;
-    }
-    // K_rr^-1 (eqs. (27)-(28)), U_rp = K_rr^-1 K_rp (29)
-    P.Kinv.assign((size_t)nr * nr, 0.0);
-    for (int i = 0; i < nr; ++i) P.Kinv[(size_t)i * nr + i] = 1.0;
-    chol_solve(Lr, nr, P.Kinv, nr);
-    for (int i = 0; i < nr; ++i)  // symmetrise the computed inverse
-        for (int j = i + 1; j < nr; ++j) {
-            double v = 0.5 * (P.Kinv[(size_t)i * nr + j] + P.Kinv[(size_t)j * nr + i]);
-            P.Kinv[(size_t)i * nr + j] = P.Kinv[(size_t)j * nr + i] = v;
-        }
-    P.Urp = P.Krp;
-    chol_solve(Lr, nr, P.Urp, np);
-    P.Fdd.assign((size_t)nd * nd, 0.0);
-    for (int i = 0; i < nd; ++i)
-        for (int j = 0; j < nd; ++j) P.Fdd[(size_t)i * nd + j] = P.Kinv[(size_t)(ni + i) * nr + ni + j];
-    // S_dd = K_dd - K_di K_ii^-1 K_id (30)
-    std::vector<double> Li = Kii;
-    if (!cholesky(Li, ni)) {
-        P.ok = false;
-        P.err = "principal K_ii is not positive definite";
-        return;
-    }
-    std::vector<double> X = Kid;
-    chol_solve(Li, ni, X, nd);
-    P.Sdd = Kdd;
-    for (int i = 0; i < nd; ++i)
-        for (int j = 0; j < nd; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < ni; ++k) s += Kid[(size_t)k * nd + i] * X[(size_t)k * nd + j];
-            P.Sdd[(size_t)i * nd + j] -= s;
-        }
-}
 
 template <class F>
 void parallel_for(int n, F f) {
@@ -734,7 +639,27 @@ void parallel_for(int n, F f) {
 }  // namespace
 
 // ------------------------------------------------------------------ offline phase
+// IFETI_SETUP_VERBOSE=1 prints the wall time of each offline stage (the stream is synchronised at
+// each mark, so the times include the device work of the stage)
+struct StageClock {
+    ifeti_ctx *c;
+    bool on;
+    std::chrono::steady_clock::time_point t;
+    explicit StageClock(ifeti_ctx *cc) : c(cc), on(std::getenv("IFETI_SETUP_VERBOSE") != nullptr) {
+        t = std::chrono::steady_clock::now();
+    }
+    void mark(const char *what) {
+        if (!on) return;
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        const auto n = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[ifeti setup] %-28s %8.1f ms\n", what,
+                     std::chrono::duration<double, std::milli>(n - t).count());
+        t = n;
+    }
+};
+
 void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in) {
+    StageClock clk(c);
     const RefTables &R = c->ref;
     const int N = c->N, nr = c->n_r, np = c->n_p, nd = c->n_d, ni = c->n_i;
     // 1. greedy (Algorithm 4) on the device; affine coordinates (56) on the host
@@ -755,18 +680,57 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
             }
         }
     }
-    // 2. principal bank (eqs. (22), (27)-(30), (39))
-    const size_t kst_n = (size_t)R.n_ctrl * R.n_off * R.dim * R.dim;
+    clk.mark("greedy + affine coordinates");
+    // 2. principal bank (eqs. (22), (27)-(30), (39)): the principal cells' augmented matrices
+    //    [K_rr K_rp I; K_pr K_pp 0; I 0 0] factorised on the GPU (the batched elimination of the
+    //    standard FETI-DP form with every r row selected), giving K_rr^-1, U_rp, S_pp, S_dd, K_pr, K_pp
     std::vector<Principal> bank(K);
-    for (int k = 0; k < K; ++k) {
-        bank[k].Kst.resize(kst_n);
-        IFETI_HIP(hipMemcpyAsync(bank[k].Kst.data(), c->Kst.p + (size_t)sigma[k] * kst_n, kst_n * sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
+    {
+        DevBuf<int> dsig;
+        dsig.upload(sigma, c->stream);
+        DevBuf<double> dFq, dSdd, dUqT, dSpp, dKpr, dKpp;
+        dFq.alloc((size_t)K * nr * nr);
+        dSdd.alloc((size_t)K * nd * nd);
+        dUqT.alloc((size_t)K * np * nr);
+        dSpp.alloc((size_t)K * np * np);
+        dKpr.alloc((size_t)K * np * nr);
+        dKpp.alloc((size_t)K * np * np);
+        FactorOut o;
+        o.Fq = dFq.p;
+        o.Sdd = dSdd.p;
+        o.UqT = dUqT.p;
+        o.Spp = dSpp.p;
+        o.Kpr = dKpr.p;
+        o.Kpp = dKpp.p;
+        factor_cells(c, dsig.p, K, 0, nr, o);
+        std::vector<double> hFq(dFq.n), hSdd(dSdd.n), hUqT(dUqT.n), hKpr(dKpr.n), hKpp(dKpp.n);
+        dFq.download(hFq, c->stream);
+        dSdd.download(hSdd, c->stream);
+        dUqT.download(hUqT, c->stream);
+        dKpr.download(hKpr, c->stream);
+        dKpp.download(hKpp, c->stream);
+        IFETI_HIP(hipStreamSynchronize(c->stream));
+        parallel_for(K, [&](int k) {
+            Principal &P = bank[k];
+            P.Kinv.assign(&hFq[(size_t)k * nr * nr], &hFq[(size_t)(k + 1) * nr * nr]);
+            P.Sdd.assign(&hSdd[(size_t)k * nd * nd], &hSdd[(size_t)(k + 1) * nd * nd]);
+            P.Urp.assign((size_t)nr * np, 0.0);
+            P.Krp.assign((size_t)nr * np, 0.0);
+            for (int r = 0; r < nr; ++r)
+                for (int a = 0; a < np; ++a) {
+                    P.Urp[(size_t)r * np + a] = hUqT[((size_t)k * np + a) * nr + r];
+                    P.Krp[(size_t)r * np + a] = hKpr[((size_t)k * np + a) * nr + r];
+                }
+            P.Kpp.assign((size_t)np * np, 0.0);
+            for (int a = 0; a < np; ++a)
+                for (int b = 0; b <= a; ++b)
+                    P.Kpp[(size_t)a * np + b] = P.Kpp[(size_t)b * np + a] = hKpp[((size_t)k * np + a) * np + b];
+            P.Fdd.assign((size_t)nd * nd, 0.0);
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < nd; ++j) P.Fdd[(size_t)i * nd + j] = P.Kinv[(size_t)(ni + i) * nr + ni + j];
+        });
     }
-    IFETI_HIP(hipStreamSynchronize(c->stream));
-    StencilView sv(c);
-    parallel_for(K, [&](int k) { build_principal(c, sv, bank[k]); });
-    for (int k = 0; k < K; ++k) IFETI_REQUIRE(bank[k].ok, IFETI_ENOTSPD, bank[k].err);
+    clk.mark("principal bank");
     // 3. traces of eq. (42) with every cell's own operator K^(s).  K^(s) is linear in the cell's
     //    pulled-back tensor at the quadrature points (eq. (52)), so each trace tr(U^T K^(s) V) is the
     //    dot product of the cell snapshot with a table Psi[q][ab][cd] = w_q sum_col (grad U)_ab (grad V)_cd
@@ -871,6 +835,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
         IFETI_HIP(hipStreamSynchronize(c->stream));
     }
     c->snap_valid = true;
+    clk.mark("trace tables + snapshot GEMM");
     // 4. per-cell pi, delta (41)
     std::vector<double> pi((size_t)N * K), delta((size_t)N * K);
     parallel_for(N, [&](int s) {
@@ -886,6 +851,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
         std::copy(x.begin(), x.end(), &pi[(size_t)s * K]);
         std::copy(y.begin(), y.end(), &delta[(size_t)s * K]);
     });
+    clk.mark("pi, delta systems");
     // 5. S̊_pp^(s) = sym(K̊_pp - K̊_rp^T Ů_rp) (43) and the coarse matrix (Sec. 3.2.1)
     std::vector<double> Q((size_t)K * K * np * np);  // Q[m][k] = K_rp^(m)T U_rp^(k)
     for (int m = 0; m < K; ++m)
@@ -925,23 +891,10 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     }
     c->co.h_Sband = band;
     c->co.bw = bw;
-    // banded Cholesky: band[i][i-j] <- L[i][j]
-    for (int j = 0; j < nP; ++j) {
-        double s = band[(size_t)j * (bw + 1)];
-        for (int k = std::max(0, j - bw); k < j; ++k) {
-            double l = band[(size_t)j * (bw + 1) + (j - k)];
-            s -= l * l;
-        }
-        IFETI_REQUIRE(s > 0.0, IFETI_ENOTSPD, "coarse matrix S_PP is not positive definite");
-        double ljj = std::sqrt(s);
-        band[(size_t)j * (bw + 1)] = ljj;
-        for (int i = j + 1; i <= std::min(nP - 1, j + bw); ++i) {
-            double t = band[(size_t)i * (bw + 1) + (i - j)];
-            for (int k = std::max(0, i - bw); k < j; ++k)
-                t -= band[(size_t)i * (bw + 1) + (i - k)] * band[(size_t)j * (bw + 1) + (j - k)];
-            band[(size_t)i * (bw + 1) + (i - j)] = t / ljj;
-        }
-    }
+    // banded Cholesky factor L[i][j] -> band[i][i-j], on the GPU
+    clk.mark("coarse matrix assembly");
+    band = band_cholesky_device(c, band, nP, bw);
+    clk.mark("coarse factor");
     // 6. upload the bank and the coefficients
     c->K = K;
     c->sigma = sigma;
@@ -989,9 +942,12 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     make_lp_copies(c, {{c->Fdd.p, c->Fdd.n}, {c->Sdd.p, c->Sdd.n}, {c->W.p, c->W.n}, {c->WT.p, c->WT.n},
                        {c->UrdT.p, c->UrdT.n}, {c->Urd.p, c->Urd.n}, {c->Urp.p, c->Urp.n}, {c->UrpT.p, c->UrpT.n},
                        {c->Kinv.p, c->Kinv.n}});
+    clk.mark("bank upload + copies");
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
     coarse_inverse_device(c, c->co, band, bw);
+    clk.mark("coarse inverse");
     build_coarse_partition(c, c->co);
+    clk.mark("coarse partition");
     IFETI_HIP(hipStreamSynchronize(c->stream));
     c->rom_built = true;
 }
