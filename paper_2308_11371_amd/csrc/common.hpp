@@ -322,6 +322,9 @@ int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *princ
                   std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
 void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw);
 void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co);
+// trace tables Psi [2 npair + K][n_snap] of eq. (42) from the principal K_rr^-1 [k][n_r][n_r] and
+// U_rp^T [k][n_p][n_r] on the device
+void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *UqT, double *Psi);
 // lower-band Cholesky factor L[i][i-j] of the symmetric band matrix band[i][i-j] (ENOTSPD if not SPD)
 std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw);
 

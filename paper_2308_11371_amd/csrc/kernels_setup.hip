@@ -326,6 +326,116 @@ __global__ __launch_bounds__(64) void k_band_inverse(const double *__restrict__ 
     for (int i = lane; i < n; i += 64) X[(size_t)j * n + i] = x[i];
 }
 
+// Trace tables of eq. (42) at quadrature point eq = blockIdx.x (the lookup-table form of eqs. (52)-(54)).
+// With the gradients at the point of the principal fields, G_p[(k,ab)][a] = sum_l dN_l[j] U_rp^(k)[r(l,i)][a]
+// and G_d[(k,ab)][c] = sum_l dN_l[j] K_rr^(k)-1[r(l,i)][n_i + c] (ab = i d + j, r(l,i) the r position of
+// local dof (l,i)), and the primal unit fields ge[ab][a] = sum_l dN_l[j] [p(l,i) = a]:
+//   Psi[t][eq][ab][cd]         = w_q G_p[(i,ab)] . G_p[(j,cd)]     (A pairs t = (i <= j))
+//   Psi[npair + t][eq][ab][cd] = w_q G_d[(i,ab)] . G_d[(j,cd)]     (M pairs)
+//   Psi[2 npair + i][eq][ab][cd] = w_q G_p[(i,ab)] . ge[cd]          (b)
+// G_d is built in LDS in chunks of NC dual columns; each thread accumulates up to MAXE M entries per
+// pass in registers (fixed column order: bitwise reproducible).
+template <int D>
+__global__ __launch_bounds__(256) void k_trace_tables(const double *__restrict__ Kinv, const double *__restrict__ UqT,
+                                                      const double *__restrict__ dN, const double *__restrict__ wts,
+                                                      const int *__restrict__ elem_ctrl,
+                                                      const int *__restrict__ r_of_dof,
+                                                      const int *__restrict__ p_of_dof,
+                                                      const int *__restrict__ pair_i, const int *__restrict__ pair_j,
+                                                      int K, int n_r, int n_p, int n_i, int n_d, int nq, int nloc,
+                                                      long long nsnap, double *__restrict__ Psi) {
+    constexpr int D2 = D * D, D4 = D2 * D2, NC = 16, NCS = NC + 1, MAXE = 48;
+    extern __shared__ double sm[];
+    const int eq = blockIdx.x, E = eq / nq, tid = threadIdx.x;
+    const int KD2 = K * D2, npair = K * (K + 1) / 2, nld = nloc * D;
+    double *Gp = sm;
+    double *ge = Gp + (size_t)KD2 * n_p;
+    double *Gd = ge + (size_t)D2 * n_p;
+    double *dn = Gd + (size_t)KD2 * NCS;
+    int *rpl = (int *)(dn + nld);
+    int *ppl = rpl + nld;
+    for (int e = tid; e < nld; e += 256) {
+        const int l = e / D, i1 = e % D;
+        const int dof = elem_ctrl[(size_t)E * nloc + l] * D + i1;
+        rpl[e] = r_of_dof[dof];
+        ppl[e] = p_of_dof[dof];
+        dn[e] = dN[((size_t)eq * nloc + l) * D + i1];  // dn[l*D + j] = dN_l[j]
+    }
+    __syncthreads();
+    for (int e = tid; e < KD2 * n_p; e += 256) {
+        const int row = e / n_p, a = e % n_p, k = row / D2, ab = row % D2, i1 = ab / D, j1 = ab % D;
+        double s = 0.0;
+        for (int l = 0; l < nloc; ++l) {
+            const int rp = rpl[l * D + i1];
+            if (rp >= 0) s += dn[l * D + j1] * UqT[((size_t)k * n_p + a) * n_r + rp];
+        }
+        Gp[e] = s;
+    }
+    for (int e = tid; e < D2 * n_p; e += 256) {
+        const int ab = e / n_p, a = e % n_p, i1 = ab / D, j1 = ab % D;
+        double s = 0.0;
+        for (int l = 0; l < nloc; ++l)
+            if (ppl[l * D + i1] == a) s += dn[l * D + j1];
+        ge[e] = s;
+    }
+    __syncthreads();
+    const double w = wts[eq];
+    const size_t base = (size_t)eq * D4;
+    for (int e = tid; e < npair * D4; e += 256) {
+        const int t = e / D4, rem = e % D4, ab = rem / D2, cd = rem % D2;
+        const double *u = Gp + (size_t)(pair_i[t] * D2 + ab) * n_p, *v = Gp + (size_t)(pair_j[t] * D2 + cd) * n_p;
+        double s = 0.0;
+        for (int a = 0; a < n_p; ++a) s += u[a] * v[a];
+        Psi[(size_t)t * nsnap + base + rem] = w * s;
+    }
+    for (int e = tid; e < K * D4; e += 256) {
+        const int i = e / D4, rem = e % D4, ab = rem / D2, cd = rem % D2;
+        const double *u = Gp + (size_t)(i * D2 + ab) * n_p, *v = ge + (size_t)cd * n_p;
+        double s = 0.0;
+        for (int a = 0; a < n_p; ++a) s += u[a] * v[a];
+        Psi[(size_t)(2 * npair + i) * nsnap + base + rem] = w * s;
+    }
+    const int nM = npair * D4;
+    for (int e0 = 0; e0 < nM; e0 += 256 * MAXE) {
+        double acc[MAXE];
+#pragma unroll
+        for (int m = 0; m < MAXE; ++m) acc[m] = 0.0;
+        for (int c0 = 0; c0 < n_d; c0 += NC) {
+            __syncthreads();  // the previous chunk is consumed
+            for (int e = tid; e < KD2 * NC; e += 256) {
+                const int row = e / NC, cc = e % NC, col = c0 + cc;
+                const int k = row / D2, ab = row % D2, i1 = ab / D, j1 = ab % D;
+                double s = 0.0;
+                if (col < n_d)
+                    for (int l = 0; l < nloc; ++l) {
+                        const int rp = rpl[l * D + i1];
+                        if (rp >= 0) s += dn[l * D + j1] * Kinv[((size_t)k * n_r + rp) * n_r + n_i + col];
+                    }
+                Gd[(size_t)row * NCS + cc] = s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MAXE; ++m) {
+                const int e = e0 + tid + 256 * m;
+                if (e < nM) {
+                    const int t = e / D4, rem = e % D4, ab = rem / D2, cd = rem % D2;
+                    const double *u = Gd + (size_t)(pair_i[t] * D2 + ab) * NCS;
+                    const double *v = Gd + (size_t)(pair_j[t] * D2 + cd) * NCS;
+                    double s = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc) s += u[cc] * v[cc];
+                    acc[m] += s;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MAXE; ++m) {
+            const int e = e0 + tid + 256 * m;
+            if (e < nM) Psi[(size_t)(npair + e / D4) * nsnap + base + e % D4] = w * acc[m];
+        }
+    }
+}
+
 inline unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -427,6 +537,36 @@ __global__ __launch_bounds__(kBlock) void k_sym_pack(const double *__restrict__ 
         const int r = I * 64 + e / 64, cc = J * 64 + e % 64;
         dst[e] = (r < n && cc < n) ? S[(size_t)r * n + cc] : 0.0;
     }
+}
+
+void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *UqT, double *Psi) {
+    const RefTables &R = c->ref;
+    const int npair = K * (K + 1) / 2, d2 = R.dim * R.dim, nld = R.nloc * R.dim;
+    std::vector<int> pi((size_t)npair), pj((size_t)npair);
+    for (int i = 0, t = 0; i < K; ++i)
+        for (int j = i; j < K; ++j, ++t) {
+            pi[t] = i;
+            pj[t] = j;
+        }
+    DevBuf<int> dpi, dpj;
+    dpi.upload(pi, c->stream);
+    dpj.upload(pj, c->stream);
+    const size_t lds = sizeof(double) * ((size_t)K * d2 * c->n_p + (size_t)d2 * c->n_p + (size_t)K * d2 * 17 + nld) +
+                       sizeof(int) * 2 * (size_t)nld;
+    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "too many principal cells for the trace tables");
+    const int nqp = R.n_elem * R.nq;
+    auto launch = [&](auto kern) {
+        IFETI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(nqp), dim3(256), lds, c->stream, Kinv, UqT, c->g_tables_dN.p, c->g_tables_w.p,
+                           c->g_tables_ctrl.p, c->r_of_dof.p, c->p_of_dof.p, dpi.p, dpj.p, K, c->n_r, c->n_p,
+                           c->n_i, c->n_d, R.nq, R.nloc, (long long)R.n_snap, Psi);
+    };
+    if (R.dim == 2)
+        launch(k_trace_tables<2>);
+    else
+        launch(k_trace_tables<3>);
+    IFETI_HIP(hipGetLastError());
+    IFETI_HIP(hipStreamSynchronize(c->stream));  // the pair tables are released on return
 }
 
 void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw) {

@@ -685,10 +685,11 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     //    [K_rr K_rp I; K_pr K_pp 0; I 0 0] factorised on the GPU (the batched elimination of the
     //    standard FETI-DP form with every r row selected), giving K_rr^-1, U_rp, S_pp, S_dd, K_pr, K_pp
     std::vector<Principal> bank(K);
+    DevBuf<double> dFq, dUqT;  // K_rr^-1 and U_rp^T of the principals, also used by the trace tables
     {
         DevBuf<int> dsig;
         dsig.upload(sigma, c->stream);
-        DevBuf<double> dFq, dSdd, dUqT, dSpp, dKpr, dKpp;
+        DevBuf<double> dSdd, dSpp, dKpr, dKpp;
         dFq.alloc((size_t)K * nr * nr);
         dSdd.alloc((size_t)K * nd * nd);
         dUqT.alloc((size_t)K * np * nr);
@@ -749,67 +750,10 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                 ++t;
             }
     }
-    std::vector<int> rpos_of(R.n_dof, -1), ppos_of(R.n_dof, -1);
-    for (int i = 0; i < nr; ++i) rpos_of[c->idx_r[i]] = i;
-    for (int i = 0; i < np; ++i) ppos_of[c->idx_p[i]] = i;
     const size_t nsnap = (size_t)R.n_snap;
-    std::vector<double> Psi((size_t)ncoef * nsnap, 0.0);
-    const int nqp = R.n_elem * R.nq;
-    parallel_for(nqp, [&](int eq) {
-        const int E = eq / R.nq;
-        const double wq = R.w[eq];
-        // gradients at this point: gp[k][ab][a] (U_rp), gd[k][ab][col] (U_rd), ge[ab][a] (primal unit fields)
-        std::vector<double> gp((size_t)K * d2 * np, 0.0), gd((size_t)K * d2 * nd, 0.0), ge((size_t)d2 * np, 0.0);
-        for (int l = 0; l < R.nloc; ++l) {
-            const int a = R.elem_ctrl[E * R.nloc + l];
-            const double *dNl = &R.dN[((size_t)eq * R.nloc + l) * d];
-            for (int i1 = 0; i1 < d; ++i1) {
-                const int dof = a * d + i1;
-                const int rp = rpos_of[dof], pp = ppos_of[dof];
-                for (int j1 = 0; j1 < d; ++j1) {
-                    const int ab = i1 * d + j1;
-                    const double g = dNl[j1];
-                    if (pp >= 0) ge[(size_t)ab * np + pp] += g;
-                    if (rp < 0) continue;
-                    for (int k = 0; k < K; ++k) {
-                        const double *urp = &bank[k].Urp[(size_t)rp * np];
-                        double *gpk = &gp[((size_t)k * d2 + ab) * np];
-                        for (int t = 0; t < np; ++t) gpk[t] += g * urp[t];
-                        const double *urd = &bank[k].Kinv[(size_t)rp * nr + ni];
-                        double *gdk = &gd[((size_t)k * d2 + ab) * nd];
-                        for (int t = 0; t < nd; ++t) gdk[t] += g * urd[t];
-                    }
-                }
-            }
-        }
-        const size_t base = (size_t)eq * d4;
-        for (int t = 0; t < npair; ++t) {
-            const int i = pi_i[t], j = pi_j[t];
-            double *psiA = &Psi[(size_t)t * nsnap + base];
-            double *psiM = &Psi[(size_t)(npair + t) * nsnap + base];
-            for (int ab = 0; ab < d2; ++ab)
-                for (int cd = 0; cd < d2; ++cd) {
-                    const double *u = &gp[((size_t)i * d2 + ab) * np], *v = &gp[((size_t)j * d2 + cd) * np];
-                    double sa = 0.0;
-                    for (int q = 0; q < np; ++q) sa += u[q] * v[q];
-                    psiA[ab * d2 + cd] = wq * sa;
-                    const double *x = &gd[((size_t)i * d2 + ab) * nd], *y = &gd[((size_t)j * d2 + cd) * nd];
-                    double sm = 0.0;
-                    for (int q = 0; q < nd; ++q) sm += x[q] * y[q];
-                    psiM[ab * d2 + cd] = wq * sm;
-                }
-        }
-        for (int i = 0; i < K; ++i) {
-            double *psib = &Psi[(size_t)(2 * npair + i) * nsnap + base];
-            for (int ab = 0; ab < d2; ++ab)
-                for (int cd = 0; cd < d2; ++cd) {
-                    const double *u = &gp[((size_t)i * d2 + ab) * np], *v = &ge[(size_t)cd * np];
-                    double sb = 0.0;
-                    for (int q = 0; q < np; ++q) sb += u[q] * v[q];
-                    psib[ab * d2 + cd] = wq * sb;
-                }
-        }
-    });
+    DevBuf<double> dPsi;
+    dPsi.alloc((size_t)ncoef * nsnap);
+    trace_tables_device(c, K, dFq.p, dUqT.p, dPsi.p);
     std::vector<double> dv(K);
     for (int m = 0; m < K; ++m) {
         double tr = 0.0;
@@ -820,8 +764,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     launch_pulled_back(c);
     std::vector<double> traces((size_t)N * ncoef);
     {
-        DevBuf<double> dPsi, dOut;
-        dPsi.upload(Psi, c->stream);
+        DevBuf<double> dOut;
         dOut.alloc((size_t)N * ncoef);
         GemmGroup g;
         g.A = dPsi.p;
@@ -854,7 +797,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     clk.mark("pi, delta systems");
     // 5. S̊_pp^(s) = sym(K̊_pp - K̊_rp^T Ů_rp) (43) and the coarse matrix (Sec. 3.2.1)
     std::vector<double> Q((size_t)K * K * np * np);  // Q[m][k] = K_rp^(m)T U_rp^(k)
-    for (int m = 0; m < K; ++m)
+    parallel_for(K, [&](int m) {
         for (int k = 0; k < K; ++k)
             for (int a = 0; a < np; ++a)
                 for (int b = 0; b < np; ++b) {
@@ -862,6 +805,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                     for (int r = 0; r < nr; ++r) s += bank[m].Krp[(size_t)r * np + a] * bank[k].Urp[(size_t)r * np + b];
                     Q[(((size_t)m * K + k) * np + a) * np + b] = s;
                 }
+    });
     const int nP = c->nP;
     int bw = 0;
     for (int s = 0; s < N; ++s)
@@ -871,9 +815,10 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                 if (A1 >= 0 && B1 >= 0) bw = std::max(bw, std::abs(A1 - B1));
             }
     std::vector<double> band((size_t)nP * (bw + 1), 0.0);  // band[i][i-j] for j <= i
-    for (int s = 0; s < N; ++s) {
+    std::vector<double> Xs((size_t)N * np * np, 0.0);     // per-cell S̊_pp, in parallel
+    parallel_for(N, [&](int s) {
         const double *a = &alpha[(size_t)s * K], *pk = &pi[(size_t)s * K];
-        std::vector<double> X((size_t)np * np, 0.0);
+        double *X = &Xs[(size_t)s * np * np];
         for (int m = 0; m < K; ++m) {
             for (int t = 0; t < np * np; ++t) X[t] += a[m] * bank[m].Kpp[t];
             for (int k = 0; k < K; ++k) {
@@ -882,6 +827,9 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
                 for (int t = 0; t < np * np; ++t) X[t] -= w * q[t];
             }
         }
+    });
+    for (int s = 0; s < N; ++s) {  // assembly in cell order (fixed summation order)
+        const double *X = &Xs[(size_t)s * np * np];
         for (int i = 0; i < np; ++i)
             for (int j = 0; j < np; ++j) {
                 int I = c->h_Ap[(size_t)s * np + i], J = c->h_Ap[(size_t)s * np + j];
@@ -907,7 +855,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     std::vector<double> Fdd((size_t)K * nd * nd), Sdd((size_t)K * nd * nd), W((size_t)K * nd * np),
         WT((size_t)K * np * nd), UrdT((size_t)K * nd * nr), Urd((size_t)K * nr * nd), Urp((size_t)K * nr * np),
         UrpT((size_t)K * np * nr), Kinv((size_t)K * nr * nr);
-    for (int k = 0; k < K; ++k) {
+    parallel_for(K, [&](int k) {  // each principal fills its own slices
         const Principal &P = bank[k];
         std::copy(P.Fdd.begin(), P.Fdd.end(), &Fdd[(size_t)k * nd * nd]);
         std::copy(P.Sdd.begin(), P.Sdd.end(), &Sdd[(size_t)k * nd * nd]);
@@ -928,7 +876,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
             }
             for (int a = 0; a < np; ++a) UrpT[((size_t)k * np + a) * nr + r] = P.Urp[(size_t)r * np + a];
         }
-    }
+    });
     c->Fdd.upload(Fdd, c->stream);
     c->Sdd.upload(Sdd, c->stream);
     c->W.upload(W, c->stream);
