@@ -222,11 +222,6 @@ struct ifeti_ctx {
     ifeti::CoarseSolver co_ex;
     ifeti::DevBuf<double> ex_w, ex_g, ex_z, ex_d;
     bool rom_built = false;
-    struct LPCopy {                     // fp32 / bf16 copies of a bank array (precision form)
-        const double *src = nullptr;
-        size_t n = 0;
-        void *f32 = nullptr, *bf16 = nullptr;
-    };
     bool capturing = false;             // a HIP graph capture is in progress on `stream`
     hipStream_t own_stream = nullptr;   // non-blocking stream of the graph form (default priority)
     void *h_pin = nullptr;              // pinned host staging for convergence reads (hipHostMalloc)
@@ -249,7 +244,6 @@ struct ifeti_ctx {
     long long rom_gen = 0;              // bumped whenever the reduced basis / cell data change
     std::map<std::vector<long long>, int> tuned;  // contraction shape -> chosen tile candidate
     hipEvent_t ev_own_in = nullptr, ev_own_out = nullptr;
-    std::vector<LPCopy> lp;
     struct FragCopy {                   // a bank array in MFMA-fragment order, per (M, Kd, K, element type) view
         const double *src = nullptr;
         int M = 0, Kd = 0, K = 0, kind = 0;  // kind: IFETI_FP64 / IFETI_FP32_LOCAL / IFETI_BF16_LOCAL
@@ -258,11 +252,6 @@ struct ifeti_ctx {
     std::vector<FragCopy> frag;
     void free_copies() {
         ++rom_gen;
-        for (auto &cp : lp) {
-            if (cp.f32) (void)hipFree(cp.f32);
-            if (cp.bf16) (void)hipFree(cp.bf16);
-        }
-        lp.clear();
         for (auto &cp : frag)
             if (cp.frag) (void)hipFree(cp.frag);
         frag.clear();
@@ -332,8 +321,6 @@ std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
           bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
-void make_lp_copies(ifeti_ctx *c, const std::vector<std::pair<const double *, size_t>> &arrays);
-const void *lp_copy(ifeti_ctx *c, const double *A, int precision);
 
 // ops.hip
 class SideStream {

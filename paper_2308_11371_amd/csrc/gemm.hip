@@ -7,21 +7,21 @@
 // operators of eqs. (48), (49), Algorithm 3 and eq. (46a) as sums over the
 // principal cells), so all cells become one dense contraction.
 //
-// Mapping (one wave64 = one 16-column block x BM 16-row blocks):
-//  * the wave keeps its 16 cell vectors X[:, c] in registers, one chunk of
-//    up to 128 rows at a time (B fragment of the MFMA: lane l holds column
-//    l%16, rows 4t + l/16), and scales them by the cell coefficient of the
-//    current principal while feeding the MFMA;
-//  * the principal operator streams from L2 (A fragment: lane l holds row
-//    l%16, columns 4t + l/16); 8 steps of A fragments are loaded ahead of
-//    their MFMAs to cover the L2 latency;
-//  * a workgroup is 4 waves.  SPLIT = 1: the 4 waves own 4 consecutive
-//    column blocks of the same rows (they read the same A stream, shared
-//    through L1).  SPLIT = 4: the 4 waves own the same tile and split the
-//    principals (k = wave mod 4); partial sums are reduced through LDS in a
-//    fixed order (small M, e.g. the 8 primal rows).
+// Kernels (each principal operator is copied once into MFMA-fragment order, so
+// a wave reads one coalesced 16-byte unit per lane per MFMA group):
+//  * pc64_tile — operators resident in L2 (the dual/primal blocks of the
+//    bank): NW waves share one output tile, split the (principal, inner step)
+//    sequence round-robin and sum their partial tiles through LDS by a fixed
+//    pairwise tree;
+//  * k_pc64_big — tall operators (the stacked local inverses of eq. (46a)):
+//    waves own distinct row tiles and run the whole sequence;
+//  * k_pclp_tile / k_pclp_big — the same two shapes for the precision form
+//    (FP32 16x16x4 or BF16 16x16x32 MFMAs, FP32 accumulation).
+// The cell vectors of a tile's columns are staged in LDS (plain columns, or
+// gathered from the interface multipliers through the jump codes) and scaled
+// by the cell's coefficient of the current principal as they are fed.
 // The 16x16 f64 MFMA returns D with lane l, register i -> row 4*i + l/16,
-// column l % 16 (checked on gfx950).
+// column l % 16; the f32 / bf16 ones row 4*(l/16) + i (checked on gfx950).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -50,129 +50,9 @@ struct GemmArgsDev {
     int ldy, M, ncols, ncells, accumulate;
 };
 
-constexpr int LT = 64;          // columns of A per LDS tile
-constexpr int KCH = 128;       // rows of X held in registers per chunk
-constexpr int TSTEPS = KCH / 4;
-constexpr int PF = 8;          // A-fragment steps loaded ahead
 
-// ---------------------------------------------------------------- low-precision operands
-// Precision form: the principal operators (and the cell vectors, rounded as they
-// are fed) in fp32 (v_mfma_f32_16x16x4f32) or bf16 (v_mfma_f32_16x16x32_bf16)
-// with fp32 accumulation; results are returned in float64.  Same staging as the
-// FP64 kernel: 32 x 64 operator tiles in LDS, double-buffered through registers;
-// each wave keeps 16 cell vectors in registers.  The f32/bf16 16x16 MFMAs return
-// D with lane l, register i -> row 4*(l/16) + i, column l % 16 (checked on gfx950).
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-struct GemmArgsLP {
-    const void *A[2];
-    const double *X[2];
-    const double *coef[2];
-    int Kd[2], ldx[2], K[2];
-    long long xbs[2];
-    double scale[2];
-    int ngroups;
-    double *Y;
-    long long ybs;
-    int ldy, M, ncols, ncells, accumulate;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_pcontract_lp(GemmArgsLP g) {
-    constexpr bool BF = sizeof(T) == 2;
-    constexpr int KS = BF ? 32 : 4;          // reduction depth of one MFMA
-    constexpr int LDL = LT + (BF ? 8 : 4);   // padded LDS row (elements)
-    __shared__ __attribute__((aligned(16))) T As[2][32][LDL];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int m0 = blockIdx.y * 32;
-    const int col = (blockIdx.x * 4 + wave) * 16 + lr;
-    const bool cvalid = col < g.ncols;
-    const int cell = cvalid ? col % g.ncells : 0;
-    const long long rhs = cvalid ? col / g.ncells : 0;
-    const int ld_row = tid >> 3, ld_c = (tid & 7) * 8;
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    for (int gi = 0; gi < g.ngroups; ++gi) {
-        const T *__restrict__ A = reinterpret_cast<const T *>(g.A[gi]);
-        const double *__restrict__ coef = g.coef[gi];
-        const int Kd = g.Kd[gi], K = g.K[gi];
-        const long long strideA = (long long)g.M * Kd;
-        const double *__restrict__ xcol = g.X[gi] + rhs * g.xbs[gi] + (size_t)cell * g.ldx[gi];
-        const double scale = g.scale[gi];
-        for (int kk = 0; kk < Kd; kk += KCH) {
-            // lane's share of the chunk: f32: k = 4t + l/16; bf16: k = 32t + 8(l/16) + e
-            float braw[TSTEPS];
-#pragma unroll
-            for (int t = 0; t < TSTEPS; ++t) {
-                const int kx = BF ? kk + 32 * (t / 8) + 8 * lk + (t % 8) : kk + 4 * t + lk;
-                braw[t] = (cvalid && kx < Kd) ? (float)xcol[kx] : 0.f;
-            }
-            const int nsub = (std::min(KCH, Kd - kk) + LT - 1) / LT;
-            const int ntile = K * nsub;
-            T st[8];
-            auto fetch = [&](int tile) {
-                const int k = tile / nsub, sub = tile % nsub;
-                const int row = m0 + ld_row, c0 = kk + sub * LT + ld_c;
-                const T *src = A + (size_t)k * strideA + (size_t)row * Kd + c0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) st[u] = (row < g.M && c0 + u < Kd) ? src[u] : T(0.f);
-            };
-            fetch(0);
-            for (int tile = 0; tile < ntile; ++tile) {
-                const int buf = tile & 1;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) As[buf][ld_row][ld_c + u] = st[u];
-                __syncthreads();
-                if (tile + 1 < ntile) fetch(tile + 1);
-                const int k = tile / nsub, sub = tile % nsub;
-                const float cf = cvalid ? (float)(scale * (coef ? coef[(size_t)cell * K + k] : 1.0)) : 0.f;
-                auto consume = [&](auto SUB) {
-                    constexpr int sb = decltype(SUB)::value;
-#pragma unroll
-                    for (int u = 0; u < LT / KS; ++u) {
-                        if constexpr (BF) {
-                            const v8bf a0 = *reinterpret_cast<const v8bf *>(&As[buf][lr][KS * u + 8 * lk]);
-                            const v8bf a1 = *reinterpret_cast<const v8bf *>(&As[buf][16 + lr][KS * u + 8 * lk]);
-                            v8bf b;
-#pragma unroll
-                            for (int e = 0; e < 8; ++e) b[e] = (__bf16)(braw[(sb * (LT / KS) + u) * 8 + e] * cf);
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc1, 0, 0, 0);
-                        } else {
-                            const float b = braw[sb * (LT / KS) + u] * cf;
-                            const float a0 = As[buf][lr][KS * u + lk];
-                            const float a1 = As[buf][16 + lr][KS * u + lk];
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc1, 0, 0, 0);
-                        }
-                    }
-                };
-                if (sub == 0)
-                    consume(std::integral_constant<int, 0>{});
-                else
-                    consume(std::integral_constant<int, 1>{});
-                __syncthreads();
-            }
-        }
-    }
-    if (!cvalid) return;
-    double *ycol = g.Y + rhs * g.ybs + (size_t)cell * g.ldy;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r0 = m0 + 4 * lk + i, r1 = r0 + 16;
-        if (r0 < g.M) ycol[r0] = g.accumulate ? ycol[r0] + (double)acc0[i] : (double)acc0[i];
-        if (r1 < g.M) ycol[r1] = g.accumulate ? ycol[r1] + (double)acc1[i] : (double)acc1[i];
-    }
-}
-
-__global__ void k_to_lp(const double *__restrict__ x, float *__restrict__ f, __bf16 *__restrict__ b, long long n) {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const float v = (float)x[t];
-    f[t] = v;
-    b[t] = (__bf16)v;
-}
 
 // ---------------------------------------------------------------- fragment-ordered FP64 path
 // For operators that stay resident in L2 (the dual/primal blocks of the
@@ -220,10 +100,10 @@ constexpr int kMaxCoefK = 40;
 // fused (weighted) jump transpose from the signed multiplier rows in `gcodes`.  Entries
 // are taken in batches of up to SBMAX per thread with every load of a batch (codes, then
 // multiplier rows and weights) issued before the first is consumed.
-template <int NC, int KC, int NT, int XST, int SBMAX>
-__device__ __forceinline__ void stage_chunk(const GemmArgsFrag &g, const double *__restrict__ X,
+template <int NC, int KC, int NT, int XST, int SBMAX, typename G, typename XT>
+__device__ __forceinline__ void stage_chunk(const G &g, const double *__restrict__ X,
                                             const int *__restrict__ gcodes, const double *__restrict__ gw, int Kd,
-                                            int ldx, long long xbs, int col0, int kk, int kc, double *__restrict__ Xs,
+                                            int ldx, long long xbs, int col0, int kk, int kc, XT *__restrict__ Xs,
                                             int tid) {
     constexpr int PER = (NC * KC + NT - 1) / NT;
     constexpr int SB = PER < SBMAX ? PER : SBMAX;
@@ -265,7 +145,7 @@ __device__ __forceinline__ void stage_chunk(const GemmArgsFrag &g, const double 
 #pragma unroll
         for (int i = 0; i < SB; ++i) {
             const int e = tid + (i0 + i) * NT;
-            if (e < NC * KC) Xs[(e / KC) * XST + e % KC] = v[i];
+            if (e < NC * KC) Xs[(e / KC) * XST + e % KC] = (XT)v[i];
         }
     }
 }
@@ -755,6 +635,166 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_big(GemmArgsFragLP g) {
         }
 }
 
+// ---------------------------------------------------------------- precision form, small M
+// FP32 / BF16 counterpart of pc64_tile for operators that stay in L2: NW waves
+// share one output tile of RT row tiles x CB column blocks; the cell vectors of
+// the tile's columns are staged in LDS as FP32 (gathered from the multipliers
+// when jump codes are given) and the (principal, fragment unit) sequence is
+// dealt round-robin to the waves; partial tiles are summed in FP32 by a fixed
+// pairwise tree, so each column's result does not depend on the launch shape.
+constexpr int LKC = 128;      // inner rows staged per chunk
+constexpr int LXS = LKC + 4;  // LDS row stride (floats)
+
+template <int RT, int CB, int NW>
+struct PclpLds {
+    static constexpr int NC = 16 * CB;
+    static constexpr int XW = NC * LXS;
+    static constexpr int RED = (NW / 2) * RT * CB * 256;
+    static constexpr int SX = XW > RED ? XW : RED;
+};
+
+template <typename T, int RT, int CB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_pclp_tile(GemmArgsFragLP g) {
+    static_assert((NW & (NW - 1)) == 0, "NW must be a power of two");
+    constexpr bool BF = sizeof(T) == 2;
+    constexpr int KPF = LpUnit<T>::KPF, U = LpUnit<T>::U, PF = 2;
+    constexpr int NT = 64 * NW, NC = 16 * CB;
+    using L = PclpLds<RT, CB, NW>;
+    __shared__ __attribute__((aligned(16))) float Xs[L::SX];
+    __shared__ float Cs[kMaxCoefK * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mt0 = blockIdx.y * RT, col0 = blockIdx.x * NC;
+    v4f acc[RT][CB];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    bool rtv[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) rtv[rt] = mt0 + rt < g.MT;
+
+    for (int gi = 0; gi < g.ngroups; ++gi) {
+        const T *__restrict__ Af = reinterpret_cast<const T *>(g.Af[gi]);
+        const double *__restrict__ X = g.X[gi];
+        const double *__restrict__ coef = g.coef[gi];
+        const int *__restrict__ gcodes = g.gcodes[gi];
+        const double *__restrict__ gw = g.gw[gi];
+        const int Kd = g.Kd[gi], K = g.K[gi], QU = g.QU[gi], ldx = g.ldx[gi];
+        const long long xbs = g.xbs[gi];
+        const double scale = g.scale[gi];
+        for (int kk = 0; kk < Kd; kk += LKC) {
+            const int kc = min(LKC, Kd - kk);
+            __syncthreads();  // previous chunk fully consumed
+            stage_chunk<NC, LKC, NT, LXS, 4>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
+            for (int e = tid; e < K * NC; e += NT) {
+                const int k = e / NC, cc = e % NC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
+                Cs[e] = (float)v;
+            }
+            __syncthreads();
+            const int np = (kc + KPF - 1) / KPF, q0 = kk / KPF, total = K * np;
+            const int ns = wave < total ? (total - wave + NW - 1) / NW : 0;  // steps s = wave + NW i
+            auto load = [&](int i, uint4 (&dst)[RT]) {
+                const int s = wave + NW * i, k = s / np, q = s % np;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    dst[rt] = rtv[rt] ? reinterpret_cast<const uint4 *>(
+                                            Af + ((((size_t)k * g.MT + mt0 + rt) * QU + q0 + q) * 64 + lane) * U)[0]
+                                      : uint4{0u, 0u, 0u, 0u};
+            };
+            uint4 ab[PF][RT];
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (u < ns) load(u, ab[u]);
+            for (int i0 = 0; i0 < ns; i0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int i = i0 + u;
+                    if (i < ns) {
+                        uint4 a[RT];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt) a[rt] = ab[u][rt];
+                        if (i + PF < ns) load(i + PF, ab[u]);
+                        const int s = wave + NW * i, k = s / np, q = s % np;
+                        float cf[CB];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+                        if constexpr (BF) {
+                            v8bf b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) {
+                                const float *xr = Xs + (cb * 16 + lr) * LXS + q * KPF + 8 * lk;
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
+                            }
+#pragma unroll
+                            for (int rt = 0; rt < RT; ++rt) {
+                                const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int r = q * KPF + 4 * j + lk;
+                                float b[CB];
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * LXS + r] * cf[cb];
+#pragma unroll
+                                for (int rt = 0; rt < RT; ++rt) {
+                                    const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
+                                    const float av = __builtin_bit_cast(float, aw);
+#pragma unroll
+                                    for (int cb = 0; cb < CB; ++cb)
+                                        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // pairwise tree over the waves: wave w += wave w + h, h = NW/2, NW/4, ..., 1
+#pragma unroll
+    for (int h = NW / 2; h >= 1; h >>= 1) {
+        __syncthreads();
+        if (wave >= h && wave < 2 * h)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        Xs[(((wave - h) * RT + rt) * CB + cb) * 256 + i * 64 + lane] = acc[rt][cb][i];
+        __syncthreads();
+        if (wave < h)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[rt][cb][i] += Xs[((wave * RT + rt) * CB + cb) * 256 + i * 64 + lane];
+    }
+    if (wave != 0) return;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int mt = mt0 + rt, col = col0 + cb * 16 + lr;
+            if (mt >= g.MT || col >= g.ncols) continue;
+            double *ycol = g.Y + (long long)(col / g.ncells) * g.ybs + (size_t)(col % g.ncells) * g.ldy;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * lk + i;
+                if (row < g.M) ycol[row] = g.accumulate ? ycol[row] + (double)acc[rt][cb][i] : (double)acc[rt][cb][i];
+            }
+        }
+}
+
 template <int RTW, int CB, int NW, int KCB, int PF = 2>
 void launch_big(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     dim3 grid((unsigned)((a.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((a.MT + RTW * NW - 1) / (RTW * NW)),
@@ -778,32 +818,6 @@ void launch_frag(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t
 }  // namespace
 
 // fp32/bf16 copies of the principal operators used by the precision form
-void make_lp_copies(ifeti_ctx *c, const std::vector<std::pair<const double *, size_t>> &arrays) {
-    IFETI_HIP(hipStreamSynchronize(c->stream));
-    c->free_copies();  // the bank was (re)built: every derived copy is stale
-    for (auto &ar : arrays) {
-        ifeti_ctx::LPCopy cp;
-        cp.src = ar.first;
-        cp.n = ar.second;
-        IFETI_HIP(hipMalloc(&cp.f32, ar.second * sizeof(float)));
-        IFETI_HIP(hipMalloc(&cp.bf16, ar.second * 2));
-        hipLaunchKernelGGL(k_to_lp, dim3((unsigned)((ar.second + 255) / 256)), dim3(256), 0, c->stream, ar.first,
-                           (float *)cp.f32, (__bf16 *)cp.bf16, (long long)ar.second);
-        IFETI_HIP(hipGetLastError());
-        c->lp.push_back(cp);
-    }
-}
-
-const void *lp_copy(ifeti_ctx *c, const double *A, int precision) {
-    for (auto &cp : c->lp)
-        if (A >= cp.src && A < cp.src + cp.n) {
-            const size_t off = A - cp.src;
-            return precision == IFETI_FP32_LOCAL ? (const void *)((const float *)cp.f32 + off)
-                                                 : (const void *)((const uint16_t *)cp.bf16 + off);
-        }
-    return nullptr;
-}
-
 // ---------------------------------------------------------------- tile autotuner
 // Candidate tile shapes of the two FP64 fragment kernels.  With options.autotune on, the first
 // launch of each (shape, column count) times every candidate of its family in place (the output
@@ -860,17 +874,28 @@ void launch_lp_big(const GemmArgsFragLP &f, hipStream_t s) {
     dim3 grid((unsigned)((f.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((f.MT + RTW * NW - 1) / (RTW * NW)));
     hipLaunchKernelGGL((k_pclp_big<T, RTW, CB, NW, KCB>), grid, dim3(64 * NW), 0, s, f);
 }
+template <typename T, int RT, int CB, int NW>
+void launch_lp_tile(const GemmArgsFragLP &f, hipStream_t s) {
+    dim3 grid((unsigned)((f.ncols + 16 * CB - 1) / (16 * CB)), (unsigned)((f.MT + RT - 1) / RT));
+    hipLaunchKernelGGL((k_pclp_tile<T, RT, CB, NW>), grid, dim3(64 * NW), 0, s, f);
+}
 using LpLauncher = void (*)(const GemmArgsFragLP &, hipStream_t);
-const LpLauncher kLpF32Candidates[] = {launch_lp_big<float, 2, 4, 4, 64>, launch_lp_big<float, 4, 2, 4, 64>,
-                                       launch_lp_big<float, 2, 2, 8, 64>, launch_lp_big<float, 2, 4, 4, 128>};
-const LpLauncher kLpBF16Candidates[] = {launch_lp_big<__bf16, 2, 4, 4, 64>, launch_lp_big<__bf16, 4, 2, 4, 64>,
-                                        launch_lp_big<__bf16, 2, 2, 8, 64>, launch_lp_big<__bf16, 2, 4, 4, 128>};
 constexpr int kNLp = 4;
+// [precision][shape][candidate]: FP32 / BF16; row-owning waves (large M) / shared tiles (small M)
+const LpLauncher kLpCandidates[2][2][kNLp] = {
+    {{launch_lp_big<float, 2, 4, 4, 64>, launch_lp_big<float, 4, 2, 4, 64>, launch_lp_big<float, 2, 2, 8, 64>,
+      launch_lp_big<float, 2, 4, 4, 128>},
+     {launch_lp_tile<float, 4, 2, 8>, launch_lp_tile<float, 2, 4, 4>, launch_lp_tile<float, 2, 2, 4>,
+      launch_lp_tile<float, 1, 2, 8>}},
+    {{launch_lp_big<__bf16, 2, 4, 4, 64>, launch_lp_big<__bf16, 4, 2, 4, 64>, launch_lp_big<__bf16, 2, 2, 8, 64>,
+      launch_lp_big<__bf16, 2, 4, 4, 128>},
+     {launch_lp_tile<__bf16, 4, 2, 8>, launch_lp_tile<__bf16, 2, 4, 4>, launch_lp_tile<__bf16, 2, 2, 4>,
+      launch_lp_tile<__bf16, 1, 2, 8>}}};
 
-static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool bf, bool tunable) {
-    const LpLauncher *cand = bf ? kLpBF16Candidates : kLpF32Candidates;
-    if (!c->opt.autotune || !tunable || c->capturing) return cand[2];  // the tuner's usual choice
-    std::vector<long long> key = {bf ? 3 : 2, f.M, f.ncols, f.ngroups};
+static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool bf, bool big, bool tunable) {
+    const LpLauncher *cand = kLpCandidates[bf ? 1 : 0][big ? 0 : 1];
+    if (!c->opt.autotune || !tunable || c->capturing) return cand[big ? 2 : 0];  // the tuner's usual choice
+    std::vector<long long> key = {bf ? 3 : 2, big ? 1 : 0, f.M, f.ncols, f.ngroups};
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) return cand[it->second];
@@ -896,8 +921,8 @@ static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool
     (void)hipEventDestroy(e1);
     c->tuned[key] = best;
     if (std::getenv("IFETI_TUNE_VERBOSE"))
-        std::fprintf(stderr, "[ifeti tune] %s M=%d ncols=%d Kd=%d K=%d -> candidate %d\n", bf ? "bf16" : "fp32", f.M,
-                     f.ncols, f.Kd[0], f.K[0], best);
+        std::fprintf(stderr, "[ifeti tune] %s %s M=%d ncols=%d Kd=%d K=%d -> candidate %d\n", bf ? "bf16" : "fp32",
+                     big ? "big" : "tile", f.M, f.ncols, f.Kd[0], f.K[0], best);
     return cand[best];
 }
 
@@ -989,16 +1014,14 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             bytes += 8.0 * (double)ncols * groups[i].Kd;
         }
     }
-    const long long cblocks = (ncols + 15) / 16;
     double abytes = 0.0;
     for (int i = 0; i < ngroups; ++i) abytes += 8.0 * (double)groups[i].K * M * groups[i].Kd;
     const bool lp_path = lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16;
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
-    const bool frag_path = !lp_path;
     // large operators, or many columns (a block of load cases): row-owning waves, fragment units
-    const bool lp_big = lp_path && Kmax <= kMaxCoefK && ((!frag_small && M >= 512) || (M >= 64 && ncols >= 16384));
-    if (lp_big) {
+    const bool lp_big = lp_path && ((!frag_small && M >= 512) || (M >= 64 && ncols >= 16384));
+    if (lp_path) {
         GemmArgsFragLP f{};
         const int kind = c->opt.precision;
         const bool bf = kind == IFETI_BF16_LOCAL;
@@ -1024,76 +1047,16 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         f.ncols = ncols;
         f.ncells = a.ncells;
         f.accumulate = a.accumulate;
-        const double esz = bf ? 2.0 : 4.0;
-        double lbytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
-        for (int i = 0; i < ngroups; ++i)
-            lbytes += esz * (double)groups[i].K * M * groups[i].Kd + 8.0 * (double)ncols * groups[i].Kd;
+        // as the FP64 count, with the operators moved in the narrow type
+        const double lbytes = bytes - (8.0 - (bf ? 2.0 : 4.0)) * abytes / 8.0;
         Prof prof(c, tag, flops, lbytes);
-        LpLauncher launch_fn = choose_lp_launcher(c, f, bf, !accumulate);
+        LpLauncher launch_fn = choose_lp_launcher(c, f, bf, lp_big, !accumulate);
         launch_fn(f, c->stream);
         IFETI_HIP(hipGetLastError());
         return;
     }
-    if (ngather > 0 && !frag_path) {
-        // only the fragment kernel stages through the jump codes: gather first, then contract
-        IFETI_REQUIRE(ngather == 1, IFETI_EINVAL, "gemm: at most one gathered group");
-        IFETI_REQUIRE(ncells <= 0 || ncells == c->N, IFETI_EINVAL, "gemm: gathered group needs all cells");
-        GemmGroup gg[2];
-        for (int i = 0; i < ngroups; ++i) {
-            gg[i] = groups[i];
-            if (gg[i].gcodes) {
-                const int nrhs = (int)(ncols / c->N);
-                op_gather(c, gg[i].X, gg[i].xbs, c->w_Lam.p, nrhs, gg[i].gw != nullptr);
-                gg[i].X = c->w_Lam.p;
-                gg[i].ldx = gg[i].Kd;
-                gg[i].xbs = 0;
-                gg[i].gcodes = nullptr;
-                gg[i].gw = nullptr;
-            }
-        }
-        gemm(c, gg, ngroups, Y, ldy, ybs, M, ncols, accumulate, ncells, tag, lp_ok);
-        return;
-    }
-    if (lp_path) {
-        GemmArgsLP b{};
-        bool all = true;
-        for (int i = 0; i < ngroups; ++i) {
-            const void *lpA = lp_copy(c, groups[i].A, c->opt.precision);
-            all = all && lpA;
-            b.A[i] = lpA;
-            b.X[i] = a.X[i];
-            b.coef[i] = a.coef[i];
-            b.Kd[i] = a.Kd[i];
-            b.ldx[i] = a.ldx[i];
-            b.xbs[i] = a.xbs[i];
-            b.K[i] = a.K[i];
-            b.scale[i] = a.scale[i];
-        }
-        if (all) {
-            b.ngroups = ngroups;
-            b.Y = Y;
-            b.ybs = a.ybs;
-            b.ldy = ldy;
-            b.M = M;
-            b.ncols = ncols;
-            b.ncells = a.ncells;
-            b.accumulate = a.accumulate;
-            const double esz = c->opt.precision == IFETI_FP32_LOCAL ? 4.0 : 2.0;
-            double lbytes = 8.0 * (double)ncols * M * (accumulate ? 2 : 1);
-            for (int i = 0; i < ngroups; ++i)
-                lbytes += esz * (double)groups[i].K * M * groups[i].Kd + 8.0 * (double)ncols * groups[i].Kd;
-            Prof prof(c, tag, flops, lbytes);
-            dim3 grid((unsigned)((cblocks + 3) / 4), (unsigned)((M + 31) / 32));
-            if (c->opt.precision == IFETI_FP32_LOCAL)
-                hipLaunchKernelGGL(k_pcontract_lp<float>, grid, dim3(256), 0, c->stream, b);
-            else
-                hipLaunchKernelGGL(k_pcontract_lp<__bf16>, grid, dim3(256), 0, c->stream, b);
-            IFETI_HIP(hipGetLastError());
-            return;
-        }
-    }
-    // L2-resident operators (a few MB per XCD) take the fragment-ordered path
-    if (frag_path) {
+    // FP64: L2-resident operators (a few MB per XCD) take the fragment-ordered path
+    {
         GemmArgsFrag f{};
         for (int i = 0; i < ngroups; ++i) {
             f.Af[i] = frag_copy(c, groups[i].A, M, groups[i].Kd, groups[i].K);
@@ -1138,7 +1101,6 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         IFETI_HIP(hipGetLastError());
         return;
     }
-    IFETI_REQUIRE(false, IFETI_EINVAL, "gemm: no kernel for this contraction");
 }
 
 

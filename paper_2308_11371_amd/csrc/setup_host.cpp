@@ -887,10 +887,9 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     c->UrpT.upload(UrpT, c->stream);
     c->Kinv.upload(Kinv, c->stream);
     combine_coarse_maps(c);
-    make_lp_copies(c, {{c->Fdd.p, c->Fdd.n}, {c->Sdd.p, c->Sdd.n}, {c->W.p, c->W.n}, {c->WT.p, c->WT.n},
-                       {c->UrdT.p, c->UrdT.n}, {c->Urd.p, c->Urd.n}, {c->Urp.p, c->Urp.n}, {c->UrpT.p, c->UrpT.n},
-                       {c->Kinv.p, c->Kinv.n}});
-    clk.mark("bank upload + copies");
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    c->free_copies();  // the bank was (re)built: every fragment-ordered copy is stale
+    clk.mark("bank upload");
     // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
     coarse_inverse_device(c, c->co, band, bw);
     clk.mark("coarse inverse");

@@ -14,13 +14,22 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
 
 
-@pytest.fixture(scope="module")
-def pair():
+CASES = {
+    "c1": lambda: latticegen.make("c1"),
+    # ragged tile counts (rows and columns), a traction load, and a 3D lattice
+    "ragged2d": lambda: latticegen.tiny(2, (5, 3), 4, n_principal=4, tractions=[[0.3, -0.7]]),
+    "tiny3d": lambda: latticegen.tiny(3, (2, 2, 2), 2, n_principal=3),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from oracle import Model
     from paper_2308_11371_amd import ifeti
-    prob = latticegen.make("c1")
+    print(f"[gpu precision] case {request.param}", flush=True)
+    prob = CASES[request.param]()
     m = Model(prob)
     m.build_reduced_basis()
     ctx = ifeti.setup(prob, principal_in=m.sigma)
@@ -43,6 +52,11 @@ def test_operators_low_precision(pair, prec, tol_op):
             err = rel(got, ref)
             print(f"{prec} {name}: rel err {err:.2e}")
             assert err < tol_op
+        # a block of load cases takes the same contraction per column
+        X = np.random.default_rng(5).standard_normal((3, m.L))
+        Y = ctx.apply_F(torch.tensor(X.ravel(), device="cuda"), nrhs=3).cpu().numpy().reshape(3, m.L)
+        for r in range(3):
+            assert rel(Y[r], m.apply_F(X[r])) < tol_op
     finally:
         ctx.set_options(precision=ifeti.IFETI_FP64)
 
