@@ -105,6 +105,12 @@ typedef struct {
     int coarse_parts;       /* coarse solve S̊_PP^-1 for 1-3 load cases: 0 automatic (fewest bytes per
                                apply), 1 the explicit inverse in symmetric tiles, p >= 2 the partitioned
                                solve with p interior blocks (EINVAL if the band does not allow p) */
+    int true_operator;      /* cell operator K^(s) in the true operator (16) (ifeti_apply_A, the outer
+                               solver, the displacement recovery): 0 the assembled stencil values,
+                               1 matrix-free (Sec. 4.2.1, Remark 9): from the pulled-back tensor at the
+                               quadrature points and the shared 1D B-spline tables, element by element
+                               in 3^dim colours (quadratic B-splines only, EINVAL otherwise); both
+                               are deterministic */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

@@ -65,6 +65,7 @@ int ifeti_create(ifeti_ctx **out, const ifeti_lattice_desc *d, void *stream) {
             c->g_tables_w.upload(R.w, c->stream);
             c->g_tables_xi.upload(R.xi, c->stream);
             c->g_tables_dN.upload(R.dN, c->stream);
+            c->g_tables_1d.upload(R.tab1, c->stream);
             c->g_tables_ctrl.upload(R.elem_ctrl, c->stream);
             c->g_idx_r.upload(c->idx_r, c->stream);
             c->g_idx_p.upload(c->idx_p, c->stream);
@@ -178,6 +179,9 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.timing_every = std::max(1, opt->timing_every);
         c->opt.use_graph = opt->use_graph ? 1 : 0;
         c->opt.autotune = opt->autotune ? 1 : 0;
+        REQ(opt->true_operator == 0 || opt->true_operator == 1, "true_operator must be 0 or 1");
+        REQ(opt->true_operator == 0 || c->ref.p == 2, "the matrix-free true operator needs quadratic B-splines");
+        c->opt.true_operator = opt->true_operator;
         REQ(opt->coarse_parts >= 0, "coarse_parts must be >= 0");
         if (opt->coarse_parts != c->opt.coarse_parts) {
             c->opt.coarse_parts = opt->coarse_parts;

@@ -86,6 +86,7 @@ struct RefTables {
     std::vector<double> xi;       // [E][q][dim] reference coordinates
     std::vector<double> dN;       // [E][q][l][dim] gradients of the local functions
     std::vector<int> elem_ctrl;   // [E][l] local control point index
+    std::vector<double> tab1;     // 1D tables: values [e][g][l], derivatives [e][g][l], weights [e][g]
 };
 
 // One group of the principal-combined contraction:
@@ -115,6 +116,7 @@ struct Options {
     int use_graph = 0;          // replay captured interface-PCG iterations (HIP graph)
     int autotune = 0;           // time the candidate tile shapes on first use of each contraction shape
     int coarse_parts = 0;       // coarse solve: 0 automatic, 1 symmetric-tile inverse, >= 2 that many blocks
+    int true_operator = 0;      // K^(s) in (16): 0 stencil values, 1 matrix-free from the pulled-back tensor
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -195,7 +197,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<int> p_of_dof;     // [n_dof] p position or -1
     ifeti::DevBuf<int> g_tables_ctrl;  // ref elem_ctrl
     ifeti::DevBuf<int> g_idx_r, g_idx_p;  // local dof of each r / p position
-    ifeti::DevBuf<double> g_tables_w, g_tables_xi, g_tables_dN;
+    ifeti::DevBuf<double> g_tables_w, g_tables_xi, g_tables_dN, g_tables_1d;
     bool cells_built = false;
     bool snap_valid = false;         // snapshots not yet consumed by a greedy
 

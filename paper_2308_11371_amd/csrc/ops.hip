@@ -745,6 +745,193 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
     }
 }
 
+// ------------------------------------------------------------------ matrix-free true cell operator
+// K^(s) u without the assembled values (Sec. 4.2.1, Remark 9): the stiffness is linear in the
+// pulled-back tensor Ĉ^(s) at the quadrature points (eq. (52)), so per element E and point q
+//   G_kl = sum_b u_{b,k} dN_{b,l}(q),  sigma_ij = sum_kl Ĉ_ijkl(q) G_kl,
+//   y_{a,i} += w_q sum_j dN_{a,j}(q) sigma_ij,
+// with dN built from the shared 1D B-spline tables (values v, derivatives d, weights w per
+// element and Gauss point).  Elements are taken in 3^D colours (e_j mod 3 per direction): two
+// elements of one colour share no control point (quadratic supports span 3), so each colour is
+// two passes — sigma of a batch of its elements into LDS, then the batch's outputs added into
+// the LDS result — and every output is summed over its elements in one fixed order.
+constexpr int kMfB = 256;
+
+template <int D>
+__global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ snap, const double *__restrict__ tab1,
+                                                    const double *__restrict__ x, long long x_rs, long long nU,
+                                                    const int *__restrict__ Ap, const int *__restrict__ idx_r,
+                                                    const int *__restrict__ idx_p, const int *__restrict__ r_of_dof,
+                                                    const int *__restrict__ p_of_dof, const int *__restrict__ gl,
+                                                    int N, int n_r, int n_p, int n_i, int n_d, int n_el, int eb,
+                                                    double *__restrict__ y, long long y_rs,
+                                                    double *__restrict__ yp_cells) {
+    constexpr int P1 = 3;                                   // quadratic: 3 functions and 3 points per direction
+    constexpr int NQ = D == 2 ? 9 : 27, NL = NQ, DD = D * D, D4 = DD * DD;
+    extern __shared__ double sm[];
+    const int nc = n_el + 2;
+    int n_ctrl = 1, n_elem = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        n_ctrl *= nc;
+        n_elem *= n_el;
+    }
+    const int n_dof = n_ctrl * D, nt1 = n_el * P1 * P1;
+    double *ul = sm, *yl = ul + n_dof, *sig = yl + n_dof, *tv = sig + (size_t)eb * NQ * DD, *td = tv + nt1,
+           *tw = td + nt1;
+    const int col = blockIdx.x, rhs = col / N, s = col % N, tid = threadIdx.x;
+    const double *u = x + rhs * x_rs;
+    const double *lam = u + nU;
+    for (int i = tid; i < n_r; i += kMfB) ul[idx_r[i]] = u[(size_t)s * n_r + i];
+    for (int j = tid; j < n_p; j += kMfB) {
+        const int P = Ap[(size_t)s * n_p + j];
+        ul[idx_p[j]] = P >= 0 ? u[(size_t)N * n_r + P] : 0.0;
+    }
+    for (int i = tid; i < n_dof; i += kMfB) yl[i] = 0.0;
+    for (int i = tid; i < 2 * nt1 + n_el * P1; i += kMfB) tv[i] = tab1[i];
+    __syncthreads();
+    const double *Cs = snap + (size_t)s * n_elem * NQ * D4;
+    int ncolour = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) ncolour *= 3;
+    for (int cl = 0; cl < ncolour; ++cl) {
+        int c0[D], cnt[D], ncl = 1;
+#pragma unroll
+        for (int j = 0, t = cl; j < D; ++j, t /= 3) {
+            c0[j] = t % 3;
+            cnt[j] = c0[j] < n_el ? (n_el - c0[j] + 2) / 3 : 0;
+            ncl *= cnt[j];
+        }
+        for (int b0 = 0; b0 < ncl; b0 += eb) {
+            const int nb = min(eb, ncl - b0);
+            // pass 1: w_q sigma(q) of each (element, point) of the batch
+            for (int t = tid; t < nb * NQ; t += kMfB) {
+                const int ie = t / NQ, q = t % NQ;
+                int e[D], g[D], E = 0;
+#pragma unroll
+                for (int j = 0, r = b0 + ie, qq = q; j < D; ++j) {
+                    e[j] = c0[j] + 3 * (r % cnt[j]);
+                    r /= cnt[j];
+                    g[j] = qq % P1;
+                    qq /= P1;
+                }
+#pragma unroll
+                for (int j = D - 1; j >= 0; --j) E = E * n_el + e[j];
+                double V[D][P1], Dv[D][P1], w = 1.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    w *= tw[e[j] * P1 + g[j]];
+#pragma unroll
+                    for (int l = 0; l < P1; ++l) {
+                        V[j][l] = tv[(e[j] * P1 + g[j]) * P1 + l];
+                        Dv[j][l] = td[(e[j] * P1 + g[j]) * P1 + l];
+                    }
+                }
+                double G[D][D];
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int l = 0; l < D; ++l) G[k][l] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    int lb[D], a = 0;
+#pragma unroll
+                    for (int j = 0, bb = b; j < D; ++j, bb /= P1) lb[j] = bb % P1;
+#pragma unroll
+                    for (int j = D - 1; j >= 0; --j) a = a * nc + e[j] + lb[j];
+                    double dN[D];
+#pragma unroll
+                    for (int l = 0; l < D; ++l) {
+                        double v = 1.0;
+#pragma unroll
+                        for (int m = 0; m < D; ++m) v *= m == l ? Dv[m][lb[m]] : V[m][lb[m]];
+                        dN[l] = v;
+                    }
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double uk = ul[a * D + k];
+#pragma unroll
+                        for (int l = 0; l < D; ++l) G[k][l] += uk * dN[l];
+                    }
+                }
+                const double *C = Cs + ((size_t)E * NQ + q) * D4;
+                double *sg = sig + (size_t)t * DD;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+#pragma unroll
+                            for (int l = 0; l < D; ++l) acc += C[((i * D + j) * D + k) * D + l] * G[k][l];
+                        sg[i * D + j] = w * acc;
+                    }
+            }
+            __syncthreads();
+            // pass 2: y_{a,i} += sum_q sum_j dN_{a,j}(q) sigma_ij(q); supports of one colour are disjoint
+            for (int t = tid; t < nb * NL * D; t += kMfB) {
+                const int ie = t / (NL * D), la = (t / D) % NL, i = t % D;
+                int e[D], lv[D], a = 0;
+#pragma unroll
+                for (int j = 0, r = b0 + ie, ll = la; j < D; ++j) {
+                    e[j] = c0[j] + 3 * (r % cnt[j]);
+                    r /= cnt[j];
+                    lv[j] = ll % P1;
+                    ll /= P1;
+                }
+#pragma unroll
+                for (int j = D - 1; j >= 0; --j) a = a * nc + e[j] + lv[j];
+                double V[D][P1], Dv[D][P1];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+#pragma unroll
+                    for (int g = 0; g < P1; ++g) {
+                        V[j][g] = tv[(e[j] * P1 + g) * P1 + lv[j]];
+                        Dv[j][g] = td[(e[j] * P1 + g) * P1 + lv[j]];
+                    }
+                const double *sg = sig + (size_t)ie * NQ * DD + i * D;
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    int g[D];
+#pragma unroll
+                    for (int j = 0, qq = q; j < D; ++j, qq /= P1) g[j] = qq % P1;
+#pragma unroll
+                    for (int jd = 0; jd < D; ++jd) {
+                        double v = 1.0;
+#pragma unroll
+                        for (int m = 0; m < D; ++m) v *= m == jd ? Dv[m][g[m]] : V[m][g[m]];
+                        acc += v * sg[q * DD + jd];
+                    }
+                }
+                yl[a * D + i] += acc;
+            }
+            __syncthreads();
+        }
+    }
+    double *yr = y + rhs * y_rs + (size_t)s * n_r;
+    for (int row = tid; row < n_dof; row += kMfB) {
+        double acc = yl[row];
+        const int rp = r_of_dof[row];
+        if (rp >= 0) {
+            if (rp >= n_i) {  // dual dof: add B_d^T lam
+                const int j = rp - n_i;
+#pragma unroll
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    const int code = gl[((size_t)s * n_d + j) * 2 + t2];
+                    if (code == 0) continue;
+                    const double lv = lam[(code > 0 ? code : -code) - 1];
+                    acc += code > 0 ? lv : -lv;
+                }
+            }
+            yr[rp] = acc;
+        } else {
+            yp_cells[(size_t)col * n_p + p_of_dof[row]] = acc;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ reductions (deterministic)
 __device__ inline double block_reduce(double v, double *sh) {
     int tid = threadIdx.x;
@@ -1255,7 +1442,32 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const long long nU = c->nU, rs = nU + c->L;
     const RefTables &R = c->ref;
     size_t shmem = (size_t)R.n_dof * sizeof(double);
-    {
+    if (c->opt.true_operator == 1) {
+        IFETI_REQUIRE(c->snap_valid, IFETI_EINVAL, "matrix-free true operator: pulled-back tensor not available");
+        IFETI_REQUIRE(R.p == 2, IFETI_EINVAL, "matrix-free true operator: quadratic B-splines only");
+        // pass-1 buffer of up to 2048 doubles (whole colours of the c2/c3 cells in one batch)
+        const int DD = c->dim * c->dim;
+        const int eb = std::max(1, 2048 / (R.nq * DD));
+        const size_t lds = (size_t)(2 * R.n_dof + eb * R.nq * DD + 2 * R.n_el * 9 + R.n_el * 3) * sizeof(double);
+        IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "matrix-free true operator: cell too large for LDS");
+        const double colsd = (double)N * nrhs;
+        // flops: per element and point, G (2 D^2 nloc), sigma (2 D^4), outputs (2 D^2 nloc)
+        const double fl = colsd * R.n_elem * R.nq * (4.0 * DD * R.nloc + 2.0 * DD * DD);
+        Prof prof(c, "true_K_mf", fl, 8.0 * (double)N * R.n_snap + colsd * 8.0 * 2.0 * R.n_dof);
+        if (c->dim == 2) {
+            IFETI_HIP(hipFuncSetAttribute((const void *)k_true_K_mf<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds));
+            hipLaunchKernelGGL(k_true_K_mf<2>, dim3(N * nrhs), dim3(kMfB), lds, c->stream, c->snap.p,
+                               c->g_tables_1d.p, x, rs, nU, c->g_Ap.p, c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p,
+                               c->p_of_dof.p, c->g_gather.p, N, nr, np, c->n_i, c->n_d, R.n_el, eb, y, rs, c->w_c.p);
+        } else {
+            IFETI_HIP(hipFuncSetAttribute((const void *)k_true_K_mf<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds));
+            hipLaunchKernelGGL(k_true_K_mf<3>, dim3(N * nrhs), dim3(kMfB), lds, c->stream, c->snap.p,
+                               c->g_tables_1d.p, x, rs, nU, c->g_Ap.p, c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p,
+                               c->p_of_dof.p, c->g_gather.p, N, nr, np, c->n_i, c->n_d, R.n_el, eb, y, rs, c->w_c.p);
+        }
+    } else {
     const double colsd = (double)N * nrhs;
     Prof prof(c, "true_K", colsd * 2.0 * c->nnz_full,
               8.0 * (double)N * R.n_ctrl * R.n_off * c->dim * c->dim + colsd * 8.0 * 2.0 * R.n_dof);

@@ -160,6 +160,9 @@ void build_reference_tables(ifeti_ctx *c) {
             w1[e * R.nq1 + g] = gw[g] / n_el;
             span_basis_ders(U, e + p, u, p, &v1[(e * R.nq1 + g) * (p + 1)], &d1[(e * R.nq1 + g) * (p + 1)]);
         }
+    R.tab1.assign(v1.begin(), v1.end());
+    R.tab1.insert(R.tab1.end(), d1.begin(), d1.end());
+    R.tab1.insert(R.tab1.end(), w1.begin(), w1.end());
     R.w.assign(R.n_elem * R.nq, 0.0);
     R.xi.assign(R.n_elem * R.nq * dim, 0.0);
     R.dN.assign((size_t)R.n_elem * R.nq * R.nloc * dim, 0.0);

@@ -97,6 +97,33 @@ def test_operator_parity(pair, op):
     assert rel(got, expect) < 1e-11, f"{name} {op}: rel err {rel(got, expect):.3e}"
 
 
+def test_matrix_free_true_operator(pair):
+    """The matrix-free cell operator (Remark 9: from the pulled-back tensor at the quadrature points and
+    the shared 1D tables) gives the oracle's assembled K^(s) products in the true operator (16), agrees
+    with the stencil form to rounding, is bitwise the same for a block of load cases as for single
+    ones, and the outer solve reaches the same solution with it."""
+    name, prob, m, ctx = pair
+    x = _rand(m.nU + m.L, 13)
+    X = np.stack([_rand(m.nU + m.L, 90 + r) for r in range(3)])
+    stencil = host(ctx.apply_A(dev(x)))
+    ctx.set_options(true_operator=1)
+    try:
+        got = host(ctx.apply_A(dev(x)))
+        assert rel(got, m.apply_A(x)) < 1e-11, f"{name}: rel err {rel(got, m.apply_A(x)):.3e}"
+        assert rel(got, stencil) < 1e-12
+        Y = host(ctx.apply_A(dev(X.ravel()), nrhs=3)).reshape(3, -1)
+        for r in range(3):
+            assert np.array_equal(Y[r], host(ctx.apply_A(dev(X[r]))))
+        ro = m.solve(tol=1e-12, inner_tol=1e-13, maxit=80)
+        f, d = ctx.get_rhs()
+        u, lam, info = ctx.solve(f[:m.nU].contiguous(), d[:m.L].contiguous(), tol=1e-12, inner_tol=1e-13,
+                                 maxit=80)
+        assert info["relres"][0] < 1e-11
+        assert rel(host(u), ro["u"]) < 1e-9
+    finally:
+        ctx.set_options()
+
+
 def test_multi_rhs_equals_single(pair):
     name, prob, m, ctx = pair
     L = m.L
