@@ -206,7 +206,7 @@ def run_true_operator(ctx, reps=10):
         us = k["total_ms"] * 1e3 / k["timed"]
         gb = k["bytes"] / k["launches"] / 1e9
         out["stencil" if mode == 0 else "matrix_free"] = {"kernel": tag, "us_per_apply": us,
-                                                          "algorithmic_gb": gb, "tb_per_s": gb / us * 1e-3}
+                                                          "algorithmic_gb": gb, "tb_per_s": gb / us * 1e3}
     ctx.set_options()
     log(f"true operator: stencil {out['stencil']['us_per_apply']:.1f} us, "
         f"matrix-free {out['matrix_free']['us_per_apply']:.1f} us")
