@@ -748,13 +748,14 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
 // ------------------------------------------------------------------ matrix-free true cell operator
 // K^(s) u without the assembled values (Sec. 4.2.1, Remark 9): the stiffness is linear in the
 // pulled-back tensor Ĉ^(s) at the quadrature points (eq. (52)), so per element E and point q
-//   G_kl = sum_b u_{b,k} dN_{b,l}(q),  sigma_ij = sum_kl Ĉ_ijkl(q) G_kl,
-//   y_{a,i} += w_q sum_j dN_{a,j}(q) sigma_ij,
-// with dN built from the shared 1D B-spline tables (values v, derivatives d, weights w per
-// element and Gauss point).  Elements are taken in 3^D colours (e_j mod 3 per direction): two
-// elements of one colour share no control point (quadratic supports span 3), so each colour is
-// two passes — sigma of a batch of its elements into LDS, then the batch's outputs added into
-// the LDS result — and every output is summed over its elements in one fixed order.
+//   G_kl = sum_b u_{b,k} dN_{b,l}(q),  sigma_ij = w_q sum_kl Ĉ_ijkl(q) G_kl,
+//   y_{a,i} += sum_j dN_{a,j}(q) sigma_ij.
+// dN is a tensor product of the shared 1D B-spline tables (values v, derivatives d per element
+// and Gauss point), so both G and the outputs are taken one direction at a time (sum
+// factorisation: three-term contractions through LDS instead of 3^d x 3^d products).  Elements
+// are taken in 3^d colours (e_j mod 3 per direction): two elements of one colour share no control
+// point (quadratic supports span 3), so each colour's outputs are added into the LDS result
+// without conflicts, and every output is summed over its elements in one fixed order.
 constexpr int kMfB = 256;
 
 template <int D>
@@ -766,8 +767,7 @@ __global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ s
                                                     int N, int n_r, int n_p, int n_i, int n_d, int n_el, int eb,
                                                     double *__restrict__ y, long long y_rs,
                                                     double *__restrict__ yp_cells) {
-    constexpr int P1 = 3;                                   // quadratic: 3 functions and 3 points per direction
-    constexpr int NQ = D == 2 ? 9 : 27, NL = NQ, DD = D * D, D4 = DD * DD;
+    constexpr int NQ = D == 2 ? 9 : 27, DD = D * D, D4 = DD * DD;
     extern __shared__ double sm[];
     const int nc = n_el + 2;
     int n_ctrl = 1, n_elem = 1;
@@ -776,9 +776,9 @@ __global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ s
         n_ctrl *= nc;
         n_elem *= n_el;
     }
-    const int n_dof = n_ctrl * D, nt1 = n_el * P1 * P1;
-    double *ul = sm, *yl = ul + n_dof, *sig = yl + n_dof, *tv = sig + (size_t)eb * NQ * DD, *td = tv + nt1,
-           *tw = td + nt1;
+    const int n_dof = n_ctrl * D, nt1 = n_el * 9;
+    double *ul = sm, *yl = ul + n_dof, *bA = yl + n_dof, *bB = bA + (size_t)eb * NQ * DD, *tv = bB + (size_t)eb * NQ * DD,
+           *td = tv + nt1, *tw = td + nt1;
     const int col = blockIdx.x, rhs = col / N, s = col % N, tid = threadIdx.x;
     const double *u = x + rhs * x_rs;
     const double *lam = u + nU;
@@ -788,9 +788,10 @@ __global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ s
         ul[idx_p[j]] = P >= 0 ? u[(size_t)N * n_r + P] : 0.0;
     }
     for (int i = tid; i < n_dof; i += kMfB) yl[i] = 0.0;
-    for (int i = tid; i < 2 * nt1 + n_el * P1; i += kMfB) tv[i] = tab1[i];
+    for (int i = tid; i < 2 * nt1 + n_el * 3; i += kMfB) tv[i] = tab1[i];
     __syncthreads();
     const double *Cs = snap + (size_t)s * n_elem * NQ * D4;
+    // 1D tables of element e: V(e, g, b) = tv[(3e + g) * 3 + b], derivative td, weight tw[3e + g]
     int ncolour = 1;
 #pragma unroll
     for (int j = 0; j < D; ++j) ncolour *= 3;
@@ -802,112 +803,234 @@ __global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ s
             cnt[j] = c0[j] < n_el ? (n_el - c0[j] + 2) / 3 : 0;
             ncl *= cnt[j];
         }
-        for (int b0 = 0; b0 < ncl; b0 += eb) {
-            const int nb = min(eb, ncl - b0);
-            // pass 1: w_q sigma(q) of each (element, point) of the batch
-            for (int t = tid; t < nb * NQ; t += kMfB) {
-                const int ie = t / NQ, q = t % NQ;
-                int e[D], g[D], E = 0;
-#pragma unroll
-                for (int j = 0, r = b0 + ie, qq = q; j < D; ++j) {
-                    e[j] = c0[j] + 3 * (r % cnt[j]);
-                    r /= cnt[j];
-                    g[j] = qq % P1;
-                    qq /= P1;
-                }
-#pragma unroll
-                for (int j = D - 1; j >= 0; --j) E = E * n_el + e[j];
-                double V[D][P1], Dv[D][P1], w = 1.0;
+        for (int bb = 0; bb < ncl; bb += eb) {
+            const int nb = min(eb, ncl - bb);
+            auto elem = [&](int ie, int (&e)[D]) {
+                int r = bb + ie;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    w *= tw[e[j] * P1 + g[j]];
-#pragma unroll
-                    for (int l = 0; l < P1; ++l) {
-                        V[j][l] = tv[(e[j] * P1 + g[j]) * P1 + l];
-                        Dv[j][l] = td[(e[j] * P1 + g[j]) * P1 + l];
-                    }
-                }
-                double G[D][D];
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-#pragma unroll
-                    for (int l = 0; l < D; ++l) G[k][l] = 0.0;
-#pragma unroll
-                for (int b = 0; b < NL; ++b) {
-                    int lb[D], a = 0;
-#pragma unroll
-                    for (int j = 0, bb = b; j < D; ++j, bb /= P1) lb[j] = bb % P1;
-#pragma unroll
-                    for (int j = D - 1; j >= 0; --j) a = a * nc + e[j] + lb[j];
-                    double dN[D];
-#pragma unroll
-                    for (int l = 0; l < D; ++l) {
-                        double v = 1.0;
-#pragma unroll
-                        for (int m = 0; m < D; ++m) v *= m == l ? Dv[m][lb[m]] : V[m][lb[m]];
-                        dN[l] = v;
-                    }
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        const double uk = ul[a * D + k];
-#pragma unroll
-                        for (int l = 0; l < D; ++l) G[k][l] += uk * dN[l];
-                    }
-                }
-                const double *C = Cs + ((size_t)E * NQ + q) * D4;
-                double *sg = sig + (size_t)t * DD;
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        double acc = 0.0;
-#pragma unroll
-                        for (int k = 0; k < D; ++k)
-#pragma unroll
-                            for (int l = 0; l < D; ++l) acc += C[((i * D + j) * D + k) * D + l] * G[k][l];
-                        sg[i * D + j] = w * acc;
-                    }
-            }
-            __syncthreads();
-            // pass 2: y_{a,i} += sum_q sum_j dN_{a,j}(q) sigma_ij(q); supports of one colour are disjoint
-            for (int t = tid; t < nb * NL * D; t += kMfB) {
-                const int ie = t / (NL * D), la = (t / D) % NL, i = t % D;
-                int e[D], lv[D], a = 0;
-#pragma unroll
-                for (int j = 0, r = b0 + ie, ll = la; j < D; ++j) {
                     e[j] = c0[j] + 3 * (r % cnt[j]);
                     r /= cnt[j];
-                    lv[j] = ll % P1;
-                    ll /= P1;
                 }
+            };
+            if constexpr (D == 3) {
+                // 1: T0[ie][k][b2][b1][g0] = (sum_b0 v u, sum_b0 d u)
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int g0 = t % 3, b1 = (t / 3) % 3, b2 = (t / 9) % 3, k = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const int nb0 = (e[0] + nc * ((e[1] + b1) + nc * (e[2] + b2))) * 3 + k;
+                    const double *V = tv + (3 * e[0] + g0) * 3, *Dv = td + (3 * e[0] + g0) * 3;
+                    double v = 0.0, d = 0.0;
 #pragma unroll
-                for (int j = D - 1; j >= 0; --j) a = a * nc + e[j] + lv[j];
-                double V[D][P1], Dv[D][P1];
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-#pragma unroll
-                    for (int g = 0; g < P1; ++g) {
-                        V[j][g] = tv[(e[j] * P1 + g) * P1 + lv[j]];
-                        Dv[j][g] = td[(e[j] * P1 + g) * P1 + lv[j]];
+                    for (int b0 = 0; b0 < 3; ++b0) {
+                        const double uu = ul[nb0 + 3 * b0];
+                        v += V[b0] * uu;
+                        d += Dv[b0] * uu;
                     }
-                const double *sg = sig + (size_t)ie * NQ * DD + i * D;
-                double acc = 0.0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    int g[D];
-#pragma unroll
-                    for (int j = 0, qq = q; j < D; ++j, qq /= P1) g[j] = qq % P1;
-#pragma unroll
-                    for (int jd = 0; jd < D; ++jd) {
-                        double v = 1.0;
-#pragma unroll
-                        for (int m = 0; m < D; ++m) v *= m == jd ? Dv[m][g[m]] : V[m][g[m]];
-                        acc += v * sg[q * DD + jd];
-                    }
+                    bA[2 * t] = v;
+                    bA[2 * t + 1] = d;
                 }
-                yl[a * D + i] += acc;
+                __syncthreads();
+                // 2: T1[ie][k][b2][g1][g0] = (vv, vd, dv) over b1
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int g0 = t % 3, g1 = (t / 3) % 3, b2 = (t / 9) % 3, k = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const double *V = tv + (3 * e[1] + g1) * 3, *Dv = td + (3 * e[1] + g1) * 3;
+                    const double *T = bA + (size_t)((((ie * 3 + k) * 3 + b2) * 3) * 3 + g0) * 2;
+                    double vv = 0.0, vd = 0.0, dv = 0.0;
+#pragma unroll
+                    for (int b1 = 0; b1 < 3; ++b1) {
+                        const double tvv = T[b1 * 6], tdd = T[b1 * 6 + 1];
+                        vv += V[b1] * tvv;
+                        vd += Dv[b1] * tvv;
+                        dv += V[b1] * tdd;
+                    }
+                    bB[3 * t] = vv;
+                    bB[3 * t + 1] = vd;
+                    bB[3 * t + 2] = dv;
+                }
+                __syncthreads();
+                // 3: G[ie][q][k][l] over b2
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int g0 = t % 3, g1 = (t / 3) % 3, g2 = (t / 9) % 3, k = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const double *V = tv + (3 * e[2] + g2) * 3, *Dv = td + (3 * e[2] + g2) * 3;
+                    const double *T = bB + (size_t)(((ie * 3 + k) * 3) * 3 * 3 + g1 * 3 + g0) * 3;
+                    double G0 = 0.0, G1 = 0.0, G2 = 0.0;
+#pragma unroll
+                    for (int b2 = 0; b2 < 3; ++b2) {
+                        const double *Tb = T + b2 * 27;
+                        G0 += V[b2] * Tb[2];
+                        G1 += V[b2] * Tb[1];
+                        G2 += Dv[b2] * Tb[0];
+                    }
+                    double *Gq = bA + ((size_t)(ie * 27 + g0 + 3 * g1 + 9 * g2) * 3 + k) * 3;
+                    Gq[0] = G0;
+                    Gq[1] = G1;
+                    Gq[2] = G2;
+                }
+                __syncthreads();
+                // 4: sigma[ie][q][i][j] = w_q sum_kl C_ijkl G_kl
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int i = t % 3, q = (t / 3) % 27, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const int g0 = q % 3, g1 = (q / 3) % 3, g2 = q / 9;
+                    const int E = e[0] + n_el * (e[1] + n_el * e[2]);
+                    const double w = tw[3 * e[0] + g0] * tw[3 * e[1] + g1] * tw[3 * e[2] + g2];
+                    const double *C = Cs + ((size_t)E * 27 + q) * 81 + i * 27;
+                    const double *G = bA + (size_t)(ie * 27 + q) * 9;
+                    double sg[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+#pragma unroll
+                        for (int kl = 0; kl < 9; ++kl) sg[j] += C[j * 9 + kl] * G[kl];
+                    double *S = bB + (size_t)(ie * 27 + q) * 9 + i * 3;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) S[j] = w * sg[j];
+                }
+                __syncthreads();
+                // 5: A[ie][i][b2][g1][g0] over g2: (v Z0, v Z1, d Z2)
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int g0 = t % 3, g1 = (t / 3) % 3, b2 = (t / 9) % 3, i = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+                    for (int g2 = 0; g2 < 3; ++g2) {
+                        const double v = tv[(3 * e[2] + g2) * 3 + b2], d = td[(3 * e[2] + g2) * 3 + b2];
+                        const double *Z = bB + (size_t)(ie * 27 + g0 + 3 * g1 + 9 * g2) * 9 + i * 3;
+                        a0 += v * Z[0];
+                        a1 += v * Z[1];
+                        a2 += d * Z[2];
+                    }
+                    bA[3 * t] = a0;
+                    bA[3 * t + 1] = a1;
+                    bA[3 * t + 2] = a2;
+                }
+                __syncthreads();
+                // 6: B[ie][i][b2][b1][g0] over g1: (v A0, d A1 + v A2)
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int g0 = t % 3, b1 = (t / 3) % 3, b2 = (t / 9) % 3, i = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const double *A = bA + (size_t)((((ie * 3 + i) * 3 + b2) * 3) * 3 + g0) * 3;
+                    double pp = 0.0, qq = 0.0;
+#pragma unroll
+                    for (int g1 = 0; g1 < 3; ++g1) {
+                        const double v = tv[(3 * e[1] + g1) * 3 + b1], d = td[(3 * e[1] + g1) * 3 + b1];
+                        const double *Ag = A + g1 * 9;
+                        pp += v * Ag[0];
+                        qq += d * Ag[1] + v * Ag[2];
+                    }
+                    bB[2 * t] = pp;
+                    bB[2 * t + 1] = qq;
+                }
+                __syncthreads();
+                // 7: y over g0, added at the element's control points (disjoint within a colour)
+                for (int t = tid; t < nb * 81; t += kMfB) {
+                    const int b0 = t % 3, b1 = (t / 3) % 3, b2 = (t / 9) % 3, i = (t / 27) % 3, ie = t / 81;
+                    int e[3];
+                    elem(ie, e);
+                    const double *B = bB + (size_t)((((ie * 3 + i) * 3 + b2) * 3 + b1) * 3) * 2;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int g0 = 0; g0 < 3; ++g0)
+                        acc += td[(3 * e[0] + g0) * 3 + b0] * B[2 * g0] + tv[(3 * e[0] + g0) * 3 + b0] * B[2 * g0 + 1];
+                    yl[((e[0] + b0) + nc * ((e[1] + b1) + nc * (e[2] + b2))) * 3 + i] += acc;
+                }
+                __syncthreads();
+            } else {
+                // 1: T0[ie][k][b1][g0] = (sum_b0 v u, sum_b0 d u)
+                for (int t = tid; t < nb * 18; t += kMfB) {
+                    const int g0 = t % 3, b1 = (t / 3) % 3, k = (t / 9) % 2, ie = t / 18;
+                    int e[2];
+                    elem(ie, e);
+                    const int nb0 = (e[0] + nc * (e[1] + b1)) * 2 + k;
+                    const double *V = tv + (3 * e[0] + g0) * 3, *Dv = td + (3 * e[0] + g0) * 3;
+                    double v = 0.0, d = 0.0;
+#pragma unroll
+                    for (int b0 = 0; b0 < 3; ++b0) {
+                        const double uu = ul[nb0 + 2 * b0];
+                        v += V[b0] * uu;
+                        d += Dv[b0] * uu;
+                    }
+                    bA[2 * t] = v;
+                    bA[2 * t + 1] = d;
+                }
+                __syncthreads();
+                // 2: G[ie][q][k][l] over b1
+                for (int t = tid; t < nb * 18; t += kMfB) {
+                    const int g0 = t % 3, g1 = (t / 3) % 3, k = (t / 9) % 2, ie = t / 18;
+                    int e[2];
+                    elem(ie, e);
+                    const double *V = tv + (3 * e[1] + g1) * 3, *Dv = td + (3 * e[1] + g1) * 3;
+                    const double *T = bA + (size_t)((ie * 2 + k) * 9 + g0) * 2;
+                    double G0 = 0.0, G1 = 0.0;
+#pragma unroll
+                    for (int b1 = 0; b1 < 3; ++b1) {
+                        G0 += V[b1] * T[b1 * 6 + 1];
+                        G1 += Dv[b1] * T[b1 * 6];
+                    }
+                    double *Gq = bB + ((size_t)(ie * 9 + g0 + 3 * g1) * 2 + k) * 2;
+                    Gq[0] = G0;
+                    Gq[1] = G1;
+                }
+                __syncthreads();
+                // 3: sigma[ie][q][i][j] = w_q sum_kl C_ijkl G_kl
+                for (int t = tid; t < nb * 18; t += kMfB) {
+                    const int i = t % 2, q = (t / 2) % 9, ie = t / 18;
+                    int e[2];
+                    elem(ie, e);
+                    const int g0 = q % 3, g1 = q / 3;
+                    const int E = e[0] + n_el * e[1];
+                    const double w = tw[3 * e[0] + g0] * tw[3 * e[1] + g1];
+                    const double *C = Cs + ((size_t)E * 9 + q) * 16 + i * 8;
+                    const double *G = bB + (size_t)(ie * 9 + q) * 4;
+                    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int kl = 0; kl < 4; ++kl) {
+                        s0 += C[kl] * G[kl];
+                        s1 += C[4 + kl] * G[kl];
+                    }
+                    double *S = bA + (size_t)(ie * 9 + q) * 4 + i * 2;
+                    S[0] = w * s0;
+                    S[1] = w * s1;
+                }
+                __syncthreads();
+                // 4: B[ie][i][b1][g0] over g1: (v Z0, d Z1)
+                for (int t = tid; t < nb * 18; t += kMfB) {
+                    const int g0 = t % 3, b1 = (t / 3) % 3, i = (t / 9) % 2, ie = t / 18;
+                    int e[2];
+                    elem(ie, e);
+                    double pp = 0.0, qq = 0.0;
+#pragma unroll
+                    for (int g1 = 0; g1 < 3; ++g1) {
+                        const double *Z = bA + (size_t)(ie * 9 + g0 + 3 * g1) * 4 + i * 2;
+                        pp += tv[(3 * e[1] + g1) * 3 + b1] * Z[0];
+                        qq += td[(3 * e[1] + g1) * 3 + b1] * Z[1];
+                    }
+                    bB[2 * t] = pp;
+                    bB[2 * t + 1] = qq;
+                }
+                __syncthreads();
+                // 5: y over g0, added at the element's control points (disjoint within a colour)
+                for (int t = tid; t < nb * 18; t += kMfB) {
+                    const int b0 = t % 3, b1 = (t / 3) % 3, i = (t / 9) % 2, ie = t / 18;
+                    int e[2];
+                    elem(ie, e);
+                    const double *B = bB + (size_t)(((ie * 2 + i) * 3 + b1) * 3) * 2;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int g0 = 0; g0 < 3; ++g0)
+                        acc += td[(3 * e[0] + g0) * 3 + b0] * B[2 * g0] + tv[(3 * e[0] + g0) * 3 + b0] * B[2 * g0 + 1];
+                    yl[((e[0] + b0) + nc * (e[1] + b1)) * 2 + i] += acc;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     double *yr = y + rhs * y_rs + (size_t)s * n_r;
@@ -1445,13 +1568,13 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     if (c->opt.true_operator == 1) {
         IFETI_REQUIRE(c->snap_valid, IFETI_EINVAL, "matrix-free true operator: pulled-back tensor not available");
         IFETI_REQUIRE(R.p == 2, IFETI_EINVAL, "matrix-free true operator: quadratic B-splines only");
-        // pass-1 buffer of up to 2048 doubles (whole colours of the c2/c3 cells in one batch)
+        // two stage buffers of up to 2048 doubles each (whole colours of the c2/c3 cells in one batch)
         const int DD = c->dim * c->dim;
         const int eb = std::max(1, 2048 / (R.nq * DD));
-        const size_t lds = (size_t)(2 * R.n_dof + eb * R.nq * DD + 2 * R.n_el * 9 + R.n_el * 3) * sizeof(double);
+        const size_t lds = (size_t)(2 * R.n_dof + 2 * eb * R.nq * DD + 2 * R.n_el * 9 + R.n_el * 3) * sizeof(double);
         IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "matrix-free true operator: cell too large for LDS");
         const double colsd = (double)N * nrhs;
-        // flops: per element and point, G (2 D^2 nloc), sigma (2 D^4), outputs (2 D^2 nloc)
+        // flops of the definition: per element and point, G (2 D^2 nloc), sigma (2 D^4), outputs (2 D^2 nloc)
         const double fl = colsd * R.n_elem * R.nq * (4.0 * DD * R.nloc + 2.0 * DD * DD);
         Prof prof(c, "true_K_mf", fl, 8.0 * (double)N * R.n_snap + colsd * 8.0 * 2.0 * R.n_dof);
         if (c->dim == 2) {
