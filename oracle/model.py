@@ -13,8 +13,13 @@ Operators (paper Sec. 3.2):
                  solves of eq. (46), the Gram matrix taken with the cell's own
                  K_rr^(s)
   apply_A        the true saddle operator of eq. (16)
+  apply_MD_rom   M̊_D^-ROM of eq. (47): the Dirichlet preconditioner (30) with
+                 each cell's interior solve replaced by the reduced solve of
+                 eq. (46) on the interior block (principal K_ii^(σk)-1)
   apply_prec     the block preconditioner (44), Algorithm 1 (signs as printed:
-                 y = -F̊^-pcg w̄ and x = K̊^-ROM v - Ůᵀ y)
+                 y = -F̊^-pcg w̄ and x = K̊^-ROM v - Ůᵀ y); the interface block
+                 -F̊^-pcg may instead be one application of M̊_D^-1 (49) or of
+                 M̊_D^-ROM (47), the alternative of Sec. 3.2.3
   solve          right-preconditioned FGMRES on (16)
 
 Parity: pinned by tests/test_oracle_*.py (brute-force dense operators, exact
@@ -64,6 +69,7 @@ class Model:
         self.Kvals = cell_matrix_values(self.ref, problem, np.arange(self.N)) if build_all_cells else None
         self.f_cells = cell_loads(self.ref, problem)            # (N, n_dof, nrhs)
         self.rhs_f = None
+        self._Kii_inv = None
         if build_all_cells:
             self._build_rhs()
 
@@ -135,6 +141,31 @@ class Model:
         dd, b = self.dd, self.bank
         Lam = dd.gather(r, weights=True)
         Y = comb(self.alpha, b.Sdd, Lam)
+        return dd.scatter(Y, weights=True)
+
+    # ----------------------------------------------------------- M̊_D^-ROM (47)
+    def apply_MD_rom(self, r: np.ndarray) -> np.ndarray:
+        """Eq. (47): sum_s D B_d^(s) S_dd^(s) B_d^(s)T D r as in (30), S_dd^(s) = K_dd - K_di K_ii^-1 K_id,
+        with K_ii^(s)-1 w replaced by the reduced solve of eq. (46) on the interior block:
+        R = [K_ii^(σk)-1 w]_k, x = R (Rᵀ K_ii^(s) R)^-1 Rᵀ w."""
+        dd = self.dd
+        ni = dd.n_i
+        if self._Kii_inv is None:
+            self._Kii_inv = []
+            for s in self.sigma:
+                Krr, _ = romlib.cell_blocks(self.ref, dd, self.Kvals[s])
+                self._Kii_inv.append(np.linalg.inv(Krr[:ni, :ni].toarray()))
+        Lam = dd.gather(r, weights=True)
+        Y = np.zeros_like(Lam)
+        for s in range(self.N):
+            Krr, _ = romlib.cell_blocks(self.ref, dd, self.Kvals[s])
+            Kii, Kid = Krr[:ni, :ni], Krr[:ni, ni:]
+            w = Kid @ Lam[s]
+            x = np.zeros(ni)
+            if np.any(w):
+                R = np.stack([Ki @ w for Ki in self._Kii_inv], axis=1)
+                x = R @ romlib.spd_solve(R.T @ (Kii @ R), R.T @ w)
+            Y[s] = Krr[ni:, ni:] @ Lam[s] - Krr[ni:, :ni] @ x
         return dd.scatter(Y, weights=True)
 
     # ----------------------------------------------------------- Ů, Ůᵀ (Alg. 3)
@@ -212,21 +243,30 @@ class Model:
         return pcg(self.apply_F, self.apply_MD, rhs, tol=tol, maxit=maxit)
 
     # ----------------------------------------------------------- Alg. 1 / (44)
-    def apply_prec(self, x: np.ndarray, inner_tol=1e-11, inner_maxit=1000) -> np.ndarray:
+    def apply_prec(self, x: np.ndarray, inner_tol=1e-11, inner_maxit=1000, interface="pcg") -> np.ndarray:
+        """interface: "pcg" F̊^-pcg (PCG on (48) with (49)), "md" one application of M̊_D^-1 (49),
+        "mdrom" one application of M̊_D^-ROM (47)."""
         v, w = x[:self.nU], x[self.nU:]
         wbar = w - self.apply_U(v)
-        lam, its, _ = self.solve_interface(wbar, tol=inner_tol, maxit=inner_maxit)
+        if interface == "pcg":
+            lam, its, _ = self.solve_interface(wbar, tol=inner_tol, maxit=inner_maxit)
+        elif interface == "md":
+            lam, its = self.apply_MD(wbar), 0
+        elif interface == "mdrom":
+            lam, its = self.apply_MD_rom(wbar), 0
+        else:
+            raise ValueError(f"unknown interface block {interface!r}")
         y = -lam
         self.inner_its.append(its)
         xo = self.apply_Kinv_rom(v) - self.apply_Ut(y)
         return np.concatenate([xo, y])
 
-    def solve(self, rhs_index=0, tol=1e-8, maxit=100, inner_tol=1e-11, inner_maxit=1000):
+    def solve(self, rhs_index=0, tol=1e-8, maxit=100, inner_tol=1e-11, inner_maxit=1000, interface="pcg"):
         """FGMRES on (16).  Returns dict(u, lam, outer_its, inner_its, relres, time)."""
         self.inner_its = []
         b = np.concatenate([self.rhs_f[rhs_index], self.rhs_d])
         t0 = time.perf_counter()
-        x, its, hist = fgmres(self.apply_A, lambda r: self.apply_prec(r, inner_tol, inner_maxit), b,
+        x, its, hist = fgmres(self.apply_A, lambda r: self.apply_prec(r, inner_tol, inner_maxit, interface), b,
                               tol=tol, maxit=maxit)
         t1 = time.perf_counter()
         res = np.linalg.norm(b - self.apply_A(x)) / np.linalg.norm(b)

@@ -256,3 +256,31 @@ def test_fgmres_matches_dense_and_one_step_with_exact_inverse():
     Ainv = np.linalg.inv(A)
     x1, its1, _ = fgmres(lambda v: A @ v, lambda v: Ainv @ v, b, tol=1e-10)
     assert its1 == 1 and np.allclose(x1, np.linalg.solve(A, b), rtol=1e-10)
+
+
+def test_MD_rom_is_exact_dirichlet_when_every_cell_is_principal():
+    """Eq. (47) with every cell principal: the reduced interior solve contains K_ii^(s)-1 w itself, so
+    M̊_D^-ROM is the exact Dirichlet preconditioner (30) (interior Cholesky in the exact FETI-DP)."""
+    p = latticegen.tiny(2, (2, 2), 3, n_principal=4)
+    m = Model(p)
+    m.build_reduced_basis(principal_in=[0, 1, 2, 3])
+    ex = ExactFETIDP(m)
+    lam = np.random.default_rng(6).standard_normal(m.L)
+    assert np.allclose(m.apply_MD_rom(lam), ex.apply_MD(lam), rtol=1e-9, atol=1e-11)
+
+
+def test_MD_rom_is_exact_dirichlet_for_identical_cells(m_ident):
+    ex = ExactFETIDP(m_ident)
+    lam = np.random.default_rng(7).standard_normal(m_ident.L)
+    assert np.allclose(m_ident.apply_MD_rom(lam), ex.apply_MD(lam), rtol=1e-9, atol=1e-11)
+
+
+def test_MD_rom_positively_homogeneous_and_energy_positive(m2):
+    """The reduced solve is a Galerkin projection onto a space spanned by the input's own principal
+    solves: scaling the input scales the output, and rᵀ M̊_D^-ROM r ≥ rᵀ M_D^-1 r > 0 (a Galerkin
+    approximation of K_ii^-1 w under-estimates wᵀ K_ii^-1 w, so S̃_dd over-estimates S_dd)."""
+    ex = ExactFETIDP(m2)
+    r = np.random.default_rng(8).standard_normal(m2.L)
+    y = m2.apply_MD_rom(r)
+    assert np.allclose(m2.apply_MD_rom(-2.5 * r), -2.5 * y, rtol=1e-12, atol=1e-13)
+    assert r @ y >= r @ ex.apply_MD(r) * (1 - 1e-12) > 0

@@ -81,3 +81,17 @@ def test_more_principals_fewer_outer_iterations():
         m.build_reduced_basis(n_principal=K)
         its.append(m.solve(tol=1e-8)["outer_its"])
     assert its[1] <= its[0]
+
+
+@pytest.mark.parametrize("interface", ["md", "mdrom"])
+def test_interface_block_variants_reach_direct_solution(interface):
+    """Alg. 1 with the interface block -F̊^-pcg replaced by one application of M̊_D^-1 (49) or of
+    M̊_D^-ROM (47): FGMRES still reaches the conforming solution of (16), with more outer iterations."""
+    m = Model(latticegen.tiny(2, (3, 3), 3, n_principal=3))
+    m.build_reduced_basis()
+    r = m.solve(tol=1e-12, maxit=200, interface=interface)
+    ref = conforming_solve(m)
+    assert r["relres"] < 1e-11
+    assert _rel(r["u"], ref["u"]) < 1e-9
+    assert r["outer_its"] >= m.solve(tol=1e-12, inner_tol=1e-13)["outer_its"]
+    assert sum(r["inner_its"]) == 0
