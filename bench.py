@@ -133,13 +133,13 @@ def cpu_baseline(budget_s: float = 10.0):
                        f"{applies} cell applies in {dt:.1f} s")
 
 
-def timed_solve(ctx, f, d, nrhs, tol, inner_tol, reps=1):
+def timed_solve(ctx, f, d, nrhs, tol, inner_tol, reps=1, maxit=200):
     import torch
-    ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=200)  # untimed warm-up
+    ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit)  # untimed warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=200)
+        u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps, info
 
@@ -164,6 +164,14 @@ def run_forms(ctx, f, d, t_fp64, args):
                      "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
         log(f"form {name}: {t:.3f}s (fp64 at inner tol {itol:g}: {t64:.3f}s) outer={info['outer_its'][0]} "
             f"pcg={info['inner_its'][0]}")
+    ctx.set_options()
+    # interface block of Alg. 1: one application of (49) or of (47) in place of the interface PCG
+    for name, block in (("interface_md_once", 1), ("interface_md_rom_once", 2)):
+        ctx.set_options(interface_block=block, fgmres_restart=200)
+        t, info = timed_solve(ctx, f, d, 1, args.tol, 1e-11, maxit=200)
+        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
+                     "relres": float(info["relres"][0])}
+        log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]}")
     ctx.set_options()
     res["true_operator"] = run_true_operator(ctx)
     prob = latticegen.make("c4")

@@ -111,6 +111,11 @@ typedef struct {
                                quadrature points and the shared 1D B-spline tables, element by element
                                in 3^dim colours (quadratic B-splines only, EINVAL otherwise); both
                                are deterministic */
+    int interface_block;    /* interface block of the preconditioner (Alg. 1): 0 F̊^-pcg (PCG on (48)
+                               preconditioned by (49)); 1 one application of M̊_D^-1 (49); 2 one
+                               application of M̊_D^-ROM (47), the Dirichlet preconditioner with
+                               reduced interior solves (Sec. 3.2.3).  1 and 2 make the preconditioner
+                               cheaper and the outer FGMRES longer */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts
@@ -183,6 +188,14 @@ int ifeti_get_coefficients(ifeti_ctx *ctx, double *alpha, double *pi, double *de
 int ifeti_apply_F(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
 /* out = M̊_D^-1 r, the ROM Dirichlet preconditioner of eq. (49). */
 int ifeti_apply_MD(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
+
+/* M̊_D^-ROM of eq. (47) (Sec. 3.2.3): out = sum_s D B_d^(s) S̃_dd^(s) B_d^(s)T D r with
+ * S̃_dd^(s) = K_dd - K_di K̊_ii^-ROM K_id, where K̊_ii^-ROM w = R (Rᵀ K_ii^(s) R)^-1 Rᵀ w and
+ * R = [K_ii^(σk)-1 w]_k is the reduced solve of eq. (46) on the interior block.  r and out: device,
+ * nrhs contiguous vectors of length L.  The principal interior inverses K_ii^(σk)-1 (K n_r^2 doubles,
+ * zero-padded) are built on the first call after ifeti_build_reduced_basis and kept.  Positively
+ * homogeneous, not linear (the projection space depends on r).  EINVAL before the reduced basis. */
+int ifeti_apply_MD_rom(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
 /* z = Ů v (Algorithm 3), v dev nU x nrhs, z dev L x nrhs. */
 int ifeti_apply_U(ifeti_ctx *ctx, const double *v, double *z, int nrhs);
 /* x = Ůᵀ y, y dev L x nrhs, x dev nU x nrhs. */

@@ -179,6 +179,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.timing_every = std::max(1, opt->timing_every);
         c->opt.use_graph = opt->use_graph ? 1 : 0;
         c->opt.autotune = opt->autotune ? 1 : 0;
+        REQ(opt->interface_block >= 0 && opt->interface_block <= 2, "interface_block must be 0, 1 or 2");
+        c->opt.interface_block = opt->interface_block;
         REQ(opt->true_operator == 0 || opt->true_operator == 1, "true_operator must be 0 or 1");
         REQ(opt->true_operator == 0 || c->ref.p == 2, "the matrix-free true operator needs quadratic B-splines");
         c->opt.true_operator = opt->true_operator;
@@ -285,6 +287,15 @@ int ifeti_apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs) {
         ROM_READY(c, nrhs);
         REQ(r && out && r != out, "bad pointers");
         apply_MD(c, r, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
+int ifeti_apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+    return guarded([&]() {
+        ROM_READY(c, nrhs);
+        REQ(r && out && r != out, "bad pointers");
+        apply_MD_rom(c, r, out, nrhs);
         return IFETI_OK;
     });
 }

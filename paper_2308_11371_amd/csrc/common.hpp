@@ -117,6 +117,7 @@ struct Options {
     int autotune = 0;           // time the candidate tile shapes on first use of each contraction shape
     int coarse_parts = 0;       // coarse solve: 0 automatic, 1 symmetric-tile inverse, >= 2 that many blocks
     int true_operator = 0;      // K^(s) in (16): 0 stencil values, 1 matrix-free from the pulled-back tensor
+    int interface_block = 0;    // Alg. 1 interface block: 0 PCG on (48), 1 one M̊_D^-1 (49), 2 one M̊_D^-ROM (47)
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -252,8 +253,13 @@ struct ifeti_ctx {
         void *frag = nullptr;
     };
     std::vector<FragCopy> frag;
+    // M̊_D^-ROM (47): principal interior inverses K_ii^(σk)-1 zero-padded to n_r x n_r, rows interleaved
+    // [r][k][n_r] like the stacked K_rr^-1 (built on first use for the current bank), and work vectors
+    ifeti::DevBuf<double> Kii_pad, mdr_X, mdr_Y, mdr_v, mdr_x;
+    long long bank_gen = 0, kii_gen = -1;
     void free_copies() {
         ++rom_gen;
+        ++bank_gen;
         for (auto &cp : frag)
             if (cp.frag) (void)hipFree(cp.frag);
         frag.clear();
@@ -353,7 +359,9 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 // the same with an explicit coarse solver (the exact FETI-DP operators carry their own)
 void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
                   int nrhs, double scale);
-void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs);
+void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
+                  const double *bank = nullptr, const char *rtag = "rom_R_gemm");
+void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs);
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);

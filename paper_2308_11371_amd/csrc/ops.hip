@@ -1471,14 +1471,15 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
     IFETI_HIP(hipGetLastError());
 }
 
-void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs) {
+void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
+                  const double *bank, const char *rtag) {
     const int N = c->N, nr = c->n_r, K = c->K;
     IFETI_REQUIRE(K <= kMaxK, IFETI_EINVAL, "reduced local solve supports at most 40 principal cells");
     // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
-    // column comes out as [r][k]
+    // column comes out as [r][k] (or the zero-padded interior inverses of (47))
     GemmGroup g;
-    g.A = c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
-    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, "rom_R_gemm");
+    g.A = bank ? bank : c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
+    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, rtag);
     // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
     const RefTables &R = c->ref;
     const int cols = N * nrhs;
@@ -1559,8 +1560,9 @@ void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
 }
 
 // ------------------------------------------------------------------ true saddle operator (16)
-void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
-    ensure_work(c, nrhs);
+// per-cell part of (16) on packed saddle vectors (stride nU + L): y_R = K_rr u_r + K_rp u_p + B_r^T lam,
+// and the cells' primal rows K_pr u_r + K_pp u_p into w_c (stencil values or matrix-free, by option)
+static void op_cell_K(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const int N = c->N, nr = c->n_r, np = c->n_p;
     const long long nU = c->nU, rs = nU + c->L;
     const RefTables &R = c->ref;
@@ -1603,9 +1605,132 @@ void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
                            c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
     }
+}
+
+void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs) {
+    ensure_work(c, nrhs);
+    const int N = c->N, nr = c->n_r;
+    const long long nU = c->nU, rs = nU + c->L;
+    op_cell_K(c, x, y, nrhs);
     op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, y + (size_t)N * nr, rs, nrhs);
     op_scatter(c, x, nr, c->n_i, rs, y + nU, rs, nrhs, false);  // B u
     c->applies[IFETI_OP_A] += nrhs;
+    IFETI_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ M̊_D^-ROM (47)
+// Principal interior inverses from the stacked K_rr^-1 (rows interleaved [r][k][n_r]) and S_dd by
+// block inversion: with A = K_rr^-1, A_dd = S_dd^-1 and K_ii^-1 = A_ii - A_id S_dd A_di.  One
+// workgroup per (interior row i, principal k); written zero-padded to n_r x n_r in the same
+// interleaved layout, so the reduced solve of (46) takes it in place of K_rr^-1.
+__global__ __launch_bounds__(256) void k_kii_inverse(const double *__restrict__ Kinv, const double *__restrict__ Sdd,
+                                                     int K, int n_r, int n_i, int n_d, double *__restrict__ out) {
+    extern __shared__ double sh[];  // a_d[n_d], t[n_d]
+    const int i = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+    double *ad = sh, *t = sh + n_d;
+    const double *Ai = Kinv + ((size_t)i * K + k) * n_r;  // row i of A_k
+    for (int b = tid; b < n_d; b += 256) ad[b] = Ai[n_i + b];
+    __syncthreads();
+    const double *S = Sdd + (size_t)k * n_d * n_d;
+    for (int a = tid; a < n_d; a += 256) {  // t = A_id(i,:) S (S symmetric: column a = row a)
+        double acc = 0.0;
+        for (int b = 0; b < n_d; ++b) acc += ad[b] * S[(size_t)a * n_d + b];
+        t[a] = acc;
+    }
+    __syncthreads();
+    double *o = out + ((size_t)i * K + k) * n_r;
+    for (int j = tid; j < n_r; j += 256) {
+        double v = 0.0;
+        if (j < n_i) {
+            double acc = 0.0;
+            for (int a = 0; a < n_d; ++a) acc += t[a] * Kinv[((size_t)(n_i + a) * K + k) * n_r + j];
+            v = Ai[j] - acc;
+        }
+        o[j] = v;
+    }
+}
+
+// zero rows of the padded bank beyond the interior
+__global__ __launch_bounds__(256) void k_zero_rows(double *__restrict__ out, long long from, long long n) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) out[from + t] = 0.0;
+}
+
+// packed saddle vectors (stride rs) for the cell operator: u_r^(s) = [-x_i^(s); Lam_s] (x null: zero
+// interior), u_P = 0, lam = 0
+__global__ __launch_bounds__(kB) void k_mdrom_saddle(const double *__restrict__ Lam, const double *__restrict__ xr,
+                                                     int N, int n_r, int n_i, int n_d, long long rs,
+                                                     double *__restrict__ X, int nrhs) {
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= rs * nrhs) return;
+    const int rhs = (int)(t / rs);
+    const long long e = t % rs;
+    double v = 0.0;
+    if (e < (long long)N * n_r) {
+        const int s = (int)(e / n_r), j = (int)(e % n_r);
+        const size_t col = (size_t)rhs * N + s;
+        v = j >= n_i ? Lam[col * n_d + (j - n_i)] : (xr ? -xr[col * n_r + j] : 0.0);
+    }
+    X[t] = v;
+}
+
+// interior part of the cells' r rows of packed saddle vectors, dual part zero: out [rhs][s][n_r]
+__global__ __launch_bounds__(kB) void k_r_interior(const double *__restrict__ Y, long long rs, int N, int n_r,
+                                                   int n_i, double *__restrict__ out, int nrhs) {
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    const long long per = (long long)N * n_r;
+    if (t >= per * nrhs) return;
+    const int rhs = (int)(t / per);
+    const long long e = t % per;
+    out[t] = (int)(e % n_r) < n_i ? Y[rhs * rs + e] : 0.0;
+}
+
+static void build_kii_bank(ifeti_ctx *c) {
+    if (c->kii_gen == c->bank_gen && c->Kii_pad.p) return;
+    const int K = c->K, nr = c->n_r, ni = c->n_i, nd = c->n_d;
+    c->Kii_pad.alloc((size_t)K * nr * nr);
+    if (ni > 0) {
+        const size_t lds = (size_t)2 * nd * sizeof(double);
+        IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "M_D^-ROM: dual block too large for LDS");
+        if (lds > 64 * 1024)
+            IFETI_HIP(hipFuncSetAttribute((const void *)k_kii_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds));
+        hipLaunchKernelGGL(k_kii_inverse, dim3(ni, K), dim3(256), lds, c->stream, c->Kinv.p, c->Sdd.p, K, nr, ni, nd,
+                           c->Kii_pad.p);
+        IFETI_HIP(hipGetLastError());
+    }
+    const long long from = (long long)ni * K * nr, n = (long long)(nr - ni) * K * nr;
+    if (n > 0) hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->Kii_pad.p, from, n);
+    IFETI_HIP(hipGetLastError());
+    c->kii_gen = c->bank_gen;
+}
+
+// out = sum_s D B_d^(s) S̃_dd^(s) B_d^(s)T D r with S̃_dd = K_dd - K_di x(w), w = K_id Lam_s and x(w) the
+// reduced interior solve of (46) with the principal K_ii^-1 (eq. (47)):
+//   1. Lam = D-weighted gather; u_r = [0; Lam]; w_r = interior rows of K_rr u_r (cell operator)
+//   2. x = R (Rᵀ K_ii R)^-1 Rᵀ w, R = [K_ii^(σk)-1 w]_k (the reduced local solve on the padded bank)
+//   3. y = dual rows of K_rr [-x_i; Lam] (cell operator); out = D-weighted scatter of y
+void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs) {
+    ensure_work(c, nrhs);
+    build_kii_bank(c);
+    const int N = c->N, nr = c->n_r;
+    const long long rs = c->nU + c->L, per = (long long)N * nr;
+    hipStream_t s = c->stream;
+    c->mdr_X.ensure((size_t)rs * nrhs, s);
+    c->mdr_Y.ensure((size_t)rs * nrhs, s);
+    c->mdr_v.ensure((size_t)per * nrhs, s);
+    c->mdr_x.ensure((size_t)per * nrhs, s);
+    op_gather(c, r, c->L, c->w_Lam.p, nrhs, true);
+    const unsigned gX = (unsigned)((rs * nrhs + kB - 1) / kB), gR = (unsigned)((per * nrhs + kB - 1) / kB);
+    hipLaunchKernelGGL(k_mdrom_saddle, dim3(gX), dim3(kB), 0, s, c->w_Lam.p, nullptr, N, nr, c->n_i, c->n_d, rs,
+                       c->mdr_X.p, nrhs);
+    op_cell_K(c, c->mdr_X.p, c->mdr_Y.p, nrhs);
+    hipLaunchKernelGGL(k_r_interior, dim3(gR), dim3(kB), 0, s, c->mdr_Y.p, rs, N, nr, c->n_i, c->mdr_v.p, nrhs);
+    op_rom_local(c, c->mdr_v.p, per, c->mdr_x.p, per, nrhs, c->Kii_pad.p, "mdrom_R_gemm");
+    hipLaunchKernelGGL(k_mdrom_saddle, dim3(gX), dim3(kB), 0, s, c->w_Lam.p, c->mdr_x.p, N, nr, c->n_i, c->n_d, rs,
+                       c->mdr_X.p, nrhs);
+    op_cell_K(c, c->mdr_X.p, c->mdr_Y.p, nrhs);
+    op_scatter(c, c->mdr_Y.p, nr, c->n_i, rs, out, c->L, nrhs, true);
     IFETI_HIP(hipGetLastError());
 }
 

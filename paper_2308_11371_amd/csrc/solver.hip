@@ -510,6 +510,7 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
 
 // ------------------------------------------------------------------ Algorithm 1 / (44)
 // x = (v, w) -> (x_u, y):  w̄ = w - Ů v;  y = -F̊^-pcg w̄;  x_u = K̊^-ROM v - Ůᵀ y
+// (option interface_block: F̊^-pcg replaced by one application of M̊_D^-1 (49) or M̊_D^-ROM (47))
 static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, double inner_tol, int inner_maxit,
                       std::vector<long long> &inner_total, DevBuf<double> &t_u, DevBuf<double> &t_L, DevBuf<double> &t_L2,
                       DevBuf<double> &t_u2) {
@@ -524,10 +525,16 @@ static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, dou
     apply_U(c, t_u.p, t_L2.p, nrhs);                                      // Ů v
     hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
                        -1.0);                                            // w̄ = w - Ů v
-    std::vector<int> its(nrhs);
-    int st = solve_interface(c, t_L.p, t_L2.p, nrhs, inner_tol, inner_maxit, its.data(), nullptr);
-    for (int r = 0; r < nrhs; ++r) inner_total[r] += its[r];
-    if (st != IFETI_OK && st != IFETI_EMAXIT) return st;
+    if (c->opt.interface_block == 1) {
+        apply_MD(c, t_L.p, t_L2.p, nrhs);      // lambda = M̊_D^-1 w̄ (49), no inner iteration
+    } else if (c->opt.interface_block == 2) {
+        apply_MD_rom(c, t_L.p, t_L2.p, nrhs);  // lambda = M̊_D^-ROM w̄ (47)
+    } else {
+        std::vector<int> its(nrhs);
+        int st = solve_interface(c, t_L.p, t_L2.p, nrhs, inner_tol, inner_maxit, its.data(), nullptr);
+        for (int r = 0; r < nrhs; ++r) inner_total[r] += its[r];
+        if (st != IFETI_OK && st != IFETI_EMAXIT) return st;
+    }
     // y = -lambda; x_u = K̊^-ROM v + Ůᵀ lambda
     apply_Kinv_rom(c, t_u.p, t_u2.p, nrhs);
     apply_Ut(c, t_L2.p, t_u.p, nrhs);

@@ -22,7 +22,8 @@ IFETI_FP64, IFETI_FP32_LOCAL, IFETI_BF16_LOCAL = 0, 1, 2
 
 EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_sizes", "ifeti_set_options",
             "ifeti_build_cells", "ifeti_get_rhs", "ifeti_build_reduced_basis", "ifeti_get_coefficients",
-            "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_U", "ifeti_apply_Ut", "ifeti_apply_Kinv_rom",
+            "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_MD_rom", "ifeti_apply_U", "ifeti_apply_Ut",
+            "ifeti_apply_Kinv_rom",
             "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
             "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths",
             "ifeti_build_exact", "ifeti_exact_apply_F", "ifeti_exact_apply_MD", "ifeti_exact_solve",
@@ -47,7 +48,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int),
                 ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32),
                 ("timing_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int)]
+                ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int), ("interface_block", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_get_coefficients": [P, P, P, P],
         "ifeti_apply_F": [P, P, P, I],
         "ifeti_apply_MD": [P, P, P, I],
+        "ifeti_apply_MD_rom": [P, P, P, I],
         "ifeti_apply_U": [P, P, P, I],
         "ifeti_apply_Ut": [P, P, P, I],
         "ifeti_apply_Kinv_rom": [P, P, P, I],
@@ -184,9 +186,10 @@ class Context:
         return s
 
     def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
-                    timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0):
+                    timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
+                    interface_block=0):
         o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
-                    timing_every, use_graph, autotune, coarse_parts, true_operator)
+                    timing_every, use_graph, autotune, coarse_parts, true_operator, interface_block)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
 
     def stats(self) -> dict:
@@ -251,6 +254,9 @@ class Context:
 
     def apply_MD(self, r, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_MD, r, self.sizes.L, nrhs, out)
+
+    def apply_MD_rom(self, r, nrhs=1, out=None):
+        return self._apply(self.lib.ifeti_apply_MD_rom, r, self.sizes.L, nrhs, out)
 
     def apply_U(self, v, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_U, v, self.sizes.L, nrhs, out)
