@@ -82,7 +82,13 @@ int ifeti_create(ifeti_ctx **out, const ifeti_lattice_desc *d, void *stream) {
 void ifeti_destroy(ifeti_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->local_stream) (void)hipStreamSynchronize(c->local_stream);
     release_events(c);
+    if (c->local_stream) {
+        (void)hipStreamDestroy(c->local_stream);
+        (void)hipEventDestroy(c->ev_local_fork);
+        (void)hipEventDestroy(c->ev_local_join);
+    }
     if (c->side_stream) {
         (void)hipStreamSynchronize(c->side_stream);
         (void)hipStreamDestroy(c->side_stream);
@@ -181,6 +187,7 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.autotune = opt->autotune ? 1 : 0;
         REQ(opt->interface_block >= 0 && opt->interface_block <= 2, "interface_block must be 0, 1 or 2");
         c->opt.interface_block = opt->interface_block;
+        c->opt.overlap_local = opt->overlap_local ? 1 : 0;
         REQ(opt->true_operator == 0 || opt->true_operator == 1, "true_operator must be 0 or 1");
         REQ(opt->true_operator == 0 || c->ref.p == 2, "the matrix-free true operator needs quadratic B-splines");
         c->opt.true_operator = opt->true_operator;

@@ -118,6 +118,7 @@ struct Options {
     int coarse_parts = 0;       // coarse solve: 0 automatic, 1 symmetric-tile inverse, >= 2 that many blocks
     int true_operator = 0;      // K^(s) in (16): 0 stencil values, 1 matrix-free from the pulled-back tensor
     int interface_block = 0;    // Alg. 1 interface block: 0 PCG on (48), 1 one M̊_D^-1 (49), 2 one M̊_D^-ROM (47)
+    int overlap_local = 1;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -165,6 +166,8 @@ struct ifeti_ctx {
     hipStream_t side_stream = nullptr;   // second stream for the coarse path
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool side_pending = false;
+    hipStream_t local_stream = nullptr;  // third stream: reduced local solves beside the interface PCG
+    hipEvent_t ev_local_fork = nullptr, ev_local_join = nullptr;
     ifeti::Options opt;
     ifeti::RefTables ref;
 
@@ -377,7 +380,7 @@ void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double
 int dot_blocks(long long n);
 void apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs);
 void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs);
-void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs);
+void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs, bool local_done = false);
 void apply_A(ifeti_ctx *c, const double *x, double *y, int nrhs);
 // V_i = Vp[i] when a device pointer table is given, else V + i*vstride
 void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *w, long long n, long long rs,

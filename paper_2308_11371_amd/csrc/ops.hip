@@ -1539,7 +1539,7 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
 }
 
 // ------------------------------------------------------------------ K̊^-ROM (45), Algorithm 2
-void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
+void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs, bool local_done) {
     ensure_work(c, nrhs);
     const int N = c->N, np = c->n_p, nr = c->n_r, K = c->K;
     const int cols = N * nrhs;
@@ -1550,7 +1550,7 @@ void apply_Kinv_rom(ifeti_ctx *c, const double *v, double *x, int nrhs) {
     op_assemble_primal(c, c->w_c.p, v + (size_t)N * nr, nU, -1.0, c->w_zP.p, c->nP, nrhs);
     double *xP = x + (size_t)N * nr;
     op_coarse_solve(c, c->w_zP.p, c->nP, xP, nU, nrhs, 1.0);
-    op_rom_local(c, v, nU, x, nU, nrhs);                       // x_R = K̊_RR^-ROM v_R
+    if (!local_done) op_rom_local(c, v, nU, x, nU, nrhs);      // x_R = K̊_RR^-ROM v_R (unless already there)
     op_restrict_primal(c, xP, nU, c->w_yp.p, nrhs);
     GemmGroup g;                                                 // x_R -= Ů_RP x_P
     g.A = c->Urp.p; g.X = c->w_yp.p; g.coef = c->pi.p; g.Kd = np; g.ldx = np; g.K = K; g.scale = -1.0;

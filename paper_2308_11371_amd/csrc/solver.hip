@@ -522,6 +522,24 @@ static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, dou
     t_L.ensure((size_t)L * nrhs, s);
     t_L2.ensure((size_t)L * nrhs, s);
     hipLaunchKernelGGL(k_unpack, dim3(nblocks(ns * nrhs)), dim3(kB), 0, s, in, nU, L, t_u.p, t_L.p, nrhs);
+    // the reduced local solves of (46) depend on v alone: with overlap_local they run on a third
+    // stream (into the r rows of x_u) while Ů v and the interface PCG run here; they touch only
+    // their own work buffers (R, H), which nothing on this stream uses
+    const bool overlap = c->opt.overlap_local && !c->opt.use_graph && c->opt.interface_block == 0;
+    if (overlap) {
+        ensure_work(c, nrhs);  // no reallocation while the third stream runs
+        if (!c->local_stream) {
+            IFETI_HIP(hipStreamCreateWithFlags(&c->local_stream, hipStreamNonBlocking));
+            IFETI_HIP(hipEventCreateWithFlags(&c->ev_local_fork, hipEventDisableTiming | hipEventDisableSystemFence));
+            IFETI_HIP(hipEventCreateWithFlags(&c->ev_local_join, hipEventDisableTiming | hipEventDisableSystemFence));
+        }
+        IFETI_HIP(hipEventRecord(c->ev_local_fork, s));
+        IFETI_HIP(hipStreamWaitEvent(c->local_stream, c->ev_local_fork, 0));
+        c->stream = c->local_stream;
+        op_rom_local(c, t_u.p, nU, t_u2.p, nU, nrhs);
+        IFETI_HIP(hipEventRecord(c->ev_local_join, c->local_stream));
+        c->stream = s;
+    }
     apply_U(c, t_u.p, t_L2.p, nrhs);                                      // Ů v
     hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
                        -1.0);                                            // w̄ = w - Ů v
@@ -533,10 +551,14 @@ static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, dou
         std::vector<int> its(nrhs);
         int st = solve_interface(c, t_L.p, t_L2.p, nrhs, inner_tol, inner_maxit, its.data(), nullptr);
         for (int r = 0; r < nrhs; ++r) inner_total[r] += its[r];
-        if (st != IFETI_OK && st != IFETI_EMAXIT) return st;
+        if (st != IFETI_OK && st != IFETI_EMAXIT) {
+            if (overlap) IFETI_HIP(hipStreamWaitEvent(s, c->ev_local_join, 0));
+            return st;
+        }
     }
     // y = -lambda; x_u = K̊^-ROM v + Ůᵀ lambda
-    apply_Kinv_rom(c, t_u.p, t_u2.p, nrhs);
+    if (overlap) IFETI_HIP(hipStreamWaitEvent(s, c->ev_local_join, 0));
+    apply_Kinv_rom(c, t_u.p, t_u2.p, nrhs, overlap);
     apply_Ut(c, t_L2.p, t_u.p, nrhs);
     hipLaunchKernelGGL(k_sub, dim3(nblocks(nU * nrhs)), dim3(kB), 0, s, t_u2.p, nU, t_u.p, nU, t_u2.p, nU, nU,
                        nrhs, 1.0);

@@ -157,6 +157,24 @@ def test_interface_block_variants(pair, block, label):
     assert int(info["inner_its"][0]) == 0
 
 
+def test_overlap_local_bitwise(pair):
+    """Reduced local solves on a third stream beside Ů v and the interface PCG: the same kernels on the
+    same inputs, so the solve is bitwise that of the single-stream order."""
+    name, prob, m, ctx = pair
+    f, d = ctx.get_rhs()
+    f = f[:m.nU].contiguous()
+    d = d[:m.L].contiguous()
+    ctx.set_options(overlap_local=0)
+    try:
+        u0, lam0, i0 = ctx.solve(f, d, tol=1e-10, maxit=80)
+        ctx.set_options(overlap_local=1)
+        u1, lam1, i1 = ctx.solve(f, d, tol=1e-10, maxit=80)
+    finally:
+        ctx.set_options()
+    assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(lam0), host(lam1))
+    assert int(i0["outer_its"][0]) == int(i1["outer_its"][0])
+
+
 def test_multi_rhs_equals_single(pair):
     name, prob, m, ctx = pair
     L = m.L
