@@ -978,8 +978,6 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     for (int i = 0; i < ngroups; ++i)
         IFETI_REQUIRE(groups[i].K >= 1 && groups[i].K <= kMaxCoefK, IFETI_EINVAL, "gemm: 1 to 40 principal operators");
     if (ncols <= 0 || M <= 0) return;
-    int ngather = 0;
-    for (int i = 0; i < ngroups; ++i) ngather += groups[i].gcodes ? 1 : 0;
     GemmArgsDev a{};
     a.ncells = ncells > 0 ? ncells : c->N;
     int Kmax = 0, Kdmax = 0;

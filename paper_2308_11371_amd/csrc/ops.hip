@@ -153,13 +153,14 @@ __global__ __launch_bounds__(64 * NWC) void k_restrict_c(const double *__restric
     }
 #pragma unroll
     for (int i = 0; i < NPM; ++i) {
-        if (i >= n_p) break;
-        double v = acc[i];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) part[wave][i] = v;
+        if (i < n_p) {  // uniform over the workgroup
+            double v = acc[i];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) part[wave][i] = v;
+        }
     }
     __syncthreads();
-    if (threadIdx.x < n_p) {
+    if ((int)threadIdx.x < n_p) {
         double v = part[0][threadIdx.x];
 #pragma unroll
         for (int w = 1; w < NWC; ++w) v += part[w][threadIdx.x];
@@ -1105,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double *__restri
 #pragma unroll
             for (int g = 0; g < G; ++g) sh[wave][g] = acc[g];
         __syncthreads();
-        if (threadIdx.x < ng)
+        if ((int)threadIdx.x < ng)
             partial[((size_t)rhs * nv + g0 + threadIdx.x) * nblk + b] =
                 ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
         __syncthreads();

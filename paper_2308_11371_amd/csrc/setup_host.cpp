@@ -740,7 +740,6 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     //    dot product of the cell snapshot with a table Psi[q][ab][cd] = w_q sum_col (grad U)_ab (grad V)_cd
     //    built once from the principal fields (the lookup-table idea of Sec. 4.2.1, Remark 9); all cells
     //    then need one GEMM against their snapshots.
-    const int d = R.dim, d2 = d * d, d4 = d2 * d2;
     const int npair = K * (K + 1) / 2;
     const int ncoef = 2 * npair + K;  // A pairs, M pairs, b
     std::vector<int> pi_i(npair), pi_j(npair);

@@ -579,8 +579,16 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
     // Krylov blocks come from a pool kept in the context: allocated the first time an iteration
     // count is reached, reused by later solves (memory ~ iterations used x load cases)
     const size_t nblk_elems = (size_t)ns * nrhs;
-    c->fg_dV.ensure(m + 1, s);
-    c->fg_dZ.ensure(m + 1, s);
+    // device tables of block pointers: growing one reallocates it without its entries, so the host
+    // mirrors are cleared with it and every block pointer is uploaded again on first use
+    if (c->fg_dV.n < (size_t)m + 1) {
+        c->fg_dV.ensure(m + 1, s);
+        std::fill(c->fg_hV.begin(), c->fg_hV.end(), nullptr);
+    }
+    if (c->fg_dZ.n < (size_t)m + 1) {
+        c->fg_dZ.ensure(m + 1, s);
+        std::fill(c->fg_hZ.begin(), c->fg_hZ.end(), nullptr);
+    }
     if (c->fg_hV.size() < (size_t)m + 1) c->fg_hV.resize(m + 1, nullptr);
     if (c->fg_hZ.size() < (size_t)m + 1) c->fg_hZ.resize(m + 1, nullptr);
     int nV = 0, nZ = 0;

@@ -157,6 +157,24 @@ def test_interface_block_variants(pair, block, label):
     assert int(info["inner_its"][0]) == 0
 
 
+def test_fgmres_restart_growth(pair):
+    """A solve with a larger Krylov limit than earlier solves of the same context grows the device
+    tables of Krylov-block pointers; every entry must be valid again (regression: the grown table
+    lost its entries while the host mirror still held them)."""
+    name, prob, m, ctx = pair
+    f, d = ctx.get_rhs()
+    f = f[:m.nU].contiguous()
+    d = d[:m.L].contiguous()
+    try:
+        ctx.set_options(fgmres_restart=30)
+        u0, lam0, i0 = ctx.solve(f, d, tol=1e-10, maxit=30)
+        ctx.set_options(fgmres_restart=300)
+        u1, lam1, i1 = ctx.solve(f, d, tol=1e-10, maxit=300)
+    finally:
+        ctx.set_options()
+    assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(lam0), host(lam1))
+
+
 def test_overlap_local_bitwise(pair):
     """Reduced local solves on a third stream beside Ů v and the interface PCG: the same kernels on the
     same inputs, so the solve is bitwise that of the single-stream order."""
