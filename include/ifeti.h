@@ -116,11 +116,12 @@ typedef struct {
                                application of M̊_D^-ROM (47), the Dirichlet preconditioner with
                                reduced interior solves (Sec. 3.2.3).  1 and 2 make the preconditioner
                                cheaper and the outer FGMRES longer */
-    int overlap_local;      /* 1 (the context's initial setting): inside the preconditioner, the
-                               reduced local solves of (46) on v run on a third stream while Ů v and
-                               the interface PCG run on the main stream (they share no buffers);
-                               results are bitwise those of 0 (c2: 131.5 against 133.0 ms).
-                               Ignored with use_graph = 1 or interface_block != 0 */
+    int overlap_local;      /* 1: inside the preconditioner, the reduced local solves of (46) on v
+                               run on a third stream while Ů v and the interface PCG run on the main
+                               stream (they share no buffers); results are bitwise those of 0.  The
+                               solve gains about 1 % on c2 while the interface contractions that meet
+                               the local solve's contraction slow down; 0 by default.  Ignored with
+                               use_graph = 1 or interface_block != 0 */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

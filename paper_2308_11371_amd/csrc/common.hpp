@@ -118,7 +118,7 @@ struct Options {
     int coarse_parts = 0;       // coarse solve: 0 automatic, 1 symmetric-tile inverse, >= 2 that many blocks
     int true_operator = 0;      // K^(s) in (16): 0 stencil values, 1 matrix-free from the pulled-back tensor
     int interface_block = 0;    // Alg. 1 interface block: 0 PCG on (48), 1 one M̊_D^-1 (49), 2 one M̊_D^-ROM (47)
-    int overlap_local = 1;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
+    int overlap_local = 0;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)

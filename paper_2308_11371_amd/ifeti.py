@@ -188,7 +188,7 @@ class Context:
 
     def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
                     timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
-                    interface_block=0, overlap_local=1):
+                    interface_block=0, overlap_local=0):
         o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
                     timing_every, use_graph, autotune, coarse_parts, true_operator, interface_block, overlap_local)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
