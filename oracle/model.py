@@ -13,6 +13,8 @@ Operators (paper Sec. 3.2):
                  solves of eq. (46), the Gram matrix taken with the cell's own
                  K_rr^(s)
   apply_A        the true saddle operator of eq. (16)
+  rom_local_solve the reduced local solve of eq. (46), or with local_iters > 1
+                 the multi-preconditioned CG of Remark 6 (K̊^-MPCG)
   apply_MD_rom   M̊_D^-ROM of eq. (47): the Dirichlet preconditioner (30) with
                  each cell's interior solve replaced by the reduced solve of
                  eq. (46) on the interior block (principal K_ii^(σk)-1)
@@ -70,6 +72,7 @@ class Model:
         self.f_cells = cell_loads(self.ref, problem)            # (N, n_dof, nrhs)
         self.rhs_f = None
         self._Kii_inv = None
+        self.local_iters = 1                 # > 1: multi-preconditioned local solves (Remark 6)
         if build_all_cells:
             self._build_rhs()
 
@@ -191,8 +194,17 @@ class Model:
         return np.concatenate([xR.reshape(-1), xP])
 
     # ----------------------------------------------------------- K̊^-ROM (45)-(46)
-    def rom_local_solve(self, vR: np.ndarray) -> np.ndarray:
-        """Eq. (46): x_r = R (R^T K_rr^(s) R)^-1 R^T v_r, R = [K_rr^(sigma_k)-1 v_r]_k, per cell."""
+    def rom_local_solve(self, vR: np.ndarray, iters=None) -> np.ndarray:
+        """Eq. (46): x_r = R (R^T K_rr^(s) R)^-1 R^T v_r, R = [K_rr^(sigma_k)-1 v_r]_k, per cell.
+
+        iters > 1 (default: self.local_iters): the multi-preconditioned CG of Remark 6 with the
+        principal inverses as the preconditioners.  Iteration t takes Z = [K_rr^(σk)-1 r]_k, makes it
+        K_rr^(s)-conjugate to every earlier block (Z -= P_j G_j^-1 (K_rr^(s) P_j)^T Z), and minimises the
+        energy error over its span: x += Z a, r -= K_rr^(s) Z a, a = (Z^T K_rr^(s) Z)^-1 Z^T r.  The
+        first iteration is eq. (46)."""
+        iters = self.local_iters if iters is None else iters
+        if iters > 1:
+            return self._mpcg_local_solve(vR, iters)
         b = self.bank
         N, nr = vR.shape
         K = b.K
@@ -205,6 +217,27 @@ class Model:
             G = R[s].T @ (Krr @ R[s])
             c = romlib.spd_solve(G, R[s].T @ vR[s])
             x[s] = R[s] @ c
+        return x
+
+    def _mpcg_local_solve(self, vR: np.ndarray, iters: int) -> np.ndarray:
+        b = self.bank
+        x = np.zeros_like(vR)
+        for s in range(vR.shape[0]):
+            if not np.any(vR[s]):
+                continue
+            Krr, _ = romlib.cell_blocks(self.ref, self.dd, self.Kvals[s])
+            r = vR[s].copy()
+            blocks = []
+            for _ in range(iters):
+                Z = np.stack([Ki @ r for Ki in b.Kinv], axis=1)
+                for P, KP, G in blocks:
+                    Z = Z - P @ romlib.spd_solve(G, KP.T @ Z)
+                KZ = Krr @ Z
+                G = Z.T @ KZ
+                a = romlib.spd_solve(G, Z.T @ r)
+                x[s] += Z @ a
+                r -= KZ @ a
+                blocks.append((Z, KZ, G))
         return x
 
     def apply_Kinv_rom(self, v: np.ndarray) -> np.ndarray:

@@ -6,6 +6,7 @@ import scipy.sparse as sp
 
 import latticegen
 from oracle import Model
+import oracle.rom as romlib
 from oracle.assembly import dense
 from oracle.greedy import greedy
 from oracle.fetidp import ExactFETIDP
@@ -284,3 +285,30 @@ def test_MD_rom_positively_homogeneous_and_energy_positive(m2):
     y = m2.apply_MD_rom(r)
     assert np.allclose(m2.apply_MD_rom(-2.5 * r), -2.5 * y, rtol=1e-12, atol=1e-13)
     assert r @ y >= r @ ex.apply_MD(r) * (1 - 1e-12) > 0
+
+
+def test_mpcg_local_solve_improves_and_converges(m2):
+    """Remark 6: the multi-preconditioned CG local solve minimises the K_rr^(s)-energy error over a
+    growing conjugate space, so the error never grows with the iteration count, the first iteration
+    is eq. (46), and enough iterations give K_rr^(s)-1 v (checked against a dense solve per cell)."""
+    rng = np.random.default_rng(9)
+    vR = rng.standard_normal((m2.N, m2.dd.n_r))
+    exact = np.array([np.linalg.solve(romlib.cell_blocks(m2.ref, m2.dd, m2.Kvals[s])[0].toarray(), vR[s])
+                      for s in range(m2.N)])
+    x1 = m2.rom_local_solve(vR, iters=1)
+    assert np.allclose(m2._mpcg_local_solve(vR, 1), x1, rtol=1e-10, atol=1e-12)
+    prev = None
+    for it in (1, 2, 3, 5):
+        x = m2.rom_local_solve(vR, iters=it)
+        err = []
+        for s in range(m2.N):
+            Krr = romlib.cell_blocks(m2.ref, m2.dd, m2.Kvals[s])[0]
+            e = x[s] - exact[s]
+            err.append(e @ (Krr @ e))
+        err = np.array(err)
+        if prev is not None:
+            assert np.all(err <= prev * (1 + 1e-8) + 1e-20)
+        prev = err
+    n_r, K = m2.dd.n_r, m2.bank.K
+    xf = m2.rom_local_solve(vR, iters=n_r // K + 4)
+    assert np.allclose(xf, exact, rtol=1e-8, atol=1e-10)

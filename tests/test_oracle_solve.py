@@ -95,3 +95,17 @@ def test_interface_block_variants_reach_direct_solution(interface):
     assert _rel(r["u"], ref["u"]) < 1e-9
     assert r["outer_its"] >= m.solve(tol=1e-12, inner_tol=1e-13)["outer_its"]
     assert sum(r["inner_its"]) == 0
+
+
+def test_mpcg_local_solves_reach_direct_solution():
+    """K̊^-MPCG (Remark 6, two multi-preconditioned CG iterations per local solve) inside Alg. 1: the
+    outer FGMRES reaches the conforming solution, in no more outer iterations than with eq. (46)."""
+    m = Model(latticegen.tiny(2, (3, 3), 3, n_principal=3))
+    m.build_reduced_basis()
+    r1 = m.solve(tol=1e-12, inner_tol=1e-13, maxit=80)
+    m.local_iters = 2
+    r2 = m.solve(tol=1e-12, inner_tol=1e-13, maxit=80)
+    ref = conforming_solve(m)
+    assert r2["relres"] < 1e-11
+    assert _rel(r2["u"], ref["u"]) < 1e-10
+    assert r2["outer_its"] <= r1["outer_its"]
