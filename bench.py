@@ -173,6 +173,14 @@ def run_forms(ctx, f, d, t_fp64, args):
                      "relres": float(info["relres"][0])}
         log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]}")
     ctx.set_options()
+    # K̊^-MPCG (Remark 6): multi-preconditioned CG local solves, two and three iterations each
+    for it in (2, 3):
+        ctx.set_options(local_iters=it)
+        t, info = timed_solve(ctx, f, d, 1, args.tol, 1e-11)
+        res[f"mpcg_local_{it}"] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
+                                   "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0])}
+        log(f"form mpcg_local_{it}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+    ctx.set_options()
     res["true_operator"] = run_true_operator(ctx)
     prob = latticegen.make("c4")
     c4 = ifeti.setup(prob)

@@ -122,6 +122,10 @@ typedef struct {
                                solve gains about 1 % on c2 while the interface contractions that meet
                                the local solve's contraction slow down; 0 by default.  Ignored with
                                use_graph = 1 or interface_block != 0 */
+    int local_iters;        /* 1: the reduced local solves of (46); 2..8: K̊^-MPCG of Remark 6, that
+                               many multi-preconditioned CG iterations per cell with the principal
+                               inverses as the preconditioners (the first iteration is (46); later
+                               blocks are made K_rr^(s)-conjugate to all earlier ones) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

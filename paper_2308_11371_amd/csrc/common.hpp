@@ -119,6 +119,7 @@ struct Options {
     int true_operator = 0;      // K^(s) in (16): 0 stencil values, 1 matrix-free from the pulled-back tensor
     int interface_block = 0;    // Alg. 1 interface block: 0 PCG on (48), 1 one M̊_D^-1 (49), 2 one M̊_D^-ROM (47)
     int overlap_local = 0;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
+    int local_iters = 1;        // > 1: K̊^-MPCG, multi-preconditioned CG local solves (Remark 6)
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -259,6 +260,9 @@ struct ifeti_ctx {
     // M̊_D^-ROM (47): principal interior inverses K_ii^(σk)-1 zero-padded to n_r x n_r, rows interleaved
     // [r][k][n_r] like the stacked K_rr^-1 (built on first use for the current bank), and work vectors
     ifeti::DevBuf<double> Kii_pad, mdr_X, mdr_Y, mdr_v, mdr_x;
+    // K̊^-MPCG: residuals of the local problems and the whitened blocks of each iteration
+    ifeti::DevBuf<double> mp_r;
+    std::vector<std::unique_ptr<ifeti::DevBuf<double>>> mp_P, mp_KP;
     long long bank_gen = 0, kii_gen = -1;
     void free_copies() {
         ++rom_gen;

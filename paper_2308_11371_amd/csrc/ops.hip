@@ -519,18 +519,13 @@ __global__ __launch_bounds__(kRomHB) void k_rom_H(const double *__restrict__ R, 
     }
 }
 
-// Small dense solve by one lane: x = A^-1 b for symmetric A (K x K, row-major).
-// Cholesky; if a pivot is not positive, a cyclic Jacobi eigen-decomposition
-// gives the pseudo-inverse with a 1e-13 relative cut.
-__device__ void small_sym_solve(double *A, double *Lm, double *V, const double *b, double *x, int K) {
-    bool ok = true;
-    for (int j = 0; j < K && ok; ++j) {
+// Cholesky A = L L^T of a symmetric K x K matrix (row-major) by one lane; false at the first
+// pivot that is not positive.
+__device__ bool small_chol(const double *A, double *Lm, int K) {
+    for (int j = 0; j < K; ++j) {
         double sj = A[j * K + j];
         for (int k = 0; k < j; ++k) sj -= Lm[j * K + k] * Lm[j * K + k];
-        if (!(sj > 0.0)) {
-            ok = false;
-            break;
-        }
+        if (!(sj > 0.0)) return false;
         double l = sqrt(sj);
         Lm[j * K + j] = l;
         for (int i = j + 1; i < K; ++i) {
@@ -539,19 +534,12 @@ __device__ void small_sym_solve(double *A, double *Lm, double *V, const double *
             Lm[i * K + j] = t / l;
         }
     }
-    if (ok) {
-        for (int i = 0; i < K; ++i) {
-            double t = b[i];
-            for (int k = 0; k < i; ++k) t -= Lm[i * K + k] * x[k];
-            x[i] = t / Lm[i * K + i];
-        }
-        for (int i = K - 1; i >= 0; --i) {
-            double t = x[i];
-            for (int k = i + 1; k < K; ++k) t -= Lm[k * K + i] * x[k];
-            x[i] = t / Lm[i * K + i];
-        }
-        return;
-    }
+    return true;
+}
+
+// Cyclic Jacobi eigen-decomposition by one lane: A is diagonalised in place (eigenvalues on the
+// diagonal), V holds the eigenvectors as columns.
+__device__ void small_sym_jacobi(double *A, double *V, int K) {
     for (int i = 0; i < K * K; ++i) V[i] = 0.0;
     for (int i = 0; i < K; ++i) V[i * K + i] = 1.0;
     for (int sweep = 0; sweep < 100; ++sweep) {
@@ -587,6 +575,26 @@ __device__ void small_sym_solve(double *A, double *Lm, double *V, const double *
                 }
             }
     }
+}
+
+// Small dense solve by one lane: x = A^-1 b for symmetric A (K x K, row-major).
+// Cholesky; if a pivot is not positive, a cyclic Jacobi eigen-decomposition
+// gives the pseudo-inverse with a 1e-13 relative cut.
+__device__ void small_sym_solve(double *A, double *Lm, double *V, const double *b, double *x, int K) {
+    if (small_chol(A, Lm, K)) {
+        for (int i = 0; i < K; ++i) {
+            double t = b[i];
+            for (int k = 0; k < i; ++k) t -= Lm[i * K + k] * x[k];
+            x[i] = t / Lm[i * K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double t = x[i];
+            for (int k = i + 1; k < K; ++k) t -= Lm[k * K + i] * x[k];
+            x[i] = t / Lm[i * K + i];
+        }
+        return;
+    }
+    small_sym_jacobi(A, V, K);
     double wmax = 0.0;
     for (int i = 0; i < K; ++i) wmax = fmax(wmax, A[i * K + i]);
     for (int i = 0; i < K; ++i) x[i] = 0.0;
@@ -673,6 +681,173 @@ __global__ __launch_bounds__(64 * WPB) void k_rom_gram(const double *__restrict_
             for (int k = 0; k < K; ++k) t += Rc[(size_t)r * K + k] * cv[k];
             x[r] = t;
         }
+    }
+}
+
+// ------------------------------------------------------------------ K̊^-MPCG (Remark 6)
+// Multi-preconditioned CG for the local problems K_rr^(s) x = v with the principal inverses as the K
+// preconditioners.  Each iteration's block Z = [K_rr^(σk)-1 r]_k is whitened, Ẑ = Z T with
+// Ẑᵀ K_rr^(s) Ẑ = I on the range of G = Zᵀ K_rr^(s) Z, so the energy minimisation is
+// x += Ẑ Ẑᵀ r, r -= K Ẑ Ẑᵀ r (that is Z G^-1 Zᵀ r) and the conjugation of a later block against it
+// is Z -= Ẑ (K Ẑ)ᵀ Z (that is P G^-1 (K P)ᵀ Z).  Cholesky gives T = L^-T; a pivot that is not positive
+// switches to the Jacobi eigen-decomposition, T = V diag(w^-1/2) over the eigenvalues above 1e-13 of
+// the largest (the pseudo-inverse of the reduced solve).
+
+// T (K x K, row-major) with Tᵀ A T = I on the range of A; A is overwritten.  One lane.
+__device__ void small_sym_whiten(double *A, double *Lm, double *V, double *T, int K) {
+    if (small_chol(A, Lm, K)) {
+        for (int i = 0; i < K * K; ++i) T[i] = 0.0;
+        for (int j = 0; j < K; ++j) {  // column j of L^-1 is row j of T = L^-T
+            T[j * K + j] = 1.0 / Lm[j * K + j];
+            for (int i = j + 1; i < K; ++i) {
+                double t = 0.0;
+                for (int k = j; k < i; ++k) t += Lm[i * K + k] * T[j * K + k];
+                T[j * K + i] = -t / Lm[i * K + i];
+            }
+        }
+        return;
+    }
+    small_sym_jacobi(A, V, K);
+    double wmax = 0.0;
+    for (int i = 0; i < K; ++i) wmax = fmax(wmax, A[i * K + i]);
+    for (int k = 0; k < K; ++k) {
+        const double wk = A[k * K + k];
+        const double sc = wk > 1e-13 * wmax ? 1.0 / sqrt(wk) : 0.0;
+        for (int i = 0; i < K; ++i) T[i * K + k] = V[i * K + k] * sc;
+    }
+}
+
+// acc = Aᵀ [B | b] over the n_r rows of one column (A, B: [r][k] with K columns; b optional), on the
+// FP64 MFMA; the K x K block and the extra column are left in LDS (M row-major, m).
+template <int KB>
+__device__ __forceinline__ void col_gram(const double *__restrict__ Ac, const double *__restrict__ Bc,
+                                         const double *__restrict__ bv, int K, int n_r, int lane, double *M,
+                                         double *m) {
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d acc[KB][KB];
+#pragma unroll
+    for (int a = 0; a < KB; ++a)
+#pragma unroll
+        for (int b = 0; b < KB; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nt4 = (n_r + 3) / 4;
+    for (int t = 0; t < nt4; ++t) {  // uniform trip count: the MFMA needs all 64 lanes
+        const int r = 4 * t + lk;
+        const bool rin = r < n_r;
+        double af[KB], bf[KB];
+#pragma unroll
+        for (int a = 0; a < KB; ++a) {
+            const int k1 = 16 * a + lr;
+            af[a] = (rin && k1 < K) ? Ac[(size_t)r * K + k1] : 0.0;
+            bf[a] = !rin ? 0.0 : (k1 < K ? Bc[(size_t)r * K + k1] : (k1 == K && bv ? bv[r] : 0.0));
+        }
+#pragma unroll
+        for (int a = 0; a < KB; ++a)
+#pragma unroll
+            for (int b = 0; b < KB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < KB; ++a)
+#pragma unroll
+        for (int b = 0; b < KB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + 4 * i + lk, cc = 16 * b + lr;
+                if (row >= K) continue;
+                if (cc == K) m[row] = acc[a][b][i];
+                else if (cc < K) M[row * K + cc] = acc[a][b][i];
+            }
+}
+
+// One MPCG step per column (one wave each): G = Zᵀ KZ, g = Zᵀ r, T from G, â = Tᵀ g;
+// P = Z T, KP = KZ T (stored for later conjugations), x (+)= P â, r -= KP â.
+template <int KB, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_mpcg_step(const double *__restrict__ Z, const double *__restrict__ KZ,
+                                                        double *__restrict__ r, double *__restrict__ xR,
+                                                        long long x_rs, int first, double *__restrict__ P,
+                                                        double *__restrict__ KP, int N, int ncols, int K,
+                                                        int n_r) {
+    constexpr int KM = 16 * KB;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * WPB + wave;
+    const bool active = col < ncols;
+    const int rhs = col / N, s = col % N;
+    double *G = lds + (size_t)wave * (4 * K * K + 2 * K);
+    double *Lm = G + K * K, *Vm = Lm + K * K, *T = Vm + K * K, *g = T + K * K, *ah = g + K;
+    const double *Zc = Z + (size_t)col * K * n_r, *KZc = KZ + (size_t)col * K * n_r;
+    double *rc = r + (size_t)col * n_r;
+    if (active) col_gram<KB>(Zc, KZc, rc, K, n_r, lane, G, g);
+    __syncthreads();
+    if (active && lane == 0) {
+        for (int i = 0; i < K; ++i)  // symmetric from the upper triangle
+            for (int j = i + 1; j < K; ++j) G[j * K + i] = G[i * K + j];
+        small_sym_whiten(G, Lm, Vm, T, K);
+        for (int b = 0; b < K; ++b) {
+            double t = 0.0;
+            for (int a = 0; a < K; ++a) t += T[a * K + b] * g[a];
+            ah[b] = t;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    double *x = xR + rhs * x_rs + (size_t)s * n_r;
+    double *Pc = P + (size_t)col * K * n_r, *KPc = KP + (size_t)col * K * n_r;
+    for (int row = lane; row < n_r; row += 64) {
+        double zh[KM], kh[KM];
+#pragma unroll
+        for (int b = 0; b < KM; ++b) zh[b] = kh[b] = 0.0;
+        for (int a = 0; a < K; ++a) {
+            const double za = Zc[(size_t)row * K + a], ka = KZc[(size_t)row * K + a];
+#pragma unroll
+            for (int b = 0; b < KM; ++b) {
+                const double t = b < K ? T[a * K + b] : 0.0;
+                zh[b] += za * t;
+                kh[b] += ka * t;
+            }
+        }
+        double xu = 0.0, ru = 0.0;
+#pragma unroll
+        for (int b = 0; b < KM; ++b) {
+            if (b < K) {
+                Pc[(size_t)row * K + b] = zh[b];
+                KPc[(size_t)row * K + b] = kh[b];
+                xu += zh[b] * ah[b];
+                ru += kh[b] * ah[b];
+            }
+        }
+        x[row] = first ? xu : x[row] + xu;
+        rc[row] -= ru;
+    }
+}
+
+// Conjugation of a new block against a stored whitened one: Z -= P (KPᵀ Z), one wave per column.
+template <int KB, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_mpcg_conj(double *__restrict__ Z, const double *__restrict__ P,
+                                                        const double *__restrict__ KP, int ncols, int K, int n_r) {
+    constexpr int KM = 16 * KB;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * WPB + wave;
+    const bool active = col < ncols;
+    double *C = lds + (size_t)wave * (K * K + K);
+    double *Zc = Z + (size_t)col * K * n_r;
+    const double *Pc = P + (size_t)col * K * n_r, *KPc = KP + (size_t)col * K * n_r;
+    if (active) col_gram<KB>(KPc, Zc, nullptr, K, n_r, lane, C, C + K * K);
+    __syncthreads();
+    if (!active) return;
+    for (int row = lane; row < n_r; row += 64) {
+        double d[KM];
+#pragma unroll
+        for (int b = 0; b < KM; ++b) d[b] = 0.0;
+        for (int a = 0; a < K; ++a) {
+            const double pa = Pc[(size_t)row * K + a];
+#pragma unroll
+            for (int b = 0; b < KM; ++b) d[b] += pa * (b < K ? C[a * K + b] : 0.0);
+        }
+#pragma unroll
+        for (int b = 0; b < KM; ++b)
+            if (b < K) Zc[(size_t)row * K + b] -= d[b];
     }
 }
 
@@ -1472,18 +1647,11 @@ void apply_Ut(ifeti_ctx *c, const double *y, double *x, int nrhs) {
     IFETI_HIP(hipGetLastError());
 }
 
-void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
-                  const double *bank, const char *rtag) {
-    const int N = c->N, nr = c->n_r, K = c->K;
-    IFETI_REQUIRE(K <= kMaxK, IFETI_EINVAL, "reduced local solve supports at most 40 principal cells");
-    // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
-    // column comes out as [r][k] (or the zero-padded interior inverses of (47))
-    GemmGroup g;
-    g.A = bank ? bank : c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
-    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, rtag);
-    // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
+// (46b) H = K_rr^(s) R for the K columns of R (work buffers w_R -> w_H) of `cols` cell columns,
+// in LDS-staged column chunks
+static void launch_rom_H(ifeti_ctx *c, int cols) {
     const RefTables &R = c->ref;
-    const int cols = N * nrhs;
+    const int N = c->N, nr = c->n_r, K = c->K;
     const double colsd = (double)cols;
     {
         int kcol = 4;
@@ -1519,6 +1687,92 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
             IFETI_HIP(hipGetLastError());
         }
     }
+}
+
+// cell r-vectors of every column into one contiguous block: out[col][n_r], col = rhs*N + s
+__global__ __launch_bounds__(kB) void k_cells_contiguous(const double *__restrict__ v, long long v_rs, int N, int n_r,
+                                                         long long total, double *__restrict__ out) {
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= total) return;
+    const long long col = t / n_r;
+    out[t] = v[(col / N) * v_rs + (col % N) * n_r + t % n_r];
+}
+
+// K̊^-MPCG (Remark 6): opt.local_iters multi-preconditioned CG iterations per cell, the first of which
+// is the reduced solve (46); the whitened blocks of earlier iterations are kept for the conjugations
+static void op_mpcg_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs) {
+    const int N = c->N, nr = c->n_r, K = c->K, iters = c->opt.local_iters;
+    const int cols = N * nrhs;
+    const size_t blk = (size_t)cols * K * nr;
+    hipStream_t s = c->stream;
+    c->mp_r.ensure((size_t)cols * nr, s);
+    while ((int)c->mp_P.size() < iters) {
+        c->mp_P.emplace_back(new DevBuf<double>());
+        c->mp_KP.emplace_back(new DevBuf<double>());
+    }
+    for (int j = 0; j < iters; ++j) {
+        c->mp_P[j]->ensure(blk, s);
+        c->mp_KP[j]->ensure(blk, s);
+    }
+    const long long total = (long long)cols * nr;
+    hipLaunchKernelGGL(k_cells_contiguous, dim3((unsigned)((total + kB - 1) / kB)), dim3(kB), 0, s, vR, v_rs, N, nr,
+                       total, c->mp_r.p);
+    const int kb = (K + 1 + 15) / 16, wpb = kb == 3 ? 2 : 4;
+    const dim3 grid((cols + wpb - 1) / wpb), block(64 * wpb);
+    const size_t lds_step = (size_t)wpb * (4 * K * K + 2 * K) * sizeof(double);
+    const size_t lds_conj = (size_t)wpb * (K * K + K) * sizeof(double);
+    const double colsd = (double)cols;
+    for (int it = 0; it < iters; ++it) {
+        GemmGroup g;  // Z = [K_rr^(σk)-1 r]_k
+        g.A = c->Kinv.p; g.X = c->mp_r.p; g.Kd = nr; g.ldx = nr; g.xbs = (long long)N * nr; g.K = 1;
+        gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, cols, false, 0, "rom_R_gemm");
+        for (int j = 0; j < it; ++j) {
+            Prof prof(c, "mpcg_conj", colsd * 4.0 * K * K * nr, colsd * 8.0 * 4.0 * K * nr);
+            const double *P = c->mp_P[j]->p, *KP = c->mp_KP[j]->p;
+            if (kb == 1)
+                hipLaunchKernelGGL((k_mpcg_conj<1, 4>), grid, block, lds_conj, s, c->w_R.p, P, KP, cols, K, nr);
+            else if (kb == 2)
+                hipLaunchKernelGGL((k_mpcg_conj<2, 4>), grid, block, lds_conj, s, c->w_R.p, P, KP, cols, K, nr);
+            else
+                hipLaunchKernelGGL((k_mpcg_conj<3, 2>), grid, block, lds_conj, s, c->w_R.p, P, KP, cols, K, nr);
+            IFETI_HIP(hipGetLastError());
+        }
+        launch_rom_H(c, cols);
+        {
+            Prof prof(c, "mpcg_step", colsd * (2.0 * (K + 1.0) * K * nr + 4.0 * K * K * nr),
+                      colsd * 8.0 * (6.0 * K * nr + 3.0 * nr));
+            double *P = c->mp_P[it]->p, *KP = c->mp_KP[it]->p;
+            if (kb == 1)
+                hipLaunchKernelGGL((k_mpcg_step<1, 4>), grid, block, lds_step, s, c->w_R.p, c->w_H.p, c->mp_r.p, xR,
+                                   x_rs, it == 0 ? 1 : 0, P, KP, N, cols, K, nr);
+            else if (kb == 2)
+                hipLaunchKernelGGL((k_mpcg_step<2, 4>), grid, block, lds_step, s, c->w_R.p, c->w_H.p, c->mp_r.p, xR,
+                                   x_rs, it == 0 ? 1 : 0, P, KP, N, cols, K, nr);
+            else
+                hipLaunchKernelGGL((k_mpcg_step<3, 2>), grid, block, lds_step, s, c->w_R.p, c->w_H.p, c->mp_r.p, xR,
+                                   x_rs, it == 0 ? 1 : 0, P, KP, N, cols, K, nr);
+            IFETI_HIP(hipGetLastError());
+        }
+    }
+}
+
+void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
+                  const double *bank, const char *rtag) {
+    const int N = c->N, nr = c->n_r, K = c->K;
+    IFETI_REQUIRE(K <= kMaxK, IFETI_EINVAL, "reduced local solve supports at most 40 principal cells");
+    if (c->opt.local_iters > 1 && !bank) {
+        op_mpcg_local(c, vR, v_rs, xR, x_rs, nrhs);
+        return;
+    }
+    // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
+    // column comes out as [r][k] (or the zero-padded interior inverses of (47))
+    GemmGroup g;
+    g.A = bank ? bank : c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
+    gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, rtag);
+    // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
+    const int cols = N * nrhs;
+    const double colsd = (double)cols;
+    launch_rom_H(c, cols);
     {
         Prof prof(c, "rom_gram", colsd * (2.0 * (K + 1.0) * K * nr + 2.0 * K * nr),
                   colsd * 8.0 * (3.0 * K * nr + 2.0 * nr));

@@ -157,6 +157,31 @@ def test_interface_block_variants(pair, block, label):
     assert int(info["inner_its"][0]) == 0
 
 
+@pytest.mark.parametrize("iters", [2, 3])
+def test_mpcg_local_parity(pair, iters):
+    """K̊^-MPCG (Remark 6): K̊^-ROM with multi-preconditioned CG local solves against the oracle's, and
+    the outer solve with two iterations per local solve reaches the oracle's solution."""
+    name, prob, m, ctx = pair
+    v = _rand(m.nU, 14)
+    ctx.set_options(local_iters=iters)
+    m.local_iters = iters
+    try:
+        got = host(ctx.apply_Kinv_rom(dev(v)))
+        expect = m.apply_Kinv_rom(v)
+        assert rel(got, expect) < 1e-10, f"{name} MPCG {iters}: rel err {rel(got, expect):.3e}"
+        if iters == 2:
+            ro = m.solve(tol=1e-10, inner_tol=1e-12, maxit=80)
+            f, d = ctx.get_rhs()
+            u, lam, info = ctx.solve(f[:m.nU].contiguous(), d[:m.L].contiguous(), tol=1e-10, inner_tol=1e-12,
+                                     maxit=80)
+            assert info["relres"][0] < 1e-10
+            assert rel(host(u), ro["u"]) < 1e-8
+            assert abs(int(info["outer_its"][0]) - ro["outer_its"]) <= 1
+    finally:
+        ctx.set_options()
+        m.local_iters = 1
+
+
 def test_fgmres_restart_growth(pair):
     """A solve with a larger Krylov limit than earlier solves of the same context grows the device
     tables of Krylov-block pointers; every entry must be valid again (regression: the grown table
