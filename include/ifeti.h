@@ -199,6 +199,13 @@ int ifeti_apply_F(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
 /* out = M̊_D^-1 r, the ROM Dirichlet preconditioner of eq. (49). */
 int ifeti_apply_MD(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
 
+/* Per-cell view of a displacement in the layout of eq. (13): out[rhs][s][e] for every local dof e of
+ * cell s in the cell's own order (control points in lexicographic order, components interleaved):
+ * the r entries from u_r^(s), the primal entries from u_P through the cell's primal map, zero at
+ * clamped corners.  u: device, nrhs vectors of length nU; out: device, nrhs * N * n_dof doubles.
+ * Needs ifeti_build_cells; EINVAL on null or aliased pointers or nrhs < 1. */
+int ifeti_cell_displacements(ifeti_ctx *ctx, const double *u, double *out, int nrhs);
+
 /* M̊_D^-ROM of eq. (47) (Sec. 3.2.3): out = sum_s D B_d^(s) S̃_dd^(s) B_d^(s)T D r with
  * S̃_dd^(s) = K_dd - K_di K̊_ii^-ROM K_id, where K̊_ii^-ROM w = R (Rᵀ K_ii^(s) R)^-1 Rᵀ w and
  * R = [K_ii^(σk)-1 w]_k is the reduced solve of eq. (46) on the interior block.  r and out: device,

@@ -309,6 +309,16 @@ int ifeti_apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs) {
     });
 }
 
+int ifeti_cell_displacements(ifeti_ctx *c, const double *u, double *out, int nrhs) {
+    return guarded([&]() {
+        REQ(c && c->cells_built, "cells not built");
+        REQ(nrhs >= 1 && (long long)c->N * c->ref.n_dof * nrhs < (1LL << 40), "nrhs out of range");
+        REQ(u && out && u != out, "bad pointers");
+        cell_displacements(c, u, out, nrhs);
+        return IFETI_OK;
+    });
+}
+
 int ifeti_apply_U(ifeti_ctx *c, const double *v, double *z, int nrhs) {
     return guarded([&]() {
         ROM_READY(c, nrhs);

@@ -369,6 +369,7 @@ void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_r
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
                   const double *bank = nullptr, const char *rtag = "rom_R_gemm");
 void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs);
+void cell_displacements(ifeti_ctx *c, const double *u, double *out, int nrhs);
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);

@@ -1989,6 +1989,38 @@ void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs) {
     IFETI_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ per-cell displacement view
+// out[rhs][s][e] for every local dof e of every cell (node-major, components interleaved): the r
+// entries of u_r^(s), the primal entries from u_P through A_p, zero at clamped corners
+__global__ __launch_bounds__(kB) void k_cell_view(const double *__restrict__ u, long long nU, int N, int n_r, int n_p,
+                                                  int n_dof, const int *__restrict__ r_of_dof,
+                                                  const int *__restrict__ p_of_dof, const int *__restrict__ Ap,
+                                                  double *__restrict__ out, long long total) {
+    const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+    if (t >= total) return;
+    const int e = (int)(t % n_dof);
+    const long long col = t / n_dof;
+    const int s = (int)(col % N);
+    const double *ur = u + (col / N) * nU;
+    const int rp = r_of_dof[e];
+    double v = 0.0;
+    if (rp >= 0) {
+        v = ur[(size_t)s * n_r + rp];
+    } else {
+        const int P = Ap[(size_t)s * n_p + p_of_dof[e]];
+        v = P >= 0 ? ur[(size_t)N * n_r + P] : 0.0;
+    }
+    out[t] = v;
+}
+
+void cell_displacements(ifeti_ctx *c, const double *u, double *out, int nrhs) {
+    const long long total = (long long)nrhs * c->N * c->ref.n_dof;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_cell_view, dim3((unsigned)((total + kB - 1) / kB)), dim3(kB), 0, c->stream, u, c->nU, c->N,
+                       c->n_r, c->n_p, c->ref.n_dof, c->r_of_dof.p, c->p_of_dof.p, c->g_Ap.p, out, total);
+    IFETI_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ vector helpers
 
 // out_dev[rhs*nv + i] = V_i[rhs] . w[rhs]

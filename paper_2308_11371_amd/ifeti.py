@@ -27,7 +27,7 @@ EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_size
             "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
             "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths",
             "ifeti_build_exact", "ifeti_exact_apply_F", "ifeti_exact_apply_MD", "ifeti_exact_solve",
-            "ifeti_exact_cell_blocks")
+            "ifeti_exact_cell_blocks", "ifeti_cell_displacements")
 
 
 class LatticeDesc(ctypes.Structure):
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_apply_F": [P, P, P, I],
         "ifeti_apply_MD": [P, P, P, I],
         "ifeti_apply_MD_rom": [P, P, P, I],
+        "ifeti_cell_displacements": [P, P, P, I],
         "ifeti_apply_U": [P, P, P, I],
         "ifeti_apply_Ut": [P, P, P, I],
         "ifeti_apply_Kinv_rom": [P, P, P, I],
@@ -259,6 +260,10 @@ class Context:
 
     def apply_MD_rom(self, r, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_MD_rom, r, self.sizes.L, nrhs, out)
+
+    def cell_displacements(self, u, nrhs=1, out=None):
+        """Per-cell (N, n_dof) view of u per load case (clamped corners zero)."""
+        return self._apply(self.lib.ifeti_cell_displacements, u, self.sizes.N * self.sizes.n_dof, nrhs, out)
 
     def apply_U(self, v, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_U, v, self.sizes.L, nrhs, out)

@@ -218,6 +218,17 @@ def test_overlap_local_bitwise(pair):
     assert int(i0["outer_its"][0]) == int(i1["outer_its"][0])
 
 
+def test_cell_displacements(pair):
+    """Per-cell view of u (eq. (13) layout -> each cell's own dofs, clamped corners zero): bitwise the
+    oracle's, for one and two load cases."""
+    name, prob, m, ctx = pair
+    U = np.stack([_rand(m.nU, 80 + r) for r in range(2)])
+    n_dof = m.ref.n_dof
+    got = host(ctx.cell_displacements(dev(U.ravel()), nrhs=2)).reshape(2, m.N, n_dof)
+    for r in range(2):
+        assert np.array_equal(got[r], m.full_cell_displacements(U[r]))
+
+
 def test_multi_rhs_equals_single(pair):
     name, prob, m, ctx = pair
     L = m.L
