@@ -195,15 +195,6 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
         const double scale = g.scale[gi];
         for (int kk = 0; kk < Kd; kk += FKC) {
             const int kc = min(FKC, Kd - kk);
-            __syncthreads();  // previous chunk fully consumed
-            stage_chunk<NC, FKC, NT, FXS, 4>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
-            for (int e = tid; e < K * NC; e += NT) {
-                const int k = e / NC, cc = e % NC, col = col0 + cc;
-                double v = 0.0;
-                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
-                Cs[e] = v;
-            }
-            __syncthreads();
             const int np = (kc + 7) / 8;  // fragment pairs of this chunk
             const int q0 = kk / 8;
             const int total = K * np;
@@ -222,10 +213,21 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
                     }
                 }
             };
+            __syncthreads();  // previous chunk fully consumed
+            // the first operator fragments do not depend on the staged columns: their loads are in
+            // flight while the columns and coefficients are staged
             double2 ab[PF][RT];
 #pragma unroll
             for (int u = 0; u < PF; ++u)
                 if (u < ns) load(u, ab[u]);
+            stage_chunk<NC, FKC, NT, FXS, 4>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
+            for (int e = tid; e < K * NC; e += NT) {
+                const int k = e / NC, cc = e % NC, col = col0 + cc;
+                double v = 0.0;
+                if (col < g.ncols) v = scale * (coef ? coef[(size_t)(col % g.ncells) * K + k] : 1.0);
+                Cs[e] = v;
+            }
+            __syncthreads();
             for (int i0 = 0; i0 < ns; i0 += PF) {
 #pragma unroll
                 for (int u = 0; u < PF; ++u) {
