@@ -164,6 +164,15 @@ def run_forms(ctx, f, d, t_fp64, args):
                      "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
         log(f"form {name}: {t:.3f}s (fp64 at inner tol {itol:g}: {t64:.3f}s) outer={info['outer_its'][0]} "
             f"pcg={info['inner_its'][0]}")
+    # BF16 Dirichlet preconditioner (49) under FP64 or FP32 operators (PCG needs only an SPD
+    # preconditioner; the interface solve keeps the operators' accuracy)
+    for name, prec, itol in (("fp64_bf16_preconditioner", ifeti.IFETI_FP64, 1e-11),
+                             ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6)):
+        ctx.set_options(precision=prec, md_precision=ifeti.IFETI_BF16_LOCAL)
+        t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
+        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
+                     "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
+        log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
     ctx.set_options()
     # interface block of Alg. 1: one application of (49) or of (47) in place of the interface PCG
     for name, block in (("interface_md_once", 1), ("interface_md_rom_once", 2)):

@@ -126,6 +126,9 @@ typedef struct {
                                many multi-preconditioned CG iterations per cell with the principal
                                inverses as the preconditioners (the first iteration is (46); later
                                blocks are made K_rr^(s)-conjugate to all earlier ones) */
+    int md_precision;       /* precision of the M̊_D^-1 contraction (49), an ifeti_precision, or -1 for
+                               the value of `precision`: e.g. FP32 operators with a BF16 preconditioner
+                               (PCG only needs the preconditioner to stay symmetric positive definite) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

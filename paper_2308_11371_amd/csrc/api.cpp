@@ -188,6 +188,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         REQ(opt->interface_block >= 0 && opt->interface_block <= 2, "interface_block must be 0, 1 or 2");
         c->opt.interface_block = opt->interface_block;
         c->opt.overlap_local = opt->overlap_local ? 1 : 0;
+        REQ(opt->md_precision >= -1 && opt->md_precision <= IFETI_BF16_LOCAL, "md_precision must be -1, 0, 1 or 2");
+        c->opt.md_precision = opt->md_precision;
         REQ(opt->local_iters >= 1 && opt->local_iters <= 8, "local_iters must be in [1, 8]");
         c->opt.local_iters = opt->local_iters;
         REQ(opt->true_operator == 0 || opt->true_operator == 1, "true_operator must be 0 or 1");

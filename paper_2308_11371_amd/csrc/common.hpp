@@ -120,6 +120,7 @@ struct Options {
     int interface_block = 0;    // Alg. 1 interface block: 0 PCG on (48), 1 one M̊_D^-1 (49), 2 one M̊_D^-ROM (47)
     int overlap_local = 0;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
     int local_iters = 1;        // > 1: K̊^-MPCG, multi-preconditioned CG local solves (Remark 6)
+    int md_precision = -1;      // precision of the M̊_D^-1 contraction (49); -1: as `precision`
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -167,6 +168,7 @@ struct ifeti_ctx {
     hipStream_t side_stream = nullptr;   // second stream for the coarse path
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool side_pending = false;
+    int prec_override = -1;              // >= 0: precision of the contractions issued in the current scope
     hipStream_t local_stream = nullptr;  // third stream: reduced local solves beside the interface PCG
     hipEvent_t ev_local_fork = nullptr, ev_local_join = nullptr;
     ifeti::Options opt;

@@ -1016,14 +1016,15 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     }
     double abytes = 0.0;
     for (int i = 0; i < ngroups; ++i) abytes += 8.0 * (double)groups[i].K * M * groups[i].Kd;
-    const bool lp_path = lp_ok && c->opt.precision != IFETI_FP64 && M > 16 && Kdmax > 16;
+    const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
+    const bool lp_path = lp_ok && prec != IFETI_FP64 && M > 16 && Kdmax > 16;
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
     // large operators, or many columns (a block of load cases): row-owning waves, fragment units
     const bool lp_big = lp_path && ((!frag_small && M >= 512) || (M >= 64 && ncols >= 16384));
     if (lp_path) {
         GemmArgsFragLP f{};
-        const int kind = c->opt.precision;
+        const int kind = prec;
         const bool bf = kind == IFETI_BF16_LOCAL;
         for (int i = 0; i < ngroups; ++i) {
             f.Af[i] = frag_copy_lp(c, groups[i].A, M, groups[i].Kd, groups[i].K, kind);

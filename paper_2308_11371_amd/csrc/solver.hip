@@ -388,7 +388,8 @@ int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, doub
         const void *bufs[] = {lam, r, z, p, q, st, ist, pa, pb, pc, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p,
                               c->w_yP.p, c->co.w_symP.p, c->w_split.p, c->w_Lam.p, c->side_stream, c->stream};
         for (const void *b : bufs) key.push_back((uintptr_t)b);
-        for (long long v : {(long long)nrhs, (long long)c->opt.precision, c->rom_gen, (long long)nblk,
+        for (long long v : {(long long)nrhs, (long long)c->opt.precision, (long long)c->opt.md_precision, c->rom_gen,
+                            (long long)nblk,
                             (long long)exact})
             key.push_back((uintptr_t)v);
         double tv = tol;

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32),
                 ("timing_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int), ("interface_block", ctypes.c_int),
-                ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int)]
+                ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int), ("md_precision", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -189,10 +189,10 @@ class Context:
 
     def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
                     timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
-                    interface_block=0, overlap_local=0, local_iters=1):
+                    interface_block=0, overlap_local=0, local_iters=1, md_precision=-1):
         o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
                     timing_every, use_graph, autotune, coarse_parts, true_operator, interface_block, overlap_local,
-                    local_iters)
+                    local_iters, md_precision)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
 
     def stats(self) -> dict:

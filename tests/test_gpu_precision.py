@@ -77,3 +77,24 @@ def test_refined_solve_matches_fp64_oracle(pair, prec, inner):
         assert err < 1e-6
     finally:
         ctx.set_options(precision=ifeti.IFETI_FP64)
+
+
+@pytest.mark.parametrize("prec,inner", [("fp64", 1e-11), ("fp32", 1e-6)])
+def test_bf16_preconditioner_refined_solve(pair, prec, inner):
+    """BF16 Dirichlet preconditioner (49) under FP64 or FP32 operators: PCG needs only a symmetric
+    positive definite preconditioner, and the outer FP64 FGMRES reaches the FP64 oracle's solution."""
+    from paper_2308_11371_amd import ifeti
+    prob, m, ctx = pair
+    ro = m.solve(tol=1e-12, inner_tol=1e-13)
+    p = {"fp64": ifeti.IFETI_FP64, "fp32": ifeti.IFETI_FP32_LOCAL}[prec]
+    ctx.set_options(precision=p, md_precision=ifeti.IFETI_BF16_LOCAL)
+    try:
+        f, d = ctx.get_rhs()
+        u, lam, info = ctx.solve(f, d, tol=1e-10, inner_tol=inner, maxit=100)
+        err = rel(u.cpu().numpy(), ro["u"])
+        print(f"{prec} + bf16 M_D: outer {info['outer_its'][0]} relres {info['relres'][0]:.1e} u err {err:.2e}")
+        assert info["relres"][0] <= 1e-10
+        assert err < 1e-6
+    finally:
+        ctx.set_options(precision=ifeti.IFETI_FP64)
+
