@@ -302,9 +302,14 @@ def run_c3(args):
     f, d = ctx.get_rhs()
     f = f[:s.nU].contiguous()
     d = d[:s.L].contiguous()
-    for name, prec, itol in (("fp64_plain", ifeti.IFETI_FP64, 1e-11), ("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6),
-                             ("bf16_local", ifeti.IFETI_BF16_LOCAL, 1e-3)):
-        ctx.set_options(precision=prec, pcg_maxit=200, autotune=1)  # tiles tuned in the untimed warm-up
+    B16 = ifeti.IFETI_BF16_LOCAL
+    for name, prec, itol, mdp in (("fp64_plain", ifeti.IFETI_FP64, 1e-11, -1),
+                                  ("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6, -1),
+                                  ("bf16_local", B16, 1e-3, -1),
+                                  ("fp64_bf16_preconditioner", ifeti.IFETI_FP64, 1e-11, B16),
+                                  ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6, B16)):
+        # tiles tuned in the untimed warm-up
+        ctx.set_options(precision=prec, md_precision=mdp, pcg_maxit=200, autotune=1)
         t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
         out[name] = {"solve_time_s": t, "outer_its": int(info["outer_its"][0]), "pcg_its": int(info["inner_its"][0]),
                      "relres": float(info["relres"][0]), "inner_tol": itol}
