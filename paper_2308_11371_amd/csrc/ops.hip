@@ -1381,7 +1381,9 @@ void op_gather(ifeti_ctx *c, const double *lam, long long lam_rs, double *Lam, i
                        Lam, c->N, c->n_d, nrhs, weights ? 1 : 0);
 }
 
-int dot_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(1024, (n + 1023) / 1024)); }
+// blocks of 512 entries for the interface-vector kernels: enough workgroups to keep the gathers and
+// streams in flight, few enough partial sums for every block of the next kernel to add them up
+int dot_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(2048, (n + 511) / 512)); }
 
 void op_scatter(ifeti_ctx *c, const double *Y, int y_ld, int y_off, long long y_rs, double *out, long long out_rs,
                 int nrhs, bool weights, const double *dot_w, double *dot_part, const double *Y2) {
