@@ -1597,9 +1597,15 @@ void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double
     GemmGroup g;  // D-scaled B_d^T r fused into the staging
     g.A = c->Sdd.p; g.X = r; g.xbs = c->L; g.gcodes = c->g_gather.p; g.gw = c->g_Dw.p; g.coef = c->alpha.p;
     g.Kd = nd; g.K = K;
-    c->prec_override = c->opt.md_precision;  // the preconditioner's own precision, if set
-    gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false, 0, "MD_gemm");
-    c->prec_override = -1;
+    {
+        // the preconditioner's own precision, if set (restored also when the contraction throws)
+        struct Scope {
+            ifeti_ctx *c;
+            ~Scope() { c->prec_override = -1; }
+        } scope{c};
+        c->prec_override = c->opt.md_precision;
+        gemm(c, &g, 1, c->w_Y.p, nd, 0, nd, N * nrhs, false, 0, "MD_gemm");
+    }
     op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, true, dot_w, dot_part);
     c->applies[IFETI_OP_MD] += nrhs;
     IFETI_HIP(hipGetLastError());

@@ -536,10 +536,14 @@ static int apply_prec(ifeti_ctx *c, const double *in, double *out, int nrhs, dou
         }
         IFETI_HIP(hipEventRecord(c->ev_local_fork, s));
         IFETI_HIP(hipStreamWaitEvent(c->local_stream, c->ev_local_fork, 0));
+        struct Scope {  // the main stream is restored also when the local solve throws
+            ifeti_ctx *c;
+            hipStream_t s;
+            ~Scope() { c->stream = s; }
+        } scope{c, s};
         c->stream = c->local_stream;
         op_rom_local(c, t_u.p, nU, t_u2.p, nU, nrhs);
         IFETI_HIP(hipEventRecord(c->ev_local_join, c->local_stream));
-        c->stream = s;
     }
     apply_U(c, t_u.p, t_L2.p, nrhs);                                      // Ů v
     hipLaunchKernelGGL(k_sub, dim3(nblocks(L * nrhs)), dim3(kB), 0, s, t_L.p, L, t_L2.p, L, t_L.p, L, L, nrhs,
