@@ -107,3 +107,25 @@ def test_largest_reduced_basis_matches_oracle():
     with pytest.raises(ifeti.IfetiError):
         ifeti.setup(latticegen.tiny(2, (8, 6), 4, amp=0.15, width=("uniform", 0.15, 0.30, 9), smooth=True,
                                     n_principal=41))
+
+
+@pytest.mark.parametrize("shape,K", [((1, 1), 1), ((4, 1), 2), ((1, 3), 1)])
+def test_degenerate_lattices_match_direct(shape, K):
+    """A single cell (no interface multipliers, only Dirichlet rows), one-cell-wide strips, and a
+    single principal cell: the solve reaches the direct solution of the conforming problem."""
+    _cuda()
+    from oracle import Model
+    from oracle.direct import conforming_solve
+    from paper_2308_11371_amd import ifeti
+    prob = latticegen.tiny(2, shape, 3, n_principal=K)
+    m = Model(prob)
+    m.build_reduced_basis()
+    ctx = ifeti.setup(prob, principal_in=m.sigma)
+    try:
+        f, d = ctx.get_rhs()
+        u, lam, info = ctx.solve(f[:m.nU].contiguous(), d[:m.L].contiguous(), tol=1e-12, inner_tol=1e-13, maxit=80)
+        ref = conforming_solve(m)
+        assert info["relres"][0] < 1e-11
+        assert rel(host(u), ref["u"]) < 1e-9
+    finally:
+        ctx.close()
