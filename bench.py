@@ -167,7 +167,8 @@ def run_forms(ctx, f, d, t_fp64, args):
     # BF16 Dirichlet preconditioner (49) under FP64 or FP32 operators (PCG needs only an SPD
     # preconditioner; the interface solve keeps the operators' accuracy)
     for name, prec, itol in (("fp64_bf16_preconditioner", ifeti.IFETI_FP64, 1e-11),
-                             ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6)):
+                             ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6),
+                             ("fp32_bf16_preconditioner_inner_1e-3", ifeti.IFETI_FP32_LOCAL, 1e-3)):
         ctx.set_options(precision=prec, md_precision=ifeti.IFETI_BF16_LOCAL)
         t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
         res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
