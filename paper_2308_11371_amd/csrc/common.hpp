@@ -132,7 +132,9 @@ struct CoarseRow {
 // Direct solver of an assembled coarse problem S_PP (banded in the lexicographic vertex order).
 struct CoarseSolver {
     std::vector<double> h_Sband;  // lower band before factorisation, [i][i-j], width bw+1
+    std::vector<double> h_bandL;  // its Cholesky factor in the same band form
     int bw = 0;
+    bool inv_ready = false;       // explicit inverse built (on first use by a path that reads it)
     DevBuf<double> SPPinv;        // [nP][nP] explicit inverse
     DevBuf<double> SPPt;          // its lower-triangle 64x64 tiles, tile (I, J), I >= J, at I(I+1)/2 + J, row-major
     DevBuf<int> sym_tiles;        // [tile] -> (I, J)
@@ -327,6 +329,7 @@ void launch_stiffness(ifeti_ctx *c);
 int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in,
                   std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
 void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw);
+void ensure_coarse_inverse(ifeti_ctx *c, CoarseSolver &co);
 void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co);
 // trace tables Psi [2 npair + K][n_snap] of eq. (42) from the principal K_rr^-1 [k][n_r][n_r] and
 // U_rp^T [k][n_p][n_r] on the device

@@ -596,7 +596,8 @@ void build_exact(ifeti_ctx *c) {
     c->co_ex.h_Sband = band;
     c->co_ex.bw = bw;
     if (nP > 0) {
-        coarse_inverse_device(c, c->co_ex, band_cholesky_device(c, band, nP, bw), bw);
+        c->co_ex.h_bandL = band_cholesky_device(c, band, nP, bw);  // explicit inverse on first use
+        c->co_ex.inv_ready = false;
         build_coarse_partition(c, c->co_ex);
     }
     IFETI_HIP(hipStreamSynchronize(c->stream));

@@ -595,6 +595,15 @@ void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<dou
     co.sym_tiles.upload(tl, c->stream);
     co.w_symP.alloc(ntiles * 3 * 128);  // up to 3 load cases per pass
     IFETI_HIP(hipStreamSynchronize(c->stream));
+    co.inv_ready = true;
+}
+
+// The explicit inverse serves the symmetric-tile solve and the many-load-case contraction only; the
+// partitioned solve needs the band alone, so the inverse is built the first time a path reads it.
+void ensure_coarse_inverse(ifeti_ctx *c, CoarseSolver &co) {
+    if (co.inv_ready) return;
+    IFETI_REQUIRE(!c->capturing, IFETI_EINVAL, "coarse inverse must exist before graph capture");
+    coarse_inverse_device(c, co, co.h_bandL, co.bw);
 }
 
 }  // namespace ifeti

@@ -1482,7 +1482,10 @@ void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_r
     if (c->nP == 0) return;
     if (nrhs < 4 && co.cp_p >= 2) {
         coarse_partitioned(c, co, z, z_rs, y, y_rs, nrhs, scale);
-    } else if (nrhs < 4) {
+        return;
+    }
+    ensure_coarse_inverse(c, co);
+    if (nrhs < 4) {
         const double n = (double)c->nP, nt = (double)co.nT * (co.nT + 1) / 2;
         {
             // algorithmic: the symmetric operator's n(n+1)/2 entries read once, the vectors, the partials

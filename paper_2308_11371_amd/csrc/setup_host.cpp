@@ -892,9 +892,9 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     IFETI_HIP(hipStreamSynchronize(c->stream));
     c->free_copies();  // the bank was (re)built: every fragment-ordered copy is stale
     clk.mark("bank upload");
-    // 7. explicit coarse inverse S̊_PP^-1 from the banded factor (device)
-    coarse_inverse_device(c, c->co, band, bw);
-    clk.mark("coarse inverse");
+    // 7. coarse solve: the band factor is kept; the explicit inverse S̊_PP^-1 follows on first use
+    c->co.h_bandL = band;  // the explicit inverse is built on first use
+    c->co.inv_ready = false;
     build_coarse_partition(c, c->co);
     clk.mark("coarse partition");
     IFETI_HIP(hipStreamSynchronize(c->stream));
