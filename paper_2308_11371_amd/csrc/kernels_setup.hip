@@ -290,40 +290,68 @@ __global__ __launch_bounds__(kBlock) void k_gs_update(double *__restrict__ A, lo
     }
 }
 
-// Row j of (L L^T)^-1 (= column j, the inverse is symmetric) for a banded lower factor
-// band[i*(bw+1) + (i-k)] = L[i][k]: one single-wave workgroup per j, the solution vector in LDS
-// (dynamic, n doubles), the lanes spread over the band of each substitution step and a fixed
-// butterfly per step.
-__global__ __launch_bounds__(64) void k_band_inverse(const double *__restrict__ band, int n, int bw,
+// Columns of (L L^T)^-1 for a banded lower factor band[i*(bw+1) + (i-k)] = L[i][k]: one wave per
+// CPW = 64/S consecutive columns j, S lanes per column splitting the band dot product of each
+// substitution step (fixed butterfly over the S lanes), the column's last bw entries in an LDS ring
+// of W > bw slots.  Forward L y = e_j from row j0 of the wave's first column (entries above a
+// column's own j stay zero), then backward L^T x = y over all rows.  Entries are stored as rows of
+// X (X[i][j]; the inverse is symmetric), so the lanes of a step write contiguous entries.
+template <int S>
+__global__ __launch_bounds__(64) void k_band_inverse(const double *__restrict__ band, int n, int bw, int W,
                                                      double *__restrict__ X) {
-    extern __shared__ double x[];
-    const int j = blockIdx.x, lane = threadIdx.x;
+    constexpr int CPW = 64 / S;
+    extern __shared__ double ring_all[];
+    const int lane = threadIdx.x, cl = lane / S, sl = lane % S;
+    const int j0 = blockIdx.x * CPW, j = j0 + cl;
+    const bool valid = j < n;
+    double *ring = ring_all + (size_t)cl * W;
     const int ld = bw + 1;
-    for (int i = lane; i < n; i += 64) x[i] = 0.0;
+    for (int e = sl; e < W; e += S) ring[e] = 0.0;
     __syncthreads();
-    // forward: L y = e_j (rows above j stay 0)
-    for (int i = j; i < n; ++i) {
+    for (int i = j0; i < n; ++i) {  // forward
         const double *Li = band + (size_t)i * ld;
+        const int klo = max(0, i - bw) + sl;
+        int pos = klo % W;
         double t = 0.0;
-        for (int k = max(j, i - bw) + lane; k < i; k += 64) t += Li[i - k] * x[k];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-        const double v = ((i == j ? 1.0 : 0.0) - t) / Li[0];
-        __syncthreads();  // every lane has read x[] for this step
-        if (lane == 0) x[i] = v;
+#pragma unroll 8
+        for (int k = klo; k < i; k += S) {  // unrolled: the band loads of several terms in flight
+            t += Li[i - k] * ring[pos];
+            pos += S;
+            if (pos >= W) pos -= W;
+        }
+#pragma unroll
+        for (int off = S / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const double v = ((valid && i == j ? 1.0 : 0.0) - t) / Li[0];
+        __syncthreads();  // every lane has read the ring for this step
+        if (sl == 0) {
+            ring[i % W] = v;
+            if (valid) X[(size_t)i * n + j] = v;
+        }
         __syncthreads();
     }
-    // backward: L^T x = y
-    for (int i = n - 1; i >= 0; --i) {
+    for (int e = sl; e < W; e += S) ring[e] = 0.0;
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {  // backward
+        const int khi = min(n - 1, i + bw);
+        int pos = (i + 1 + sl) % W;
         double t = 0.0;
-        const int k1 = min(n - 1, i + bw);
-        for (int k = i + 1 + lane; k <= k1; k += 64) t += band[(size_t)k * ld + (k - i)] * x[k];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-        const double v = (x[i] - t) / band[(size_t)i * ld];
+#pragma unroll 8
+        for (int k = i + 1 + sl; k <= khi; k += S) {
+            t += band[(size_t)k * ld + (k - i)] * ring[pos];
+            pos += S;
+            if (pos >= W) pos -= W;
+        }
+#pragma unroll
+        for (int off = S / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+        const double y = (valid && i >= j) ? X[(size_t)i * n + j] : 0.0;  // zero above j (not written forward)
+        const double v = (y - t) / band[(size_t)i * ld];
         __syncthreads();
-        if (lane == 0) x[i] = v;
+        if (sl == 0) {
+            ring[i % W] = v;
+            if (valid) X[(size_t)i * n + j] = v;
+        }
         __syncthreads();
     }
-    for (int i = lane; i < n; i += 64) X[(size_t)j * n + i] = x[i];
 }
 
 // Trace tables of eq. (42) at quadrature point eq = blockIdx.x (the lookup-table form of eqs. (52)-(54)).
@@ -573,11 +601,14 @@ void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<dou
     DevBuf<double> band;
     band.upload(band_L, c->stream);
     co.SPPinv.alloc((size_t)c->nP * c->nP);
-    const size_t lds = (size_t)c->nP * sizeof(double);
-    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "coarse problem too large for the LDS");
-    IFETI_HIP(hipFuncSetAttribute((const void *)k_band_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_band_inverse, dim3(c->nP), dim3(64), (size_t)c->nP * sizeof(double), c->stream, band.p, c->nP,
-                       bw, co.SPPinv.p);
+    constexpr int S = 16, CPW = 64 / S;  // ~n/4 single-wave workgroups: several per compute unit
+    const int W = std::max(bw + 1, S + 1) | 1;  // ring slots: more than the band and than S, odd
+    const size_t lds = (size_t)CPW * W * sizeof(double);
+    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "coarse band too wide for the LDS");
+    IFETI_HIP(hipFuncSetAttribute((const void *)k_band_inverse<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    hipLaunchKernelGGL(k_band_inverse<S>, dim3((c->nP + CPW - 1) / CPW), dim3(64), lds, c->stream, band.p, c->nP, bw,
+                       W, co.SPPinv.p);
     IFETI_HIP(hipGetLastError());
     const int nT = (c->nP + 63) / 64;
     const size_t ntiles = (size_t)nT * (nT + 1) / 2;
