@@ -82,20 +82,6 @@ std::vector<double> band_chol(const Band &A, int lo, int m) {
     return L;
 }
 
-// x <- (L L^T)^-1 x for a banded factor of order m
-void band_solve(const std::vector<double> &L, int m, int bw, double *x) {
-    for (int i = 0; i < m; ++i) {
-        double t = x[i];
-        for (int k = std::max(0, i - bw); k < i; ++k) t -= L[(size_t)i * (bw + 1) + (i - k)] * x[k];
-        x[i] = t / L[(size_t)i * (bw + 1)];
-    }
-    for (int i = m - 1; i >= 0; --i) {
-        double t = x[i];
-        for (int k = i + 1; k <= std::min(m - 1, i + bw); ++k) t -= L[(size_t)k * (bw + 1) + (k - i)] * x[k];
-        x[i] = t / L[(size_t)i * (bw + 1)];
-    }
-}
-
 struct Layout {
     int p = 0, ns = 0;
     std::vector<int> lo, hi;  // interior block i = [lo, hi); separator j = [hi[j], lo[j+1])
@@ -157,15 +143,8 @@ void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co) {
     std::vector<std::vector<double>> Ainv(p), EL(p), ER(p);
     for (int i = 0; i < p; ++i) {
         const int lo = best.lo[i], m = best.hi[i] - lo;
-        const std::vector<double> L = band_chol(A, lo, m);
         std::vector<double> &X = Ainv[i];
-        X.assign((size_t)m * m, 0.0);
-        par_for(m, [&](int col) {
-            std::vector<double> e(m, 0.0);
-            e[col] = 1.0;
-            band_solve(L, m, bw, e.data());
-            for (int r = 0; r < m; ++r) X[(size_t)r * m + col] = e[r];
-        });
+        X = band_inverse_device(c, band_chol(A, lo, m), m, bw);
         for (int r = 0; r < m; ++r)  // symmetrise
             for (int q = r + 1; q < m; ++q) {
                 const double v = 0.5 * (X[(size_t)r * m + q] + X[(size_t)q * m + r]);
@@ -231,14 +210,7 @@ void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co) {
     for (int a = 0; a < ns; ++a)
         for (int d = 0; d <= std::min(sbw, a); ++d) Sb[(size_t)a * (sbw + 1) + d] = S[(size_t)a * ns + a - d];
     const Band SB{Sb, ns, sbw};
-    const std::vector<double> LS = band_chol(SB, 0, ns);
-    std::vector<double> Sinv((size_t)ns * ns, 0.0);
-    par_for(ns, [&](int col) {
-        std::vector<double> e(ns, 0.0);
-        e[col] = 1.0;
-        band_solve(LS, ns, sbw, e.data());
-        for (int r = 0; r < ns; ++r) Sinv[(size_t)r * ns + col] = e[r];
-    });
+    std::vector<double> Sinv = band_inverse_device(c, band_chol(SB, 0, ns), ns, sbw);
     for (int a = 0; a < ns; ++a)
         for (int b = a + 1; b < ns; ++b) {
             const double v = 0.5 * (Sinv[(size_t)a * ns + b] + Sinv[(size_t)b * ns + a]);

@@ -330,6 +330,8 @@ int greedy_device(ifeti_ctx *c, int n_principal, double tol_rb, const int *princ
                   std::vector<int> &sigma, std::vector<double> &beta, std::vector<double> &norms);
 void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw);
 void ensure_coarse_inverse(ifeti_ctx *c, CoarseSolver &co);
+// (L L^T)^-1 as a dense row-major n x n host array, from a banded lower factor L[i][i-j] (width bw+1)
+std::vector<double> band_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int n, int bw);
 void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co);
 // trace tables Psi [2 npair + K][n_snap] of eq. (42) from the principal K_rr^-1 [k][n_r][n_r] and
 // U_rp^T [k][n_p][n_r] on the device

@@ -597,19 +597,35 @@ void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *
     IFETI_HIP(hipStreamSynchronize(c->stream));  // the pair tables are released on return
 }
 
+// (L L^T)^-1 into X [n][n] from a banded lower factor on the device
+static void launch_band_inverse(ifeti_ctx *c, const double *band, int n, int bw, double *X) {
+    constexpr int S = 16, CPW = 64 / S;  // ~n/4 single-wave workgroups: several per compute unit
+    const int W = std::max(bw + 1, S + 1) | 1;  // ring slots: more than the band and than S, odd
+    const size_t lds = (size_t)CPW * W * sizeof(double);
+    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "band too wide for the LDS of the band inverse");
+    IFETI_HIP(hipFuncSetAttribute((const void *)k_band_inverse<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    hipLaunchKernelGGL(k_band_inverse<S>, dim3((n + CPW - 1) / CPW), dim3(64), lds, c->stream, band, n, bw, W, X);
+    IFETI_HIP(hipGetLastError());
+}
+
+std::vector<double> band_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int n, int bw) {
+    std::vector<double> out;
+    if (n == 0) return out;
+    DevBuf<double> band, X;
+    band.upload(band_L, c->stream);
+    X.alloc((size_t)n * n);
+    launch_band_inverse(c, band.p, n, bw, X.p);
+    X.download(out, c->stream);
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    return out;
+}
+
 void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<double> &band_L, int bw) {
     DevBuf<double> band;
     band.upload(band_L, c->stream);
     co.SPPinv.alloc((size_t)c->nP * c->nP);
-    constexpr int S = 16, CPW = 64 / S;  // ~n/4 single-wave workgroups: several per compute unit
-    const int W = std::max(bw + 1, S + 1) | 1;  // ring slots: more than the band and than S, odd
-    const size_t lds = (size_t)CPW * W * sizeof(double);
-    IFETI_REQUIRE(lds <= 160 * 1024, IFETI_EINVAL, "coarse band too wide for the LDS");
-    IFETI_HIP(hipFuncSetAttribute((const void *)k_band_inverse<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
-    hipLaunchKernelGGL(k_band_inverse<S>, dim3((c->nP + CPW - 1) / CPW), dim3(64), lds, c->stream, band.p, c->nP, bw,
-                       W, co.SPPinv.p);
-    IFETI_HIP(hipGetLastError());
+    launch_band_inverse(c, band.p, c->nP, bw, co.SPPinv.p);
     const int nT = (c->nP + 63) / 64;
     const size_t ntiles = (size_t)nT * (nT + 1) / 2;
     co.nT = nT;
