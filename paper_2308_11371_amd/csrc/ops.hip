@@ -168,6 +168,48 @@ __global__ __launch_bounds__(64 * NWC) void k_restrict_c(const double *__restric
     }
 }
 
+// the same with one wave per column and n_p <= 8: the 8 per-lane partial sums go through LDS, lane
+// (i, g) adds the partials of row i held by lanes 8g..8g+7, and three butterfly steps over g finish
+template <int NPM>
+__global__ __launch_bounds__(64) void k_restrict_c1(const double *__restrict__ C, const int *__restrict__ gl,
+                                                    const double *__restrict__ lam, long long lam_rs, int N, int n_d,
+                                                    int n_p, int ncols, double *__restrict__ out) {
+    static_assert(NPM == 8, "one row per group of 8 lanes");
+    __shared__ double part[64][NPM + 1];
+    const int lane = threadIdx.x;
+    const int col = blockIdx.x;
+    const int rhs = col / N, s = col % N;
+    const double *l = lam + rhs * lam_rs;
+    const double *Cs = C + (size_t)s * n_p * n_d;
+    double acc[NPM];
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) acc[i] = 0.0;
+    for (int j = lane; j < n_d; j += 64) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int code = gl[((size_t)s * n_d + j) * 2 + u];
+            if (code == 0) continue;
+            const double x = l[(code > 0 ? code : -code) - 1];
+            v += code > 0 ? x : -x;
+        }
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (i < n_p) acc[i] += Cs[(size_t)i * n_d + j] * v;
+    }
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) part[lane][i] = acc[i];
+    __syncthreads();
+    const int i = lane >> 3, g = lane & 7;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v += part[8 * g + t][i];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    if (g == 0 && i < n_p) out[(size_t)col * n_p + i] = v;
+}
+
 // Y_s (+)= C_s^T y_P[A_p(s)] for column (rhs, s): one workgroup of NWC waves per
 // column, lanes over the cell's dual rows (coalesced rows of C_s); the n_p
 // primal values of the cell are uniform.
@@ -1543,7 +1585,9 @@ void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long lo
     Prof prof(c, tag, 2.0 * (double)cols * np * nd,
               8.0 * (double)N * np * nd + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
     if (np <= 8)
-        hipLaunchKernelGGL((k_restrict_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
+        // 2D: one wave per cell; its partial sums are reduced through LDS rather than by eight
+        // butterflies, which compete for the LDS pipe with the contraction running beside it
+        hipLaunchKernelGGL((k_restrict_c1<8>), dim3(cols), dim3(64), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
                            N, nd, np, cols, out);
     else
         // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
