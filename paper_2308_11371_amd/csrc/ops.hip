@@ -259,6 +259,35 @@ __global__ __launch_bounds__(kB) void k_assemble_primal(const int *__restrict__ 
     zP[rhs * z_rs + P] = b + sgn * v;
 }
 
+// the same for a fixed number of contributions per primal dof (2^dim): every pull entry and every
+// contribution is loaded before the first is added (two dependent loads per thread instead of
+// 2 MAXC), the sum taken in the same order; one wave per block spreads the few rows over more CUs
+template <int MAXC>
+__global__ __launch_bounds__(64) void k_assemble_primal_t(const int *__restrict__ pull, const double *__restrict__ cp,
+                                                          int N, int n_p, const double *__restrict__ base,
+                                                          long long b_rs, double sgn, double *__restrict__ zP,
+                                                          long long z_rs, int nP, int nrhs) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nP * nrhs) return;
+    int rhs = (int)(t / nP), P = (int)(t % nP);
+    int e[MAXC];
+#pragma unroll
+    for (int u = 0; u < MAXC; ++u) e[u] = pull[(size_t)P * MAXC + u];
+    bool live[MAXC];
+    double x[MAXC];
+#pragma unroll
+    for (int u = 0; u < MAXC; ++u) {
+        live[u] = e[u] >= 0 && (u == 0 || live[u - 1]);  // a list ends at its first negative entry
+        x[u] = live[u] ? cp[((size_t)rhs * N) * n_p + e[u]] : 0.0;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < MAXC; ++u)
+        if (live[u]) v += x[u];
+    double b = base ? base[rhs * b_rs + P] : 0.0;
+    zP[rhs * z_rs + P] = b + sgn * v;
+}
+
 __global__ __launch_bounds__(kB) void k_restrict_primal(const int *__restrict__ Ap, const double *__restrict__ xP,
                                                         long long x_rs, double *__restrict__ xp, int N, int n_p,
                                                         int nrhs) {
@@ -1450,8 +1479,16 @@ void op_assemble_primal(ifeti_ctx *c, const double *cp, const double *base, long
     if (n == 0) return;
     Prof prof(c, "assemble_primal", 0.0,
               8.0 * ((double)c->N * c->n_p * nrhs + (double)n * (base ? 2 : 1)) + 4.0 * (double)c->nP * c->maxc);
-    hipLaunchKernelGGL(k_assemble_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ppull.p, c->maxc, cp, c->N,
-                       c->n_p, base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
+    const unsigned nb64 = (unsigned)((n + 63) / 64);
+    if (c->maxc == 4)
+        hipLaunchKernelGGL(k_assemble_primal_t<4>, dim3(nb64), dim3(64), 0, c->stream, c->g_Ppull.p, cp, c->N, c->n_p,
+                           base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
+    else if (c->maxc == 8)
+        hipLaunchKernelGGL(k_assemble_primal_t<8>, dim3(nb64), dim3(64), 0, c->stream, c->g_Ppull.p, cp, c->N, c->n_p,
+                           base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
+    else
+        hipLaunchKernelGGL(k_assemble_primal, dim3(nblocks(n)), dim3(kB), 0, c->stream, c->g_Ppull.p, c->maxc, cp,
+                           c->N, c->n_p, base, b_rs, sgn, zP, z_rs, c->nP, nrhs);
 }
 
 void op_restrict_primal(ifeti_ctx *c, const double *xP, long long x_rs, double *xp, int nrhs) {
