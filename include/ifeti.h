@@ -89,7 +89,7 @@ typedef struct {
 
 typedef struct {
     int precision;          /* ifeti_precision of the principal contractions */
-    int pcg_check_every;    /* PCG host convergence check interval (>= 1)    */
+    int pcg_check_every;    /* PCG host convergence check interval (>= 1; default 2) */
     int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
     int pcg_maxit;          /* iteration cap of the interface PCG inside the preconditioner */
     int timing;             /* 1: time kernel launches with HIP events       */

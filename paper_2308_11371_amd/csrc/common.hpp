@@ -107,7 +107,7 @@ struct GemmGroup {
 
 struct Options {
     int precision = IFETI_FP64;
-    int pcg_check_every = 4;
+    int pcg_check_every = 2;
     int fgmres_restart = 60;
     int pcg_maxit = 1000;
     int timing = 0;

@@ -187,7 +187,7 @@ class Context:
         _check(self.lib.ifeti_get_sizes(self.h, ctypes.byref(s)))
         return s
 
-    def set_options(self, precision=IFETI_FP64, pcg_check_every=4, fgmres_restart=60, pcg_maxit=1000, timing=0,
+    def set_options(self, precision=IFETI_FP64, pcg_check_every=2, fgmres_restart=60, pcg_maxit=1000, timing=0,
                     timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
                     interface_block=0, overlap_local=0, local_iters=1, md_precision=-1):
         o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
