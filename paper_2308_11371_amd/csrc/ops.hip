@@ -222,6 +222,29 @@ __global__ __launch_bounds__(64 * NWC) void k_prolong_c(const double *__restrict
     const int rhs = col / N, s = col % N;
     const double *zP = yP + rhs * yP_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
+    double *Yc = Y + (size_t)col * n_d;
+    if (n_d <= 64 * NWC) {  // one row per thread: its C column and Y entry are loaded before the primal values
+        const int j = threadIdx.x;
+        const bool in = j < n_d;
+        double cv[NPM];
+#pragma unroll
+        for (int i = 0; i < NPM; ++i) cv[i] = (in && i < n_p) ? Cs[(size_t)i * n_d + j] : 0.0;
+        double v = (in && accumulate) ? Yc[j] : 0.0;
+        double ypv[NPM];
+#pragma unroll
+        for (int i = 0; i < NPM; ++i) {
+            ypv[i] = 0.0;
+            if (i < n_p) {
+                const int P = Ap[(size_t)s * n_p + i];
+                if (P >= 0) ypv[i] = zP[P];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (i < n_p) v += cv[i] * ypv[i];
+        if (in) Yc[j] = v;
+        return;
+    }
     double yp[NPM];
 #pragma unroll
     for (int i = 0; i < NPM; ++i) {
@@ -231,7 +254,6 @@ __global__ __launch_bounds__(64 * NWC) void k_prolong_c(const double *__restrict
             if (P >= 0) yp[i] = zP[P];
         }
     }
-    double *Yc = Y + (size_t)col * n_d;
     for (int j = threadIdx.x; j < n_d; j += 64 * NWC) {
         double v = accumulate ? Yc[j] : 0.0;
 #pragma unroll
