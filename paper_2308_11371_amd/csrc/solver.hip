@@ -88,6 +88,8 @@ __global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr
 
 // alpha = rho / p.q (breakdown if p.q <= 0 or not finite); lam += alpha p,
 // r -= alpha q; partial ||r||^2.  Reads slot 0, writes slot 1.
+constexpr int kPre = 2;  // interface-vector entries per thread loaded ahead of the partial sums
+
 __global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, double *__restrict__ r,
                                                  const double *__restrict__ p, const double *__restrict__ q,
                                                  long long n, long long rs, int nrhs, double *__restrict__ st,
@@ -99,6 +101,21 @@ __global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, doubl
     const int *i0s = ist + (size_t)rhs * I_N;
     double *s1 = st + ((size_t)nrhs + rhs) * S_N;
     int *i1s = ist + ((size_t)nrhs + rhs) * I_N;
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
+    const size_t base = (size_t)rhs * rs;
+    // the thread's first kPre entries are loaded before the partial sums are reduced (they do not
+    // depend on them), the rest in the loop below; every entry takes the same operations in order
+    double pr[kPre], pp[kPre], pqv[kPre], pl[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const long long t = j0 + threadIdx.x + (long long)u * kB;
+        const bool in = t < j1;
+        pr[u] = in ? r[base + t] : 0.0;
+        pp[u] = in ? p[base + t] : 0.0;
+        pqv[u] = in ? q[base + t] : 0.0;
+        pl[u] = in ? lam[base + t] : 0.0;
+    }
     const double pq = sum_partials(p_pq + (size_t)rhs * nblk, nblk, sh);
     int act = i0s[I_ACT], brk = i0s[I_BRK];
     double a = 0.0;
@@ -118,11 +135,21 @@ __global__ __launch_bounds__(kB) void k_pcg_step(double *__restrict__ lam, doubl
         i1s[I_ITER] = i0s[I_ITER];
         i1s[I_BRK] = brk;
     }
-    const long long chunk = (n + nblk - 1) / nblk;
-    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
-    const size_t base = (size_t)rhs * rs;
     double acc = 0.0;
-    for (long long t = j0 + threadIdx.x; t < j1; t += kB) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const long long t = j0 + threadIdx.x + (long long)u * kB;
+        if (t < j1) {
+            double rv = pr[u];
+            if (a != 0.0) {
+                lam[base + t] = pl[u] + a * pp[u];
+                rv -= a * pqv[u];
+                r[base + t] = rv;
+            }
+            acc += rv * rv;
+        }
+    }
+    for (long long t = j0 + threadIdx.x + (long long)kPre * kB; t < j1; t += kB) {
         double rv = r[base + t];
         if (a != 0.0) {
             lam[base + t] += a * p[base + t];
@@ -147,6 +174,17 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
     int *i0s = ist + (size_t)rhs * I_N;
     const double *s1 = st + ((size_t)nrhs + rhs) * S_N;
     const int *i1s = ist + ((size_t)nrhs + rhs) * I_N;
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
+    const size_t base = (size_t)rhs * rs;
+    double pz[kPre], pp[kPre];  // the thread's first kPre entries, loaded before the partial sums
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const long long t = j0 + threadIdx.x + (long long)u * kB;
+        const bool in = t < j1;
+        pz[u] = in ? z[base + t] : 0.0;
+        pp[u] = in ? p[base + t] : 0.0;
+    }
     const double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
     const double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
     const int it = i1s[I_ITER] + 1;  // this iteration's number, kept on the device (graph replays)
@@ -172,10 +210,13 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
         i0s[I_BRK] = i1s[I_BRK];
     }
     if (!act) return;
-    const long long chunk = (n + nblk - 1) / nblk;
-    const long long j0 = b * chunk, j1 = min(n, j0 + chunk);
-    const size_t base = (size_t)rhs * rs;
-    for (long long t = j0 + threadIdx.x; t < j1; t += kB) p[base + t] = z[base + t] + beta * p[base + t];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const long long t = j0 + threadIdx.x + (long long)u * kB;
+        if (t < j1) p[base + t] = pz[u] + beta * pp[u];
+    }
+    for (long long t = j0 + threadIdx.x + (long long)kPre * kB; t < j1; t += kB)
+        p[base + t] = z[base + t] + beta * p[base + t];
 }
 
 __global__ __launch_bounds__(kB) void k_copy(const double *__restrict__ x, double *__restrict__ y, long long n) {
