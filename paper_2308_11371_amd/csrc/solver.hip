@@ -59,6 +59,32 @@ __device__ inline double sum_partials(const double *part, int nblk, double *sh) 
     return block_reduce(acc, sh);
 }
 
+// two sums of partials through one reduction tree (the same order per sum as sum_partials, half
+// the barriers); both partial sets are loaded before the first addition
+__device__ inline void sum_partials2(const double *pa, const double *pb, int nblk, double *sh2, double &a,
+                                     double &b) {
+    double x = 0.0, y = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kB) {
+        const double u = pa[k], v = pb[k];
+        x += u;
+        y += v;
+    }
+    const int tid = threadIdx.x;
+    sh2[tid] = x;
+    sh2[kB + tid] = y;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            sh2[tid] += sh2[tid + off];
+            sh2[kB + tid] += sh2[kB + tid + off];
+        }
+        __syncthreads();
+    }
+    a = sh2[0];
+    b = sh2[kB];
+    __syncthreads();
+}
+
 // stage 0: r0 = ||r||, rho = r.z
 __global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr, const double *__restrict__ p_rz,
                                                  int nblk, double *__restrict__ st, int *__restrict__ ist) {
@@ -168,7 +194,7 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
                                                  long long rs, int nrhs, double *__restrict__ st,
                                                  int *__restrict__ ist, const double *__restrict__ p_rr,
                                                  const double *__restrict__ p_rz, int nblk, double tol) {
-    __shared__ double sh[kB];
+    __shared__ double sh[2 * kB];
     const int b = blockIdx.x, rhs = blockIdx.y;
     double *s0 = st + (size_t)rhs * S_N;
     int *i0s = ist + (size_t)rhs * I_N;
@@ -185,8 +211,8 @@ __global__ __launch_bounds__(kB) void k_pcg_next(double *__restrict__ p, const d
         pz[u] = in ? z[base + t] : 0.0;
         pp[u] = in ? p[base + t] : 0.0;
     }
-    const double rr = sum_partials(p_rr + (size_t)rhs * nblk, nblk, sh);
-    const double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
+    double rr, rz;
+    sum_partials2(p_rr + (size_t)rhs * nblk, p_rz + (size_t)rhs * nblk, nblk, sh, rr, rz);
     const int it = i1s[I_ITER] + 1;  // this iteration's number, kept on the device (graph replays)
     int act = i1s[I_ACT], its = i1s[I_IT];
     double rel = s1[S_REL], rho = s1[S_RHO], beta = 0.0;
