@@ -155,7 +155,7 @@ def run_forms(ctx, f, d, t_fp64, args):
     for name, prec, itol in (("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6), ("bf16_local", ifeti.IFETI_BF16_LOCAL, 1e-3)):
         # FP64 at the same (looser) inner tolerance: separates the gain of the narrow contractions from
         # that of the looser inner solve
-        ctx.set_options()
+        ctx.reset_options()
         t64, _ = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
         ctx.set_options(precision=prec)
         t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
@@ -174,7 +174,7 @@ def run_forms(ctx, f, d, t_fp64, args):
         res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
                      "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
         log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
-    ctx.set_options()
+    ctx.reset_options()
     # interface block of Alg. 1: one application of (49) or of (47) in place of the interface PCG
     for name, block in (("interface_md_once", 1), ("interface_md_rom_once", 2)):
         ctx.set_options(interface_block=block, fgmres_restart=200)
@@ -182,7 +182,7 @@ def run_forms(ctx, f, d, t_fp64, args):
         res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
                      "relres": float(info["relres"][0])}
         log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]}")
-    ctx.set_options()
+    ctx.reset_options()
     # K̊^-MPCG (Remark 6): multi-preconditioned CG local solves, two and three iterations each
     for it in (2, 3):
         ctx.set_options(local_iters=it)
@@ -190,7 +190,7 @@ def run_forms(ctx, f, d, t_fp64, args):
         res[f"mpcg_local_{it}"] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
                                    "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0])}
         log(f"form mpcg_local_{it}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
-    ctx.set_options()
+    ctx.reset_options()
     res["true_operator"] = run_true_operator(ctx)
     prob = latticegen.make("c4")
     c4 = ifeti.setup(prob)
@@ -233,7 +233,7 @@ def run_true_operator(ctx, reps=10):
         gb = k["bytes"] / k["launches"] / 1e9
         out["stencil" if mode == 0 else "matrix_free"] = {"kernel": tag, "us_per_apply": us,
                                                           "algorithmic_gb": gb, "tb_per_s": gb / us * 1e3}
-    ctx.set_options()
+    ctx.reset_options()
     log(f"true operator: stencil {out['stencil']['us_per_apply']:.1f} us, "
         f"matrix-free {out['matrix_free']['us_per_apply']:.1f} us")
     return out
@@ -267,7 +267,7 @@ def run_exact(ctx, f, d, t_rom, args, maxit=2000,
     torch.cuda.synchronize()
     out["solve_time_s"] = time.perf_counter() - t0
     st = ctx.stats()
-    ctx.set_options()
+    ctx.reset_options()
     out["pcg_its"] = int(info["iters"][0])
     out["pcg_relres"] = float(info["relres"][0])
     x = torch.cat([u, lam])
@@ -317,7 +317,7 @@ def run_c3(args):
         if name != "fp64_plain":
             out[name]["vs_fp64"] = t / out["fp64_plain"]["solve_time_s"]
         log(f"form c3 {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
-    ctx.set_options()
+    ctx.reset_options()
     out["true_operator"] = run_true_operator(ctx)
     if not args.no_exact:
         out["exact_fetidp"] = run_exact(ctx, f, d, out["fp64_plain"]["solve_time_s"], args, maxit=5000,

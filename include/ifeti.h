@@ -69,12 +69,18 @@ typedef struct {
     int n_el;               /* elements per direction per cell               */
     int degree;             /* spline degree; 2 is supported                 */
     double h;               /* cell size of the reference lattice            */
-    double E_in, E_out;     /* Young modulus inside / outside the struts     */
+    double E_in, E_out;     /* Young modulus inside (> 0) / outside (>= 0; 0 leaves voids, whose cells
+                               may be singular: ENOTSPD from the factorisations) the struts */
     double nu;              /* Poisson ratio                                 */
     double smooth_eps;      /* 0: sharp strut indicator; > 0: tanh width     */
-    int dirichlet_mask;     /* bit f set: face f clamped (u = 0); faces
-                               0:X=0 1:X=Lx 2:Y=0 3:Y=Ly 4:Z=0 5:Z=Lz       */
+    int dirichlet_mask;     /* bit f set: face f carries Dirichlet data u = u0;
+                               faces 0:X=0 1:X=Lx 2:Y=0 3:Y=Ly 4:Z=0 5:Z=Lz   */
     int load_face;          /* face carrying the constant traction, -1: none */
+    double u0_grad[9];      /* Dirichlet data (3c): u0(x) = G x at the control points of the Dirichlet
+                               faces, G row-major dim x dim (first dim*dim entries); all zero: clamped.
+                               Dual dofs on the faces take u0 through their +1 rows of B (d of eq. (14));
+                               primal corners on the faces are eliminated from u_P and their values
+                               lifted into f (f -= K u0 on those columns) by ifeti_build_cells */
 } ifeti_lattice_desc;
 
 typedef struct {
@@ -129,6 +135,10 @@ typedef struct {
     int md_precision;       /* precision of the M̊_D^-1 contraction (49), an ifeti_precision, or -1 for
                                the value of `precision`: e.g. FP32 operators with a BF16 preconditioner
                                (PCG only needs the preconditioner to stay symmetric positive definite) */
+    int tile_candidate;     /* -1: tile shapes of the principal contractions by default or by the autotuner;
+                               i >= 0: candidate i of each contraction's family (modulo the family's
+                               size), for every launch; the autotuner is bypassed.  Each candidate sums
+                               in its own fixed order (results agree across candidates to rounding) */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts
@@ -167,6 +177,8 @@ void ifeti_destroy(ifeti_ctx *ctx);
 const char *ifeti_last_error(void);
 int ifeti_get_sizes(const ifeti_ctx *ctx, ifeti_sizes *out);
 int ifeti_set_options(ifeti_ctx *ctx, const ifeti_options *opt);
+/* Current options of the context (all fields), e.g. to change one field and set them back. */
+int ifeti_get_options(const ifeti_ctx *ctx, ifeti_options *out);
 
 /* Assemble every cell (Sec. 4.2.1, eq. (52)): pulled-back material tensor at
  * the 3^d Gauss points of each element (the greedy snapshots), cell
@@ -179,7 +191,8 @@ int ifeti_set_options(ifeti_ctx *ctx, const ifeti_options *opt);
 int ifeti_build_cells(ifeti_ctx *ctx, const double *ctrl_pts, const double *widths,
                       const double *tractions, int nrhs);
 
-/* Right-hand side of (16): f (dev, nU x nrhs) and d (dev, L x nrhs). */
+/* Right-hand side of (16): f (dev, nU x nrhs) and d (dev, L x nrhs); with Dirichlet data u0 != 0
+ * f includes the lifting of the Dirichlet corners and d holds u0 on the Dirichlet rows. */
 int ifeti_get_rhs(ifeti_ctx *ctx, double *f, double *d);
 
 /* Offline phase (Sec. 3.1, 3.2.1, 4.2.2): greedy of Algorithm 4 (stops after

@@ -32,7 +32,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Problem", "make", "tiny", "CONFIG_NAMES", "greville_abscissae",
+__all__ = ["Problem", "make", "tiny", "CONFIG_NAMES", "greville_abscissae", "c4_tractions",
            "open_uniform_knots", "cell_index", "cell_coords"]
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
@@ -206,7 +206,8 @@ def _build(name, dim, shape, n_el, *, amp=0.0, map_kind="sinsin", map_seed=3, wi
                    load_face=load_face, tractions=tractions, n_principal=n_principal)
 
 
-def _c4_tractions(n: int = 32, seed: int = 4) -> np.ndarray:
+def c4_tractions(n: int = 32, seed: int = 4) -> np.ndarray:
+    """The seeded load cases of c4: constant tractions m (cos phi, sin phi), m ~ U[0.5, 1], phi ~ U[0, 2 pi)."""
     rng = np.random.default_rng(seed)
     mag = rng.uniform(0.5, 1.0, size=n)
     phi = rng.uniform(0.0, 2 * np.pi, size=n)
@@ -224,7 +225,7 @@ def make(name: str, n_principal: Optional[int] = None) -> Problem:
                    n_principal=16)
     elif name == "c4":
         p = _build("c4", 2, (64, 64), 16, amp=0.15, width=("linx", 0.15, 0.30), n_principal=12,
-                   tractions=_c4_tractions())
+                   tractions=c4_tractions())
     elif name == "c5":
         p = _build("c5", 3, (12, 12, 12), 6, map_kind="fourier3", map_seed=3,
                    width=("uniform", 0.15, 0.30, 5), n_principal=16, smooth=True)

@@ -6,7 +6,7 @@ tensor products of univariate B-splines of degree p on an open uniform knot
 vector, evaluated with the Cox-de Boor recursion.
 
 Pins: partition of unity, linear precision with Greville abscissae, derivative
-against central differences (tests/test_oracle_basis.py).
+against central differences (tests/test_oracle_assembly.py).
 """
 from __future__ import annotations
 

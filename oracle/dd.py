@@ -21,7 +21,7 @@
 * primal assembly A_p^(s): cell corner dof -> global primal dof, lattice
   vertices on the Dirichlet boundary eliminated (value lifted into f)  eq. (18)
 
-Pins (tests/test_oracle_dd.py): B annihilates any conforming field scattered
+Pins (tests/test_oracle_dd_rom.py): B annihilates any conforming field scattered
 to the cells, rank B = L, sum_s B_d B_d^T D = I in 2D, row counts.
 """
 from __future__ import annotations

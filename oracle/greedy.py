@@ -21,7 +21,7 @@ right-hand side ||A^(s)|| beta^(s).
 Ties in the argmax: the smallest cell index among those within a relative
 1e-12 of the maximum.
 
-Pins (tests/test_oracle_greedy.py): Z^T Z = I, non-increasing residual,
+Pins (tests/test_oracle_dd_rom.py): Z^T Z = I, non-increasing residual,
 interpolation alpha^(sigma_i) = e_i (eq. (55)), exact recovery (zero residual)
 after m picks on lattices with exactly m distinct cells.
 """

@@ -9,7 +9,7 @@
   stopped by tolerance and the nonlinear reduced solve (46).  x_0 = 0,
   relres = ||b - A x|| / ||b||.
 
-Pins (tests/test_oracle_krylov.py): PCG equals a dense solve on SPD systems
+Pins (tests/test_oracle_dd_rom.py): PCG equals a dense solve on SPD systems
 and reports breakdown when p^T A p <= 0; FGMRES equals a dense solve and
 converges in one iteration with the exact inverse as preconditioner.
 """

@@ -21,7 +21,7 @@ ROM local operators, eq. (43): Ů_rp = sum pi_k U_rp^(k),
 Coarse problem (Sec. 3.2.1): S̊_PP = sum_s A_p S̊_pp^(s) A_p^T, factored once
 by a banded Cholesky.
 
-Pins (tests/test_oracle_rom.py): S_dd F_dd = I, K_rr U_rp = K_rp, S_pp of a
+Pins (tests/test_oracle_dd_rom.py): S_dd F_dd = I, K_rr U_rp = K_rp, S_pp of a
 floating cell annihilates the corner values of rigid modes, pi = delta = e_i at
 principal cells, ROM operators equal the exact ones on identical-cell lattices.
 """

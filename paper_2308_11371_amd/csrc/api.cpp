@@ -44,7 +44,9 @@ int ifeti_create(ifeti_ctx **out, const ifeti_lattice_desc *d, void *stream) {
         REQ(d->dim == 3 || d->nz == 1, "nz must be 1 in 2D");
         REQ(d->n_el >= 1, "n_el must be >= 1");
         REQ(d->degree == 2, "only quadratic splines (degree 2) are supported");
-        REQ(d->h > 0 && d->E_in > 0 && d->E_out > 0, "h and moduli must be positive");
+        REQ(d->h > 0 && d->E_in > 0, "h and E_in must be positive");
+        REQ(d->E_out >= 0, "E_out must be >= 0");
+        for (int i = 0; i < 9; ++i) REQ(std::isfinite(d->u0_grad[i]), "u0_grad must be finite");
         REQ(d->nu > -1.0 && d->nu < 0.5, "Poisson ratio must lie in (-1, 0.5)");
         REQ(d->smooth_eps >= 0, "smooth_eps must be >= 0");
         REQ(d->dirichlet_mask != 0 && (d->dirichlet_mask >> (2 * d->dim)) == 0, "dirichlet_mask must name faces");
@@ -195,12 +197,39 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         REQ(opt->true_operator == 0 || opt->true_operator == 1, "true_operator must be 0 or 1");
         REQ(opt->true_operator == 0 || c->ref.p == 2, "the matrix-free true operator needs quadratic B-splines");
         c->opt.true_operator = opt->true_operator;
+        REQ(opt->tile_candidate >= -1, "tile_candidate must be >= -1");
+        c->opt.tile_candidate = opt->tile_candidate;
         REQ(opt->coarse_parts >= 0, "coarse_parts must be >= 0");
         if (opt->coarse_parts != c->opt.coarse_parts) {
             c->opt.coarse_parts = opt->coarse_parts;
             if (c->rom_built) build_coarse_partition(c, c->co);
             if (c->ex_built) build_coarse_partition(c, c->co_ex);
         }
+        return IFETI_OK;
+    });
+}
+
+int ifeti_get_options(const ifeti_ctx *c, ifeti_options *o) {
+    return guarded([&]() {
+        REQ(c && o, "null argument");
+        std::memset(o, 0, sizeof(*o));
+        const Options &p = c->opt;
+        o->precision = p.precision;
+        o->pcg_check_every = p.pcg_check_every;
+        o->fgmres_restart = p.fgmres_restart;
+        o->pcg_maxit = p.pcg_maxit;
+        o->timing = p.timing;
+        std::strncpy(o->timing_filter, p.timing_filter.c_str(), sizeof(o->timing_filter) - 1);
+        o->timing_every = p.timing_every;
+        o->use_graph = p.use_graph;
+        o->autotune = p.autotune;
+        o->coarse_parts = p.coarse_parts;
+        o->true_operator = p.true_operator;
+        o->interface_block = p.interface_block;
+        o->overlap_local = p.overlap_local;
+        o->local_iters = p.local_iters;
+        o->md_precision = p.md_precision;
+        o->tile_candidate = p.tile_candidate;
         return IFETI_OK;
     });
 }
@@ -233,6 +262,8 @@ int ifeti_build_cells(ifeti_ctx *c, const double *ctrl_pts, const double *widths
         c->cells_built = true;
         c->snap_valid = true;
         c->rom_built = false;
+        c->ex_built = false;  // the exact factorisation belongs to the previous cells
+        ++c->rom_gen;
         return IFETI_OK;
     });
 }
@@ -402,6 +433,9 @@ int ifeti_compliance_grad(ifeti_ctx *c, const double *f, const double *u, double
         REQ(c && c->cells_built, "cells not built");
         REQ(f && u && grad, "bad pointers");
         REQ(nrhs >= 1, "nrhs must be >= 1");
+        REQ(c->desc.smooth_eps > 0.0,
+            "the width gradient needs a smoothed strut indicator (smooth_eps > 0): with the sharp one the cell "
+            "operators are piecewise constant in the widths");
         ensure_work(c, nrhs);
         compliance_grad(c, f, u, grad, compliance, nrhs);
         return IFETI_OK;
@@ -420,6 +454,7 @@ int ifeti_update_widths(ifeti_ctx *c, const double *widths) {
         IFETI_HIP(hipMemcpyAsync(c->widths.p, widths, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         launch_pulled_back(c);
         launch_stiffness(c);
+        if (has_dirichlet_data(c)) build_loads(c);  // the lifting of the Dirichlet corners uses K
         IFETI_HIP(hipStreamSynchronize(c->stream));
         c->snap_valid = true;
         ++c->rom_gen;

@@ -119,6 +119,10 @@ std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw
 }
 
 void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co) {
+    // a captured PCG iteration holds the partition's buffers and row counts: drop it
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    release_graph(c);
+    ++c->rom_gen;
     co.cp_p = 0;
     co.cp_ns = 0;
     const int n = c->nP, bw = co.bw;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <map>
@@ -121,6 +122,7 @@ struct Options {
     int overlap_local = 0;      // reduced local solves of (46) on a third stream beside Ů v and the PCG
     int local_iters = 1;        // > 1: K̊^-MPCG, multi-preconditioned CG local solves (Remark 6)
     int md_precision = -1;      // precision of the M̊_D^-1 contraction (49); -1: as `precision`
+    int tile_candidate = -1;    // >= 0: force this candidate of every contraction family's tile shapes
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -187,10 +189,12 @@ struct ifeti_ctx {
     ifeti::DevBuf<int> g_scatter;    // [l*2 + t]: sign*(s*n_d + j + 1), 0 none
     ifeti::DevBuf<double> g_Dw;      // [L] multiplicity weights
     ifeti::DevBuf<int> g_Ap;         // [s*n_p + j] global primal dof or -1
+    ifeti::DevBuf<double> g_up_dir;  // [s*n_p + j] u0 at primal corners on a Dirichlet face (0 elsewhere)
     ifeti::DevBuf<int> g_Ppull;      // [P*maxc + t]: s*n_p + j, -1 none
     int maxc = 0;
     std::vector<int> h_Ap;
-    std::vector<double> h_d;         // Dirichlet data (zero: clamped faces)
+    std::vector<int> h_sca;          // host copy of g_scatter (Dirichlet rows name their cell dof)
+    std::vector<double> h_d;         // Dirichlet data d of (14) (zero on clamped faces)
 
     // ---- cells (device)
     int nrhs = 0;
@@ -275,6 +279,19 @@ struct ifeti_ctx {
             if (cp.frag) (void)hipFree(cp.frag);
         frag.clear();
     }
+    // drop the fragment-order copies of one source array whose contents are rewritten in place
+    // (the copies are keyed by the source pointer); also invalidates a cached graph
+    void drop_copies(const void *src) {
+        ++rom_gen;
+        for (auto &cp : frag)
+            if (cp.src == src && cp.frag) {
+                (void)hipStreamSynchronize(stream);  // queued work may still read the copy
+                (void)hipFree(cp.frag);
+                cp.frag = nullptr;
+            }
+        frag.erase(std::remove_if(frag.begin(), frag.end(), [](const FragCopy &cp) { return !cp.frag; }),
+                   frag.end());
+    }
     ~ifeti_ctx() { free_copies(); }
 
     // ---- statistics
@@ -321,6 +338,7 @@ void build_reference_tables(ifeti_ctx *c);
 void build_partition(ifeti_ctx *c);
 void build_decomposition(ifeti_ctx *c);
 void build_loads(ifeti_ctx *c);
+bool has_dirichlet_data(const ifeti_ctx *c);  // u0 != 0 on the Dirichlet faces
 void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int *principal_in);
 
 // kernels_setup.hip
@@ -377,6 +395,8 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
                   const double *bank = nullptr, const char *rtag = "rom_R_gemm");
 void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs);
 void cell_displacements(ifeti_ctx *c, const double *u, double *out, int nrhs);
+// y_s = K^(s) x_s for every cell from the stencil values; x, y device [N][n_dof] (setup use)
+void cell_matvec_full(ifeti_ctx *c, const double *x, double *y);
 // dot_w / dot_part (optional): the final scatter also writes the per-block partial
 // sums of out . dot_w, dot_blocks(L) per load case (consumed by the PCG kernels)
 void combine_coarse_maps(ifeti_ctx *c);

@@ -837,6 +837,7 @@ constexpr int kNBig = sizeof(kBigCandidates) / sizeof(kBigCandidates[0]);
 static FragLauncher choose_launcher(ifeti_ctx *c, const GemmArgsFrag &f, bool big, int def, bool tunable) {
     const FragLauncher *cand = big ? kBigCandidates : kSmallCandidates;
     const int n = big ? kNBig : kNSmall;
+    if (c->opt.tile_candidate >= 0) return cand[c->opt.tile_candidate % n];
     if (!c->opt.autotune || !tunable || c->capturing) return cand[def];
     std::vector<long long> key = {big ? 1 : 0, f.M, f.ncols, f.ngroups};
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
@@ -896,6 +897,7 @@ const LpLauncher kLpCandidates[2][2][kNLp] = {
 
 static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool bf, bool big, bool tunable) {
     const LpLauncher *cand = kLpCandidates[bf ? 1 : 0][big ? 0 : 1];
+    if (c->opt.tile_candidate >= 0) return cand[c->opt.tile_candidate % kNLp];
     if (!c->opt.autotune || !tunable || c->capturing) return cand[big ? 2 : 0];  // the tuner's usual choice
     std::vector<long long> key = {bf ? 3 : 2, big ? 1 : 0, f.M, f.ncols, f.ngroups};
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});

@@ -625,6 +625,8 @@ void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<dou
     DevBuf<double> band;
     band.upload(band_L, c->stream);
     co.SPPinv.alloc((size_t)c->nP * c->nP);
+    // the inverse is rewritten in place: fragment copies made from an earlier one are stale
+    c->drop_copies(co.SPPinv.p);
     launch_band_inverse(c, band.p, c->nP, bw, co.SPPinv.p);
     const int nT = (c->nP + 63) / 64;
     const size_t ntiles = (size_t)nT * (nT + 1) / 2;

@@ -1014,6 +1014,42 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
     }
 }
 
+// y_s = K^(s) x_s over all n_dof rows of every cell (stencil values; one workgroup per cell)
+template <int D>
+__global__ __launch_bounds__(kB) void k_cell_matvec_full(const double *__restrict__ Kst, const double *__restrict__ x,
+                                                         int nc, int n_ctrl, int n_off, int p,
+                                                         double *__restrict__ y) {
+    const int s = blockIdx.x;
+    const int n_dof = n_ctrl * D, w = 2 * p + 1;
+    const double *xs = x + (size_t)s * n_dof;
+    const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
+    for (int t = threadIdx.x; t < n_dof; t += kB) {
+        const int i = t / n_ctrl, a = t % n_ctrl;
+        int ma[D];
+        int ta = a;
+        for (int j = 0; j < D; ++j) {
+            ma[j] = ta % nc;
+            ta /= nc;
+        }
+        double acc = 0.0;
+        for (int o = 0; o < n_off; ++o) {
+            int to = o, b = 0;
+            bool ok = true;
+            int mb[D];
+            for (int j = 0; j < D; ++j) {
+                mb[j] = ma[j] + (to % w) - p;
+                to /= w;
+                if (mb[j] < 0 || mb[j] >= nc) ok = false;
+            }
+            if (!ok) continue;
+            for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc += Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a] * xs[b * D + k];
+        }
+        y[(size_t)s * n_dof + a * D + i] = acc;
+    }
+}
+
 // ------------------------------------------------------------------ matrix-free true cell operator
 // K^(s) u without the assembled values (Sec. 4.2.1, Remark 9): the stiffness is linear in the
 // pulled-back tensor Ĉ^(s) at the quadrature points (eq. (52)), so per element E and point q
@@ -2111,7 +2147,8 @@ void apply_MD_rom(ifeti_ctx *c, const double *r, double *out, int nrhs) {
 __global__ __launch_bounds__(kB) void k_cell_view(const double *__restrict__ u, long long nU, int N, int n_r, int n_p,
                                                   int n_dof, const int *__restrict__ r_of_dof,
                                                   const int *__restrict__ p_of_dof, const int *__restrict__ Ap,
-                                                  double *__restrict__ out, long long total) {
+                                                  const double *__restrict__ up_dir, double *__restrict__ out,
+                                                  long long total) {
     const long long t = (long long)blockIdx.x * kB + threadIdx.x;
     if (t >= total) return;
     const int e = (int)(t % n_dof);
@@ -2123,17 +2160,30 @@ __global__ __launch_bounds__(kB) void k_cell_view(const double *__restrict__ u, 
     if (rp >= 0) {
         v = ur[(size_t)s * n_r + rp];
     } else {
-        const int P = Ap[(size_t)s * n_p + p_of_dof[e]];
-        v = P >= 0 ? ur[(size_t)N * n_r + P] : 0.0;
+        const int j = p_of_dof[e];
+        const int P = Ap[(size_t)s * n_p + j];
+        v = P >= 0 ? ur[(size_t)N * n_r + P] : (up_dir ? up_dir[(size_t)s * n_p + j] : 0.0);
     }
     out[t] = v;
+}
+
+void cell_matvec_full(ifeti_ctx *c, const double *x, double *y) {
+    const RefTables &R = c->ref;
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_cell_matvec_full<2>, dim3(c->N), dim3(kB), 0, c->stream, c->Kst.p, x, R.nc, R.n_ctrl,
+                           R.n_off, R.p, y);
+    else
+        hipLaunchKernelGGL(k_cell_matvec_full<3>, dim3(c->N), dim3(kB), 0, c->stream, c->Kst.p, x, R.nc, R.n_ctrl,
+                           R.n_off, R.p, y);
+    IFETI_HIP(hipGetLastError());
 }
 
 void cell_displacements(ifeti_ctx *c, const double *u, double *out, int nrhs) {
     const long long total = (long long)nrhs * c->N * c->ref.n_dof;
     if (total == 0) return;
     hipLaunchKernelGGL(k_cell_view, dim3((unsigned)((total + kB - 1) / kB)), dim3(kB), 0, c->stream, u, c->nU, c->N,
-                       c->n_r, c->n_p, c->ref.n_dof, c->r_of_dof.p, c->p_of_dof.p, c->g_Ap.p, out, total);
+                       c->n_r, c->n_p, c->ref.n_dof, c->r_of_dof.p, c->p_of_dof.p, c->g_Ap.p,
+                       c->g_up_dir.n ? c->g_up_dir.p : nullptr, out, total);
     IFETI_HIP(hipGetLastError());
 }
 

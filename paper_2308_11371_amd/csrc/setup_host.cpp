@@ -356,6 +356,7 @@ void build_decomposition(ifeti_ctx *c) {
     }
     c->g_gather.upload(gat, c->stream);
     c->g_scatter.upload(sca, c->stream);
+    c->h_sca = sca;
     c->g_Dw.upload(Dw, c->stream);
     c->h_d.assign(L, 0.0);
 
@@ -395,6 +396,58 @@ void build_decomposition(ifeti_ctx *c) {
             pull[(size_t)P * c->maxc + cnt[P]++] = s * n_p + j;
         }
     c->g_Ppull.upload(pull, c->stream);
+}
+
+bool has_dirichlet_data(const ifeti_ctx *c) {
+    for (int i = 0; i < c->dim * c->dim; ++i)
+        if (c->desc.u0_grad[i] != 0.0) return true;
+    return false;
+}
+
+// Dirichlet data u0(x) = G x (3c) at the control points of the Dirichlet faces: d of (14) on the
+// Dirichlet rows, and the values of the eliminated primal corners, lifted into the cell loads
+// (f_s -= K^(s) u0 on those columns) so that (16) holds for the remaining unknowns.
+static void apply_dirichlet_data(ifeti_ctx *c, std::vector<double> &fc) {
+    const RefTables &R = c->ref;
+    const int dim = c->dim, N = c->N, n_dof = R.n_dof, n_p = c->n_p, n_d = c->n_d;
+    c->h_d.assign(c->L, 0.0);
+    c->g_up_dir.release();
+    if (!has_dirichlet_data(c)) return;
+    const double *G = c->desc.u0_grad;
+    std::vector<double> P((size_t)N * R.n_ctrl * dim);
+    IFETI_HIP(hipMemcpyAsync(P.data(), c->ctrl.p, P.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    auto u0 = [&](int s, int a, int comp) {
+        double v = 0.0;
+        for (int m = 0; m < dim; ++m) v += G[comp * dim + m] * P[((size_t)s * R.n_ctrl + a) * dim + m];
+        return v;
+    };
+    for (int r = c->L_int; r < c->L; ++r) {  // Dirichlet rows: one +1 entry at a cell's dual dof
+        const int e = c->h_sca[2 * (size_t)r] - 1, s = e / n_d, j = e % n_d, dof = c->idx_d[j];
+        c->h_d[r] = u0(s, dof / dim, dof % dim);
+    }
+    std::vector<double> up((size_t)N * n_p, 0.0), uD((size_t)N * n_dof, 0.0);
+    bool any = false;
+    for (int s = 0; s < N; ++s)
+        for (int j = 0; j < n_p; ++j) {
+            if (c->h_Ap[(size_t)s * n_p + j] >= 0) continue;  // a free lattice vertex
+            const int dof = c->idx_p[j];
+            const double v = u0(s, dof / dim, dof % dim);
+            up[(size_t)s * n_p + j] = v;
+            uD[(size_t)s * n_dof + dof] = v;
+            any = any || v != 0.0;
+        }
+    c->g_up_dir.upload(up, c->stream);
+    if (!any) return;
+    DevBuf<double> dx, dy;
+    dx.upload(uD, c->stream);
+    dy.alloc(uD.size());
+    cell_matvec_full(c, dx.p, dy.p);
+    std::vector<double> KuD(uD.size());
+    IFETI_HIP(hipMemcpyAsync(KuD.data(), dy.p, KuD.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    for (int r = 0; r < c->nrhs; ++r)
+        for (size_t t = 0; t < KuD.size(); ++t) fc[(size_t)r * N * n_dof + t] -= KuD[t];
 }
 
 // ------------------------------------------------------------------ loads (5b)
@@ -476,6 +529,7 @@ void build_loads(ifeti_ctx *c) {
             }
         }
     }
+    apply_dirichlet_data(c, fc);
     c->f_cells.upload(fc, c->stream);
     // f of (16): f_R per cell, f_P assembled (18)
     std::vector<double> fv((size_t)nrhs * c->nU, 0.0);

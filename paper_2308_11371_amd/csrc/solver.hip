@@ -94,15 +94,17 @@ __global__ __launch_bounds__(kB) void k_pcg_init(const double *__restrict__ p_rr
     double rz = sum_partials(p_rz + (size_t)rhs * nblk, nblk, sh);
     if (threadIdx.x == 0) {
         double r0 = sqrt(rr);
+        // a non-finite right-hand side (or preconditioned residual) is a breakdown, not convergence
+        const bool bad = !isfinite(rr) || !isfinite(rz);
         st[rhs * S_N + S_RHO] = rz;
         st[rhs * S_N + S_R0] = r0;
         st[rhs * S_N + S_REL] = r0 > 0.0 ? 1.0 : 0.0;
         st[rhs * S_N + S_ALPHA] = 0.0;
         st[rhs * S_N + S_BETA] = 0.0;
-        ist[rhs * I_N + I_ACT] = r0 > 0.0 ? 1 : 0;
+        ist[rhs * I_N + I_ACT] = (!bad && r0 > 0.0) ? 1 : 0;
         ist[rhs * I_N + I_IT] = 0;
         ist[rhs * I_N + I_ITER] = 0;
-        ist[rhs * I_N + I_BRK] = 0;
+        ist[rhs * I_N + I_BRK] = bad ? 1 : 0;
     }
 }
 

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "EBREAKD
 IFETI_FP64, IFETI_FP32_LOCAL, IFETI_BF16_LOCAL = 0, 1, 2
 
 EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_sizes", "ifeti_set_options",
+            "ifeti_get_options",
             "ifeti_build_cells", "ifeti_get_rhs", "ifeti_build_reduced_basis", "ifeti_get_coefficients",
             "ifeti_apply_F", "ifeti_apply_MD", "ifeti_apply_MD_rom", "ifeti_apply_U", "ifeti_apply_Ut",
             "ifeti_apply_Kinv_rom",
@@ -34,7 +35,8 @@ class LatticeDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("n_el", ctypes.c_int), ("degree", ctypes.c_int), ("h", ctypes.c_double),
                 ("E_in", ctypes.c_double), ("E_out", ctypes.c_double), ("nu", ctypes.c_double),
-                ("smooth_eps", ctypes.c_double), ("dirichlet_mask", ctypes.c_int), ("load_face", ctypes.c_int)]
+                ("smooth_eps", ctypes.c_double), ("dirichlet_mask", ctypes.c_int), ("load_face", ctypes.c_int),
+                ("u0_grad", ctypes.c_double * 9)]
 
 
 class Sizes(ctypes.Structure):
@@ -49,7 +51,14 @@ class Options(ctypes.Structure):
                 ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32),
                 ("timing_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int), ("interface_block", ctypes.c_int),
-                ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int), ("md_precision", ctypes.c_int)]
+                ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int), ("md_precision", ctypes.c_int),
+                ("tile_candidate", ctypes.c_int)]
+
+OPTION_NAMES = tuple(name for name, _ in Options._fields_)
+# the library's defaults (a new context starts with these)
+DEFAULT_OPTIONS = dict(precision=IFETI_FP64, pcg_check_every=2, fgmres_restart=60, pcg_maxit=1000, timing=0,
+                       timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
+                       interface_block=0, overlap_local=0, local_iters=1, md_precision=-1, tile_candidate=-1)
 
 
 class KernelStat(ctypes.Structure):
@@ -90,6 +99,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_destroy": [P],
         "ifeti_get_sizes": [P, ctypes.POINTER(Sizes)],
         "ifeti_set_options": [P, ctypes.POINTER(Options)],
+        "ifeti_get_options": [P, ctypes.POINTER(Options)],
         "ifeti_build_cells": [P, P, P, P, I],
         "ifeti_get_rhs": [P, P, P],
         "ifeti_build_reduced_basis": [P, I, D, P, P, P],
@@ -140,15 +150,17 @@ def _check(status: int):
 
 
 def desc_from_problem(problem) -> LatticeDesc:
-    """LatticeDesc of a latticegen.Problem (clamped faces only)."""
-    if np.any(problem.u0_grad != 0.0):
-        raise ValueError("the library supports clamped (u0 = 0) Dirichlet faces")
+    """LatticeDesc of a latticegen.Problem (Dirichlet data u0(x) = u0_grad x on its Dirichlet faces)."""
     shape = tuple(problem.shape) + (1,) * (3 - len(problem.shape))
     mask = 0
     for f in problem.dirichlet_faces:
         mask |= 1 << f
+    g = np.zeros(9)
+    dim = problem.dim
+    g[:dim * dim] = np.asarray(problem.u0_grad, dtype=np.float64).reshape(dim * dim)
     return LatticeDesc(problem.dim, shape[0], shape[1], shape[2], problem.n_el, problem.degree, problem.h,
-                       problem.E_in, problem.E_out, problem.nu, problem.smooth_eps, mask, problem.load_face)
+                       problem.E_in, problem.E_out, problem.nu, problem.smooth_eps, mask, problem.load_face,
+                       (ctypes.c_double * 9)(*g))
 
 
 class Context:
@@ -187,13 +199,29 @@ class Context:
         _check(self.lib.ifeti_get_sizes(self.h, ctypes.byref(s)))
         return s
 
-    def set_options(self, precision=IFETI_FP64, pcg_check_every=2, fgmres_restart=60, pcg_maxit=1000, timing=0,
-                    timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
-                    interface_block=0, overlap_local=0, local_iters=1, md_precision=-1):
-        o = Options(precision, pcg_check_every, fgmres_restart, pcg_maxit, timing, timing_filter.encode()[:31],
-                    timing_every, use_graph, autotune, coarse_parts, true_operator, interface_block, overlap_local,
-                    local_iters, md_precision)
+    def get_options(self) -> dict:
+        o = Options()
+        _check(self.lib.ifeti_get_options(self.h, ctypes.byref(o)))
+        out = {n: getattr(o, n) for n in OPTION_NAMES}
+        out["timing_filter"] = o.timing_filter.decode()
+        return out
+
+    def set_options(self, **kw):
+        """Change the named options (see ifeti_options); every other option keeps its current value."""
+        unknown = set(kw) - set(OPTION_NAMES)
+        if unknown:
+            raise TypeError(f"unknown options {sorted(unknown)}")
+        o = Options()
+        _check(self.lib.ifeti_get_options(self.h, ctypes.byref(o)))
+        for name, value in kw.items():
+            setattr(o, name, value.encode()[:31] if name == "timing_filter" else value)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
+
+    def reset_options(self, **kw):
+        """Every option back to the library default, then the named ones changed."""
+        opts = dict(DEFAULT_OPTIONS)
+        opts.update(kw)
+        self.set_options(**opts)
 
     def stats(self) -> dict:
         s = Stats()

@@ -76,7 +76,7 @@ def test_partitioned_matches_oracle(pair):
             ref_sym = F3
         else:
             assert rel(F3, ref_sym) < 1e-12      # partitioned vs explicit inverse: rounding only
-    ctx.set_options()
+    ctx.reset_options()
 
 
 def test_block_count_beyond_the_band_is_rejected(pair):
@@ -87,4 +87,4 @@ def test_block_count_beyond_the_band_is_rejected(pair):
     # the context falls back to the explicit inverse and stays usable
     x = np.random.default_rng(3).standard_normal(m.L)
     assert rel(host(ctx.apply_F(dev(x))), m.apply_F(x)) < 1e-11
-    ctx.set_options()
+    ctx.reset_options()

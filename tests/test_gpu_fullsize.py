@@ -1,7 +1,7 @@
 """Full-size parity on the c2 lattice (4096 cells, 12 principal cells, FP64), in the configuration the
-benchmark times: the library against oracle values sampled from a whole-lattice oracle run
-(tests/golden/c2_samples.json, written by tests/golden/make_c2_samples.py from oracle/ only), and
-properties of the full solve that hold at any size."""
+benchmark times: the library against oracle values sampled from whole-lattice oracle runs
+(tests/golden/c2_samples.json and c2_solve.json, written by tests/golden/make_c2_samples.py and
+make_c2_solve.py from oracle/ only), and properties of the full solve that hold at any size."""
 import json
 import os
 
@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_samples.json")
+GOLDEN_SOLVE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_solve.json")
 
 
 @pytest.fixture(scope="module")
@@ -87,6 +88,37 @@ def test_full_solve_properties(c2):
     rel = (torch.linalg.norm(r) / torch.linalg.norm(torch.cat([f, d]))).item()
     assert rel <= 1.01e-8
     assert 1 <= int(info["outer_its"][0]) <= 60
+
+
+def test_full_solve_displacements_match_oracle(c2):
+    """The whole c2 solve at the parity tolerances (outer 1e-12, interface PCG 1e-13) against the
+    oracle's ROM-FETI-DP solve of the whole lattice: sampled displacements and multipliers within 1e-9
+    relative, and the norms of u and lambda."""
+    prob, ctx, gold = c2
+    with open(GOLDEN_SOLVE) as fh:
+        g = json.load(fh)
+    assert list(ctx.sigma) == g["sigma"]
+    s = ctx.sizes
+    f, d = ctx.get_rhs()
+    f = f[:s.nU].contiguous()
+    d = d[:s.L].contiguous()
+    ctx.set_options(fgmres_restart=200)
+    try:
+        u, lam, info = ctx.solve(f, d, tol=g["tol"], inner_tol=g["inner_tol"], maxit=200, check=False)
+    finally:
+        ctx.reset_options()
+    u = u.cpu().numpy()
+    lam = lam.cpu().numpy()
+    iu, il = np.array(g["u_idx"]), np.array(g["lam_idx"])
+    eu = np.linalg.norm(u[iu] - np.array(g["u_val"])) / np.linalg.norm(g["u_val"])
+    el = np.linalg.norm(lam[il] - np.array(g["lam_val"])) / np.linalg.norm(g["lam_val"])
+    nu = abs(np.linalg.norm(u) - g["u_norm"]) / g["u_norm"]
+    nl = abs(np.linalg.norm(lam) - g["lam_norm"]) / g["lam_norm"]
+    print(f"[gpu fullsize] c2 solve: outer {info['outer_its'][0]} (oracle {g['outer_its']}), relres "
+          f"{info['relres'][0]:.2e}; u samples {eu:.2e}, lam samples {el:.2e}, norms {nu:.2e} / {nl:.2e}",
+          flush=True)
+    assert eu <= 1e-9 and el <= 1e-9
+    assert nu <= 1e-9 and nl <= 1e-9
 
 
 def test_exact_fetidp_full_size(c2):

@@ -121,7 +121,7 @@ def test_matrix_free_true_operator(pair):
         assert info["relres"][0] < 1e-11
         assert rel(host(u), ro["u"]) < 1e-9
     finally:
-        ctx.set_options()
+        ctx.reset_options()
 
 
 def test_MD_rom_parity(pair):
@@ -149,7 +149,7 @@ def test_interface_block_variants(pair, block, label):
     try:
         u, lam, info = ctx.solve(f[:m.nU].contiguous(), d[:m.L].contiguous(), tol=1e-10, maxit=400)
     finally:
-        ctx.set_options()
+        ctx.reset_options()
     assert info["relres"][0] < 1e-10
     assert rel(host(u), ro["u"]) < 1e-8
     # rounding differences may move the stop by a step or two over a few hundred iterations
@@ -178,7 +178,7 @@ def test_mpcg_local_parity(pair, iters):
             assert rel(host(u), ro["u"]) < 1e-8
             assert abs(int(info["outer_its"][0]) - ro["outer_its"]) <= 1
     finally:
-        ctx.set_options()
+        ctx.reset_options()
         m.local_iters = 1
 
 
@@ -196,7 +196,7 @@ def test_fgmres_restart_growth(pair):
         ctx.set_options(fgmres_restart=300)
         u1, lam1, i1 = ctx.solve(f, d, tol=1e-10, maxit=300)
     finally:
-        ctx.set_options()
+        ctx.reset_options()
     assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(lam0), host(lam1))
 
 
@@ -213,7 +213,7 @@ def test_overlap_local_bitwise(pair):
         ctx.set_options(overlap_local=1)
         u1, lam1, i1 = ctx.solve(f, d, tol=1e-10, maxit=80)
     finally:
-        ctx.set_options()
+        ctx.reset_options()
     assert np.array_equal(host(u0), host(u1)) and np.array_equal(host(lam0), host(lam1))
     assert int(i0["outer_its"][0]) == int(i1["outer_its"][0])
 

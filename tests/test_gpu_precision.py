@@ -58,7 +58,7 @@ def test_operators_low_precision(pair, prec, tol_op):
         for r in range(3):
             assert rel(Y[r], m.apply_F(X[r])) < tol_op
     finally:
-        ctx.set_options(precision=ifeti.IFETI_FP64)
+        ctx.reset_options()
 
 
 @pytest.mark.parametrize("prec,inner", [("fp32", 1e-6), ("bf16", 1e-3)])
@@ -76,7 +76,7 @@ def test_refined_solve_matches_fp64_oracle(pair, prec, inner):
         assert info["relres"][0] <= 1e-10
         assert err < 1e-6
     finally:
-        ctx.set_options(precision=ifeti.IFETI_FP64)
+        ctx.reset_options()
 
 
 @pytest.mark.parametrize("prec,inner", [("fp64", 1e-11), ("fp32", 1e-6)])
@@ -96,5 +96,5 @@ def test_bf16_preconditioner_refined_solve(pair, prec, inner):
         assert info["relres"][0] <= 1e-10
         assert err < 1e-6
     finally:
-        ctx.set_options(precision=ifeti.IFETI_FP64)
+        ctx.reset_options()
 

@@ -116,3 +116,42 @@ def test_strut_distance_2d_and_3d():
     xi3 = np.array([[0.5, 0.5, 0.5], [0.5, 0.05, 0.02], [0.0, 0.4, 0.3]])
     d3 = strut_distance(xi3, 3)
     assert np.allclose(d3, [0.5, 0.05, 0.3])
+
+
+def _bspline_integrals(n_el, p=2):
+    """Integral over [0, 1] of each B-spline of the open uniform knot vector: the textbook identity
+    int N_a = (Xi_{a+p+1} - Xi_a) / (p + 1)."""
+    kn = latticegen.open_uniform_knots(n_el, p)
+    return np.array([(kn[a + p + 1] - kn[a]) / (p + 1) for a in range(n_el + p)])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cell_loads_closed_form_on_straight_face(dim):
+    """Consistent loads (5b) entry by entry.  The macro maps fix the lattice boundary and Greville
+    control points reproduce affine maps, so the loaded face X = L_x is flat and each cell's face map is
+    affine with measure h^(dim-1) dxi: the load on face control point a is t h^(dim-1) prod_j int N_{a_j}
+    over the tangential directions, and every other entry (other control points, cells off the face)
+    is zero.  A load on the wrong face, wrong per-node weights or a wrong measure fails here."""
+    if dim == 2:
+        t = np.array([0.7, -0.4])
+        p = latticegen.tiny(2, (3, 2), 4, tractions=[t])
+    else:
+        t = np.array([0.3, -0.2, 0.5])
+        p = latticegen.tiny(3, (2, 2, 2), 3, tractions=[t])
+    assert p.load_face == 1  # X = L_x
+    ref = RefCell(dim, p.n_el)
+    f = cell_loads(ref, p)[:, :, 0].reshape(p.N, -1, dim)
+    I1 = _bspline_integrals(p.n_el)
+    nc = p.nc
+    expect = np.zeros_like(f)
+    coords = latticegen.cell_coords(p.shape)
+    for s in range(p.N):
+        if coords[s, 0] != p.shape[0] - 1:
+            continue
+        for a in range(p.n_ctrl):
+            mi = [(a // nc ** j) % nc for j in range(dim)]
+            if mi[0] != nc - 1:
+                continue
+            w = p.h ** (dim - 1) * np.prod([I1[mi[j]] for j in range(1, dim)])
+            expect[s, a] = w * t
+    assert np.abs(f - expect).max() <= 1e-14 * np.abs(expect).max()

@@ -109,3 +109,17 @@ def test_mpcg_local_solves_reach_direct_solution():
     assert r2["relres"] < 1e-11
     assert _rel(r2["u"], ref["u"]) < 1e-10
     assert r2["outer_its"] <= r1["outer_its"]
+
+
+@pytest.mark.parametrize("dim,shape,n_el", [(2, (3, 2), 3), (3, (2, 2, 2), 2)])
+def test_exact_fetidp_solve_equals_direct_cholesky(dim, shape, n_el):
+    """Standard FETI-DP (Sec. 2.2.4): the right-hand side d̄ of eq. (25), PCG on F (24) with M_D (30) and
+    the recovery of eqs. (21) then (20) reach the conforming solution of (16) and its multipliers."""
+    p = latticegen.tiny(dim, shape, n_el, n_principal=2)
+    m = Model(p)
+    ref = conforming_solve(m)
+    r = ExactFETIDP(m).solve(tol=1e-13, maxit=500)
+    eu = np.linalg.norm(r["u"] - ref["u"]) / np.linalg.norm(ref["u"])
+    el = np.linalg.norm(r["lam"] - ref["lam"]) / np.linalg.norm(ref["lam"])
+    assert eu < 1e-10, eu
+    assert el < 1e-9, el
