@@ -69,45 +69,58 @@ def test_gradient_matches_central_differences_and_autograd():
     ctx.close()
 
 
-def test_c5_gradient_finite_differences_on_sampled_cells():
-    """Full-size c5 (1728 cells, smoothed indicator): the adjoint gradient on all 20 seeded cells
-    against (a) the oracle's FP64 gradient -u_s^T dK^(s)/dw_s u_s evaluated with the GPU's converged u,
-    which checks the gradient kernel at full size, and (b) central differences (step 1e-6) of the
-    compliance of two GPU solves per cell, which checks the whole chain."""
+C5_FD_CELLS = latticegen.fd_cells(1728, count=20)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    """Full-size c5 (1728 cells, smoothed indicator): converged FP64 solve and its adjoint gradient."""
     _cuda()
-    from oracle import Model
-    from oracle.gradient import compliance_gradient
     from paper_2308_11371_amd import ifeti
     print("[gpu gradient] c5 setup", flush=True)
     prob = latticegen.make("c5")
+    assert prob.N == 1728
     ctx = ifeti.setup(prob)
     ctx.set_options(pcg_maxit=200, fgmres_restart=100)
     f, d = ctx.get_rhs()
     w0 = torch.tensor(prob.widths, dtype=torch.float64, device="cuda")
     u, lam, info = ctx.solve(f, d, tol=1e-12, inner_tol=1e-11, maxit=100)
     c0, g = ctx.compliance_grad(f, u)
-    g = g.cpu().numpy()
+    yield prob, ctx, f, d, w0, u, g.cpu().numpy()
+    ctx.close()
+
+
+def test_c5_gradient_matches_oracle_on_fd_cells(c5):
+    """The adjoint gradient on the 20 seeded cells against the oracle's FP64 gradient
+    -u_s^T dK^(s)/dw_s u_s evaluated with the GPU's converged u (checks the gradient kernel at full
+    size; cell matrices are built only for those cells)."""
+    from oracle import Model
+    from oracle.gradient import compliance_gradient
+    prob, ctx, f, d, w0, u, g = c5
     assert np.all(g < 0)
-    cells = latticegen.fd_cells(prob.N, count=20)
-    m0 = Model(prob, build_all_cells=False)          # cell matrices only for the sampled cells
-    go = compliance_gradient(m0, u.cpu().numpy(), cells=cells)
-    eo = np.abs(g[cells] - go).max() / np.abs(go).max()
-    print(f"[gpu gradient] c5 adjoint vs oracle on {cells.size} cells: max rel {eo:.2e}", flush=True)
+    m0 = Model(prob, build_all_cells=False)
+    go = compliance_gradient(m0, u.cpu().numpy(), cells=C5_FD_CELLS)
+    eo = np.abs(g[C5_FD_CELLS] - go).max() / np.abs(go).max()
+    print(f"[gpu gradient] c5 adjoint vs oracle on {C5_FD_CELLS.size} cells: max rel {eo:.2e}", flush=True)
     assert eo <= 1e-10
+
+
+@pytest.mark.parametrize("cell", [int(s) for s in C5_FD_CELLS])
+def test_c5_gradient_central_difference(c5, cell):
+    """Central difference (step 1e-6) of the compliance of two GPU solves against the adjoint gradient
+    of one of the 20 seeded cells (checks the whole chain: width update, solve, gradient)."""
+    prob, ctx, f, d, w0, u, g = c5
     h = 1e-6
-    worst = 0.0
-    for s in cells:
-        vals = []
+    vals = []
+    try:
         for sgn in (1, -1):
             ww = w0.clone()
-            ww[s] += sgn * h
+            ww[cell] += sgn * h
             ctx.update_widths(ww)
             uu, _, inf = ctx.solve(f, d, tol=1e-12, inner_tol=1e-11, maxit=100)
             vals.append(ctx.compliance_grad(f, uu)[0][0])
-        fd = (vals[0] - vals[1]) / (2 * h)
-        worst = max(worst, abs(fd - g[s]) / abs(g[s]))
-        print(f"c5 cell {s}: fd {fd:.6e} adjoint {g[s]:.6e}", flush=True)
-        assert abs(fd - g[s]) <= 2e-3 * abs(g[s])
-    print(f"[gpu gradient] c5 central differences on {cells.size} cells: max rel {worst:.2e}", flush=True)
-    ctx.update_widths(w0)
-    ctx.close()
+    finally:
+        ctx.update_widths(w0)
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"c5 cell {cell}: fd {fd:.6e} adjoint {g[cell]:.6e} rel {abs(fd - g[cell]) / abs(g[cell]):.1e}", flush=True)
+    assert abs(fd - g[cell]) <= 2e-3 * abs(g[cell])
