@@ -212,6 +212,17 @@ int ifeti_get_coefficients(ifeti_ctx *ctx, double *alpha, double *pi, double *de
 
 /* out = F̊ lam, the ROM dual operator of eq. (48), lam/out dev L x nrhs. */
 int ifeti_apply_F(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops that
+ * forbid hipMalloc): out = F̊ lam exactly as ifeti_apply_F computes it (bitwise the same values), with
+ * its work buffers in a device array the library holds for the life of the process, 32 MiB on each
+ * GPU it runs on; the call makes no device or host allocation.  All work goes to the context stream
+ * (no second stream).  Limits: 1 to 3 load cases, and 8 * (N nrhs (2 n_d + n_p) + 2 nP nrhs) bytes
+ * (each part rounded up to 256 B) at most 32 MiB (c2: one to three load cases), EINVAL otherwise.
+ * Needs the copies ifeti_build_reduced_basis makes (FP64 operators); in the FP32/BF16 precision form
+ * the narrow copies are made by the first ifeti_apply_F in that precision (EINVAL before).  Calls
+ * share each GPU's array: calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and give wrong results.  No statistics are recorded for these calls. */
+int ifeti_apply_F_noalloc(ifeti_ctx *ctx, const double *lam, double *out, int nrhs);
 /* out = M̊_D^-1 r, the ROM Dirichlet preconditioner of eq. (49). */
 int ifeti_apply_MD(ifeti_ctx *ctx, const double *r, double *out, int nrhs);
 

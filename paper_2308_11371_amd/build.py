@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build", "ifeti")
 LIB = os.path.join(HERE, "libifeti.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "stats.cpp", "setup_host.cpp", "kernels_setup.hip", "gemm.hip", "ops.hip", "solver.hip", "gradient.hip", "coarse_part.cpp", "exact.hip"]
+SOURCES = ["api.cpp", "stats.cpp", "setup_host.cpp", "kernels_setup.hip", "gemm.hip", "ops.hip", "solver.hip", "gradient.hip", "coarse_part.cpp", "exact.hip", "noalloc.hip"]
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
          "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 

@@ -238,6 +238,8 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> ex_w, ex_g, ex_z, ex_d;
     bool rom_built = false;
     bool capturing = false;             // a HIP graph capture is in progress on `stream`
+    bool no_alloc = false;              // inside an allocation-free call: anything that would allocate
+                                        // (copies, inverses, work buffers, timing events) is an EINVAL
     hipStream_t own_stream = nullptr;   // non-blocking stream of the graph form (default priority)
     void *h_pin = nullptr;              // pinned host staging for convergence reads (hipHostMalloc)
     size_t h_pin_bytes = 0;
@@ -358,6 +360,8 @@ void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *
 std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw);
 
 // gemm.hip
+// fragment-order FP64 copies of the operators the interface operators contract with (built at setup)
+void prepare_operator_copies(ifeti_ctx *c);
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
           bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
@@ -407,6 +411,10 @@ const void *read_back(ifeti_ctx *c, const void *dev, size_t bytes);
 void coarse_reduce(ifeti_ctx *c, const CoarseSolver &co, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);
+// F̊ lam with explicit work buffers: Y, Yc [N*nrhs][n_d], cb [N*nrhs][n_p], zP, yP [nrhs][nP]; side: the
+// contraction on the second stream beside the coarse branch (else everything on the context stream)
+void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double *Y, double *Yc, double *cb,
+                  double *zP, double *yP, bool side, const double *dot_w, double *dot_part);
 void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
               double *dot_part = nullptr);
 int dot_blocks(long long n);

@@ -843,6 +843,7 @@ static FragLauncher choose_launcher(ifeti_ctx *c, const GemmArgsFrag &f, bool bi
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) return cand[it->second];
+    if (c->no_alloc) return cand[def];  // timing the candidates needs events
     hipEvent_t e0, e1;
     IFETI_HIP(hipEventCreate(&e0));
     IFETI_HIP(hipEventCreate(&e1));
@@ -903,6 +904,7 @@ static LpLauncher choose_lp_launcher(ifeti_ctx *c, const GemmArgsFragLP &f, bool
     for (int i = 0; i < f.ngroups; ++i) key.insert(key.end(), {f.Kd[i], f.K[i], f.gcodes[i] ? 1 : 0});
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) return cand[it->second];
+    if (c->no_alloc) return cand[big ? 2 : 0];
     hipEvent_t e0, e1;
     IFETI_HIP(hipEventCreate(&e0));
     IFETI_HIP(hipEventCreate(&e1));
@@ -935,6 +937,9 @@ static const double *frag_copy(ifeti_ctx *c, const double *A, int M, int Kd, int
     for (auto &cp : c->frag)
         if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K && cp.kind == IFETI_FP64)
             return (const double *)cp.frag;
+    IFETI_REQUIRE(!c->no_alloc, IFETI_EINVAL,
+                  "allocation-free call: the fragment-order copy of an operator is not built (ifeti_apply_F "
+                  "builds it)");
     const int MT = (M + 15) / 16, KT2 = (Kd + 7) / 8;
     const long long n = (long long)K * MT * KT2 * 128;
     ifeti_ctx::FragCopy cp;
@@ -955,6 +960,9 @@ static const double *frag_copy(ifeti_ctx *c, const double *A, int M, int Kd, int
 static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, int K, int kind) {
     for (auto &cp : c->frag)
         if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == K && cp.kind == kind) return cp.frag;
+    IFETI_REQUIRE(!c->no_alloc, IFETI_EINVAL,
+                  "allocation-free call: the FP32/BF16 copy of an operator is not built (the first ifeti_apply_F "
+                  "in that precision builds it)");
     const bool bf = kind == IFETI_BF16_LOCAL;
     const int MT = (M + 15) / 16, QU = (Kd + (bf ? 31 : 15)) / (bf ? 32 : 16), U = bf ? 8 : 4;
     const long long n = (long long)K * MT * QU * 64 * U;
@@ -974,6 +982,12 @@ static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, in
     IFETI_HIP(hipGetLastError());
     c->frag.push_back(cp);
     return cp.frag;
+}
+
+void prepare_operator_copies(ifeti_ctx *c) {
+    if (c->K < 1) return;
+    (void)frag_copy(c, c->Fdd.p, c->n_d, c->n_d, c->K);  // F̊ (48)
+    (void)frag_copy(c, c->Sdd.p, c->n_d, c->n_d, c->K);  // M̊_D^-1 (49)
 }
 
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
@@ -1089,6 +1103,8 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             // tall operator, few columns (coarse solve of a block of load cases): 64-row tiles, inner range
             // split 8 ways over blockIdx.z, partials summed in split order
             f.ksplit = 8;
+            IFETI_REQUIRE(!c->no_alloc || c->w_split.n >= (size_t)f.ksplit * ncols * M, IFETI_EINVAL,
+                          "allocation-free call: the split-K partial buffer is too small (ifeti_apply_F grows it)");
             c->w_split.ensure((size_t)f.ksplit * ncols * M, c->stream);
             f.part = c->w_split.p;
             launch_big<1, 2, 4, 128, 8>(f, c->stream, prof.start(), prof.stop());  // 8 pairs in flight per wave

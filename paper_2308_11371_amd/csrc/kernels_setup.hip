@@ -652,6 +652,7 @@ void coarse_inverse_device(ifeti_ctx *c, CoarseSolver &co, const std::vector<dou
 void ensure_coarse_inverse(ifeti_ctx *c, CoarseSolver &co) {
     if (co.inv_ready) return;
     IFETI_REQUIRE(!c->capturing, IFETI_EINVAL, "coarse inverse must exist before graph capture");
+    IFETI_REQUIRE(!c->no_alloc, IFETI_EINVAL, "allocation-free call: the explicit coarse inverse is not built");
     coarse_inverse_device(c, co, co.h_bandL, co.bw);
 }
 

@@ -1710,26 +1710,33 @@ void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long
 // the coarse branch (restriction, assembly, symmetric coarse solve) runs on the
 // side stream while the main stream runs the dominant contraction; the
 // prolongation is folded into the final scatter.
-void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
-    ensure_work(c, nrhs);
+void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double *Y, double *Yc, double *cb,
+                  double *zP, double *yP, bool side, const double *dot_w, double *dot_part) {
     const int N = c->N, nd = c->n_d, K = c->K;
     const int cols = N * nrhs;
-    {
+    GemmGroup g1;  // B_d^T lam fused into the staging
+    g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
+    g1.K = K;
+    if (side) {
         // the dominant contraction runs beside the coarse branch, into its own buffer
-        SideStream side(c);
-        GemmGroup g1;  // B_d^T lam fused into the staging
-        g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
-        g1.K = K;
-        gemm(c, &g1, 1, c->w_Y.p, nd, 0, nd, cols, false, 0, "F_gemm");
+        SideStream s(c);
+        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+    } else {
+        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
     }
-    op_restrict_cells(c, c->Wc.p, lam, c->L, c->w_c.p, nrhs, "F_restrict");
-    op_assemble_primal(c, c->w_c.p, nullptr, 0, 1.0, c->w_zP.p, c->nP, nrhs);
-    op_coarse_solve(c, c->w_zP.p, c->nP, c->w_yP.p, c->nP, nrhs, 1.0);
-    op_prolong_cells(c, c->Wc.p, c->w_yP.p, c->nP, c->w_Yc.p, nrhs, false, "F_prolong");
-    join_side(c);
-    op_scatter(c, c->w_Y.p, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, c->w_Yc.p);
+    op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
+    op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
+    op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
+    op_prolong_cells(c, c->Wc.p, yP, c->nP, Yc, nrhs, false, "F_prolong");
+    if (side) join_side(c);
+    op_scatter(c, Y, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, Yc);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
+}
+
+void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
+    ensure_work(c, nrhs);
+    apply_F_into(c, lam, out, nrhs, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p, c->w_yP.p, true, dot_w, dot_part);
 }
 
 // ------------------------------------------------------------------ M̊_D^-1 (49)

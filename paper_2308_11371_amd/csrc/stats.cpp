@@ -39,7 +39,8 @@ static bool filter_match(const std::string &filter, const char *name) {
 }
 
 Prof::Prof(ifeti_ctx *c, const char *name, double flops, double bytes, bool in_packet)
-    : c_(c), id_(stat_id(c, name)), in_packet_(in_packet) {
+    : c_(c), id_(c->no_alloc ? -1 : stat_id(c, name)), in_packet_(in_packet) {
+    if (id_ < 0) return;  // allocation-free call: no statistics entries, no events
     KernelStat &k = c->kstats[id_];
     k.launches += 1;
     k.flops += flops;

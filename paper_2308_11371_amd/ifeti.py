@@ -28,7 +28,7 @@ EXPORTED = ("ifeti_create", "ifeti_destroy", "ifeti_last_error", "ifeti_get_size
             "ifeti_apply_A", "ifeti_solve_interface", "ifeti_recover_displacement", "ifeti_solve",
             "ifeti_get_stats", "ifeti_reset_stats", "ifeti_compliance_grad", "ifeti_update_widths",
             "ifeti_build_exact", "ifeti_exact_apply_F", "ifeti_exact_apply_MD", "ifeti_exact_solve",
-            "ifeti_exact_cell_blocks", "ifeti_cell_displacements")
+            "ifeti_exact_cell_blocks", "ifeti_cell_displacements", "ifeti_apply_F_noalloc")
 
 
 class LatticeDesc(ctypes.Structure):
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ifeti_build_reduced_basis": [P, I, D, P, P, P],
         "ifeti_get_coefficients": [P, P, P, P],
         "ifeti_apply_F": [P, P, P, I],
+        "ifeti_apply_F_noalloc": [P, P, P, I],
         "ifeti_apply_MD": [P, P, P, I],
         "ifeti_apply_MD_rom": [P, P, P, I],
         "ifeti_cell_displacements": [P, P, P, I],
@@ -282,6 +283,10 @@ class Context:
 
     def apply_F(self, lam, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_F, lam, self.sizes.L, nrhs, out)
+
+    def apply_F_noalloc(self, lam, nrhs=1, out=None):
+        """F̊ lam by the allocation-free entry point (its output tensor must be given or is made here)."""
+        return self._apply(self.lib.ifeti_apply_F_noalloc, lam, self.sizes.L, nrhs, out)
 
     def apply_MD(self, r, nrhs=1, out=None):
         return self._apply(self.lib.ifeti_apply_MD, r, self.sizes.L, nrhs, out)
