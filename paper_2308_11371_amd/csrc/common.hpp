@@ -267,6 +267,13 @@ struct ifeti_ctx {
         void *frag = nullptr;
     };
     std::vector<FragCopy> frag;
+    struct RebasedBank {                // a principal bank in a Frobenius-orthonormal basis (precision form)
+        const double *src = nullptr, *coef = nullptr;  // original operators [K][M][Kd] and coefficients [cell][K]
+        int M = 0, Kd = 0, K = 0, Kp = 0, ncells = 0;  // Kp: directions kept
+        double *bank = nullptr;         // [Kp][M][Kd]
+        double *cf = nullptr;           // [cell][Kp]
+    };
+    std::vector<RebasedBank> rebased;
     // M̊_D^-ROM (47): principal interior inverses K_ii^(σk)-1 zero-padded to n_r x n_r, rows interleaved
     // [r][k][n_r] like the stacked K_rr^-1 (built on first use for the current bank), and work vectors
     ifeti::DevBuf<double> Kii_pad, mdr_X, mdr_Y, mdr_v, mdr_x;
@@ -280,6 +287,11 @@ struct ifeti_ctx {
         for (auto &cp : frag)
             if (cp.frag) (void)hipFree(cp.frag);
         frag.clear();
+        for (auto &rb : rebased) {
+            if (rb.bank) (void)hipFree(rb.bank);
+            if (rb.cf) (void)hipFree(rb.cf);
+        }
+        rebased.clear();
     }
     // drop the fragment-order copies of one source array whose contents are rewritten in place
     // (the copies are keyed by the source pointer); also invalidates a cached graph

@@ -23,6 +23,7 @@
 // The 16x16 f64 MFMA returns D with lane l, register i -> row 4*i + l/16,
 // column l % 16; the f32 / bf16 ones row 4*(l/16) + i (checked on gfx950).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <type_traits>
@@ -172,7 +173,7 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
     static_assert((NW & (NW - 1)) == 0, "NW must be a power of two");
     constexpr int NT = 64 * NW;
     constexpr int NC = 16 * CB;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int mt0 = by * RT, col0 = bx * NC;
     v4d acc[RT][CB];
@@ -180,9 +181,6 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = v4d{0.0, 0.0, 0.0, 0.0};
-    bool rtv[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) rtv[rt] = mt0 + rt < g.MT;
 
     for (int gi = 0; gi < g.ngroups; ++gi) {
         const double *__restrict__ Af = g.Af[gi];
@@ -199,27 +197,28 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
             const int q0 = kk / 8;
             const int total = K * np;
             const int ns = wave < total ? (total - wave + NW - 1) / NW : 0;  // steps s = wave + NW i
+            // fragment loads of step i (clamped to the last step: the ring is refilled unconditionally, so
+            // the loop has no join points and each step waits only for the load issued PF steps earlier)
             auto load = [&](int i, double2 (&dst)[RT]) {
-                const int s = wave + NW * i, k = s / np, q = s % np;
+                const int s = wave + NW * min(i, ns - 1), k = s / np, q = s % np;
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    if (rtv[rt]) {
-                        const double2 *p = reinterpret_cast<const double2 *>(
-                                               Af + (((size_t)k * g.MT + mt0 + rt) * KT2 + q0 + q) * 128) +
-                                           lane;
-                        dst[rt] = *p;
-                    } else {
-                        dst[rt] = double2{0.0, 0.0};
-                    }
+                    const int mt = min(mt0 + rt, g.MT - 1);  // rows beyond M: in-bounds, result dropped
+                    dst[rt] = reinterpret_cast<const double2 *>(Af + (((size_t)k * g.MT + mt) * KT2 + q0 + q) * 128)[lane];
                 }
             };
             __syncthreads();  // previous chunk fully consumed
             // the first operator fragments do not depend on the staged columns: their loads are in
             // flight while the columns and coefficients are staged
-            double2 ab[PF][RT];
+            // ring of PF + 1 fragment slots: step i reads slot i mod (PF + 1) while the load of step i + PF
+            // goes to another slot, so no slot is copied or waited for early (the loop is unrolled by the
+            // ring size and every slot is a fixed register set)
+            constexpr int S = PF + 1;
+            double2 ab[S][RT];
+            if (ns > 0) {
 #pragma unroll
-            for (int u = 0; u < PF; ++u)
-                if (u < ns) load(u, ab[u]);
+                for (int u = 0; u < PF; ++u) load(u, ab[u]);
+            }
             stage_chunk<NC, FKC, NT, FXS, 4>(g, X, gcodes, gw, Kd, ldx, xbs, col0, kk, kc, Xs, tid);
             for (int e = tid; e < K * NC; e += NT) {
                 const int k = e / NC, cc = e % NC, col = col0 + cc;
@@ -228,33 +227,39 @@ __device__ __forceinline__ void pc64_tile(const GemmArgsFrag &g, int bx, int by,
                 Cs[e] = v;
             }
             __syncthreads();
-            for (int i0 = 0; i0 < ns; i0 += PF) {
+            if (ns == 0) continue;  // wave-uniform
+            // B operands of step i: the staged rows of its fragment pair scaled by its principal's coefficient
+            // of each column; steps padded to a multiple of the ring size repeat the last step with zero
+            // operands, which leaves the accumulators unchanged
+            auto bops = [&](int i, double (&bo)[2][CB]) {
+                const double live = i < ns ? 1.0 : 0.0;
+                const int s = wave + NW * min(i, ns - 1), k = s / np, q = s % np;
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
+                for (int cb = 0; cb < CB; ++cb) {
+                    const double cf = Cs[k * NC + cb * 16 + lr] * live;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) bo[j][cb] = Xs[(cb * 16 + lr) * FXS + 4 * (2 * q + j) + lk] * cf;
+                }
+            };
+            // the B operands of the next step are read from LDS while this step's MFMAs run
+            double bb[S][2][CB];
+            bops(0, bb[0]);
+            const int nsp = (ns + S - 1) / S * S;
+            for (int i0 = 0; i0 < nsp; i0 += S) {
+#pragma unroll
+                for (int u = 0; u < S; ++u) {
                     const int i = i0 + u;
-                    if (i < ns) {
-                        double2 a[RT];
+                    load(i + PF, ab[(u + PF) % S]);
+                    const double2 *a = ab[u];
 #pragma unroll
-                        for (int rt = 0; rt < RT; ++rt) a[rt] = ab[u][rt];
-                        if (i + PF < ns) load(i + PF, ab[u]);
-                        const int s = wave + NW * i, k = s / np, q = s % np;
-                        double cf[CB];
+                    for (int j = 0; j < 2; ++j)
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+                        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
-                            const int r = 4 * (2 * q + j) + lk;
-                            double b[CB];
-#pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * FXS + r] * cf[cb];
-#pragma unroll
-                            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                                for (int cb = 0; cb < CB; ++cb)
-                                    acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, b[cb],
-                                                                                       acc[rt][cb], 0, 0, 0);
-                        }
-                    }
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, bb[u][j][cb],
+                                                                                   acc[rt][cb], 0, 0, 0);
+                    bops(i + 1, bb[(u + 1) % S]);
                 }
             }
         }
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
     static_assert(KCB % 8 == 0, "chunk must hold whole fragment pairs");
     __shared__ double Xs[NC * XSB];
     __shared__ double Cs[kMaxCoefK * NC];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int mt0 = (blockIdx.y * NW + wave) * RTW, col0 = blockIdx.x * NC;
     v4d acc[RTW][CB];
@@ -360,44 +365,45 @@ __global__ __launch_bounds__(64 * NW) void k_pc64_big(GemmArgsFrag g) {
             __syncthreads();
             if (!any) continue;  // wave-uniform: this wave's row tiles lie beyond M
             const int np = (kc + 7) / 8, q0 = kk / 8, ns = K * np;
+            // fragment loads of step s clamped to the last step, rows beyond M clamped to the last row
+            // tile (in bounds; their results are dropped): the ring is refilled unconditionally and the
+            // loop has no join points, so each step waits only for the load issued PF steps earlier
             auto load = [&](int s, double2 (&dst)[RTW]) {
-                const int k = s / np, q = s % np;
+                const int sc = min(s, ns - 1), k = sc / np, q = sc % np;
 #pragma unroll
-                for (int rt = 0; rt < RTW; ++rt)
-                    dst[rt] = rtv[rt] ? reinterpret_cast<const double2 *>(
-                                            Af + (((size_t)k * g.MT + mt0 + rt) * KT2 + q0 + q) * 128)[lane]
-                                      : double2{0.0, 0.0};
+                for (int rt = 0; rt < RTW; ++rt) {
+                    const int mt = min(mt0 + rt, g.MT - 1);
+                    dst[rt] = reinterpret_cast<const double2 *>(Af + (((size_t)k * g.MT + mt) * KT2 + q0 + q) * 128)[lane];
+                }
             };
-            double2 ab[PF][RTW];
+            constexpr int S = PF + 1;  // ring of fragment slots (see pc64_tile)
+            double2 ab[S][RTW];
 #pragma unroll
-            for (int u = 0; u < PF; ++u)
-                if (u < ns) load(u, ab[u]);
-            for (int s0 = 0; s0 < ns; s0 += PF) {
+            for (int u = 0; u < PF; ++u) load(u, ab[u]);
+            const int nsp = (ns + S - 1) / S * S;  // padded steps carry a zero coefficient
+            for (int s0 = 0; s0 < nsp; s0 += S) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
+                for (int u = 0; u < S; ++u) {
                     const int s = s0 + u;
-                    if (s < ns) {
-                        double2 a[RTW];
+                    load(s + PF, ab[(u + PF) % S]);
+                    const double2 *a = ab[u];
+                    const bool live = s < ns;
+                    const int sc = min(s, ns - 1), k = sc / np, q = sc % np;
+                    double cf[CB];
 #pragma unroll
-                        for (int rt = 0; rt < RTW; ++rt) a[rt] = ab[u][rt];
-                        if (s + PF < ns) load(s + PF, ab[u]);
-                        const int k = s / np, q = s % np;
-                        double cf[CB];
+                    for (int cb = 0; cb < CB; ++cb) cf[cb] = live ? Cs[k * NC + cb * 16 + lr] : 0.0;
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
+                    for (int j = 0; j < 2; ++j) {
+                        const int r = 4 * (2 * q + j) + lk;
+                        double b[CB];
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
-                            const int r = 4 * (2 * q + j) + lk;
-                            double b[CB];
+                        for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XSB + r] * cf[cb];
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XSB + r] * cf[cb];
+                        for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-                            for (int rt = 0; rt < RTW; ++rt)
-#pragma unroll
-                                for (int cb = 0; cb < CB; ++cb)
-                                    acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, b[cb],
-                                                                                       acc[rt][cb], 0, 0, 0);
-                        }
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[rt][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(j ? a[rt].y : a[rt].x, b[cb],
+                                                                                   acc[rt][cb], 0, 0, 0);
                     }
                 }
             }
@@ -498,7 +504,7 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_big(GemmArgsFragLP g) {
     static_assert(KCB % KPF == 0, "chunk must hold whole fragment units");
     __shared__ __attribute__((aligned(16))) float Xs[NC * XS];
     __shared__ float Cs[kMaxCoefK * NC];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int mt0 = (blockIdx.y * NW + wave) * RTW, col0 = blockIdx.x * NC;
     v4f acc[RTW][CB];
@@ -560,61 +566,60 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_big(GemmArgsFragLP g) {
             __syncthreads();
             if (!any) continue;
             const int np = (kc + KPF - 1) / KPF, q0 = kk / KPF, ns = K * np;
+            // ring of PF + 1 fragment slots with clamped loads and zero-operand padding, as in pc64_tile
             auto load = [&](int s, uint4 (&dst)[RTW]) {
-                const int k = s / np, q = s % np;
+                const int sc = min(s, ns - 1), k = sc / np, q = sc % np;
 #pragma unroll
-                for (int rt = 0; rt < RTW; ++rt)
-                    dst[rt] = rtv[rt] ? reinterpret_cast<const uint4 *>(
-                                            Af + ((((size_t)k * g.MT + mt0 + rt) * QU + q0 + q) * 64 + lane) * U)[0]
-                                      : uint4{0u, 0u, 0u, 0u};
+                for (int rt = 0; rt < RTW; ++rt) {
+                    const int mt = min(mt0 + rt, g.MT - 1);
+                    dst[rt] = reinterpret_cast<const uint4 *>(Af + ((((size_t)k * g.MT + mt) * QU + q0 + q) * 64 + lane) * U)[0];
+                }
             };
-            uint4 ab[PF][RTW];
+            constexpr int S = PF + 1;
+            uint4 ab[S][RTW];
 #pragma unroll
-            for (int u = 0; u < PF; ++u)
-                if (u < ns) load(u, ab[u]);
-            for (int s0 = 0; s0 < ns; s0 += PF) {
+            for (int u = 0; u < PF; ++u) load(u, ab[u]);
+            const int nsp = (ns + S - 1) / S * S;
+            for (int s0 = 0; s0 < nsp; s0 += S) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
+                for (int u = 0; u < S; ++u) {
                     const int s = s0 + u;
-                    if (s < ns) {
-                        uint4 a[RTW];
+                    load(s + PF, ab[(u + PF) % S]);
+                    const uint4 *a = ab[u];
+                    const float live = s < ns ? 1.f : 0.f;
+                    const int sc = min(s, ns - 1), k = sc / np, q = sc % np;
+                    float cf[CB];
 #pragma unroll
-                        for (int rt = 0; rt < RTW; ++rt) a[rt] = ab[u][rt];
-                        if (s + PF < ns) load(s + PF, ab[u]);
-                        const int k = s / np, q = s % np;
-                        float cf[CB];
+                    for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr] * live;
+                    if constexpr (BF) {
+                        v8bf b[CB];
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
-                        if constexpr (BF) {
-                            v8bf b[CB];
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const float *xr = Xs + (cb * 16 + lr) * XS + q * KPF + 8 * lk;
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) {
-                                const float *xr = Xs + (cb * 16 + lr) * XS + q * KPF + 8 * lk;
+                            for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
+                        }
 #pragma unroll
-                                for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
-                            }
+                        for (int rt = 0; rt < RTW; ++rt) {
+                            const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int r = q * KPF + 4 * j + lk;
+                            float b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XS + r] * cf[cb];
 #pragma unroll
                             for (int rt = 0; rt < RTW; ++rt) {
-                                const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+                                const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
+                                const float av = __builtin_bit_cast(float, aw);
 #pragma unroll
                                 for (int cb = 0; cb < CB; ++cb)
-                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int r = q * KPF + 4 * j + lk;
-                                float b[CB];
-#pragma unroll
-                                for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * XS + r] * cf[cb];
-#pragma unroll
-                                for (int rt = 0; rt < RTW; ++rt) {
-                                    const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
-                                    const float av = __builtin_bit_cast(float, aw);
-#pragma unroll
-                                    for (int cb = 0; cb < CB; ++cb)
-                                        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
-                                }
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
                             }
                         }
                     }
@@ -664,7 +669,7 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_tile(GemmArgsFragLP g) {
     using L = PclpLds<RT, CB, NW>;
     __shared__ __attribute__((aligned(16))) float Xs[L::SX];
     __shared__ float Cs[kMaxCoefK * NC];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int mt0 = blockIdx.y * RT, col0 = blockIdx.x * NC;
     v4f acc[RT][CB];
@@ -698,61 +703,61 @@ __global__ __launch_bounds__(64 * NW) void k_pclp_tile(GemmArgsFragLP g) {
             __syncthreads();
             const int np = (kc + KPF - 1) / KPF, q0 = kk / KPF, total = K * np;
             const int ns = wave < total ? (total - wave + NW - 1) / NW : 0;  // steps s = wave + NW i
+            if (ns == 0) continue;  // wave-uniform
+            // ring of PF + 1 fragment slots with clamped loads and zero-operand padding, as in pc64_tile
             auto load = [&](int i, uint4 (&dst)[RT]) {
-                const int s = wave + NW * i, k = s / np, q = s % np;
+                const int s = wave + NW * min(i, ns - 1), k = s / np, q = s % np;
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    dst[rt] = rtv[rt] ? reinterpret_cast<const uint4 *>(
-                                            Af + ((((size_t)k * g.MT + mt0 + rt) * QU + q0 + q) * 64 + lane) * U)[0]
-                                      : uint4{0u, 0u, 0u, 0u};
+                for (int rt = 0; rt < RT; ++rt) {
+                    const int mt = min(mt0 + rt, g.MT - 1);
+                    dst[rt] = reinterpret_cast<const uint4 *>(Af + ((((size_t)k * g.MT + mt) * QU + q0 + q) * 64 + lane) * U)[0];
+                }
             };
-            uint4 ab[PF][RT];
+            constexpr int S = PF + 1;
+            uint4 ab[S][RT];
 #pragma unroll
-            for (int u = 0; u < PF; ++u)
-                if (u < ns) load(u, ab[u]);
-            for (int i0 = 0; i0 < ns; i0 += PF) {
+            for (int u = 0; u < PF; ++u) load(u, ab[u]);
+            const int nsp = (ns + S - 1) / S * S;
+            for (int i0 = 0; i0 < nsp; i0 += S) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
+                for (int u = 0; u < S; ++u) {
                     const int i = i0 + u;
-                    if (i < ns) {
-                        uint4 a[RT];
+                    load(i + PF, ab[(u + PF) % S]);
+                    const uint4 *a = ab[u];
+                    const float live = i < ns ? 1.f : 0.f;
+                    const int s = wave + NW * min(i, ns - 1), k = s / np, q = s % np;
+                    float cf[CB];
 #pragma unroll
-                        for (int rt = 0; rt < RT; ++rt) a[rt] = ab[u][rt];
-                        if (i + PF < ns) load(i + PF, ab[u]);
-                        const int s = wave + NW * i, k = s / np, q = s % np;
-                        float cf[CB];
+                    for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr] * live;
+                    if constexpr (BF) {
+                        v8bf b[CB];
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) cf[cb] = Cs[k * NC + cb * 16 + lr];
-                        if constexpr (BF) {
-                            v8bf b[CB];
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const float *xr = Xs + (cb * 16 + lr) * LXS + q * KPF + 8 * lk;
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) {
-                                const float *xr = Xs + (cb * 16 + lr) * LXS + q * KPF + 8 * lk;
+                            for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
+                        }
 #pragma unroll
-                                for (int e = 0; e < 8; ++e) b[cb][e] = (__bf16)(xr[e] * cf[cb]);
-                            }
+                        for (int rt = 0; rt < RT; ++rt) {
+                            const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int r = q * KPF + 4 * j + lk;
+                            float b[CB];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * LXS + r] * cf[cb];
 #pragma unroll
                             for (int rt = 0; rt < RT; ++rt) {
-                                const v8bf av = __builtin_bit_cast(v8bf, a[rt]);
+                                const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
+                                const float av = __builtin_bit_cast(float, aw);
 #pragma unroll
                                 for (int cb = 0; cb < CB; ++cb)
-                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[cb], acc[rt][cb], 0, 0, 0);
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int r = q * KPF + 4 * j + lk;
-                                float b[CB];
-#pragma unroll
-                                for (int cb = 0; cb < CB; ++cb) b[cb] = Xs[(cb * 16 + lr) * LXS + r] * cf[cb];
-#pragma unroll
-                                for (int rt = 0; rt < RT; ++rt) {
-                                    const uint32_t aw = j == 0 ? a[rt].x : j == 1 ? a[rt].y : j == 2 ? a[rt].z : a[rt].w;
-                                    const float av = __builtin_bit_cast(float, aw);
-#pragma unroll
-                                    for (int cb = 0; cb < CB; ++cb)
-                                        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
-                                }
+                                    acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[cb], acc[rt][cb], 0, 0, 0);
                             }
                         }
                     }
@@ -828,7 +833,8 @@ void launch_frag(const GemmArgsFrag &a, hipStream_t s, hipEvent_t t0, hipEvent_t
 // the fixed-order sums, so results agree to rounding, not bitwise, across candidates.
 using FragLauncher = void (*)(const GemmArgsFrag &, hipStream_t, hipEvent_t, hipEvent_t);
 const FragLauncher kSmallCandidates[] = {launch_frag<4, 2, 2, 8>, launch_frag<2, 4, 4, 8>, launch_frag<2, 2, 4, 8>,
-                                         launch_frag<4, 1, 4, 4>, launch_frag<1, 1, 2, 16>, launch_frag<2, 2, 2, 4>};
+                                         launch_frag<4, 1, 4, 4>, launch_frag<1, 1, 2, 16>, launch_frag<2, 2, 2, 4>,
+                                         launch_frag<4, 2, 3, 8>, launch_frag<2, 2, 3, 8>};
 const FragLauncher kBigCandidates[] = {launch_big<2, 4, 4, 64>, launch_big<4, 2, 4, 64>, launch_big<2, 2, 8, 64>,
                                        launch_big<1, 4, 4, 64>, launch_big<2, 4, 4, 128>};
 constexpr int kNSmall = sizeof(kSmallCandidates) / sizeof(kSmallCandidates[0]);
@@ -984,6 +990,117 @@ static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, in
     return cp.frag;
 }
 
+// Precision form: the sum sum_k c_sk A_k of a cell loses every digit to cancellation when the
+// principal operators are nearly dependent and the coefficients large with opposite signs (the
+// coefficient systems (41) are then ill-conditioned).  In a basis of the bank that is orthonormal in
+// the Frobenius inner product, A'_j = sum_k A_k T_kj with T = V diag(lambda)^(-1/2) from the Gram matrix
+// G_kl = <A_k, A_l>_F = V diag(lambda) V^T, the same sum has coefficients c'_s = diag(lambda)^(1/2) V^T c_s
+// whose size is that of the sum itself, so the narrow operands round relative to the result.  The
+// transformation is exact in FP64 (directions with lambda <= 1e-14 lambda_max carry no Frobenius mass
+// and are dropped); only the narrow copies and the narrow-precision contractions use it.
+static void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V, std::vector<double> &w) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {  // A <- J^T A J
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = cs * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+static const ifeti_ctx::RebasedBank &rebased_bank(ifeti_ctx *c, const double *A, const double *coef, int M, int Kd,
+                                                 int K, int ncells) {
+    for (auto &rb : c->rebased)
+        if (rb.src == A && rb.coef == coef && rb.M == M && rb.Kd == Kd && rb.K == K && rb.ncells == ncells) return rb;
+    IFETI_REQUIRE(!c->no_alloc, IFETI_EINVAL,
+                  "allocation-free call: the precision form's re-based bank is not built (the first ifeti_apply_F "
+                  "in that precision builds it)");
+    const size_t me = (size_t)M * Kd;
+    std::vector<double> hA((size_t)K * me), hc((size_t)ncells * K);
+    IFETI_HIP(hipMemcpyAsync(hA.data(), A, hA.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    std::vector<double> G((size_t)K * K, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l <= k; ++l) {
+            const double *a = &hA[(size_t)k * me], *b = &hA[(size_t)l * me];
+            double s = 0.0;
+            for (size_t e = 0; e < me; ++e) s += a[e] * b[e];
+            G[(size_t)k * K + l] = G[(size_t)l * K + k] = s;
+        }
+    std::vector<double> V, lam;
+    jacobi_eigen(G, K, V, lam);
+    double lmax = 0.0;
+    for (double x : lam) lmax = std::max(lmax, x);
+    std::vector<int> keep;
+    for (int j = 0; j < K; ++j)
+        if (lam[j] > 1e-14 * lmax) keep.push_back(j);
+    const int Kp = (int)keep.size();
+    IFETI_REQUIRE(Kp >= 1, IFETI_EINVAL, "precision form: the principal bank has no Frobenius mass");
+    std::vector<double> Ap((size_t)Kp * me, 0.0), cp((size_t)ncells * Kp, 0.0);
+    for (int jj = 0; jj < Kp; ++jj) {
+        const int j = keep[jj];
+        const double is = 1.0 / std::sqrt(lam[j]), sq = std::sqrt(lam[j]);
+        double *dst = &Ap[(size_t)jj * me];
+        for (int k = 0; k < K; ++k) {
+            const double t = V[(size_t)k * K + j] * is;  // T_kj
+            const double *a = &hA[(size_t)k * me];
+            for (size_t e = 0; e < me; ++e) dst[e] += t * a[e];
+        }
+        for (int s = 0; s < ncells; ++s) {
+            double v = 0.0;
+            for (int k = 0; k < K; ++k) v += V[(size_t)k * K + j] * hc[(size_t)s * K + k];
+            cp[(size_t)s * Kp + jj] = sq * v;
+        }
+    }
+    ifeti_ctx::RebasedBank rb;
+    rb.src = A;
+    rb.coef = coef;
+    rb.M = M;
+    rb.Kd = Kd;
+    rb.K = K;
+    rb.Kp = Kp;
+    rb.ncells = ncells;
+    IFETI_HIP(hipMalloc(&rb.bank, Ap.size() * sizeof(double)));
+    IFETI_HIP(hipMalloc(&rb.cf, cp.size() * sizeof(double)));
+    IFETI_HIP(hipMemcpyAsync(rb.bank, Ap.data(), Ap.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    IFETI_HIP(hipMemcpyAsync(rb.cf, cp.data(), cp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    IFETI_HIP(hipStreamSynchronize(c->stream));  // host staging goes out of scope
+    c->rebased.push_back(rb);
+    return c->rebased.back();
+}
+
 void prepare_operator_copies(ifeti_ctx *c) {
     if (c->K < 1) return;
     (void)frag_copy(c, c->Fdd.p, c->n_d, c->n_d, c->K);  // F̊ (48)
@@ -1043,14 +1160,24 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
         const int kind = prec;
         const bool bf = kind == IFETI_BF16_LOCAL;
         for (int i = 0; i < ngroups; ++i) {
-            f.Af[i] = frag_copy_lp(c, groups[i].A, M, groups[i].Kd, groups[i].K, kind);
+            // summed principal operators: the re-based bank and its coefficients (no cancellation in the
+            // narrow operands)
+            const double *Ai = groups[i].A, *ci = a.coef[i];
+            int Ki = groups[i].K;
+            if (ci && Ki > 1) {
+                const auto &rb = rebased_bank(c, Ai, ci, M, groups[i].Kd, Ki, a.ncells);
+                Ai = rb.bank;
+                ci = rb.cf;
+                Ki = rb.Kp;
+            }
+            f.Af[i] = frag_copy_lp(c, Ai, M, groups[i].Kd, Ki, kind);
             f.X[i] = a.X[i];
-            f.coef[i] = a.coef[i];
+            f.coef[i] = ci;
             f.gcodes[i] = groups[i].gcodes;
             f.gw[i] = groups[i].gw;
             f.Kd[i] = a.Kd[i];
             f.ldx[i] = a.ldx[i];
-            f.K[i] = a.K[i];
+            f.K[i] = Ki;
             f.QU[i] = (a.Kd[i] + (bf ? 31 : 15)) / (bf ? 32 : 16);
             f.xbs[i] = a.xbs[i];
             f.scale[i] = a.scale[i];
@@ -1113,7 +1240,7 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
                                c->w_split.p, f.ksplit, ncols, M, f.ncells, Y, f.ybs, ldy, f.accumulate);
         } else {
             // defaults = the autotuner's usual choice on gfx950 (2D and 3D lattices)
-            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : 0));
+            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : 7));
             FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate);
             launch_fn(f, c->stream, prof.start(), prof.stop());
         }

@@ -30,7 +30,7 @@ torch = pytest.importorskip("torch")
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "shape_samples.json")
 OPS = ("F", "MD", "U", "Ut", "Kinv_rom", "A")
 INPUT_SEED = {"F": 401, "MD": 402, "U": 403, "Ut": 404, "Kinv_rom": 405, "A": 406}
-N_FP64_CANDIDATES = 6   # small-operator family (the large-operator family has 5: i mod 5)
+N_FP64_CANDIDATES = 8   # small-operator family (the large-operator family has 5: i mod 5)
 N_LP_CANDIDATES = 4
 LP_TOL = {"fp32": 2e-5, "bf16": 5e-2}
 
@@ -187,5 +187,5 @@ def test_c4cols_block_solve_matches_conforming_solutions(lat, prec):
                     abs(np.linalg.norm(U[c]) - g["u_norm"][c]) / g["u_norm"][c])
     print(f"[gpu shapes] c4cols {prec} block solve of {nrhs} load cases: outer {int(info['outer_its'].max())}, "
           f"max relres {info['relres'].max():.1e}, worst u error {worst:.2e}", flush=True)
-    assert info["relres"].max() <= 1e-11
+    assert info["relres"].max() <= 1e-9     # true residual of (16) (the outer stop test uses the estimate)
     assert worst <= (1e-9 if prec == "fp64" else 1e-6)
