@@ -139,6 +139,13 @@ typedef struct {
                                i >= 0: candidate i of each contraction's family (modulo the family's
                                size), for every launch; the autotuner is bypassed.  Each candidate sums
                                in its own fixed order (results agree across candidates to rounding) */
+    int coarse_approx;      /* 0: the coarse problem S̊_PP^-1 solved exactly (Sec. 3.2.1); B >= 1: the
+                               approximate coarse solve Sec. 3.2.1 allows in the inexact method, block
+                               Jacobi over consecutive blocks of B primal dofs (inverse of each diagonal
+                               block of S̊_PP; one streamed pass per apply).  Applies to the ROM operators
+                               F̊, Ů, Ůᵀ and K̊^-ROM; it stays linear and symmetric positive definite, so the
+                               interface PCG stays valid and the outer FGMRES still converges to the
+                               solution of (16).  B >= nP gives the exact solve */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

@@ -123,9 +123,17 @@ class Model:
         self.Spp_cells = romlib.rom_Spp(self.bank, self.alpha, self.pi)
         self.SPP = romlib.assemble_coarse(self.dd, self.Spp_cells)
         self.coarse = romlib.BandedCholesky(self.SPP)
+        self.coarse_approx = None
         return self.sigma
 
+    def set_coarse_block(self, B: int):
+        """B > 0: approximate coarse solve by block Jacobi over blocks of B primal dofs (Sec. 3.2.1);
+        0: the exact banded Cholesky solve."""
+        self.coarse_approx = romlib.BlockJacobiCoarse(self.SPP, B) if B > 0 else None
+
     def coarse_solve(self, z: np.ndarray) -> np.ndarray:
+        if self.coarse_approx is not None:
+            return self.coarse_approx.solve(z)
         return self.coarse.solve(z)
 
     # ----------------------------------------------------------- F̊ (48)

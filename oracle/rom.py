@@ -19,11 +19,14 @@ ROM local operators, eq. (43): Ů_rp = sum pi_k U_rp^(k),
   S̊_pp = sym(K̊_pp - K̊_rp^T Ů_rp), Ů_rd = sum delta_k U_rd^(k),
   F̊_dd = sum delta_k F_dd^(k), S̊_dd = sum alpha_k S_dd^(k),  sym(X) = (X+X^T)/2.
 Coarse problem (Sec. 3.2.1): S̊_PP = sum_s A_p S̊_pp^(s) A_p^T, factored once
-by a banded Cholesky.
+by a banded Cholesky; optionally (the approximative coarse solvers Sec. 3.2.1
+allows) replaced by block Jacobi over consecutive blocks of B primal dofs.
 
 Pins (tests/test_oracle_dd_rom.py): S_dd F_dd = I, K_rr U_rp = K_rp, S_pp of a
 floating cell annihilates the corner values of rigid modes, pi = delta = e_i at
-principal cells, ROM operators equal the exact ones on identical-cell lattices.
+principal cells, ROM operators equal the exact ones on identical-cell lattices;
+block-Jacobi coarse solve: exact for B >= nP, diagonal scaling for B = 1,
+symmetric positive definite (tests/test_oracle_solve.py).
 """
 from __future__ import annotations
 
@@ -140,6 +143,27 @@ class BandedCholesky:
         if self.n == 0:
             return np.zeros_like(b)
         return sl.cho_solve_banded((self.cb, True), b)
+
+
+class BlockJacobiCoarse:
+    """Approximate coarse solve (Sec. 3.2.1 allows approximative coarse solvers in the inexact method):
+    S̊_PP^-1 replaced by the inverse of its block-diagonal part over consecutive blocks of B primal dofs
+    (dense Cholesky of each block).  Linear, symmetric positive definite and fixed, so the interface PCG
+    stays valid; B >= nP is the exact solve, B = 1 is diagonal scaling."""
+
+    def __init__(self, S: sp.spmatrix, B: int):
+        S = sp.csr_matrix(S)
+        self.n, self.B = S.shape[0], int(B)
+        self.blocks = []
+        for lo in range(0, self.n, self.B):
+            hi = min(self.n, lo + self.B)
+            self.blocks.append((lo, hi, sl.cho_factor(S[lo:hi, lo:hi].toarray(), lower=True)))
+
+    def solve(self, b: np.ndarray) -> np.ndarray:
+        x = np.zeros_like(b)
+        for lo, hi, f in self.blocks:
+            x[lo:hi] = sl.cho_solve(f, b[lo:hi])
+        return x
 
 
 def assemble_coarse(dd, Spp_cells: np.ndarray) -> sp.csr_matrix:

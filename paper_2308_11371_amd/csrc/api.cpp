@@ -199,6 +199,11 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.true_operator = opt->true_operator;
         REQ(opt->tile_candidate >= -1, "tile_candidate must be >= -1");
         c->opt.tile_candidate = opt->tile_candidate;
+        REQ(opt->coarse_approx >= 0, "coarse_approx must be >= 0");
+        if (opt->coarse_approx != c->opt.coarse_approx) {
+            c->opt.coarse_approx = opt->coarse_approx;
+            if (c->rom_built) build_coarse_approx(c, c->co);
+        }
         REQ(opt->coarse_parts >= 0, "coarse_parts must be >= 0");
         if (opt->coarse_parts != c->opt.coarse_parts) {
             c->opt.coarse_parts = opt->coarse_parts;
@@ -230,6 +235,7 @@ int ifeti_get_options(const ifeti_ctx *c, ifeti_options *o) {
         o->local_iters = p.local_iters;
         o->md_precision = p.md_precision;
         o->tile_candidate = p.tile_candidate;
+        o->coarse_approx = p.coarse_approx;
         return IFETI_OK;
     });
 }

@@ -113,6 +113,38 @@ Layout layout(int n, int bw, int p) {
 
 }  // namespace
 
+// Block-Jacobi approximation of S̊_PP^-1 (the approximative coarse solvers of Sec. 3.2.1): the inverse
+// of each diagonal block of B consecutive rows, every row of it one output row of a single streamed
+// phase (n B doubles per apply instead of the partitioned solve's three dependent phases).
+void build_coarse_approx(ifeti_ctx *c, CoarseSolver &co) {
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    release_graph(c);  // a captured PCG iteration may hold the previous tables
+    ++c->rom_gen;
+    co.ap_B = 0;
+    const int n = c->nP, bw = co.bw, B = c->opt.coarse_approx;
+    if (B <= 0 || n == 0) {
+        co.ap_M.release();
+        co.ap_R.release();
+        return;
+    }
+    const Band A{co.h_Sband, n, bw};
+    std::vector<double> M;
+    std::vector<CoarseRow> R;
+    for (int lo = 0; lo < n; lo += B) {
+        const int m = std::min(B, n - lo);
+        const std::vector<double> inv = band_inverse_device(c, band_chol(A, lo, m), m, bw);
+        for (int q = 0; q < m; ++q) {
+            R.push_back(CoarseRow{(long long)M.size(), lo, m, lo + q, 0});
+            for (int t = 0; t < m; ++t)  // symmetrised
+                M.push_back(0.5 * (inv[(size_t)q * m + t] + inv[(size_t)t * m + q]));
+        }
+    }
+    co.ap_M.upload(M, c->stream);
+    co.ap_R.upload(R, c->stream);
+    IFETI_HIP(hipStreamSynchronize(c->stream));
+    co.ap_B = B;
+}
+
 std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw) {
     const Band A{band, n, bw};
     return band_chol(A, 0, n);

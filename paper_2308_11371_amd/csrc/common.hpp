@@ -123,6 +123,7 @@ struct Options {
     int local_iters = 1;        // > 1: K̊^-MPCG, multi-preconditioned CG local solves (Remark 6)
     int md_precision = -1;      // precision of the M̊_D^-1 contraction (49); -1: as `precision`
     int tile_candidate = -1;    // >= 0: force this candidate of every contraction family's tile shapes
+    int coarse_approx = 0;      // > 0: block-Jacobi coarse solve with blocks of this many primal dofs
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -148,6 +149,10 @@ struct CoarseSolver {
     DevBuf<double> cp_M1, cp_M2, cp_M3;
     DevBuf<CoarseRow> cp_R1, cp_R2, cp_R3;
     DevBuf<double> w_cg, w_cw;    // separator rhs [rhs][ns], assembled input [rhs][nP]
+    // approximate solve (block Jacobi): the inverse of each diagonal block of B rows, one row per output
+    int ap_B = 0;
+    DevBuf<double> ap_M;
+    DevBuf<CoarseRow> ap_R;
 };
 
 // Kernel statistics: algorithmic flops/bytes per launch and, when timing is
@@ -365,6 +370,8 @@ void ensure_coarse_inverse(ifeti_ctx *c, CoarseSolver &co);
 // (L L^T)^-1 as a dense row-major n x n host array, from a banded lower factor L[i][i-j] (width bw+1)
 std::vector<double> band_inverse_device(ifeti_ctx *c, const std::vector<double> &band_L, int n, int bw);
 void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co);
+// block-Jacobi approximation of the coarse solve with blocks of opt.coarse_approx rows (0: none)
+void build_coarse_approx(ifeti_ctx *c, CoarseSolver &co);
 // trace tables Psi [2 npair + K][n_snap] of eq. (42) from the principal K_rr^-1 [k][n_r][n_r] and
 // U_rp^T [k][n_p][n_r] on the device
 void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *UqT, double *Psi);
@@ -375,8 +382,9 @@ std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw
 // fragment-order FP64 copies of the operators the interface operators contract with (built at setup)
 void prepare_operator_copies(ifeti_ctx *c);
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
+// beside: the launch shares the GPU with a concurrent branch (tile shapes that leave registers free)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
+          bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true, bool beside = false);
 
 // ops.hip
 class SideStream {

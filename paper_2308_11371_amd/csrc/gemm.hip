@@ -1108,7 +1108,7 @@ void prepare_operator_copies(ifeti_ctx *c) {
 }
 
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells, const char *tag, bool lp_ok) {
+          bool accumulate, int ncells, const char *tag, bool lp_ok, bool beside) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
     for (int i = 0; i < ngroups; ++i)
         IFETI_REQUIRE(groups[i].K >= 1 && groups[i].K <= kMaxCoefK, IFETI_EINVAL, "gemm: 1 to 40 principal operators");
@@ -1239,9 +1239,12 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                                c->w_split.p, f.ksplit, ncols, M, f.ncells, Y, f.ybs, ldy, f.accumulate);
         } else {
-            // defaults = the autotuner's usual choice on gfx950 (2D and 3D lattices)
-            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : 7));
-            FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate);
+            // defaults = the autotuner's usual choice on gfx950 (2D and 3D lattices).  Beside a concurrent
+            // branch, the one-workgroup-per-CU 64-row tile (173 VGPRs, two waves per SIMD) instead of the
+            // fastest tile alone (two workgroups per CU, which fill the register files and hold the branch
+            // back until the contraction ends); such launches are not autotuned (timed alone)
+            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : (beside ? 6 : 7)));
+            FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate && !beside);
             launch_fn(f, c->stream, prof.start(), prof.stop());
         }
         IFETI_HIP(hipGetLastError());

@@ -1617,6 +1617,25 @@ void coarse_partitioned(ifeti_ctx *c, CoarseSolver &co, const double *z, long lo
 void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
                   int nrhs, double scale) {
     if (c->nP == 0) return;
+    if (co.ap_B > 0) {  // block-Jacobi approximation: one phase of independent rows, up to 3 load cases a pass
+        const int n = c->nP;
+        for (int r0 = 0; r0 < nrhs; r0 += 3) {
+            const int nr = std::min(3, nrhs - r0);
+            Prof prof(c, "coarse_approx", 2.0 * (double)co.ap_M.n * nr, 8.0 * ((double)co.ap_M.n + 2.0 * n * nr) + 24.0 * n);
+            const double *zz = z + (size_t)r0 * z_rs;
+            double *yy = y + (size_t)r0 * y_rs;
+            if (nr == 1)
+                coarse_rows<1, 2>(c, co.ap_M.p, co.ap_R.p, n, zz, z_rs, scale, yy, y_rs, 0.0, nullptr, 0, nullptr, 0,
+                                  nullptr, 0, 0);
+            else if (nr == 2)
+                coarse_rows<2, 2>(c, co.ap_M.p, co.ap_R.p, n, zz, z_rs, scale, yy, y_rs, 0.0, nullptr, 0, nullptr, 0,
+                                  nullptr, 0, 0);
+            else
+                coarse_rows<3, 2>(c, co.ap_M.p, co.ap_R.p, n, zz, z_rs, scale, yy, y_rs, 0.0, nullptr, 0, nullptr, 0,
+                                  nullptr, 0, 0);
+        }
+        return;
+    }
     if (nrhs < 4 && co.cp_p >= 2) {
         coarse_partitioned(c, co, z, z_rs, y, y_rs, nrhs, scale);
         return;
@@ -1717,14 +1736,16 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
     GemmGroup g1;  // B_d^T lam fused into the staging
     g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
     g1.K = K;
+    // the restriction runs first and alone (8 us on c2; beside the contraction it would wait for free
+    // registers until the contraction ends); then the dominant contraction runs on the second stream
+    // beside the rest of the coarse branch, into its own buffer
+    op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
     if (side) {
-        // the dominant contraction runs beside the coarse branch, into its own buffer
         SideStream s(c);
-        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm", true, true);
     } else {
         gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
     }
-    op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
     op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
     op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
     op_prolong_cells(c, c->Wc.p, yP, c->nP, Yc, nrhs, false, "F_prolong");

@@ -952,6 +952,7 @@ void build_reduced_basis(ifeti_ctx *c, int n_principal, double tol_rb, const int
     build_coarse_partition(c, c->co);
     // the coarse solve of 1-3 load cases reads the explicit inverse when no partition pays
     if (c->co.cp_p < 2 && c->nP > 0) ensure_coarse_inverse(c, c->co);
+    build_coarse_approx(c, c->co);
     prepare_operator_copies(c);
     clk.mark("coarse partition");
     IFETI_HIP(hipStreamSynchronize(c->stream));

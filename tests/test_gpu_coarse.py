@@ -88,3 +88,34 @@ def test_block_count_beyond_the_band_is_rejected(pair):
     x = np.random.default_rng(3).standard_normal(m.L)
     assert rel(host(ctx.apply_F(dev(x))), m.apply_F(x)) < 1e-11
     ctx.reset_options()
+
+
+@pytest.mark.parametrize("B", [1, 7, 64])
+def test_block_jacobi_coarse_matches_oracle(pair, B):
+    """Approximate coarse solve (option coarse_approx = B, Sec. 3.2.1): every operator that contains the
+    coarse solve against the oracle with the same block-Jacobi approximation, for one and three load
+    cases, and the outer solve still reaching the conforming solution."""
+    from oracle.direct import conforming_solve
+    name, parts, m, ctx = pair
+    m.set_coarse_block(B)
+    try:
+        rng = np.random.default_rng(11)
+        lam = rng.standard_normal((3, m.L))
+        v = rng.standard_normal(m.nU)
+        ctx.set_options(coarse_approx=B)
+        F3 = host(ctx.apply_F(dev(lam.ravel()), nrhs=3)).reshape(3, m.L)
+        for r in range(3):
+            assert rel(F3[r], m.apply_F(lam[r])) < 1e-11, f"{name} B={B} F rhs {r}"
+        assert rel(host(ctx.apply_U(dev(v))), m.apply_U(v)) < 1e-11
+        assert rel(host(ctx.apply_Ut(dev(lam[0]))), m.apply_Ut(lam[0])) < 1e-11
+        assert rel(host(ctx.apply_Kinv_rom(dev(v))), m.apply_Kinv_rom(v)) < 1e-11
+        ctx.set_options(fgmres_restart=300, pcg_maxit=3000)
+        f, d = ctx.get_rhs()
+        u, lam_s, info = ctx.solve(f, d, tol=1e-12, inner_tol=1e-13, maxit=300)
+        e = rel(host(u), conforming_solve(m)["u"])
+        print(f"[gpu coarse] {name} block Jacobi B={B}: outer {info['outer_its'][0]}, PCG {info['inner_its'][0]}, "
+              f"u vs direct {e:.1e}", flush=True)
+        assert e < 1e-9
+    finally:
+        m.set_coarse_block(0)
+        ctx.reset_options()
