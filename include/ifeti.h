@@ -146,6 +146,12 @@ typedef struct {
                                F̊, Ů, Ůᵀ and K̊^-ROM; it stays linear and symmetric positive definite, so the
                                interface PCG stays valid and the outer FGMRES still converges to the
                                solution of (16).  B >= nP gives the exact solve */
+    int block_cg;           /* 0: several load cases of the interface problem run as independent PCG
+                               recurrences sharing each operator application; 1: O'Leary's block PCG on
+                               them (the block Krylov space of all load cases; breakdown-free form: the
+                               search block is orthonormalised each step and linearly dependent
+                               directions dropped, so dependent load cases cost no operator columns).
+                               Single load cases and the standard FETI-DP solve are unaffected */
 } ifeti_options;
 
 /* Per-kernel-family statistics.  flops and bytes are the algorithmic counts

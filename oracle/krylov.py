@@ -9,9 +9,19 @@
   stopped by tolerance and the nonlinear reduced solve (46).  x_0 = 0,
   relres = ||b - A x|| / ||b||.
 
-Pins (tests/test_oracle_dd_rom.py): PCG equals a dense solve on SPD systems
-and reports breakdown when p^T A p <= 0; FGMRES equals a dense solve and
-converges in one iteration with the exact inverse as preconditioner.
+* Block PCG for several right-hand sides at once (O'Leary's block conjugate
+  gradient, the N4 variant for many load cases), in the breakdown-free form:
+  the search block is orthonormalised at every step from the eigendecomposition
+  of its Gram matrix and directions of relative eigenvalue <= drop are dropped,
+  so right-hand sides that are (nearly) linearly dependent do not break the
+  recurrence; the step and conjugation coefficients are small dense solves.
+
+Pins (tests/test_oracle_dd_rom.py, tests/test_oracle_solve.py): PCG equals a
+dense solve on SPD systems and reports breakdown when p^T A p <= 0; FGMRES
+equals a dense solve and converges in one iteration with the exact inverse as
+preconditioner; block PCG with one column follows PCG, reaches the dense
+solution for rank-deficient blocks, and needs no more iterations than the
+single-column solves.
 """
 from __future__ import annotations
 
@@ -52,6 +62,60 @@ def pcg(apply_A, apply_M, b, tol=1e-11, maxit=1000):
         p = z + (rho_new / rho) * p
         rho = rho_new
     return x, it, hist
+
+
+def _orth(W, drop):
+    """Orthonormal basis of the column space of W from the eigendecomposition of D W^T W D, D the
+    inverse column norms (zero for zero columns), directions of relative eigenvalue <= drop removed.
+    The scaling makes the drop test one of linear dependence: a load case whose residual is much smaller
+    than the others' keeps its direction."""
+    G = W.T @ W
+    d = np.diag(G).copy()
+    D = np.where(d > 0.0, 1.0 / np.sqrt(np.where(d > 0.0, d, 1.0)), 0.0)
+    Gs = D[:, None] * G * D[None, :]
+    lam, V = np.linalg.eigh(0.5 * (Gs + Gs.T))
+    keep = lam > drop * max(lam.max(), 0.0)
+    if not np.any(keep):
+        return W[:, :0]
+    return W @ (D[:, None] * V[:, keep] / np.sqrt(lam[keep]))
+
+
+def block_pcg(apply_A, apply_M, B, tol=1e-11, maxit=1000, drop=1e-12):
+    """Block PCG on A X = B (B: n x s), X_0 = 0, until ||r_j|| <= tol ||b_j|| for every column j.
+    apply_A / apply_M act on one vector.  Returns (X, iterations, history of the largest relative
+    residual)."""
+    n, s = B.shape
+    X = np.zeros_like(B)
+    R = B.copy()
+    nb = np.linalg.norm(B, axis=0)
+    live = nb > 0.0
+    hist = [1.0 if live.any() else 0.0]
+    if not live.any():
+        return X, 0, hist
+
+    def block(fn, Y):
+        return np.stack([fn(Y[:, j]) for j in range(Y.shape[1])], axis=1) if Y.shape[1] else Y.copy()
+
+    P = _orth(block(apply_M, R), drop)
+    it = 0
+    while it < maxit and P.shape[1] > 0:
+        Q = block(apply_A, P)
+        PQ = P.T @ Q
+        PQ = 0.5 * (PQ + PQ.T)
+        if not np.all(np.isfinite(PQ)) or np.linalg.eigvalsh(PQ).min() <= 0.0:
+            raise Breakdown(f"P^T A P not positive definite at iteration {it}")
+        alpha = np.linalg.solve(PQ, P.T @ R)
+        X += P @ alpha
+        R -= Q @ alpha
+        it += 1
+        rel = np.where(live, np.linalg.norm(R, axis=0) / np.where(live, nb, 1.0), 0.0)
+        hist.append(float(rel.max()))
+        if rel.max() <= tol:
+            break
+        Z = block(apply_M, R)
+        beta = -np.linalg.solve(PQ, Q.T @ Z)
+        P = _orth(Z + P @ beta, drop)
+    return X, it, hist
 
 
 def fgmres(apply_A, apply_P, b, tol=1e-8, maxit=200):

@@ -199,6 +199,8 @@ int ifeti_set_options(ifeti_ctx *c, const ifeti_options *opt) {
         c->opt.true_operator = opt->true_operator;
         REQ(opt->tile_candidate >= -1, "tile_candidate must be >= -1");
         c->opt.tile_candidate = opt->tile_candidate;
+        REQ(opt->block_cg == 0 || opt->block_cg == 1, "block_cg must be 0 or 1");
+        c->opt.block_cg = opt->block_cg;
         REQ(opt->coarse_approx >= 0, "coarse_approx must be >= 0");
         if (opt->coarse_approx != c->opt.coarse_approx) {
             c->opt.coarse_approx = opt->coarse_approx;
@@ -236,6 +238,7 @@ int ifeti_get_options(const ifeti_ctx *c, ifeti_options *o) {
         o->md_precision = p.md_precision;
         o->tile_candidate = p.tile_candidate;
         o->coarse_approx = p.coarse_approx;
+        o->block_cg = p.block_cg;
         return IFETI_OK;
     });
 }

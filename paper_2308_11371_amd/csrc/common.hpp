@@ -124,6 +124,7 @@ struct Options {
     int md_precision = -1;      // precision of the M̊_D^-1 contraction (49); -1: as `precision`
     int tile_candidate = -1;    // >= 0: force this candidate of every contraction family's tile shapes
     int coarse_approx = 0;      // > 0: block-Jacobi coarse solve with blocks of this many primal dofs
+    int block_cg = 0;           // 1: O'Leary block PCG for several load cases of the interface problem
 };
 
 // One row of a partitioned coarse-solve phase: out[out] = alpha * M[off .. off+len) . x[xlo .. xlo+len)
@@ -326,6 +327,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<double> pcg_r, pcg_z, pcg_p, pcg_q, pcg_st, pcg_pa, pcg_pb, pcg_pc;  // interface PCG state
     ifeti::DevBuf<int> pcg_ist;
     ifeti::DevBuf<double> w_scal;       // PCG scalars
+    ifeti::DevBuf<double> bcg_part, bcg_G, bcg_C;  // block PCG: Gram partial sums, Gram matrices, coefficients
     ifeti::DevBuf<int> w_iflag;
 };
 
@@ -379,6 +381,8 @@ void trace_tables_device(ifeti_ctx *c, int K, const double *Kinv, const double *
 std::vector<double> band_cholesky(const std::vector<double> &band, int n, int bw);
 
 // gemm.hip
+// eigenpairs of a small symmetric matrix (cyclic Jacobi; A is overwritten): A = V diag(w) V^T, V row-major
+void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V, std::vector<double> &w);
 // fragment-order FP64 copies of the operators the interface operators contract with (built at setup)
 void prepare_operator_copies(ifeti_ctx *c);
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)

@@ -998,7 +998,7 @@ static const void *frag_copy_lp(ifeti_ctx *c, const double *A, int M, int Kd, in
 // whose size is that of the sum itself, so the narrow operands round relative to the result.  The
 // transformation is exact in FP64 (directions with lambda <= 1e-14 lambda_max carry no Frobenius mass
 // and are dropped); only the narrow copies and the narrow-precision contractions use it.
-static void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V, std::vector<double> &w) {
+void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V, std::vector<double> &w) {
     V.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
     for (int sweep = 0; sweep < 100; ++sweep) {

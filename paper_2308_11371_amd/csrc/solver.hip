@@ -293,6 +293,79 @@ __global__ __launch_bounds__(kB) void k_sub(const double *__restrict__ a, long l
     out[rhs * o_rs + i] = a[rhs * a_rs + i] + sb * b[rhs * b_rs + i];
 }
 
+// ---- block PCG (O'Leary), breakdown-free form: tall-skinny Gram matrices and block combinations.
+// Gram G = U^T V of a <= 32 and b <= 32 columns (column i of U at U + i*urs): one workgroup per chunk of
+// kGramRows rows stages the chunk of every column in LDS (rows padded by one against bank conflicts)
+// and writes its a x b partial sums; k_gram_reduce adds the chunks in order (bitwise repeatable).
+constexpr int kGramRows = 256;
+constexpr int kGramStride = kGramRows + 1;
+constexpr int kBlockMax = 32;
+
+__global__ __launch_bounds__(kB) void k_gram_partial(const double *__restrict__ U, long long urs, int a,
+                                                     const double *__restrict__ V, long long vrs, int b, long long n,
+                                                     double *__restrict__ part) {
+    extern __shared__ double gsh[];  // (a + b) x kGramStride
+    const long long r0 = (long long)blockIdx.x * kGramRows;
+    const int rows = (int)min((long long)kGramRows, n - r0);
+    for (int e = threadIdx.x; e < (a + b) * kGramRows; e += kB) {
+        const int col = e / kGramRows, r = e % kGramRows;
+        double v = 0.0;
+        if (r < rows) v = col < a ? U[col * urs + r0 + r] : V[(col - a) * vrs + r0 + r];
+        gsh[col * kGramStride + r] = v;
+    }
+    __syncthreads();
+    // 2 x 2 blocks of (i, j) per thread
+    const int ai = (a + 1) / 2, bj = (b + 1) / 2;
+    for (int t = threadIdx.x; t < ai * bj; t += kB) {
+        const int i = 2 * (t / bj), j = 2 * (t % bj);
+        const double *u0 = gsh + i * kGramStride, *u1 = gsh + min(i + 1, a - 1) * kGramStride;
+        const double *v0 = gsh + (a + j) * kGramStride, *v1 = gsh + (a + min(j + 1, b - 1)) * kGramStride;
+        double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+        for (int r = 0; r < kGramRows; ++r) {
+            const double x0 = u0[r], x1 = u1[r], y0 = v0[r], y1 = v1[r];
+            s00 += x0 * y0;
+            s01 += x0 * y1;
+            s10 += x1 * y0;
+            s11 += x1 * y1;
+        }
+        double *p = part + (size_t)blockIdx.x * a * b;
+        p[i * b + j] = s00;
+        if (j + 1 < b) p[i * b + j + 1] = s01;
+        if (i + 1 < a) p[(i + 1) * b + j] = s10;
+        if (i + 1 < a && j + 1 < b) p[(i + 1) * b + j + 1] = s11;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_gram_reduce(const double *__restrict__ part, int nchunk, int ab,
+                                                    double *__restrict__ G) {
+    const int t = blockIdx.x * kB + threadIdx.x;
+    if (t >= ab) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(size_t)k * ab + t];
+    G[t] = s;
+}
+
+// Y_j = alpha Y_j + sum_i C[i][j] X_i for j < b (row-parallel; C is a x b row-major, staged in LDS)
+__global__ __launch_bounds__(kB) void k_block_combine(double *__restrict__ Y, long long yrs, int b, double alpha,
+                                                      const double *__restrict__ X, long long xrs, int a,
+                                                      const double *__restrict__ Cm, long long n) {
+    __shared__ double cs[kBlockMax * kBlockMax];
+    for (int e = threadIdx.x; e < a * b; e += kB) cs[e] = Cm[e];
+    __syncthreads();
+    const long long l = (long long)blockIdx.x * kB + threadIdx.x;
+    if (l >= n) return;
+    double x[kBlockMax];
+#pragma unroll
+    for (int i = 0; i < kBlockMax; ++i) x[i] = i < a ? X[i * xrs + l] : 0.0;
+    for (int j = 0; j < b; ++j) {
+        double v = alpha == 0.0 ? 0.0 : alpha * Y[j * yrs + l];
+#pragma unroll
+        for (int i = 0; i < kBlockMax; ++i)
+            if (i < a) v += cs[i * b + j] * x[i];
+        Y[j * yrs + l] = v;
+    }
+}
+
 // One captured PCG iteration (both streams, joined through the fork/join events), instantiated
 // and kept in the context while its key (every buffer the iteration touches, load cases,
 // tolerance, precision, reduced-basis generation) is unchanged; the statistics of the
@@ -392,8 +465,187 @@ class OwnStream {
 
 void release_graph(ifeti_ctx *c) { GraphIteration::release(c); }
 
+// ------------------------------------------------------------------ block PCG (O'Leary)
+// The load cases' interface problems F̊ Lam = R_0 solved together in the block Krylov space of all of
+// them: Q = F̊ P, alpha = (P^T Q)^-1 P^T R, Lam += P alpha, R -= Q alpha, Z = M̊_D^-1 R,
+// beta = -(P^T Q)^-1 Q^T Z, P = orth(Z + P beta).  Breakdown-free form: orth() takes the eigenvectors of
+// the Gram matrix of Z + P beta and drops directions of relative eigenvalue <= 1e-12, so linearly
+// dependent load cases (the c4 tractions span two directions) cost no operator columns.  The k x k
+// algebra runs on the host from the Gram matrices (three reads per iteration).
+static void gram(ifeti_ctx *c, const double *U, long long urs, int a, const double *V, long long vrs, int b,
+                 long long n, double *G) {
+    const int nchunk = (int)((n + kGramRows - 1) / kGramRows);
+    c->bcg_part.ensure((size_t)nchunk * a * b, c->stream);
+    const size_t lds = (size_t)(a + b) * kGramStride * sizeof(double);
+    IFETI_HIP(hipFuncSetAttribute((const void *)k_gram_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    Prof prof(c, "bcg_gram", 2.0 * a * b * (double)n, 8.0 * (a + b) * (double)n);
+    hipLaunchKernelGGL(k_gram_partial, dim3(nchunk), dim3(kB), lds, c->stream, U, urs, a, V, vrs, b, n,
+                       c->bcg_part.p);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((a * b + kB - 1) / kB), dim3(kB), 0, c->stream, c->bcg_part.p, nchunk,
+                       a * b, G);
+    IFETI_HIP(hipGetLastError());
+}
+
+static void combine(ifeti_ctx *c, double *Y, long long yrs, int b, double alpha, const double *X, long long xrs,
+                    int a, const std::vector<double> &Cm, long long n) {
+    if (b == 0) return;
+    IFETI_HIP(hipMemcpyAsync(c->bcg_C.p, Cm.data(), Cm.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    Prof prof(c, "bcg_combine", 2.0 * a * b * (double)n, 8.0 * (a + b + (alpha != 0.0 ? b : 0)) * (double)n);
+    hipLaunchKernelGGL(k_block_combine, dim3(nblocks(n)), dim3(kB), 0, c->stream, Y, yrs, b, alpha, X, xrs, a,
+                       c->bcg_C.p, n);
+    IFETI_HIP(hipGetLastError());
+}
+
+// X = G^-1 B (G k x k symmetric, B k x s) through the eigenpairs of G; false if G is not positive definite
+static bool spd_solve_eig(std::vector<double> G, int k, const std::vector<double> &B, int s, std::vector<double> &X) {
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j) G[(size_t)i * k + j] = G[(size_t)j * k + i] = 0.5 * (G[(size_t)i * k + j] + G[(size_t)j * k + i]);
+    for (double v : G)
+        if (!std::isfinite(v)) return false;
+    std::vector<double> V, w;
+    jacobi_eigen(G, k, V, w);
+    double wmax = 0.0;
+    for (double x : w) wmax = std::max(wmax, x);
+    for (double x : w)
+        if (!(x > 1e-14 * wmax)) return false;
+    X.assign((size_t)k * s, 0.0);
+    for (int m = 0; m < k; ++m)
+        for (int j = 0; j < s; ++j) {
+            double t = 0.0;
+            for (int i = 0; i < k; ++i) t += V[(size_t)i * k + m] * B[(size_t)i * s + j];
+            t /= w[m];
+            for (int i = 0; i < k; ++i) X[(size_t)i * s + j] += V[(size_t)i * k + m] * t;
+        }
+    return true;
+}
+
+static int solve_interface_block(ifeti_ctx *c, const double *rhs, double *lam, int s, double tol, int maxit,
+                                 int *iters, double *relres) {
+    IFETI_REQUIRE(s <= kBlockMax, IFETI_EINVAL, "block PCG takes at most 32 load cases");
+    const long long L = c->L, n = L * s;
+    hipStream_t st = c->stream;
+    c->pcg_r.ensure(n, st);
+    c->pcg_z.ensure(n, st);
+    c->pcg_p.ensure(n, st);
+    c->pcg_q.ensure(n, st);
+    c->bcg_G.ensure(5 * kBlockMax * kBlockMax, st);
+    c->bcg_C.ensure(kBlockMax * kBlockMax, st);
+    double *R = c->pcg_r.p, *Z = c->pcg_z.p, *P = c->pcg_p.p, *Q = c->pcg_q.p, *G = c->bcg_G.p;
+    double *G1 = G, *G2 = G + 1024, *Grr = G + 2048, *G3 = G + 3072, *G4 = G + 4096;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kB), 0, st, rhs, R, n);
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kB), 0, st, lam, n, 0.0);
+    auto fetch = [&](const double *dev, size_t count) {
+        const double *h = (const double *)read_back(c, dev, count * sizeof(double));
+        return std::vector<double>(h, h + count);
+    };
+    gram(c, R, L, s, R, L, s, L, Grr);
+    std::vector<double> nb(s);
+    {
+        const auto g = fetch(Grr, (size_t)s * s);
+        for (int j = 0; j < s; ++j) nb[j] = std::sqrt(std::max(g[(size_t)j * s + j], 0.0));
+    }
+    for (double v : nb)
+        if (!std::isfinite(v)) {
+            set_last_error("PCG breakdown: non-finite right-hand side");
+            return IFETI_EBREAKDOWN;
+        }
+    std::vector<double> rel(s, 0.0);
+    for (int j = 0; j < s; ++j) rel[j] = nb[j] > 0.0 ? 1.0 : 0.0;
+    // P = orth(W) from the Gram matrix of W (s columns at W) scaled to unit column norms (zero columns
+    // stay zero), so that only linear dependence drops a direction: the new block's coefficients T (s x k)
+    auto orth = [&](const double *W) {
+        gram(c, W, L, s, W, L, s, L, G4);
+        std::vector<double> g4 = fetch(G4, (size_t)s * s), V, w, D(s);
+        for (int i = 0; i < s; ++i) {
+            const double dg = g4[(size_t)i * s + i];
+            D[i] = dg > 0.0 && std::isfinite(dg) ? 1.0 / std::sqrt(dg) : 0.0;
+        }
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) g4[(size_t)i * s + j] *= D[i] * D[j];
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < i; ++j)
+                g4[(size_t)i * s + j] = g4[(size_t)j * s + i] = 0.5 * (g4[(size_t)i * s + j] + g4[(size_t)j * s + i]);
+        jacobi_eigen(g4, s, V, w);
+        double wmax = 0.0;
+        for (double x : w) wmax = std::max(wmax, x);
+        std::vector<int> keep;
+        for (int m = 0; m < s; ++m)
+            if (w[m] > 1e-12 * wmax && std::isfinite(w[m])) keep.push_back(m);
+        const int k = (int)keep.size();
+        std::vector<double> T((size_t)s * k);
+        for (int i = 0; i < s; ++i)
+            for (int m = 0; m < k; ++m)
+                T[(size_t)i * k + m] = D[i] * V[(size_t)i * s + keep[m]] / std::sqrt(w[keep[m]]);
+        combine(c, P, L, k, 0.0, W, L, s, T, L);
+        return k;
+    };
+    int it = 0, status = IFETI_OK;
+    bool done = *std::max_element(nb.begin(), nb.end()) == 0.0;
+    int k = 0;
+    if (!done) {
+        apply_MD(c, R, Z, s);
+        k = orth(Z);
+    }
+    while (!done && k > 0 && it < maxit) {
+        apply_F(c, P, Q, k);                                   // Q = F̊ P
+        gram(c, P, L, k, Q, L, k, L, G1);                      // P^T Q
+        gram(c, P, L, k, R, L, s, L, G2);                      // P^T R
+        const std::vector<double> g12 = fetch(G1, 2048);  // P^T Q and P^T R in one read
+        const std::vector<double> g1(g12.begin(), g12.begin() + (size_t)k * k);
+        const std::vector<double> g2(g12.begin() + 1024, g12.begin() + 1024 + (size_t)k * s);
+        std::vector<double> alpha, beta;
+        if (!spd_solve_eig(g1, k, g2, s, alpha)) {
+            set_last_error("PCG breakdown: P^T F P not positive definite or non-finite");
+            status = IFETI_EBREAKDOWN;
+            break;
+        }
+        combine(c, lam, L, s, 1.0, P, L, k, alpha, L);         // Lam += P alpha
+        std::vector<double> malpha(alpha);
+        for (double &v : malpha) v = -v;
+        combine(c, R, L, s, 1.0, Q, L, k, malpha, L);          // R -= Q alpha
+        ++it;
+        apply_MD(c, R, Z, s);                                   // Z = M̊_D^-1 R
+        gram(c, R, L, s, R, L, s, L, Grr);                      // R^T R (convergence)
+        gram(c, Q, L, k, Z, L, s, L, G3);                       // Q^T Z
+        const std::vector<double> g33 = fetch(Grr, 2048);  // R^T R and Q^T Z in one read
+        {
+            const auto &g = g33;
+            done = true;
+            for (int j = 0; j < s; ++j) {
+                rel[j] = nb[j] > 0.0 ? std::sqrt(std::max(g[(size_t)j * s + j], 0.0)) / nb[j] : 0.0;
+                done = done && rel[j] <= tol;
+            }
+        }
+        if (done) break;
+        const std::vector<double> g3(g33.begin() + 1024, g33.begin() + 1024 + (size_t)k * s);
+        if (!spd_solve_eig(g1, k, g3, s, beta)) {
+            set_last_error("PCG breakdown: P^T F P not positive definite or non-finite");
+            status = IFETI_EBREAKDOWN;
+            break;
+        }
+        for (double &v : beta) v = -v;
+        combine(c, Z, L, s, 1.0, P, L, k, beta, L);            // W = Z + P beta (in Z)
+        k = orth(Z);                                            // P = orth(W)
+    }
+    int live = 0;
+    for (int j = 0; j < s; ++j) {
+        live += nb[j] > 0.0 ? 1 : 0;
+        if (iters) iters[j] = nb[j] > 0.0 ? it : 0;
+        if (relres) relres[j] = rel[j];
+    }
+    c->pcg_its += (long long)it * live;
+    if (status != IFETI_OK) return status;
+    if (!done) {
+        set_last_error("PCG reached the iteration limit");
+        return IFETI_EMAXIT;
+    }
+    return IFETI_OK;
+}
+
 int solve_interface(ifeti_ctx *c, const double *rhs, double *lam, int nrhs, double tol, int maxit, int *iters,
                     double *relres, bool exact) {
+    if (c->opt.block_cg && nrhs > 1 && !exact) return solve_interface_block(c, rhs, lam, nrhs, tol, maxit, iters, relres);
     auto opF = exact ? apply_F_exact : apply_F;
     auto opMD = exact ? apply_MD_exact : apply_MD;
     OwnStream own(c, c->opt.use_graph != 0);

@@ -52,14 +52,15 @@ class Options(ctypes.Structure):
                 ("timing_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int), ("interface_block", ctypes.c_int),
                 ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int), ("md_precision", ctypes.c_int),
-                ("tile_candidate", ctypes.c_int), ("coarse_approx", ctypes.c_int)]
+                ("tile_candidate", ctypes.c_int), ("coarse_approx", ctypes.c_int),
+                ("block_cg", ctypes.c_int)]
 
 OPTION_NAMES = tuple(name for name, _ in Options._fields_)
 # the library's defaults (a new context starts with these)
 DEFAULT_OPTIONS = dict(precision=IFETI_FP64, pcg_check_every=2, fgmres_restart=60, pcg_maxit=1000, timing=0,
                        timing_filter="", timing_every=1, use_graph=0, autotune=0, coarse_parts=0, true_operator=0,
                        interface_block=0, overlap_local=0, local_iters=1, md_precision=-1, tile_candidate=-1,
-                       coarse_approx=0)
+                       coarse_approx=0, block_cg=0)
 
 
 class KernelStat(ctypes.Structure):

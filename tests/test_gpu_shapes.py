@@ -159,11 +159,12 @@ def test_c3cell_interface_pcg_and_full_solve(lat):
     assert eu <= 1e-9 and el <= 1e-9 and nu <= 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c4cols_block_solve_matches_conforming_solutions(lat, prec):
-    """32 load cases at once (block PCG, shared operator applications): each load case's displacements
-    against the conforming solution, FP64 within 1e-9 and FP32 local contractions (FP64 PCG, coarse
-    solve and outer refinement) within 1e-6."""
+@pytest.mark.parametrize("prec,block_cg", [("fp64", 0), ("fp32", 0), ("fp64", 1)])
+def test_c4cols_block_solve_matches_conforming_solutions(lat, prec, block_cg):
+    """32 load cases at once (shared operator applications; independent PCG recurrences, or one block
+    PCG over all load cases with block_cg): each load case's displacements against the conforming
+    solution, FP64 within 1e-9 and FP32 local contractions (FP64 PCG, coarse solve and outer
+    refinement) within 1e-6."""
     from paper_2308_11371_amd import ifeti
     name, prob, ctx, gold, inputs = lat
     if name != "c4cols":
@@ -173,7 +174,7 @@ def test_c4cols_block_solve_matches_conforming_solutions(lat, prec):
     nrhs = gold["nrhs"]
     f, d = ctx.get_rhs()
     p = {"fp64": ifeti.IFETI_FP64, "fp32": ifeti.IFETI_FP32_LOCAL}[prec]
-    ctx.set_options(precision=p, autotune=1)
+    ctx.set_options(precision=p, autotune=1, block_cg=block_cg)
     try:
         u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=1e-11, inner_tol=1e-12 if prec == "fp64" else 1e-6, maxit=100)
     finally:
@@ -185,7 +186,8 @@ def test_c4cols_block_solve_matches_conforming_solutions(lat, prec):
         exp = np.array(g["u_val"][c])
         worst = max(worst, np.linalg.norm(U[c][idx] - exp) / np.linalg.norm(exp),
                     abs(np.linalg.norm(U[c]) - g["u_norm"][c]) / g["u_norm"][c])
-    print(f"[gpu shapes] c4cols {prec} block solve of {nrhs} load cases: outer {int(info['outer_its'].max())}, "
+    print(f"[gpu shapes] c4cols {prec} block_cg={block_cg} solve of {nrhs} load cases: outer "
+          f"{int(info['outer_its'].max())}, inner {int(np.sum(info['inner_its']))}, "
           f"max relres {info['relres'].max():.1e}, worst u error {worst:.2e}", flush=True)
     assert info["relres"].max() <= 1e-9     # true residual of (16) (the outer stop test uses the estimate)
     assert worst <= (1e-9 if prec == "fp64" else 1e-6)

@@ -159,3 +159,43 @@ def test_block_jacobi_coarse_solve_reaches_direct_solution(B):
     m.set_coarse_block(B)
     r = m.solve(tol=1e-12, inner_tol=1e-13, maxit=150)
     assert _rel(r["u"], conforming_solve(m)["u"]) < 1e-9
+
+
+def test_block_pcg_one_column_follows_pcg_and_rank_deficient_blocks_converge():
+    """O'Leary's block CG (breakdown-free form): with one column it is PCG; on a block whose columns are
+    linearly dependent (b1, b2, b1 + b2, 2 b1) every column reaches the dense solution without
+    breakdown, in no more iterations than the single-column solves; on F̊ with M̊_D^-1 likewise."""
+    from oracle.krylov import pcg, block_pcg
+    rng = np.random.default_rng(4)
+    n = 60
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Qm @ np.diag(np.logspace(0, 3, n)) @ Qm.T
+    Dm = 1.0 / np.diag(A)
+    fA, fM = (lambda v: A @ v), (lambda v: Dm * v)
+    b1, b2 = rng.standard_normal(n), rng.standard_normal(n)
+    x1, it1, h1 = pcg(fA, fM, b1, tol=1e-12)
+    X, itb, hb = block_pcg(fA, fM, b1[:, None], tol=1e-12)
+    # the same iterates in exact arithmetic: equal residual histories until finite-precision loss of
+    # orthogonality separates the two recurrences, and the same converged solution
+    assert np.allclose(hb[:15], h1[:15], rtol=1e-8, atol=0.0)
+    assert abs(itb - it1) <= 3 and _rel(X[:, 0], x1) < 1e-10
+    B = np.stack([b1, b2, b1 + b2, 2 * b1], axis=1)
+    X, itb, _ = block_pcg(fA, fM, B, tol=1e-12)
+    ref = np.linalg.solve(A, B)
+    assert max(_rel(X[:, j], ref[:, j]) for j in range(4)) < 1e-10
+    assert itb <= max(pcg(fA, fM, B[:, j], tol=1e-12)[1] for j in range(4))
+    m = Model(latticegen.tiny(2, (3, 3), 3, n_principal=3))
+    m.build_reduced_basis()
+    R = rng.standard_normal((m.L, 3))
+    R[:, 2] = R[:, 0] - 0.5 * R[:, 1]
+    X, itb, _ = block_pcg(m.apply_F, m.apply_MD, R, tol=1e-12)
+    Fd = np.stack([m.apply_F(e) for e in np.eye(m.L)], axis=1)
+    ref = np.linalg.solve(Fd, R)
+    assert max(_rel(X[:, j], ref[:, j]) for j in range(3)) < 1e-9
+    # a load case 1e-9 times smaller than the others keeps its own direction (the drop test compares
+    # unit columns), and a zero load case stays zero
+    B = np.stack([b1, 1e-9 * b2, np.zeros(n), 2 * b1], axis=1)
+    X, itb, _ = block_pcg(fA, fM, B, tol=1e-12)
+    ref = np.linalg.solve(A, B)
+    assert max(_rel(X[:, j], ref[:, j]) for j in (0, 1, 3)) < 1e-10
+    assert not X[:, 2].any()
