@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 CELL_OPS = ("F", "MD", "U", "Ut", "Kinv_rom")
 
@@ -91,26 +92,7 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(budget_s: float = 10.0):
-    """The CPU oracle on a bounded sample of the same workload.
-
-    Sample: the c2 cell discretisation (16x16 quadratic elements per cell,
-    12 principal cells, same material, map amplitude and width recipe) on a
-    32x32-cell lattice; FGMRES solves capped at three outer iterations are
-    repeated until `budget_s` seconds of CPU work; applies counted as on the GPU.
-    """
-    import numpy as np
-    import latticegen
-    from oracle import Model
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    p = latticegen.tiny(2, (32, 32), 16, amp=0.15, width=("linx", 0.15, 0.30), n_principal=12)
-    m = Model(p)
-    m.build_reduced_basis()
-    counts = dict.fromkeys(CELL_OPS, 0)
+def _count_applies(m, counts):
     for op in CELL_OPS:
         fn = getattr(m, "apply_" + op)
 
@@ -118,97 +100,289 @@ def cpu_baseline(budget_s: float = 10.0):
             counts[_op] += 1
             return _fn(x)
         setattr(m, "apply_" + op, wrapped)
+
+
+def cpu_worker(flag_dir: str):
+    """The CPU oracle on the measured workload itself (c2), in a process of its own pinned to the cores
+    the GPU process does not use: the oracle model and reduced basis are built while the GPU legs run
+    (setup, not timed), then, once the parent signals that the GPU work is done, the bounded sample is
+    timed on all the worker's cores and on one thread (the paper's serial setting).  Sample: one outer
+    FGMRES iteration of the c2 solve with the interface PCG capped at 4 iterations; cell applies
+    counted as on the GPU."""
+    import numpy as np
+    import latticegen
+    from oracle import Model
+    from threadpoolctl import threadpool_info, threadpool_limits
     t0 = time.perf_counter()
-    nsolve = 0
-    while True:
-        r = m.solve(tol=1e-8, maxit=3)
-        nsolve += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s:
-            break
-    applies = sum(counts.values()) * p.N
-    return dict(value=applies / dt, unit="cell-applies/s", cores=int(cores), kind="oracle",
-                sample=f"{nsolve} oracle FP64 solves capped at 3 outer FGMRES iterations ({r['inner_its']} PCG "
-                       f"iterations each) on a 32x32-cell lattice with the c2 cell discretisation; "
-                       f"{applies} cell applies in {dt:.1f} s")
+    p = latticegen.make("c2")
+    m = Model(p)
+    m.build_reduced_basis()
+    setup_s = time.perf_counter() - t0
+    open(os.path.join(flag_dir, "ready"), "w").close()
+    go = os.path.join(flag_dir, "go")
+    t1 = time.perf_counter()
+    while not os.path.exists(go) and time.perf_counter() - t1 < 900:
+        time.sleep(0.5)
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    out = {"setup_s": setup_s, "cores": int(cores)}
+    for label, nthreads in (("all_cores", cores), ("one_thread", 1)):
+        counts = dict.fromkeys(CELL_OPS, 0)
+        _count_applies(m, counts)
+        with threadpool_limits(limits=nthreads):
+            ts = time.perf_counter()
+            r = m.solve(tol=1e-8, maxit=1, inner_maxit=4)
+            dt = time.perf_counter() - ts
+        applies = sum(counts.values()) * p.N
+        out[label] = {"value": applies / dt, "seconds": dt, "cell_applies": applies, "threads": nthreads,
+                      "applies": dict(counts), "pcg_its": [int(x) for x in r["inner_its"]]}
+        for op in CELL_OPS:  # the counting wrappers are instance attributes: drop them for the next pass
+            delattr(m, "apply_" + op)
+    print(json.dumps(out), flush=True)
 
 
-def timed_solve(ctx, f, d, nrhs, tol, inner_tol, reps=1, maxit=200):
+class CpuBaseline:
+    """Starts the oracle worker at once (its setup overlaps the GPU legs) and collects its sample."""
+
+    def __init__(self):
+        import subprocess
+        import tempfile
+        self.dir = tempfile.mkdtemp(prefix="ifeti_cpu_")
+        # the process's CPU share: the affinity set, capped by the thread budget the box sets
+        mine = sorted(os.sched_getaffinity(0))
+        ncpu = min(len(mine), int(os.environ.get("OMP_NUM_THREADS", len(mine)) or len(mine)))
+        mine = mine[:ncpu]
+        # the GPU process keeps four cores (launches, polls); the oracle gets the rest
+        self.gpu_cores, self.cpu_cores = mine[:4], (mine[4:] or mine)
+        env = dict(os.environ)
+        n = str(len(self.cpu_cores))
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[k] = n
+        env["HIP_VISIBLE_DEVICES"] = ""  # the worker never touches the GPU
+        self.proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", self.dir],
+                                     stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env, text=True,
+                                     preexec_fn=lambda: os.sched_setaffinity(0, self.cpu_cores))
+        os.sched_setaffinity(0, self.gpu_cores)
+        self.ncpu = ncpu
+
+    def collect(self, timeout_s: float = 420.0):
+        open(os.path.join(self.dir, "go"), "w").close()
+        try:
+            out, err = self.proc.communicate(timeout=timeout_s)
+        except Exception:
+            self.proc.kill()
+            return None
+        finally:
+            os.sched_setaffinity(0, set(self.gpu_cores) | set(self.cpu_cores))
+        try:
+            r = json.loads(out.strip().splitlines()[-1])
+        except (ValueError, IndexError):
+            log(f"cpu baseline worker failed: {err[-2000:]}")
+            return None
+        a, o = r["all_cores"], r["one_thread"]
+        return dict(value=a["value"], unit="cell-applies/s", cores=a["threads"], kind="oracle",
+                    sample=(f"c2 itself (4096 cells, 12 principal cells, FP64): one outer FGMRES iteration with the "
+                            f"interface PCG capped at 4 iterations ({a['cell_applies']} cell applies: "
+                            f"{a['applies']}) in {a['seconds']:.1f} s on {a['threads']} threads; oracle setup "
+                            f"(model, greedy, bank, coefficients, coarse factor) {r['setup_s']:.0f} s, not timed, "
+                            f"overlapping the GPU legs on cores of its own"),
+                    one_thread={"value": o["value"], "seconds": o["seconds"], "cell_applies": o["cell_applies"]},
+                    setup_s=r["setup_s"], box_cpus=self.ncpu)
+
+
+def timed_solve(ctx, f, d, nrhs, tol, inner_tol, reps=1, maxit=200, check=True):
+    """Mean wall time of `reps` solves after one untimed warm-up; returns (seconds, info, u of the last).
+    check=False: a solve that stops at the iteration limit is timed and reported, not raised."""
     import torch
-    ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit)  # untimed warm-up
+    ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit, check=check)  # untimed warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit)
+        u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=tol, inner_tol=inner_tol, maxit=maxit, check=check)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps, info
+    return (time.perf_counter() - t0) / reps, info, u
 
 
-def run_forms(ctx, f, d, t_fp64, args):
-    """Precision form (FP32 / BF16 local contractions, FP64 PCG, coarse solve and outer FGMRES) on the
-    same lattice, and the block-RHS form: 32 load cases in one batched solve (FP32 local, contraction
-    tiles autotuned during the untimed warm-up solve), each against the plain FP64 solve time per load
-    case."""
+def rel_err(u, ref):
+    import torch
+    return float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
+
+
+def reference_solution(ctx, f, d, nrhs=1, maxit=200):
+    """FP64 plain solve at the parity tolerances (outer 1e-12, interface PCG 1e-13): the reference every
+    precision-form result is compared with."""
+    ctx.reset_options(fgmres_restart=max(200, maxit), pcg_maxit=3000)
+    u, lam, info = ctx.solve(f, d, nrhs=nrhs, tol=1e-12, inner_tol=1e-13, maxit=maxit, check=False)
+    ctx.reset_options()
+    return u.clone(), float(max(info["relres"]))
+
+
+def op_rates(ctx, reps=20):
+    """Each cell operator applied alone, back to back (one load case, FP64 unless the context's precision
+    says otherwise): time per apply and cell local-solve applies per second (cells / time)."""
+    import torch
+    s = ctx.sizes
+    g = torch.Generator("cuda").manual_seed(9)
+    n_in = {"F": s.L, "MD": s.L, "Ut": s.L, "U": s.nU, "Kinv_rom": s.nU}
+    out = {}
+    for op in ("F", "MD", "Kinv_rom", "U", "Ut"):
+        x = torch.randn(n_in[op], dtype=torch.float64, device="cuda", generator=g)
+        fn = getattr(ctx, "apply_" + op)
+        y = fn(x)
+        for _ in range(2):
+            fn(x, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(x, out=y)
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[op] = {"us_per_apply": us, "cell_applies_per_s": s.N / us * 1e6}
+    return out
+
+
+def kernel_roofline(ctx, fam, peak, unit="TFLOP/s"):
+    """Average HIP-event time of one kernel family (timed launches) and its algorithmic rate."""
+    k = ctx.stats()["kernels"].get(fam)
+    if not k or not k["timed"]:
+        return None
+    us = k["total_ms"] * 1e3 / k["timed"]
+    fl = k["flops"] / max(k["launches"], 1)
+    by = k["bytes"] / max(k["launches"], 1)
+    ach = fl / us / 1e6
+    return {"kernel": fam, "avg_us": us, "flops_per_launch": fl, "bytes_per_launch": by, "achieved": ach,
+            "peak": peak, "unit": unit, "frac": ach / peak, "hbm_gb_s": by / us / 1e3}
+
+
+def run_forms(ctx, f, d, t_fp64, args, u_ref):
+    """Precision form (FP32 / BF16 local contractions, FP64 PCG, coarse solve and outer FGMRES), the
+    approximate coarse solve, the interface-block and local-solve variants on the same lattice, each
+    against the plain FP64 solve time and with ||u - u_FP64|| / ||u_FP64|| against the FP64 solve at
+    the parity tolerances; then the c2 lattice with 40 principal cells and the block-RHS form c4."""
     import latticegen
     from paper_2308_11371_amd import ifeti
     res = {"fp64_plain": {"solve_time_s": t_fp64}}
-    for name, prec, itol in (("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6), ("bf16_local", ifeti.IFETI_BF16_LOCAL, 1e-3)):
+
+    def leg(name, itol, maxit=200, check=True, **opts):
+        ctx.reset_options(**opts)
+        t, info, u = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3, maxit=maxit, check=check)
+        r = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
+             "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol,
+             "converged": int(info["status"]) == 0, "err_vs_fp64": rel_err(u, u_ref)}
+        log(f"form {name}: {t:.3f}s outer={r['outer_its']} pcg={r['pcg_its']} relres={r['relres']:.1e} "
+            f"err={r['err_vs_fp64']:.1e}")
+        res[name] = r
+        return r
+
+    B16, F32 = ifeti.IFETI_BF16_LOCAL, ifeti.IFETI_FP32_LOCAL
+    for name, prec, itol in (("fp32_local", F32, 1e-6), ("bf16_local", B16, 1e-3)):
         # FP64 at the same (looser) inner tolerance: separates the gain of the narrow contractions from
         # that of the looser inner solve
-        ctx.reset_options()
-        t64, _ = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
-        ctx.set_options(precision=prec)
-        t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
-        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "fp64_same_inner_tol_s": t64,
-                     "vs_fp64_same_inner_tol": t / t64, "outer_its": int(info["outer_its"][0]),
-                     "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
-        log(f"form {name}: {t:.3f}s (fp64 at inner tol {itol:g}: {t64:.3f}s) outer={info['outer_its'][0]} "
-            f"pcg={info['inner_its'][0]}")
+        t64 = leg(name + "_fp64_same_inner_tol", itol)["solve_time_s"]
+        r = leg(name, itol, precision=prec)
+        r["vs_fp64_same_inner_tol"] = r["solve_time_s"] / t64
     # BF16 Dirichlet preconditioner (49) under FP64 or FP32 operators (PCG needs only an SPD
     # preconditioner; the interface solve keeps the operators' accuracy)
-    for name, prec, itol in (("fp64_bf16_preconditioner", ifeti.IFETI_FP64, 1e-11),
-                             ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6),
-                             ("fp32_bf16_preconditioner_inner_1e-3", ifeti.IFETI_FP32_LOCAL, 1e-3)):
-        ctx.set_options(precision=prec, md_precision=ifeti.IFETI_BF16_LOCAL)
-        t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
-        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
-                     "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0]), "inner_tol": itol}
-        log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
-    ctx.reset_options()
+    leg("fp64_bf16_preconditioner", 1e-11, md_precision=B16)
+    leg("fp32_bf16_preconditioner", 1e-6, precision=F32, md_precision=B16)
+    leg("fp32_bf16_preconditioner_inner_1e-3", 1e-3, precision=F32, md_precision=B16)
+    # approximate coarse solve (Sec. 3.2.1): block Jacobi over blocks of B primal dofs; the outer FGMRES
+    # corrects the inexact F̊ (a leg that stops at 200 outer iterations is reported as such)
+    for B in (128, 1040):
+        leg(f"coarse_block_jacobi_{B}", 1e-11, check=False, coarse_approx=B, fgmres_restart=200)
     # interface block of Alg. 1: one application of (49) or of (47) in place of the interface PCG
-    for name, block in (("interface_md_once", 1), ("interface_md_rom_once", 2)):
-        ctx.set_options(interface_block=block, fgmres_restart=200)
-        t, info = timed_solve(ctx, f, d, 1, args.tol, 1e-11, maxit=200)
-        res[name] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
-                     "relres": float(info["relres"][0])}
-        log(f"form {name}: {t:.3f}s outer={info['outer_its'][0]}")
-    ctx.reset_options()
+    leg("interface_md_once", 1e-11, interface_block=1, fgmres_restart=200)
+    leg("interface_md_rom_once", 1e-11, interface_block=2, fgmres_restart=200)
     # K̊^-MPCG (Remark 6): multi-preconditioned CG local solves, two and three iterations each
     for it in (2, 3):
-        ctx.set_options(local_iters=it)
-        t, info = timed_solve(ctx, f, d, 1, args.tol, 1e-11)
-        res[f"mpcg_local_{it}"] = {"solve_time_s": t, "vs_fp64": t / t_fp64, "outer_its": int(info["outer_its"][0]),
-                                   "pcg_its": int(info["inner_its"][0]), "relres": float(info["relres"][0])}
-        log(f"form mpcg_local_{it}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+        leg(f"mpcg_local_{it}", 1e-11, local_iters=it)
     ctx.reset_options()
     res["true_operator"] = run_true_operator(ctx)
-    prob = latticegen.make("c4")
-    c4 = ifeti.setup(prob)
-    s4 = c4.sizes
-    f4, d4 = c4.get_rhs()
-    c4.set_options(precision=ifeti.IFETI_FP32_LOCAL, autotune=1)  # tiles tuned during the warm-up solve
-    t, info = timed_solve(c4, f4, d4, s4.nrhs, args.tol, 1e-6)
-    res["block_rhs_fp32_local"] = {
-        "workload": f"c4: the c2 lattice with {s4.nrhs} seeded right-edge load cases in one batched solve",
-        "nrhs": int(s4.nrhs), "solve_time_s": t, "per_load_case_s": t / s4.nrhs,
-        "vs_fp64_plain_per_load_case": t / s4.nrhs / t_fp64, "autotuned_tiles": True,
-        "max_outer_its": int(max(info["outer_its"])), "max_relres": float(max(info["relres"]))}
-    log(f"form block_rhs: {t:.3f}s for {s4.nrhs} load cases")
-    c4.close()
+    res["c2_K40"] = run_k40(args)
+    res["block_rhs_fp32_local"] = run_c4(args, t_fp64)
     if not args.no_3d:
         res["c3_3d"] = run_c3(args)
         res["c5_gradient"] = run_c5(args)
     return res
+
+
+def run_k40(args):
+    """c2 with the greedy capped at 40 principal cells (the configuration's "reduced basis 40 modes per
+    cell"): same kernels with K = 40, FP64 solve to 1e-8, the principal contraction's roofline."""
+    import torch
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+    prob = latticegen.make("c2", n_principal=40)
+    t0 = time.perf_counter()
+    ctx = ifeti.setup(prob)
+    torch.cuda.synchronize()
+    s = ctx.sizes
+    f, d = ctx.get_rhs()
+    out = {"workload": f"c2 with {s.K} principal cells (greedy capped at 40), FP64, 1 load case",
+           "principal_cells": s.K, "setup_s": time.perf_counter() - t0}
+    ctx.set_options(timing=1, timing_filter="MD_gemm", timing_every=8)
+    ctx.reset_stats()
+    t, info, u = timed_solve(ctx, f, d, 1, args.tol, args.inner_tol, reps=3)
+    st = ctx.stats()
+    out.update(solve_time_s=t, outer_its=int(info["outer_its"][0]), pcg_its=int(info["inner_its"][0]),
+               relres=float(info["relres"][0]),
+               cell_applies_per_s=sum(st["applies"][op] for op in CELL_OPS) * s.N / (4 * t),
+               roofline_MD_gemm=kernel_roofline(ctx, "MD_gemm", PEAK_FP64_TFLOPS))
+    ctx.reset_options()
+    out["operators"] = op_rates(ctx)
+    log(f"c2 K={s.K}: solve {t:.3f}s outer={out['outer_its']} pcg={out['pcg_its']}")
+    ctx.close()
+    return out
+
+
+def run_c4(args, t_fp64):
+    """c4: the c2 lattice with 32 seeded load cases in one batched solve (block PCG: 32 recurrences
+    sharing every operator application), FP32 local contractions with FP64 PCG, coarse solve and outer
+    FGMRES, tiles autotuned in the untimed warm-up; per-load-case time against the FP64 single solve,
+    the contractions' rooflines against the FP32 matrix peak and the error of every load case against
+    the FP64 block solve at the parity tolerances."""
+    import torch
+    import latticegen
+    from paper_2308_11371_amd import ifeti
+    prob = latticegen.make("c4")
+    ctx = ifeti.setup(prob)
+    s = ctx.sizes
+    f, d = ctx.get_rhs()
+    u_ref, _ = reference_solution(ctx, f, d, nrhs=s.nrhs)
+    ctx.set_options(precision=ifeti.IFETI_FP32_LOCAL, autotune=1)
+    ctx.solve(f, d, nrhs=s.nrhs, tol=args.tol, inner_tol=1e-6, maxit=200)  # tiles tuned here
+    torch.cuda.synchronize()
+    ctx.set_options(timing=1, timing_filter="F_gemm,MD_gemm,coarse_gemm,F_restrict", timing_every=4)
+    ctx.reset_stats()
+    t, info, u = timed_solve(ctx, f, d, s.nrhs, args.tol, 1e-6)
+    U, R = u.view(s.nrhs, -1), u_ref.view(s.nrhs, -1)
+    errs = [rel_err(U[r], R[r]) for r in range(s.nrhs)]
+    out = {"workload": f"c4: the c2 lattice with {s.nrhs} seeded right-edge load cases in one batched solve",
+           "nrhs": int(s.nrhs), "solve_time_s": t, "per_load_case_s": t / s.nrhs,
+           "vs_fp64_plain_per_load_case": t / s.nrhs / t_fp64, "autotuned_tiles": True,
+           "max_outer_its": int(max(info["outer_its"])), "max_relres": float(max(info["relres"])),
+           "max_err_vs_fp64": max(errs),
+           "roofline_F_gemm_fp32": kernel_roofline(ctx, "F_gemm", PEAK_FP32_MATRIX_TFLOPS),
+           "roofline_MD_gemm_fp32": kernel_roofline(ctx, "MD_gemm", PEAK_FP32_MATRIX_TFLOPS),
+           "coarse_gemm_fp64": kernel_roofline(ctx, "coarse_gemm", PEAK_FP64_TFLOPS),
+           "F_restrict": kernel_roofline(ctx, "F_restrict", PEAK_FP64_TFLOPS)}
+    log(f"form block_rhs: {t:.3f}s for {s.nrhs} load cases, max err {max(errs):.1e}")
+    # the same solve with one block PCG over all load cases inside the preconditioner (O'Leary): the
+    # block space spans every load case's Krylov space, the tractions' two directions collapse
+    ctx.set_options(block_cg=1, timing=0)
+    tb, infob, ub = timed_solve(ctx, f, d, s.nrhs, args.tol, 1e-6)
+    Ub = ub.view(s.nrhs, -1)
+    errs_b = [rel_err(Ub[r], R[r]) for r in range(s.nrhs)]
+    out["block_cg"] = {"solve_time_s": tb, "per_load_case_s": tb / s.nrhs, "speedup_vs_independent": t / tb,
+                       "max_outer_its": int(max(infob["outer_its"])), "max_relres": float(max(infob["relres"])),
+                       "inner_its_max": int(max(infob["inner_its"])),
+                       "inner_its_max_independent": int(max(info["inner_its"])),
+                       "max_err_vs_fp64": max(errs_b)}
+    ctx.reset_options()
+    log(f"form block_rhs with block PCG: {tb:.3f}s, max err {max(errs_b):.1e}")
+    ctx.close()
+    return out
 
 
 def run_true_operator(ctx, reps=10):
@@ -303,6 +477,8 @@ def run_c3(args):
     f, d = ctx.get_rhs()
     f = f[:s.nU].contiguous()
     d = d[:s.L].contiguous()
+    u_ref, rr = reference_solution(ctx, f, d)
+    out["reference"] = {"tol": 1e-12, "inner_tol": 1e-13, "relres": rr}
     B16 = ifeti.IFETI_BF16_LOCAL
     for name, prec, itol, mdp in (("fp64_plain", ifeti.IFETI_FP64, 1e-11, -1),
                                   ("fp32_local", ifeti.IFETI_FP32_LOCAL, 1e-6, -1),
@@ -310,13 +486,14 @@ def run_c3(args):
                                   ("fp64_bf16_preconditioner", ifeti.IFETI_FP64, 1e-11, B16),
                                   ("fp32_bf16_preconditioner", ifeti.IFETI_FP32_LOCAL, 1e-6, B16)):
         # tiles tuned in the untimed warm-up
-        ctx.set_options(precision=prec, md_precision=mdp, pcg_maxit=200, autotune=1)
-        t, info = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
+        ctx.reset_options(precision=prec, md_precision=mdp, pcg_maxit=200, autotune=1)
+        t, info, u = timed_solve(ctx, f, d, 1, args.tol, itol, reps=3)
         out[name] = {"solve_time_s": t, "outer_its": int(info["outer_its"][0]), "pcg_its": int(info["inner_its"][0]),
-                     "relres": float(info["relres"][0]), "inner_tol": itol}
+                     "relres": float(info["relres"][0]), "inner_tol": itol, "err_vs_fp64": rel_err(u, u_ref)}
         if name != "fp64_plain":
             out[name]["vs_fp64"] = t / out["fp64_plain"]["solve_time_s"]
-        log(f"form c3 {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]}")
+        log(f"form c3 {name}: {t:.3f}s outer={info['outer_its'][0]} pcg={info['inner_its'][0]} "
+            f"err={out[name]['err_vs_fp64']:.1e}")
     ctx.reset_options()
     out["true_operator"] = run_true_operator(ctx)
     if not args.no_exact:
@@ -390,6 +567,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-11)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--roofline-kernel", default="MD_gemm",
                     help="kernel families (comma-separated, pooled) of the dominant kernel for the roofline")
     ap.add_argument("--also-time", default="F_gemm",
@@ -397,15 +575,20 @@ def main():
     ap.add_argument("--all-kernels", action="store_true", help="event-time every kernel family (slower)")
     ap.add_argument("--timing-every", type=int, default=8,
                     help="event-time one launch in this many of each timed family (keeps the timeline unperturbed)")
-    ap.add_argument("--no-forms", action="store_true", help="skip the precision and block-RHS legs")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (c3) precision leg of the forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision, variant and block-RHS legs")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (c3, c5) legs of the forms")
     ap.add_argument("--no-exact", action="store_true", help="skip the standard FETI-DP comparison leg")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    # the CPU oracle's setup runs on cores of its own while the GPU legs run (no GPU use in that process)
+    cpu = None if args.no_cpu_baseline else CpuBaseline()
 
     import torch
     import latticegen
@@ -450,7 +633,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     st = ctx.stats()
-    ctx.set_options(timing=0)
+    ctx.reset_options()
     applies = sum(st["applies"][op] for op in CELL_OPS) * s.N
     value = applies / elapsed
     roof = roofline_of(st["kernels"], args.roofline_kernel.split(","))
@@ -459,9 +642,22 @@ def main():
     kernels = {k: dict(launches=v["launches"], timed=v["timed"], avg_us=v["total_ms"] * 1e3 / max(v["timed"], 1),
                        share=v["total_ms"] / max(v["timed"], 1) * v["launches"] / 1e3 / elapsed) for k, v in sorted(
                            st["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])[:10] if v["total_ms"] > 0}
-    forms = None if args.no_forms else run_forms(ctx, f, d, elapsed / args.steps, args)
-    if forms is not None and not args.no_exact:
-        forms["exact_fetidp"] = run_exact(ctx, f, d, elapsed / args.steps, args)
+    per_solve = {k: v // args.steps for k, v in st["applies"].items()}
+    pcg_its = int(infos[-1]["inner_its"][0])
+    outer = int(infos[-1]["outer_its"][0])
+    ops = op_rates(ctx)
+    per_operator = {op: {"applies_per_solve": per_solve[op], "in_solve_cell_applies_per_s": per_solve[op] * s.N /
+                         (elapsed / args.steps), **ops[op]} for op in CELL_OPS}
+    # one F̊ per PCG iteration; the others come from the look-ahead of the convergence polls (iterations
+    # that run past convergence before a poll sees it leave the iterate unchanged)
+    past = {"F": per_solve["F"] - pcg_its, "MD": per_solve["MD"] - pcg_its - outer}
+    forms = None
+    if not args.no_forms:
+        u_ref, _ = reference_solution(ctx, f, d)
+        forms = run_forms(ctx, f, d, elapsed / args.steps, args, u_ref)
+        if not args.no_exact:
+            forms["exact_fetidp"] = run_exact(ctx, f, d, elapsed / args.steps, args)
+    lat = "2D 64x64-cell lattice, 648 dof/cell" if prob.dim == 2 else f"3D {'x'.join(map(str, prob.shape))}-cell lattice, {s.n_dof} dof/cell"
     out = {
         "metric": "cell local-solve applies/s; solve time to rel. residual 1e-8 vs FP64 plain",
         "value": value,
@@ -475,25 +671,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 2D 64x64-cell lattice, 648 dof/cell, {s.K} principal cells, "
-                               f"FP64, 1 load case, FGMRES to relres {args.tol:g}",
+        "config": {"workload": f"{args.config}: {lat}, {s.K} principal cells, FP64, {s.nrhs if s.nrhs > 1 else 1} "
+                               f"load case{'s' if s.nrhs > 1 else ''} solved one at a time, FGMRES to relres {args.tol:g}",
                    "cells": s.N, "dof_torn": int(s.nU), "multipliers": s.L, "principal_cells": s.K,
                    "precision": "fp64", "nrhs": 1},
         "solve_time_s": elapsed / args.steps,
         "setup_s": setup_s,
-        "outer_its": int(infos[-1]["outer_its"][0]),
-        "pcg_its_per_solve": int(infos[-1]["inner_its"][0]),
+        "outer_its": outer,
+        "pcg_its_per_solve": pcg_its,
         "relres": float(infos[-1]["relres"][0]),
-        "applies_per_solve": {k: v // args.steps for k, v in st["applies"].items()},
+        "applies_per_solve": per_solve,
+        "applies_past_convergence_per_solve": past,
+        "value_definition": "cell applies of F̊, M̊_D^-1, Ů, Ůᵀ and K̊^-ROM (one per cell per load case) over the "
+                            "timed solves, divided by their wall time; per_operator gives each operator alone",
+        "per_operator": per_operator,
         "roofline": roof,
         "kernels": kernels,
     }
     if forms is not None:
         out["forms"] = forms
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample) ...")
-        out["cpu_baseline"] = cpu_baseline()
     ctx.close()
+    if cpu is not None:
+        log("cpu baseline (oracle on c2, bounded sample) ...")
+        out["cpu_baseline"] = cpu.collect()
     print(json.dumps(out), flush=True)
 
 
