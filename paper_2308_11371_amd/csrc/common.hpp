@@ -168,6 +168,8 @@ struct PendingEvent {
     hipEvent_t a, b;
 };
 
+void release_blas(void *handle);  // destroys a rocBLAS handle (null: nothing)
+
 }  // namespace ifeti
 
 struct ifeti_ctx {
@@ -312,7 +314,11 @@ struct ifeti_ctx {
         frag.erase(std::remove_if(frag.begin(), frag.end(), [](const FragCopy &cp) { return !cp.frag; }),
                    frag.end());
     }
-    ~ifeti_ctx() { free_copies(); }
+    void *blas = nullptr;               // rocBLAS handle of the plain FP64 products (created on first use)
+    ~ifeti_ctx() {
+        free_copies();
+        ifeti::release_blas(blas);
+    }
 
     // ---- statistics
     long long applies[IFETI_OP_COUNT] = {0, 0, 0, 0, 0, 0};
@@ -386,9 +392,8 @@ void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V, std::ve
 // fragment-order FP64 copies of the operators the interface operators contract with (built at setup)
 void prepare_operator_copies(ifeti_ctx *c);
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
-// beside: the launch shares the GPU with a concurrent branch (tile shapes that leave registers free)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true, bool beside = false);
+          bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
 
 // ops.hip
 class SideStream {
@@ -435,10 +440,9 @@ const void *read_back(ifeti_ctx *c, const void *dev, size_t bytes);
 void coarse_reduce(ifeti_ctx *c, const CoarseSolver &co, double *y, long long y_rs, int nrhs, double scale);
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w = nullptr,
              double *dot_part = nullptr);
-// F̊ lam with explicit work buffers: Y, Yc [N*nrhs][n_d], cb [N*nrhs][n_p], zP, yP [nrhs][nP]; side: the
-// contraction on the second stream beside the coarse branch (else everything on the context stream)
+// F̊ lam with explicit work buffers: Y, Yc [N*nrhs][n_d], cb [N*nrhs][n_p], zP, yP [nrhs][nP]
 void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double *Y, double *Yc, double *cb,
-                  double *zP, double *yP, bool side, const double *dot_w, double *dot_part);
+                  double *zP, double *yP, const double *dot_w, double *dot_part);
 void apply_MD(ifeti_ctx *c, const double *r, double *out, int nrhs, const double *dot_w = nullptr,
               double *dot_part = nullptr);
 int dot_blocks(long long n);

@@ -30,6 +30,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <rocblas/rocblas.h>
+
 #include "common.hpp"
 
 namespace ifeti {
@@ -1107,8 +1109,46 @@ void prepare_operator_copies(ifeti_ctx *c) {
     (void)frag_copy(c, c->Sdd.p, c->n_d, c->n_d, c->K);  // M̊_D^-1 (49)
 }
 
+void release_blas(void *handle) {
+    if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
+}
+
+// A plain product (one operator, no principal coefficients, no fused gather) with many rows in FP64:
+// the stacked principal inverses of (46a) applied to every cell vector.  rocBLAS's DGEMM runs it at
+// 0.87 of the FP64 matrix peak on the c2 shape (7680 x 640 times 640 x 4096), against 0.51 for the
+// principal-shared kernel, whose LDS staging is built for the coefficient-weighted sums.  A forced
+// tile candidate keeps the own kernel (its parity tests force every candidate), and so does an
+// allocation-free call.
+static bool library_gemm(ifeti_ctx *c, const GemmGroup &g, double *Y, int ldy, long long ybs, int M, int ncols,
+                         int ncells, bool accumulate, const char *tag) {
+    if (g.K != 1 || g.coef || g.gcodes || g.gw || g.scale != 1.0 || accumulate || M < 512 || c->no_alloc ||
+        c->opt.tile_candidate >= 0 || ncols % ncells != 0)
+        return false;
+    if (!c->blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return false;
+        c->blas = h;
+    }
+    rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+    const int nrhs = ncols / ncells;
+    const long long xbs = g.xbs ? g.xbs : (long long)ncells * g.ldx;
+    const long long ys = ybs ? ybs : (long long)ncells * ldy;
+    IFETI_REQUIRE(rocblas_set_stream(h, c->stream) == rocblas_status_success, IFETI_EHIP, "rocblas_set_stream");
+    const double one = 1.0, zero = 0.0;
+    Prof prof(c, tag, 2.0 * M * (double)ncols * g.Kd,
+              8.0 * ((double)M * g.Kd + (double)ncols * g.Kd + (double)ncols * M));
+    // Y (M x ncells per load case, column-major, ld ldy) = A (M x Kd, row-major = transposed
+    // column-major) times X (Kd x ncells, ld ldx)
+    const rocblas_status st = rocblas_dgemm_strided_batched(
+        h, rocblas_operation_transpose, rocblas_operation_none, M, ncells, g.Kd, &one, g.A, g.Kd, 0, g.X, g.ldx,
+        xbs, &zero, Y, ldy, ys, nrhs);
+    IFETI_REQUIRE(st == rocblas_status_success, IFETI_EHIP,
+                  std::string("rocblas_dgemm_strided_batched: ") + rocblas_status_to_string(st));
+    return true;
+}
+
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
-          bool accumulate, int ncells, const char *tag, bool lp_ok, bool beside) {
+          bool accumulate, int ncells, const char *tag, bool lp_ok) {
     IFETI_REQUIRE(ngroups >= 1 && ngroups <= 2, IFETI_EINVAL, "gemm: 1 or 2 groups");
     for (int i = 0; i < ngroups; ++i)
         IFETI_REQUIRE(groups[i].K >= 1 && groups[i].K <= kMaxCoefK, IFETI_EINVAL, "gemm: 1 to 40 principal operators");
@@ -1151,6 +1191,8 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     for (int i = 0; i < ngroups; ++i) abytes += 8.0 * (double)groups[i].K * M * groups[i].Kd;
     const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
     const bool lp_path = lp_ok && prec != IFETI_FP64 && M > 16 && Kdmax > 16;
+    if (!lp_path && ngroups == 1 && library_gemm(c, groups[0], Y, ldy, a.ybs, M, ncols, a.ncells, accumulate, tag))
+        return;
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
     // large operators, or many columns (a block of load cases): row-owning waves, fragment units
@@ -1243,8 +1285,8 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
             // branch, the one-workgroup-per-CU 64-row tile (173 VGPRs, two waves per SIMD) instead of the
             // fastest tile alone (two workgroups per CU, which fill the register files and hold the branch
             // back until the contraction ends); such launches are not autotuned (timed alone)
-            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : (beside ? 6 : 7)));
-            FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate && !beside);
+            const int def = frag_big ? 2 : (f.MT <= 2 ? 4 : (Kdmax <= 16 ? 3 : 7));
+            FragLauncher launch_fn = choose_launcher(c, f, frag_big, def, !accumulate);
             launch_fn(f, c->stream, prof.start(), prof.stop());
         }
         IFETI_HIP(hipGetLastError());

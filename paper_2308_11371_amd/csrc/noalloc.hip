@@ -62,7 +62,7 @@ extern "C" int ifeti_apply_F_noalloc(ifeti_ctx *c, const double *lam, double *ou
         double *base = scratch_on_current_device();
         double *Y = base, *Yc = Y + nY, *cb = Yc + nY, *zP = cb + nC, *yP = zP + nPv;
         NoAllocScope scope(c);
-        apply_F_into(c, lam, out, nrhs, Y, Yc, cb, zP, yP, false, nullptr, nullptr);
+        apply_F_into(c, lam, out, nrhs, Y, Yc, cb, zP, yP, nullptr, nullptr);
         IFETI_HIP(hipGetLastError());
         return IFETI_OK;
     } catch (const Error &e) {

@@ -1680,9 +1680,8 @@ void op_coarse_solve(ifeti_ctx *c, const double *z, long long z_rs, double *y, l
 
 // ------------------------------------------------------------------ F̊ (48)
 // Lambda = B_d^T lam; c_s = (T_dr Ů_rp^(s))^T Lambda_s, assembled and sent through the
-// coarse solve on the side stream while the main stream runs the dominant
-// contraction sum_k delta_k F_dd^(k) Lambda; the coarse correction
-// (T_dr Ů_rp^(s)) A_p^T y_P is added after the join, then B_d scatters.
+// coarse solve; the dominant contraction sum_k delta_k F_dd^(k) Lambda; the coarse correction
+// (T_dr Ů_rp^(s)) A_p^T y_P is added as B_d scatters.
 void combine_coarse_maps(ifeti_ctx *c) {
     const int npd = c->n_p * c->n_d;
     IFETI_REQUIRE(c->n_p <= kMaxNp, IFETI_EINVAL, "too many primal dofs per cell");
@@ -1730,26 +1729,20 @@ void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long
 // side stream while the main stream runs the dominant contraction; the
 // prolongation is folded into the final scatter.
 void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double *Y, double *Yc, double *cb,
-                  double *zP, double *yP, bool side, const double *dot_w, double *dot_part) {
+                  double *zP, double *yP, const double *dot_w, double *dot_part) {
     const int N = c->N, nd = c->n_d, K = c->K;
     const int cols = N * nrhs;
     GemmGroup g1;  // B_d^T lam fused into the staging
     g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
     g1.K = K;
-    // the restriction runs first and alone (8 us on c2; beside the contraction it would wait for free
-    // registers until the contraction ends); then the dominant contraction runs on the second stream
-    // beside the rest of the coarse branch, into its own buffer
+    // one stream, in order: the coarse branch beside the contraction on a second stream measured
+    // slower on c2 (each cross-stream wait costs about 15 us on the host and leaves a gap of that
+    // order on the GPU, more than the overlap gains)
     op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
-    if (side) {
-        SideStream s(c);
-        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm", true, true);
-    } else {
-        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
-    }
+    gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
     op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
     op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
     op_prolong_cells(c, c->Wc.p, yP, c->nP, Yc, nrhs, false, "F_prolong");
-    if (side) join_side(c);
     op_scatter(c, Y, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, Yc);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
@@ -1757,7 +1750,7 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
 
 void apply_F(ifeti_ctx *c, const double *lam, double *out, int nrhs, const double *dot_w, double *dot_part) {
     ensure_work(c, nrhs);
-    apply_F_into(c, lam, out, nrhs, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p, c->w_yP.p, true, dot_w, dot_part);
+    apply_F_into(c, lam, out, nrhs, c->w_Y.p, c->w_Yc.p, c->w_c.p, c->w_zP.p, c->w_yP.p, dot_w, dot_part);
 }
 
 // ------------------------------------------------------------------ M̊_D^-1 (49)
