@@ -276,12 +276,29 @@ void build_coarse_partition(ifeti_ctx *c, CoarseSolver &co) {
             for (int t = 0; t < br; ++t) M3.push_back(-ER[i][(size_t)t * m + q]);
         }
     }
+    // tiles of up to 16 consecutive rows with one input range (one MFMA row tile each)
+    auto tiles = [](const std::vector<CoarseRow> &R) {
+        std::vector<CoarseTile> T;
+        for (int i = 0; i < (int)R.size();) {
+            int j = i + 1;
+            while (j < (int)R.size() && j - i < 16 && R[j].xlo == R[i].xlo && R[j].len == R[i].len &&
+                   R[j].off == R[j - 1].off + R[i].len)
+                ++j;
+            T.push_back(CoarseTile{i, j - i});
+            i = j;
+        }
+        return T;
+    };
     co.cp_M1.upload(M1, c->stream);
     co.cp_M2.upload(Sinv, c->stream);
     co.cp_M3.upload(M3, c->stream);
     co.cp_R1.upload(R1, c->stream);
     co.cp_R2.upload(R2, c->stream);
     co.cp_R3.upload(R3, c->stream);
+    const std::vector<CoarseTile> T1 = tiles(R1), T2 = tiles(R2), T3 = tiles(R3);  // live until the sync below
+    co.cp_T1.upload(T1, c->stream);
+    co.cp_T2.upload(T2, c->stream);
+    co.cp_T3.upload(T3, c->stream);
     co.w_cg.alloc((size_t)ns * 3);
     co.w_cw.alloc((size_t)n * 3);
     IFETI_HIP(hipStreamSynchronize(c->stream));

@@ -132,6 +132,10 @@ struct CoarseRow {
     long long off;
     int xlo, len, out, pad;
 };
+// up to 16 consecutive rows of one phase that share their input range (stored one after another)
+struct CoarseTile {
+    int row0, nrows;
+};
 
 // Direct solver of an assembled coarse problem S_PP (banded in the lexicographic vertex order).
 struct CoarseSolver {
@@ -149,6 +153,7 @@ struct CoarseSolver {
     int cp_p = 0, cp_ns = 0;      // interior blocks (0: not built), separator rows
     DevBuf<double> cp_M1, cp_M2, cp_M3;
     DevBuf<CoarseRow> cp_R1, cp_R2, cp_R3;
+    DevBuf<CoarseTile> cp_T1, cp_T2, cp_T3;  // the same rows in tiles (blocks of load cases)
     DevBuf<double> w_cg, w_cw;    // separator rhs [rhs][ns], assembled input [rhs][nP]
     // approximate solve (block Jacobi): the inverse of each diagonal block of B rows, one row per output
     int ap_B = 0;
@@ -329,6 +334,8 @@ struct ifeti_ctx {
 
     // ---- work buffers
     ifeti::DevBuf<double> w_Lam, w_Y, w_c, w_zP, w_yP, w_yp, w_R, w_H, w_Yc, w_split, w_x, w_tmpL, w_tmpU;
+    ifeti::DevBuf<float> w_R32;          // precision form: R of (46a) in FP32 (the library's narrow product)
+    ifeti::DevBuf<unsigned short> w_v16; // the narrow copy of v (FP32 as two halves, or BF16)
     ifeti::DevBuf<double> w_red;        // reduction partials
     ifeti::DevBuf<double> pcg_r, pcg_z, pcg_p, pcg_q, pcg_st, pcg_pa, pcg_pb, pcg_pc;  // interface PCG state
     ifeti::DevBuf<int> pcg_ist;
@@ -394,6 +401,12 @@ void prepare_operator_copies(ifeti_ctx *c);
 // Y column c at Y + (c / ncells)*ybs + (c % ncells)*ldy (ybs 0: ncells*ldy; ncells 0: N)
 void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy, long long ybs, int M, int ncols,
           bool accumulate, int ncells = 0, const char *tag = "gemm", bool lp_ok = true);
+// The plain product Y32 = A X (A M x Kd row-major, column s of load case r at X + r*xbs + s*ldx) with
+// narrow operands (kind IFETI_FP32_LOCAL or IFETI_BF16_LOCAL, FP32 accumulation and FP32 result) by the
+// library: Y32 column r*ncells + s at Y32 + (r*ncells + s)*M.  False when it does not apply (the caller
+// then runs the own kernels).
+bool library_gemm_narrow(ifeti_ctx *c, const double *A, int M, int Kd, const double *X, int ldx, long long xbs,
+                         int ncells, int nrhs, int kind, float *Y32, const char *tag);
 
 // ops.hip
 class SideStream {

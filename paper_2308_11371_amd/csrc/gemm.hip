@@ -1116,13 +1116,14 @@ void release_blas(void *handle) {
 // A plain product (one operator, no principal coefficients, no fused gather) with many rows in FP64:
 // the stacked principal inverses of (46a) applied to every cell vector.  rocBLAS's DGEMM runs it at
 // 0.87 of the FP64 matrix peak on the c2 shape (7680 x 640 times 640 x 4096), against 0.51 for the
-// principal-shared kernel, whose LDS staging is built for the coefficient-weighted sums.  A forced
-// tile candidate keeps the own kernel (its parity tests force every candidate), and so does an
-// allocation-free call.
+// principal-shared kernel, whose LDS staging is built for the coefficient-weighted sums.  Few columns
+// (the coarse solve of a block of load cases: 8320 x 8320 times 32 columns) stay with the own kernels,
+// where the library runs at a quarter of their rate.  A forced tile candidate keeps the own kernel
+// (its parity tests force every candidate), and so does an allocation-free call.
 static bool library_gemm(ifeti_ctx *c, const GemmGroup &g, double *Y, int ldy, long long ybs, int M, int ncols,
                          int ncells, bool accumulate, const char *tag) {
-    if (g.K != 1 || g.coef || g.gcodes || g.gw || g.scale != 1.0 || accumulate || M < 512 || c->no_alloc ||
-        c->opt.tile_candidate >= 0 || ncols % ncells != 0)
+    if (g.K != 1 || g.coef || g.gcodes || g.gw || g.scale != 1.0 || accumulate || M < 512 || ncols < 1024 ||
+        c->no_alloc || c->opt.tile_candidate >= 0 || ncols % ncells != 0)
         return false;
     if (!c->blas) {
         rocblas_handle h = nullptr;
@@ -1144,6 +1145,84 @@ static bool library_gemm(ifeti_ctx *c, const GemmGroup &g, double *Y, int ldy, l
         xbs, &zero, Y, ldy, ys, nrhs);
     IFETI_REQUIRE(st == rocblas_status_success, IFETI_EHIP,
                   std::string("rocblas_dgemm_strided_batched: ") + rocblas_status_to_string(st));
+    return true;
+}
+
+// narrow copies for the library: A row-major in FP32 or BF16 (cached with the fragment copies, kind
+// 100 + precision), X cast column by column
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_cols(const double *__restrict__ X, int ldx, long long xbs, int Kd,
+                                                   int ncells, int nrhs, T *__restrict__ Y) {
+    const long long n = (long long)Kd * ncells * nrhs;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const long long col = e / Kd;
+    const int k = (int)(e % Kd), r = (int)(col / ncells), s = (int)(col % ncells);
+    Y[e] = (T)X[r * xbs + (long long)s * ldx + k];
+}
+
+static const void *plain_copy_narrow(ifeti_ctx *c, const double *A, int M, int Kd, int kind) {
+    const int key = 100 + kind;
+    for (auto &cp : c->frag)
+        if (cp.src == A && cp.M == M && cp.Kd == Kd && cp.K == 1 && cp.kind == key) return cp.frag;
+    const bool bf = kind == IFETI_BF16_LOCAL;
+    const long long n = (long long)M * Kd;
+    ifeti_ctx::FragCopy cp;
+    cp.src = A;
+    cp.M = M;
+    cp.Kd = Kd;
+    cp.K = 1;
+    cp.kind = key;
+    IFETI_HIP(hipMalloc(&cp.frag, n * (bf ? 2 : 4)));
+    if (bf)
+        hipLaunchKernelGGL(k_cast_cols<__bf16>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, Kd,
+                           0LL, Kd, M, 1, (__bf16 *)cp.frag);
+    else
+        hipLaunchKernelGGL(k_cast_cols<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, A, Kd, 0LL,
+                           Kd, M, 1, (float *)cp.frag);
+    IFETI_HIP(hipGetLastError());
+    c->frag.push_back(cp);
+    return cp.frag;
+}
+
+bool library_gemm_narrow(ifeti_ctx *c, const double *A, int M, int Kd, const double *X, int ldx, long long xbs,
+                         int ncells, int nrhs, int kind, float *Y32, const char *tag) {
+    if ((kind != IFETI_FP32_LOCAL && kind != IFETI_BF16_LOCAL) || c->no_alloc || c->opt.tile_candidate >= 0 ||
+        (long long)ncells * nrhs < 1024)
+        return false;
+    if (!c->blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return false;
+        c->blas = h;
+    }
+    rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+    const bool bf = kind == IFETI_BF16_LOCAL;
+    const void *An = plain_copy_narrow(c, A, M, Kd, kind);
+    const long long nx = (long long)Kd * ncells * nrhs;
+    c->w_v16.ensure((size_t)nx * (bf ? 1 : 2), c->stream);
+    if (bf)
+        hipLaunchKernelGGL(k_cast_cols<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, X, ldx,
+                           xbs, Kd, ncells, nrhs, (__bf16 *)c->w_v16.p);
+    else
+        hipLaunchKernelGGL(k_cast_cols<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, X, ldx, xbs,
+                           Kd, ncells, nrhs, (float *)c->w_v16.p);
+    IFETI_HIP(hipGetLastError());
+    IFETI_REQUIRE(rocblas_set_stream(h, c->stream) == rocblas_status_success, IFETI_EHIP, "rocblas_set_stream");
+    const double cols = (double)ncells * nrhs;
+    Prof prof(c, tag, 2.0 * M * cols * Kd, (bf ? 2.0 : 4.0) * ((double)M * Kd + cols * Kd) + 4.0 * cols * M);
+    const float one = 1.0f, zero = 0.0f;
+    const rocblas_int n = ncells * nrhs;  // the narrow copy of X is one contiguous Kd x n matrix
+    rocblas_status st;
+    if (bf)
+        st = rocblas_gemm_ex(h, rocblas_operation_transpose, rocblas_operation_none, M, n, Kd, &one, An,
+                             rocblas_datatype_bf16_r, Kd, c->w_v16.p, rocblas_datatype_bf16_r, Kd, &zero, Y32,
+                             rocblas_datatype_f32_r, M, Y32, rocblas_datatype_f32_r, M, rocblas_datatype_f32_r,
+                             rocblas_gemm_algo_standard, 0, 0);
+    else
+        st = rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, M, n, Kd, &one, (const float *)An, Kd,
+                           (const float *)c->w_v16.p, Kd, &zero, Y32, M);
+    IFETI_REQUIRE(st == rocblas_status_success, IFETI_EHIP,
+                  std::string("rocBLAS narrow product: ") + rocblas_status_to_string(st));
     return true;
 }
 

@@ -470,6 +470,91 @@ __global__ __launch_bounds__(256) void k_coarse_rows(const double *__restrict__ 
     }
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// The same phase rows for a block of load cases, as FP64 MFMA tiles: one workgroup of four waves per
+// tile of up to 16 rows sharing their input range, output [16 rows] x [16 NT load cases]; the waves
+// take every fourth 16-column step of the range (a phase has only about a hundred tiles, each a few
+// hundred KB of rows) and their partial tiles are added in wave order through LDS.  The k index of the
+// 16x16x4 product is assigned so that lane (lr, lk) of step t takes column c + 4 lk + t: each lane then
+// walks four consecutive entries of its row of M and of its load case's input.  Workgroups past the
+// tiles copy cz into cw (ncopy entries per load case) as the row form does.
+template <int NT>
+__global__ __launch_bounds__(256) void k_coarse_tiles(const double *__restrict__ M, const CoarseRow *__restrict__ rows,
+                                                      const CoarseTile *__restrict__ tiles, int ntiles,
+                                                      const double *__restrict__ x, long long x_rs, double alpha,
+                                                      double *__restrict__ y, long long y_rs, double alpha2,
+                                                      double *__restrict__ y2, long long y2_rs,
+                                                      const double *__restrict__ cz, long long cz_rs,
+                                                      double *__restrict__ cw, long long cw_rs, int ncopy, int nrhs) {
+    constexpr int WPT = 4;
+    __shared__ double part[WPT][NT][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((int)blockIdx.x >= ntiles) {  // the copy: whole workgroups, before any barrier
+        const long long e = (long long)(blockIdx.x - ntiles) * 256 + threadIdx.x;
+        if (e < (long long)ncopy * nrhs) {
+            const int q = (int)(e / ncopy);
+            const long long i = e % ncopy;
+            cw[q * cw_rs + i] = cz[q * cz_rs + i];
+        }
+        return;
+    }
+    const CoarseTile T = tiles[blockIdx.x];
+    const CoarseRow R0 = rows[T.row0];
+    const int lr = lane & 15, lk = lane >> 4;
+    const bool rowok = lr < T.nrows;
+    const double *m = M + R0.off + (size_t)(rowok ? lr : 0) * R0.len;
+    const double *xb = x + R0.xlo;
+    v4d acc[NT];
+    bool qok[NT];
+    const double *xq[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int q = 16 * j + lr;
+        qok[j] = q < nrhs;
+        xq[j] = xb + (size_t)(qok[j] ? q : 0) * x_rs;
+    }
+    const int len = R0.len;
+    for (int c = 16 * wave; c < len; c += 16 * WPT) {  // uniform per wave: the MFMA needs all 64 lanes
+        double a[4], b[NT][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int cc = c + 4 * lk + t;
+            const bool in = cc < len;
+            a[t] = rowok && in ? m[cc] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) b[j][t] = qok[j] && in ? xq[j][cc] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[j][t], acc[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[wave][j][i][lane] = acc[j][i];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 4 * i + lk;
+        if (row >= T.nrows) continue;
+        const int out = rows[T.row0 + row].out;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int q = 16 * j + lr;
+            if (q >= nrhs) continue;
+            double sum = part[0][j][i][lane];
+#pragma unroll
+            for (int w = 1; w < WPT; ++w) sum += part[w][j][i][lane];
+            y[q * y_rs + out] = alpha * sum;
+            if (y2) y2[q * y2_rs + out] = alpha2 * sum;
+        }
+    }
+}
+
 // one workgroup per (block row I, load case): thread (part, r) sums the
 // contributions J = part, part + 16, ... of row r; the 16 parts are added in
 // order through LDS
@@ -504,7 +589,6 @@ __global__ __launch_bounds__(1024) void k_sym_reduce(const double *__restrict__ 
 // G = R^T K_rr^(s) R uses the cell's own stencil values; G c = R^T v is solved
 // by Cholesky (symmetric pseudo-inverse with a 1e-13 relative cut if a pivot
 // fails) and x = R c is written.
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 // (46b) step 1: H_c = K_rr^(s) R for a chunk of KCOL reduced-basis vectors.
 // One workgroup per column c; the chunk of R (n_r x KCOL, from the [r][k] layout) is staged in LDS
@@ -777,6 +861,212 @@ __global__ __launch_bounds__(64 * WPB) void k_rom_gram(const double *__restrict_
     }
 }
 
+// (46b) fused, one workgroup per column (cell s, load case): H = K_rr^(s) R is formed chunk by chunk
+// in LDS and never stored; as each chunk of H appears, the waves add its share of
+// [G | g] = R^T [H | v] on the FP64 MFMA (rows of R split across waves, partial tiles summed in wave
+// order), then the block solves G c = g and writes x = R c.  H takes the place of the staged chunk of R,
+// so the Gram product and the combination read R again (from L2 or the last-level cache); keeping both
+// resident halves the workgroups per CU and measured slower.  K <= 16, one 16 x 16 tile of [G | g]:
+// a chunk has at most 15 columns, so column kc of the first chunk carries R^T v.
+template <typename TR, int D, int KCOL>
+__global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, const double *__restrict__ Kst,
+                                                      const int *__restrict__ r_of_dof,
+                                                      const double *__restrict__ vR, long long v_rs, int N,
+                                                      int nrhs, int K, int n_r, int nc, int n_ctrl,
+                                                      double *__restrict__ xR, long long x_rs) {
+    constexpr int P = 2;  // quadratic B-splines: neighbours within +-2
+    constexpr int W = 2 * P + 1;
+    constexpr int NOFF = D == 2 ? W * W : W * W * W;
+    constexpr int KP = KCOL | 1;  // odd row stride: lanes reading neighbouring rows hit distinct banks
+    static_assert(KCOL <= 15, "column KCOL of the Gram tile carries R^T v");
+    extern __shared__ double lds[];
+    // workgroups go to the eight XCDs in turn: with several load cases, workgroup b takes cell
+    // (b mod 8) + 8 (j / nrhs) and load case j mod nrhs, j = b / 8, so the load cases of a cell run
+    // together on one XCD and its L2 serves them the cell's stencil (the grid is padded to 8 ceil(N/8)
+    // cells; one load case: the identity)
+    int s = blockIdx.x, rhs = 0;
+    if (nrhs > 1) {
+        const int j = blockIdx.x >> 3;
+        s = (blockIdx.x & 7) + 8 * (j / nrhs);
+        rhs = j % nrhs;
+        if (s >= N) return;  // padding: the whole workgroup, before any barrier
+    }
+    const int col = rhs * N + s, tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const size_t rows = (size_t)(n_r + 1) * KP;
+    double *Rl = lds;                             // [n_r + 1][KP] a chunk of R, row n_r zero
+    double *Hl = lds;                             // then H of the chunk, then the wave partials
+    double *G = Hl + rows;                        // [K][K], then a copy of it, Lm, V [K][K], g [K], c [K]
+    double *G0 = G + K * K, *Lm = G0 + K * K, *Vm = Lm + K * K, *gb = Vm + K * K, *cv = gb + K;
+    int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or the zero row n_r
+    const TR *Rc = R + (size_t)col * K * n_r;
+    const double *v = vR + (size_t)rhs * v_rs + (size_t)s * n_r;
+    const double *Ks = Kst + (size_t)s * n_ctrl * NOFF * D * D;
+    for (int e = tid; e < n_ctrl * D; e += nt) {
+        const int rr = r_of_dof[e];
+        rmap[e] = rr >= 0 ? rr : n_r;
+    }
+    for (int k0 = 0; k0 < K; k0 += KCOL) {
+        const int kc = min(KCOL, K - k0);
+        const int tot = (n_r + 1) * KCOL;
+        // four loads in flight per thread, then the stores (c2: 661 us against 705 with one; the Gram loop
+        // below unrolled the same way ran out of registers and slowed to 774 us)
+        constexpr int SU = 4;
+        for (int e0 = tid; e0 < tot; e0 += SU * nt) {
+            double tmp[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int e = e0 + u * nt, r = e / KCOL, kk = e % KCOL;
+                tmp[u] = (e < tot && kk < kc && r < n_r) ? (double)Rc[(size_t)r * K + k0 + kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int e = e0 + u * nt;
+                if (e < tot) Rl[(e / KCOL) * KP + e % KCOL] = tmp[u];
+            }
+        }
+        __syncthreads();
+        double h[D][KCOL];
+        const int a = tid;  // one control point per thread (blockDim >= n_ctrl)
+        if (a < n_ctrl) {
+            int ma[D], stride[D];
+            {
+                int ta = a, st = 1;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    ma[j] = ta % nc;
+                    ta /= nc;
+                    stride[j] = st;
+                    st *= nc;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int q = 0; q < KCOL; ++q) h[i][q] = 0.0;
+#pragma unroll W
+            for (int o = 0; o < NOFF; ++o) {
+                int b = a;
+                bool ok = true;
+                {
+                    int to = o;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const int d = to % W - P;
+                        to /= W;
+                        const int m = ma[j] + d;
+                        ok = ok && m >= 0 && m < nc;
+                        b += d * stride[j];
+                    }
+                }
+                if (!ok) b = a;  // stencil value stored as zero for this offset
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double *row = Rl + rmap[b * D + k] * KP;
+                    double kv[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) kv[i] = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
+#pragma unroll
+                    for (int q = 0; q < KCOL; ++q) {
+                        const double rq = row[q];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) h[i][q] += kv[i] * rq;
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every thread has read the chunk of R before H takes its place
+        if (a < n_ctrl)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int ri = rmap[a * D + i];
+                if (ri < n_r)
+#pragma unroll
+                    for (int q = 0; q < KCOL; ++q) Hl[ri * KP + q] = h[i][q];
+            }
+        __syncthreads();
+        // this chunk's columns of [G | g]: rows k = 4 i + lk, column q = lr (q == kc: R^T v, first chunk)
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        const int nt4 = (n_r + 3) / 4;
+        for (int t = wave; t < nt4; t += nw) {  // uniform per wave: the MFMA needs all 64 lanes
+            const int r = 4 * t + lk;
+            const bool rin = r < n_r;
+            const double af = (rin && lr < K) ? (double)Rc[(size_t)r * K + lr] : 0.0;
+            const double bf = !rin ? 0.0 : (lr < kc ? Hl[r * KP + lr] : (lr == kc && k0 == 0 ? v[r] : 0.0));
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
+        }
+        __syncthreads();  // H read by every wave: its rows take the partial tiles
+        double *part = Hl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[(size_t)(wave * 4 + i) * 64 + lane] = acc[i];
+        __syncthreads();
+        if (tid < 256) {
+            const int i = tid >> 6, l = tid & 63;
+            const int k = 4 * i + (l >> 4), q = l & 15;
+            double sum = 0.0;
+            for (int w = 0; w < nw; ++w) sum += part[(size_t)(w * 4 + i) * 64 + l];
+            if (k < K) {
+                if (q < kc) G[k * K + k0 + q] = sum;
+                else if (q == kc && k0 == 0) gb[k] = sum;
+            }
+        }
+        __syncthreads();  // partials consumed before the next chunk is staged
+    }
+    for (int e = tid; e < K * K; e += nt) {  // the upper triangle, mirrored; a copy for the fallback
+        const int i = e / K, j = e % K;
+        G0[e] = G[e] = j < i ? G[j * K + i] : G[e];
+    }
+    __syncthreads();
+    // G c = g by a Cholesky factorisation spread over the block (one barrier per step; the one-lane
+    // form would leave the CU idle for tens of microseconds per column); a pivot that is not positive
+    // hands the copy to the one-lane solve with its eigen-decomposition fallback
+    bool spd = true;
+    for (int j = 0; j < K && spd; ++j) {
+        const double d = G[j * K + j];  // the same value in every thread: a uniform branch
+        if (!(d > 0.0)) {
+            spd = false;
+            break;
+        }
+        const double l = sqrt(d);
+        if (tid > j && tid < K) G[tid * K + j] /= l;
+        __syncthreads();
+        if (tid == 0) G[j * K + j] = l;
+        for (int e = tid; e < K * K; e += nt) {
+            const int i = e / K, m = e % K;
+            if (m > j && m <= i) G[e] -= G[i * K + j] * G[m * K + j];
+        }
+        __syncthreads();
+    }
+    if (spd) {
+        if (tid < K) cv[tid] = gb[tid];
+        __syncthreads();
+        for (int j = 0; j < K; ++j) {  // L y = g, column by column
+            const double yj = cv[j] / G[j * K + j];
+            __syncthreads();
+            if (tid > j && tid < K) cv[tid] -= G[tid * K + j] * yj;
+            if (tid == j) cv[j] = yj;
+            __syncthreads();
+        }
+        for (int j = K - 1; j >= 0; --j) {  // L^T c = y
+            const double cj = cv[j] / G[j * K + j];
+            __syncthreads();
+            if (tid < j) cv[tid] -= G[j * K + tid] * cj;
+            if (tid == j) cv[j] = cj;
+            __syncthreads();
+        }
+    } else {
+        if (tid == 0) small_sym_solve(G0, Lm, Vm, gb, cv, K);
+        __syncthreads();
+    }
+    double *x = xR + (size_t)rhs * x_rs + (size_t)s * n_r;
+    for (int r = tid; r < n_r; r += nt) {
+        double t = 0.0;
+        for (int k = 0; k < K; ++k) t += (double)Rc[(size_t)r * K + k] * cv[k];
+        x[r] = t;
+    }
+}
+
 // ------------------------------------------------------------------ K̊^-MPCG (Remark 6)
 // Multi-preconditioned CG for the local problems K_rr^(s) x = v with the principal inverses as the K
 // preconditioners.  Each iteration's block Z = [K_rr^(σk)-1 r]_k is whitened, Ẑ = Z T with
@@ -954,10 +1244,18 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
                                                const int *__restrict__ gl, int N, int n_r, int n_p, int n_i,
                                                int n_d, int nc, int n_ctrl, int n_off, int p,
                                                double *__restrict__ y, long long y_rs,
-                                               double *__restrict__ yp_cells) {
+                                               double *__restrict__ yp_cells, int nrhs) {
     extern __shared__ double uloc[];
-    const int col = blockIdx.x;
-    const int rhs = col / N, s = col % N;
+    // several load cases: the load cases of a cell together on one XCD (its L2 then serves the cell's
+    // stencil to all of them), as in the fused reduced local solve
+    int s = blockIdx.x, rhs = 0;
+    if (nrhs > 1) {
+        const int j = blockIdx.x >> 3;
+        s = (blockIdx.x & 7) + 8 * (j / nrhs);
+        rhs = j % nrhs;
+        if (s >= N) return;  // padding: the whole workgroup, before any barrier
+    }
+    const int col = rhs * N + s;
     const int tid = threadIdx.x;
     const int n_dof = n_ctrl * D;
     const double *u = x + rhs * x_rs;
@@ -1575,6 +1873,53 @@ void coarse_rows(ifeti_ctx *c, const double *M, const CoarseRow *rows, int nrows
     IFETI_HIP(hipGetLastError());
 }
 
+// the phases for a block of load cases (up to 32 a pass): the tile form, each row of the phase matrices
+// read once per 32 load cases
+static void coarse_partitioned_tiles(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y,
+                                     long long y_rs, int nrhs, double scale) {
+    const int n = c->nP, ns = co.cp_ns;
+    const int nb = std::min(nrhs, 32);
+    co.w_cg.ensure((size_t)ns * nb, c->stream);
+    co.w_cw.ensure((size_t)n * nb, c->stream);
+    for (int r0 = 0; r0 < nrhs; r0 += 32) {
+        const int nr = std::min(32, nrhs - r0);
+        const double *zz = z + (size_t)r0 * z_rs;
+        double *yy = y + (size_t)r0 * y_rs;
+        auto launch = [&](const double *M, const CoarseRow *rows, const CoarseTile *tiles, int ntiles,
+                          const double *x, long long x_rs, double alpha, double *yo, long long yo_rs, double alpha2,
+                          double *y2, long long y2_rs, const double *cz, int ncopy) {
+            const unsigned blocks = (unsigned)(ntiles + ((long long)ncopy * nr + 255) / 256);
+            if (nr <= 16)
+                hipLaunchKernelGGL(k_coarse_tiles<1>, dim3(blocks), dim3(256), 0, c->stream, M, rows, tiles, ntiles, x,
+                                   x_rs, alpha, yo, yo_rs, alpha2, y2, y2_rs, cz, z_rs, co.w_cw.p, (long long)n,
+                                   ncopy, nr);
+            else
+                hipLaunchKernelGGL(k_coarse_tiles<2>, dim3(blocks), dim3(256), 0, c->stream, M, rows, tiles, ntiles, x,
+                                   x_rs, alpha, yo, yo_rs, alpha2, y2, y2_rs, cz, z_rs, co.w_cw.p, (long long)n,
+                                   ncopy, nr);
+            IFETI_HIP(hipGetLastError());
+        };
+        {
+            Prof prof(c, "coarse_sep_rhs", 2.0 * (double)co.cp_M1.n * nr,
+                      8.0 * ((double)co.cp_M1.n + (double)ns * nr + 2.0 * n * nr) + 24.0 * ns);
+            launch(co.cp_M1.p, co.cp_R1.p, co.cp_T1.p, (int)co.cp_T1.n, zz, z_rs, -1.0, co.w_cg.p, ns, 0.0, nullptr, 0,
+                   zz, n);
+        }
+        {
+            Prof prof(c, "coarse_sep_solve", 2.0 * (double)ns * ns * nr,
+                      8.0 * ((double)ns * ns + 3.0 * ns * nr) + 24.0 * ns);
+            launch(co.cp_M2.p, co.cp_R2.p, co.cp_T2.p, (int)co.cp_T2.n, co.w_cg.p, ns, 1.0, co.w_cw.p, n, scale, yy,
+                   y_rs, nullptr, 0);
+        }
+        {
+            Prof prof(c, "coarse_interior", 2.0 * (double)co.cp_M3.n * nr,
+                      8.0 * ((double)co.cp_M3.n + 2.0 * (double)n * nr) + 24.0 * (n - ns));
+            launch(co.cp_M3.p, co.cp_R3.p, co.cp_T3.p, (int)co.cp_T3.n, co.w_cw.p, n, scale, yy, y_rs, 0.0, nullptr, 0,
+                   nullptr, 0);
+        }
+    }
+}
+
 // y = scale * S̊_PP^-1 z through the three phases of the partitioned solve (1 to 3 load cases)
 void coarse_partitioned(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_rs, double *y, long long y_rs,
                         int nrhs, double scale) {
@@ -1638,6 +1983,10 @@ void coarse_solve(ifeti_ctx *c, CoarseSolver &co, const double *z, long long z_r
     }
     if (nrhs < 4 && co.cp_p >= 2) {
         coarse_partitioned(c, co, z, z_rs, y, y_rs, nrhs, scale);
+        return;
+    }
+    if (co.cp_p >= 2 && !c->no_alloc) {
+        coarse_partitioned_tiles(c, co, z, z_rs, y, y_rs, nrhs, scale);
         return;
     }
     ensure_coarse_inverse(c, co);
@@ -1735,14 +2084,23 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
     GemmGroup g1;  // B_d^T lam fused into the staging
     g1.A = c->Fdd.p; g1.X = lam; g1.xbs = c->L; g1.gcodes = c->g_gather.p; g1.coef = c->delta.p; g1.Kd = nd;
     g1.K = K;
-    // one stream, in order: the coarse branch beside the contraction on a second stream measured
-    // slower on c2 (each cross-stream wait costs about 15 us on the host and leaves a gap of that
-    // order on the GPU, more than the overlap gains)
+    // Up to three load cases everything runs in order on one stream: the coarse branch beside the
+    // contraction on a second stream measured slower on c2 (each cross-stream wait costs about 15 us on
+    // the host and leaves a gap of that order on the GPU, more than the overlap gains).  With a block
+    // of load cases both branches take hundreds of microseconds and the contraction runs on the second
+    // stream beside the coarse branch, after the restriction.
+    const bool side = nrhs >= 4 && !c->no_alloc;
     op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
-    gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+    if (side) {
+        SideStream ss(c);
+        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+    } else {
+        gemm(c, &g1, 1, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+    }
     op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
     op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
     op_prolong_cells(c, c->Wc.p, yP, c->nP, Yc, nrhs, false, "F_prolong");
+    if (side) join_side(c);
     op_scatter(c, Y, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part, Yc);
     c->applies[IFETI_OP_F] += nrhs;
     IFETI_HIP(hipGetLastError());
@@ -1929,6 +2287,57 @@ static void op_mpcg_local(ifeti_ctx *c, const double *vR, long long v_rs, double
     }
 }
 
+// (46b) in one pass when the cell and K allow it (K <= 16, the LDS footprint below 160 KB): the variant
+// (0: 2D, 12 columns a chunk; 1: 2D, 8; 2: 3D, 8) and its LDS bytes, or -1 for the two-kernel form
+static int rom_local_mode(ifeti_ctx *c, size_t *lds_out) {
+    const RefTables &R = c->ref;
+    const int nr = c->n_r, K = c->K, D = c->dim;
+    if (K > 16 || R.p != 2 || (D != 2 && D != 3)) return -1;
+    const int nthr = (R.n_ctrl + 63) / 64 * 64;
+    if (nthr > kRomHB) return -1;
+    auto lds_of = [&](int kcol) {
+        const size_t rows = (size_t)(nr + 1) * (kcol | 1);
+        if ((size_t)(nthr / 64) * 256 > rows) return (size_t)1 << 30;  // the wave partials must fit in H's rows
+        return rows * sizeof(double) + (size_t)(4 * K * K + 2 * K) * sizeof(double) +
+               (size_t)R.n_ctrl * D * sizeof(int);
+    };
+    constexpr size_t kLds = 160 * 1024;
+    // c2: 661 us, against 790 us for the two-kernel form
+    int mode = -1;
+    if (D == 2 && K <= 12 && lds_of(12) <= kLds) mode = 0;
+    else if (D == 2 && lds_of(8) <= kLds) mode = 1;
+    else if (D == 3 && lds_of(8) <= kLds) mode = 2;
+    if (mode >= 0) *lds_out = mode == 0 ? lds_of(12) : lds_of(8);
+    return mode;
+}
+
+// R: [col][n_r][K] in FP64, or in FP32 (the precision form's narrow product)
+template <typename TR>
+static void launch_rom_local(ifeti_ctx *c, int mode, size_t lds, const TR *Rp, const double *vR, long long v_rs,
+                             double *xR, long long x_rs, int cols) {
+    const RefTables &R = c->ref;
+    const int nr = c->n_r, K = c->K, D = c->dim;
+    const int nthr = (R.n_ctrl + 63) / 64 * 64;
+    const int nrhs = cols / c->N;
+    const unsigned grid = nrhs == 1 ? (unsigned)cols : 8u * (unsigned)((c->N + 7) / 8) * (unsigned)nrhs;
+    const double colsd = (double)cols, chunks = mode == 0 ? 1.0 : (double)((K + 7) / 8);
+    // algorithmic: the stencil of the column's cell once per chunk, R, v and x once
+    Prof prof(c, "rom_local", colsd * (2.0 * K * c->nnz_rr + 2.0 * (K + 1.0) * K * nr + 2.0 * K * nr),
+              colsd * (8.0 * chunks * (double)R.n_ctrl * R.n_off * D * D + (double)sizeof(TR) * K * nr + 16.0 * nr));
+#define IFETI_ROM_LOCAL(DD, KC)                                                                                   \
+    do {                                                                                                          \
+        IFETI_HIP(hipFuncSetAttribute((const void *)k_rom_local<TR, DD, KC>,                                \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                     \
+        hipLaunchKernelGGL((k_rom_local<TR, DD, KC>), dim3(grid), dim3(nthr), lds, c->stream, Rp, c->Kst.p,      \
+                           c->r_of_dof.p, vR, v_rs, c->N, nrhs, K, nr, R.nc, R.n_ctrl, xR, x_rs);               \
+    } while (0)
+    if (mode == 0) IFETI_ROM_LOCAL(2, 12);
+    else if (mode == 1) IFETI_ROM_LOCAL(2, 8);
+    else IFETI_ROM_LOCAL(3, 8);
+#undef IFETI_ROM_LOCAL
+    IFETI_HIP(hipGetLastError());
+}
+
 void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, long long x_rs, int nrhs,
                   const double *bank, const char *rtag) {
     const int N = c->N, nr = c->n_r, K = c->K;
@@ -1939,12 +2348,28 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     }
     // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
     // column comes out as [r][k] (or the zero-padded interior inverses of (47))
+    const int cols = N * nrhs;
+    size_t lds = 0;
+    const int mode = rom_local_mode(c, &lds);
+    const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
+    if (mode >= 0 && prec != IFETI_FP64) {
+        // precision form: the narrow product by the library into an FP32 R, read as such by (46b)
+        c->w_R32.ensure((size_t)cols * K * nr, c->stream);
+        if (library_gemm_narrow(c, bank ? bank : c->Kinv.p, K * nr, nr, vR, nr, v_rs, N, nrhs, prec, c->w_R32.p,
+                                rtag)) {
+            launch_rom_local(c, mode, lds, c->w_R32.p, vR, v_rs, xR, x_rs, cols);
+            return;
+        }
+    }
     GemmGroup g;
     g.A = bank ? bank : c->Kinv.p; g.X = vR; g.Kd = nr; g.ldx = nr; g.xbs = v_rs; g.K = 1;
     gemm(c, &g, 1, c->w_R.p, K * nr, 0, K * nr, N * nrhs, false, 0, rtag);
     // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
-    const int cols = N * nrhs;
     const double colsd = (double)cols;
+    if (mode >= 0) {
+        launch_rom_local(c, mode, lds, (const double *)c->w_R.p, vR, v_rs, xR, x_rs, cols);
+        return;
+    }
     launch_rom_H(c, cols);
     {
         Prof prof(c, "rom_gram", colsd * (2.0 * (K + 1.0) * K * nr + 2.0 * K * nr),
@@ -2024,14 +2449,15 @@ static void op_cell_K(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const double colsd = (double)N * nrhs;
     Prof prof(c, "true_K", colsd * 2.0 * c->nnz_full,
               8.0 * (double)N * R.n_ctrl * R.n_off * c->dim * c->dim + colsd * 8.0 * 2.0 * R.n_dof);
+    const unsigned grid = nrhs == 1 ? (unsigned)N : 8u * (unsigned)((N + 7) / 8) * (unsigned)nrhs;
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_true_K<2>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
+        hipLaunchKernelGGL(k_true_K<2>, dim3(grid), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
-                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
+                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p, nrhs);
     else
-        hipLaunchKernelGGL(k_true_K<3>, dim3(N * nrhs), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
+        hipLaunchKernelGGL(k_true_K<3>, dim3(grid), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
-                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p);
+                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p, nrhs);
     }
 }
 

@@ -119,3 +119,33 @@ def test_block_jacobi_coarse_matches_oracle(pair, B):
     finally:
         m.set_coarse_block(0)
         ctx.reset_options()
+
+
+@pytest.mark.parametrize("nrhs", [4, 17, 35])
+def test_partitioned_tiles_for_blocks_of_load_cases(pair, nrhs):
+    """Four or more load cases take the partitioned phases as FP64 MFMA tiles (16 or 32 load cases a
+    pass, more in passes of 32): F̊, Ů and K̊^-ROM of every load case against the oracle, for every block
+    count."""
+    name, parts, m, ctx = pair
+    rng = np.random.default_rng(11 + nrhs)
+    lam = rng.standard_normal((nrhs, m.L))
+    v = rng.standard_normal((nrhs, m.nU))
+    pick = [0, nrhs // 2, nrhs - 1]
+    F_ref = {r: m.apply_F(lam[r]) for r in pick}
+    U_ref = {r: m.apply_U(v[r]) for r in pick}
+    K_ref = {r: m.apply_Kinv_rom(v[r]) for r in pick}
+    for p in parts:
+        if p == 1:
+            continue  # one block: the explicit inverse, not the partitioned phases
+        ctx.set_options(coarse_parts=p)
+        F = host(ctx.apply_F(dev(lam.ravel()), nrhs=nrhs)).reshape(nrhs, m.L)
+        U = host(ctx.apply_U(dev(v.ravel()), nrhs=nrhs)).reshape(nrhs, m.L)
+        K = host(ctx.apply_Kinv_rom(dev(v.ravel()), nrhs=nrhs)).reshape(nrhs, m.nU)
+        for r in pick:
+            e = max(rel(F[r], F_ref[r]), rel(U[r], U_ref[r]), rel(K[r], K_ref[r]))
+            print(f"[gpu coarse] {name} p={p} nrhs={nrhs} load case {r}: {e:.1e}", flush=True)
+            assert e < 1e-11
+        # every load case equals its single apply (the row form) to rounding
+        for r in range(nrhs):
+            assert rel(F[r], host(ctx.apply_F(dev(lam[r])))) < 1e-12
+    ctx.reset_options()
