@@ -353,7 +353,8 @@ def run_c4(args, t_fp64):
     ctx.set_options(precision=ifeti.IFETI_FP32_LOCAL, autotune=1)
     ctx.solve(f, d, nrhs=s.nrhs, tol=args.tol, inner_tol=1e-6, maxit=200)  # tiles tuned here
     torch.cuda.synchronize()
-    ctx.set_options(timing=1, timing_filter="F_gemm,MD_gemm,coarse_gemm,F_restrict", timing_every=4)
+    ctx.set_options(timing=1, timing_filter="F_gemm,MD_gemm,coarse_sep_rhs,coarse_sep_solve,coarse_interior,"
+                    "F_restrict,F_prolong,rom_R_gemm,rom_local", timing_every=4)
     ctx.reset_stats()
     t, info, u = timed_solve(ctx, f, d, s.nrhs, args.tol, 1e-6)
     U, R = u.view(s.nrhs, -1), u_ref.view(s.nrhs, -1)
@@ -365,8 +366,13 @@ def run_c4(args, t_fp64):
            "max_err_vs_fp64": max(errs),
            "roofline_F_gemm_fp32": kernel_roofline(ctx, "F_gemm", PEAK_FP32_MATRIX_TFLOPS),
            "roofline_MD_gemm_fp32": kernel_roofline(ctx, "MD_gemm", PEAK_FP32_MATRIX_TFLOPS),
-           "coarse_gemm_fp64": kernel_roofline(ctx, "coarse_gemm", PEAK_FP64_TFLOPS),
-           "F_restrict": kernel_roofline(ctx, "F_restrict", PEAK_FP64_TFLOPS)}
+           "rom_R_gemm_fp32": kernel_roofline(ctx, "rom_R_gemm", PEAK_FP32_MATRIX_TFLOPS),
+           "rom_local": kernel_roofline(ctx, "rom_local", PEAK_FP64_TFLOPS),
+           # the coarse branch runs beside F_gemm on the other stream: its event times include the waits
+           # for compute units the contraction holds
+           "coarse_branch_beside_F_gemm": {k: kernel_roofline(ctx, k, PEAK_FP64_TFLOPS) for k in
+                                           ("F_restrict", "coarse_sep_rhs", "coarse_sep_solve", "coarse_interior",
+                                            "F_prolong")}}
     log(f"form block_rhs: {t:.3f}s for {s.nrhs} load cases, max err {max(errs):.1e}")
     # the same solve with one block PCG over all load cases inside the preconditioner (O'Leary): the
     # block space spans every load case's Krylov space, the tractions' two directions collapse
