@@ -16,6 +16,23 @@
 namespace ifeti {
 namespace {
 
+// Workgroup b of a cell-batched launch -> (cell s, load case rhs).  Workgroups go to the eight XCDs in
+// turn; with several load cases, b takes cell (b mod 8) + 8 (j / nrhs) and load case j mod nrhs,
+// j = b / 8, so the load cases of a cell run together on one XCD and its L2 serves them the cell's
+// data (the grid is padded to 8 ceil(N/8) cells; false for a padding workgroup, which exits whole).
+// One load case: the identity.
+__device__ __forceinline__ bool cell_of_block(int b, int N, int nrhs, int &s, int &rhs) {
+    if (nrhs <= 1) {
+        s = b;
+        rhs = 0;
+        return true;
+    }
+    const int j = b >> 3;
+    s = (b & 7) + 8 * (j / nrhs);
+    rhs = j % nrhs;
+    return s < N;
+}
+
 constexpr int kB = 256;
 inline unsigned nblocks(long long n, int b = kB) { return (unsigned)((n + b - 1) / b); }
 
@@ -131,8 +148,9 @@ __global__ __launch_bounds__(64 * NWC) void k_restrict_c(const double *__restric
                                                           int n_d, int n_p, int ncols, double *__restrict__ out) {
     __shared__ double part[NWC][NPM];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = blockIdx.x;
-    const int rhs = col / N, s = col % N;
+    int s, rhs;
+    if (!cell_of_block(blockIdx.x, N, ncols / N, s, rhs)) return;  // whole workgroup, before any barrier
+    const int col = rhs * N + s;
     const double *l = lam + rhs * lam_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
     double acc[NPM];
@@ -177,8 +195,9 @@ __global__ __launch_bounds__(64) void k_restrict_c1(const double *__restrict__ C
     static_assert(NPM == 8, "one row per group of 8 lanes");
     __shared__ double part[64][NPM + 1];
     const int lane = threadIdx.x;
-    const int col = blockIdx.x;
-    const int rhs = col / N, s = col % N;
+    int s, rhs;
+    if (!cell_of_block(blockIdx.x, N, ncols / N, s, rhs)) return;  // whole workgroup, before any barrier
+    const int col = rhs * N + s;
     const double *l = lam + rhs * lam_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
     double acc[NPM];
@@ -218,8 +237,9 @@ __global__ __launch_bounds__(64 * NWC) void k_prolong_c(const double *__restrict
                                                          const double *__restrict__ yP, long long yP_rs, int N,
                                                          int n_d, int n_p, int ncols, double *__restrict__ Y,
                                                          int accumulate) {
-    const int col = blockIdx.x;
-    const int rhs = col / N, s = col % N;
+    int s, rhs;
+    if (!cell_of_block(blockIdx.x, N, ncols / N, s, rhs)) return;  // whole workgroup
+    const int col = rhs * N + s;
     const double *zP = yP + rhs * yP_rs;
     const double *Cs = C + (size_t)s * n_p * n_d;
     double *Yc = Y + (size_t)col * n_d;
@@ -880,17 +900,9 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
     constexpr int KP = KCOL | 1;  // odd row stride: lanes reading neighbouring rows hit distinct banks
     static_assert(KCOL <= 15, "column KCOL of the Gram tile carries R^T v");
     extern __shared__ double lds[];
-    // workgroups go to the eight XCDs in turn: with several load cases, workgroup b takes cell
-    // (b mod 8) + 8 (j / nrhs) and load case j mod nrhs, j = b / 8, so the load cases of a cell run
-    // together on one XCD and its L2 serves them the cell's stencil (the grid is padded to 8 ceil(N/8)
-    // cells; one load case: the identity)
-    int s = blockIdx.x, rhs = 0;
-    if (nrhs > 1) {
-        const int j = blockIdx.x >> 3;
-        s = (blockIdx.x & 7) + 8 * (j / nrhs);
-        rhs = j % nrhs;
-        if (s >= N) return;  // padding: the whole workgroup, before any barrier
-    }
+    // the load cases of a cell together on one XCD, whose L2 serves them the cell's stencil
+    int s, rhs;
+    if (!cell_of_block(blockIdx.x, N, nrhs, s, rhs)) return;  // whole workgroup, before any barrier
     const int col = rhs * N + s, tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -1246,15 +1258,9 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
                                                double *__restrict__ y, long long y_rs,
                                                double *__restrict__ yp_cells, int nrhs) {
     extern __shared__ double uloc[];
-    // several load cases: the load cases of a cell together on one XCD (its L2 then serves the cell's
-    // stencil to all of them), as in the fused reduced local solve
-    int s = blockIdx.x, rhs = 0;
-    if (nrhs > 1) {
-        const int j = blockIdx.x >> 3;
-        s = (blockIdx.x & 7) + 8 * (j / nrhs);
-        rhs = j % nrhs;
-        if (s >= N) return;  // padding: the whole workgroup, before any barrier
-    }
+    // the load cases of a cell together on one XCD, whose L2 serves them the cell's stencil
+    int s, rhs;
+    if (!cell_of_block(blockIdx.x, N, nrhs, s, rhs)) return;  // whole workgroup, before any barrier
     const int col = rhs * N + s;
     const int tid = threadIdx.x;
     const int n_dof = n_ctrl * D;
@@ -1757,6 +1763,11 @@ __global__ __launch_bounds__(kB) void k_scale_copy(const double *__restrict__ x,
 }  // namespace
 
 // ================================================================== host wrappers
+// grid of a cell-batched launch whose workgroups map to cells through cell_of_block
+static unsigned cell_grid(int N, int nrhs) {
+    return nrhs <= 1 ? (unsigned)N : 8u * (unsigned)((N + 7) / 8) * (unsigned)nrhs;
+}
+
 // Work enqueued inside a SideStream scope goes to the context's second stream
 // (default priority); it starts after everything queued so far on the main
 // stream, and join_side() makes the main stream wait for it.
@@ -2049,12 +2060,12 @@ void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long lo
     if (np <= 8)
         // 2D: one wave per cell; its partial sums are reduced through LDS rather than by eight
         // butterflies, which compete for the LDS pipe with the contraction running beside it
-        hipLaunchKernelGGL((k_restrict_c1<8>), dim3(cols), dim3(64), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
+        hipLaunchKernelGGL((k_restrict_c1<8>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
                            N, nd, np, cols, out);
     else
         // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
         // coarse branch from crowding it
-        hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, C, c->g_gather.p, lam,
+        hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_gather.p, lam,
                            lam_rs, N, nd, np, cols, out);
     IFETI_HIP(hipGetLastError());
 }
@@ -2065,10 +2076,10 @@ void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long
     const int N = c->N, nd = c->n_d, np = c->n_p, cols = N * nrhs;
     Prof prof(c, tag, 2.0 * (double)cols * np * nd, 8.0 * (double)N * np * nd + 8.0 * (double)cols * nd);
     if (np <= 8)
-        hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cols), dim3(128), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N, nd,
+        hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cell_grid(N, nrhs)), dim3(128), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N, nd,
                            np, cols, Y, accumulate ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cols), dim3(64), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N,
+        hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N,
                            nd, np, cols, Y, accumulate ? 1 : 0);
     IFETI_HIP(hipGetLastError());
 }
@@ -2319,7 +2330,7 @@ static void launch_rom_local(ifeti_ctx *c, int mode, size_t lds, const TR *Rp, c
     const int nr = c->n_r, K = c->K, D = c->dim;
     const int nthr = (R.n_ctrl + 63) / 64 * 64;
     const int nrhs = cols / c->N;
-    const unsigned grid = nrhs == 1 ? (unsigned)cols : 8u * (unsigned)((c->N + 7) / 8) * (unsigned)nrhs;
+    const unsigned grid = cell_grid(c->N, nrhs);
     const double colsd = (double)cols, chunks = mode == 0 ? 1.0 : (double)((K + 7) / 8);
     // algorithmic: the stencil of the column's cell once per chunk, R, v and x once
     Prof prof(c, "rom_local", colsd * (2.0 * K * c->nnz_rr + 2.0 * (K + 1.0) * K * nr + 2.0 * K * nr),
@@ -2449,7 +2460,7 @@ static void op_cell_K(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const double colsd = (double)N * nrhs;
     Prof prof(c, "true_K", colsd * 2.0 * c->nnz_full,
               8.0 * (double)N * R.n_ctrl * R.n_off * c->dim * c->dim + colsd * 8.0 * 2.0 * R.n_dof);
-    const unsigned grid = nrhs == 1 ? (unsigned)N : 8u * (unsigned)((N + 7) / 8) * (unsigned)nrhs;
+    const unsigned grid = cell_grid(N, nrhs);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_true_K<2>, dim3(grid), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
                            c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
