@@ -660,7 +660,9 @@ def main():
     forms = None
     if not args.no_forms:
         u_ref, _ = reference_solution(ctx, f, d)
+        err_headline = rel_err(u, u_ref)  # the last timed solve against the parity-tolerance solve
         forms = run_forms(ctx, f, d, elapsed / args.steps, args, u_ref)
+        forms["fp64_plain"]["err_vs_fp64"] = err_headline
         if not args.no_exact:
             forms["exact_fetidp"] = run_exact(ctx, f, d, elapsed / args.steps, args)
     lat = "2D 64x64-cell lattice, 648 dof/cell" if prob.dim == 2 else f"3D {'x'.join(map(str, prob.shape))}-cell lattice, {s.n_dof} dof/cell"

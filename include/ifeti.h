@@ -285,8 +285,9 @@ int ifeti_solve(ifeti_ctx *ctx, const double *f, const double *d, double *u, dou
 /* Differentiation form.  Compliance c = f^T u and its gradient with respect
  * to every cell's strut width, dc/dw_s = -u_s^T (dK^(s)/dw_s) u_s (the system
  * (16) is self-adjoint and f does not depend on the widths), evaluated by
- * quadrature of the width derivative of eq. (52).  Meaningful with a smoothed
- * strut indicator (smooth_eps > 0); zero for the sharp one.
+ * quadrature of the width derivative of eq. (52).  Needs a smoothed strut
+ * indicator (smooth_eps > 0): with the sharp one the derivative vanishes almost
+ * everywhere and the call returns IFETI_EINVAL.
  *   f, u        dev nU x nrhs (u: a converged solution of ifeti_solve)
  *   grad        dev N x nrhs (rhs-major)
  *   compliance  host nrhs, nullable. */
