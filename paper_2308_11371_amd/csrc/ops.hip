@@ -907,8 +907,11 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const size_t rows = (size_t)(n_r + 1) * KP;
-    double *Rl = lds;                             // [n_r + 1][KP] a chunk of R, row n_r zero
-    double *Hl = lds;                             // then H of the chunk, then the wave partials
+    // [n_r + 1][KP] a chunk of R in R's own precision (FP32 in the precision form: half the LDS reads of
+    // the stencil loop), row n_r zero; then H of the chunk in FP64 over the same bytes, then the wave
+    // partials
+    TR *Rl = reinterpret_cast<TR *>(lds);
+    double *Hl = lds;
     double *G = Hl + rows;                        // [K][K], then a copy of it, Lm, V [K][K], g [K], c [K]
     double *G0 = G + K * K, *Lm = G0 + K * K, *Vm = Lm + K * K, *gb = Vm + K * K, *cv = gb + K;
     int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or the zero row n_r
@@ -926,11 +929,11 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
         // below unrolled the same way ran out of registers and slowed to 774 us)
         constexpr int SU = 4;
         for (int e0 = tid; e0 < tot; e0 += SU * nt) {
-            double tmp[SU];
+            TR tmp[SU];
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 const int e = e0 + u * nt, r = e / KCOL, kk = e % KCOL;
-                tmp[u] = (e < tot && kk < kc && r < n_r) ? (double)Rc[(size_t)r * K + k0 + kk] : 0.0;
+                tmp[u] = (e < tot && kk < kc && r < n_r) ? Rc[(size_t)r * K + k0 + kk] : (TR)0;
             }
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
@@ -975,13 +978,13 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
                 if (!ok) b = a;  // stencil value stored as zero for this offset
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const double *row = Rl + rmap[b * D + k] * KP;
+                    const TR *row = Rl + rmap[b * D + k] * KP;
                     double kv[D];
 #pragma unroll
                     for (int i = 0; i < D; ++i) kv[i] = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
 #pragma unroll
                     for (int q = 0; q < KCOL; ++q) {
-                        const double rq = row[q];
+                        const double rq = (double)row[q];
 #pragma unroll
                         for (int i = 0; i < D; ++i) h[i][q] += kv[i] * rq;
                     }
