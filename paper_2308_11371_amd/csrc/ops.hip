@@ -912,8 +912,8 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
     // partials
     TR *Rl = reinterpret_cast<TR *>(lds);
     double *Hl = lds;
-    double *G = Hl + rows;                        // [K][K], then a copy of it, Lm, V [K][K], g [K], c [K]
-    double *G0 = G + K * K, *Lm = G0 + K * K, *Vm = Lm + K * K, *gb = Vm + K * K, *cv = gb + K;
+    double *G = Hl + rows;  // [K][K], a copy of it, two [K][K+1] work arrays, g [K], c [K]
+    double *G0 = G + K * K, *W1 = G0 + K * K, *W2 = W1 + K * (K + 1), *gb = W2 + K * (K + 1), *cv = gb + K;
     int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or the zero row n_r
     const TR *Rc = R + (size_t)col * K * n_r;
     const double *v = vR + (size_t)rhs * v_rs + (size_t)s * n_r;
@@ -1033,47 +1033,40 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
         G0[e] = G[e] = j < i ? G[j * K + i] : G[e];
     }
     __syncthreads();
-    // G c = g by a Cholesky factorisation spread over the block (one barrier per step; the one-lane
-    // form would leave the CU idle for tens of microseconds per column); a pivot that is not positive
-    // hands the copy to the one-lane solve with its eigen-decomposition fallback
+    // G c = g by Gauss-Jordan elimination of [G | g] spread over the block, one thread per entry and
+    // one barrier per pivot (the pivots of a symmetric positive definite matrix need no exchange; a
+    // Cholesky factorisation with its two substitutions took four times the barriers, a one-lane solve
+    // leaves the CU idle for tens of microseconds per column).  A pivot that is not positive hands the
+    // copy to the one-lane solve with its eigen-decomposition fallback.
+    const int K1 = K + 1;
+    for (int e = tid; e < K * K1; e += nt) {
+        const int i = e / K1, m = e % K1;
+        W1[e] = m < K ? G[i * K + m] : gb[i];
+    }
+    __syncthreads();
     bool spd = true;
-    for (int j = 0; j < K && spd; ++j) {
-        const double d = G[j * K + j];  // the same value in every thread: a uniform branch
-        if (!(d > 0.0)) {
+    double *src = W1, *dst = W2;
+    for (int j = 0; j < K; ++j) {
+        const double piv = src[j * K1 + j];  // the same value in every thread: a uniform branch
+        if (!(piv > 0.0)) {
             spd = false;
             break;
         }
-        const double l = sqrt(d);
-        if (tid > j && tid < K) G[tid * K + j] /= l;
-        __syncthreads();
-        if (tid == 0) G[j * K + j] = l;
-        for (int e = tid; e < K * K; e += nt) {
-            const int i = e / K, m = e % K;
-            if (m > j && m <= i) G[e] -= G[i * K + j] * G[m * K + j];
+        for (int e = tid; e < K * K1; e += nt) {
+            const int i = e / K1, m = e % K1;
+            dst[e] = i == j ? src[e] / piv : src[e] - src[i * K1 + j] * (src[j * K1 + m] / piv);
         }
         __syncthreads();
+        double *t = src;
+        src = dst;
+        dst = t;
     }
     if (spd) {
-        if (tid < K) cv[tid] = gb[tid];
-        __syncthreads();
-        for (int j = 0; j < K; ++j) {  // L y = g, column by column
-            const double yj = cv[j] / G[j * K + j];
-            __syncthreads();
-            if (tid > j && tid < K) cv[tid] -= G[tid * K + j] * yj;
-            if (tid == j) cv[j] = yj;
-            __syncthreads();
-        }
-        for (int j = K - 1; j >= 0; --j) {  // L^T c = y
-            const double cj = cv[j] / G[j * K + j];
-            __syncthreads();
-            if (tid < j) cv[tid] -= G[j * K + tid] * cj;
-            if (tid == j) cv[j] = cj;
-            __syncthreads();
-        }
-    } else {
-        if (tid == 0) small_sym_solve(G0, Lm, Vm, gb, cv, K);
-        __syncthreads();
+        if (tid < K) cv[tid] = src[tid * K1 + K];
+    } else if (tid == 0) {
+        small_sym_solve(G0, W1, W2, gb, cv, K);  // W1, W2: K x K workspaces of the fallback
     }
+    __syncthreads();
     double *x = xR + (size_t)rhs * x_rs + (size_t)s * n_r;
     for (int r = tid; r < n_r; r += nt) {
         double t = 0.0;
@@ -2312,7 +2305,7 @@ static int rom_local_mode(ifeti_ctx *c, size_t *lds_out) {
     auto lds_of = [&](int kcol) {
         const size_t rows = (size_t)(nr + 1) * (kcol | 1);
         if ((size_t)(nthr / 64) * 256 > rows) return (size_t)1 << 30;  // the wave partials must fit in H's rows
-        return rows * sizeof(double) + (size_t)(4 * K * K + 2 * K) * sizeof(double) +
+        return rows * sizeof(double) + (size_t)(4 * K * K + 4 * K) * sizeof(double) +
                (size_t)R.n_ctrl * D * sizeof(int);
     };
     constexpr size_t kLds = 160 * 1024;
