@@ -229,6 +229,92 @@ __global__ __launch_bounds__(64) void k_restrict_c1(const double *__restrict__ C
     if (g == 0 && i < n_p) out[(size_t)col * n_p + i] = v;
 }
 
+// The same restriction for a block of load cases, one workgroup of four waves per cell: each wave
+// loads the cell's C_s and jump codes once (two dual rows per lane, n_d <= 128) and takes every fourth
+// load case, so C_s is read once per cell instead of once per load case.  Per load case the eight
+// partial sums are reduced as in k_restrict_c1 (LDS, then three butterflies).
+template <int NPM>
+__global__ __launch_bounds__(256) void k_restrict_cm(const double *__restrict__ C, const int *__restrict__ gl,
+                                                     const double *__restrict__ lam, long long lam_rs, int N, int n_d,
+                                                     int n_p, int nrhs, double *__restrict__ out) {
+    static_assert(NPM == 8, "one row per group of 8 lanes");
+    __shared__ double part[4][64][NPM + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int s = blockIdx.x;
+    const double *Cs = C + (size_t)s * n_p * n_d;
+    double cv[2][NPM];
+    int code[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = lane + 64 * h;
+        const bool in = j < n_d;
+#pragma unroll
+        for (int i = 0; i < NPM; ++i) cv[h][i] = (in && i < n_p) ? Cs[(size_t)i * n_d + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) code[h][u] = in ? gl[((size_t)s * n_d + j) * 2 + u] : 0;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {  // the same trip count in every wave: barriers below
+        const int rhs = r0 + wave;
+        const bool act = rhs < nrhs;
+        const double *l = lam + (act ? rhs : 0) * lam_rs;
+        double acc[NPM];
+#pragma unroll
+        for (int i = 0; i < NPM; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int cd = act ? code[h][u] : 0;
+                if (cd == 0) continue;
+                const double x = l[(cd > 0 ? cd : -cd) - 1];
+                v += cd > 0 ? x : -x;
+            }
+#pragma unroll
+            for (int i = 0; i < NPM; ++i) acc[i] += cv[h][i] * v;
+        }
+#pragma unroll
+        for (int i = 0; i < NPM; ++i) part[wave][lane][i] = acc[i];
+        __syncthreads();
+        const int i = lane >> 3, g = lane & 7;
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v += part[wave][8 * g + t][i];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (act && g == 0 && i < n_p) out[((size_t)rhs * N + s) * n_p + i] = v;
+        __syncthreads();  // the partials are read before the next load cases overwrite them
+    }
+}
+
+// Y_s (+)= C_s^T y_P[A_p(s)] for a block of load cases: one workgroup of n_d threads (n_d <= 256) per
+// cell, each thread's column of C_s loaded once and used for every load case
+template <int NPM>
+__global__ __launch_bounds__(256) void k_prolong_cm(const double *__restrict__ C, const int *__restrict__ Ap,
+                                                    const double *__restrict__ yP, long long yP_rs, int N, int n_d,
+                                                    int n_p, int nrhs, double *__restrict__ Y, int accumulate) {
+    const int s = blockIdx.x, j = threadIdx.x;
+    const bool in = j < n_d;
+    const double *Cs = C + (size_t)s * n_p * n_d;
+    double cv[NPM];
+    int P[NPM];
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) {
+        cv[i] = (in && i < n_p) ? Cs[(size_t)i * n_d + j] : 0.0;
+        P[i] = i < n_p ? Ap[(size_t)s * n_p + i] : -1;
+    }
+    for (int rhs = 0; rhs < nrhs; ++rhs) {
+        const double *zP = yP + rhs * yP_rs;
+        double *Yc = Y + ((size_t)rhs * N + s) * n_d;
+        double v = (in && accumulate) ? Yc[j] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NPM; ++i)
+            if (P[i] >= 0) v += cv[i] * zP[P[i]];
+        if (in) Yc[j] = v;
+    }
+}
+
 // Y_s (+)= C_s^T y_P[A_p(s)] for column (rhs, s): one workgroup of NWC waves per
 // column, lanes over the cell's dual rows (coalesced rows of C_s); the n_p
 // primal values of the cell are uniform.
@@ -2053,7 +2139,11 @@ void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long lo
     const int N = c->N, nd = c->n_d, np = c->n_p, cols = N * nrhs;
     Prof prof(c, tag, 2.0 * (double)cols * np * nd,
               8.0 * (double)N * np * nd + 8.0 * ((double)c->L * nrhs + (double)cols * np) + 8.0 * (double)N * nd);
-    if (np <= 8)
+    if (np <= 8 && nd <= 128 && nrhs >= 4)
+        // a block of load cases: C_s and the codes read once per cell
+        hipLaunchKernelGGL((k_restrict_cm<8>), dim3(N), dim3(256), 0, c->stream, C, c->g_gather.p, lam, lam_rs, N, nd,
+                           np, nrhs, out);
+    else if (np <= 8)
         // 2D: one wave per cell; its partial sums are reduced through LDS rather than by eight
         // butterflies, which compete for the LDS pipe with the contraction running beside it
         hipLaunchKernelGGL((k_restrict_c1<8>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
@@ -2071,7 +2161,10 @@ void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long
                       bool accumulate, const char *tag) {
     const int N = c->N, nd = c->n_d, np = c->n_p, cols = N * nrhs;
     Prof prof(c, tag, 2.0 * (double)cols * np * nd, 8.0 * (double)N * np * nd + 8.0 * (double)cols * nd);
-    if (np <= 8)
+    if (np <= 8 && nd <= 256 && nrhs >= 4)
+        hipLaunchKernelGGL((k_prolong_cm<8>), dim3(N), dim3((nd + 63) / 64 * 64), 0, c->stream, C, c->g_Ap.p, yP, yP_rs,
+                           N, nd, np, nrhs, Y, accumulate ? 1 : 0);
+    else if (np <= 8)
         hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cell_grid(N, nrhs)), dim3(128), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N, nd,
                            np, cols, Y, accumulate ? 1 : 0);
     else
