@@ -1113,6 +1113,108 @@ void release_blas(void *handle) {
     if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
+// Principal-weighted products with one small side (M <= 16 rows, or Kd <= 16 inputs: the restrictions
+// and prolongations between the r block and the primal corners) for a block of load cases: one
+// workgroup per cell forms the cell's combined operator sum_k coef_k A_k once and applies it to every
+// load case, instead of K products per column on 16-row MFMA tiles of which the small side fills half.
+// Rows: the combined M x Kd operator in LDS, one wave per load case, lanes over the Kd inputs and a
+// wave reduction per row.  Columns: each thread keeps its rows' Kd combined entries in registers.
+template <int MMAX>
+__global__ __launch_bounds__(256) void k_small_rows(const double *__restrict__ A, const double *__restrict__ coef, int K,
+                                                    int M, int Kd, const double *__restrict__ X, int ldx, long long xbs,
+                                                    int ncells, int nrhs, double scale, double *__restrict__ Y, int ldy,
+                                                    long long ybs, int accumulate) {
+    extern __shared__ double Cl[];  // [M][Kd]
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t mk = (size_t)M * Kd;
+    for (size_t e = tid; e < mk; e += 256) {
+        double v = 0.0;
+        for (int k = 0; k < K; ++k) v += coef[(size_t)s * K + k] * A[(size_t)k * mk + e];
+        Cl[e] = v;
+    }
+    __syncthreads();
+    for (int rhs = wave; rhs < nrhs; rhs += 4) {  // no barrier below: any trip count per wave
+        const double *x = X + rhs * xbs + (size_t)s * ldx;
+        double acc[MMAX];
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) acc[m] = 0.0;
+        for (int j = lane; j < Kd; j += 64) {
+            const double xv = x[j];
+#pragma unroll
+            for (int m = 0; m < MMAX; ++m)
+                if (m < M) acc[m] += Cl[(size_t)m * Kd + j] * xv;
+        }
+        double *y = Y + rhs * ybs + (size_t)s * ldy;
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) {
+            double v = acc[m];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0 && m < M) y[m] = accumulate ? y[m] + scale * v : scale * v;
+        }
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_small_cols(const double *__restrict__ A, const double *__restrict__ coef, int K,
+                                                    int M, int Kd, const double *__restrict__ X, int ldx, long long xbs,
+                                                    int ncells, int nrhs, double scale, double *__restrict__ Y, int ldy,
+                                                    long long ybs, int accumulate) {
+    const int s = blockIdx.x;
+    const size_t mk = (size_t)M * Kd;
+    for (int m = threadIdx.x; m < M; m += 256) {
+        double cr[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) cr[j] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double ck = coef[(size_t)s * K + k];
+            const double *a = A + (size_t)k * mk + (size_t)m * Kd;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < Kd) cr[j] += ck * a[j];
+        }
+        for (int rhs = 0; rhs < nrhs; ++rhs) {
+            const double *x = X + rhs * xbs + (size_t)s * ldx;
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < Kd) v += cr[j] * x[j];
+            double *y = Y + rhs * ybs + (size_t)s * ldy + m;
+            *y = accumulate ? *y + scale * v : scale * v;
+        }
+    }
+}
+
+static bool small_side_gemm(ifeti_ctx *c, const GemmGroup &g, double *Y, int ldy, long long ybs, int M, int ncols,
+                            int ncells, bool accumulate, const char *tag) {
+    if (!g.coef || g.gcodes || g.gw || ncols % ncells != 0 || ncols / ncells < 4 || c->opt.tile_candidate >= 0)
+        return false;
+    const int nrhs = ncols / ncells;
+    const long long xbs = g.xbs ? g.xbs : (long long)ncells * g.ldx;
+    const long long ys = ybs ? ybs : (long long)ncells * ldy;
+    const double cols = (double)ncols;
+    if (M <= 8 && (size_t)M * g.Kd * sizeof(double) <= 64 * 1024) {
+        const size_t lds = (size_t)M * g.Kd * sizeof(double);
+        Prof prof(c, tag, 2.0 * M * cols * g.Kd + 2.0 * g.K * M * (double)g.Kd * ncells,
+                  8.0 * ((double)g.K * M * g.Kd + cols * g.Kd + cols * M * (accumulate ? 2 : 1)));
+        IFETI_HIP(hipFuncSetAttribute((const void *)k_small_rows<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+        hipLaunchKernelGGL(k_small_rows<8>, dim3(ncells), dim3(256), lds, c->stream, g.A, g.coef, g.K, M, g.Kd, g.X,
+                           g.ldx, xbs, ncells, nrhs, g.scale, Y, ldy, ys, accumulate ? 1 : 0);
+        IFETI_HIP(hipGetLastError());
+        return true;
+    }
+    if (g.Kd <= 8) {
+        Prof prof(c, tag, 2.0 * M * cols * g.Kd + 2.0 * g.K * M * (double)g.Kd * ncells,
+                  8.0 * ((double)g.K * M * g.Kd + cols * g.Kd + cols * M * (accumulate ? 2 : 1)));
+        hipLaunchKernelGGL(k_small_cols<8>, dim3(ncells), dim3(256), 0, c->stream, g.A, g.coef, g.K, M, g.Kd, g.X,
+                           g.ldx, xbs, ncells, nrhs, g.scale, Y, ldy, ys, accumulate ? 1 : 0);
+        IFETI_HIP(hipGetLastError());
+        return true;
+    }
+    return false;
+}
+
 // A plain product (one operator, no principal coefficients, no fused gather) with many rows in FP64:
 // the stacked principal inverses of (46a) applied to every cell vector.  rocBLAS's DGEMM runs it at
 // 0.87 of the FP64 matrix peak on the c2 shape (7680 x 640 times 640 x 4096), against 0.51 for the
@@ -1271,6 +1373,9 @@ void gemm(ifeti_ctx *c, const GemmGroup *groups, int ngroups, double *Y, int ldy
     const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
     const bool lp_path = lp_ok && prec != IFETI_FP64 && M > 16 && Kdmax > 16;
     if (!lp_path && ngroups == 1 && library_gemm(c, groups[0], Y, ldy, a.ybs, M, ncols, a.ncells, accumulate, tag))
+        return;
+    if (!lp_path && ngroups == 1 &&
+        small_side_gemm(c, groups[0], Y, ldy, a.ybs, M, ncols, a.ncells, accumulate, tag))
         return;
     const bool frag_small = abytes <= 4.0 * 1024 * 1024;  // operators that stay resident in L2
     const bool frag_big = !frag_small && M >= 512;         // many row tiles: waves own rows
