@@ -1330,7 +1330,7 @@ __global__ __launch_bounds__(64 * WPB) void k_mpcg_conj(double *__restrict__ Z, 
 
 // ------------------------------------------------------------------ true cell operator (16)
 // y_R = K_rr u_r + K_rp u_p + B_r^T lam ;  yp (per cell) = K_pr u_r + K_pp u_p
-template <int D>
+template <int D, int NRB>
 __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, const double *__restrict__ x,
                                                long long x_rs, long long nU, const int *__restrict__ Ap,
                                                const int *__restrict__ idx_r, const int *__restrict__ idx_p,
@@ -1339,24 +1339,27 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
                                                int n_d, int nc, int n_ctrl, int n_off, int p,
                                                double *__restrict__ y, long long y_rs,
                                                double *__restrict__ yp_cells, int nrhs) {
-    extern __shared__ double uloc[];
-    // the load cases of a cell together on one XCD, whose L2 serves them the cell's stencil
-    int s, rhs;
-    if (!cell_of_block(blockIdx.x, N, nrhs, s, rhs)) return;  // whole workgroup, before any barrier
-    const int col = rhs * N + s;
+    extern __shared__ double uloc[];  // [NRB][n_dof]
+    // NRB load cases per workgroup share every stencil value they read; the groups of a cell run
+    // together on one XCD, whose L2 serves them the cell's stencil
+    const int ngroups = (nrhs + NRB - 1) / NRB;
+    int s, grp;
+    if (!cell_of_block(blockIdx.x, N, ngroups, s, grp)) return;  // whole workgroup, before any barrier
+    const int r0 = grp * NRB, nq = min(NRB, nrhs - r0);
     const int tid = threadIdx.x;
     const int n_dof = n_ctrl * D;
-    const double *u = x + rhs * x_rs;
-    const double *lam = u + nU;
-    for (int i = tid; i < n_r; i += kB) uloc[idx_r[i]] = u[(size_t)s * n_r + i];
-    for (int j = tid; j < n_p; j += kB) {
-        int P = Ap[(size_t)s * n_p + j];
-        uloc[idx_p[j]] = P >= 0 ? u[(size_t)N * n_r + P] : 0.0;
+    for (int q = 0; q < nq; ++q) {
+        const double *u = x + (r0 + q) * x_rs;
+        double *ul = uloc + (size_t)q * n_dof;
+        for (int i = tid; i < n_r; i += kB) ul[idx_r[i]] = u[(size_t)s * n_r + i];
+        for (int j = tid; j < n_p; j += kB) {
+            int P = Ap[(size_t)s * n_p + j];
+            ul[idx_p[j]] = P >= 0 ? u[(size_t)N * n_r + P] : 0.0;
+        }
     }
     __syncthreads();
     const int w = 2 * p + 1;
     const double *Ks = Kst + (size_t)s * n_ctrl * n_off * D * D;
-    double *yr = y + rhs * y_rs + (size_t)s * n_r;
     for (int t = tid; t < n_dof; t += kB) {
         const int i = t / n_ctrl, a = t % n_ctrl;
         const int row = a * D + i;
@@ -1366,7 +1369,9 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
             ma[j] = ta % nc;
             ta /= nc;
         }
-        double acc = 0.0;
+        double acc[NRB];
+#pragma unroll
+        for (int q = 0; q < NRB; ++q) acc[q] = 0.0;
         for (int o = 0; o < n_off; ++o) {
             int to = o, b = 0;
             bool ok = true;
@@ -1379,23 +1384,33 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
             if (!ok) continue;
             for (int j = D - 1; j >= 0; --j) b = b * nc + mb[j];
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc += Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a] * uloc[b * D + k];
-        }
-        int rp = r_of_dof[row];
-        if (rp >= 0) {
-            if (rp >= n_i) {  // dual dof: add B_d^T lam
-                int j = rp - n_i;
+            for (int k = 0; k < D; ++k) {
+                const double kv = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
 #pragma unroll
-                for (int t2 = 0; t2 < 2; ++t2) {
-                    int code = gl[((size_t)s * n_d + j) * 2 + t2];
-                    if (code == 0) continue;
-                    double lv = lam[(code > 0 ? code : -code) - 1];
-                    acc += code > 0 ? lv : -lv;
-                }
+                for (int q = 0; q < NRB; ++q)
+                    if (q < nq) acc[q] += kv * uloc[(size_t)q * n_dof + b * D + k];
             }
-            yr[rp] = acc;
-        } else {
-            yp_cells[(size_t)col * n_p + p_of_dof[row]] = acc;
+        }
+        const int rp = r_of_dof[row];
+        for (int q = 0; q < nq; ++q) {
+            const int rhs = r0 + q, col = rhs * N + s;
+            double v = acc[q];
+            if (rp >= 0) {
+                if (rp >= n_i) {  // dual dof: add B_d^T lam
+                    const double *lam = x + rhs * x_rs + nU;
+                    int j = rp - n_i;
+#pragma unroll
+                    for (int t2 = 0; t2 < 2; ++t2) {
+                        int code = gl[((size_t)s * n_d + j) * 2 + t2];
+                        if (code == 0) continue;
+                        double lv = lam[(code > 0 ? code : -code) - 1];
+                        v += code > 0 ? lv : -lv;
+                    }
+                }
+                y[rhs * y_rs + (size_t)s * n_r + rp] = v;
+            } else {
+                yp_cells[(size_t)col * n_p + p_of_dof[row]] = v;
+            }
         }
     }
 }
@@ -2549,15 +2564,22 @@ static void op_cell_K(ifeti_ctx *c, const double *x, double *y, int nrhs) {
     const double colsd = (double)N * nrhs;
     Prof prof(c, "true_K", colsd * 2.0 * c->nnz_full,
               8.0 * (double)N * R.n_ctrl * R.n_off * c->dim * c->dim + colsd * 8.0 * 2.0 * R.n_dof);
-    const unsigned grid = cell_grid(N, nrhs);
-    if (c->dim == 2)
-        hipLaunchKernelGGL(k_true_K<2>, dim3(grid), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
-                           c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
-                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p, nrhs);
-    else
-        hipLaunchKernelGGL(k_true_K<3>, dim3(grid), dim3(kB), shmem, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,
-                           c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np,
-                           c->n_i, c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p, nrhs);
+    // four load cases a workgroup for a block of them (each stencil value read once for the four)
+    const int nrb = nrhs >= 4 ? 4 : 1;
+    const unsigned grid = cell_grid(N, (nrhs + nrb - 1) / nrb);
+    const size_t shm = shmem * nrb;
+#define IFETI_TRUE_K(DD, NB)                                                                                      \
+    hipLaunchKernelGGL((k_true_K<DD, NB>), dim3(grid), dim3(kB), shm, c->stream, c->Kst.p, x, rs, nU, c->g_Ap.p,   \
+                       c->g_idx_r.p, c->g_idx_p.p, c->r_of_dof.p, c->p_of_dof.p, c->g_gather.p, N, nr, np, c->n_i, \
+                       c->n_d, R.nc, R.n_ctrl, R.n_off, R.p, y, rs, c->w_c.p, nrhs)
+    if (c->dim == 2) {
+        if (nrb == 4) IFETI_TRUE_K(2, 4);
+        else IFETI_TRUE_K(2, 1);
+    } else {
+        if (nrb == 4) IFETI_TRUE_K(3, 4);
+        else IFETI_TRUE_K(3, 1);
+    }
+#undef IFETI_TRUE_K
     }
 }
 

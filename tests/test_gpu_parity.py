@@ -309,13 +309,15 @@ def test_block_rhs_equals_single_solves():
 
 
 def test_five_rhs_match_single(pair):
-    """Five load cases at once take the block coarse solve (a split-K contraction with the dense
-    inverse) instead of the symmetric tile pass; each load case matches its single apply."""
+    """Five load cases at once take the block forms (coarse tiles, per-cell combined small-side
+    products, the restriction/prolongation and the true operator over load-case groups); each load case
+    matches its single apply."""
     name, prob, m, ctx = pair
     L, nU = m.L, m.nU
     X = np.stack([_rand(L, 80 + r) for r in range(5)])
     V = np.stack([_rand(nU, 90 + r) for r in range(5)])
-    for op, Z, n in (("F", X, L), ("Ut", X, nU), ("U", V, L), ("Kinv_rom", V, nU)):
+    S = np.stack([_rand(nU + L, 100 + r) for r in range(5)])
+    for op, Z, n in (("F", X, L), ("Ut", X, nU), ("U", V, L), ("Kinv_rom", V, nU), ("A", S, nU + L)):
         Y = host(getattr(ctx, "apply_" + op)(dev(Z.ravel()), nrhs=5)).reshape(5, n)
         for r in range(5):
             y1 = host(getattr(ctx, "apply_" + op)(dev(Z[r])))
