@@ -99,7 +99,8 @@ typedef struct {
     int fgmres_restart;     /* maximum Krylov dimension of the outer solver */
     int pcg_maxit;          /* iteration cap of the interface PCG inside the preconditioner */
     int timing;             /* 1: time kernel launches with HIP events       */
-    char timing_filter[32]; /* "" : every kernel family; else a comma-separated list of families */
+    char timing_filter[256]; /* "" : every kernel family; else a comma-separated list of families
+                                (NUL-terminated; longer lists are the caller's error) */
     int timing_every;       /* time one launch in this many of each family (<= 1: every launch) */
     int use_graph;          /* 1: the interface PCG runs its first iteration eagerly, captures the
                                second in a HIP graph (both streams) and replays it for the rest;

@@ -1388,7 +1388,7 @@ __global__ __launch_bounds__(kB) void k_true_K(const double *__restrict__ Kst, c
                 const double kv = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
 #pragma unroll
                 for (int q = 0; q < NRB; ++q)
-                    if (q < nq) acc[q] += kv * uloc[(size_t)q * n_dof + b * D + k];
+                    if (NRB == 1 || q < nq) acc[q] += kv * uloc[(size_t)q * n_dof + b * D + k];
             }
         }
         const int rp = r_of_dof[row];
@@ -2163,9 +2163,13 @@ void op_restrict_cells(ifeti_ctx *c, const double *C, const double *lam, long lo
         // butterflies, which compete for the LDS pipe with the contraction running beside it
         hipLaunchKernelGGL((k_restrict_c1<8>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_gather.p, lam, lam_rs,
                            N, nd, np, cols, out);
+    else if (nrhs < 4)
+        // 3D, in order on one stream: four waves per cell keep the 166 KB of C_s per cell streaming
+        hipLaunchKernelGGL((k_restrict_c<kMaxNp, 4>), dim3(cell_grid(N, nrhs)), dim3(256), 0, c->stream, C, c->g_gather.p,
+                           lam, lam_rs, N, nd, np, cols, out);
     else
-        // 3D: the contraction on the side stream is the critical path; one wave per cell keeps the
-        // coarse branch from crowding it
+        // 3D beside the contraction on the second stream: one wave per cell keeps the coarse branch from
+        // crowding it
         hipLaunchKernelGGL((k_restrict_c<kMaxNp, 1>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_gather.p, lam,
                            lam_rs, N, nd, np, cols, out);
     IFETI_HIP(hipGetLastError());
@@ -2182,6 +2186,9 @@ void op_prolong_cells(ifeti_ctx *c, const double *C, const double *yP, long long
     else if (np <= 8)
         hipLaunchKernelGGL((k_prolong_c<8, 2>), dim3(cell_grid(N, nrhs)), dim3(128), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N, nd,
                            np, cols, Y, accumulate ? 1 : 0);
+    else if (nrhs < 4)
+        hipLaunchKernelGGL((k_prolong_c<kMaxNp, 4>), dim3(cell_grid(N, nrhs)), dim3(256), 0, c->stream, C, c->g_Ap.p, yP,
+                           yP_rs, N, nd, np, cols, Y, accumulate ? 1 : 0);
     else
         hipLaunchKernelGGL((k_prolong_c<kMaxNp, 1>), dim3(cell_grid(N, nrhs)), dim3(64), 0, c->stream, C, c->g_Ap.p, yP, yP_rs, N,
                            nd, np, cols, Y, accumulate ? 1 : 0);

@@ -48,7 +48,7 @@ class Sizes(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("pcg_check_every", ctypes.c_int), ("fgmres_restart", ctypes.c_int),
-                ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 32),
+                ("pcg_maxit", ctypes.c_int), ("timing", ctypes.c_int), ("timing_filter", ctypes.c_char * 256),
                 ("timing_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("coarse_parts", ctypes.c_int), ("true_operator", ctypes.c_int), ("interface_block", ctypes.c_int),
                 ("overlap_local", ctypes.c_int), ("local_iters", ctypes.c_int), ("md_precision", ctypes.c_int),
@@ -217,7 +217,11 @@ class Context:
         o = Options()
         _check(self.lib.ifeti_get_options(self.h, ctypes.byref(o)))
         for name, value in kw.items():
-            setattr(o, name, value.encode()[:31] if name == "timing_filter" else value)
+            if name == "timing_filter":
+                value = value.encode()
+                if len(value) > 255:
+                    raise ValueError("timing_filter: at most 255 characters")
+            setattr(o, name, value)
         _check(self.lib.ifeti_set_options(self.h, ctypes.byref(o)))
 
     def reset_options(self, **kw):
