@@ -202,6 +202,7 @@ struct ifeti_ctx {
     ifeti::DevBuf<int> g_scatter;    // [l*2 + t]: sign*(s*n_d + j + 1), 0 none
     ifeti::DevBuf<double> g_Dw;      // [L] multiplicity weights
     ifeti::DevBuf<int> g_Ap;         // [s*n_p + j] global primal dof or -1
+    ifeti::DevBuf<int> g_Apc;        // [(s*n_p + j)*2 + t]: A_p as gather codes (t = 0: dof + 1, 0 none; t = 1: 0)
     ifeti::DevBuf<double> g_up_dir;  // [s*n_p + j] u0 at primal corners on a Dirichlet face (0 elsewhere)
     ifeti::DevBuf<int> g_Ppull;      // [P*maxc + t]: s*n_p + j, -1 none
     int maxc = 0;

@@ -1107,6 +1107,10 @@ void prepare_operator_copies(ifeti_ctx *c) {
     if (c->K < 1) return;
     (void)frag_copy(c, c->Fdd.p, c->n_d, c->n_d, c->K);  // F̊ (48)
     (void)frag_copy(c, c->Sdd.p, c->n_d, c->n_d, c->K);  // M̊_D^-1 (49)
+    if (c->n_p > 0) {  // the coarse restriction and prolongation of F̊ in principal form
+        (void)frag_copy(c, c->WT.p, c->n_p, c->n_d, c->K);
+        (void)frag_copy(c, c->W.p, c->n_d, c->n_p, c->K);
+    }
 }
 
 void release_blas(void *handle) {

@@ -2212,6 +2212,35 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
     // of load cases both branches take hundreds of microseconds and the contraction runs on the second
     // stream beside the coarse branch, after the restriction.
     const bool side = nrhs >= 4 && !c->no_alloc;
+    const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
+    const bool bank_streamed = 8.0 * K * nd * nd > 4.0 * 1024 * 1024 && nd >= 512;  // the F_dd bank exceeds L2
+    if (!side && prec == IFETI_FP64 && bank_streamed) {
+        // Principal form of the coarse branch: the restriction c_s = sum_k pi_sk (T_dr U_rp^(k))^T Lambda_s
+        // is a small contraction over the principal maps (L2-resident) with the jump gather fused, and the
+        // prolongation sum_k pi_sk (T_dr U_rp^(k)) y_P[A_p(s)] is a second group of the dominant
+        // contraction (its cell vectors gathered from y_P through A_p): neither streams the per-cell
+        // combined maps (340 MB on the 3D c3 lattice), and the prolongation needs no launch of its own.
+        // Where the bank streams from HBM the extra group adds n_p / n_d of the contraction's steps (c3:
+        // restriction 136 -> 72 us, prolongation 107 us -> +62 us in the contraction); where the bank
+        // stays in L2 the contraction is short and the extra group's latency is not hidden (c2: +12.7 us
+        // against a 7.5 us prolongation, the restriction unchanged), so the combined maps serve there.
+        const int np = c->n_p;
+        GemmGroup gr;
+        gr.A = c->WT.p; gr.X = lam; gr.xbs = c->L; gr.gcodes = c->g_gather.p; gr.coef = c->pi.p; gr.Kd = nd;
+        gr.K = K;
+        gemm(c, &gr, 1, cb, np, 0, np, cols, false, 0, "F_restrict", false);
+        op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
+        op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
+        GemmGroup g2[2];
+        g2[0] = g1;
+        g2[1].A = c->W.p; g2[1].X = yP; g2[1].xbs = c->nP; g2[1].gcodes = c->g_Apc.p; g2[1].coef = c->pi.p;
+        g2[1].Kd = np; g2[1].K = K;
+        gemm(c, g2, 2, Y, nd, 0, nd, cols, false, 0, "F_gemm");
+        op_scatter(c, Y, nd, 0, (long long)N * nd, out, c->L, nrhs, false, dot_w, dot_part);
+        c->applies[IFETI_OP_F] += nrhs;
+        IFETI_HIP(hipGetLastError());
+        return;
+    }
     op_restrict_cells(c, c->Wc.p, lam, c->L, cb, nrhs, "F_restrict");
     if (side) {
         SideStream ss(c);

@@ -386,6 +386,11 @@ void build_decomposition(ifeti_ctx *c) {
         }
     }
     c->g_Ap.upload(c->h_Ap, c->stream);
+    {
+        std::vector<int> codes(2 * c->h_Ap.size(), 0);
+        for (size_t i = 0; i < c->h_Ap.size(); ++i) codes[2 * i] = c->h_Ap[i] < 0 ? 0 : c->h_Ap[i] + 1;
+        c->g_Apc.upload(codes, c->stream);
+    }
     c->maxc = 1 << dim;
     std::vector<int> pull((size_t)c->nP * c->maxc, -1), cnt(c->nP, 0);
     for (int s = 0; s < N; ++s)
