@@ -47,7 +47,8 @@ def test_operators_low_precision(pair, prec, tol_op):
         lam = np.random.default_rng(3).standard_normal(m.L)
         v = np.random.default_rng(4).standard_normal(m.nU)
         for name, x, ref in (("F", lam, m.apply_F(lam)), ("MD", lam, m.apply_MD(lam)),
-                             ("Ut", lam, m.apply_Ut(lam)), ("U", v, m.apply_U(v))):
+                             ("Ut", lam, m.apply_Ut(lam)), ("U", v, m.apply_U(v)),
+                             ("Kinv_rom", v, m.apply_Kinv_rom(v))):
             got = getattr(ctx, "apply_" + name)(torch.tensor(x, device="cuda")).cpu().numpy()
             err = rel(got, ref)
             print(f"{prec} {name}: rel err {err:.2e}")
@@ -57,6 +58,13 @@ def test_operators_low_precision(pair, prec, tol_op):
         Y = ctx.apply_F(torch.tensor(X.ravel(), device="cuda"), nrhs=3).cpu().numpy().reshape(3, m.L)
         for r in range(3):
             assert rel(Y[r], m.apply_F(X[r])) < tol_op
+        # a block of load cases in the reduced local solve: each column equals its single apply bitwise
+        V = np.random.default_rng(6).standard_normal((3, m.nU))
+        Z = ctx.apply_Kinv_rom(torch.tensor(V.ravel(), device="cuda"), nrhs=3).cpu().numpy().reshape(3, m.nU)
+        for r in range(3):
+            assert rel(Z[r], m.apply_Kinv_rom(V[r])) < tol_op
+            one = ctx.apply_Kinv_rom(torch.tensor(V[r], device="cuda")).cpu().numpy()
+            assert np.array_equal(Z[r], one)
     finally:
         ctx.reset_options()
 

@@ -114,6 +114,32 @@ def test_low_precision_tile_candidates(lat, prec, cand):
         ctx.reset_options()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_low_precision_library_path(lat, prec):
+    """The precision form as the solves run it (no forced candidate): on c4cols the narrow library
+    product of (46a) gives R in FP32 for the reduced local solve, for the 32 load cases and for three."""
+    from paper_2308_11371_amd import ifeti
+    name, prob, ctx, gold, inputs = lat
+    ctx.set_options(precision={"fp32": ifeti.IFETI_FP32_LOCAL, "bf16": ifeti.IFETI_BF16_LOCAL}[prec])
+    try:
+        for op in OPS:
+            es, en = _errors(ctx, gold, inputs, op)
+            print(f"[gpu shapes] {name} {prec} library path {op}: sampled {es:.1e} norm {en:.1e}", flush=True)
+            tol = 1e-10 if op == "A" else LP_TOL[prec]
+            assert es <= tol and en <= tol, f"{name} {prec} library path {op}: {es:.2e} / {en:.2e}"
+        if gold["nrhs"] < 3:
+            return
+        n = inputs["Kinv_rom"].numel() // gold["nrhs"]
+        y = ctx.apply_Kinv_rom(inputs["Kinv_rom"][:3 * n], nrhs=3).cpu().numpy().reshape(3, n)
+        for r in range(3):
+            g = gold["ops"]["Kinv_rom"][r]
+            exp = np.array(g["val"])
+            err = np.linalg.norm(y[r][np.array(g["idx"])] - exp) / np.linalg.norm(exp)
+            assert err <= LP_TOL[prec], f"{name} {prec} three load cases, column {r}: {err:.2e}"
+    finally:
+        ctx.reset_options()
+
+
 def test_autotuned_tiles_match_oracle(lat):
     name, prob, ctx, gold, inputs = lat
     ctx.set_options(autotune=1)
