@@ -992,22 +992,29 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
     const int col = rhs * N + s, tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const size_t rows = (size_t)(n_r + 1) * KP;
-    // [n_r + 1][KP] a chunk of R in R's own precision (FP32 in the precision form: half the LDS reads of
-    // the stencil loop), row n_r zero; then H of the chunk in FP64 over the same bytes, then the wave
-    // partials
+    // [D n_ctrl + 1][KP] a chunk of R in R's own precision (FP32 in the precision form: half the LDS
+    // reads of the stencil loop), its rows component-major (slot k n_ctrl + a for component k of control
+    // point a, the last slot zero): the lanes of the stencil loop, consecutive control points, then read
+    // rows KP apart, an odd number of banks (with the dof order they were D KP apart and hit each bank
+    // twice); then H of the chunk in FP64 over the same bytes in the order of R, then the wave partials
+    const int zslot = D * n_ctrl;
+    const size_t rows = (size_t)(zslot + 1) * KP;
     TR *Rl = reinterpret_cast<TR *>(lds);
     double *Hl = lds;
     double *G = Hl + rows;  // [K][K], a copy of it, two [K][K+1] work arrays, g [K], c [K]
     double *G0 = G + K * K, *W1 = G0 + K * K, *W2 = W1 + K * (K + 1), *gb = W2 + K * (K + 1), *cv = gb + K;
-    int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or the zero row n_r
+    int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or n_r for none
+    int *rslot = rmap + n_ctrl * D;               // [n_r + 1]: LDS slot of each row of R, the zero row last
     const TR *Rc = R + (size_t)col * K * n_r;
     const double *v = vR + (size_t)rhs * v_rs + (size_t)s * n_r;
     const double *Ks = Kst + (size_t)s * n_ctrl * NOFF * D * D;
     for (int e = tid; e < n_ctrl * D; e += nt) {
         const int rr = r_of_dof[e];
         rmap[e] = rr >= 0 ? rr : n_r;
+        if (rr >= 0) rslot[rr] = (e % D) * n_ctrl + e / D;
     }
+    if (tid == 0) rslot[n_r] = zslot;
+    __syncthreads();
     for (int k0 = 0; k0 < K; k0 += KCOL) {
         const int kc = min(KCOL, K - k0);
         const int tot = (n_r + 1) * KCOL;
@@ -1024,7 +1031,7 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 const int e = e0 + u * nt;
-                if (e < tot) Rl[(e / KCOL) * KP + e % KCOL] = tmp[u];
+                if (e < tot) Rl[rslot[e / KCOL] * KP + e % KCOL] = tmp[u];
             }
         }
         __syncthreads();
@@ -1064,7 +1071,7 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
                 if (!ok) b = a;  // stencil value stored as zero for this offset
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const TR *row = Rl + rmap[b * D + k] * KP;
+                    const TR *row = Rl + (rmap[b * D + k] < n_r ? k * n_ctrl + b : zslot) * KP;
                     double kv[D];
 #pragma unroll
                     for (int i = 0; i < D; ++i) kv[i] = Ks[(((size_t)o * D + i) * D + k) * n_ctrl + a];
@@ -2447,10 +2454,10 @@ static int rom_local_mode(ifeti_ctx *c, size_t *lds_out) {
     const int nthr = (R.n_ctrl + 63) / 64 * 64;
     if (nthr > kRomHB) return -1;
     auto lds_of = [&](int kcol) {
-        const size_t rows = (size_t)(nr + 1) * (kcol | 1);
+        const size_t rows = (size_t)(D * R.n_ctrl + 1) * (kcol | 1);
         if ((size_t)(nthr / 64) * 256 > rows) return (size_t)1 << 30;  // the wave partials must fit in H's rows
         return rows * sizeof(double) + (size_t)(4 * K * K + 4 * K) * sizeof(double) +
-               (size_t)R.n_ctrl * D * sizeof(int);
+               ((size_t)R.n_ctrl * D + nr + 1) * sizeof(int);
     };
     constexpr size_t kLds = 160 * 1024;
     // c2: 661 us, against 790 us for the two-kernel form
