@@ -2219,9 +2219,8 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
     // of load cases both branches take hundreds of microseconds and the contraction runs on the second
     // stream beside the coarse branch, after the restriction.
     const bool side = nrhs >= 4 && !c->no_alloc;
-    const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
     const bool bank_streamed = 8.0 * K * nd * nd > 4.0 * 1024 * 1024 && nd >= 512;  // the F_dd bank exceeds L2
-    if (!side && prec == IFETI_FP64 && bank_streamed) {
+    if (!side && bank_streamed) {
         // Principal form of the coarse branch: the restriction c_s = sum_k pi_sk (T_dr U_rp^(k))^T Lambda_s
         // is a small contraction over the principal maps (L2-resident) with the jump gather fused, and the
         // prolongation sum_k pi_sk (T_dr U_rp^(k)) y_P[A_p(s)] is a second group of the dominant
@@ -2230,12 +2229,14 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
         // Where the bank streams from HBM the extra group adds n_p / n_d of the contraction's steps (c3:
         // restriction 136 -> 72 us, prolongation 107 us -> +62 us in the contraction); where the bank
         // stays in L2 the contraction is short and the extra group's latency is not hidden (c2: +12.7 us
-        // against a 7.5 us prolongation, the restriction unchanged), so the combined maps serve there.
+        // against a 7.5 us prolongation, the restriction unchanged), so the combined maps serve there.  In
+        // the precision form both maps run in the narrow precision with the contraction (the coarse solve
+        // stays FP64).
         const int np = c->n_p;
         GemmGroup gr;
         gr.A = c->WT.p; gr.X = lam; gr.xbs = c->L; gr.gcodes = c->g_gather.p; gr.coef = c->pi.p; gr.Kd = nd;
         gr.K = K;
-        gemm(c, &gr, 1, cb, np, 0, np, cols, false, 0, "F_restrict", false);
+        gemm(c, &gr, 1, cb, np, 0, np, cols, false, 0, "F_restrict");
         op_assemble_primal(c, cb, nullptr, 0, 1.0, zP, c->nP, nrhs);
         op_coarse_solve(c, zP, c->nP, yP, c->nP, nrhs, 1.0);
         GemmGroup g2[2];
