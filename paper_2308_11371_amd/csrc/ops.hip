@@ -112,13 +112,16 @@ __global__ __launch_bounds__(kB) void k_scatter_dot(const int *__restrict__ sl, 
         if (w) acc += v * w[rhs * out_rs + l];
     }
     if (!part) return;  // uniform
-    sh[tid] = acc;
+    // a butterfly within each wave, then the wave sums in wave order (fixed order)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
     __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
-        if (tid < off) sh[tid] += sh[tid + off];
-        __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kB / 64; ++w) t += sh[w];
+        part[(size_t)rhs * nblk + b] = t;
     }
-    if (tid == 0) part[(size_t)rhs * nblk + b] = sh[0];
 }
 
 // ------------------------------------------------------------------ coarse maps of F̊ (48)
@@ -1769,15 +1772,15 @@ __global__ __launch_bounds__(kMfB) void k_true_K_mf(const double *__restrict__ s
 }
 
 // ------------------------------------------------------------------ reductions (deterministic)
+// a butterfly within each wave, then the wave sums in wave order (fixed order, one barrier pair)
 __device__ inline double block_reduce(double v, double *sh) {
-    int tid = threadIdx.x;
-    sh[tid] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (tid < off) sh[tid] += sh[tid + off];
-        __syncthreads();
-    }
-    double r = sh[0];
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += sh[w];
     __syncthreads();
     return r;
 }

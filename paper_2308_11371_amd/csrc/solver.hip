@@ -26,15 +26,17 @@ enum { S_RHO = 0, S_R0, S_REL, S_ALPHA, S_BETA, S_N };
 // ints: active, iterations when last active, breakdown, iterations executed (all load cases)
 enum { I_ACT = 0, I_IT, I_BRK, I_ITER, I_N };
 
+// Block sum in a fixed order: a butterfly within each wave (lane i adds lane i ^ 32, ^ 16, ..., ^ 1; every
+// lane ends with the same bits), then the wave sums in wave order from LDS: one barrier pair instead of
+// a barrier per tree level.
 __device__ inline double block_reduce(double v, double *sh) {
-    int tid = threadIdx.x;
-    sh[tid] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (tid < off) sh[tid] += sh[tid + off];
-        __syncthreads();
-    }
-    double r = sh[0];
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
@@ -59,8 +61,8 @@ __device__ inline double sum_partials(const double *part, int nblk, double *sh) 
     return block_reduce(acc, sh);
 }
 
-// two sums of partials through one reduction tree (the same order per sum as sum_partials, half
-// the barriers); both partial sets are loaded before the first addition
+// two sums of partials through one reduction (the same order per sum as sum_partials, half the
+// barriers); both partial sets are loaded before the first addition
 __device__ inline void sum_partials2(const double *pa, const double *pb, int nblk, double *sh2, double &a,
                                      double &b) {
     double x = 0.0, y = 0.0;
@@ -69,19 +71,23 @@ __device__ inline void sum_partials2(const double *pa, const double *pb, int nbl
         x += u;
         y += v;
     }
-    const int tid = threadIdx.x;
-    sh2[tid] = x;
-    sh2[kB + tid] = y;
-    __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-            sh2[tid] += sh2[tid + off];
-            sh2[kB + tid] += sh2[kB + tid + off];
-        }
-        __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off);
+        y += __shfl_xor(y, off);
     }
-    a = sh2[0];
-    b = sh2[kB];
+    constexpr int nw = kB / 64;
+    if ((threadIdx.x & 63) == 0) {
+        sh2[threadIdx.x >> 6] = x;
+        sh2[nw + (threadIdx.x >> 6)] = y;
+    }
+    __syncthreads();
+    a = 0.0;
+    b = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        a += sh2[w];
+        b += sh2[nw + w];
+    }
     __syncthreads();
 }
 
