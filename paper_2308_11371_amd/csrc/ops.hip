@@ -999,12 +999,15 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
     // reads of the stencil loop), its rows component-major (slot k n_ctrl + a for component k of control
     // point a, the last slot zero): the lanes of the stencil loop, consecutive control points, then read
     // rows KP apart, an odd number of banks (with the dof order they were D KP apart and hit each bank
-    // twice); then H of the chunk in FP64 over the same bytes in the order of R, then the wave partials
+    // twice); then H of the chunk over the same bytes in the order of R, also in R's precision (FP32 in
+    // the precision form: half the LDS of a workgroup, three workgroups per CU in 2D instead of two),
+    // then the wave partials in FP64
     const int zslot = D * n_ctrl;
     const size_t rows = (size_t)(zslot + 1) * KP;
     TR *Rl = reinterpret_cast<TR *>(lds);
-    double *Hl = lds;
-    double *G = Hl + rows;  // [K][K], a copy of it, two [K][K+1] work arrays, g [K], c [K]
+    TR *Hl = Rl;
+    double *G = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + ((rows * sizeof(TR) + 15) & ~(size_t)15));
+    // G: [K][K], a copy of it, two [K][K+1] work arrays, g [K], c [K]
     double *G0 = G + K * K, *W1 = G0 + K * K, *W2 = W1 + K * (K + 1), *gb = W2 + K * (K + 1), *cv = gb + K;
     int *rmap = reinterpret_cast<int *>(cv + K);  // [n_ctrl][D]: row of R, or n_r for none
     int *rslot = rmap + n_ctrl * D;               // [n_r + 1]: LDS slot of each row of R, the zero row last
@@ -1094,7 +1097,7 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
                 const int ri = rmap[a * D + i];
                 if (ri < n_r)
 #pragma unroll
-                    for (int q = 0; q < KCOL; ++q) Hl[ri * KP + q] = h[i][q];
+                    for (int q = 0; q < KCOL; ++q) Hl[ri * KP + q] = (TR)h[i][q];
             }
         __syncthreads();
         // this chunk's columns of [G | g]: rows k = 4 i + lk, column q = lr (q == kc: R^T v, first chunk)
@@ -1104,11 +1107,11 @@ __global__ __launch_bounds__(kRomHB) void k_rom_local(const TR *__restrict__ R, 
             const int r = 4 * t + lk;
             const bool rin = r < n_r;
             const double af = (rin && lr < K) ? (double)Rc[(size_t)r * K + lr] : 0.0;
-            const double bf = !rin ? 0.0 : (lr < kc ? Hl[r * KP + lr] : (lr == kc && k0 == 0 ? v[r] : 0.0));
+            const double bf = !rin ? 0.0 : (lr < kc ? (double)Hl[r * KP + lr] : (lr == kc && k0 == 0 ? v[r] : 0.0));
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
         }
         __syncthreads();  // H read by every wave: its rows take the partial tiles
-        double *part = Hl;
+        double *part = lds;
 #pragma unroll
         for (int i = 0; i < 4; ++i) part[(size_t)(wave * 4 + i) * 64 + lane] = acc[i];
         __syncthreads();
@@ -2451,32 +2454,37 @@ static void op_mpcg_local(ifeti_ctx *c, const double *vR, long long v_rs, double
 
 // (46b) in one pass when the cell and K allow it (K <= 16, the LDS footprint below 160 KB): the variant
 // (0: 2D, 12 columns a chunk; 1: 2D, 8; 2: 3D, 8) and its LDS bytes, or -1 for the two-kernel form
-static int rom_local_mode(ifeti_ctx *c, size_t *lds_out) {
+// LDS bytes of k_rom_local with chunks of kcol columns and R (and H) in elements of esize bytes, or a
+// huge value when the FP64 wave partials do not fit in the chunk's bytes
+static size_t rom_local_lds(ifeti_ctx *c, int kcol, size_t esize) {
     const RefTables &R = c->ref;
-    const int nr = c->n_r, K = c->K, D = c->dim;
+    const int K = c->K, D = c->dim;
+    const int nthr = (R.n_ctrl + 63) / 64 * 64;
+    const size_t rbytes = ((size_t)(D * R.n_ctrl + 1) * (kcol | 1) * esize + 15) & ~(size_t)15;
+    if ((size_t)(nthr / 64) * 256 * sizeof(double) > rbytes) return (size_t)1 << 30;
+    return rbytes + (size_t)(4 * K * K + 4 * K) * sizeof(double) + ((size_t)R.n_ctrl * D + c->n_r + 1) * sizeof(int);
+}
+
+static int rom_local_mode(ifeti_ctx *c) {
+    const RefTables &R = c->ref;
+    const int K = c->K, D = c->dim;
     if (K > 16 || R.p != 2 || (D != 2 && D != 3)) return -1;
     const int nthr = (R.n_ctrl + 63) / 64 * 64;
     if (nthr > kRomHB) return -1;
-    auto lds_of = [&](int kcol) {
-        const size_t rows = (size_t)(D * R.n_ctrl + 1) * (kcol | 1);
-        if ((size_t)(nthr / 64) * 256 > rows) return (size_t)1 << 30;  // the wave partials must fit in H's rows
-        return rows * sizeof(double) + (size_t)(4 * K * K + 4 * K) * sizeof(double) +
-               ((size_t)R.n_ctrl * D + nr + 1) * sizeof(int);
-    };
     constexpr size_t kLds = 160 * 1024;
     // c2: 661 us, against 790 us for the two-kernel form
     int mode = -1;
-    if (D == 2 && K <= 12 && lds_of(12) <= kLds) mode = 0;
-    else if (D == 2 && lds_of(8) <= kLds) mode = 1;
-    else if (D == 3 && lds_of(8) <= kLds) mode = 2;
-    if (mode >= 0) *lds_out = mode == 0 ? lds_of(12) : lds_of(8);
+    if (D == 2 && K <= 12 && rom_local_lds(c, 12, sizeof(double)) <= kLds) mode = 0;
+    else if (D == 2 && rom_local_lds(c, 8, sizeof(double)) <= kLds) mode = 1;
+    else if (D == 3 && rom_local_lds(c, 8, sizeof(double)) <= kLds) mode = 2;
     return mode;
 }
 
 // R: [col][n_r][K] in FP64, or in FP32 (the precision form's narrow product)
 template <typename TR>
-static void launch_rom_local(ifeti_ctx *c, int mode, size_t lds, const TR *Rp, const double *vR, long long v_rs,
+static void launch_rom_local(ifeti_ctx *c, int mode, const TR *Rp, const double *vR, long long v_rs,
                              double *xR, long long x_rs, int cols) {
+    const size_t lds = rom_local_lds(c, mode == 0 ? 12 : 8, sizeof(TR));
     const RefTables &R = c->ref;
     const int nr = c->n_r, K = c->K, D = c->dim;
     const int nthr = (R.n_ctrl + 63) / 64 * 64;
@@ -2511,15 +2519,14 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     // (46a) R = [K_rr^(sigma_k)-1 v]_k : one GEMM with the row-interleaved explicit inverses, so each
     // column comes out as [r][k] (or the zero-padded interior inverses of (47))
     const int cols = N * nrhs;
-    size_t lds = 0;
-    const int mode = rom_local_mode(c, &lds);
+    const int mode = rom_local_mode(c);
     const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
     if (mode >= 0 && prec != IFETI_FP64) {
         // precision form: the narrow product by the library into an FP32 R, read as such by (46b)
         c->w_R32.ensure((size_t)cols * K * nr, c->stream);
         if (library_gemm_narrow(c, bank ? bank : c->Kinv.p, K * nr, nr, vR, nr, v_rs, N, nrhs, prec, c->w_R32.p,
                                 rtag)) {
-            launch_rom_local(c, mode, lds, c->w_R32.p, vR, v_rs, xR, x_rs, cols);
+            launch_rom_local(c, mode, c->w_R32.p, vR, v_rs, xR, x_rs, cols);
             return;
         }
     }
@@ -2529,7 +2536,7 @@ void op_rom_local(ifeti_ctx *c, const double *vR, long long v_rs, double *xR, lo
     // (46b) H = K_rr^(s) R in column chunks, then the per-cell Gram system and combination
     const double colsd = (double)cols;
     if (mode >= 0) {
-        launch_rom_local(c, mode, lds, (const double *)c->w_R.p, vR, v_rs, xR, x_rs, cols);
+        launch_rom_local(c, mode, (const double *)c->w_R.p, vR, v_rs, xR, x_rs, cols);
         return;
     }
     launch_rom_H(c, cols);
