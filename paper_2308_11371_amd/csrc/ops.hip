@@ -2226,7 +2226,8 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
     // stream beside the coarse branch, after the restriction.
     const bool side = nrhs >= 4 && !c->no_alloc;
     const bool bank_streamed = 8.0 * K * nd * nd > 4.0 * 1024 * 1024 && nd >= 512;  // the F_dd bank exceeds L2
-    if (!side && bank_streamed) {
+    const int prec = c->prec_override >= 0 ? c->prec_override : c->opt.precision;
+    if (!side && bank_streamed && prec != IFETI_BF16_LOCAL) {
         // Principal form of the coarse branch: the restriction c_s = sum_k pi_sk (T_dr U_rp^(k))^T Lambda_s
         // is a small contraction over the principal maps (L2-resident) with the jump gather fused, and the
         // prolongation sum_k pi_sk (T_dr U_rp^(k)) y_P[A_p(s)] is a second group of the dominant
@@ -2236,8 +2237,9 @@ void apply_F_into(ifeti_ctx *c, const double *lam, double *out, int nrhs, double
         // restriction 136 -> 72 us, prolongation 107 us -> +62 us in the contraction); where the bank
         // stays in L2 the contraction is short and the extra group's latency is not hidden (c2: +12.7 us
         // against a 7.5 us prolongation, the restriction unchanged), so the combined maps serve there.  In
-        // the precision form both maps run in the narrow precision with the contraction (the coarse solve
-        // stays FP64).
+        // the FP32 precision form both maps run in FP32 with the contraction (the coarse solve stays FP64;
+        // c3 FP32 local 2.47 -> 2.16 s); in BF16 they slowed the outer iteration (c3: 26 -> 44 outer
+        // iterations), so the BF16 form keeps the FP64 combined maps.
         const int np = c->n_p;
         GemmGroup gr;
         gr.A = c->WT.p; gr.X = lam; gr.xbs = c->L; gr.gcodes = c->g_gather.p; gr.coef = c->pi.p; gr.Kd = nd;
