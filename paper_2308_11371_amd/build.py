@@ -18,8 +18,12 @@ LIB = os.path.join(HERE, "libifeti.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "stats.cpp", "setup_host.cpp", "kernels_setup.hip", "gemm.hip", "ops.hip", "solver.hip", "gradient.hip", "coarse_part.cpp", "exact.hip", "noalloc.hip"]
+# MFMA accumulators in VGPRs rather than AGPRs: on gfx950 a chain of v_mfma_f64_16x16x4f64 with its
+# accumulators in AGPRs issues at 0.3-0.6 of the published FP64 rate and in VGPRs at 0.84-0.97 (measured),
+# and the compiler picks AGPRs for some of the tiles by itself
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
-         "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
+         "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _compile(src: str) -> str:
