@@ -591,7 +591,7 @@ def main():
         cpu_worker(args.cpu_worker)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     # the CPU oracle's setup runs on cores of its own while the GPU legs run (no GPU use in that process)
     cpu = None if args.no_cpu_baseline else CpuBaseline()
