@@ -116,8 +116,9 @@ def test_low_precision_tile_candidates(lat, prec, cand):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_low_precision_library_path(lat, prec):
-    """The precision form as the solves run it (no forced candidate): on c4cols the narrow library
-    product of (46a) gives R in FP32 for the reduced local solve, for the 32 load cases and for three."""
+    """The precision form as the solves run it (no forced candidate): the narrow library product of
+    (46a) gives R in FP32 for the reduced local solve (c4cols: the 32 load cases and three; c3cell: 32
+    copies of its load case, 1024 cell columns)."""
     from paper_2308_11371_amd import ifeti
     name, prob, ctx, gold, inputs = lat
     ctx.set_options(precision={"fp32": ifeti.IFETI_FP32_LOCAL, "bf16": ifeti.IFETI_BF16_LOCAL}[prec])
@@ -128,6 +129,15 @@ def test_low_precision_library_path(lat, prec):
             tol = 1e-10 if op == "A" else LP_TOL[prec]
             assert es <= tol and en <= tol, f"{name} {prec} library path {op}: {es:.2e} / {en:.2e}"
         if gold["nrhs"] < 3:
+            # 32 copies of the single load case: 1024 cell columns take the narrow library product and
+            # the 3D reduced local solve with R and H in FP32
+            n = inputs["Kinv_rom"].numel()
+            y = ctx.apply_Kinv_rom(inputs["Kinv_rom"].repeat(32), nrhs=32).cpu().numpy().reshape(32, n)
+            g = gold["ops"]["Kinv_rom"][0]
+            exp = np.array(g["val"])
+            for r in (0, 17, 31):
+                err = np.linalg.norm(y[r][np.array(g["idx"])] - exp) / np.linalg.norm(exp)
+                assert err <= LP_TOL[prec], f"{name} {prec} 32 copies, column {r}: {err:.2e}"
             return
         n = inputs["Kinv_rom"].numel() // gold["nrhs"]
         y = ctx.apply_Kinv_rom(inputs["Kinv_rom"][:3 * n], nrhs=3).cpu().numpy().reshape(3, n)
