@@ -470,6 +470,12 @@ void multidot(ifeti_ctx *c, const double *V, long long vstride, int nv, const do
 // w = a w + cscale * sum_k coef_k V_k (per load case)
 void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const double *coef_dev, double a, double *w,
                long long n, long long rs, int nrhs, const double *const *Vp = nullptr, double cscale = 1.0);
+// w += cscale * V coef (a pointer array of nv <= kAxpyDotMax vectors) and, in the same pass, the dot products of
+// the updated w with the nv vectors (norm = false) or with itself (norm = true) into out_dev, equal
+// bitwise to multiaxpy followed by multidot; false (nothing done) for more than kAxpyDotMax vectors
+constexpr int kAxpyDotMax = 16;
+bool axpy_dot(ifeti_ctx *c, int nv, const double *coef_dev, double cscale, double *w, long long n, long long rs,
+              int nrhs, const double *const *Vp, bool norm, double *out_dev);
 void inv_sqrt(ifeti_ctx *c, const double *h, double *sc, int n);
 void scale_copy(ifeti_ctx *c, const double *x, long long n, long long rs, const double *sc_dev, double *y, int nrhs);
 

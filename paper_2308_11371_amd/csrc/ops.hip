@@ -1855,6 +1855,61 @@ __global__ __launch_bounds__(kB) void k_multiaxpy(const double *__restrict__ V, 
     w[rhs * rs + i] = acc;
 }
 
+// w[rhs] += cscale * sum_i coef[rhs*nv + i] V_i[rhs] (the terms of k_multiaxpy with a = 1, in its order),
+// written back, and in the same pass the partial sums of the updated w with every V_i (NORM = false:
+// those of k_multidot_partial) or with itself (NORM = true: one per load case).  The chunks, the
+// per-thread order and the reduction are those of k_multidot_partial, so the results equal those of
+// the separate passes bitwise while the vectors are read once instead of twice.
+template <int NVMAX, bool NORM>
+__global__ __launch_bounds__(256) void k_axpy_dot(const double *const *__restrict__ Vp, int nv,
+                                                  const double *__restrict__ coef, double cscale,
+                                                  double *__restrict__ w, long long n, long long rs, int nblk,
+                                                  double *__restrict__ partial) {
+    constexpr int NP = NORM ? 1 : NVMAX;
+    __shared__ double sh[4][NP];
+    const int b = blockIdx.x, rhs = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long i0 = b * chunk, i1 = min(n, i0 + chunk);
+    double *wr = w + rhs * rs;
+    const double *vp[NVMAX];
+    double cf[NVMAX], acc[NP];
+#pragma unroll
+    for (int g = 0; g < NVMAX; ++g) {
+        vp[g] = g < nv ? Vp[g] + rhs * rs : wr;
+        cf[g] = g < nv ? cscale * coef[rhs * nv + g] : 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < NP; ++g) acc[g] = 0.0;
+    for (long long t = i0 + threadIdx.x; t < i1; t += 256) {
+        double v[NVMAX];
+#pragma unroll
+        for (int g = 0; g < NVMAX; ++g) v[g] = g < nv ? vp[g][t] : 0.0;
+        double x = wr[t];
+#pragma unroll
+        for (int g = 0; g < NVMAX; ++g)
+            if (g < nv) x += cf[g] * v[g];
+        wr[t] = x;
+        if constexpr (NORM) {
+            acc[0] += x * x;
+        } else {
+#pragma unroll
+            for (int g = 0; g < NVMAX; ++g)
+                if (g < nv) acc[g] += v[g] * x;
+        }
+    }
+    const int np = NORM ? 1 : nv;
+#pragma unroll
+    for (int g = 0; g < NP; ++g)
+        for (int off = 32; off > 0; off >>= 1) acc[g] += __shfl_xor(acc[g], off);
+    if (lane == 0)
+#pragma unroll
+        for (int g = 0; g < NP; ++g) sh[wave][g] = acc[g];
+    __syncthreads();
+    if ((int)threadIdx.x < np)
+        partial[((size_t)rhs * np + threadIdx.x) * nblk + b] =
+            ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
 // sc[r] = 1 / sqrt(h[r]) (0 for a zero norm)
 __global__ void k_inv_sqrt(const double *__restrict__ h, double *__restrict__ sc, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2834,6 +2889,25 @@ void multiaxpy(ifeti_ctx *c, const double *V, long long vstride, int nv, const d
     hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks(n * nrhs)), dim3(kB), 0, c->stream, V, vstride, Vp, nv, coef_dev, a, w,
                        n, rs, nrhs, cscale);
     IFETI_HIP(hipGetLastError());
+}
+
+bool axpy_dot(ifeti_ctx *c, int nv, const double *coef_dev, double cscale, double *w, long long n, long long rs,
+              int nrhs, const double *const *Vp, bool norm, double *out_dev) {
+    constexpr int kMax = kAxpyDotMax;
+    if (nv < 1 || nv > kMax || !Vp) return false;
+    const int nblk = (int)std::max<long long>(1, std::min<long long>(2048, (n + 2047) / 2048));  // as multidot
+    const int np = norm ? 1 : nv;
+    c->w_red.ensure((size_t)nblk * np * nrhs, c->stream);
+    Prof prof(c, "gmres_vec", 2.0 * n * nv * nrhs + 2.0 * n * np * nrhs, 8.0 * (double)n * (nv + 2) * nrhs);
+    if (norm)
+        hipLaunchKernelGGL((k_axpy_dot<kMax, true>), dim3(nblk, nrhs), dim3(256), 0, c->stream, Vp, nv, coef_dev, cscale,
+                           w, n, rs, nblk, c->w_red.p);
+    else
+        hipLaunchKernelGGL((k_axpy_dot<kMax, false>), dim3(nblk, nrhs), dim3(256), 0, c->stream, Vp, nv, coef_dev,
+                           cscale, w, n, rs, nblk, c->w_red.p);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(np * nrhs), dim3(kB), 0, c->stream, c->w_red.p, nblk, out_dev);
+    IFETI_HIP(hipGetLastError());
+    return true;
 }
 
 void inv_sqrt(ifeti_ctx *c, const double *h, double *sc, int n) {

@@ -990,12 +990,18 @@ int solve_fgmres(ifeti_ctx *c, const double *f, const double *d, double *u, doub
         apply_A(c, Zj, w.p, nrhs);
         // classical Gram-Schmidt, twice, with the projections kept on the device; the next basis
         // vector is normalised on the device and the host reads the Hessenberg column once
-        for (int pass = 0; pass < 2; ++pass) {
-            double *hp = hall.p + pass * hstride;
-            multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hp, dVp.p);
-            multiaxpy(c, nullptr, 0, j + 1, hp, 1.0, w.p, ns, ns, nrhs, dVp.p, -1.0);
+        // (the subtraction of each pass fused with the dot products that follow it: the basis is read
+        // three times per step instead of four, with the same results)
+        multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hall.p, dVp.p);
+        if (j + 1 <= kAxpyDotMax) {
+            axpy_dot(c, j + 1, hall.p, -1.0, w.p, ns, ns, nrhs, dVp.p, false, hall.p + hstride);
+            axpy_dot(c, j + 1, hall.p + hstride, -1.0, w.p, ns, ns, nrhs, dVp.p, true, hall.p + 2 * hstride);
+        } else {
+            multiaxpy(c, nullptr, 0, j + 1, hall.p, 1.0, w.p, ns, ns, nrhs, dVp.p, -1.0);
+            multidot(c, nullptr, 0, j + 1, w.p, ns, ns, nrhs, hall.p + hstride, dVp.p);
+            multiaxpy(c, nullptr, 0, j + 1, hall.p + hstride, 1.0, w.p, ns, ns, nrhs, dVp.p, -1.0);
+            multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hall.p + 2 * hstride);
         }
-        multidot(c, w.p, 0, 1, w.p, ns, ns, nrhs, hall.p + 2 * hstride);
         inv_sqrt(c, hall.p + 2 * hstride, scd.p, nrhs);
         double *Vn = new_block(c->fg_V, c->fg_hV, dVp, nV);
         scale_copy(c, w.p, ns, ns, scd.p, Vn, nrhs);
