@@ -434,25 +434,42 @@ def run_exact(ctx, f, d, t_rom, args, maxit=2000,
     out = {"workload": workload, "factorisation_s": time.perf_counter() - t0}
     _, _, _, _, nbytes = ctx.exact_cell_blocks(0)
     out["device_gb"] = nbytes / 1e9
-    # the interface tolerance is relative to d-bar of (25), several hundred times the norm of (f, d)
-    # here: 1e-3 of the saddle tolerance brings the true residual of (16) below it, as for the ROM solve
+    # The interface tolerance is relative to d-bar of (25).  With exact local solves the residual of
+    # (16) is the interface residual over the norm of (f, d): in 2D d-bar is several hundred times that
+    # norm and 1e-3 of the saddle tolerance suffices; in 3D the ratio is larger, so the tolerance is
+    # tightened by the measured shortfall (at most twice) until (16) meets the ROM solve's tolerance,
+    # and the solve that meets it is the one reported.
     itol = args.tol * 1e-3
-    out["interface_tol"] = itol
     ctx.exact_solve(f, d, tol=itol, maxit=maxit)  # untimed warm-up
     torch.cuda.synchronize()
-    ctx.set_options(timing=1, timing_filter="exact_F_cells,exact_MD_cells", timing_every=8)
-    ctx.reset_stats()
-    t0 = time.perf_counter()
-    u, lam, info = ctx.exact_solve(f, d, tol=itol, maxit=maxit)
-    torch.cuda.synchronize()
-    out["solve_time_s"] = time.perf_counter() - t0
-    st = ctx.stats()
-    ctx.reset_options()
-    out["pcg_its"] = int(info["iters"][0])
-    out["pcg_relres"] = float(info["relres"][0])
-    x = torch.cat([u, lam])
+    from paper_2308_11371_amd import ifeti
     b = torch.cat([f, d])
-    out["relres_saddle"] = float(torch.linalg.norm(b - ctx.apply_A(x)) / torch.linalg.norm(b))
+    tried, best = [], None
+    for attempt in range(3):
+        ctx.set_options(timing=1, timing_filter="exact_F_cells,exact_MD_cells", timing_every=8)
+        ctx.reset_stats()
+        t0 = time.perf_counter()
+        # a tightened tolerance the PCG cannot reach ends the search with the last solve that did
+        u, lam, info = ctx.exact_solve(f, d, tol=itol, maxit=maxit, check=attempt == 0)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = ctx.stats()
+        ctx.reset_options()
+        rs = float(torch.linalg.norm(b - ctx.apply_A(torch.cat([u, lam]))) / torch.linalg.norm(b))
+        rec = {"interface_tol": itol, "pcg_its": int(info["iters"][0]), "pcg_relres": float(info["relres"][0]),
+               "relres_saddle": rs, "solve_time_s": t, "status": ifeti.STATUS_NAMES.get(info["status"])}
+        tried.append(rec)
+        if info["status"] != ifeti.IFETI_OK:
+            break
+        best = (rec, st)
+        if rs <= args.tol:
+            break
+        itol *= 0.5 * args.tol / rs
+    rec, st = best
+    for k in ("interface_tol", "solve_time_s", "pcg_its", "pcg_relres", "relres_saddle"):
+        out[k] = rec[k]
+    if len(tried) > 1:
+        out["interface_tol_tried"] = tried
     out["vs_rom_solve"] = out["solve_time_s"] / t_rom
     for fam in ("exact_F_cells", "exact_MD_cells"):
         k = st["kernels"].get(fam)
